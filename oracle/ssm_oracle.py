@@ -1,0 +1,359 @@
+"""Plain, slow, obviously-correct FP64 reference for the fast cascade.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): the HIP library never
+calls into this file, and this file never imports the HIP library.
+
+Everything here is numpy float64 on the CPU, one sequence at a time, written
+for a reader holding the paper (Beylkin, arXiv 2411.17729) next to it:
+
+* ``trapezoid``        -- the trapezoidal discretization of §1 (after eq. (1.2)).
+* ``recursion``        -- the discrete LTI recursion, eq. (1.2), x_{-1} = 0.
+* ``powers``           -- Abar, Abar^2, Abar^4, ... by repeated squaring (end of §2).
+* ``impulse_response`` / ``truncated_sum`` -- the convolution sum eq. (3.1)
+  restricted to the lags that the degree-(2^{N+1}-1) polynomial H_N of
+  eq. (2.2)/(2.3) keeps.
+* ``cascade``          -- the stage-by-stage algorithm of §3, eqs. (3.2)-(3.4)
+  and the general step, followed by the output y = C v + D u.
+* ``transfer`` / ``transfer_truncated`` -- H(z) of eq. (1.3) and H_N(z) of
+  eq. (2.2) evaluated at a point z of the unit circle.
+* ``grads_*`` / ``trapezoid_adjoint`` -- reverse-mode derivatives of the maps
+  above (not in the paper; derived by the chain rule, pinned by finite
+  differences in the tests).
+
+Readings of points where the paper is loose (each also listed in the design
+notes of the repository):
+
+* Stage count. H_N has N+1 factors, so the cascade runs N+1 stages with shifts
+  1, 2, ..., 2^N, and the output is taken after the last one (§2, eq. (2.2);
+  §3 "N+1 matrix-vector multiplications"), even though the text of §3 writes
+  the final output with V^(N).
+* Output term. eq. (3.1) prints D u_k inside the sum; the output equation of
+  eq. (1.2) and the final step of §3 both add D u_l once, which is used here.
+* Boundary. Columns l < 2^n are copied unchanged at stage n (x_{-1} = 0,
+  §3); a stage whose shift reaches past the sequence changes nothing.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "trapezoid",
+    "trapezoid_adjoint",
+    "recursion",
+    "powers",
+    "impulse_response",
+    "truncated_sum",
+    "cascade",
+    "transfer",
+    "transfer_truncated",
+    "grads_recursion",
+    "grads_truncated_bruteforce",
+    "grads_full",
+    "effective_stages",
+]
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def _as_matrix_u(u):
+    u = _f64(u)
+    if u.ndim == 1:
+        u = u[:, None]
+    return u
+
+
+# --------------------------------------------------------------------------
+# Discretization (§1, the trapezoidal rule stated after eq. (1.2); also
+# eq. (4.2) for the HiPPO example of §4)
+# --------------------------------------------------------------------------
+def trapezoid(A, B, delta):
+    """Abar = (I - delta/2 A)^{-1} (I + delta/2 A),  Bbar = delta (I - delta/2 A)^{-1} B.
+
+    Both are obtained from one linear solve with the matrix I - delta/2 A, as
+    the formulas state (no explicit inverse).
+    """
+    A = _f64(A)
+    B = _f64(B)
+    if B.ndim == 1:
+        B = B[:, None]
+    m = A.shape[0]
+    eye = np.eye(m)
+    lhs = eye - 0.5 * delta * A
+    rhs = np.concatenate([eye + 0.5 * delta * A, delta * B], axis=1)
+    sol = np.linalg.solve(lhs, rhs)
+    return sol[:, :m], sol[:, m:]
+
+
+def trapezoid_adjoint(A, B, delta, gAbar, gBbar):
+    """Gradients of a scalar loss w.r.t. A and B given its gradients w.r.t. Abar, Bbar.
+
+    Derived by the chain rule from the two formulas of ``trapezoid``. With
+    M = I - delta/2 A:
+        dAbar = delta/2 M^{-1} dA (I + Abar)
+        dBbar = delta/2 M^{-1} dA Bbar + delta M^{-1} dB
+    hence
+        gA = delta/2 M^{-T} gAbar (I + Abar)^T + delta/2 M^{-T} gBbar Bbar^T
+        gB = delta M^{-T} gBbar.
+    """
+    A = _f64(A)
+    B = _f64(B)
+    if B.ndim == 1:
+        B = B[:, None]
+    m = A.shape[0]
+    eye = np.eye(m)
+    M = eye - 0.5 * delta * A
+    Abar, Bbar = trapezoid(A, B, delta)
+    # M^{-T} X is the solution of M^T Z = X.
+    gA = 0.5 * delta * np.linalg.solve(M.T, gAbar @ (eye + Abar).T)
+    gA += 0.5 * delta * np.linalg.solve(M.T, gBbar @ Bbar.T)
+    gB = delta * np.linalg.solve(M.T, gBbar)
+    return gA, gB
+
+
+# --------------------------------------------------------------------------
+# The recursion, eq. (1.2)
+# --------------------------------------------------------------------------
+def recursion(Abar, Bbar, C, D, u):
+    """x_n = Abar x_{n-1} + Bbar u_n, y_n = C x_n + D u_n, with x_{-1} = 0.
+
+    Returns (y, x) with y of shape (L, q) and x of shape (L, m).
+    """
+    Abar, Bbar, C, D = _f64(Abar), _f64(Bbar), _f64(C), _f64(D)
+    u = _as_matrix_u(u)
+    L = u.shape[0]
+    m = Abar.shape[0]
+    x = np.zeros(m)
+    xs = np.empty((L, m))
+    for n in range(L):
+        x = Abar @ x + Bbar @ u[n]
+        xs[n] = x
+    y = xs @ C.T + u @ D.T
+    return y, xs
+
+
+# --------------------------------------------------------------------------
+# Powers by repeated squaring (end of §2; §3 "compute the powers")
+# --------------------------------------------------------------------------
+def powers(Abar, N):
+    """[Abar^(2^0), Abar^(2^1), ..., Abar^(2^N)], each the square of the previous."""
+    P = [_f64(Abar).copy()]
+    for _ in range(N):
+        P.append(P[-1] @ P[-1])
+    return P
+
+
+def effective_stages(N, L):
+    """Number of cascade stages that change anything for a length-L sequence.
+
+    Stage n (shift 2^n) updates the columns 2^n <= l <= L-1 (§3); once
+    2^n >= L it updates nothing, so at most floor(log2(L-1)) + 1 stages act.
+    """
+    if L <= 1:
+        return 0
+    act = 0
+    while act <= N and (1 << act) <= L - 1:
+        act += 1
+    return act
+
+
+# --------------------------------------------------------------------------
+# The convolution sum, eq. (3.1), restricted to the lags of H_N (eq. (2.3))
+# --------------------------------------------------------------------------
+def impulse_response(Abar, Bbar, C, T):
+    """h_j = C Abar^j Bbar for j = 0..T-1, via w_{j+1} = Abar w_j, w_0 = Bbar.
+
+    Returns an array of shape (T, q, p).
+    """
+    Abar, Bbar, C = _f64(Abar), _f64(Bbar), _f64(C)
+    if Bbar.ndim == 1:
+        Bbar = Bbar[:, None]
+    h = np.empty((T, C.shape[0], Bbar.shape[1]))
+    w = Bbar.copy()
+    for j in range(T):
+        h[j] = C @ w
+        w = Abar @ w
+    return h
+
+
+def truncated_sum(Abar, Bbar, C, D, u, N):
+    """y_l = sum_{j=0}^{min(l, T-1)} C Abar^j Bbar u_{l-j} + D u_l with T = 2^(N+1).
+
+    This is eq. (3.1) with the lags cut where the polynomial H_N of
+    eq. (2.2)/(2.3) stops (degree T-1). When T >= L nothing is cut and this
+    equals ``recursion``.
+    """
+    u = _as_matrix_u(u)
+    L = u.shape[0]
+    T = 1 << (N + 1)
+    Tu = min(T, L)
+    h = impulse_response(Abar, Bbar, C, Tu)
+    y = u @ _f64(D).T
+    for j in range(Tu):
+        y[j:] += u[: L - j] @ h[j].T
+    return y
+
+
+# --------------------------------------------------------------------------
+# The cascade of §3, stage by stage
+# --------------------------------------------------------------------------
+def cascade(Abar, Bbar, C, D, u, N, return_stages=False):
+    """Apply H_N of eq. (2.3) in the time domain by the cascade of §3.
+
+    V^(0) has columns v_l = Bbar u_l (an m x L matrix). Stage n = 1..N+1 uses
+    the power Abar^(2^(n-1)) and the shift 2^(n-1):
+        v_l^(n) = Abar^(2^(n-1)) v_{l-2^(n-1)}^(n-1) + v_l^(n-1)   for 2^(n-1) <= l <= L-1,
+        v_l^(n) = v_l^(n-1)                                         otherwise
+    (eqs. (3.2)-(3.4) and the general step). Output y_l = C v_l^(N+1) + D u_l.
+
+    Returns y of shape (L, q); with ``return_stages`` also the list
+    [V^(0), ..., V^(N+1)], each of shape (m, L).
+    """
+    Abar, Bbar, C, D = _f64(Abar), _f64(Bbar), _f64(C), _f64(D)
+    if Bbar.ndim == 1:
+        Bbar = Bbar[:, None]
+    u = _as_matrix_u(u)
+    L = u.shape[0]
+    P = powers(Abar, N)
+    V = Bbar @ u.T  # m x L, column l is v_l^(0)
+    stages = [V.copy()]
+    for n in range(1, N + 2):
+        shift = 1 << (n - 1)
+        Vn = V.copy()
+        if shift <= L - 1:
+            Vn[:, shift:] = P[n - 1] @ V[:, : L - shift] + V[:, shift:]
+        V = Vn
+        stages.append(V.copy())
+    y = (C @ V).T + u @ D.T
+    if return_stages:
+        return y, stages
+    return y
+
+
+# --------------------------------------------------------------------------
+# Transfer functions, eq. (1.3) and eq. (2.2)
+# --------------------------------------------------------------------------
+def transfer(Abar, Bbar, C, D, z):
+    """H(z) = C (I - z^{-1} Abar)^{-1} Bbar + D (eq. (1.3))."""
+    Abar = _f64(Abar)
+    m = Abar.shape[0]
+    Bbar = _f64(Bbar)
+    if Bbar.ndim == 1:
+        Bbar = Bbar[:, None]
+    X = np.linalg.solve(np.eye(m) - Abar / z, Bbar.astype(complex))
+    return _f64(C) @ X + _f64(D)
+
+
+def transfer_truncated(Abar, Bbar, C, D, z, N):
+    """H_N(z) = C prod_{n=0}^{N} [I + (z^{-1} Abar)^(2^n)] Bbar + D (eq. (2.2)).
+
+    The factors commute, so the order of the product is immaterial; they are
+    multiplied in increasing n.
+    """
+    Abar = _f64(Abar)
+    m = Abar.shape[0]
+    Bbar = _f64(Bbar)
+    if Bbar.ndim == 1:
+        Bbar = Bbar[:, None]
+    Z = Abar.astype(complex) / z
+    prod = np.eye(m, dtype=complex)
+    Zp = Z.copy()
+    for _ in range(N + 1):
+        prod = prod @ (np.eye(m) + Zp)
+        Zp = Zp @ Zp
+    return _f64(C) @ prod @ Bbar + _f64(D)
+
+
+# --------------------------------------------------------------------------
+# Reverse-mode derivatives (not in the paper)
+# --------------------------------------------------------------------------
+def grads_recursion(Abar, Bbar, C, D, u, dy):
+    """Gradients of sum(dy * y) for y = recursion(...), by backpropagation in time.
+
+    lambda_l = C^T dy_l + Abar^T lambda_{l+1}  (lambda_L = 0),
+    gAbar = sum_{l>=1} lambda_l x_{l-1}^T,  gBbar = sum_l lambda_l u_l^T,
+    gC = sum_l dy_l x_l^T,  gD = sum_l dy_l u_l^T,  gu_l = Bbar^T lambda_l + D^T dy_l.
+
+    When 2^(N+1) >= L the cascade output equals the recursion output, so these
+    are also the cascade's gradients.
+    Returns dict(u, Abar, Bbar, C, D).
+    """
+    Abar, Bbar, C, D = _f64(Abar), _f64(Bbar), _f64(C), _f64(D)
+    if Bbar.ndim == 1:
+        Bbar = Bbar[:, None]
+    u = _as_matrix_u(u)
+    dy = _as_matrix_u(dy)
+    L = u.shape[0]
+    m = Abar.shape[0]
+    _, xs = recursion(Abar, Bbar, C, D, u)
+    lam = np.zeros(m)
+    gA = np.zeros((m, m))
+    gB = np.zeros_like(Bbar)
+    gu = np.empty_like(u)
+    for n in range(L - 1, -1, -1):
+        lam = C.T @ dy[n] + Abar.T @ lam
+        if n >= 1:
+            gA += np.outer(lam, xs[n - 1])
+        gB += np.outer(lam, u[n])
+        gu[n] = Bbar.T @ lam + D.T @ dy[n]
+    gC = dy.T @ xs
+    gD = dy.T @ u
+    return {"u": gu, "Abar": gA, "Bbar": gB, "C": gC, "D": gD}
+
+
+def grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N):
+    """Gradients of sum(dy * y) for y = truncated_sum(..., N), by brute force.
+
+    With T = 2^(N+1) and x_l = sum_{j<=min(l,T-1)} Abar^j Bbar u_{l-j}:
+    d(Abar^j) = sum_{a+b=j-1} Abar^a dAbar Abar^b, so
+        gAbar = sum_l sum_{1<=j<=min(l,T-1)} sum_{a+b=j-1} (Abar^T)^a g_l (Abar^b Bbar u_{l-j})^T
+    with g_l = C^T dy_l. Cost O(L T^2 m^3): tiny inputs only.
+    """
+    Abar, Bbar, C, D = _f64(Abar), _f64(Bbar), _f64(C), _f64(D)
+    if Bbar.ndim == 1:
+        Bbar = Bbar[:, None]
+    u = _as_matrix_u(u)
+    dy = _as_matrix_u(dy)
+    L = u.shape[0]
+    m = Abar.shape[0]
+    T = 1 << (N + 1)
+    pw = [np.eye(m)]
+    for _ in range(max(T, 2)):
+        pw.append(pw[-1] @ Abar)
+    g = dy @ C  # row l is (C^T dy_l)^T
+    gA = np.zeros((m, m))
+    gB = np.zeros_like(Bbar)
+    gu = np.zeros_like(u)
+    xs = np.zeros((L, m))
+    for l in range(L):
+        for j in range(min(l, T - 1) + 1):
+            xs[l] += pw[j] @ Bbar @ u[l - j]
+            # gradient w.r.t. u_{l-j} and Bbar through the term Abar^j Bbar u_{l-j}
+            lamj = pw[j].T @ g[l]
+            gu[l - j] += Bbar.T @ lamj
+            gB += np.outer(lamj, u[l - j])
+            for a in range(j):
+                b = j - 1 - a
+                gA += np.outer(pw[a].T @ g[l], pw[b] @ Bbar @ u[l - j])
+    gu += dy @ D
+    gC = dy.T @ xs
+    gD = dy.T @ u
+    return {"u": gu, "Abar": gA, "Bbar": gB, "C": gC, "D": gD}
+
+
+def grads_full(A, B, C, D, delta, u, dy, N=None):
+    """Gradients of sum(dy * y) w.r.t. (u, A, B, C, D) through the trapezoidal
+    discretization. Uses BPTT when N is None or 2^(N+1) >= L, else brute force.
+    """
+    Abar, Bbar = trapezoid(A, B, delta)
+    u = _as_matrix_u(u)
+    L = u.shape[0]
+    if N is None or (1 << (N + 1)) >= L:
+        g = grads_recursion(Abar, Bbar, C, D, u, dy)
+    else:
+        g = grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N)
+    gA, gB = trapezoid_adjoint(A, B, delta, g["Abar"], g["Bbar"])
+    return {"u": g["u"], "A": gA, "B": gB, "C": g["C"], "D": g["D"],
+            "Abar": g["Abar"], "Bbar": g["Bbar"]}
