@@ -1,0 +1,225 @@
+/*
+ * ssm_cascade.h -- C ABI of the MI355X (gfx950) fast-cascade library.
+ *
+ * The library applies the transfer function of a discrete linear
+ * time-invariant state-space model,
+ *     H(z) = C (I - z^{-1} Abar)^{-1} Bbar + D            (eq. (1.3)),
+ * in the time domain through the truncated cascade of §2-§3 of Beylkin,
+ * "Fast convolution algorithm for state space models" (arXiv 2411.17729):
+ * (I - z^{-1} Abar)^{-1} is replaced by the degree-(2^{N+1}-1) polynomial
+ * prod_{k=0..N} (I + z^{-2^k} Abar^{2^k})  (eq. (2.2)), so stage k is the
+ * shifted update  x_l <- x_l + Abar^{2^k} x_{l-2^k}  for 2^k <= l < L
+ * (eqs. (3.2)-(3.4) and the general step of §3), applied to all time steps
+ * at once. The input is v_l = Bbar u_l and the output y_l = C x_l + D u_l.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrices are dense and row-major. Sequences are stored time-major:
+ *    u of one sequence is an (L x p) block, y an (L x q) block; many
+ *    sequences are packed into one buffer at caller-chosen element offsets.
+ *  - Pointers documented as "device" point to memory from hipMalloc (or a
+ *    caching allocator on top of it) on the device that is current when the
+ *    call is made. Pointers documented as "host" are ordinary host memory.
+ *  - The caller owns every buffer: parameters, inputs, outputs, gradients and
+ *    the workspace. The library never allocates or frees device memory; a
+ *    plan is a small host object holding copied descriptors and pointers into
+ *    the caller's workspace, which must stay allocated and untouched while the
+ *    plan lives.
+ *  - Work is enqueued on the given stream (0 = the legacy default stream).
+ *    Apart from ssm_cascade_prepare (which synchronizes the stream once to
+ *    report numerical failure of the discretization), no entry point blocks
+ *    the host, so apply, backward and recursion may be captured into a HIP
+ *    graph. A plan must be used on one stream at a time.
+ *  - Every argument is checked on the host before anything is enqueued;
+ *    an invalid argument returns SSM_E_INVALID (or SSM_E_WORKSPACE for a
+ *    short workspace) and enqueues nothing. A failed kernel launch returns
+ *    SSM_E_HIP. Faults inside kernels surface at the caller's next
+ *    synchronization. NaN and Inf propagate; they are not checked.
+ *    ssm_last_error() returns a thread-local message describing the most
+ *    recent failure. Nothing throws across this ABI.
+ *  - Supported sizes: 1 <= m <= 256, 1 <= p <= m, 1 <= q <= m, L >= 1,
+ *    0 <= N <= 62. Internally the state is padded to 32, 64, 128 or 256.
+ */
+#ifndef SSM_CASCADE_H
+#define SSM_CASCADE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SSM_OK = 0,
+  SSM_E_INVALID = 1,      /* bad argument (null pointer, size, offset, dtype) */
+  SSM_E_UNSUPPORTED = 2,  /* valid request the library does not implement */
+  SSM_E_WORKSPACE = 3,    /* workspace smaller than ssm_cascade_workspace_bytes() */
+  SSM_E_HIP = 4,          /* a HIP runtime call or kernel launch failed */
+  SSM_E_NOT_PREPARED = 5, /* plan is null or was prepared without what the call needs */
+  SSM_E_NUMERIC = 6       /* I - delta/2 A is singular to working precision */
+} ssm_status;
+
+typedef enum {
+  SSM_F64 = 0,  /* IEEE binary64 */
+  SSM_F32 = 1,  /* IEEE binary32 */
+  SSM_BF16 = 2  /* bfloat16 (8-bit significand), round-to-nearest-even */
+} ssm_dtype;
+
+typedef enum {
+  /* Trapezoidal rule of §1 (the formulas after eq. (1.2)):
+   *   Abar = (I - delta/2 A)^{-1} (I + delta/2 A),  Bbar = delta (I - delta/2 A)^{-1} B. */
+  SSM_DISC_TRAPEZOID = 0,
+  /* A and B are already the discrete Abar and Bbar of eq. (1.2); delta is ignored. */
+  SSM_DISC_GIVEN = 1
+} ssm_disc;
+
+/* One sequence of a (possibly ragged) batch. Host memory. */
+typedef struct {
+  int32_t m, p, q;     /* state, input and output sizes; must equal its parameter set's */
+  int32_t N;           /* highest cascade stage: stages k = 0..N, degree 2^{N+1}-1 (eq. (2.2)) */
+  int64_t L;           /* number of time steps */
+  double delta;        /* trapezoidal step size (> 0); ignored for SSM_DISC_GIVEN */
+  int32_t param_set;   /* index into the ssm_params array */
+  int32_t reserved;    /* must be 0 */
+  int64_t u_offset;    /* element offset of this sequence's (L x p) input block */
+  int64_t y_offset;    /* element offset of this sequence's (L x q) output block */
+} ssm_seq_desc;
+
+/* One parameter set of the continuous model eq. (1.1) (or of the discrete
+ * model when SSM_DISC_GIVEN). Device pointers to FP64 row-major matrices:
+ * A (m x m), B (m x p), C (q x m), D (q x p). Read only during prepare. */
+typedef struct {
+  const double* A;
+  const double* B;
+  const double* C;
+  const double* D;
+  int32_t m, p, q;
+  int32_t reserved; /* must be 0 */
+} ssm_params;
+
+/* Gradients of the parameters are written to one flat FP64 device buffer:
+ * for each parameter set in order, dA (m x m), dB (m x p), dC (q x m) and
+ * dD (q x p), row-major and back to back, i.e. m*m + m*p + q*m + q*p
+ * doubles per set (ssm_cascade_param_grad_numel gives the total). */
+/* Plan summary, filled by ssm_cascade_plan_info (host memory). */
+typedef struct {
+  int32_t n_seq, n_ops;      /* sequences; distinct (parameter set, delta) operators */
+  int32_t compute;           /* ssm_dtype of the stage contractions */
+  int32_t max_stage;         /* largest stage index run by any sequence */
+  int64_t total_steps;       /* sum of L over sequences */
+  double stage_flops;        /* sum over sequences and run stages of 2 m^2 (L - 2^k) */
+  double io_flops;           /* 2 m p L (input) + 2 q (m + p) L (output), summed */
+  double stage_bytes;        /* algorithmic HBM bytes of the stage launches (see below) */
+  int64_t stage_launches;    /* kernel launches of the stage kernel per apply */
+} ssm_plan_info;
+
+typedef struct ssm_plan_s* ssm_plan;
+
+/* Bytes of device workspace ssm_cascade_prepare needs for this batch.
+ * with_backward != 0 reserves what ssm_cascade_backward needs as well: the
+ * adjoint ping-pong buffers, per-stage partial sums and the stage-input
+ * checkpoints. ckpt_every selects how many stage inputs the backward keeps:
+ * 1 keeps every stage input, c >= 2 keeps every c-th one and recomputes the
+ * others segment by segment, 0 picks c = ceil(sqrt(number of stages)).
+ * Returns 0 if the descriptors are invalid (ssm_last_error() says why). */
+size_t ssm_cascade_workspace_bytes(const ssm_seq_desc* seqs, int32_t n_seq,
+                                   ssm_disc disc, ssm_dtype compute,
+                                   int32_t with_backward, int32_t ckpt_every);
+
+/* Discretize, take the powers and pack them (the precomputation of §2-§3:
+ * Abar^{2^k} by repeated squaring, k = 0..N). seqs: host array of n_seq
+ * descriptors; sets: host array of n_sets ssm_params holding device
+ * pointers. compute: SSM_F64, SSM_F32 or SSM_BF16 -- the operand type of the
+ * stage contractions (accumulation is FP32 for F32/BF16 and FP64 for F64).
+ * Discretization and squaring always run in FP64 on the GPU. Sequences
+ * sharing (param_set, delta) share one operator (sharing param_set alone for
+ * SSM_DISC_GIVEN). ws: device workspace of ws_bytes >=
+ * ssm_cascade_workspace_bytes(seqs, n_seq, disc, compute, with_backward,
+ * ckpt_every). On success *out receives a new plan (free it with
+ * ssm_cascade_destroy). Synchronizes `stream` once at the end; returns
+ * SSM_E_NUMERIC if some I - delta/2 A was singular to working precision. */
+ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq,
+                               const ssm_params* sets, int32_t n_sets,
+                               ssm_disc disc, ssm_dtype compute,
+                               int32_t with_backward, int32_t ckpt_every,
+                               void* ws, size_t ws_bytes,
+                               hipStream_t stream, ssm_plan* out);
+
+/* Forward cascade, eqs. (3.2)-(3.4) and the general step of §3, then
+ * y_l = C x_l + D u_l. u: device, u_numel elements of u_dtype (SSM_F64 for
+ * an F64 plan; SSM_F32 or SSM_BF16 otherwise). y: device output, y_numel
+ * elements of double (F64 plan) or float (F32/BF16 plans). Every sequence's
+ * block must lie inside its buffer. */
+ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                             size_t u_numel, void* y, size_t y_numel,
+                             hipStream_t stream);
+
+/* Reverse-mode derivative of sum(dy * y) for y = apply(u): the adjoint cascade
+ * runs the transposed stages in reverse order with reversed shifts,
+ *     g_l <- g_l + (Abar^{2^k})^T g_{l+2^k},   k = N..0,
+ * recomputing stage inputs from checkpoints, and carries the gradient through
+ * the repeated squaring and the discretization. u, dy: device (dy has the
+ * layout and element type of y). du: device, u's layout in y's element type
+ * (float or double), or NULL. grad_params: device FP64 buffer of
+ * grad_numel >= ssm_cascade_param_grad_numel(plan) elements laid out as
+ * described above, or NULL; gradients of a set are summed over the
+ * sequences that use it, and the buffer is overwritten. Requires a plan
+ * prepared with with_backward != 0. */
+ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                                size_t u_numel, const void* dy, size_t dy_numel,
+                                void* du, double* grad_params, size_t grad_numel,
+                                hipStream_t stream);
+
+/* Number of doubles of the flat parameter-gradient buffer of a plan. */
+size_t ssm_cascade_param_grad_numel(ssm_plan plan);
+
+/* The plain recursion x_n = Abar x_{n-1} + Bbar u_n, y_n = C x_n + D u_n of
+ * eq. (1.2) on the GPU (one workgroup per sequence, L dependent steps), for
+ * comparison with the cascade. Same arguments as ssm_cascade_apply; runs in
+ * FP64 for an F64 plan and FP32 otherwise. It is the full (untruncated)
+ * recursion, so it equals the cascade when 2^{N+1} >= L. */
+ssm_status ssm_cascade_recursion(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                                 size_t u_numel, void* y, size_t y_numel,
+                                 hipStream_t stream);
+
+/* Copies the FP64 power Abar^{2^k} of operator `op` (the op-th distinct
+ * (param_set, delta) pair in order of first appearance in seqs) into the
+ * device buffer dst (m x m row-major, m of that operator), k = 0..N_op.
+ * Enqueued on `stream`. For verification of the precomputation. */
+ssm_status ssm_cascade_get_power(ssm_plan plan, int32_t op, int32_t k,
+                                 double* dst, hipStream_t stream);
+
+/* Copies Bbar (m x p) of operator `op` into dst (device, FP64). */
+ssm_status ssm_cascade_get_bbar(ssm_plan plan, int32_t op, double* dst,
+                                hipStream_t stream);
+
+/* Host-side summary of a plan. */
+ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);
+
+/* Per-launch timing with HIP events recorded on the launch stream.
+ * enable != 0 makes later apply/backward/recursion calls record an event pair
+ * around every kernel launch (this adds host work; leave it off otherwise).
+ * ssm_cascade_timing_read returns, for kernel class `kind`
+ * (0 = forward stage, 1 = adjoint stage, 2 = outer-product reduction,
+ *  3 = recursion), the number of timed launches and their summed milliseconds,
+ * after synchronizing the events, and clears the record. */
+ssm_status ssm_cascade_timing_enable(ssm_plan plan, int32_t enable);
+ssm_status ssm_cascade_timing_read(ssm_plan plan, int32_t kind, int64_t* launches,
+                                   double* total_ms);
+
+/* Frees the host plan (not the workspace). NULL is accepted. */
+ssm_status ssm_cascade_destroy(ssm_plan plan);
+
+/* Static string for a status code. */
+const char* ssm_status_string(ssm_status s);
+/* Thread-local detail of the most recent failure on this thread ("" if none). */
+const char* ssm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSM_CASCADE_H */

@@ -1,0 +1,205 @@
+"""ctypes binding of the C ABI in include/ssm_cascade.h.
+
+Argument marshalling only: every function here forwards to the entry point of
+the same name in libssm_cascade.so and raises ``SSMError`` on a non-OK status.
+Pointers are Python ints (e.g. ``tensor.data_ptr()``), streams are raw HIP
+stream handles (``torch.cuda.current_stream().cuda_stream``).
+
+torch is imported before the library is loaded, so the process maps one HIP
+runtime (the one torch ships) and torch's streams and allocations are valid
+handles for the library.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssm_cascade.so")
+
+SSM_OK, SSM_E_INVALID, SSM_E_UNSUPPORTED, SSM_E_WORKSPACE, SSM_E_HIP, SSM_E_NOT_PREPARED, SSM_E_NUMERIC = range(7)
+SSM_F64, SSM_F32, SSM_BF16 = 0, 1, 2
+SSM_DISC_TRAPEZOID, SSM_DISC_GIVEN = 0, 1
+
+# kernel classes of ssm_cascade_timing_read
+TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION = 0, 1, 2, 3
+
+
+class SSMError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class ssm_seq_desc(C.Structure):
+    _fields_ = [
+        ("m", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("N", C.c_int32),
+        ("L", C.c_int64), ("delta", C.c_double),
+        ("param_set", C.c_int32), ("reserved", C.c_int32),
+        ("u_offset", C.c_int64), ("y_offset", C.c_int64),
+    ]
+
+
+class ssm_params(C.Structure):
+    _fields_ = [
+        ("A", C.c_void_p), ("B", C.c_void_p), ("C", C.c_void_p), ("D", C.c_void_p),
+        ("m", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class ssm_plan_info(C.Structure):
+    _fields_ = [
+        ("n_seq", C.c_int32), ("n_ops", C.c_int32), ("compute", C.c_int32), ("max_stage", C.c_int32),
+        ("total_steps", C.c_int64), ("stage_flops", C.c_double), ("io_flops", C.c_double),
+        ("stage_bytes", C.c_double), ("stage_launches", C.c_int64),
+    ]
+
+
+_lib = None
+
+EXPORTS = [
+    "ssm_cascade_workspace_bytes", "ssm_cascade_prepare", "ssm_cascade_apply",
+    "ssm_cascade_backward", "ssm_cascade_param_grad_numel", "ssm_cascade_recursion",
+    "ssm_cascade_get_power", "ssm_cascade_get_bbar", "ssm_cascade_plan_info",
+    "ssm_cascade_timing_enable", "ssm_cascade_timing_read", "ssm_cascade_destroy",
+    "ssm_status_string", "ssm_last_error",
+]
+
+
+def load(path=LIB_PATH):
+    """Load the library (once). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2411_17729_amd.build.build()")
+    lib = C.CDLL(path)
+    vp, i32, i64, sz, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
+    P = C.POINTER
+    lib.ssm_cascade_workspace_bytes.restype = sz
+    lib.ssm_cascade_workspace_bytes.argtypes = [P(ssm_seq_desc), i32, i32, i32, i32, i32]
+    lib.ssm_cascade_prepare.restype = i32
+    lib.ssm_cascade_prepare.argtypes = [P(ssm_seq_desc), i32, P(ssm_params), i32, i32, i32, i32,
+                                        i32, vp, sz, vp, P(vp)]
+    lib.ssm_cascade_apply.restype = i32
+    lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
+    lib.ssm_cascade_recursion.restype = i32
+    lib.ssm_cascade_recursion.argtypes = [vp, vp, i32, sz, vp, sz, vp]
+    lib.ssm_cascade_backward.restype = i32
+    lib.ssm_cascade_backward.argtypes = [vp, vp, i32, sz, vp, sz, vp, vp, sz, vp]
+    lib.ssm_cascade_param_grad_numel.restype = sz
+    lib.ssm_cascade_param_grad_numel.argtypes = [vp]
+    lib.ssm_cascade_get_power.restype = i32
+    lib.ssm_cascade_get_power.argtypes = [vp, i32, i32, vp, vp]
+    lib.ssm_cascade_get_bbar.restype = i32
+    lib.ssm_cascade_get_bbar.argtypes = [vp, i32, vp, vp]
+    lib.ssm_cascade_plan_info.restype = i32
+    lib.ssm_cascade_plan_info.argtypes = [vp, P(ssm_plan_info)]
+    lib.ssm_cascade_timing_enable.restype = i32
+    lib.ssm_cascade_timing_enable.argtypes = [vp, i32]
+    lib.ssm_cascade_timing_read.restype = i32
+    lib.ssm_cascade_timing_read.argtypes = [vp, i32, P(i64), P(dbl)]
+    lib.ssm_cascade_destroy.restype = i32
+    lib.ssm_cascade_destroy.argtypes = [vp]
+    lib.ssm_status_string.restype = C.c_char_p
+    lib.ssm_status_string.argtypes = [i32]
+    lib.ssm_last_error.restype = C.c_char_p
+    lib.ssm_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status, where):
+    if status != SSM_OK:
+        lib = load()
+        raise SSMError(status, where, lib.ssm_last_error().decode())
+
+
+def ssm_status_string(status):
+    return load().ssm_status_string(status).decode()
+
+
+def ssm_last_error():
+    return load().ssm_last_error().decode()
+
+
+def _descs(descs):
+    arr = (ssm_seq_desc * len(descs))()
+    for i, d in enumerate(descs):
+        arr[i] = d if isinstance(d, ssm_seq_desc) else ssm_seq_desc(**d)
+    return arr
+
+
+def ssm_cascade_workspace_bytes(descs, disc, compute, with_backward, ckpt_every=0):
+    arr = _descs(descs)
+    n = load().ssm_cascade_workspace_bytes(arr, len(descs), disc, compute, int(with_backward),
+                                           ckpt_every)
+    if n == 0:
+        raise SSMError(SSM_E_INVALID, "ssm_cascade_workspace_bytes", ssm_last_error())
+    return n
+
+
+def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every, ws_ptr,
+                        ws_bytes, stream):
+    arr = _descs(descs)
+    parr = (ssm_params * len(params))()
+    for i, p in enumerate(params):
+        parr[i] = p if isinstance(p, ssm_params) else ssm_params(**p)
+    plan = C.c_void_p()
+    _check(load().ssm_cascade_prepare(arr, len(descs), parr, len(params), disc, compute,
+                                      int(with_backward), ckpt_every, ws_ptr, ws_bytes, stream,
+                                      C.byref(plan)), "ssm_cascade_prepare")
+    return plan.value
+
+
+def ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
+    _check(load().ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
+           "ssm_cascade_apply")
+
+
+def ssm_cascade_recursion(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
+    _check(load().ssm_cascade_recursion(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
+           "ssm_cascade_recursion")
+
+
+def ssm_cascade_backward(plan, u_ptr, u_dtype, u_numel, dy_ptr, dy_numel, du_ptr, grad_ptr,
+                         grad_numel, stream):
+    _check(load().ssm_cascade_backward(plan, u_ptr, u_dtype, u_numel, dy_ptr, dy_numel, du_ptr,
+                                       grad_ptr, grad_numel, stream), "ssm_cascade_backward")
+
+
+def ssm_cascade_param_grad_numel(plan):
+    return load().ssm_cascade_param_grad_numel(plan)
+
+
+def ssm_cascade_get_power(plan, op, k, dst_ptr, stream):
+    _check(load().ssm_cascade_get_power(plan, op, k, dst_ptr, stream), "ssm_cascade_get_power")
+
+
+def ssm_cascade_get_bbar(plan, op, dst_ptr, stream):
+    _check(load().ssm_cascade_get_bbar(plan, op, dst_ptr, stream), "ssm_cascade_get_bbar")
+
+
+def ssm_cascade_plan_info(plan):
+    info = ssm_plan_info()
+    _check(load().ssm_cascade_plan_info(plan, C.byref(info)), "ssm_cascade_plan_info")
+    return {f: getattr(info, f) for f, _ in ssm_plan_info._fields_}
+
+
+def ssm_cascade_timing_enable(plan, enable):
+    _check(load().ssm_cascade_timing_enable(plan, int(enable)), "ssm_cascade_timing_enable")
+
+
+def ssm_cascade_timing_read(plan, kind):
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(load().ssm_cascade_timing_read(plan, kind, C.byref(n), C.byref(ms)),
+           "ssm_cascade_timing_read")
+    return n.value, ms.value
+
+
+def ssm_cascade_destroy(plan):
+    _check(load().ssm_cascade_destroy(plan), "ssm_cascade_destroy")

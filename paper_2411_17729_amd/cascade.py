@@ -1,0 +1,211 @@
+"""PyTorch-facing wrapper of the fast-cascade library.
+
+PyTorch provides device memory and streams; every arithmetic step of the
+path runs in the HIP kernels of libssm_cascade.so, reached through
+``binding``. There is no CPU fallback: without the built library or a GPU
+these classes raise.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+_DT = {"f64": B.SSM_F64, "f32": B.SSM_F32, "bf16": B.SSM_BF16}
+_TORCH_DT = {B.SSM_F64: torch.float64, B.SSM_F32: torch.float32, B.SSM_BF16: torch.bfloat16}
+
+
+def dtype_code(name):
+    return _DT[name] if isinstance(name, str) else int(name)
+
+
+@dataclass
+class Layout:
+    """Descriptors and packed-buffer sizes of a batch of sequences."""
+    descs: List[B.ssm_seq_desc]
+    u_numel: int
+    y_numel: int
+
+
+def make_layout(seqs: Sequence, sets_dims: Sequence) -> Layout:
+    """Sequences back to back in u and y. ``seqs`` items need .param_set,
+    .delta, .L, .N; ``sets_dims`` gives (m, p, q) per parameter set."""
+    descs = []
+    uo = yo = 0
+    for s in seqs:
+        m, p, q = sets_dims[s.param_set]
+        d = B.ssm_seq_desc(m=m, p=p, q=q, N=int(s.N), L=int(s.L), delta=float(s.delta),
+                           param_set=int(s.param_set), reserved=0, u_offset=uo, y_offset=yo)
+        descs.append(d)
+        uo += int(s.L) * p
+        yo += int(s.L) * q
+    return Layout(descs, uo, yo)
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+class CascadePlan:
+    """A prepared batch: discretized operators, their powers Abar^(2^k) in the
+    compute type, and the workspace (a torch uint8 tensor) the library carves."""
+
+    def __init__(self, layout: Layout, params: Sequence, disc: str = "trapezoid",
+                 compute: str = "f32", with_backward: bool = False, ckpt_every: int = 0,
+                 device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the fast-cascade library needs a ROCm GPU")
+        B.load()
+        self.layout = layout
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.compute = dtype_code(compute)
+        self.disc = B.SSM_DISC_GIVEN if disc == "given" else B.SSM_DISC_TRAPEZOID
+        self.state_dtype = torch.float64 if self.compute == B.SSM_F64 else torch.float32
+        # parameters as contiguous FP64 device tensors (kept alive for prepare)
+        self.params = []
+        cparams = []
+        for (A, Bm, Cm, D) in params:
+            ts = [torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64) if isinstance(x, np.ndarray) else x,
+                                  dtype=torch.float64, device=self.device).contiguous()
+                  for x in (A, Bm, Cm, D)]
+            self.params.append(ts)
+            m, p, q = ts[0].shape[0], ts[1].shape[1], ts[2].shape[0]
+            cparams.append(B.ssm_params(A=ts[0].data_ptr(), B=ts[1].data_ptr(), C=ts[2].data_ptr(),
+                                        D=ts[3].data_ptr(), m=m, p=p, q=q, reserved=0))
+        nbytes = B.ssm_cascade_workspace_bytes(layout.descs, self.disc, self.compute,
+                                               with_backward, ckpt_every)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.plan = B.ssm_cascade_prepare(layout.descs, cparams, self.disc, self.compute,
+                                          with_backward, ckpt_every, self.ws_ptr, nbytes, _stream())
+        self.with_backward = with_backward
+
+    # -- forward ---------------------------------------------------------
+    def apply(self, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        u = self._check_u(u)
+        if out is None:
+            out = torch.empty(self.layout.y_numel, dtype=self.state_dtype, device=self.device)
+        B.ssm_cascade_apply(self.plan, u.data_ptr(), self._u_code(u), u.numel(), out.data_ptr(),
+                            out.numel(), _stream())
+        return out
+
+    def recursion(self, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        u = self._check_u(u)
+        if out is None:
+            out = torch.empty(self.layout.y_numel, dtype=self.state_dtype, device=self.device)
+        B.ssm_cascade_recursion(self.plan, u.data_ptr(), self._u_code(u), u.numel(),
+                                out.data_ptr(), out.numel(), _stream())
+        return out
+
+    # -- backward --------------------------------------------------------
+    def backward(self, u: torch.Tensor, dy: torch.Tensor, want_du=True, want_params=True):
+        u = self._check_u(u)
+        if dy.dtype != self.state_dtype or not dy.is_contiguous() or dy.device != self.device:
+            raise ValueError("dy must be a contiguous device tensor of the state dtype")
+        du = torch.empty(self.layout.u_numel, dtype=self.state_dtype, device=self.device) if want_du else None
+        ng = B.ssm_cascade_param_grad_numel(self.plan)
+        g = torch.empty(ng, dtype=torch.float64, device=self.device) if want_params else None
+        B.ssm_cascade_backward(self.plan, u.data_ptr(), self._u_code(u), u.numel(), dy.data_ptr(),
+                               dy.numel(), du.data_ptr() if du is not None else None,
+                               g.data_ptr() if g is not None else None, ng if g is not None else 0,
+                               _stream())
+        return du, (self.split_param_grads(g) if g is not None else None)
+
+    def split_param_grads(self, g):
+        out = []
+        off = 0
+        for ts in self.params:
+            m, p, q = ts[0].shape[0], ts[1].shape[1], ts[2].shape[0]
+            parts = []
+            for (r, c) in ((m, m), (m, p), (q, m), (q, p)):
+                parts.append(g[off: off + r * c].view(r, c))
+                off += r * c
+            out.append(parts)
+        return out
+
+    # -- inspection ------------------------------------------------------
+    def power(self, op: int, k: int) -> torch.Tensor:
+        m = self._op_m(op)
+        out = torch.empty((m, m), dtype=torch.float64, device=self.device)
+        B.ssm_cascade_get_power(self.plan, op, k, out.data_ptr(), _stream())
+        return out
+
+    def bbar(self, op: int, m: int, p: int) -> torch.Tensor:
+        out = torch.empty((m, p), dtype=torch.float64, device=self.device)
+        B.ssm_cascade_get_bbar(self.plan, op, out.data_ptr(), _stream())
+        return out
+
+    def info(self):
+        return B.ssm_cascade_plan_info(self.plan)
+
+    def timing(self, enable: bool):
+        B.ssm_cascade_timing_enable(self.plan, enable)
+
+    def timing_read(self, kind: int):
+        return B.ssm_cascade_timing_read(self.plan, kind)
+
+    def _op_m(self, op):
+        # operators are numbered by first appearance of (param_set, delta)
+        seen = []
+        for d in self.layout.descs:
+            key = (d.param_set, d.delta if self.disc == B.SSM_DISC_TRAPEZOID else 0.0)
+            if key not in seen:
+                seen.append(key)
+                if len(seen) - 1 == op:
+                    return d.m
+        raise IndexError(op)
+
+    def _u_code(self, u):
+        return {torch.float64: B.SSM_F64, torch.float32: B.SSM_F32, torch.bfloat16: B.SSM_BF16}[u.dtype]
+
+    def _check_u(self, u):
+        if u.device != self.device or not u.is_contiguous():
+            raise ValueError("u must be a contiguous tensor on the plan's device")
+        return u
+
+    def close(self):
+        if getattr(self, "plan", None):
+            B.ssm_cascade_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, device="cuda"):
+    """Builds the layout and plan of a ``workloads.Workload``."""
+    dims = [(ps.m, ps.p, ps.q) for ps in wl.sets]
+    layout = make_layout(wl.seqs, dims)
+    params = [(ps.A, ps.B, ps.C, ps.D) for ps in wl.sets]
+    return CascadePlan(layout, params, disc="given" if wl.given else "trapezoid", compute=compute,
+                       with_backward=with_backward, ckpt_every=ckpt_every, device=device)
+
+
+def pack_u(wl, dtype=torch.float32, device="cuda"):
+    """All sequences' u back to back (matching ``make_layout``)."""
+    flat = np.concatenate([np.asarray(s.u, dtype=np.float64).reshape(-1) for s in wl.seqs])
+    return torch.as_tensor(flat, device=device).to(dtype).contiguous()
+
+
+def unpack_y(wl, y):
+    """Splits a packed output into per-sequence (L, q) numpy arrays."""
+    y = y.detach().double().cpu().numpy()
+    out = []
+    off = 0
+    for s in wl.seqs:
+        q = wl.sets[s.param_set].q
+        out.append(y[off: off + s.L * q].reshape(s.L, q))
+        off += s.L * q
+    return out

@@ -1,0 +1,349 @@
+// FP64 precomputation on the GPU: trapezoidal discretization (§1, the
+// formulas after eq. (1.2)), the powers Abar^(2^k) by repeated squaring
+// (end of §2, start of §3), and their cast to the stage compute type.
+#include <float.h>
+
+#include "ssm_internal.h"
+
+namespace ssmc {
+
+// ---------------------------------------------------------------------------
+// Setup of the trapezoid system per operator (blockIdx.y = operator).
+//   aug  = [ I - h A | I ]   (mp x 2mp; the padded block of I - hA is I)
+//   nmat = I + h A            (mp x mp; zero in the padding)
+//   bsc  = delta B            (mp x p)
+// For given discrete parameters, Abar goes straight to the k = 0 power slot
+// and Bbar to bbar.
+// ---------------------------------------------------------------------------
+__global__ void k_disc_setup(const OpDev* ops, const OpSrc* src, int given, double* aug,
+                             double* nmat, double* bsc, double* pw, double* bbar) {
+  const OpDev o = ops[blockIdx.y];
+  const OpSrc sp = src[blockIdx.y];
+  const int mp = o.mp, m = o.m, p = o.p;
+  const double h = 0.5 * o.delta;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t e = e0; e < (int64_t)mp * mp; e += stride) {
+    const int r = (int)(e / mp), c = (int)(e % mp);
+    const bool in = r < m && c < m;
+    const double a = in ? sp.A[(int64_t)r * m + c] : 0.0;
+    const double id = r == c ? 1.0 : 0.0;
+    if (given) {
+      pw[o.pw + e] = a;
+    } else {
+      double* ag = aug + o.sc_aug + (int64_t)r * 2 * mp;
+      ag[c] = in ? id - h * a : id;
+      ag[mp + c] = id;
+      nmat[o.sc_n + e] = in ? id + h * a : 0.0;
+    }
+  }
+  for (int64_t e = e0; e < (int64_t)mp * p; e += stride) {
+    const int r = (int)(e / p), c = (int)(e % p);
+    const double bv = r < m ? sp.B[(int64_t)r * p + c] : 0.0;
+    if (given)
+      bbar[o.bbar + e] = bv;
+    else
+      bsc[o.sc_b + e] = o.delta * bv;
+  }
+}
+
+hipError_t launch_disc_setup(const OpDev* ops, int n_ops, const OpSrc* src, int given,
+                             double* aug, double* nmat, double* bsc, double* pw,
+                             double* bbar, int max_mp, hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  const int blocks = (max_mp * max_mp + 255) / 256;
+  hipLaunchKernelGGL(k_disc_setup, dim3(blocks < 256 ? blocks : 256, n_ops), dim3(256), 0, s,
+                     ops, src, given, aug, nmat, bsc, pw, bbar);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan elimination with partial pivoting, one workgroup per operator:
+// [M | I] -> [I | M^{-1}], then M^{-1} is copied to its slot. A pivot below
+// mp * eps * max|M| marks the operator as numerically singular.
+// ---------------------------------------------------------------------------
+constexpr int GJ_THREADS = 1024;
+
+__device__ void block_argmax(double v, int idx, double* sv, int* si, double* out_v, int* out_i) {
+  // larger value wins; on ties the smaller index
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sv[w] = v;
+    si[w] = idx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = sv[0];
+    int bi = si[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      if (sv[i] > bv || (sv[i] == bv && si[i] < bi)) {
+        bv = sv[i];
+        bi = si[i];
+      }
+    }
+    *out_v = bv;
+    *out_i = bi;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(GJ_THREADS) void k_gauss_jordan(const OpDev* ops, double* aug,
+                                                             double* minv, int* status) {
+  const OpDev o = ops[blockIdx.x];
+  const int mp = o.mp, W = 2 * mp;
+  double* a = aug + o.sc_aug;
+  __shared__ double fac[256];
+  __shared__ double red_v[GJ_THREADS / 64];
+  __shared__ int red_i[GJ_THREADS / 64];
+  __shared__ double s_v;
+  __shared__ int s_i;
+  const int tid = threadIdx.x;
+
+  // scale for the singularity threshold
+  double mx = 0.0;
+  for (int e = tid; e < mp * mp; e += GJ_THREADS) mx = fmax(mx, fabs(a[(e / mp) * W + (e % mp)]));
+  block_argmax(mx, 0, red_v, red_i, &s_v, &s_i);
+  const double thresh = (double)mp * DBL_EPSILON * s_v;
+
+  for (int c = 0; c < mp; ++c) {
+    double best = -1.0;
+    int bi = c;
+    for (int r = c + tid; r < mp; r += GJ_THREADS) {
+      const double v = fabs(a[(int64_t)r * W + c]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    block_argmax(best, bi, red_v, red_i, &s_v, &s_i);
+    const int piv = s_i;
+    if (tid == 0 && !(s_v > thresh)) atomicOr(status, 1);
+    if (piv != c) {
+      for (int j = tid; j < W; j += GJ_THREADS) {
+        const double t0 = a[(int64_t)c * W + j];
+        a[(int64_t)c * W + j] = a[(int64_t)piv * W + j];
+        a[(int64_t)piv * W + j] = t0;
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / a[(int64_t)c * W + c];
+    __syncthreads();
+    for (int j = c + tid; j < W; j += GJ_THREADS) a[(int64_t)c * W + j] *= inv;
+    for (int r = tid; r < mp; r += GJ_THREADS) fac[r] = r == c ? 0.0 : a[(int64_t)r * W + c];
+    __syncthreads();
+    const int span = W - c;
+    for (int e = tid; e < mp * span; e += GJ_THREADS) {
+      const int r = e / span, j = c + e % span;
+      const double f = fac[r];
+      if (f != 0.0) a[(int64_t)r * W + j] -= f * a[(int64_t)c * W + j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < mp * mp; e += GJ_THREADS)
+    minv[o.minv + e] = a[(int64_t)(e / mp) * W + mp + (e % mp)];
+}
+
+hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double* minv,
+                               int* status, hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(n_ops), dim3(GJ_THREADS), 0, s, ops, aug, minv,
+                     status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP64 GEMM, C = alpha op(A) op(B) + beta C (row-major), on the FP64
+// matrix cores: 64x64 output tile per workgroup, each of the 4 waves owns a
+// 32x32 quarter as 2x2 blocks of v_mfma_f64_16x16x4f64. blockIdx.z = job.
+// Lane layout of the 16x16x4 FP64 MFMA: A[i=lane%16][k=lane/16],
+// B[k=lane/16][j=lane%16], C[i=lane/16+4v][j=lane%16] (register v).
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmJob* jobs) {
+  const GemmJob jb = jobs[blockIdx.z];
+  const int tm = blockIdx.y * 64, tn = blockIdx.x * 64;
+  if (tm >= jb.M || tn >= jb.N) return;
+  constexpr int KT = 16;
+  __shared__ double As[64][KT + 1];  // As[i][k] = op(A)(tm+i, k0+k)
+  __shared__ double Bs[64][KT + 1];  // Bs[j][k] = op(B)(k0+k, tn+j)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  f64x4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < jb.K; k0 += KT) {
+    __syncthreads();
+    for (int e = tid; e < 64 * KT; e += 256) {
+      int i, kk;
+      if (jb.transA) {  // A stored K x M: consecutive i contiguous
+        i = e % 64;
+        kk = e / 64;
+      } else {
+        i = e / KT;
+        kk = e % KT;
+      }
+      const int gi = tm + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < jb.M && gk < jb.K)
+        v = jb.transA ? jb.A[(int64_t)gk * jb.lda + gi] : jb.A[(int64_t)gi * jb.lda + gk];
+      As[i][kk] = v;
+    }
+    for (int e = tid; e < 64 * KT; e += 256) {
+      int j, kk;
+      if (jb.transB) {  // B stored N x K: consecutive k contiguous
+        j = e / KT;
+        kk = e % KT;
+      } else {
+        j = e % 64;
+        kk = e / 64;
+      }
+      const int gj = tn + j, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < jb.N && gk < jb.K)
+        v = jb.transB ? jb.B[(int64_t)gj * jb.ldb + gk] : jb.B[(int64_t)gk * jb.ldb + gj];
+      Bs[j][kk] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KT; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      const double a0 = As[wi + (lane & 15)][kk];
+      const double a1 = As[wi + 16 + (lane & 15)][kk];
+      const double b0 = Bs[wj + (lane & 15)][kk];
+      const double b1 = Bs[wj + 16 + (lane & 15)][kk];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  for (int a = 0; a < 2; ++a) {
+    for (int b = 0; b < 2; ++b) {
+      const int gj = tn + wj + b * 16 + (lane & 15);
+      for (int v = 0; v < 4; ++v) {
+        const int gi = tm + wi + a * 16 + (lane >> 4) + 4 * v;
+        if (gi < jb.M && gj < jb.N) {
+          double* cp = jb.C + (int64_t)gi * jb.ldc + gj;
+          const double r = jb.alpha * acc[a][b][v];
+          *cp = jb.beta == 0.0 ? r : r + jb.beta * *cp;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_gemm_f64(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n,
+                           hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  dim3 grid((max_n + 63) / 64, (max_m + 63) / 64, n_jobs);
+  hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, s, jobs_dev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cast of the powers to the compute type and of the small matrices to the
+// state type. FP64 -> bfloat16 is rounded once, to nearest even, straight
+// from the FP64 value (no intermediate FP32 rounding) in the FP32 normal
+// range; below it the value goes through FP32 first.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f64_to_bf16_bits(double d) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(d);
+  const uint64_t sign = bits & 0x8000000000000000ull;
+  uint64_t mag = bits & 0x7fffffffffffffffull;
+  if (mag > 0x7ff0000000000000ull) return (uint16_t)((sign >> 48) | 0x7fc0u);  // NaN
+  if (mag < (uint64_t)(1023 - 126) << 52) {  // below FP32 normal range
+    const uint32_t u = __float_as_uint((float)d);
+    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+  }
+  // keep 7 fraction bits: drop the low 45 bits with round-to-nearest-even
+  const uint64_t lsb = (mag >> 45) & 1ull;
+  mag += (1ull << 44) - 1ull + lsb;
+  mag &= ~((1ull << 45) - 1ull);
+  const float f = (float)__longlong_as_double((long long)(sign | mag));  // exact (or inf)
+  return (uint16_t)(__float_as_uint(f) >> 16);
+}
+
+__global__ void k_pack_powers(const OpDev* ops, const double* pw, void* pc, int ct, int want_t) {
+  const OpDev o = ops[blockIdx.y];
+  const int mp = o.mp;
+  const int64_t n = (int64_t)(o.N + 1) * mp * mp;
+  const int64_t mm = (int64_t)mp * mp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = pw[o.pw + e];
+    const int64_t kslot = e / mm, rc = e % mm;
+    const int64_t r = rc / mp, c = rc % mp;
+    const int64_t et = kslot * mm + c * mp + r;  // transposed position
+    if (ct == DT_BF16) {
+      const uint16_t b = f64_to_bf16_bits(v);
+      ((uint16_t*)pc)[o.pc + e] = b;
+      if (want_t) ((uint16_t*)pc)[o.pct + et] = b;
+    } else if (ct == DT_F32) {
+      const float f = (float)v;
+      ((float*)pc)[o.pc + e] = f;
+      if (want_t) ((float*)pc)[o.pct + et] = f;
+    } else {
+      ((double*)pc)[o.pc + e] = v;
+      if (want_t) ((double*)pc)[o.pct + et] = v;
+    }
+  }
+}
+
+template <typename X>
+__global__ void k_pack_small(const OpDev* ops, const OpSrc* src, const double* bbar, X* sm) {
+  const OpDev o = ops[blockIdx.y];
+  const OpSrc sp = src[blockIdx.y];
+  const int mp = o.mp, m = o.m, p = o.p, q = o.q;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+  for (int e = tid; e < mp * p; e += nth) {  // Bbar (mp x p) and Bbar^T (p x mp)
+    const int r = e / p, c = e % p;
+    const X v = (X)bbar[o.bbar + e];
+    sm[o.bin + e] = v;
+    sm[o.bt + (int64_t)c * mp + r] = v;
+  }
+  for (int e = tid; e < q * mp; e += nth) {  // C (q x mp) and C^T (mp x q)
+    const int r = e / mp, c = e % mp;
+    const X v = c < m ? (X)sp.C[(int64_t)r * m + c] : (X)0;
+    sm[o.cout + e] = v;
+    sm[o.ct + (int64_t)c * q + r] = v;
+  }
+  for (int e = tid; e < q * p; e += nth) {  // D (q x p) and D^T (p x q)
+    const int r = e / p, c = e % p;
+    const X v = (X)sp.D[(int64_t)r * p + c];
+    sm[o.dmat + e] = v;
+    sm[o.dt + (int64_t)c * q + r] = v;
+  }
+}
+
+hipError_t launch_pack(const OpDev* ops, int n_ops, const OpSrc* src, const double* pw,
+                       const double* bbar, void* pc, int ct, int want_t, void* small,
+                       int state_is_f64, int max_mp, int max_N, hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  const int64_t n = (int64_t)(max_N + 1) * max_mp * max_mp;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_pack_powers, dim3(blocks, n_ops), dim3(256), 0, s, ops, pw, pc, ct,
+                     want_t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (state_is_f64)
+    hipLaunchKernelGGL(k_pack_small<double>, dim3(8, n_ops), dim3(256), 0, s, ops, src, bbar,
+                       (double*)small);
+  else
+    hipLaunchKernelGGL(k_pack_small<float>, dim3(8, n_ops), dim3(256), 0, s, ops, src, bbar,
+                       (float*)small);
+  return hipGetLastError();
+}
+
+}  // namespace ssmc

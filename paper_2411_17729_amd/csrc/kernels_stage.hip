@@ -1,0 +1,356 @@
+// Stage kernel of the fast cascade (§3 of Beylkin, arXiv 2411.17729).
+//
+// One launch applies stage k to every row tile of every sequence:
+//   forward  (eqs. (3.2)-(3.4), general step):  x_l <- x_l + P_k x_{l-2^k},   2^k <= l < L
+//   adjoint  (transpose, reversed shift):        g_l <- g_l + P_k^T g_{l+2^k}, l + 2^k < L
+// with P_k = Abar^(2^k). Rows without a partner are copied. The state is
+// stored time-major (L x mp per sequence), so a time shift is a row offset
+// and each row tile is a dense GEMM  OUT[tile] = IN[tile] + IN[tile - s] * P_k^T
+// of shape BM x mp x mp. The unshifted rows initialise the MFMA accumulators,
+// so the stage's addition is the accumulate of the matrix cores.
+//
+// At the first stage of a direction the input rows are formed on the fly from
+// the sequence input (v_l = Bbar u_l forward, g_l = C^T dy_l adjoint); at the
+// last stage the output rows are written instead of (or besides) the state
+// (y_l = C x_l + D u_l forward, du_l = Bbar^T g_l + D^T dy_l adjoint).
+#include "ssm_internal.h"
+
+namespace ssmc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// FP32 -> bfloat16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+
+template <int CT>
+struct CTraits;
+template <>
+struct CTraits<DT_BF16> {
+  using X = float;      // state / accumulator element
+  using Op = uint16_t;  // MFMA operand element (bf16 bits)
+  using Acc = f32x4;
+  static constexpr int KI = 32;  // K of one 16x16 MFMA
+  static constexpr int KPL = 8;  // K elements per lane
+  static constexpr int PAD = 8;  // LDS row padding (elements)
+  // accumulator register v of lane group g holds row 4g + v of the 16x16 block
+  static __device__ __forceinline__ int acc_row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct CTraits<DT_F32> {
+  using X = float;
+  using Op = float;
+  using Acc = f32x4;
+  static constexpr int KI = 4;
+  static constexpr int KPL = 1;
+  static constexpr int PAD = 4;  // keeps LDS rows 16-byte aligned
+  static __device__ __forceinline__ int acc_row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct CTraits<DT_F64> {
+  using X = double;
+  using Op = double;
+  using Acc = f64x4;
+  static constexpr int KI = 4;
+  static constexpr int KPL = 1;
+  static constexpr int PAD = 2;  // keeps LDS rows 16-byte aligned
+  // the FP64 16x16x4 MFMA interleaves rows: register v of lane group g is row g + 4v
+  static __device__ __forceinline__ int acc_row(int g, int v) { return g + 4 * v; }
+};
+
+template <typename Op, typename X>
+__device__ __forceinline__ Op to_op(X v);
+template <>
+__device__ __forceinline__ uint16_t to_op<uint16_t, float>(float v) {
+  return f32_to_bf16_bits(v);
+}
+template <>
+__device__ __forceinline__ float to_op<float, float>(float v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ double to_op<double, double>(double v) {
+  return v;
+}
+
+template <typename X>
+__device__ __forceinline__ X load_src(const void* src, int dtype, int64_t i) {
+  if (dtype == DT_F64) return (X)((const double*)src)[i];
+  if (dtype == DT_F32) return (X)((const float*)src)[i];
+  return (X)bf16_bits_to_f32(((const uint16_t*)src)[i]);
+}
+
+// One 16x16 MFMA step for each compute type.
+template <int CT>
+struct Mfma;
+template <>
+struct Mfma<DT_BF16> {
+  static __device__ __forceinline__ f32x4 run(const uint16_t* a, const uint16_t* b, f32x4 c) {
+    bf16x8 av = *reinterpret_cast<const bf16x8*>(a);
+    bf16x8 bv = *reinterpret_cast<const bf16x8*>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<DT_F32> {
+  static __device__ __forceinline__ f32x4 run(const float* a, const float* b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<DT_F64> {
+  static __device__ __forceinline__ f64x4 run(const double* a, const double* b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(*a, *b, c, 0, 0, 0);
+  }
+};
+
+template <int MP, int CT>
+struct StageCfg {
+  using TR = CTraits<CT>;
+  using X = typename TR::X;
+  using Op = typename TR::Op;
+  static constexpr int WC = MP >= 64 ? 4 : 2;  // waves across the state columns
+  static constexpr int WR = 4 / WC;            // waves across the rows
+  static constexpr int CW = MP / WC;           // columns per wave
+  static constexpr int CB = CW / 16;           // 16-column blocks per wave
+  static constexpr int BM = stage_bm(MP, CT);  // rows per tile
+  static constexpr int RB = BM / (WR * 16);    // 16-row blocks per wave
+  static constexpr int KC0 = 128 / (int)sizeof(Op);
+  static constexpr int KC = KC0 < MP ? KC0 : MP;  // K chunk staged in LDS
+  static constexpr int NCH = MP / KC;
+  static constexpr int KSTEPS = KC / TR::KI;
+  static constexpr int SA = KC + TR::PAD;  // LDS row stride (elements)
+  static constexpr int SE = MP + 1;        // epilogue row stride
+  static constexpr size_t LDS_MM = (size_t)(BM + MP) * SA * sizeof(Op);
+  static constexpr size_t LDS_EPI = (size_t)WR * 16 * SE * sizeof(X);
+  static constexpr size_t LDS = LDS_MM > LDS_EPI ? LDS_MM : LDS_EPI;
+  static_assert(RB >= 1 && RB * WR * 16 == BM, "tile rows");
+  static_assert(KSTEPS >= 1 && NCH * KC == MP, "K chunking");
+  static_assert((SA * sizeof(Op)) % 16 == 0, "LDS rows must stay 16-byte aligned");
+};
+
+template <int MP, int CT>
+__global__ __launch_bounds__(256) void k_stage(StageParams prm) {
+  using C = StageCfg<MP, CT>;
+  using X = typename C::X;
+  using Op = typename C::Op;
+  using TR = typename C::TR;
+  using Acc = typename TR::Acc;
+  constexpr int BM = C::BM, RB = C::RB, CB = C::CB, CW = C::CW, WC = C::WC, WR = C::WR;
+  constexpr int KC = C::KC, SA = C::SA, SE = C::SE;
+
+  __shared__ __attribute__((aligned(16))) unsigned char smem[C::LDS];
+  Op* As = reinterpret_cast<Op*>(smem);
+  Op* Bs = As + BM * SA;
+  X* Es = reinterpret_cast<X*>(smem);
+
+  // Consecutive tiles to one XCD: hardware hands workgroups to the 8 XCDs
+  // round-robin, so tile t of XCD x is start_x + blockIdx.x / 8.
+  const int nt = prm.n_tiles;
+  const int b = blockIdx.x;
+  const int xcd = b & 7, per = nt >> 3, rem = nt & 7;
+  const int tix = xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
+  const Tile t = prm.tiles[tix];
+  const SeqDev sq = prm.seqs[t.seq];
+  const OpDev o = prm.ops[sq.op];
+
+  const bool noupd = (prm.flags & SF_NOUPDATE) != 0;
+  const int k = prm.k;
+  if (!noupd && k > sq.last) return;
+  const bool adj = prm.adjoint != 0;
+  const bool first = noupd || (adj ? k == sq.last : k == 0);
+  const bool final_ = noupd || (adj ? k == 0 : k == sq.last);
+  const bool pro = (prm.flags & SF_PROLOGUE) && first;
+  const bool epi = (prm.flags & SF_EPILOGUE) && final_;
+  const bool store = !epi || (prm.flags & SF_STORE_AT_EPI);
+
+  const int64_t L = sq.L;
+  const int64_t row0 = t.row0;
+  const int64_t s = noupd ? 0 : ((int64_t)1 << k);
+  const int64_t rlast = (row0 + BM < L ? row0 + BM : L) - 1;
+  const bool upd = !noupd && (adj ? (row0 + s < L) : (rlast >= s));
+
+  const X* small = reinterpret_cast<const X*>(prm.small);
+  const X* xin = reinterpret_cast<const X*>(prm.xin) + sq.x_off;
+  X* xout = reinterpret_cast<X*>(prm.xout) + sq.x_off;
+  const int r_in = adj ? sq.q : sq.p;  // width of the src rows
+  const int64_t src_off = adj ? sq.y_off : sq.u_off;
+  const X* pin = small + (adj ? o.ct : o.bin);  // MP x r_in
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int lrow = lane & 15, lgrp = lane >> 4;
+
+  // ---- accumulators <- unshifted rows ----
+  Acc acc[RB][CB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int col = wc * CW + cb * 16 + lrow;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t l = row0 + (wr * RB + rb) * 16 + TR::acc_row(lgrp, v);
+        X val = 0;
+        if (l < L) {
+          if (pro) {
+            for (int j = 0; j < r_in; ++j)
+              val += pin[col * r_in + j] * load_src<X>(prm.src, prm.src_dtype, src_off + l * r_in + j);
+          } else {
+            val = xin[l * MP + col];
+          }
+        }
+        acc[rb][cb][v] = val;
+      }
+    }
+  }
+
+  // ---- shifted rows times P_k^T (or P_k for the adjoint) on MFMA ----
+  if (upd) {
+    const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP;
+    constexpr int VX = 16 / (int)sizeof(X);  // state elements per 16-byte load
+    constexpr int GA = KC / VX;              // groups per A row chunk
+    constexpr int VO = 16 / (int)sizeof(Op);
+    constexpr int GB = KC / VO;
+    for (int ch = 0; ch < C::NCH; ++ch) {
+      const int k0 = ch * KC;
+      __syncthreads();
+      for (int g = tid; g < BM * GA; g += 256) {
+        const int i = g / GA, kk = (g % GA) * VX;
+        const int64_t l = row0 + i;
+        const int64_t ls = adj ? l + s : l - s;
+        X vals[VX];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) vals[e] = 0;
+        if (l < L && ls >= 0 && ls < L) {
+          if (pro) {
+            for (int j = 0; j < r_in; ++j) {
+              const X uv = load_src<X>(prm.src, prm.src_dtype, src_off + ls * r_in + j);
+#pragma unroll
+              for (int e = 0; e < VX; ++e) vals[e] += pin[(k0 + kk + e) * r_in + j] * uv;
+            }
+          } else {
+            const X* srow = xin + ls * MP + k0 + kk;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) vals[e] = srow[e];
+          }
+        }
+        Op* d = As + i * SA + kk;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) d[e] = to_op<Op, X>(vals[e]);
+      }
+      for (int g = tid; g < MP * GB; g += 256) {
+        const int n = g / GB, kk = (g % GB) * VO;
+        const uint4 w = *reinterpret_cast<const uint4*>(P + (int64_t)n * MP + k0 + kk);
+        *reinterpret_cast<uint4*>(Bs + n * SA + kk) = w;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < C::KSTEPS; ++ks) {
+        const int kof = ks * TR::KI + lgrp * TR::KPL;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const Op* ap = As + ((wr * RB + rb) * 16 + lrow) * SA + kof;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const Op* bp = Bs + (wc * CW + cb * 16 + lrow) * SA + kof;
+            acc[rb][cb] = Mfma<CT>::run(ap, bp, acc[rb][cb]);
+          }
+        }
+      }
+    }
+  }
+
+  // ---- store the state rows ----
+  if (store) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int col = wc * CW + cb * 16 + lrow;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t l = row0 + (wr * RB + rb) * 16 + TR::acc_row(lgrp, v);
+          if (l < L) xout[l * MP + col] = acc[rb][cb][v];
+        }
+      }
+    }
+  }
+
+  // ---- output projection ----
+  if (epi) {
+    const int w = adj ? sq.p : sq.q;
+    const X* cm = small + (adj ? o.bt : o.cout);  // w x MP
+    const X* dm = small + (adj ? o.dt : o.dmat);  // w x r_in
+    const int64_t dst_off = adj ? sq.u_off : sq.y_off;
+    X* dst = reinterpret_cast<X*>(prm.dst);
+    for (int rb = 0; rb < RB; ++rb) {
+      __syncthreads();
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int col = wc * CW + cb * 16 + lrow;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Es[(wr * 16 + TR::acc_row(lgrp, v)) * SE + col] = acc[rb][cb][v];
+        }
+      }
+      __syncthreads();
+      for (int oi = tid; oi < WR * 16 * w; oi += 256) {
+        const int er = oi / w, j = oi % w;
+        const int64_t l = row0 + ((er / 16) * RB + rb) * 16 + (er % 16);
+        if (l < L) {
+          X a0 = 0, a1 = 0;
+          const X* crow = cm + (int64_t)j * MP;
+          const X* erow = Es + er * SE;
+          for (int n = 0; n < MP; n += 2) {
+            a0 += crow[n] * erow[n];
+            a1 += crow[n + 1] * erow[n + 1];
+          }
+          X val = a0 + a1;
+          for (int jj = 0; jj < r_in; ++jj)
+            val += dm[j * r_in + jj] * load_src<X>(prm.src, prm.src_dtype, src_off + l * r_in + jj);
+          dst[dst_off + l * w + j] = val;
+        }
+      }
+    }
+  }
+}
+
+template <int MP, int CT>
+static hipError_t launch_one(const StageParams& prm, hipStream_t s) {
+  if (prm.n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_stage<MP, CT>), dim3(prm.n_tiles), dim3(256), 0, s, prm);
+  return hipGetLastError();
+}
+
+template <int CT>
+static hipError_t launch_ct(int mp, const StageParams& prm, hipStream_t s) {
+  switch (mp) {
+    case 32: return launch_one<32, CT>(prm, s);
+    case 64: return launch_one<64, CT>(prm, s);
+    case 128: return launch_one<128, CT>(prm, s);
+    case 256: return launch_one<256, CT>(prm, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_stage(int mp, int ct, const StageParams& prm, hipStream_t s) {
+  switch (ct) {
+    case DT_BF16: return launch_ct<DT_BF16>(mp, prm, s);
+    case DT_F32: return launch_ct<DT_F32>(mp, prm, s);
+    case DT_F64: return launch_ct<DT_F64>(mp, prm, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ssmc

@@ -1,0 +1,131 @@
+// Internal declarations shared by the host API and the kernels of the
+// fast-cascade library. Not part of the public ABI (include/ssm_cascade.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssmc {
+
+// Element types (same numbering as ssm_dtype).
+enum : int32_t { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+// One sequence, as the kernels see it.
+struct SeqDev {
+  int64_t L;
+  int64_t x_off;  // element offset of row 0 in every state buffer (rows of mp)
+  int64_t u_off;  // element offset of the (L x p) block of u / du
+  int64_t y_off;  // element offset of the (L x q) block of y / dy
+  int32_t op;     // operator index
+  int32_t last;   // last stage index this sequence runs (0 if no stage acts)
+  int32_t p, q;
+};
+
+// One operator (a distinct discretized Abar with its Bbar, C, D).
+// Offsets are element offsets into the plan's buffers.
+struct OpDev {
+  int64_t pw;    // FP64 powers: Abar^(2^k) at pw + k*mp*mp (mp x mp, zero padded)
+  int64_t pc;    // packed powers in the compute type, same layout
+  int64_t pct;   // packed transposed powers (adjoint), or -1
+  int64_t bin;   // Bbar   (mp x p)  in the state type
+  int64_t cout;  // C      (q x mp)  in the state type
+  int64_t dmat;  // D      (q x p)   in the state type
+  int64_t ct;    // C^T    (mp x q)  in the state type
+  int64_t bt;    // Bbar^T (p x mp)  in the state type
+  int64_t dt;    // D^T    (p x q)   in the state type
+  int64_t bbar;  // FP64 Bbar (mp x p)
+  int64_t minv;  // FP64 (I - delta/2 A)^{-1} (mp x mp)
+  int64_t sc_aug, sc_n, sc_b;  // prepare scratch: [M | I] (mp x 2mp), I + hA, delta B
+  int32_t mp, m, p, q, N, set;
+  double delta;
+};
+
+// A row tile of one sequence for the stage kernel.
+struct Tile {
+  int32_t seq;
+  int32_t row0;
+};
+
+// Stage kernel flags.
+enum : int32_t {
+  SF_PROLOGUE = 1,     // at the first stage of the direction, rows come from src
+                       // through the input projection instead of from xin
+  SF_EPILOGUE = 2,     // at the last stage of the direction, write dst rows
+  SF_STORE_AT_EPI = 4, // also store the state rows at the epilogue stage
+  SF_NOUPDATE = 8,     // no stage update: pure projection pass over all rows,
+                       // prologue/epilogue apply unconditionally
+};
+
+struct StageParams {
+  const Tile* tiles;
+  const SeqDev* seqs;
+  const OpDev* ops;
+  const void* P;      // packed powers base (compute type)
+  const void* small;  // small-matrix base (state type)
+  const void* xin;    // state rows read
+  void* xout;         // state rows written
+  const void* src;    // u (forward) or dy (adjoint)
+  void* dst;          // y (forward) or du (adjoint)
+  int32_t src_dtype;  // DT_* of src
+  int32_t k;          // stage index
+  int32_t adjoint;    // 0: x_l += P_k x_{l-2^k};  1: g_l += P_k^T g_{l+2^k}
+  int32_t flags;
+  int32_t n_tiles;
+};
+
+// FP64 GEMM job: C = alpha * op(A) * op(B) + beta * C, row-major.
+struct GemmJob {
+  const double* A;
+  const double* B;
+  double* C;
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc;
+  int32_t transA, transB;
+  double alpha, beta;
+};
+
+// Rows per workgroup tile of the stage kernel for a padded state size and
+// compute type (4 waves, 16x16 MFMA blocks).
+__host__ __device__ constexpr int stage_bm(int mp, int ct) {
+  return ct == DT_F64 ? (mp == 256 ? 32 : mp == 128 ? 64 : mp == 64 ? 64 : 128)
+                      : (mp == 256 ? 64 : mp == 128 ? 128 : mp == 64 ? 128 : 256);
+}
+
+// Device pointers of one operator's source parameters (FP64, row-major,
+// unpadded: A m x m, B m x p, C q x m, D q x p).
+struct OpSrc {
+  const double* A;
+  const double* B;
+  const double* C;
+  const double* D;
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_stage(int mp, int ct, const StageParams& prm, hipStream_t s);
+
+hipError_t launch_gemm_f64(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n,
+                           hipStream_t s);
+
+// Builds, per operator, the trapezoid system [I - h A | I] (aug, mp x 2mp),
+// I + h A (nmat, mp x mp) and delta*B (bsc, mp x p); for given parameters
+// writes Abar into the k = 0 power slot and Bbar into bbar directly.
+hipError_t launch_disc_setup(const OpDev* ops, int n_ops, const OpSrc* src, int given,
+                             double* aug, double* nmat, double* bsc, double* pw,
+                             double* bbar, int max_mp, hipStream_t s);
+
+// Gauss-Jordan elimination with partial pivoting of aug -> minv, one
+// workgroup per operator. Sets *status to 1 if a pivot is negligible.
+hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double* minv,
+                               int* status, hipStream_t s);
+
+// Casts the FP64 powers to the compute type (and transposes when want_t),
+// and fills the small state-type matrices (Bbar, C, D and transposes).
+hipError_t launch_pack(const OpDev* ops, int n_ops, const OpSrc* src, const double* pw,
+                       const double* bbar, void* pc, int ct, int want_t, void* small,
+                       int state_is_f64, int max_mp, int max_N, hipStream_t s);
+
+hipError_t launch_recursion(int mp, int ct, const SeqDev* seqs, int n_seq, const OpDev* ops,
+                            const double* pw, const double* bbar, const void* u,
+                            int u_dtype, void* xout, hipStream_t s);
+
+}  // namespace ssmc

@@ -1,0 +1,107 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry point
+the header declares, and rejects bad arguments on the host before touching a
+GPU. No compute calls are made here."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssm_cascade.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssm_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2411_17729_amd import binding as B
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libssm_cascade.so is not built (run __graft_entry__.build())")
+    return B.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ["ssm_cascade_prepare", "ssm_cascade_apply", "ssm_cascade_backward",
+                     "ssm_cascade_recursion", "ssm_cascade_workspace_bytes"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_exposes_the_same_names():
+    from paper_2411_17729_amd import binding as B
+    for name in _declared():
+        assert callable(getattr(B, name, None)), name
+
+
+def _desc(**kw):
+    from paper_2411_17729_amd import binding as B
+    d = dict(m=64, p=1, q=1, N=11, L=4096, delta=1e-2, param_set=0, reserved=0,
+             u_offset=0, y_offset=0)
+    d.update(kw)
+    return B.ssm_seq_desc(**d)
+
+
+@pytest.mark.parametrize("bad", [dict(m=0), dict(m=300), dict(p=0), dict(p=65), dict(q=65),
+                                 dict(N=-1), dict(N=63), dict(L=0), dict(param_set=-1),
+                                 dict(reserved=1), dict(u_offset=-1), dict(delta=0.0),
+                                 dict(delta=float("nan"))])
+def test_workspace_bytes_rejects_bad_descriptors(lib, bad):
+    from paper_2411_17729_amd import binding as B
+    arr = (B.ssm_seq_desc * 1)(_desc(**bad))
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0) == 0
+    assert lib.ssm_last_error().decode() != ""
+
+
+def test_workspace_bytes_grows_with_batch(lib):
+    from paper_2411_17729_amd import binding as B
+    one = (B.ssm_seq_desc * 1)(_desc())
+    two = (B.ssm_seq_desc * 2)(_desc(), _desc(u_offset=4096, y_offset=4096))
+    n1 = lib.ssm_cascade_workspace_bytes(one, 1, 0, 1, 0, 0)
+    n2 = lib.ssm_cascade_workspace_bytes(two, 2, 0, 1, 0, 0)
+    assert 0 < n1 < n2
+    # the second sequence shares the operator: only the state buffers grow
+    assert n2 - n1 <= 2 * 4096 * 64 * 4 + 4096
+
+
+def test_prepare_rejects_on_host(lib):
+    from paper_2411_17729_amd import binding as B
+    arr = (B.ssm_seq_desc * 1)(_desc())
+    params = (B.ssm_params * 1)(B.ssm_params(A=None, B=None, C=None, D=None, m=64, p=1, q=1))
+    plan = C.c_void_p()
+    # NULL workspace
+    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, None, 0, None, C.byref(plan))
+    assert st == B.SSM_E_INVALID and plan.value is None
+    # NULL parameter matrices (non-NULL fake workspace is never dereferenced)
+    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, C.c_void_p(256), 1 << 40, None,
+                                 C.byref(plan))
+    assert st == B.SSM_E_INVALID
+    # short workspace
+    params[0] = B.ssm_params(A=256, B=256, C=256, D=256, m=64, p=1, q=1)
+    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, C.c_void_p(256), 16, None,
+                                 C.byref(plan))
+    assert st == B.SSM_E_WORKSPACE
+    # param_set beyond n_sets
+    arr2 = (B.ssm_seq_desc * 1)(_desc(param_set=1))
+    st = lib.ssm_cascade_prepare(arr2, 1, params, 1, 0, 1, 0, 0, C.c_void_p(256), 1 << 40, None,
+                                 C.byref(plan))
+    assert st == B.SSM_E_INVALID
+
+
+def test_null_plan_calls(lib):
+    from paper_2411_17729_amd import binding as B
+    assert lib.ssm_cascade_apply(None, None, 1, 0, None, 0, None) == B.SSM_E_NOT_PREPARED
+    assert lib.ssm_cascade_recursion(None, None, 1, 0, None, 0, None) == B.SSM_E_NOT_PREPARED
+    assert lib.ssm_cascade_destroy(None) == B.SSM_OK
+    assert lib.ssm_cascade_param_grad_numel(None) == 0
+    assert "INVALID" in lib.ssm_status_string(B.SSM_E_INVALID).decode()
