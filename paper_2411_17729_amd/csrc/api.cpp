@@ -106,6 +106,7 @@ struct ssm_plan_s {
   // timing
   bool timing = false;
   std::vector<TimingRec> trec;
+  std::vector<hipEvent_t> event_pool;  // events reused across timing reads
 
   template <typename T>
   T* at(const Region& r) const {
@@ -272,8 +273,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     xoff += s.L * (int64_t)P.ops[s.op].mp;
   }
   // algorithmic HBM bytes of the stage launches: per stage and row, read the
-  // row and its shifted partner and write the row (state element size);
-  // the first stage reads u instead, the last writes y instead of the state.
+  // row and (for rows with a partner) the shifted partner, and write the row
+  // (state element size); the last stage writes y instead of the state.
   const double xe = (double)P.x_elem();
   P.stage_launches = 0;
   for (int c = 0; c < 4; ++c) P.stage_launches += P.class_max_last[c] + 1;
@@ -281,7 +282,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     const SeqDev& s = P.seqs[i];
     const int m = P.ops[s.op].m;
     for (int kk = 0; kk <= s.last; ++kk) {
-      const double in_row = kk == 0 ? (double)s.p * xe : (double)m * xe;
+      const double in_row = (double)m * xe;
       const double out_row = kk == s.last ? (double)s.q * xe : (double)m * xe;
       const int64_t sh = (int64_t)1 << kk;
       const double upd_rows = sh < s.L ? (double)(s.L - sh) : 0.0;
@@ -391,10 +392,20 @@ struct TimedLaunch {
   hipEvent_t a = nullptr, b = nullptr;
   TimedLaunch(ssm_plan_s& P_, hipStream_t s_, int kind_) : P(P_), s(s_), kind(kind_) {
     if (P.timing) {
-      (void)hipEventCreate(&a);
-      (void)hipEventCreate(&b);
+      a = take();
+      b = take();
       (void)hipEventRecord(a, s);
     }
+  }
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!P.event_pool.empty()) {
+      e = P.event_pool.back();
+      P.event_pool.pop_back();
+    } else {
+      (void)hipEventCreate(&e);
+    }
+    return e;
   }
   void done() {
     if (P.timing) {
@@ -623,14 +634,19 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     prm.src_dtype = (int)u_dtype;
     prm.dst = y;
     prm.adjoint = 0;
-    prm.flags = SF_PROLOGUE | SF_EPILOGUE;
+    // V^(0) = Bbar U into the first state buffer
+    prm.xout = P.ws + P.r_x0.off;
+    prm.n_tiles = P.class_tile_count[c];
+    hipError_t e = launch_project(kClassMp[c], P.state_f64, prm, stream);
+    if (e != hipSuccess) return hip_fail(e, "projection launch");
+    prm.flags = SF_EPILOGUE;
     for (int kk = 0; kk <= P.class_max_last[c]; ++kk) {
       prm.k = kk;
       prm.xin = P.ws + ((kk & 1) ? P.r_x1.off : P.r_x0.off);
       prm.xout = P.ws + ((kk & 1) ? P.r_x0.off : P.r_x1.off);
       prm.n_tiles = P.class_active[c][kk];
       TimedLaunch tl(P, stream, 0);
-      hipError_t e = launch_stage(kClassMp[c], P.compute, prm, stream);
+      e = launch_stage(kClassMp[c], P.compute, prm, stream);
       if (e != hipSuccess) return hip_fail(e, "stage launch");
       tl.done();
     }
@@ -755,8 +771,8 @@ ssm_status ssm_cascade_timing_read(ssm_plan plan, int32_t kind, int64_t* launche
     HIP_TRY(hipEventElapsedTime(&t, r.a, r.b), "event elapsed");
     ms += t;
     ++n;
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    plan->event_pool.push_back(r.a);
+    plan->event_pool.push_back(r.b);
   }
   plan->trec.swap(keep);
   *launches = n;
@@ -770,6 +786,7 @@ ssm_status ssm_cascade_destroy(ssm_plan plan) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
+  for (hipEvent_t e : plan->event_pool) (void)hipEventDestroy(e);
   delete plan;
   return SSM_OK;
 }

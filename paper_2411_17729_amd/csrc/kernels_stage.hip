@@ -9,10 +9,12 @@
 // of shape BM x mp x mp. The unshifted rows initialise the MFMA accumulators,
 // so the stage's addition is the accumulate of the matrix cores.
 //
-// At the first stage of a direction the input rows are formed on the fly from
-// the sequence input (v_l = Bbar u_l forward, g_l = C^T dy_l adjoint); at the
-// last stage the output rows are written instead of (or besides) the state
+// The input rows of the first stage come from a projection pass (k_project:
+// v_l = Bbar u_l forward, g_l = C^T dy_l adjoint); at the last stage the
+// output rows are written instead of (or besides) the state
 // (y_l = C x_l + D u_l forward, du_l = Bbar^T g_l + D^T dy_l adjoint).
+#include <type_traits>
+
 #include "ssm_internal.h"
 
 namespace ssmc {
@@ -140,7 +142,7 @@ struct StageCfg {
 };
 
 template <int MP, int CT>
-__global__ __launch_bounds__(256) void k_stage(StageParams prm) {
+__global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
   using C = StageCfg<MP, CT>;
   using X = typename C::X;
   using Op = typename C::Op;
@@ -168,9 +170,7 @@ __global__ __launch_bounds__(256) void k_stage(StageParams prm) {
   const int k = prm.k;
   if (!noupd && k > sq.last) return;
   const bool adj = prm.adjoint != 0;
-  const bool first = noupd || (adj ? k == sq.last : k == 0);
   const bool final_ = noupd || (adj ? k == 0 : k == sq.last);
-  const bool pro = (prm.flags & SF_PROLOGUE) && first;
   const bool epi = (prm.flags & SF_EPILOGUE) && final_;
   const bool store = !epi || (prm.flags & SF_STORE_AT_EPI);
 
@@ -185,7 +185,6 @@ __global__ __launch_bounds__(256) void k_stage(StageParams prm) {
   X* xout = reinterpret_cast<X*>(prm.xout) + sq.x_off;
   const int r_in = adj ? sq.q : sq.p;  // width of the src rows
   const int64_t src_off = adj ? sq.y_off : sq.u_off;
-  const X* pin = small + (adj ? o.ct : o.bin);  // MP x r_in
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
@@ -201,60 +200,69 @@ __global__ __launch_bounds__(256) void k_stage(StageParams prm) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t l = row0 + (wr * RB + rb) * 16 + TR::acc_row(lgrp, v);
-        X val = 0;
-        if (l < L) {
-          if (pro) {
-            for (int j = 0; j < r_in; ++j)
-              val += pin[col * r_in + j] * load_src<X>(prm.src, prm.src_dtype, src_off + l * r_in + j);
-          } else {
-            val = xin[l * MP + col];
-          }
-        }
-        acc[rb][cb][v] = val;
+        acc[rb][cb][v] = l < L ? xin[l * MP + col] : (X)0;
       }
     }
   }
 
   // ---- shifted rows times P_k^T (or P_k for the adjoint) on MFMA ----
+  // K is staged through LDS in chunks; the global loads of chunk ch+1 are
+  // issued into registers before the MFMAs of chunk ch.
   if (upd) {
     const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP;
     constexpr int VX = 16 / (int)sizeof(X);  // state elements per 16-byte load
-    constexpr int GA = KC / VX;              // groups per A row chunk
+    constexpr int GA = KC / VX;              // 16-byte groups per A row chunk
     constexpr int VO = 16 / (int)sizeof(Op);
     constexpr int GB = KC / VO;
-    for (int ch = 0; ch < C::NCH; ++ch) {
+    constexpr int NA = (BM * GA + 255) / 256;  // A groups per thread
+    constexpr int NB = (MP * GB + 255) / 256;  // B groups per thread
+    using XV = typename std::conditional<sizeof(X) == 4, float4, double2>::type;
+    XV ra[NA];
+    // X rows of chunk ch (HBM) into registers
+    auto fetch = [&](int ch) {
       const int k0 = ch * KC;
-      __syncthreads();
-      for (int g = tid; g < BM * GA; g += 256) {
+#pragma unroll
+      for (int it = 0; it < NA; ++it) {
+        const int g = tid + it * 256;
         const int i = g / GA, kk = (g % GA) * VX;
         const int64_t l = row0 + i;
         const int64_t ls = adj ? l + s : l - s;
-        X vals[VX];
+        if (g < BM * GA && l < L && ls >= 0 && ls < L)
+          ra[it] = *reinterpret_cast<const XV*>(xin + ls * MP + k0 + kk);
+        else
+          ra[it] = XV{};
+      }
+    };
+    // registers -> A chunk (converted to the operand type); P_k chunk (L2) -> LDS
+    auto stash = [&](int ch) {
+      const int k0 = ch * KC;
 #pragma unroll
-        for (int e = 0; e < VX; ++e) vals[e] = 0;
-        if (l < L && ls >= 0 && ls < L) {
-          if (pro) {
-            for (int j = 0; j < r_in; ++j) {
-              const X uv = load_src<X>(prm.src, prm.src_dtype, src_off + ls * r_in + j);
+      for (int it = 0; it < NA; ++it) {
+        const int g = tid + it * 256;
+        if (g < BM * GA) {
+          const int i = g / GA, kk = (g % GA) * VX;
+          Op* d = As + i * SA + kk;
+          const X* vals = reinterpret_cast<const X*>(&ra[it]);
 #pragma unroll
-              for (int e = 0; e < VX; ++e) vals[e] += pin[(k0 + kk + e) * r_in + j] * uv;
-            }
-          } else {
-            const X* srow = xin + ls * MP + k0 + kk;
-#pragma unroll
-            for (int e = 0; e < VX; ++e) vals[e] = srow[e];
-          }
+          for (int e = 0; e < VX; ++e) d[e] = to_op<Op, X>(vals[e]);
         }
-        Op* d = As + i * SA + kk;
+      }
 #pragma unroll
-        for (int e = 0; e < VX; ++e) d[e] = to_op<Op, X>(vals[e]);
+      for (int it = 0; it < NB; ++it) {
+        const int g = tid + it * 256;
+        if (g < MP * GB) {
+          const int n = g / GB, kk = (g % GB) * VO;
+          *reinterpret_cast<uint4*>(Bs + n * SA + kk) =
+              *reinterpret_cast<const uint4*>(P + (int64_t)n * MP + k0 + kk);
+        }
       }
-      for (int g = tid; g < MP * GB; g += 256) {
-        const int n = g / GB, kk = (g % GB) * VO;
-        const uint4 w = *reinterpret_cast<const uint4*>(P + (int64_t)n * MP + k0 + kk);
-        *reinterpret_cast<uint4*>(Bs + n * SA + kk) = w;
-      }
+    };
+    fetch(0);
+    for (int ch = 0; ch < C::NCH; ++ch) {
       __syncthreads();
+      stash(ch);
+      __syncthreads();
+      if (ch + 1 < C::NCH) fetch(ch + 1);
 #pragma unroll
       for (int ks = 0; ks < C::KSTEPS; ++ks) {
         const int kof = ks * TR::KI + lgrp * TR::KPL;
@@ -323,6 +331,81 @@ __global__ __launch_bounds__(256) void k_stage(StageParams prm) {
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Input projection of a row tile: out_l = M src_l for every row l of the tile,
+//   forward: v_l = Bbar u_l   (M = Bbar, MP x p; the columns of V^(0), §3)
+//   adjoint: g_l = C^T dy_l   (M = C^T,  MP x q)
+// One workgroup per tile; M and the tile's source rows are staged in LDS in
+// chunks of 32 source columns; thread t owns state column t % MP.
+// ---------------------------------------------------------------------------
+template <int MP, typename X>
+__global__ __launch_bounds__(256) void k_project(StageParams prm) {
+  constexpr int BM = stage_bm(MP, sizeof(X) == 8 ? DT_F64 : DT_F32);
+  constexpr int RCH = 32;
+  constexpr int RG = 256 / MP;     // row groups
+  constexpr int RPT = BM / RG;     // rows per thread
+  __shared__ X Ms[MP][RCH + 1];
+  __shared__ X Us[BM][RCH + 1];
+  const int nt = prm.n_tiles;
+  const int b = blockIdx.x;
+  const int xcd = b & 7, per = nt >> 3, rem = nt & 7;
+  const Tile t = prm.tiles[xcd * per + (xcd < rem ? xcd : rem) + (b >> 3)];
+  const SeqDev sq = prm.seqs[t.seq];
+  const OpDev o = prm.ops[sq.op];
+  const bool adj = prm.adjoint != 0;
+  const int r = adj ? sq.q : sq.p;
+  const int64_t src_off = adj ? sq.y_off : sq.u_off;
+  const X* M = reinterpret_cast<const X*>(prm.small) + (adj ? o.ct : o.bin);
+  X* out = reinterpret_cast<X*>(prm.xout) + sq.x_off;
+  const int64_t L = sq.L, row0 = t.row0;
+  const int tid = threadIdx.x, n = tid % MP, rg = tid / MP;
+  X acc[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) acc[i] = 0;
+  for (int j0 = 0; j0 < r; j0 += RCH) {
+    const int jn = r - j0 < RCH ? r - j0 : RCH;
+    __syncthreads();
+    for (int e = tid; e < MP * RCH; e += 256) {
+      const int nn = e / RCH, jj = e % RCH;
+      Ms[nn][jj] = jj < jn ? M[nn * r + j0 + jj] : (X)0;
+    }
+    for (int e = tid; e < BM * RCH; e += 256) {
+      const int i = e / RCH, jj = e % RCH;
+      const int64_t l = row0 + i;
+      Us[i][jj] = (jj < jn && l < L) ? load_src<X>(prm.src, prm.src_dtype, src_off + l * r + j0 + jj)
+                                     : (X)0;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < jn; ++jj) {
+      const X mv = Ms[n][jj];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) acc[i] += mv * Us[i * RG + rg][jj];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t l = row0 + i * RG + rg;
+    if (l < L) out[l * MP + n] = acc[i];
+  }
+}
+
+template <int MP, typename X>
+static hipError_t launch_proj(const StageParams& prm, hipStream_t s) {
+  if (prm.n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_project<MP, X>), dim3(prm.n_tiles), dim3(256), 0, s, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int mp, int state_f64, const StageParams& prm, hipStream_t s) {
+  switch (mp) {
+    case 32: return state_f64 ? launch_proj<32, double>(prm, s) : launch_proj<32, float>(prm, s);
+    case 64: return state_f64 ? launch_proj<64, double>(prm, s) : launch_proj<64, float>(prm, s);
+    case 128: return state_f64 ? launch_proj<128, double>(prm, s) : launch_proj<128, float>(prm, s);
+    case 256: return state_f64 ? launch_proj<256, double>(prm, s) : launch_proj<256, float>(prm, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -48,8 +48,6 @@ struct Tile {
 
 // Stage kernel flags.
 enum : int32_t {
-  SF_PROLOGUE = 1,     // at the first stage of the direction, rows come from src
-                       // through the input projection instead of from xin
   SF_EPILOGUE = 2,     // at the last stage of the direction, write dst rows
   SF_STORE_AT_EPI = 4, // also store the state rows at the epilogue stage
   SF_NOUPDATE = 8,     // no stage update: pure projection pass over all rows,
@@ -102,6 +100,9 @@ struct OpSrc {
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_stage(int mp, int ct, const StageParams& prm, hipStream_t s);
+// Input projection into the state buffer xout: Bbar u (forward) or C^T dy
+// (adjoint) for every tile of the launch.
+hipError_t launch_project(int mp, int state_f64, const StageParams& prm, hipStream_t s);
 
 hipError_t launch_gemm_f64(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n,
                            hipStream_t s);
