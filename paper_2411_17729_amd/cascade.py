@@ -73,8 +73,9 @@ class CascadePlan:
         self.params = []
         cparams = []
         for (A, Bm, Cm, D) in params:
-            ts = [torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64) if isinstance(x, np.ndarray) else x,
-                                  dtype=torch.float64, device=self.device).contiguous()
+            ts = [(x.detach() if isinstance(x, torch.Tensor) else
+                   torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)))
+                  .to(device=self.device, dtype=torch.float64).contiguous()
                   for x in (A, Bm, Cm, D)]
             self.params.append(ts)
             m, p, q = ts[0].shape[0], ts[1].shape[1], ts[2].shape[0]
@@ -209,3 +210,43 @@ def unpack_y(wl, y):
         out.append(y[off: off + s.L * q].reshape(s.L, q))
         off += s.L * q
     return out
+
+
+class CascadeFn(torch.autograd.Function):
+    """y = cascade(u; A, B, C, D) with the hand-written adjoint cascade as its
+    backward. ``cfg`` holds the static part (layout, discretization, compute
+    type, checkpoint interval); the tensors are u followed by A, B, C, D of
+    every parameter set (FP64)."""
+
+    @staticmethod
+    def forward(ctx, cfg, u, *params):
+        layout, disc, compute, ckpt_every = cfg
+        sets = [params[i:i + 4] for i in range(0, len(params), 4)]
+        plan = CascadePlan(layout, sets, disc=disc, compute=compute, with_backward=True,
+                           ckpt_every=ckpt_every, device=u.device)
+        u_c = u.detach().contiguous()
+        y = plan.apply(u_c)
+        ctx.plan = plan
+        ctx.u = u_c
+        ctx.u_dtype = u.dtype
+        ctx.n_sets = len(sets)
+        return y
+
+    @staticmethod
+    def backward(ctx, dy):
+        plan = ctx.plan
+        need_u = ctx.needs_input_grad[1]
+        need_p = any(ctx.needs_input_grad[2:])
+        du, grads = plan.backward(ctx.u, dy.detach().to(plan.state_dtype).contiguous(),
+                                  want_du=need_u, want_params=need_p)
+        out = [None, du.to(ctx.u_dtype) if du is not None else None]
+        for i in range(ctx.n_sets):
+            out.extend(grads[i] if grads is not None else [None] * 4)
+        return tuple(out)
+
+
+def ssm_cascade(u, params, layout, disc="trapezoid", compute="f32", ckpt_every=0):
+    """Differentiable fast cascade: u is the packed input (see make_layout),
+    params a list of (A, B, C, D) FP64 tensors per parameter set."""
+    flat = [t for ps in params for t in ps]
+    return CascadeFn.apply((layout, disc, compute, ckpt_every), u, *flat)

@@ -107,6 +107,24 @@ struct ssm_plan_s {
   bool timing = false;
   std::vector<TimingRec> trec;
   std::vector<hipEvent_t> event_pool;  // events reused across timing reads
+  // backward
+  int n_ckpt = 0, n_seg = 0, chunk_rows = 256;
+  int64_t sum_x = 0;  // elements of one state buffer (all sequences)
+  Region r_ckpt, r_seg, r_xfinal, r_gfirst, r_part, r_g;
+  std::vector<RedChunk> chunks;
+  int class_chunk_start[4] = {0, 0, 0, 0}, class_chunk_count[4] = {0, 0, 0, 0};
+  int64_t class_part_off[4] = {0, 0, 0, 0};
+  int class_op_start[4] = {0, 0, 0, 0}, class_op_count[4] = {0, 0, 0, 0};
+  int class_set_start[4] = {0, 0, 0, 0}, class_set_count[4] = {0, 0, 0, 0};
+  int class_max_p[4] = {0, 0, 0, 0}, class_max_q[4] = {0, 0, 0, 0};
+  std::vector<SumJob> sj_dp, sj_dbb, sj_dc, sj_dd;  // grouped by class
+  std::vector<int32_t> set_ops;                      // operators ordered by set
+  std::vector<ScatterJob> scat;                      // one per parameter set
+  std::vector<GemmJob> bjobs;                        // FP64 jobs of the backward
+  std::vector<std::pair<int, int>> bgroups, bdims;   // (start, count), (max M, max N)
+  std::vector<int> bkind;                            // 0: GEMM, 1: axpy
+  size_t m_chunks = 0, m_sj = 0, m_set_ops = 0, m_scat = 0, m_bjobs = 0;
+  size_t grad_numel = 0;
 
   template <typename T>
   T* at(const Region& r) const {
@@ -139,6 +157,9 @@ ssm_status validate_seqs(const ssm_seq_desc* seqs, int32_t n_seq) {
   }
   return SSM_OK;
 }
+
+void plan_backward(ssm_plan_s& P);
+void plan_backward_jobs(ssm_plan_s& P);
 
 // Builds sequences, operators, tiles, info and the workspace layout.
 ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ssm_disc disc,
@@ -361,6 +382,26 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   for (const OpDev& o : P.ops) n_jobs += (size_t)o.N;
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
+  P.sum_x = xoff;
+  if (P.with_backward) {
+    plan_backward(P);
+    size_t n_bjobs = 0;
+    for (int k = 0; k < P.max_N; ++k)
+      for (const OpDev& o : P.ops)
+        if (o.N > k) n_bjobs += 2;
+    n_bjobs += (disc == SSM_DISC_TRAPEZOID ? 5 : 2) * P.ops.size();
+    P.m_chunks = off;
+    off = align_up(off + sizeof(RedChunk) * std::max<size_t>(1, P.chunks.size()));
+    P.m_sj = off;
+    off = align_up(off + sizeof(SumJob) * std::max<size_t>(
+                             1, P.sj_dp.size() + P.sj_dbb.size() + P.sj_dc.size() + P.sj_dd.size()));
+    P.m_set_ops = off;
+    off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, P.set_ops.size()));
+    P.m_scat = off;
+    off = align_up(off + sizeof(ScatterJob) * std::max<size_t>(1, P.scat.size()) + 4096);
+    P.m_bjobs = off;
+    off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_bjobs));
+  }
   P.meta_bytes = off;
 
   size_t cur = 0;
@@ -380,8 +421,206 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   take(P.r_bsc, n_bsc * 8);
   take(P.r_x0, (size_t)xoff * P.x_elem());
   take(P.r_x1, (size_t)xoff * P.x_elem());
+  if (P.with_backward) {
+    const size_t xb = (size_t)xoff * P.x_elem();
+    take(P.r_ckpt, xb * P.n_ckpt);
+    take(P.r_seg, xb * P.n_seg);
+    take(P.r_xfinal, xb);
+    take(P.r_gfirst, xb);
+    take(P.r_part, P.r_part.bytes);
+    take(P.r_g, P.r_g.bytes);
+  }
   P.ws_bytes = cur;
   return SSM_OK;
+}
+
+
+// Backward planning: checkpoint layout, reduction chunks, sum / GEMM /
+// scatter job lists and the FP64 gradient workspace. Offsets of the
+// workspace regions are assigned by the caller.
+void plan_backward(ssm_plan_s& P) {
+  const int c = P.ckpt_every;
+  P.n_ckpt = (P.max_last + 1) / c + 1;  // inputs of stages 0, c, 2c, ... and possibly K
+  P.n_seg = c - 1;
+  // reduction chunks: bounded count
+  int64_t rows = 0;
+  for (const SeqDev& s : P.seqs) rows += s.L;
+  P.chunk_rows = 256 * (int)std::max<int64_t>(1, (rows + 256 * 4096 - 1) / (256 * 4096));
+  // operators ordered by set
+  P.set_ops.clear();
+  std::vector<std::vector<int>> ops_of_set(P.n_sets), seqs_of_op(P.n_ops);
+  for (int o = 0; o < P.n_ops; ++o) ops_of_set[P.ops[o].set].push_back(o);
+  for (int i = 0; i < P.n_seq; ++i) seqs_of_op[P.seqs[i].op].push_back(i);
+  std::vector<int> set_op_first(P.n_sets, 0);
+  for (int st = 0; st < P.n_sets; ++st) {
+    set_op_first[st] = (int)P.set_ops.size();
+    for (int o : ops_of_set[st]) P.set_ops.push_back(o);
+  }
+  // FP64 gradient workspace
+  int64_t g = 0;
+  for (OpDev& o : P.ops) {
+    const int64_t mm = (int64_t)o.mp * o.mp;
+    o.g_dp = g;
+    g += (int64_t)(o.N + 1) * mm;
+    o.g_dbb = g;
+    g += (int64_t)o.mp * o.p;
+    o.g_s = g;
+    g += mm;
+    o.g_da = g;
+    g += mm;
+    o.g_db = g;
+    g += (int64_t)o.mp * o.p;
+  }
+  std::vector<int64_t> set_dc(P.n_sets, -1), set_dd(P.n_sets, -1);
+  for (int st = 0; st < P.n_sets; ++st) {
+    if (ops_of_set[st].empty()) continue;
+    const OpDev& o = P.ops[ops_of_set[st][0]];
+    set_dc[st] = g;
+    g += (int64_t)o.q * o.mp;
+    set_dd[st] = g;
+    g += (int64_t)o.q * o.p;
+  }
+  P.r_g.bytes = (size_t)g * 8;
+  // chunks and sum jobs, grouped by size class, then set, operator, sequence
+  P.chunks.clear();
+  P.sj_dp.clear();
+  P.sj_dbb.clear();
+  P.sj_dc.clear();
+  P.sj_dd.clear();
+  int64_t part = 0;
+  for (int cl = 0; cl < 4; ++cl) {
+    const int mp = kClassMp[cl];
+    const int64_t mm = (int64_t)mp * mp;
+    P.class_chunk_start[cl] = (int)P.chunks.size();
+    P.class_op_start[cl] = (int)P.sj_dp.size();
+    P.class_set_start[cl] = (int)P.sj_dc.size();
+    P.class_max_p[cl] = P.class_max_q[cl] = 0;
+    for (int st = 0; st < P.n_sets; ++st) {
+      if (ops_of_set[st].empty() || P.ops[ops_of_set[st][0]].mp != mp) continue;
+      const int set_first = (int)P.chunks.size() - P.class_chunk_start[cl];
+      for (int o : ops_of_set[st]) {
+        const OpDev& od = P.ops[o];
+        const int op_first = (int)P.chunks.size() - P.class_chunk_start[cl];
+        for (int sq : seqs_of_op[o]) {
+          const int64_t L = P.seqs[sq].L;
+          for (int64_t r0 = 0; r0 < L; r0 += P.chunk_rows) {
+            RedChunk ch;
+            ch.seq = sq;
+            ch.row0 = (int32_t)r0;
+            ch.nrows = (int32_t)std::min<int64_t>(P.chunk_rows, L - r0);
+            ch.slot = (int32_t)P.chunks.size() - P.class_chunk_start[cl];
+            P.chunks.push_back(ch);
+          }
+        }
+        const int n = (int)P.chunks.size() - P.class_chunk_start[cl] - op_first;
+        P.sj_dp.push_back(SumJob{op_first, n, (int32_t)mm, mm, od.g_dp, mm, od.N, 0});
+        P.sj_dbb.push_back(SumJob{op_first, n, od.mp * od.p, mm, od.g_dbb, 0, 0, 0});
+        P.class_max_p[cl] = std::max(P.class_max_p[cl], od.p);
+        P.class_max_q[cl] = std::max(P.class_max_q[cl], od.q);
+      }
+      const OpDev& o0 = P.ops[ops_of_set[st][0]];
+      const int n = (int)P.chunks.size() - P.class_chunk_start[cl] - set_first;
+      P.sj_dc.push_back(SumJob{set_first, n, o0.q * o0.mp, mm, set_dc[st], 0, 0, 0});
+      P.sj_dd.push_back(SumJob{set_first, n, o0.q * o0.p, mm, set_dd[st], 0, 0, 0});
+    }
+    P.class_chunk_count[cl] = (int)P.chunks.size() - P.class_chunk_start[cl];
+    P.class_op_count[cl] = (int)P.sj_dp.size() - P.class_op_start[cl];
+    P.class_set_count[cl] = (int)P.sj_dc.size() - P.class_set_start[cl];
+    P.class_part_off[cl] = part;
+    part += (int64_t)P.class_chunk_count[cl] * mm;
+  }
+  P.r_part.bytes = (size_t)part * P.x_elem();
+  // scatter jobs (set sizes as seen from the sequences; prepare completes
+  // unused sets from the parameter descriptors)
+  P.scat.assign(P.n_sets, ScatterJob{});
+  for (int st = 0; st < P.n_sets; ++st) {
+    ScatterJob& j = P.scat[st];
+    j.op_first = set_op_first[st];
+    j.n_ops = (int)ops_of_set[st].size();
+    j.m = std::max(0, P.set_m[st]);
+    j.mp = j.m ? pad_m(j.m) : 0;
+    j.p = std::max(0, P.set_p[st]);
+    j.q = std::max(0, P.set_q[st]);
+    j.dC = set_dc[st];
+    j.dD = set_dd[st];
+    j.out = 0;
+  }
+}
+
+// FP64 job lists of the backward (pointers into the workspace).
+void plan_backward_jobs(ssm_plan_s& P) {
+  double* pw = P.at<double>(P.r_pw);
+  double* bbar = P.at<double>(P.r_bbar);
+  double* minv = P.at<double>(P.r_minv);
+  double* G = P.at<double>(P.r_g);
+  P.bjobs.clear();
+  P.bgroups.clear();
+  P.bdims.clear();
+  P.bkind.clear();
+  auto close_group = [&](int start, int kind) {
+    int mx = 0, mn = 0;
+    for (size_t i = start; i < P.bjobs.size(); ++i) {
+      mx = std::max(mx, P.bjobs[i].M);
+      mn = std::max(mn, P.bjobs[i].N);
+    }
+    if ((int)P.bjobs.size() > start) {
+      P.bgroups.push_back({start, (int)P.bjobs.size() - start});
+      P.bdims.push_back({mx, mn});
+      P.bkind.push_back(kind);
+    }
+  };
+  // squaring adjoint: G_k += G_{k+1} P_k^T + P_k^T G_{k+1}, k = N-1..0
+  for (int k = P.max_N - 1; k >= 0; --k) {
+    for (int half = 0; half < 2; ++half) {
+      int start = (int)P.bjobs.size();
+      for (const OpDev& o : P.ops) {
+        if (o.N <= k) continue;
+        const int64_t mm = (int64_t)o.mp * o.mp;
+        double* Gk = G + o.g_dp + k * mm;
+        double* Gk1 = Gk + mm;
+        double* Pk = pw + o.pw + k * mm;
+        if (half == 0)
+          P.bjobs.push_back(GemmJob{Gk1, Pk, Gk, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 1, 1.0, 1.0});
+        else
+          P.bjobs.push_back(GemmJob{Pk, Gk1, Gk, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 1, 0, 1.0, 1.0});
+      }
+      close_group(start, 0);
+    }
+  }
+  int start = (int)P.bjobs.size();
+  if (P.disc == SSM_DISC_TRAPEZOID) {
+    // S = G_Abar (I + Abar)^T + G_Bbar Bbar^T;  dA = delta/2 M^{-T} S;  dB = delta M^{-T} G_Bbar
+    for (const OpDev& o : P.ops)
+      P.bjobs.push_back(GemmJob{G + o.g_dp, pw + o.pw, G + o.g_s, o.mp, o.mp, o.mp, o.mp, o.mp,
+                                o.mp, 0, 1, 1.0, 0.0});
+    close_group(start, 0);
+    start = (int)P.bjobs.size();
+    for (const OpDev& o : P.ops)
+      P.bjobs.push_back(GemmJob{G + o.g_dp, nullptr, G + o.g_s, o.mp, o.mp, 0, o.mp, 0, o.mp, 0, 0,
+                                1.0, 1.0});
+    close_group(start, 1);
+    start = (int)P.bjobs.size();
+    for (const OpDev& o : P.ops)
+      P.bjobs.push_back(GemmJob{G + o.g_dbb, bbar + o.bbar, G + o.g_s, o.mp, o.mp, o.p, o.p, o.p,
+                                o.mp, 0, 1, 1.0, 1.0});
+    close_group(start, 0);
+    start = (int)P.bjobs.size();
+    for (const OpDev& o : P.ops) {
+      P.bjobs.push_back(GemmJob{minv + o.minv, G + o.g_s, G + o.g_da, o.mp, o.mp, o.mp, o.mp, o.mp,
+                                o.mp, 1, 0, 0.5 * o.delta, 0.0});
+      P.bjobs.push_back(GemmJob{minv + o.minv, G + o.g_dbb, G + o.g_db, o.mp, o.p, o.mp, o.mp, o.p,
+                                o.p, 1, 0, o.delta, 0.0});
+    }
+    close_group(start, 0);
+  } else {
+    for (const OpDev& o : P.ops) {
+      P.bjobs.push_back(GemmJob{G + o.g_dp, nullptr, G + o.g_da, o.mp, o.mp, 0, o.mp, 0, o.mp, 0, 0,
+                                1.0, 0.0});
+      P.bjobs.push_back(GemmJob{G + o.g_dbb, nullptr, G + o.g_db, o.mp, o.p, 0, o.p, 0, o.p, 0, 0,
+                                1.0, 0.0});
+    }
+    close_group(start, 1);
+  }
 }
 
 // Records an event pair around a launch when timing is on.
@@ -510,6 +749,39 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                   o.set, ps.m, ps.p, ps.q);
     }
   }
+  // layout of the flat gradient buffer: every parameter set, in order
+  {
+    size_t off = 0;
+    std::vector<size_t> set_out(n_sets, 0);
+    for (int st = 0; st < n_sets; ++st) {
+      const ssm_params& ps = sets[st];
+      if (ps.m < 0 || ps.p < 0 || ps.q < 0) {
+        delete P;
+        return fail(SSM_E_INVALID, "parameter set %d has negative sizes", st);
+      }
+      set_out[st] = off;
+      off += (size_t)ps.m * ps.m + (size_t)ps.m * ps.p + (size_t)ps.q * ps.m + (size_t)ps.q * ps.p;
+    }
+    P->grad_numel = off;
+    if (P->with_backward) {
+      P->scat.resize(n_sets, ScatterJob{});
+      for (int st = 0; st < n_sets; ++st) {
+        ScatterJob& j = P->scat[st];
+        if (st >= P->n_sets || j.n_ops == 0) {
+          j = ScatterJob{};
+          j.op_first = 0;
+          j.n_ops = 0;
+          j.m = sets[st].m;
+          j.mp = j.m ? pad_m(j.m) : 0;
+          j.p = sets[st].p;
+          j.q = sets[st].q;
+          j.dC = -1;
+          j.dD = -1;
+        }
+        j.out = (int64_t)set_out[st];
+      }
+    }
+  }
   if (ws_bytes < P->ws_bytes) {
     size_t need = P->ws_bytes;
     delete P;
@@ -571,6 +843,27 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                 sizeof(Tile) * P->tiles.size());
   if (!J.empty())
     std::memcpy(P->meta_host.data() + P->m_jobs, J.data(), sizeof(GemmJob) * J.size());
+  if (P->with_backward) {
+    plan_backward_jobs(*P);
+    unsigned char* mh = P->meta_host.data();
+    if (!P->chunks.empty())
+      std::memcpy(mh + P->m_chunks, P->chunks.data(), sizeof(RedChunk) * P->chunks.size());
+    size_t o = P->m_sj;
+    for (auto* v : {&P->sj_dp, &P->sj_dbb, &P->sj_dc, &P->sj_dd}) {
+      if (!v->empty()) std::memcpy(mh + o, v->data(), sizeof(SumJob) * v->size());
+      o += sizeof(SumJob) * v->size();
+    }
+    if (!P->set_ops.empty())
+      std::memcpy(mh + P->m_set_ops, P->set_ops.data(), sizeof(int32_t) * P->set_ops.size());
+    if (P->m_scat + sizeof(ScatterJob) * P->scat.size() > P->m_bjobs) {
+      delete P;
+      return fail(SSM_E_INVALID, "too many parameter sets for the plan tables");
+    }
+    if (!P->scat.empty())
+      std::memcpy(mh + P->m_scat, P->scat.data(), sizeof(ScatterJob) * P->scat.size());
+    if (!P->bjobs.empty())
+      std::memcpy(mh + P->m_bjobs, P->bjobs.data(), sizeof(GemmJob) * P->bjobs.size());
+  }
 
   unsigned char* meta = P->ws + P->r_meta.off;
   const OpDev* ops_d = reinterpret_cast<const OpDev*>(meta + P->m_ops);
@@ -691,21 +984,193 @@ ssm_status ssm_cascade_recursion(ssm_plan plan, const void* u, ssm_dtype u_dtype
 ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
                                 const void* dy, size_t dy_numel, void* du, double* grad_params,
                                 size_t grad_numel, hipStream_t stream) {
-  (void)plan; (void)u; (void)u_dtype; (void)u_numel; (void)dy; (void)dy_numel; (void)du;
-  (void)grad_params; (void)grad_numel; (void)stream;
-  return fail(SSM_E_UNSUPPORTED, "backward is not built yet");
+  g_last_error.clear();
+  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  ssm_plan_s& P = *plan;
+  if (!P.with_backward)
+    return fail(SSM_E_NOT_PREPARED, "plan was prepared without with_backward");
+  ssm_status st = check_io(P, u, u_dtype, u_numel, dy, dy_numel, "dy");
+  if (st != SSM_OK) return st;
+  if (grad_params && grad_numel < P.grad_numel)
+    return fail(SSM_E_INVALID, "grad_params has %zu elements, needs %zu", grad_numel,
+                P.grad_numel);
+  unsigned char* meta = P.ws + P.r_meta.off;
+  const RedChunk* chunks_d = reinterpret_cast<const RedChunk*>(meta + P.m_chunks);
+  const SumJob* sj_d = reinterpret_cast<const SumJob*>(meta + P.m_sj);
+  const SumJob* sj_dp = sj_d;
+  const SumJob* sj_dbb = sj_dp + P.sj_dp.size();
+  const SumJob* sj_dc = sj_dbb + P.sj_dbb.size();
+  const SumJob* sj_dd = sj_dc + P.sj_dc.size();
+  const GemmJob* bj_d = reinterpret_cast<const GemmJob*>(meta + P.m_bjobs);
+  const size_t xb = (size_t)P.sum_x * P.x_elem();
+  const int c = P.ckpt_every;
+  // location of the input of stage k (k = 0..max_last+1)
+  auto loc = [&](int k) -> void* {
+    if (k % c == 0) return P.ws + P.r_ckpt.off + (size_t)(k / c) * xb;
+    return P.ws + P.r_seg.off + (size_t)(k % c - 1) * xb;
+  };
+  void* W[2] = {P.ws + P.r_x0.off, P.ws + P.r_x1.off};
+  void* xfinal = P.ws + P.r_xfinal.off;
+  void* gfirst = P.ws + P.r_gfirst.off;
+  double* G = P.at<double>(P.r_g);
+  const int sdt = P.state_f64 ? DT_F64 : DT_F32;
+  const int TO = P.state_f64 ? 64 : 128;
+  auto tiles = [&](int a, int b) { return ((a + TO - 1) / TO) * ((b + TO - 1) / TO); };
+  hipError_t e;
+
+  for (int cl = 0; cl < 4; ++cl) {
+    if (P.class_tile_count[cl] == 0) continue;
+    const int mp = kClassMp[cl];
+    const int ml = P.class_max_last[cl];
+    StageParams prm = base_params(P, cl);
+    prm.src = u;
+    prm.src_dtype = (int)u_dtype;
+    // ---- forward pass keeping stage-input checkpoints and the final states ----
+    prm.adjoint = 0;
+    prm.xout = loc(0);
+    prm.n_tiles = P.class_tile_count[cl];
+    e = launch_project(mp, P.state_f64, prm, stream);
+    if (e != hipSuccess) return hip_fail(e, "projection launch");
+    prm.flags = 0;
+    prm.xfinal = xfinal;
+    for (int k = 0; k <= ml; ++k) {
+      prm.k = k;
+      prm.xin = loc(k);
+      prm.xout = loc(k + 1);
+      prm.n_tiles = P.class_active[cl][k];
+      TimedLaunch tl(P, stream, 0);
+      e = launch_stage(mp, P.compute, prm, stream);
+      if (e != hipSuccess) return hip_fail(e, "stage launch");
+      tl.done();
+    }
+    prm.xfinal = nullptr;
+    // ---- g = C^T dy at every sequence's last stage ----
+    prm.adjoint = 1;
+    prm.src = dy;
+    prm.src_dtype = sdt;
+    prm.xout = gfirst;
+    prm.n_tiles = P.class_tile_count[cl];
+    e = launch_project(mp, P.state_f64, prm, stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint projection launch");
+
+    RedParams rp{};
+    rp.chunks = chunks_d + P.class_chunk_start[cl];
+    rp.n_chunks = P.class_chunk_count[cl];
+    rp.seqs = prm.seqs;
+    rp.u = u;
+    rp.dy = dy;
+    rp.u_dtype = (int)u_dtype;
+    rp.partial = P.ws + P.r_part.off + (size_t)P.class_part_off[cl] * P.x_elem();
+    rp.slot_stride = (int64_t)mp * mp;
+    const int ncs = P.class_set_count[cl], nco = P.class_op_count[cl];
+    const int qm = P.class_max_q[cl], pm = P.class_max_p[cl];
+    auto reduce = [&](int a_kind, const void* a_base, const void* a_first, int b_kind,
+                      const void* b_base, int k, int ty) -> hipError_t {
+      rp.a_kind = a_kind;
+      rp.a_base = a_base;
+      rp.a_first = a_first;
+      rp.b_kind = b_kind;
+      rp.b_base = b_base;
+      rp.k = k;
+      rp.check_last = k >= 0;
+      TimedLaunch tl(P, stream, 2);
+      hipError_t er = launch_outer(mp, P.state_f64, rp, ty, stream);
+      tl.done();
+      return er;
+    };
+    if (grad_params) {
+      // dC = sum dy x^T, dD = sum dy u^T per parameter set
+      e = reduce(RS_DY, nullptr, nullptr, RS_STATE, xfinal, -1, tiles(qm, mp));
+      if (e != hipSuccess) return hip_fail(e, "dC reduction launch");
+      e = launch_sum(sj_dc + P.class_set_start[cl], ncs, qm * mp, 0, rp.partial, P.state_f64, G,
+                     stream);
+      if (e != hipSuccess) return hip_fail(e, "dC sum launch");
+      e = reduce(RS_DY, nullptr, nullptr, RS_U, nullptr, -1, tiles(qm, pm));
+      if (e != hipSuccess) return hip_fail(e, "dD reduction launch");
+      e = launch_sum(sj_dd + P.class_set_start[cl], ncs, qm * pm, 0, rp.partial, P.state_f64, G,
+                     stream);
+      if (e != hipSuccess) return hip_fail(e, "dD sum launch");
+    }
+    // ---- reverse sweep, segment by segment ----
+    for (int j = ml / c; j >= 0; --j) {
+      const int kb = j * c;
+      const int ke = std::min(kb + c - 1, ml);
+      // recompute the stage inputs kb+1..ke from the checkpoint at kb
+      prm.adjoint = 0;
+      prm.flags = 0;
+      prm.xin_first = nullptr;
+      for (int k = kb; k < ke; ++k) {
+        prm.k = k;
+        prm.xin = loc(k);
+        prm.xout = loc(k + 1);
+        prm.n_tiles = P.class_active[cl][k];
+        TimedLaunch tl(P, stream, 0);
+        e = launch_stage(mp, P.compute, prm, stream);
+        if (e != hipSuccess) return hip_fail(e, "recompute stage launch");
+        tl.done();
+      }
+      for (int k = ke; k >= kb; --k) {
+        void* win = W[(k + 1) & 1];
+        void* wout = W[k & 1];
+        if (grad_params) {
+          // dL/dP_k = sum_l g_l^(k+1) x_{l-2^k}^(k)^T
+          e = reduce(RS_STATE, win, gfirst, RS_STATE, loc(k), k, tiles(mp, mp));
+          if (e != hipSuccess) return hip_fail(e, "dP reduction launch");
+          e = launch_sum(sj_dp + P.class_op_start[cl], nco, mp * mp, k, rp.partial, P.state_f64, G,
+                         stream);
+          if (e != hipSuccess) return hip_fail(e, "dP sum launch");
+        }
+        // g^(k) = g^(k+1) + shift_left(P_k^T g^(k+1)); at k = 0 also du
+        prm.adjoint = 1;
+        prm.k = k;
+        prm.src = dy;
+        prm.src_dtype = sdt;
+        prm.dst = du;
+        prm.flags = (du ? SF_EPILOGUE : 0) | SF_STORE_AT_EPI;
+        prm.xin = win;
+        prm.xin_first = gfirst;
+        prm.xout = wout;
+        prm.n_tiles = P.class_active[cl][k];
+        TimedLaunch tl(P, stream, 1);
+        e = launch_stage(mp, P.compute, prm, stream);
+        if (e != hipSuccess) return hip_fail(e, "adjoint stage launch");
+        tl.done();
+      }
+    }
+    prm.xin_first = nullptr;
+    prm.src = u;
+    prm.src_dtype = (int)u_dtype;
+    if (grad_params) {
+      // dBbar = sum g^(0) u^T per operator
+      e = reduce(RS_STATE, W[0], nullptr, RS_U, nullptr, -1, tiles(mp, pm));
+      if (e != hipSuccess) return hip_fail(e, "dBbar reduction launch");
+      e = launch_sum(sj_dbb + P.class_op_start[cl], nco, mp * pm, 0, rp.partial, P.state_f64, G,
+                     stream);
+      if (e != hipSuccess) return hip_fail(e, "dBbar sum launch");
+    }
+  }
+  if (!grad_params) return SSM_OK;
+  // ---- FP64: squaring adjoint, discretization adjoint, per-set sums ----
+  for (size_t gi = 0; gi < P.bgroups.size(); ++gi) {
+    const auto& gr = P.bgroups[gi];
+    if (P.bkind[gi] == 0)
+      e = launch_gemm_f64(bj_d + gr.first, gr.second, P.bdims[gi].first, P.bdims[gi].second,
+                          stream);
+    else
+      e = launch_axpy(bj_d + gr.first, gr.second, P.bdims[gi].first, P.bdims[gi].second, stream);
+    if (e != hipSuccess) return hip_fail(e, "FP64 adjoint launch");
+  }
+  e = launch_scatter(reinterpret_cast<const ScatterJob*>(meta + P.m_scat), (int)P.scat.size(),
+                     reinterpret_cast<const int32_t*>(meta + P.m_set_ops),
+                     reinterpret_cast<const OpDev*>(meta + P.m_ops), G, grad_params, P.max_mp,
+                     stream);
+  if (e != hipSuccess) return hip_fail(e, "gradient scatter launch");
+  return SSM_OK;
 }
 
 size_t ssm_cascade_param_grad_numel(ssm_plan plan) {
   if (!plan) return 0;
-  size_t n = 0;
-  for (int s = 0; s < plan->n_sets; ++s) {
-    const size_t m = plan->set_m[s] < 0 ? 0 : plan->set_m[s];
-    const size_t p = plan->set_p[s] < 0 ? 0 : plan->set_p[s];
-    const size_t q = plan->set_q[s] < 0 ? 0 : plan->set_q[s];
-    n += m * m + m * p + q * m + q * p;
-  }
-  return n;
+  return plan->grad_numel;
 }
 
 ssm_status ssm_cascade_get_power(ssm_plan plan, int32_t op, int32_t k, double* dst,

@@ -250,6 +250,27 @@ hipError_t launch_gemm_f64(const GemmJob* jobs_dev, int n_jobs, int max_m, int m
   return hipGetLastError();
 }
 
+// C = alpha A + beta C for each job (blockIdx.y = job); M x N, row-major.
+__global__ void k_axpy(const GemmJob* jobs) {
+  const GemmJob jb = jobs[blockIdx.y];
+  const int n = jb.M * jb.N;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int i = e / jb.N, j = e % jb.N;
+    double* cp = jb.C + (int64_t)i * jb.ldc + j;
+    const double r = jb.alpha * jb.A[(int64_t)i * jb.lda + j];
+    *cp = jb.beta == 0.0 ? r : r + jb.beta * *cp;
+  }
+}
+
+hipError_t launch_axpy(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n,
+                       hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  int bx = (max_m * max_n + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_axpy, dim3(bx, n_jobs), dim3(256), 0, s, jobs_dev);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Cast of the powers to the compute type and of the small matrices to the
 // state type. FP64 -> bfloat16 is rounded once, to nearest even, straight

@@ -170,6 +170,7 @@ __global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
   const int k = prm.k;
   if (!noupd && k > sq.last) return;
   const bool adj = prm.adjoint != 0;
+  const bool first = !noupd && (adj ? k == sq.last : k == 0);
   const bool final_ = noupd || (adj ? k == 0 : k == sq.last);
   const bool epi = (prm.flags & SF_EPILOGUE) && final_;
   const bool store = !epi || (prm.flags & SF_STORE_AT_EPI);
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
   const bool upd = !noupd && (adj ? (row0 + s < L) : (rlast >= s));
 
   const X* small = reinterpret_cast<const X*>(prm.small);
-  const X* xin = reinterpret_cast<const X*>(prm.xin) + sq.x_off;
+  const X* xin = reinterpret_cast<const X*>(first && prm.xin_first ? prm.xin_first : prm.xin) +
+                 sq.x_off;
   X* xout = reinterpret_cast<X*>(prm.xout) + sq.x_off;
   const int r_in = adj ? sq.q : sq.p;  // width of the src rows
   const int64_t src_off = adj ? sq.y_off : sq.u_off;
@@ -280,7 +282,8 @@ __global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
   }
 
   // ---- store the state rows ----
-  if (store) {
+  X* xfin = final_ && prm.xfinal ? reinterpret_cast<X*>(prm.xfinal) + sq.x_off : nullptr;
+  if (store || xfin) {
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -289,7 +292,10 @@ __global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t l = row0 + (wr * RB + rb) * 16 + TR::acc_row(lgrp, v);
-          if (l < L) xout[l * MP + col] = acc[rb][cb][v];
+          if (l < L) {
+            if (store) xout[l * MP + col] = acc[rb][cb][v];
+            if (xfin) xfin[l * MP + col] = acc[rb][cb][v];
+          }
         }
       }
     }

@@ -36,6 +36,12 @@ struct OpDev {
   int64_t bbar;  // FP64 Bbar (mp x p)
   int64_t minv;  // FP64 (I - delta/2 A)^{-1} (mp x mp)
   int64_t sc_aug, sc_n, sc_b;  // prepare scratch: [M | I] (mp x 2mp), I + hA, delta B
+  // backward, FP64 gradient workspace offsets
+  int64_t g_dp;    // dL/dP_k, k = 0..N (mp x mp each); becomes the squaring adjoint
+  int64_t g_dbb;   // dL/dBbar (mp x p)
+  int64_t g_s;     // scratch (mp x mp)
+  int64_t g_da;    // dL/dA of this operator (mp x mp)
+  int64_t g_db;    // dL/dB of this operator (mp x p)
   int32_t mp, m, p, q, N, set;
   double delta;
 };
@@ -62,6 +68,8 @@ struct StageParams {
   const void* small;  // small-matrix base (state type)
   const void* xin;    // state rows read
   void* xout;         // state rows written
+  const void* xin_first;  // if set: rows read at a sequence's first stage of the direction
+  void* xfinal;           // if set: state rows also stored here at a sequence's last stage
   const void* src;    // u (forward) or dy (adjoint)
   void* dst;          // y (forward) or du (adjoint)
   int32_t src_dtype;  // DT_* of src
@@ -69,6 +77,54 @@ struct StageParams {
   int32_t adjoint;    // 0: x_l += P_k x_{l-2^k};  1: g_l += P_k^T g_{l+2^k}
   int32_t flags;
   int32_t n_tiles;
+};
+
+// ---- backward ----
+// A chunk of rows of one sequence for the outer-product reductions.
+struct RedChunk {
+  int32_t seq, row0, nrows, slot;
+};
+
+// Row sources of the outer-product reductions.
+enum : int32_t { RS_STATE = 0, RS_U = 1, RS_DY = 2 };
+
+// partial[slot] = sum over the chunk's rows l of a_l b_{l-s}^T  (dimA x dimB),
+// a_l / b_l taken from a state buffer (width mp), u (width p) or dy (width q).
+struct RedParams {
+  const RedChunk* chunks;
+  const SeqDev* seqs;
+  const void* a_base;   // state buffer for RS_STATE
+  const void* a_first;  // state buffer read instead at k == seq.last (adjoint start), or null
+  const void* b_base;   // state buffer for RS_STATE
+  const void* u;        // user input (u_dtype)
+  const void* dy;       // user output cotangent (state type)
+  int32_t u_dtype;
+  int32_t a_kind, b_kind;
+  int32_t k;           // b rows are shifted by 2^k; -1: no shift
+  int32_t check_last;  // sequences with last < k contribute nothing
+  int32_t n_chunks;
+  void* partial;        // state type, slot stride slot_stride elements
+  int64_t slot_stride;
+};
+
+// out[e] (FP64) = sum of partial[slot0 + c][e], c < nslots, e < elems.
+struct SumJob {
+  int64_t slot0;
+  int32_t nslots, elems;
+  int64_t slot_stride;
+  int64_t out;     // element offset into the FP64 gradient workspace
+  int64_t kstride; // added k times (per-stage outputs)
+  int32_t kmax;    // the job is skipped for k > kmax
+  int32_t reserved;
+};
+
+// Sum over the operators of a parameter set and crop of the padding into the
+// caller's flat gradient buffer.
+struct ScatterJob {
+  int32_t op_first, n_ops;  // range in the set-ordered operator list
+  int32_t m, mp, p, q;
+  int64_t dC, dD;  // FP64 workspace offsets of the set's dC (q x mp) and dD (q x p)
+  int64_t out;     // offset of the set's block in the caller's buffer
 };
 
 // FP64 GEMM job: C = alpha * op(A) * op(B) + beta * C, row-major.
@@ -106,6 +162,9 @@ hipError_t launch_project(int mp, int state_f64, const StageParams& prm, hipStre
 
 hipError_t launch_gemm_f64(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n,
                            hipStream_t s);
+// C = alpha A + beta C per job (B, K, ldb, trans* unused).
+hipError_t launch_axpy(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n,
+                       hipStream_t s);
 
 // Builds, per operator, the trapezoid system [I - h A | I] (aug, mp x 2mp),
 // I + h A (nmat, mp x mp) and delta*B (bsc, mp x p); for given parameters
@@ -124,6 +183,14 @@ hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double*
 hipError_t launch_pack(const OpDev* ops, int n_ops, const OpSrc* src, const double* pw,
                        const double* bbar, void* pc, int ct, int want_t, void* small,
                        int state_is_f64, int max_mp, int max_N, hipStream_t s);
+
+hipError_t launch_outer(int mp, int state_f64, const RedParams& prm, int tiles_y,
+                        hipStream_t s);
+hipError_t launch_sum(const SumJob* jobs, int n_jobs, int max_elems, int k,
+                      const void* partial, int state_f64, double* out, hipStream_t s);
+hipError_t launch_scatter(const ScatterJob* jobs, int n_jobs, const int32_t* set_ops,
+                          const OpDev* ops, const double* gws, double* out, int max_mp,
+                          hipStream_t s);
 
 hipError_t launch_recursion(int mp, int ct, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const double* bbar, const void* u,
