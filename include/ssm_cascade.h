@@ -76,6 +76,23 @@ typedef enum {
   SSM_DISC_GIVEN = 1
 } ssm_disc;
 
+typedef enum {
+  SSM_LAUNCH_AUTO = 0,      /* persistent for ragged batches, per stage otherwise */
+  SSM_LAUNCH_PER_STAGE = 1, /* one kernel launch per stage */
+  SSM_LAUNCH_PERSISTENT = 2 /* one persistent launch for the whole forward pass */
+} ssm_launch;
+
+/* Tuning choices of a plan (host memory); a NULL pointer means all defaults.
+ * tile_rows[i] is the number of time rows per stage tile for the padded state
+ * size 32 << i (i = 0..3): 0 keeps the default, otherwise it must be the
+ * default or half of it (the persistent launch always uses the defaults).
+ * Defaults: 256, 128, 64, 64 rows for F32/BF16 and 128, 64, 64, 32 for F64. */
+typedef struct {
+  int32_t launch;        /* ssm_launch */
+  int32_t tile_rows[4];
+  int32_t reserved[11];  /* must be 0 */
+} ssm_tuning;
+
 /* One sequence of a (possibly ragged) batch. Host memory. */
 typedef struct {
   int32_t m, p, q;     /* state, input and output sizes; must equal its parameter set's */
@@ -112,8 +129,14 @@ typedef struct {
   int64_t total_steps;       /* sum of L over sequences */
   double stage_flops;        /* sum over sequences and run stages of 2 m^2 (L - 2^k) */
   double io_flops;           /* 2 m p L (input) + 2 q (m + p) L (output), summed */
-  double stage_bytes;        /* algorithmic HBM bytes of the stage launches (see below) */
-  int64_t stage_launches;    /* kernel launches of the stage kernel per apply */
+  double stage_bytes;        /* algorithmic HBM bytes of the stage kernel: per stage and row,
+                                read the row, read its shifted partner (rows that have one)
+                                and write the row; the last stage writes y instead */
+  int64_t stage_launches;    /* stage-kernel launches per apply (per-stage mode) */
+  int32_t launch;            /* ssm_launch the plan uses (never AUTO) */
+  int32_t tile_rows[4];      /* rows per stage tile per padded state size */
+  int32_t persistent_grid;   /* workgroups of the persistent launch */
+  int64_t persistent_items;  /* work items of the persistent launch */
 } ssm_plan_info;
 
 typedef struct ssm_plan_s* ssm_plan;
@@ -127,7 +150,8 @@ typedef struct ssm_plan_s* ssm_plan;
  * Returns 0 if the descriptors are invalid (ssm_last_error() says why). */
 size_t ssm_cascade_workspace_bytes(const ssm_seq_desc* seqs, int32_t n_seq,
                                    ssm_disc disc, ssm_dtype compute,
-                                   int32_t with_backward, int32_t ckpt_every);
+                                   int32_t with_backward, int32_t ckpt_every,
+                                   const ssm_tuning* tuning);
 
 /* Discretize, take the powers and pack them (the precomputation of §2-§3:
  * Abar^{2^k} by repeated squaring, k = 0..N). seqs: host array of n_seq
@@ -138,14 +162,14 @@ size_t ssm_cascade_workspace_bytes(const ssm_seq_desc* seqs, int32_t n_seq,
  * sharing (param_set, delta) share one operator (sharing param_set alone for
  * SSM_DISC_GIVEN). ws: device workspace of ws_bytes >=
  * ssm_cascade_workspace_bytes(seqs, n_seq, disc, compute, with_backward,
- * ckpt_every). On success *out receives a new plan (free it with
+ * ckpt_every, tuning) with the same tuning. On success *out receives a new plan (free it with
  * ssm_cascade_destroy). Synchronizes `stream` once at the end; returns
  * SSM_E_NUMERIC if some I - delta/2 A was singular to working precision. */
 ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq,
                                const ssm_params* sets, int32_t n_sets,
                                ssm_disc disc, ssm_dtype compute,
                                int32_t with_backward, int32_t ckpt_every,
-                               void* ws, size_t ws_bytes,
+                               const ssm_tuning* tuning, void* ws, size_t ws_bytes,
                                hipStream_t stream, ssm_plan* out);
 
 /* Forward cascade, eqs. (3.2)-(3.4) and the general step of §3, then
@@ -209,6 +233,26 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);
 ssm_status ssm_cascade_timing_enable(ssm_plan plan, int32_t enable);
 ssm_status ssm_cascade_timing_read(ssm_plan plan, int32_t kind, int64_t* launches,
                                    double* total_ms);
+
+/* HIP graphs of one call. The call is captured on `stream` (which must not be
+ * the legacy default stream 0) with the given buffers and instantiated;
+ * ssm_cascade_graph_launch replays it on any stream. The plan, the workspace
+ * and every buffer must outlive the graph; buffer contents may change
+ * between replays. Timing records are not captured. Nothing the library
+ * enqueues is a memset: counters are cleared by a kernel, so replays start
+ * from the same state. */
+typedef struct ssm_graph_s* ssm_graph;
+
+ssm_status ssm_cascade_graph_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                                   size_t u_numel, void* y, size_t y_numel,
+                                   hipStream_t stream, ssm_graph* out);
+ssm_status ssm_cascade_graph_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                                      size_t u_numel, const void* dy, size_t dy_numel,
+                                      void* du, double* grad_params, size_t grad_numel,
+                                      hipStream_t stream, ssm_graph* out);
+ssm_status ssm_cascade_graph_launch(ssm_graph graph, hipStream_t stream);
+/* NULL is accepted. */
+ssm_status ssm_cascade_graph_destroy(ssm_graph graph);
 
 /* Frees the host plan (not the workspace). NULL is accepted. */
 ssm_status ssm_cascade_destroy(ssm_plan plan);

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libssm_cascade.so")
 SSM_OK, SSM_E_INVALID, SSM_E_UNSUPPORTED, SSM_E_WORKSPACE, SSM_E_HIP, SSM_E_NOT_PREPARED, SSM_E_NUMERIC = range(7)
 SSM_F64, SSM_F32, SSM_BF16 = 0, 1, 2
 SSM_DISC_TRAPEZOID, SSM_DISC_GIVEN = 0, 1
+SSM_LAUNCH_AUTO, SSM_LAUNCH_PER_STAGE, SSM_LAUNCH_PERSISTENT = 0, 1, 2
 
 # kernel classes of ssm_cascade_timing_read
 TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION = 0, 1, 2, 3
@@ -50,12 +51,26 @@ class ssm_params(C.Structure):
     ]
 
 
+class ssm_tuning(C.Structure):
+    _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("reserved", C.c_int32 * 11)]
+
+
 class ssm_plan_info(C.Structure):
     _fields_ = [
         ("n_seq", C.c_int32), ("n_ops", C.c_int32), ("compute", C.c_int32), ("max_stage", C.c_int32),
         ("total_steps", C.c_int64), ("stage_flops", C.c_double), ("io_flops", C.c_double),
-        ("stage_bytes", C.c_double), ("stage_launches", C.c_int64),
+        ("stage_bytes", C.c_double), ("stage_launches", C.c_int64), ("launch", C.c_int32),
+        ("tile_rows", C.c_int32 * 4), ("persistent_grid", C.c_int32),
+        ("persistent_items", C.c_int64),
     ]
+
+
+def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0)):
+    t = ssm_tuning()
+    t.launch = int(launch)
+    for i, r in enumerate(tile_rows):
+        t.tile_rows[i] = int(r)
+    return t
 
 
 _lib = None
@@ -65,7 +80,8 @@ EXPORTS = [
     "ssm_cascade_backward", "ssm_cascade_param_grad_numel", "ssm_cascade_recursion",
     "ssm_cascade_get_power", "ssm_cascade_get_bbar", "ssm_cascade_plan_info",
     "ssm_cascade_timing_enable", "ssm_cascade_timing_read", "ssm_cascade_destroy",
-    "ssm_status_string", "ssm_last_error",
+    "ssm_cascade_graph_apply", "ssm_cascade_graph_backward", "ssm_cascade_graph_launch",
+    "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error",
 ]
 
 
@@ -80,10 +96,19 @@ def load(path=LIB_PATH):
     vp, i32, i64, sz, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
     P = C.POINTER
     lib.ssm_cascade_workspace_bytes.restype = sz
-    lib.ssm_cascade_workspace_bytes.argtypes = [P(ssm_seq_desc), i32, i32, i32, i32, i32]
+    lib.ssm_cascade_workspace_bytes.argtypes = [P(ssm_seq_desc), i32, i32, i32, i32, i32,
+                                                P(ssm_tuning)]
     lib.ssm_cascade_prepare.restype = i32
     lib.ssm_cascade_prepare.argtypes = [P(ssm_seq_desc), i32, P(ssm_params), i32, i32, i32, i32,
-                                        i32, vp, sz, vp, P(vp)]
+                                        i32, P(ssm_tuning), vp, sz, vp, P(vp)]
+    lib.ssm_cascade_graph_apply.restype = i32
+    lib.ssm_cascade_graph_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp, P(vp)]
+    lib.ssm_cascade_graph_backward.restype = i32
+    lib.ssm_cascade_graph_backward.argtypes = [vp, vp, i32, sz, vp, sz, vp, vp, sz, vp, P(vp)]
+    lib.ssm_cascade_graph_launch.restype = i32
+    lib.ssm_cascade_graph_launch.argtypes = [vp, vp]
+    lib.ssm_cascade_graph_destroy.restype = i32
+    lib.ssm_cascade_graph_destroy.argtypes = [vp]
     lib.ssm_cascade_apply.restype = i32
     lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
     lib.ssm_cascade_recursion.restype = i32
@@ -133,16 +158,16 @@ def _descs(descs):
     return arr
 
 
-def ssm_cascade_workspace_bytes(descs, disc, compute, with_backward, ckpt_every=0):
+def ssm_cascade_workspace_bytes(descs, disc, compute, with_backward, ckpt_every=0, tuning=None):
     arr = _descs(descs)
     n = load().ssm_cascade_workspace_bytes(arr, len(descs), disc, compute, int(with_backward),
-                                           ckpt_every)
+                                           ckpt_every, C.byref(tuning) if tuning is not None else None)
     if n == 0:
         raise SSMError(SSM_E_INVALID, "ssm_cascade_workspace_bytes", ssm_last_error())
     return n
 
 
-def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every, ws_ptr,
+def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every, tuning, ws_ptr,
                         ws_bytes, stream):
     arr = _descs(descs)
     parr = (ssm_params * len(params))()
@@ -150,8 +175,9 @@ def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every,
         parr[i] = p if isinstance(p, ssm_params) else ssm_params(**p)
     plan = C.c_void_p()
     _check(load().ssm_cascade_prepare(arr, len(descs), parr, len(params), disc, compute,
-                                      int(with_backward), ckpt_every, ws_ptr, ws_bytes, stream,
-                                      C.byref(plan)), "ssm_cascade_prepare")
+                                      int(with_backward), ckpt_every,
+                                      C.byref(tuning) if tuning is not None else None, ws_ptr,
+                                      ws_bytes, stream, C.byref(plan)), "ssm_cascade_prepare")
     return plan.value
 
 
@@ -186,7 +212,9 @@ def ssm_cascade_get_bbar(plan, op, dst_ptr, stream):
 def ssm_cascade_plan_info(plan):
     info = ssm_plan_info()
     _check(load().ssm_cascade_plan_info(plan, C.byref(info)), "ssm_cascade_plan_info")
-    return {f: getattr(info, f) for f, _ in ssm_plan_info._fields_}
+    out = {f: getattr(info, f) for f, _ in ssm_plan_info._fields_}
+    out["tile_rows"] = list(info.tile_rows)
+    return out
 
 
 def ssm_cascade_timing_enable(plan, enable):
@@ -203,3 +231,27 @@ def ssm_cascade_timing_read(plan, kind):
 
 def ssm_cascade_destroy(plan):
     _check(load().ssm_cascade_destroy(plan), "ssm_cascade_destroy")
+
+
+def ssm_cascade_graph_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
+    g = C.c_void_p()
+    _check(load().ssm_cascade_graph_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream,
+                                          C.byref(g)), "ssm_cascade_graph_apply")
+    return g.value
+
+
+def ssm_cascade_graph_backward(plan, u_ptr, u_dtype, u_numel, dy_ptr, dy_numel, du_ptr, grad_ptr,
+                               grad_numel, stream):
+    g = C.c_void_p()
+    _check(load().ssm_cascade_graph_backward(plan, u_ptr, u_dtype, u_numel, dy_ptr, dy_numel,
+                                             du_ptr, grad_ptr, grad_numel, stream, C.byref(g)),
+           "ssm_cascade_graph_backward")
+    return g.value
+
+
+def ssm_cascade_graph_launch(graph, stream):
+    _check(load().ssm_cascade_graph_launch(graph, stream), "ssm_cascade_graph_launch")
+
+
+def ssm_cascade_graph_destroy(graph):
+    _check(load().ssm_cascade_graph_destroy(graph), "ssm_cascade_graph_destroy")

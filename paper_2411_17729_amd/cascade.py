@@ -57,7 +57,7 @@ class CascadePlan:
 
     def __init__(self, layout: Layout, params: Sequence, disc: str = "trapezoid",
                  compute: str = "f32", with_backward: bool = False, ckpt_every: int = 0,
-                 device="cuda"):
+                 device="cuda", launch="auto", tile_rows=(0, 0, 0, 0)):
         if not torch.cuda.is_available():
             raise RuntimeError("the fast-cascade library needs a ROCm GPU")
         B.load()
@@ -81,13 +81,17 @@ class CascadePlan:
             m, p, q = ts[0].shape[0], ts[1].shape[1], ts[2].shape[0]
             cparams.append(B.ssm_params(A=ts[0].data_ptr(), B=ts[1].data_ptr(), C=ts[2].data_ptr(),
                                         D=ts[3].data_ptr(), m=m, p=p, q=q, reserved=0))
+        mode = {"auto": B.SSM_LAUNCH_AUTO, "per_stage": B.SSM_LAUNCH_PER_STAGE,
+                "persistent": B.SSM_LAUNCH_PERSISTENT}[launch] if isinstance(launch, str) else int(launch)
+        self.tuning = B.make_tuning(mode, tile_rows)
         nbytes = B.ssm_cascade_workspace_bytes(layout.descs, self.disc, self.compute,
-                                               with_backward, ckpt_every)
+                                               with_backward, ckpt_every, self.tuning)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) // 256 * 256
         self.plan = B.ssm_cascade_prepare(layout.descs, cparams, self.disc, self.compute,
-                                          with_backward, ckpt_every, self.ws_ptr, nbytes, _stream())
+                                          with_backward, ckpt_every, self.tuning, self.ws_ptr,
+                                          nbytes, _stream())
         self.with_backward = with_backward
 
     # -- forward ---------------------------------------------------------
@@ -132,6 +136,29 @@ class CascadePlan:
                 off += r * c
             out.append(parts)
         return out
+
+    # -- HIP graphs --------------------------------------------------------
+    def graph_apply(self, u: torch.Tensor, y: torch.Tensor, stream: torch.cuda.Stream):
+        """Captures apply(u) -> y on ``stream`` (not the default stream) into a
+        graph; returns a handle for ``graph_launch``."""
+        u = self._check_u(u)
+        return B.ssm_cascade_graph_apply(self.plan, u.data_ptr(), self._u_code(u), u.numel(),
+                                         y.data_ptr(), y.numel(), stream.cuda_stream)
+
+    def graph_backward(self, u, dy, du, g, stream: torch.cuda.Stream):
+        u = self._check_u(u)
+        return B.ssm_cascade_graph_backward(
+            self.plan, u.data_ptr(), self._u_code(u), u.numel(), dy.data_ptr(), dy.numel(),
+            du.data_ptr() if du is not None else None, g.data_ptr() if g is not None else None,
+            g.numel() if g is not None else 0, stream.cuda_stream)
+
+    @staticmethod
+    def graph_launch(graph, stream: torch.cuda.Stream):
+        B.ssm_cascade_graph_launch(graph, stream.cuda_stream)
+
+    @staticmethod
+    def graph_destroy(graph):
+        B.ssm_cascade_graph_destroy(graph)
 
     # -- inspection ------------------------------------------------------
     def power(self, op: int, k: int) -> torch.Tensor:
@@ -185,13 +212,15 @@ class CascadePlan:
             pass
 
 
-def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, device="cuda"):
+def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, device="cuda",
+                      launch="auto", tile_rows=(0, 0, 0, 0)):
     """Builds the layout and plan of a ``workloads.Workload``."""
     dims = [(ps.m, ps.p, ps.q) for ps in wl.sets]
     layout = make_layout(wl.seqs, dims)
     params = [(ps.A, ps.B, ps.C, ps.D) for ps in wl.sets]
     return CascadePlan(layout, params, disc="given" if wl.given else "trapezoid", compute=compute,
-                       with_backward=with_backward, ckpt_every=ckpt_every, device=device)
+                       with_backward=with_backward, ckpt_every=ckpt_every, device=device,
+                       launch=launch, tile_rows=tile_rows)
 
 
 def pack_u(wl, dtype=torch.float32, device="cuda"):

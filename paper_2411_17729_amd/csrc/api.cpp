@@ -107,6 +107,15 @@ struct ssm_plan_s {
   bool timing = false;
   std::vector<TimingRec> trec;
   std::vector<hipEvent_t> event_pool;  // events reused across timing reads
+  // tuning
+  int launch = SSM_LAUNCH_PER_STAGE;
+  int class_bm[4] = {0, 0, 0, 0};
+  // persistent launch
+  std::vector<PItem> items;
+  std::vector<int32_t> cnt_off, ntiles;
+  int64_t n_counters = 0;
+  int persistent_grid = 0;
+  size_t m_items = 0, m_cntoff = 0, m_ntiles = 0, m_counters = 0;
   // backward
   int n_ckpt = 0, n_seg = 0, chunk_rows = 256;
   int64_t sum_x = 0;  // elements of one state buffer (all sequences)
@@ -163,9 +172,23 @@ void plan_backward_jobs(ssm_plan_s& P);
 
 // Builds sequences, operators, tiles, info and the workspace layout.
 ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ssm_disc disc,
-                      ssm_dtype compute, int32_t with_backward, int32_t ckpt_every) {
+                      ssm_dtype compute, int32_t with_backward, int32_t ckpt_every,
+                      const ssm_tuning* tuning) {
   ssm_status st = validate_seqs(seqs, n_seq);
   if (st != SSM_OK) return st;
+  ssm_tuning tn{};
+  if (tuning) tn = *tuning;
+  for (int i = 0; i < 11; ++i)
+    if (tn.reserved[i] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.launch < SSM_LAUNCH_AUTO || tn.launch > SSM_LAUNCH_PERSISTENT)
+    return fail(SSM_E_INVALID, "unknown launch mode %d", tn.launch);
+  for (int c = 0; c < 4; ++c) {
+    const int d = stage_bm(kClassMp[c], (int)compute);
+    const int r = tn.tile_rows[c];
+    if (r != 0 && r != d && r != d / 2)
+      return fail(SSM_E_INVALID, "tile_rows[%d] = %d: supported %d or %d", c, r, d, d / 2);
+    P.class_bm[c] = r ? r : d;
+  }
   if (disc != SSM_DISC_TRAPEZOID && disc != SSM_DISC_GIVEN)
     return fail(SSM_E_INVALID, "unknown discretization %d", (int)disc);
   if (compute != SSM_F64 && compute != SSM_F32 && compute != SSM_BF16)
@@ -246,7 +269,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       if (P.ops[P.seqs[i].op].mp == kClassMp[c]) ids.push_back(i);
     std::stable_sort(ids.begin(), ids.end(),
                      [&](int a, int b) { return P.seqs[a].last > P.seqs[b].last; });
-    const int bm = stage_bm(kClassMp[c], P.compute);
+    const int bm = P.class_bm[c];
     P.class_tile_start[c] = (int)P.tiles.size();
     int ml = -1;
     for (int i : ids) {
@@ -261,6 +284,50 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       for (int ti = P.class_tile_start[c]; ti < (int)P.tiles.size(); ++ti)
         if (P.seqs[P.tiles[ti].seq].last >= kk) ++cnt;
       P.class_active[c][kk] = cnt;
+    }
+  }
+
+  // launch mode: persistent for ragged batches unless asked otherwise
+  {
+    int classes = 0, lmin = 1 << 30, lmax = -1;
+    for (int c = 0; c < 4; ++c) classes += P.class_tile_count[c] > 0;
+    for (const SeqDev& sq : P.seqs) {
+      lmin = std::min(lmin, sq.last);
+      lmax = std::max(lmax, sq.last);
+    }
+    P.launch = tn.launch == SSM_LAUNCH_AUTO
+                   ? ((classes > 1 || lmin != lmax) ? SSM_LAUNCH_PERSISTENT : SSM_LAUNCH_PER_STAGE)
+                   : tn.launch;
+  }
+  // persistent work items, level by level (projection = level -1), longer
+  // sequences first inside a level; default tile heights
+  P.items.clear();
+  P.cnt_off.assign(n_seq, 0);
+  P.ntiles.assign(n_seq, 0);
+  if (P.launch == SSM_LAUNCH_PERSISTENT) {
+    std::vector<int> order(n_seq);
+    for (int i = 0; i < n_seq; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
+    int64_t cnt = 1;  // counter 0 hands out tickets
+    int maxl = 0;
+    for (int i = 0; i < n_seq; ++i) {
+      const int mp = P.ops[P.seqs[i].op].mp;
+      const int bm = stage_bm(mp, P.compute);
+      P.ntiles[i] = (int32_t)((P.seqs[i].L + bm - 1) / bm);
+      P.cnt_off[i] = (int32_t)cnt;
+      cnt += P.seqs[i].last + 2;
+      maxl = std::max(maxl, P.seqs[i].last);
+    }
+    P.n_counters = cnt;
+    for (int lev = -1; lev <= maxl; ++lev) {
+      for (int i : order) {
+        const SeqDev& sq = P.seqs[i];
+        if (lev > sq.last) continue;
+        const int mp = P.ops[sq.op].mp;
+        const int bm = stage_bm(mp, P.compute);
+        for (int t = 0; t < P.ntiles[i]; ++t) P.items.push_back(PItem{i, lev, t * bm, mp});
+      }
     }
   }
 
@@ -383,6 +450,16 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
   P.sum_x = xoff;
+  if (P.launch == SSM_LAUNCH_PERSISTENT) {
+    P.m_items = off;
+    off = align_up(off + sizeof(PItem) * std::max<size_t>(1, P.items.size()));
+    P.m_cntoff = off;
+    off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, P.cnt_off.size()));
+    P.m_ntiles = off;
+    off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, P.ntiles.size()));
+    P.m_counters = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)P.n_counters);
+  }
   if (P.with_backward) {
     plan_backward(P);
     size_t n_bjobs = 0;
@@ -710,16 +787,18 @@ const char* ssm_last_error(void) { return g_last_error.c_str(); }
 
 size_t ssm_cascade_workspace_bytes(const ssm_seq_desc* seqs, int32_t n_seq, ssm_disc disc,
                                    ssm_dtype compute, int32_t with_backward,
-                                   int32_t ckpt_every) {
+                                   int32_t ckpt_every, const ssm_tuning* tuning) {
   ssm_plan_s P;
-  if (build_plan(P, seqs, n_seq, disc, compute, with_backward, ckpt_every) != SSM_OK) return 0;
+  if (build_plan(P, seqs, n_seq, disc, compute, with_backward, ckpt_every, tuning) != SSM_OK)
+    return 0;
   return P.ws_bytes;
 }
 
 ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ssm_params* sets,
                                int32_t n_sets, ssm_disc disc, ssm_dtype compute,
-                               int32_t with_backward, int32_t ckpt_every, void* ws,
-                               size_t ws_bytes, hipStream_t stream, ssm_plan* out) {
+                               int32_t with_backward, int32_t ckpt_every,
+                               const ssm_tuning* tuning, void* ws, size_t ws_bytes,
+                               hipStream_t stream, ssm_plan* out) {
   g_last_error.clear();
   if (!out) return fail(SSM_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -727,7 +806,7 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (!ws) return fail(SSM_E_INVALID, "workspace is NULL");
   ssm_plan_s* P = new (std::nothrow) ssm_plan_s();
   if (!P) return fail(SSM_E_INVALID, "out of host memory");
-  ssm_status st = build_plan(*P, seqs, n_seq, disc, compute, with_backward, ckpt_every);
+  ssm_status st = build_plan(*P, seqs, n_seq, disc, compute, with_backward, ckpt_every, tuning);
   if (st != SSM_OK) {
     delete P;
     return st;
@@ -843,6 +922,20 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                 sizeof(Tile) * P->tiles.size());
   if (!J.empty())
     std::memcpy(P->meta_host.data() + P->m_jobs, J.data(), sizeof(GemmJob) * J.size());
+  if (P->launch == SSM_LAUNCH_PERSISTENT) {
+    unsigned char* mh = P->meta_host.data();
+    if (!P->items.empty())
+      std::memcpy(mh + P->m_items, P->items.data(), sizeof(PItem) * P->items.size());
+    std::memcpy(mh + P->m_cntoff, P->cnt_off.data(), sizeof(int32_t) * P->cnt_off.size());
+    std::memcpy(mh + P->m_ntiles, P->ntiles.data(), sizeof(int32_t) * P->ntiles.size());
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+      ncu = 256;
+    const int64_t g = (int64_t)persistent_blocks_per_cu(P->compute) * ncu;
+    P->persistent_grid = (int)std::min<int64_t>(g, (int64_t)P->items.size());
+  }
   if (P->with_backward) {
     plan_backward_jobs(*P);
     unsigned char* mh = P->meta_host.data();
@@ -920,6 +1013,30 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
   ssm_plan_s& P = *plan;
   ssm_status st = check_io(P, u, u_dtype, u_numel, y, y_numel, "y");
   if (st != SSM_OK) return st;
+  if (P.launch == SSM_LAUNCH_PERSISTENT) {
+    unsigned char* meta = P.ws + P.r_meta.off;
+    PersistParams pp{};
+    pp.base = base_params(P, 0);
+    pp.base.tiles = nullptr;
+    pp.base.src = u;
+    pp.base.src_dtype = (int)u_dtype;
+    pp.base.dst = y;
+    pp.base.flags = SF_EPILOGUE;
+    pp.items = reinterpret_cast<const PItem*>(meta + P.m_items);
+    pp.n_items = (int32_t)P.items.size();
+    pp.counters = reinterpret_cast<int32_t*>(meta + P.m_counters);
+    pp.cnt_off = reinterpret_cast<const int32_t*>(meta + P.m_cntoff);
+    pp.ntiles = reinterpret_cast<const int32_t*>(meta + P.m_ntiles);
+    pp.x0 = P.ws + P.r_x0.off;
+    pp.x1 = P.ws + P.r_x1.off;
+    hipError_t e = launch_zero_i32(pp.counters, P.n_counters, stream);
+    if (e != hipSuccess) return hip_fail(e, "counter reset launch");
+    TimedLaunch tl(P, stream, 0);
+    e = launch_persistent(P.compute, pp, P.persistent_grid, stream);
+    if (e != hipSuccess) return hip_fail(e, "persistent launch");
+    tl.done();
+    return SSM_OK;
+  }
   for (int c = 0; c < 4; ++c) {
     if (P.class_tile_count[c] == 0) continue;
     StageParams prm = base_params(P, c);
@@ -930,7 +1047,7 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     // V^(0) = Bbar U into the first state buffer
     prm.xout = P.ws + P.r_x0.off;
     prm.n_tiles = P.class_tile_count[c];
-    hipError_t e = launch_project(kClassMp[c], P.state_f64, prm, stream);
+    hipError_t e = launch_project(kClassMp[c], P.state_f64, P.class_bm[c], prm, stream);
     if (e != hipSuccess) return hip_fail(e, "projection launch");
     prm.flags = SF_EPILOGUE;
     for (int kk = 0; kk <= P.class_max_last[c]; ++kk) {
@@ -939,7 +1056,7 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       prm.xout = P.ws + ((kk & 1) ? P.r_x0.off : P.r_x1.off);
       prm.n_tiles = P.class_active[c][kk];
       TimedLaunch tl(P, stream, 0);
-      e = launch_stage(kClassMp[c], P.compute, prm, stream);
+      e = launch_stage(kClassMp[c], P.compute, P.class_bm[c], prm, stream);
       if (e != hipSuccess) return hip_fail(e, "stage launch");
       tl.done();
     }
@@ -975,7 +1092,7 @@ ssm_status ssm_cascade_recursion(ssm_plan plan, const void* u, ssm_dtype u_dtype
     prm.xin = P.ws + P.r_x0.off;
     prm.xout = P.ws + P.r_x1.off;
     prm.n_tiles = P.class_tile_count[c];
-    hipError_t e = launch_stage(kClassMp[c], P.compute, prm, stream);
+    hipError_t e = launch_stage(kClassMp[c], P.compute, P.class_bm[c], prm, stream);
     if (e != hipSuccess) return hip_fail(e, "projection launch");
   }
   return SSM_OK;
@@ -1029,7 +1146,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
     prm.adjoint = 0;
     prm.xout = loc(0);
     prm.n_tiles = P.class_tile_count[cl];
-    e = launch_project(mp, P.state_f64, prm, stream);
+    e = launch_project(mp, P.state_f64, P.class_bm[cl], prm, stream);
     if (e != hipSuccess) return hip_fail(e, "projection launch");
     prm.flags = 0;
     prm.xfinal = xfinal;
@@ -1039,7 +1156,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       prm.xout = loc(k + 1);
       prm.n_tiles = P.class_active[cl][k];
       TimedLaunch tl(P, stream, 0);
-      e = launch_stage(mp, P.compute, prm, stream);
+      e = launch_stage(mp, P.compute, P.class_bm[cl], prm, stream);
       if (e != hipSuccess) return hip_fail(e, "stage launch");
       tl.done();
     }
@@ -1050,7 +1167,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
     prm.src_dtype = sdt;
     prm.xout = gfirst;
     prm.n_tiles = P.class_tile_count[cl];
-    e = launch_project(mp, P.state_f64, prm, stream);
+    e = launch_project(mp, P.state_f64, P.class_bm[cl], prm, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint projection launch");
 
     RedParams rp{};
@@ -1105,7 +1222,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
         prm.xout = loc(k + 1);
         prm.n_tiles = P.class_active[cl][k];
         TimedLaunch tl(P, stream, 0);
-        e = launch_stage(mp, P.compute, prm, stream);
+        e = launch_stage(mp, P.compute, P.class_bm[cl], prm, stream);
         if (e != hipSuccess) return hip_fail(e, "recompute stage launch");
         tl.done();
       }
@@ -1132,7 +1249,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
         prm.xout = wout;
         prm.n_tiles = P.class_active[cl][k];
         TimedLaunch tl(P, stream, 1);
-        e = launch_stage(mp, P.compute, prm, stream);
+        e = launch_stage(mp, P.compute, P.class_bm[cl], prm, stream);
         if (e != hipSuccess) return hip_fail(e, "adjoint stage launch");
         tl.done();
       }
@@ -1210,6 +1327,10 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->io_flops = plan->io_flops;
   info->stage_bytes = plan->stage_bytes;
   info->stage_launches = plan->stage_launches;
+  info->launch = plan->launch;
+  for (int c = 0; c < 4; ++c) info->tile_rows[c] = plan->class_bm[c];
+  info->persistent_grid = plan->persistent_grid;
+  info->persistent_items = (int64_t)plan->items.size();
   return SSM_OK;
 }
 
@@ -1242,6 +1363,91 @@ ssm_status ssm_cascade_timing_read(ssm_plan plan, int32_t kind, int64_t* launche
   plan->trec.swap(keep);
   *launches = n;
   *total_ms = ms;
+  return SSM_OK;
+}
+
+}  // extern "C"
+
+struct ssm_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <typename F>
+ssm_status capture(ssm_plan plan, hipStream_t stream, ssm_graph* out, F&& call) {
+  if (!out) return fail(SSM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  if (!stream) return fail(SSM_E_INVALID, "graph capture needs a stream other than 0");
+  const bool timing = plan->timing;
+  plan->timing = false;
+  hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    plan->timing = timing;
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  ssm_status st = call();
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(stream, &g);
+  plan->timing = timing;
+  if (st != SSM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  ssm_graph_s* G = new (std::nothrow) ssm_graph_s();
+  if (!G) {
+    (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
+    return fail(SSM_E_INVALID, "out of host memory");
+  }
+  G->graph = g;
+  G->exec = x;
+  *out = G;
+  return SSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssm_status ssm_cascade_graph_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                                   size_t u_numel, void* y, size_t y_numel, hipStream_t stream,
+                                   ssm_graph* out) {
+  return capture(plan, stream, out, [&]() {
+    return ssm_cascade_apply(plan, u, u_dtype, u_numel, y, y_numel, stream);
+  });
+}
+
+ssm_status ssm_cascade_graph_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                                      size_t u_numel, const void* dy, size_t dy_numel, void* du,
+                                      double* grad_params, size_t grad_numel, hipStream_t stream,
+                                      ssm_graph* out) {
+  return capture(plan, stream, out, [&]() {
+    return ssm_cascade_backward(plan, u, u_dtype, u_numel, dy, dy_numel, du, grad_params,
+                                grad_numel, stream);
+  });
+}
+
+ssm_status ssm_cascade_graph_launch(ssm_graph graph, hipStream_t stream) {
+  if (!graph) return fail(SSM_E_INVALID, "graph is NULL");
+  HIP_TRY(hipGraphLaunch(graph->exec, stream), "hipGraphLaunch");
+  return SSM_OK;
+}
+
+ssm_status ssm_cascade_graph_destroy(ssm_graph graph) {
+  if (!graph) return SSM_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
   return SSM_OK;
 }
 

@@ -116,7 +116,7 @@ struct Mfma<DT_F64> {
   }
 };
 
-template <int MP, int CT>
+template <int MP, int CT, int BM_ = stage_bm(MP, CT)>
 struct StageCfg {
   using TR = CTraits<CT>;
   using X = typename TR::X;
@@ -125,7 +125,7 @@ struct StageCfg {
   static constexpr int WR = 4 / WC;            // waves across the rows
   static constexpr int CW = MP / WC;           // columns per wave
   static constexpr int CB = CW / 16;           // 16-column blocks per wave
-  static constexpr int BM = stage_bm(MP, CT);  // rows per tile
+  static constexpr int BM = BM_;               // rows per tile
   static constexpr int RB = BM / (WR * 16);    // 16-row blocks per wave
   static constexpr int KC0 = 128 / (int)sizeof(Op);
   static constexpr int KC = KC0 < MP ? KC0 : MP;  // K chunk staged in LDS
@@ -141,9 +141,12 @@ struct StageCfg {
   static_assert((SA * sizeof(Op)) % 16 == 0, "LDS rows must stay 16-byte aligned");
 };
 
-template <int MP, int CT>
-__global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
-  using C = StageCfg<MP, CT>;
+// One row tile of one stage (the body shared by the per-stage kernel and the
+// persistent ragged kernel). smem must hold StageCfg<MP, CT>::LDS bytes.
+template <int MP, int CT, int BM_ = stage_bm(MP, CT)>
+__device__ __forceinline__ void stage_tile(const StageParams& prm, const Tile t,
+                                           unsigned char* smem) {
+  using C = StageCfg<MP, CT, BM_>;
   using X = typename C::X;
   using Op = typename C::Op;
   using TR = typename C::TR;
@@ -151,18 +154,10 @@ __global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
   constexpr int BM = C::BM, RB = C::RB, CB = C::CB, CW = C::CW, WC = C::WC, WR = C::WR;
   constexpr int KC = C::KC, SA = C::SA, SE = C::SE;
 
-  __shared__ __attribute__((aligned(16))) unsigned char smem[C::LDS];
   Op* As = reinterpret_cast<Op*>(smem);
   Op* Bs = As + BM * SA;
   X* Es = reinterpret_cast<X*>(smem);
 
-  // Consecutive tiles to one XCD: hardware hands workgroups to the 8 XCDs
-  // round-robin, so tile t of XCD x is start_x + blockIdx.x / 8.
-  const int nt = prm.n_tiles;
-  const int b = blockIdx.x;
-  const int xcd = b & 7, per = nt >> 3, rem = nt & 7;
-  const int tix = xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
-  const Tile t = prm.tiles[tix];
   const SeqDev sq = prm.seqs[t.seq];
   const OpDev o = prm.ops[sq.op];
 
@@ -340,6 +335,21 @@ __global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
   }
 }
 
+
+// Consecutive tiles to one XCD: hardware hands workgroups to the 8 XCDs
+// round-robin, so tile t of XCD x is start_x + blockIdx.x / 8.
+__device__ __forceinline__ int xcd_tile(int nt) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7, per = nt >> 3, rem = nt & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
+}
+
+template <int MP, int CT, int BM>
+__global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[StageCfg<MP, CT, BM>::LDS];
+  stage_tile<MP, CT, BM>(prm, prm.tiles[xcd_tile(prm.n_tiles)], smem);
+}
+
 // ---------------------------------------------------------------------------
 // Input projection of a row tile: out_l = M src_l for every row l of the tile,
 //   forward: v_l = Bbar u_l   (M = Bbar, MP x p; the columns of V^(0), §3)
@@ -348,17 +358,22 @@ __global__ __launch_bounds__(256, 2) void k_stage(StageParams prm) {
 // chunks of 32 source columns; thread t owns state column t % MP.
 // ---------------------------------------------------------------------------
 template <int MP, typename X>
-__global__ __launch_bounds__(256) void k_project(StageParams prm) {
-  constexpr int BM = stage_bm(MP, sizeof(X) == 8 ? DT_F64 : DT_F32);
-  constexpr int RCH = 32;
+struct ProjCfg {
+  static constexpr int PB = 64;  // rows per sub-block
+  static constexpr int RCH = 32; // source columns per LDS chunk
+  static constexpr size_t LDS = (size_t)(MP + PB) * (RCH + 1) * sizeof(X);
+};
+
+// rows: the tile height of the launch's tile table.
+template <int MP, typename X>
+__device__ __forceinline__ void project_tile(const StageParams& prm, const Tile t, int rows,
+                                             unsigned char* smem) {
+  constexpr int PB = ProjCfg<MP, X>::PB;
+  constexpr int RCH = ProjCfg<MP, X>::RCH;
   constexpr int RG = 256 / MP;     // row groups
-  constexpr int RPT = BM / RG;     // rows per thread
-  __shared__ X Ms[MP][RCH + 1];
-  __shared__ X Us[BM][RCH + 1];
-  const int nt = prm.n_tiles;
-  const int b = blockIdx.x;
-  const int xcd = b & 7, per = nt >> 3, rem = nt & 7;
-  const Tile t = prm.tiles[xcd * per + (xcd < rem ? xcd : rem) + (b >> 3)];
+  constexpr int RPT = PB / RG;     // rows per thread per sub-block
+  X (*Ms)[RCH + 1] = reinterpret_cast<X (*)[RCH + 1]>(smem);
+  X (*Us)[RCH + 1] = reinterpret_cast<X (*)[RCH + 1]>(smem + (size_t)MP * (RCH + 1) * sizeof(X));
   const SeqDev sq = prm.seqs[t.seq];
   const OpDev o = prm.ops[sq.op];
   const bool adj = prm.adjoint != 0;
@@ -366,78 +381,203 @@ __global__ __launch_bounds__(256) void k_project(StageParams prm) {
   const int64_t src_off = adj ? sq.y_off : sq.u_off;
   const X* M = reinterpret_cast<const X*>(prm.small) + (adj ? o.ct : o.bin);
   X* out = reinterpret_cast<X*>(prm.xout) + sq.x_off;
-  const int64_t L = sq.L, row0 = t.row0;
+  // rows of this tile: [t.row0, min(L, t.row0 + rows))
+  const int64_t L = (int64_t)t.row0 + rows < sq.L ? (int64_t)t.row0 + rows : sq.L;
   const int tid = threadIdx.x, n = tid % MP, rg = tid / MP;
-  X acc[RPT];
+  for (int sb = 0; sb < rows; sb += PB) {
+    const int64_t row0 = (int64_t)t.row0 + sb;
+    if (row0 >= L) break;
+    X acc[RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) acc[i] = 0;
-  for (int j0 = 0; j0 < r; j0 += RCH) {
-    const int jn = r - j0 < RCH ? r - j0 : RCH;
-    __syncthreads();
-    for (int e = tid; e < MP * RCH; e += 256) {
-      const int nn = e / RCH, jj = e % RCH;
-      Ms[nn][jj] = jj < jn ? M[nn * r + j0 + jj] : (X)0;
-    }
-    for (int e = tid; e < BM * RCH; e += 256) {
-      const int i = e / RCH, jj = e % RCH;
-      const int64_t l = row0 + i;
-      Us[i][jj] = (jj < jn && l < L) ? load_src<X>(prm.src, prm.src_dtype, src_off + l * r + j0 + jj)
-                                     : (X)0;
-    }
-    __syncthreads();
-    for (int jj = 0; jj < jn; ++jj) {
-      const X mv = Ms[n][jj];
+    for (int i = 0; i < RPT; ++i) acc[i] = 0;
+    for (int j0 = 0; j0 < r; j0 += RCH) {
+      const int jn = r - j0 < RCH ? r - j0 : RCH;
+      __syncthreads();
+      for (int e = tid; e < MP * RCH; e += 256) {
+        const int nn = e / RCH, jj = e % RCH;
+        Ms[nn][jj] = jj < jn ? M[nn * r + j0 + jj] : (X)0;
+      }
+      for (int e = tid; e < PB * RCH; e += 256) {
+        const int i = e / RCH, jj = e % RCH;
+        const int64_t l = row0 + i;
+        Us[i][jj] = (jj < jn && l < L) ? load_src<X>(prm.src, prm.src_dtype, src_off + l * r + j0 + jj)
+                                       : (X)0;
+      }
+      __syncthreads();
+      for (int jj = 0; jj < jn; ++jj) {
+        const X mv = Ms[n][jj];
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) acc[i] += mv * Us[i * RG + rg][jj];
+        for (int i = 0; i < RPT; ++i) acc[i] += mv * Us[i * RG + rg][jj];
+      }
     }
-  }
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int64_t l = row0 + i * RG + rg;
-    if (l < L) out[l * MP + n] = acc[i];
+    for (int i = 0; i < RPT; ++i) {
+      const int64_t l = row0 + i * RG + rg;
+      if (l < L) out[l * MP + n] = acc[i];
+    }
   }
 }
 
 template <int MP, typename X>
-static hipError_t launch_proj(const StageParams& prm, hipStream_t s) {
-  if (prm.n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_project<MP, X>), dim3(prm.n_tiles), dim3(256), 0, s, prm);
+__global__ __launch_bounds__(256) void k_project(StageParams prm, int rows) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[ProjCfg<MP, X>::LDS];
+  project_tile<MP, X>(prm, prm.tiles[xcd_tile(prm.n_tiles)], rows, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent ragged forward pass: one launch works through all items of the
+// plan (projection tiles, then stage 0 tiles, stage 1 tiles, ... of every
+// sequence) from a ticket counter. A stage-k tile of a sequence starts when
+// all stage-(k-1) tiles of that sequence are done (a completion counter per
+// sequence and stage). Dependencies always hold smaller tickets, and a
+// workgroup only waits after taking its ticket, so the smallest unfinished
+// ticket can always proceed: there is no deadlock for any grid size, and
+// every workgroup leaves once the counter passes the last item.
+// ---------------------------------------------------------------------------
+template <int CT>
+struct PersistLds {
+  using X = typename CTraits<CT>::X;
+  static constexpr size_t m1(size_t a, size_t b) { return a > b ? a : b; }
+  static constexpr size_t S = m1(m1(StageCfg<32, CT>::LDS, StageCfg<64, CT>::LDS),
+                                 m1(StageCfg<128, CT>::LDS, StageCfg<256, CT>::LDS));
+  static constexpr size_t Pj = m1(m1(ProjCfg<32, X>::LDS, ProjCfg<64, X>::LDS),
+                                  m1(ProjCfg<128, X>::LDS, ProjCfg<256, X>::LDS));
+  static constexpr size_t LDS = m1(S, Pj);
+};
+
+template <int CT>
+__global__ __launch_bounds__(256, 1) void k_persistent(PersistParams pp) {
+  using X = typename CTraits<CT>::X;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[PersistLds<CT>::LDS];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(pp.counters, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= pp.n_items) break;
+    const PItem w = pp.items[it];
+    if (w.k >= 0) {
+      if (threadIdx.x == 0) {
+        const int* c = pp.counters + pp.cnt_off[w.seq] + w.k;  // level k-1
+        const int target = pp.ntiles[w.seq];
+        while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target)
+          __builtin_amdgcn_s_sleep(1);
+      }
+      __syncthreads();
+    }
+    StageParams prm = pp.base;
+    const Tile t{w.seq, w.row0};
+    if (w.k < 0) {
+      prm.xout = pp.x0;
+      switch (w.mp) {
+        case 32: project_tile<32, X>(prm, t, stage_bm(32, CT), smem); break;
+        case 64: project_tile<64, X>(prm, t, stage_bm(64, CT), smem); break;
+        case 128: project_tile<128, X>(prm, t, stage_bm(128, CT), smem); break;
+        default: project_tile<256, X>(prm, t, stage_bm(256, CT), smem); break;
+      }
+    } else {
+      prm.k = w.k;
+      prm.xin = (w.k & 1) ? pp.x1 : pp.x0;
+      prm.xout = (w.k & 1) ? pp.x0 : pp.x1;
+      switch (w.mp) {
+        case 32: stage_tile<32, CT>(prm, t, smem); break;
+        case 64: stage_tile<64, CT>(prm, t, smem); break;
+        case 128: stage_tile<128, CT>(prm, t, smem); break;
+        default: stage_tile<256, CT>(prm, t, smem); break;
+      }
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(pp.counters + pp.cnt_off[w.seq] + w.k + 1, 1);
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t b = (n + 255) / 256;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)(b < 1024 ? b : 1024)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
-hipError_t launch_project(int mp, int state_f64, const StageParams& prm, hipStream_t s) {
-  switch (mp) {
-    case 32: return state_f64 ? launch_proj<32, double>(prm, s) : launch_proj<32, float>(prm, s);
-    case 64: return state_f64 ? launch_proj<64, double>(prm, s) : launch_proj<64, float>(prm, s);
-    case 128: return state_f64 ? launch_proj<128, double>(prm, s) : launch_proj<128, float>(prm, s);
-    case 256: return state_f64 ? launch_proj<256, double>(prm, s) : launch_proj<256, float>(prm, s);
+hipError_t launch_persistent(int ct, const PersistParams& pp, int grid, hipStream_t s) {
+  if (pp.n_items <= 0 || grid <= 0) return hipSuccess;
+  switch (ct) {
+    case DT_BF16: hipLaunchKernelGGL(k_persistent<DT_BF16>, dim3(grid), dim3(256), 0, s, pp); break;
+    case DT_F32: hipLaunchKernelGGL(k_persistent<DT_F32>, dim3(grid), dim3(256), 0, s, pp); break;
+    case DT_F64: hipLaunchKernelGGL(k_persistent<DT_F64>, dim3(grid), dim3(256), 0, s, pp); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int ct) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (ct) {
+    case DT_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<DT_BF16>, 256, 0); break;
+    case DT_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<DT_F32>, 256, 0); break;
+    case DT_F64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<DT_F64>, 256, 0); break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+template <int MP, typename X>
+static hipError_t launch_proj(const StageParams& prm, int rows, hipStream_t s) {
+  if (prm.n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_project<MP, X>), dim3(prm.n_tiles), dim3(256), 0, s, prm, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int mp, int state_f64, int rows, const StageParams& prm,
+                          hipStream_t s) {
+  if (rows <= 0) return hipErrorInvalidValue;
+  switch (mp) {
+    case 32: return state_f64 ? launch_proj<32, double>(prm, rows, s) : launch_proj<32, float>(prm, rows, s);
+    case 64: return state_f64 ? launch_proj<64, double>(prm, rows, s) : launch_proj<64, float>(prm, rows, s);
+    case 128: return state_f64 ? launch_proj<128, double>(prm, rows, s) : launch_proj<128, float>(prm, rows, s);
+    case 256: return state_f64 ? launch_proj<256, double>(prm, rows, s) : launch_proj<256, float>(prm, rows, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int MP, int CT, int BM>
+static hipError_t launch_one(const StageParams& prm, hipStream_t s) {
+  if (prm.n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_stage<MP, CT, BM>), dim3(prm.n_tiles), dim3(256), 0, s, prm);
+  return hipGetLastError();
 }
 
 template <int MP, int CT>
-static hipError_t launch_one(const StageParams& prm, hipStream_t s) {
-  if (prm.n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_stage<MP, CT>), dim3(prm.n_tiles), dim3(256), 0, s, prm);
-  return hipGetLastError();
+static hipError_t launch_bm(int bm, const StageParams& prm, hipStream_t s) {
+  constexpr int D = stage_bm(MP, CT);
+  if (bm == D) return launch_one<MP, CT, D>(prm, s);
+  if (bm == D / 2) return launch_one<MP, CT, D / 2>(prm, s);
+  return hipErrorInvalidValue;
 }
 
 template <int CT>
-static hipError_t launch_ct(int mp, const StageParams& prm, hipStream_t s) {
+static hipError_t launch_ct(int mp, int bm, const StageParams& prm, hipStream_t s) {
   switch (mp) {
-    case 32: return launch_one<32, CT>(prm, s);
-    case 64: return launch_one<64, CT>(prm, s);
-    case 128: return launch_one<128, CT>(prm, s);
-    case 256: return launch_one<256, CT>(prm, s);
+    case 32: return launch_bm<32, CT>(bm, prm, s);
+    case 64: return launch_bm<64, CT>(bm, prm, s);
+    case 128: return launch_bm<128, CT>(bm, prm, s);
+    case 256: return launch_bm<256, CT>(bm, prm, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_stage(int mp, int ct, const StageParams& prm, hipStream_t s) {
+hipError_t launch_stage(int mp, int ct, int bm, const StageParams& prm, hipStream_t s) {
   switch (ct) {
-    case DT_BF16: return launch_ct<DT_BF16>(mp, prm, s);
-    case DT_F32: return launch_ct<DT_F32>(mp, prm, s);
-    case DT_F64: return launch_ct<DT_F64>(mp, prm, s);
+    case DT_BF16: return launch_ct<DT_BF16>(mp, bm, prm, s);
+    case DT_F32: return launch_ct<DT_F32>(mp, bm, prm, s);
+    case DT_F64: return launch_ct<DT_F64>(mp, bm, prm, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -79,6 +79,25 @@ struct StageParams {
   int32_t n_tiles;
 };
 
+// ---- persistent ragged launch ----
+// One row tile of one stage (k >= 0), or of the input projection (k == -1),
+// of one sequence. Items are ordered by stage level.
+struct PItem {
+  int32_t seq, k, row0, mp;
+};
+
+struct PersistParams {
+  StageParams base;        // seqs, ops, P, small, src, dst, src_dtype, flags
+  const PItem* items;
+  int32_t n_items;
+  int32_t reserved;
+  int32_t* counters;       // [0]: ticket counter; then (last+2) completion counters per sequence
+  const int32_t* cnt_off;  // per sequence: index of its first completion counter
+  const int32_t* ntiles;   // per sequence: number of row tiles
+  void* x0;
+  void* x1;
+};
+
 // ---- backward ----
 // A chunk of rows of one sequence for the outer-product reductions.
 struct RedChunk {
@@ -142,7 +161,7 @@ struct GemmJob {
 // compute type (4 waves, 16x16 MFMA blocks).
 __host__ __device__ constexpr int stage_bm(int mp, int ct) {
   return ct == DT_F64 ? (mp == 256 ? 32 : mp == 128 ? 64 : mp == 64 ? 64 : 128)
-                      : (mp == 256 ? 64 : mp == 128 ? 128 : mp == 64 ? 128 : 256);
+                      : (mp == 256 ? 64 : mp == 128 ? 64 : mp == 64 ? 128 : 256);
 }
 
 // Device pointers of one operator's source parameters (FP64, row-major,
@@ -155,10 +174,12 @@ struct OpSrc {
 };
 
 // ---- launchers (defined in the .hip files) ----
-hipError_t launch_stage(int mp, int ct, const StageParams& prm, hipStream_t s);
+// bm: rows per tile of the launch's tile table (stage_bm or half of it).
+hipError_t launch_stage(int mp, int ct, int bm, const StageParams& prm, hipStream_t s);
 // Input projection into the state buffer xout: Bbar u (forward) or C^T dy
-// (adjoint) for every tile of the launch.
-hipError_t launch_project(int mp, int state_f64, const StageParams& prm, hipStream_t s);
+// (adjoint) for every tile of the launch (rows: rows per tile).
+hipError_t launch_project(int mp, int state_f64, int rows, const StageParams& prm,
+                          hipStream_t s);
 
 hipError_t launch_gemm_f64(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n,
                            hipStream_t s);
@@ -183,6 +204,13 @@ hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double*
 hipError_t launch_pack(const OpDev* ops, int n_ops, const OpSrc* src, const double* pw,
                        const double* bbar, void* pc, int ct, int want_t, void* small,
                        int state_is_f64, int max_mp, int max_N, hipStream_t s);
+
+// Zeroes n int32 counters (a kernel, so that graph capture records no memset).
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+// One persistent launch that runs every item of the plan's forward pass.
+hipError_t launch_persistent(int ct, const PersistParams& pp, int grid, hipStream_t s);
+// Workgroups of the persistent kernel that fit on one compute unit.
+int persistent_blocks_per_cu(int ct);
 
 hipError_t launch_outer(int mp, int state_f64, const RedParams& prm, int tiles_y,
                         hipStream_t s);

@@ -59,7 +59,7 @@ def _desc(**kw):
 def test_workspace_bytes_rejects_bad_descriptors(lib, bad):
     from paper_2411_17729_amd import binding as B
     arr = (B.ssm_seq_desc * 1)(_desc(**bad))
-    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0) == 0
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, None) == 0
     assert lib.ssm_last_error().decode() != ""
 
 
@@ -67,8 +67,8 @@ def test_workspace_bytes_grows_with_batch(lib):
     from paper_2411_17729_amd import binding as B
     one = (B.ssm_seq_desc * 1)(_desc())
     two = (B.ssm_seq_desc * 2)(_desc(), _desc(u_offset=4096, y_offset=4096))
-    n1 = lib.ssm_cascade_workspace_bytes(one, 1, 0, 1, 0, 0)
-    n2 = lib.ssm_cascade_workspace_bytes(two, 2, 0, 1, 0, 0)
+    n1 = lib.ssm_cascade_workspace_bytes(one, 1, 0, 1, 0, 0, None)
+    n2 = lib.ssm_cascade_workspace_bytes(two, 2, 0, 1, 0, 0, None)
     assert 0 < n1 < n2
     # the second sequence shares the operator: only the state buffers grow
     assert n2 - n1 <= 2 * 4096 * 64 * 4 + 4096
@@ -80,21 +80,21 @@ def test_prepare_rejects_on_host(lib):
     params = (B.ssm_params * 1)(B.ssm_params(A=None, B=None, C=None, D=None, m=64, p=1, q=1))
     plan = C.c_void_p()
     # NULL workspace
-    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, None, 0, None, C.byref(plan))
+    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, None, None, 0, None, C.byref(plan))
     assert st == B.SSM_E_INVALID and plan.value is None
     # NULL parameter matrices (non-NULL fake workspace is never dereferenced)
-    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, C.c_void_p(256), 1 << 40, None,
-                                 C.byref(plan))
+    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, None, C.c_void_p(256), 1 << 40,
+                                 None, C.byref(plan))
     assert st == B.SSM_E_INVALID
     # short workspace
     params[0] = B.ssm_params(A=256, B=256, C=256, D=256, m=64, p=1, q=1)
-    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, C.c_void_p(256), 16, None,
+    st = lib.ssm_cascade_prepare(arr, 1, params, 1, 0, 1, 0, 0, None, C.c_void_p(256), 16, None,
                                  C.byref(plan))
     assert st == B.SSM_E_WORKSPACE
     # param_set beyond n_sets
     arr2 = (B.ssm_seq_desc * 1)(_desc(param_set=1))
-    st = lib.ssm_cascade_prepare(arr2, 1, params, 1, 0, 1, 0, 0, C.c_void_p(256), 1 << 40, None,
-                                 C.byref(plan))
+    st = lib.ssm_cascade_prepare(arr2, 1, params, 1, 0, 1, 0, 0, None, C.c_void_p(256), 1 << 40,
+                                 None, C.byref(plan))
     assert st == B.SSM_E_INVALID
 
 
@@ -105,3 +105,23 @@ def test_null_plan_calls(lib):
     assert lib.ssm_cascade_destroy(None) == B.SSM_OK
     assert lib.ssm_cascade_param_grad_numel(None) == 0
     assert "INVALID" in lib.ssm_status_string(B.SSM_E_INVALID).decode()
+
+
+def test_tuning_is_validated(lib):
+    from paper_2411_17729_amd import binding as B
+    arr = (B.ssm_seq_desc * 1)(_desc())
+    for bad in (B.make_tuning(launch=7), B.make_tuning(tile_rows=(0, 100, 0, 0))):
+        assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(bad)) == 0
+    t = B.make_tuning(tile_rows=(0, 64, 0, 0))  # half of the default 128 for m <= 64
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
+    t = B.make_tuning()
+    t.reserved[3] = 1
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
+
+
+def test_graph_calls_reject_on_host(lib):
+    from paper_2411_17729_amd import binding as B
+    g = C.c_void_p()
+    assert lib.ssm_cascade_graph_apply(None, None, 1, 0, None, 0, None, C.byref(g)) == B.SSM_E_NOT_PREPARED
+    assert lib.ssm_cascade_graph_launch(None, None) == B.SSM_E_INVALID
+    assert lib.ssm_cascade_graph_destroy(None) == B.SSM_OK

@@ -1,0 +1,172 @@
+"""Ragged batches: the single persistent launch against per-stage launches and
+the FP64 oracle, HIP-graph replays of apply and backward, tile-height
+variants, and the autotuner."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2411_17729_amd import workloads as W
+from tests.helpers import rel_err, state_part
+
+pytestmark = pytest.mark.gpu
+
+
+def _ragged_small(seed=3):
+    rng = np.random.default_rng(seed)
+    sets, seqs = [], []
+    spec = [(20, 2, 2, 700, 9), (64, 4, 4, 1500, 10), (100, 1, 3, 333, 8), (128, 4, 4, 2049, 11),
+            (256, 4, 4, 1200, 10), (200, 2, 2, 64, 5), (7, 1, 1, 1, 0), (50, 3, 2, 2, 1)]
+    for i, (m, p, q, L, N) in enumerate(spec):
+        A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, p)) / math.sqrt(m),
+                               rng.standard_normal((q, m)) / math.sqrt(m),
+                               rng.standard_normal((q, p)) / math.sqrt(m)))
+        seqs.append(W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, N, rng.standard_normal((L, p))))
+    return W.Workload("ragged_small", sets, seqs)
+
+
+def _oracle(wl, idx=None):
+    out = {}
+    for i, s in enumerate(wl.seqs):
+        if idx is not None and i not in idx:
+            continue
+        ps = wl.sets[s.param_set]
+        Abar, Bbar = O.trapezoid(ps.A, ps.B, s.delta)
+        u = s.u.astype(np.float32).astype(np.float64)
+        if (1 << (s.N + 1)) >= s.L:
+            out[i], _ = O.recursion(Abar, Bbar, ps.C, ps.D, u)
+        else:
+            out[i] = O.truncated_sum(Abar, Bbar, ps.C, ps.D, u, s.N)
+    return out
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_persistent_matches_per_stage_and_oracle(compute):
+    from paper_2411_17729_amd import cascade as CC
+    wl = _ragged_small()
+    u = CC.pack_u(wl, dtype=torch.float32)
+    ys = {}
+    for mode in ("persistent", "per_stage"):
+        plan = CC.plan_for_workload(wl, compute=compute, launch=mode)
+        info = plan.info()
+        assert info["launch"] == (2 if mode == "persistent" else 1)
+        ys[mode] = plan.apply(u).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(ys["persistent"], ys["per_stage"])
+    got = CC.unpack_y(wl, ys["persistent"])
+    ref = _oracle(wl)
+    tol = 1e-5 if compute == "f32" else 2e-2
+    uq = [s.u.astype(np.float32).astype(np.float64) for s in wl.seqs]
+    st_g = state_part(wl, got, uq)
+    st_r = state_part(wl, [ref[i] for i in range(len(wl.seqs))], uq)
+    for i in range(len(wl.seqs)):
+        e = rel_err(st_g[i], st_r[i])
+        assert e <= tol, (i, e)
+
+
+def test_auto_launch_picks_persistent_for_ragged():
+    from paper_2411_17729_amd import cascade as CC
+    plan = CC.plan_for_workload(_ragged_small(), compute="f32")
+    assert plan.info()["launch"] == 2
+    plan = CC.plan_for_workload(W.batched(seed=1, batch=2, m=64, L=512, N=8, p=2, q=2), compute="f32")
+    assert plan.info()["launch"] == 1
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_tile_row_variants_are_bitwise_equal(compute):
+    from paper_2411_17729_amd import cascade as CC
+    wl = _ragged_small(5)
+    u = CC.pack_u(wl, dtype=torch.float32)
+    a = CC.plan_for_workload(wl, compute=compute, launch="per_stage").apply(u).clone()
+    half = tuple({32: 128, 64: 64, 128: 32, 256: 32}[mp] for mp in (32, 64, 128, 256))
+    b = CC.plan_for_workload(wl, compute=compute, launch="per_stage", tile_rows=half).apply(u)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_ragged_256_sequences_bf16_sampled():
+    # 256 sequences, L log-uniform in [512, 65536], m in {64, 128, 256}: one
+    # persistent launch, checked in full on a sample of sequences
+    from paper_2411_17729_amd import cascade as CC
+    wl = W.ragged(seed=0, with_dy=False)
+    plan = CC.plan_for_workload(wl, compute="bf16")
+    assert plan.info()["launch"] == 2
+    u = CC.pack_u(wl, dtype=torch.float32)
+    y = CC.unpack_y(wl, plan.apply(u))
+    Ls = [s.L for s in wl.seqs]
+    sample = sorted({int(np.argmax(Ls)), int(np.argmin(Ls)), 0, 1, 77, 200})
+    ref = _oracle(wl, set(sample))
+    for i in sample:
+        s = wl.seqs[i]
+        uq = s.u.astype(np.float32).astype(np.float64)
+        D = wl.sets[s.param_set].D
+        e = rel_err(y[i] - uq @ D.T, ref[i] - uq @ D.T)
+        print("seq", i, "L", s.L, "m", wl.sets[s.param_set].m, "rel_state", f"{e:.3e}", flush=True)
+        assert e <= 2e-2, (i, e)
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_stage"])
+def test_graph_replay_apply(mode):
+    from paper_2411_17729_amd import cascade as CC
+    wl = _ragged_small(7)
+    plan = CC.plan_for_workload(wl, compute="f32", launch=mode)
+    stream = torch.cuda.Stream()
+    u = CC.pack_u(wl, dtype=torch.float32)
+    y = torch.empty(plan.layout.y_numel, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    g = plan.graph_apply(u, y, stream)
+    try:
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                u.mul_(1.0 + 0.25 * rep)  # eager work between replays
+            CC.CascadePlan.graph_launch(g, stream)
+            stream.synchronize()
+            ref = plan.apply(u)
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref), rep
+    finally:
+        CC.CascadePlan.graph_destroy(g)
+
+
+def test_graph_replay_backward():
+    from paper_2411_17729_amd import cascade as CC
+    wl = W.backward(seed=8, batch=2, m=64, L=600, N=9, p=2, q=2, delta=1e-2)
+    plan = CC.plan_for_workload(wl, compute="f32", with_backward=True)
+    stream = torch.cuda.Stream()
+    u = CC.pack_u(wl, dtype=torch.float32)
+    dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in wl.dy]), device="cuda").float()
+    du = torch.empty_like(u)
+    from paper_2411_17729_amd import binding as B
+    g = torch.empty(B.ssm_cascade_param_grad_numel(plan.plan), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    gr = plan.graph_backward(u, dy, du, g, stream)
+    try:
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                dy.mul_(-0.5 - rep)
+            CC.CascadePlan.graph_launch(gr, stream)
+            stream.synchronize()
+            du_ref, gp_ref = plan.backward(u, dy)
+            torch.cuda.synchronize()
+            assert torch.equal(du, du_ref), rep
+            flat = torch.cat([t.reshape(-1) for parts in gp_ref for t in parts])
+            assert torch.equal(g, flat), rep
+    finally:
+        CC.CascadePlan.graph_destroy(gr)
+
+
+def test_autotuner_picks_a_measured_candidate(tmp_path):
+    from paper_2411_17729_amd import tune
+    wl = _ragged_small(11)
+    best = tune.best_tuning(wl, compute="bf16", path=str(tmp_path / "cache.json"))
+    cache = tune.load_cache(str(tmp_path / "cache.json"))
+    (key, rec), = cache.items()
+    assert min(c["ms"] for c in rec["candidates"]) == rec["ms"]
+    assert best["launch"] == rec["launch"]
+    # a second call is served from the cache
+    again = tune.best_tuning(wl, compute="bf16", path=str(tmp_path / "cache.json"))
+    assert again == best
