@@ -15,6 +15,7 @@ from .ssm_oracle import (  # noqa: F401
     powers,
     impulse_response,
     truncated_sum,
+    truncated_sum_fft,
     cascade,
     transfer,
     transfer_truncated,

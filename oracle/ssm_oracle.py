@@ -44,6 +44,7 @@ __all__ = [
     "powers",
     "impulse_response",
     "truncated_sum",
+    "truncated_sum_fft",
     "cascade",
     "transfer",
     "transfer_truncated",
@@ -193,6 +194,23 @@ def truncated_sum(Abar, Bbar, C, D, u, N):
     y = u @ _f64(D).T
     for j in range(Tu):
         y[j:] += u[: L - j] @ h[j].T
+    return y
+
+
+def truncated_sum_fft(Abar, Bbar, C, D, u, N):
+    """The same sum as ``truncated_sum``, each (output, input) channel pair a
+    causal convolution of u with the taps h_j = C Abar^j Bbar (j < T),
+    evaluated with an FFT (scipy.signal.fftconvolve) for long sequences."""
+    from scipy.signal import fftconvolve
+
+    u = _as_matrix_u(u)
+    L = u.shape[0]
+    T = 1 << (N + 1)
+    h = impulse_response(Abar, Bbar, C, min(T, L))
+    y = u @ _f64(D).T
+    for qi in range(h.shape[1]):
+        for pi in range(h.shape[2]):
+            y[:, qi] += fftconvolve(u[:, pi], h[:, qi, pi])[:L]
     return y
 
 

@@ -321,3 +321,13 @@ def test_effective_stages():
     assert O.effective_stages(5, 3) == 2
     assert O.effective_stages(11, 4096) == 12
     assert O.effective_stages(3, 4096) == 4
+
+
+def test_fft_truncated_sum_matches_direct_sum():
+    rng = np.random.default_rng(31)
+    Abar, Bbar, C, D = _rand_system(rng, 4, 2, 3, gamma=1.02)
+    u = rng.standard_normal((500, 2))
+    for N in (2, 5, 9):
+        a = O.truncated_sum(Abar, Bbar, C, D, u, N)
+        b = O.truncated_sum_fft(Abar, Bbar, C, D, u, N)
+        assert np.max(np.abs(a - b)) < 1e-10 * max(1.0, np.max(np.abs(a)))
