@@ -87,10 +87,18 @@ typedef enum {
  * size 32 << i (i = 0..3): 0 keeps the default, otherwise it must be the
  * default or half of it (the persistent launch always uses the defaults).
  * Defaults: 256, 128, 64, 64 rows for F32/BF16 and 128, 64, 64, 32 for F64. */
+typedef enum {
+  SSM_STAGE_AUTO = 0,     /* resident where supported, tiled otherwise */
+  SSM_STAGE_TILED = 1,    /* power streamed through LDS in K chunks per row tile */
+  SSM_STAGE_RESIDENT = 2  /* power resident in LDS, waves stream 16-row blocks
+                             (BF16/FP32 operands and padded m of 64..256 only) */
+} ssm_stage_kernel;
+
 typedef struct {
   int32_t launch;        /* ssm_launch */
   int32_t tile_rows[4];
-  int32_t reserved[11];  /* must be 0 */
+  int32_t stage_kernel;  /* ssm_stage_kernel, per-stage launches only */
+  int32_t reserved[10];  /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -134,6 +142,7 @@ typedef struct {
                                 and write the row; the last stage writes y instead */
   int64_t stage_launches;    /* stage-kernel launches per apply (per-stage mode) */
   int32_t launch;            /* ssm_launch the plan uses (never AUTO) */
+  int32_t stage_kernel;      /* ssm_stage_kernel the plan uses (never AUTO) */
   int32_t tile_rows[4];      /* rows per stage tile per padded state size */
   int32_t persistent_grid;   /* workgroups of the persistent launch */
   int64_t persistent_items;  /* work items of the persistent launch */

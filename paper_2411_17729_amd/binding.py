@@ -24,6 +24,7 @@ SSM_OK, SSM_E_INVALID, SSM_E_UNSUPPORTED, SSM_E_WORKSPACE, SSM_E_HIP, SSM_E_NOT_
 SSM_F64, SSM_F32, SSM_BF16 = 0, 1, 2
 SSM_DISC_TRAPEZOID, SSM_DISC_GIVEN = 0, 1
 SSM_LAUNCH_AUTO, SSM_LAUNCH_PER_STAGE, SSM_LAUNCH_PERSISTENT = 0, 1, 2
+SSM_STAGE_AUTO, SSM_STAGE_TILED, SSM_STAGE_RESIDENT = 0, 1, 2
 
 # kernel classes of ssm_cascade_timing_read
 TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION = 0, 1, 2, 3
@@ -52,7 +53,8 @@ class ssm_params(C.Structure):
 
 
 class ssm_tuning(C.Structure):
-    _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("reserved", C.c_int32 * 11)]
+    _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
+                ("reserved", C.c_int32 * 10)]
 
 
 class ssm_plan_info(C.Structure):
@@ -60,14 +62,15 @@ class ssm_plan_info(C.Structure):
         ("n_seq", C.c_int32), ("n_ops", C.c_int32), ("compute", C.c_int32), ("max_stage", C.c_int32),
         ("total_steps", C.c_int64), ("stage_flops", C.c_double), ("io_flops", C.c_double),
         ("stage_bytes", C.c_double), ("stage_launches", C.c_int64), ("launch", C.c_int32),
-        ("tile_rows", C.c_int32 * 4), ("persistent_grid", C.c_int32),
+        ("stage_kernel", C.c_int32), ("tile_rows", C.c_int32 * 4), ("persistent_grid", C.c_int32),
         ("persistent_items", C.c_int64),
     ]
 
 
-def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0)):
+def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO):
     t = ssm_tuning()
     t.launch = int(launch)
+    t.stage_kernel = int(stage_kernel)
     for i, r in enumerate(tile_rows):
         t.tile_rows[i] = int(r)
     return t

@@ -109,7 +109,14 @@ struct ssm_plan_s {
   std::vector<hipEvent_t> event_pool;  // events reused across timing reads
   // tuning
   int launch = SSM_LAUNCH_PER_STAGE;
+  int stage_kernel = SSM_STAGE_TILED;
   int class_bm[4] = {0, 0, 0, 0};
+  // resident-power stage kernel: row ranges per class, longest-running first
+  std::vector<ResRange> ranges;
+  int class_range_start[4] = {0, 0, 0, 0}, class_range_count[4] = {0, 0, 0, 0};
+  std::vector<int> class_range_active[4];
+  std::vector<int> class_final[4];  // sequences whose last stage is k
+  size_t m_ranges = 0;
   // persistent launch
   std::vector<PItem> items;
   std::vector<int32_t> cnt_off, ntiles;
@@ -178,8 +185,14 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (st != SSM_OK) return st;
   ssm_tuning tn{};
   if (tuning) tn = *tuning;
-  for (int i = 0; i < 11; ++i)
+  for (int i = 0; i < 10; ++i)
     if (tn.reserved[i] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.stage_kernel < SSM_STAGE_AUTO || tn.stage_kernel > SSM_STAGE_RESIDENT)
+    return fail(SSM_E_INVALID, "unknown stage kernel %d", tn.stage_kernel);
+  if (tn.stage_kernel == SSM_STAGE_RESIDENT && compute == SSM_F64)
+    return fail(SSM_E_UNSUPPORTED, "the resident stage kernel takes BF16 or FP32 operands");
+  P.stage_kernel = tn.stage_kernel == SSM_STAGE_TILED || compute == SSM_F64 ? SSM_STAGE_TILED
+                                                                          : SSM_STAGE_RESIDENT;
   if (tn.launch < SSM_LAUNCH_AUTO || tn.launch > SSM_LAUNCH_PERSISTENT)
     return fail(SSM_E_INVALID, "unknown launch mode %d", tn.launch);
   for (int c = 0; c < 4; ++c) {
@@ -285,6 +298,36 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
         if (P.seqs[P.tiles[ti].seq].last >= kk) ++cnt;
       P.class_active[c][kk] = cnt;
     }
+  }
+
+  // row ranges of the resident-power kernel (about 512 per class)
+  P.ranges.clear();
+  for (int c = 0; c < 4; ++c) {
+    std::vector<int> ids;
+    int64_t rows = 0;
+    for (int i = 0; i < n_seq; ++i)
+      if (P.ops[P.seqs[i].op].mp == kClassMp[c]) {
+        ids.push_back(i);
+        rows += P.seqs[i].L;
+      }
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int a, int b) { return P.seqs[a].last > P.seqs[b].last; });
+    const int64_t R = std::max<int64_t>(128, ((rows + 511) / 512 + 127) / 128 * 128);
+    P.class_range_start[c] = (int)P.ranges.size();
+    for (int i : ids)
+      for (int64_t r0 = 0; r0 < P.seqs[i].L; r0 += R)
+        P.ranges.push_back(ResRange{i, (int32_t)r0, (int32_t)std::min<int64_t>(R, P.seqs[i].L - r0), 0});
+    P.class_range_count[c] = (int)P.ranges.size() - P.class_range_start[c];
+    const int ml = P.class_max_last[c];
+    P.class_range_active[c].assign(ml + 1, 0);
+    P.class_final[c].assign(ml + 1, 0);
+    for (int kk = 0; kk <= ml; ++kk) {
+      int cnt = 0;
+      for (int r = P.class_range_start[c]; r < (int)P.ranges.size(); ++r)
+        if (P.seqs[P.ranges[r].seq].last >= kk) ++cnt;
+      P.class_range_active[c][kk] = cnt;
+    }
+    for (int i : ids) P.class_final[c][P.seqs[i].last] += 1;
   }
 
   // launch mode: persistent for ragged batches unless asked otherwise
@@ -450,6 +493,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
   P.sum_x = xoff;
+  P.m_ranges = off;
+  off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.ranges.size()));
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
     P.m_items = off;
     off = align_up(off + sizeof(PItem) * std::max<size_t>(1, P.items.size()));
@@ -752,6 +797,23 @@ ssm_status check_io(const ssm_plan_s& P, const void* u, ssm_dtype u_dtype, size_
   return SSM_OK;
 }
 
+// One per-stage launch of class c at stage prm.k: the resident-power kernel
+// where the plan uses it and it can apply this stage, the tiled one otherwise.
+hipError_t launch_stage_any(const ssm_plan_s& P, int c, StageParams prm, hipStream_t stream) {
+  const int mp = kClassMp[c];
+  const int k = prm.k;
+  const bool final_here = (prm.flags & SF_EPILOGUE) &&
+                          (prm.adjoint ? k == 0 : (k < (int)P.class_final[c].size() &&
+                                                   P.class_final[c][k] > 0));
+  if (P.stage_kernel == SSM_STAGE_RESIDENT && res_supported(mp, P.compute) &&
+      !(final_here && res_splits_rows(mp, P.compute))) {
+    const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
+                         P.class_range_start[c];
+    return launch_stage_res(mp, P.compute, prm, rg, P.class_range_active[c][k], stream);
+  }
+  return launch_stage(mp, P.compute, P.class_bm[c], prm, stream);
+}
+
 StageParams base_params(const ssm_plan_s& P, int c) {
   StageParams prm{};
   prm.tiles = reinterpret_cast<const Tile*>(P.ws + P.r_meta.off + P.m_tiles) +
@@ -922,6 +984,9 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                 sizeof(Tile) * P->tiles.size());
   if (!J.empty())
     std::memcpy(P->meta_host.data() + P->m_jobs, J.data(), sizeof(GemmJob) * J.size());
+  if (!P->ranges.empty())
+    std::memcpy(P->meta_host.data() + P->m_ranges, P->ranges.data(),
+                sizeof(ResRange) * P->ranges.size());
   if (P->launch == SSM_LAUNCH_PERSISTENT) {
     unsigned char* mh = P->meta_host.data();
     if (!P->items.empty())
@@ -1056,7 +1121,7 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       prm.xout = P.ws + ((kk & 1) ? P.r_x0.off : P.r_x1.off);
       prm.n_tiles = P.class_active[c][kk];
       TimedLaunch tl(P, stream, 0);
-      e = launch_stage(kClassMp[c], P.compute, P.class_bm[c], prm, stream);
+      e = launch_stage_any(P, c, prm, stream);
       if (e != hipSuccess) return hip_fail(e, "stage launch");
       tl.done();
     }
@@ -1156,7 +1221,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       prm.xout = loc(k + 1);
       prm.n_tiles = P.class_active[cl][k];
       TimedLaunch tl(P, stream, 0);
-      e = launch_stage(mp, P.compute, P.class_bm[cl], prm, stream);
+      e = launch_stage_any(P, cl, prm, stream);
       if (e != hipSuccess) return hip_fail(e, "stage launch");
       tl.done();
     }
@@ -1222,7 +1287,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
         prm.xout = loc(k + 1);
         prm.n_tiles = P.class_active[cl][k];
         TimedLaunch tl(P, stream, 0);
-        e = launch_stage(mp, P.compute, P.class_bm[cl], prm, stream);
+        e = launch_stage_any(P, cl, prm, stream);
         if (e != hipSuccess) return hip_fail(e, "recompute stage launch");
         tl.done();
       }
@@ -1249,7 +1314,7 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
         prm.xout = wout;
         prm.n_tiles = P.class_active[cl][k];
         TimedLaunch tl(P, stream, 1);
-        e = launch_stage(mp, P.compute, P.class_bm[cl], prm, stream);
+        e = launch_stage_any(P, cl, prm, stream);
         if (e != hipSuccess) return hip_fail(e, "adjoint stage launch");
         tl.done();
       }
@@ -1328,6 +1393,7 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->stage_bytes = plan->stage_bytes;
   info->stage_launches = plan->stage_launches;
   info->launch = plan->launch;
+  info->stage_kernel = plan->stage_kernel;
   for (int c = 0; c < 4; ++c) info->tile_rows[c] = plan->class_bm[c];
   info->persistent_grid = plan->persistent_grid;
   info->persistent_items = (int64_t)plan->items.size();

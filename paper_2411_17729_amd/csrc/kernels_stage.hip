@@ -15,106 +15,9 @@
 // (y_l = C x_l + D u_l forward, du_l = Bbar^T g_l + D^T dy_l adjoint).
 #include <type_traits>
 
-#include "ssm_internal.h"
+#include "stage_common.h"
 
 namespace ssmc {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// FP32 -> bfloat16, round to nearest even (NaN stays NaN).
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
-  return __uint_as_float(((uint32_t)b) << 16);
-}
-
-template <int CT>
-struct CTraits;
-template <>
-struct CTraits<DT_BF16> {
-  using X = float;      // state / accumulator element
-  using Op = uint16_t;  // MFMA operand element (bf16 bits)
-  using Acc = f32x4;
-  static constexpr int KI = 32;  // K of one 16x16 MFMA
-  static constexpr int KPL = 8;  // K elements per lane
-  static constexpr int PAD = 8;  // LDS row padding (elements)
-  // accumulator register v of lane group g holds row 4g + v of the 16x16 block
-  static __device__ __forceinline__ int acc_row(int g, int v) { return 4 * g + v; }
-};
-template <>
-struct CTraits<DT_F32> {
-  using X = float;
-  using Op = float;
-  using Acc = f32x4;
-  static constexpr int KI = 4;
-  static constexpr int KPL = 1;
-  static constexpr int PAD = 4;  // keeps LDS rows 16-byte aligned
-  static __device__ __forceinline__ int acc_row(int g, int v) { return 4 * g + v; }
-};
-template <>
-struct CTraits<DT_F64> {
-  using X = double;
-  using Op = double;
-  using Acc = f64x4;
-  static constexpr int KI = 4;
-  static constexpr int KPL = 1;
-  static constexpr int PAD = 2;  // keeps LDS rows 16-byte aligned
-  // the FP64 16x16x4 MFMA interleaves rows: register v of lane group g is row g + 4v
-  static __device__ __forceinline__ int acc_row(int g, int v) { return g + 4 * v; }
-};
-
-template <typename Op, typename X>
-__device__ __forceinline__ Op to_op(X v);
-template <>
-__device__ __forceinline__ uint16_t to_op<uint16_t, float>(float v) {
-  return f32_to_bf16_bits(v);
-}
-template <>
-__device__ __forceinline__ float to_op<float, float>(float v) {
-  return v;
-}
-template <>
-__device__ __forceinline__ double to_op<double, double>(double v) {
-  return v;
-}
-
-template <typename X>
-__device__ __forceinline__ X load_src(const void* src, int dtype, int64_t i) {
-  if (dtype == DT_F64) return (X)((const double*)src)[i];
-  if (dtype == DT_F32) return (X)((const float*)src)[i];
-  return (X)bf16_bits_to_f32(((const uint16_t*)src)[i]);
-}
-
-// One 16x16 MFMA step for each compute type.
-template <int CT>
-struct Mfma;
-template <>
-struct Mfma<DT_BF16> {
-  static __device__ __forceinline__ f32x4 run(const uint16_t* a, const uint16_t* b, f32x4 c) {
-    bf16x8 av = *reinterpret_cast<const bf16x8*>(a);
-    bf16x8 bv = *reinterpret_cast<const bf16x8*>(b);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-  }
-};
-template <>
-struct Mfma<DT_F32> {
-  static __device__ __forceinline__ f32x4 run(const float* a, const float* b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
-  }
-};
-template <>
-struct Mfma<DT_F64> {
-  static __device__ __forceinline__ f64x4 run(const double* a, const double* b, f64x4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(*a, *b, c, 0, 0, 0);
-  }
-};
 
 template <int MP, int CT, int BM_ = stage_bm(MP, CT)>
 struct StageCfg {

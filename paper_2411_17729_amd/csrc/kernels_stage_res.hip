@@ -1,0 +1,221 @@
+// Stage kernel with the power resident in LDS (BF16 and FP32 operands).
+//
+// Same stage as k_stage (§3: x_l <- x_l + P_k x_{l-2^k}, or the adjoint
+// g_l <- g_l + P_k^T g_{l+2^k}), organised for HBM streaming: a workgroup
+// loads its rows of P_k once into LDS (128 KB for m = 256 in BF16) and then
+// its eight waves stream independent 16-row blocks of one sequence through
+// the matrix cores, with no further workgroup barriers. Each wave computes
+// the transposed product
+//     OUT^T[n, l] = IN^T[n, l] + sum_j P[n, j] IN[l - s, j]
+// so the P fragments come from LDS (A operand), the shifted rows straight
+// from HBM into registers (B operand), and every lane's accumulators hold 4
+// consecutive state entries of one time row: the unshifted rows are read and
+// the result rows written as 16-byte vectors. When P_k does not fit (FP32,
+// m = 256) the state rows are split between two workgroups (blockIdx.y).
+#include "stage_common.h"
+
+namespace ssmc {
+
+template <int MP, int CT>
+struct ResCfg {
+  using TR = CTraits<CT>;
+  using X = typename TR::X;
+  using Op = typename TR::Op;
+  static constexpr int NS = (size_t)MP * MP * sizeof(Op) > 136 * 1024 ? 2 : 1;
+  static constexpr int NR = MP / NS;  // output state rows per workgroup
+  static constexpr int NB = NR / 16;  // 16-row output blocks per wave
+  static constexpr int PADP = 16 / (int)sizeof(Op);
+  static constexpr int SP = MP + PADP;  // LDS row stride (elements)
+  static constexpr int WAVES = 8;
+  static constexpr size_t LDS = (size_t)NR * SP * sizeof(Op);
+  static constexpr int NV = MP / 16;  // float4 pieces of a shifted row held per lane
+};
+
+template <int MP, int CT>
+__global__ __launch_bounds__(512, 1) void k_stage_res(StageParams prm, const ResRange* ranges) {
+  using C = ResCfg<MP, CT>;
+  using X = float;
+  using Op = typename C::Op;
+  constexpr int NR = C::NR, NB = C::NB, SP = C::SP, NV = C::NV;
+  static_assert(sizeof(typename C::X) == 4, "FP32 state");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_res[];
+  Op* Ps = reinterpret_cast<Op*>(smem_res);
+
+  const ResRange rg = ranges[blockIdx.x];
+  const SeqDev sq = prm.seqs[rg.seq];
+  const OpDev o = prm.ops[sq.op];
+  const int k = prm.k;
+  if (k > sq.last) return;
+  const bool adj = prm.adjoint != 0;
+  const bool first = adj ? k == sq.last : k == 0;
+  const bool final_ = adj ? k == 0 : k == sq.last;
+  const bool epi = (prm.flags & SF_EPILOGUE) && final_ && C::NS == 1;
+  const bool store = !((prm.flags & SF_EPILOGUE) && final_) || (prm.flags & SF_STORE_AT_EPI);
+  const int n0 = blockIdx.y * NR;
+  const int64_t L = sq.L;
+  const int64_t s = (int64_t)1 << k;
+
+  // P_k (or P_k^T) rows n0..n0+NR-1 into LDS
+  {
+    const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP +
+                  (int64_t)n0 * MP;
+    constexpr int VO = 16 / (int)sizeof(Op);
+    for (int e = threadIdx.x; e < NR * (MP / VO); e += 512) {
+      const int r = e / (MP / VO), c = (e % (MP / VO)) * VO;
+      *reinterpret_cast<uint4*>(Ps + r * SP + c) =
+          *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + c);
+    }
+    __syncthreads();
+  }
+
+  const X* xin = reinterpret_cast<const X*>(first && prm.xin_first ? prm.xin_first : prm.xin) +
+                 sq.x_off;
+  X* xout = reinterpret_cast<X*>(prm.xout) + sq.x_off;
+  X* xfin = final_ && prm.xfinal ? reinterpret_cast<X*>(prm.xfinal) + sq.x_off : nullptr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+
+  const int nblk = (rg.nrows + 15) / 16;
+  for (int b = wave; b < nblk; b += C::WAVES) {
+    const int64_t l = (int64_t)rg.row0 + b * 16 + j;  // this lane's time row
+    const bool lv = l < L && l < (int64_t)rg.row0 + rg.nrows;
+    // accumulators <- unshifted row l, entries n0 + 16 nb + 4 g .. +3
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      if (lv)
+        acc[nb] = *reinterpret_cast<const f32x4*>(xin + l * MP + n0 + nb * 16 + 4 * g);
+      else
+        acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // does any row of the block have a partner?
+    const int64_t lb = (int64_t)rg.row0 + b * 16;
+    const bool any = adj ? (lb + s < L) : (lb + 15 >= s);
+    if (any) {
+      const int64_t ls = adj ? l + s : l - s;
+      const bool sv = lv && ls >= 0 && ls < L;
+      const X* srow = xin + ls * MP;
+      f32x4 bv[NV];
+      if constexpr (CT == DT_BF16) {
+        // k = 32 c + 8 g + 4 h + e for MFMA step c
+#pragma unroll
+        for (int c = 0; c < MP / 32; ++c)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            bv[2 * c + h] = sv ? *reinterpret_cast<const f32x4*>(srow + 32 * c + 8 * g + 4 * h)
+                               : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < MP / 32; ++c) {
+          bf16x8 bop;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            bop[e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(bv[2 * c][e]));
+            bop[4 + e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(bv[2 * c + 1][e]));
+          }
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const bf16x8 aop =
+                *reinterpret_cast<const bf16x8*>(Ps + (nb * 16 + j) * SP + 32 * c + 8 * g);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[nb], 0, 0, 0);
+          }
+        }
+      } else {
+        // FP32: MFMA step (a, t) contracts k = 16 a + 4 g + t (t = 0..3)
+#pragma unroll
+        for (int a = 0; a < MP / 16; ++a)
+          bv[a] = sv ? *reinterpret_cast<const f32x4*>(srow + 16 * a + 4 * g)
+                     : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < MP / 16; ++a) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const f32x4 av =
+                *reinterpret_cast<const f32x4*>(Ps + (nb * 16 + j) * SP + 16 * a + 4 * g);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[a][t], acc[nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (lv) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        if (store) *reinterpret_cast<f32x4*>(xout + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
+        if (xfin) *reinterpret_cast<f32x4*>(xfin + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
+      }
+    }
+    if (epi) {
+      // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint):
+      // partial dot over this lane's entries, then over the four lane groups
+      const int w = adj ? sq.p : sq.q;
+      const int r_in = adj ? sq.q : sq.p;
+      const X* cm = reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout);
+      const X* dm = reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat);
+      const int64_t src_off = adj ? sq.y_off : sq.u_off;
+      const int64_t dst_off = adj ? sq.u_off : sq.y_off;
+      X* dst = reinterpret_cast<X*>(prm.dst);
+      for (int qq = 0; qq < w; ++qq) {
+        float part = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const f32x4 cv = *reinterpret_cast<const f32x4*>(cm + (int64_t)qq * MP + nb * 16 + 4 * g);
+          part += cv[0] * acc[nb][0] + cv[1] * acc[nb][1] + cv[2] * acc[nb][2] + cv[3] * acc[nb][3];
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0 && lv) {
+          for (int c = 0; c < r_in; ++c)
+            part += dm[qq * r_in + c] * load_src<X>(prm.src, prm.src_dtype, src_off + l * r_in + c);
+          dst[dst_off + l * w + qq] = part;
+        }
+      }
+    }
+  }
+}
+
+template <int MP, int CT>
+static hipError_t launch_res_t(const StageParams& prm, const ResRange* ranges, int n_ranges,
+                               hipStream_t s) {
+  using C = ResCfg<MP, CT>;
+  if (n_ranges <= 0) return hipSuccess;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_res<MP, CT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_stage_res<MP, CT>), dim3(n_ranges, C::NS), dim3(512), C::LDS, s, prm,
+                     ranges);
+  return hipGetLastError();
+}
+
+bool res_supported(int mp, int ct) {
+  return (ct == DT_BF16 || ct == DT_F32) && (mp == 64 || mp == 128 || mp == 256);
+}
+
+bool res_splits_rows(int mp, int ct) {
+  if (ct == DT_F32 && mp == 256) return ResCfg<256, DT_F32>::NS > 1;
+  return false;
+}
+
+hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
+                            int n_ranges, hipStream_t s) {
+  if (ct == DT_BF16) {
+    switch (mp) {
+      case 64: return launch_res_t<64, DT_BF16>(prm, ranges, n_ranges, s);
+      case 128: return launch_res_t<128, DT_BF16>(prm, ranges, n_ranges, s);
+      case 256: return launch_res_t<256, DT_BF16>(prm, ranges, n_ranges, s);
+    }
+  } else if (ct == DT_F32) {
+    switch (mp) {
+      case 64: return launch_res_t<64, DT_F32>(prm, ranges, n_ranges, s);
+      case 128: return launch_res_t<128, DT_F32>(prm, ranges, n_ranges, s);
+      case 256: return launch_res_t<256, DT_F32>(prm, ranges, n_ranges, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ssmc

@@ -79,6 +79,11 @@ struct StageParams {
   int32_t n_tiles;
 };
 
+// A range of rows of one sequence for the resident-power stage kernel.
+struct ResRange {
+  int32_t seq, row0, nrows, reserved;
+};
+
 // ---- persistent ragged launch ----
 // One row tile of one stage (k >= 0), or of the input projection (k == -1),
 // of one sequence. Items are ordered by stage level.
@@ -204,6 +209,14 @@ hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double*
 hipError_t launch_pack(const OpDev* ops, int n_ops, const OpSrc* src, const double* pw,
                        const double* bbar, void* pc, int ct, int want_t, void* small,
                        int state_is_f64, int max_mp, int max_N, hipStream_t s);
+
+// Resident-power stage kernel (BF16/FP32 operands, padded m of 64..256).
+bool res_supported(int mp, int ct);
+// True when a workgroup holds only part of the state rows (then the stage
+// cannot apply the output projection).
+bool res_splits_rows(int mp, int ct);
+hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
+                            int n_ranges, hipStream_t s);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
