@@ -98,7 +98,15 @@ typedef struct {
   int32_t launch;        /* ssm_launch */
   int32_t tile_rows[4];
   int32_t stage_kernel;  /* ssm_stage_kernel, per-stage launches only */
-  int32_t reserved[10];  /* must be 0 */
+  /* Leading stages folded into the input pass (resident kernel, per-stage
+   * launches): after stages 0..j-1 the state is
+   *   x_l = sum_{i < 2^j} Abar^i Bbar u_{l-i} = K_j [u_l; u_{l-1}; ...; u_{l-2^j+1}]
+   * with K_j = [Bbar, Abar Bbar, ..., Abar^(2^j - 1) Bbar] built by doubling
+   * with the powers, K_{i+1} = [K_i | P_i K_i], i.e. the product of the first j
+   * factors of eq. (2.2) applied to Bbar. 0: automatic (the largest j with
+   * 2^j p <= m, if at least 2), -1: none, j > 0: at most j. */
+  int32_t input_stages;
+  int32_t reserved[9];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -143,6 +151,7 @@ typedef struct {
   int64_t stage_launches;    /* stage-kernel launches per apply (per-stage mode) */
   int32_t launch;            /* ssm_launch the plan uses (never AUTO) */
   int32_t stage_kernel;      /* ssm_stage_kernel the plan uses (never AUTO) */
+  int32_t input_stages;      /* largest number of leading stages folded into the input pass */
   int32_t tile_rows[4];      /* rows per stage tile per padded state size */
   int32_t persistent_grid;   /* workgroups of the persistent launch */
   int64_t persistent_items;  /* work items of the persistent launch */

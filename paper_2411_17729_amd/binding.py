@@ -54,7 +54,7 @@ class ssm_params(C.Structure):
 
 class ssm_tuning(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
-                ("reserved", C.c_int32 * 10)]
+                ("input_stages", C.c_int32), ("reserved", C.c_int32 * 9)]
 
 
 class ssm_plan_info(C.Structure):
@@ -62,15 +62,18 @@ class ssm_plan_info(C.Structure):
         ("n_seq", C.c_int32), ("n_ops", C.c_int32), ("compute", C.c_int32), ("max_stage", C.c_int32),
         ("total_steps", C.c_int64), ("stage_flops", C.c_double), ("io_flops", C.c_double),
         ("stage_bytes", C.c_double), ("stage_launches", C.c_int64), ("launch", C.c_int32),
-        ("stage_kernel", C.c_int32), ("tile_rows", C.c_int32 * 4), ("persistent_grid", C.c_int32),
+        ("stage_kernel", C.c_int32), ("input_stages", C.c_int32), ("tile_rows", C.c_int32 * 4),
+        ("persistent_grid", C.c_int32),
         ("persistent_items", C.c_int64),
     ]
 
 
-def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO):
+def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
+                input_stages=0):
     t = ssm_tuning()
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
+    t.input_stages = int(input_stages)
     for i, r in enumerate(tile_rows):
         t.tile_rows[i] = int(r)
     return t

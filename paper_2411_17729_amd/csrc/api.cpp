@@ -98,6 +98,7 @@ struct ssm_plan_s {
   std::vector<GemmJob> jobs;            // prepare jobs, in launch order
   std::vector<std::pair<int, int>> job_groups;  // (start, count) per launch
   std::vector<std::pair<int, int>> job_dims;    // (max M, max N) per launch
+  std::vector<int> job_kind;                    // 0: GEMM, 1: axpy
   size_t meta_bytes = 0;
   std::vector<unsigned char> meta_host;
   // info
@@ -111,6 +112,10 @@ struct ssm_plan_s {
   int launch = SSM_LAUNCH_PER_STAGE;
   int stage_kernel = SSM_STAGE_TILED;
   int class_bm[4] = {0, 0, 0, 0};
+  int max_kry = 0;                  // leading stages folded into the input pass
+  int class_min_kry[4] = {0, 0, 0, 0};
+  int class_all_kry[4] = {0, 0, 0, 0};  // every sequence of the class is folded
+  Region r_kw;
   // resident-power stage kernel: row ranges per class, longest-running first
   std::vector<ResRange> ranges;
   int class_range_start[4] = {0, 0, 0, 0}, class_range_count[4] = {0, 0, 0, 0};
@@ -185,7 +190,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (st != SSM_OK) return st;
   ssm_tuning tn{};
   if (tuning) tn = *tuning;
-  for (int i = 0; i < 10; ++i)
+  for (size_t i = 0; i < sizeof(tn.reserved) / sizeof(tn.reserved[0]); ++i)
     if (tn.reserved[i] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
   if (tn.stage_kernel < SSM_STAGE_AUTO || tn.stage_kernel > SSM_STAGE_RESIDENT)
     return fail(SSM_E_INVALID, "unknown stage kernel %d", tn.stage_kernel);
@@ -342,6 +347,41 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
                    ? ((classes > 1 || lmin != lmax) ? SSM_LAUNCH_PERSISTENT : SSM_LAUNCH_PER_STAGE)
                    : tn.launch;
   }
+  // leading stages folded into the input pass (resident kernel, per-stage launches)
+  P.max_kry = 0;
+  for (OpDev& o : P.ops) {
+    o.kry = 0;
+    o.kdim = 0;
+    o.kw = o.kc = -1;
+    if (tn.input_stages < 0 || P.launch != SSM_LAUNCH_PER_STAGE ||
+        P.stage_kernel != SSM_STAGE_RESIDENT || !res_supported(o.mp, P.compute))
+      continue;
+    int j = 0;
+    while (((int64_t)o.p << (j + 1)) <= o.mp && j + 1 <= o.N + 1) ++j;
+    if (tn.input_stages > 0) j = std::min(j, tn.input_stages);
+    if (j >= 2) {
+      o.kry = j;
+      o.kdim = o.p << j;
+    }
+  }
+  for (int c = 0; c < 4; ++c) {
+    P.class_min_kry[c] = 1 << 30;
+    P.class_all_kry[c] = 1;
+  }
+  for (SeqDev& sq : P.seqs) {
+    const OpDev& o = P.ops[sq.op];
+    int kr = std::min(o.kry, sq.last + 1);
+    if (kr == sq.last + 1 && res_splits_rows(o.mp, P.compute)) kr = sq.last;
+    if (kr < 2) kr = 0;
+    sq.kry = kr;
+    P.max_kry = std::max(P.max_kry, kr);
+    const int c = class_of(o.mp);
+    P.class_min_kry[c] = std::min(P.class_min_kry[c], kr);
+    if (kr == 0) P.class_all_kry[c] = 0;
+  }
+  for (int c = 0; c < 4; ++c)
+    if (P.class_min_kry[c] == (1 << 30)) P.class_min_kry[c] = 0;
+
   // persistent work items, level by level (projection = level -1), longer
   // sequences first inside a level; default tile heights
   P.items.clear();
@@ -408,11 +448,18 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // (state element size); the last stage writes y instead of the state.
   const double xe = (double)P.x_elem();
   P.stage_launches = 0;
-  for (int c = 0; c < 4; ++c) P.stage_launches += P.class_max_last[c] + 1;
+  for (int c = 0; c < 4; ++c)
+    if (P.class_max_last[c] >= 0)
+      P.stage_launches += std::max(0, P.class_max_last[c] + 1 - P.class_min_kry[c]);
+  P.stage_flops = 0;
   for (int i = 0; i < n_seq; ++i) {
     const SeqDev& s = P.seqs[i];
     const int m = P.ops[s.op].m;
-    for (int kk = 0; kk <= s.last; ++kk) {
+    for (int kk = s.kry; kk <= s.last; ++kk) {
+      const int64_t sh = (int64_t)1 << kk;
+      if (sh < s.L) P.stage_flops += 2.0 * m * m * (double)(s.L - sh);
+    }
+    for (int kk = s.kry; kk <= s.last; ++kk) {
       const double in_row = (double)m * xe;
       const double out_row = kk == s.last ? (double)s.q * xe : (double)m * xe;
       const int64_t sh = (int64_t)1 << kk;
@@ -430,13 +477,19 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // ---- workspace layout ----
   const size_t ce = dt_size(P.compute);
   size_t n_pw = 0, n_pc = 0, n_bbar = 0, n_minv = 0, n_small = 0, n_aug = 0, n_nmat = 0,
-         n_bsc = 0;
+         n_bsc = 0, n_kw = 0;
   for (OpDev& o : P.ops) {
     const size_t mm = (size_t)o.mp * o.mp;
     o.pw = (int64_t)n_pw;
     n_pw += (size_t)(o.N + 1) * mm;
     o.pc = (int64_t)n_pc;
     n_pc += (size_t)(o.N + 1) * mm;
+    if (o.kry > 0) {
+      o.kc = (int64_t)n_pc;
+      n_pc += mm;
+      o.kw = (int64_t)n_kw;
+      n_kw += mm;
+    }
     if (P.with_backward) {
       o.pct = (int64_t)n_pc;
       n_pc += (size_t)(o.N + 1) * mm;
@@ -489,7 +542,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + 16);
   // jobs: 2 per operator (discretization) + one per operator and squaring
   size_t n_jobs = 2 * P.ops.size();
-  for (const OpDev& o : P.ops) n_jobs += (size_t)o.N;
+  for (const OpDev& o : P.ops) n_jobs += (size_t)o.N + (o.kry > 0 ? 1 + o.kry : 0);
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
   P.sum_x = xoff;
@@ -537,6 +590,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   take(P.r_pc, n_pc * ce);
   take(P.r_bbar, n_bbar * 8);
   take(P.r_minv, n_minv * 8);
+  take(P.r_kw, n_kw * 8);
   take(P.r_small, n_small * P.x_elem());
   take(P.r_aug, n_aug * 8);
   take(P.r_nmat, n_nmat * 8);
@@ -946,6 +1000,7 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   double* nmat = P->at<double>(P->r_nmat);
   double* bsc = P->at<double>(P->r_bsc);
   std::vector<GemmJob>& J = P->jobs;
+  P->job_kind.clear();
   if (disc == SSM_DISC_TRAPEZOID) {
     int start = (int)J.size(), mx = 0, mxn = 0;
     for (const OpDev& o : P->ops) {
@@ -960,6 +1015,7 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     }
     P->job_groups.push_back({start, (int)J.size() - start});
     P->job_dims.push_back({mx, mxn});
+    P->job_kind.push_back(0);
   }
   for (int kk = 0; kk < P->max_N; ++kk) {  // P_{k+1} = P_k P_k
     int start = (int)J.size(), mx = 0;
@@ -972,6 +1028,40 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     }
     P->job_groups.push_back({start, (int)J.size() - start});
     P->job_dims.push_back({mx, mx});
+    P->job_kind.push_back(0);
+  }
+  // K_j = [Bbar, Abar Bbar, ...] by doubling: K_0 = Bbar; K_{i+1} = [K_i | P_i K_i]
+  if (P->max_kry > 0) {
+    double* kw = P->at<double>(P->r_kw);
+    int start = (int)J.size(), mx = 0, mn = 0;
+    for (const OpDev& o : P->ops) {
+      if (o.kry <= 0) continue;
+      J.push_back(GemmJob{bbar + o.bbar, nullptr, kw + o.kw, o.mp, o.p, 0, o.p, 0, o.mp, 0, 0, 1.0,
+                          0.0});
+      mx = std::max(mx, o.mp);
+      mn = std::max(mn, o.p);
+    }
+    P->job_groups.push_back({start, (int)J.size() - start});
+    P->job_dims.push_back({mx, mn});
+    P->job_kind.push_back(1);
+    for (int i = 0; i < P->max_kry; ++i) {
+      start = (int)J.size();
+      mx = mn = 0;
+      for (const OpDev& o : P->ops) {
+        if (o.kry <= i) continue;
+        const int64_t mm = (int64_t)o.mp * o.mp;
+        const int w = o.p << i;
+        J.push_back(GemmJob{pw + o.pw + i * mm, kw + o.kw, kw + o.kw + w, o.mp, w, o.mp, o.mp, o.mp,
+                            o.mp, 0, 0, 1.0, 0.0});
+        mx = std::max(mx, o.mp);
+        mn = std::max(mn, w);
+      }
+      if ((int)J.size() > start) {
+        P->job_groups.push_back({start, (int)J.size() - start});
+        P->job_dims.push_back({mx, mn});
+        P->job_kind.push_back(0);
+      }
+    }
   }
 
   // host image of the meta region
@@ -1037,6 +1127,10 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                                 stream);
   if (e != hipSuccess) return bail(hip_fail(e, "upload of plan tables"));
   const int given = disc == SSM_DISC_GIVEN;
+  if (P->r_kw.bytes > 0) {
+    e = launch_zero_i32(P->at<int32_t>(P->r_kw), (int64_t)(P->r_kw.bytes / 4), stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "zero fill"));
+  }
   e = launch_disc_setup(ops_d, P->n_ops, src_d, given, P->at<double>(P->r_aug), nmat, bsc, pw,
                         bbar, P->max_mp, stream);
   if (e != hipSuccess) return bail(hip_fail(e, "discretization setup launch"));
@@ -1052,9 +1146,18 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   }
   for (; g < P->job_groups.size(); ++g) {
     const auto& grp = P->job_groups[g];
-    e = launch_gemm_f64(jobs_d + grp.first, grp.second, P->job_dims[g].first,
-                        P->job_dims[g].second, stream);
+    if (P->job_kind[g] == 1)
+      e = launch_axpy(jobs_d + grp.first, grp.second, P->job_dims[g].first, P->job_dims[g].second,
+                      stream);
+    else
+      e = launch_gemm_f64(jobs_d + grp.first, grp.second, P->job_dims[g].first,
+                          P->job_dims[g].second, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "squaring GEMM launch"));
+  }
+  if (P->max_kry > 0) {
+    e = launch_pack_krylov(ops_d, P->n_ops, P->at<double>(P->r_kw), P->ws + P->r_pc.off, P->compute,
+                           P->max_mp, stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "Krylov pack launch"));
   }
   e = launch_pack(ops_d, P->n_ops, src_d, pw, bbar, P->ws + P->r_pc.off, P->compute,
                   P->with_backward, P->ws + P->r_small.off, P->state_f64, P->max_mp, P->max_N,
@@ -1109,13 +1212,28 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     prm.src_dtype = (int)u_dtype;
     prm.dst = y;
     prm.adjoint = 0;
-    // V^(0) = Bbar U into the first state buffer
-    prm.xout = P.ws + P.r_x0.off;
-    prm.n_tiles = P.class_tile_count[c];
-    hipError_t e = launch_project(kClassMp[c], P.state_f64, P.class_bm[c], prm, stream);
-    if (e != hipSuccess) return hip_fail(e, "projection launch");
+    hipError_t e = hipSuccess;
+    if (!P.class_all_kry[c]) {
+      // V^(0) = Bbar U into the first state buffer
+      prm.xout = P.ws + P.r_x0.off;
+      prm.n_tiles = P.class_tile_count[c];
+      e = launch_project(kClassMp[c], P.state_f64, P.class_bm[c], prm, stream);
+      if (e != hipSuccess) return hip_fail(e, "projection launch");
+    }
     prm.flags = SF_EPILOGUE;
-    for (int kk = 0; kk <= P.class_max_last[c]; ++kk) {
+    int k_begin = 0;
+    if (P.max_kry > 0 && res_supported(kClassMp[c], P.compute)) {
+      // the leading stages folded into the input pass, x^(kry) in buffer kry % 2
+      prm.xin = P.ws + P.r_x0.off;
+      prm.xout = P.ws + P.r_x1.off;
+      const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
+                           P.class_range_start[c];
+      e = launch_krylov_res(kClassMp[c], P.compute, prm, rg, P.class_range_count[c], stream);
+      if (e != hipSuccess) return hip_fail(e, "input pass launch");
+      prm.skip_kry = 1;
+      k_begin = P.class_min_kry[c];
+    }
+    for (int kk = k_begin; kk <= P.class_max_last[c]; ++kk) {
       prm.k = kk;
       prm.xin = P.ws + ((kk & 1) ? P.r_x1.off : P.r_x0.off);
       prm.xout = P.ws + ((kk & 1) ? P.r_x0.off : P.r_x1.off);
@@ -1394,6 +1512,7 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->stage_launches = plan->stage_launches;
   info->launch = plan->launch;
   info->stage_kernel = plan->stage_kernel;
+  info->input_stages = plan->max_kry;
   for (int c = 0; c < 4; ++c) info->tile_rows[c] = plan->class_bm[c];
   info->persistent_grid = plan->persistent_grid;
   info->persistent_items = (int64_t)plan->items.size();

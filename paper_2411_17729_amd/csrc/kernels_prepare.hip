@@ -321,6 +321,31 @@ __global__ void k_pack_powers(const OpDev* ops, const double* pw, void* pc, int 
   }
 }
 
+__global__ void k_pack_krylov(const OpDev* ops, const double* kw, void* kc, int ct) {
+  const OpDev o = ops[blockIdx.y];
+  if (o.kw < 0) return;
+  const int64_t n = (int64_t)o.mp * o.mp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = kw[o.kw + e];
+    if (ct == DT_BF16)
+      ((uint16_t*)kc)[o.kc + e] = f64_to_bf16_bits(v);
+    else if (ct == DT_F32)
+      ((float*)kc)[o.kc + e] = (float)v;
+    else
+      ((double*)kc)[o.kc + e] = v;
+  }
+}
+
+hipError_t launch_pack_krylov(const OpDev* ops, int n_ops, const double* kw, void* kc, int ct,
+                              int max_mp, hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  int blocks = (max_mp * max_mp + 255) / 256;
+  if (blocks > 256) blocks = 256;
+  hipLaunchKernelGGL(k_pack_krylov, dim3(blocks, n_ops), dim3(256), 0, s, ops, kw, kc, ct);
+  return hipGetLastError();
+}
+
 template <typename X>
 __global__ void k_pack_small(const OpDev* ops, const OpSrc* src, const double* bbar, X* sm) {
   const OpDev o = ops[blockIdx.y];

@@ -67,6 +67,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& prm, const Tile t,
   const bool noupd = (prm.flags & SF_NOUPDATE) != 0;
   const int k = prm.k;
   if (!noupd && k > sq.last) return;
+  if (!noupd && prm.skip_kry && k < sq.kry) return;
   const bool adj = prm.adjoint != 0;
   const bool first = !noupd && (adj ? k == sq.last : k == 0);
   const bool final_ = noupd || (adj ? k == 0 : k == sq.last);

@@ -46,6 +46,7 @@ __global__ __launch_bounds__(512, 1) void k_stage_res(StageParams prm, const Res
   const OpDev o = prm.ops[sq.op];
   const int k = prm.k;
   if (k > sq.last) return;
+  if (prm.skip_kry && k < sq.kry) return;
   const bool adj = prm.adjoint != 0;
   const bool first = adj ? k == sq.last : k == 0;
   const bool final_ = adj ? k == 0 : k == sq.last;
@@ -213,6 +214,150 @@ hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRan
       case 64: return launch_res_t<64, DT_F32>(prm, ranges, n_ranges, s);
       case 128: return launch_res_t<128, DT_F32>(prm, ranges, n_ranges, s);
       case 256: return launch_res_t<256, DT_F32>(prm, ranges, n_ranges, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Input pass with the leading j = kry stages folded in (forward only):
+//   x^(j)_l = sum_{i < 2^j} Abar^i Bbar u_{l-i} = K_j w_l,
+//   w_l = [u_l; u_{l-1}; ...; u_{l-2^j+1}] (zero before the sequence start),
+// with K_j resident in LDS like P_k above and w_l gathered from u.
+// ---------------------------------------------------------------------------
+template <int MP, int CT>
+__global__ __launch_bounds__(512, 1) void k_krylov_res(StageParams prm, const ResRange* ranges) {
+  using C = ResCfg<MP, CT>;
+  using X = float;
+  using Op = typename C::Op;
+  constexpr int NR = C::NR, NB = C::NB, SP = C::SP;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_res[];
+  Op* Ks = reinterpret_cast<Op*>(smem_res);
+
+  const ResRange rg = ranges[blockIdx.x];
+  const SeqDev sq = prm.seqs[rg.seq];
+  const OpDev o = prm.ops[sq.op];
+  if (sq.kry <= 0) return;
+  const int n0 = blockIdx.y * NR;
+  const int64_t L = sq.L;
+  const int p = sq.p;
+  const int kdim = (1 << sq.kry) * p;
+  const bool final_ = sq.kry == sq.last + 1;
+  const bool epi = (prm.flags & SF_EPILOGUE) && final_ && C::NS == 1;
+  {
+    const Op* K = reinterpret_cast<const Op*>(prm.P) + o.kc + (int64_t)n0 * MP;
+    constexpr int VO = 16 / (int)sizeof(Op);
+    for (int e = threadIdx.x; e < NR * (MP / VO); e += 512) {
+      const int r = e / (MP / VO), c = (e % (MP / VO)) * VO;
+      *reinterpret_cast<uint4*>(Ks + r * SP + c) =
+          *reinterpret_cast<const uint4*>(K + (int64_t)r * MP + c);
+    }
+    __syncthreads();
+  }
+  X* xo = reinterpret_cast<X*>((sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  // u value of window column kk for time row l (zero outside)
+  auto wv = [&](int64_t l, int kk) -> X {
+    if (kk >= kdim) return 0.f;
+    const int64_t lu = l - kk / p;
+    if (lu < 0) return 0.f;
+    return load_src<X>(prm.src, prm.src_dtype, sq.u_off + lu * p + (kk % p));
+  };
+  const int nblk = (rg.nrows + 15) / 16;
+  for (int b = wave; b < nblk; b += C::WAVES) {
+    const int64_t l = (int64_t)rg.row0 + b * 16 + j;
+    const bool lv = l < L && l < (int64_t)rg.row0 + rg.nrows;
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (CT == DT_BF16) {
+      for (int c = 0; c < (kdim + 31) / 32; ++c) {
+        bf16x8 bop;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          bop[e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(lv ? wv(l, 32 * c + 8 * g + e) : 0.f));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x8 aop =
+              *reinterpret_cast<const bf16x8*>(Ks + (nb * 16 + j) * SP + 32 * c + 8 * g);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[nb], 0, 0, 0);
+        }
+      }
+    } else {
+      for (int a = 0; a < (kdim + 15) / 16; ++a) {
+        f32x4 bv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[t] = lv ? wv(l, 16 * a + 4 * g + t) : 0.f;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const f32x4 av =
+              *reinterpret_cast<const f32x4*>(Ks + (nb * 16 + j) * SP + 16 * a + 4 * g);
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[t], acc[nb], 0, 0, 0);
+        }
+      }
+    }
+    if (lv && !epi) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        *reinterpret_cast<f32x4*>(xo + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
+    }
+    if (epi) {
+      const int w = sq.q;
+      const X* cm = reinterpret_cast<const X*>(prm.small) + o.cout;
+      const X* dm = reinterpret_cast<const X*>(prm.small) + o.dmat;
+      X* dst = reinterpret_cast<X*>(prm.dst);
+      for (int qq = 0; qq < w; ++qq) {
+        float part = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const f32x4 cv = *reinterpret_cast<const f32x4*>(cm + (int64_t)qq * MP + nb * 16 + 4 * g);
+          part += cv[0] * acc[nb][0] + cv[1] * acc[nb][1] + cv[2] * acc[nb][2] + cv[3] * acc[nb][3];
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0 && lv) {
+          for (int c = 0; c < p; ++c)
+            part += dm[qq * p + c] * load_src<X>(prm.src, prm.src_dtype, sq.u_off + l * p + c);
+          dst[sq.y_off + l * w + qq] = part;
+        }
+      }
+    }
+  }
+}
+
+template <int MP, int CT>
+static hipError_t launch_kry_t(const StageParams& prm, const ResRange* ranges, int n_ranges,
+                               hipStream_t s) {
+  using C = ResCfg<MP, CT>;
+  if (n_ranges <= 0) return hipSuccess;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_krylov_res<MP, CT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_krylov_res<MP, CT>), dim3(n_ranges, C::NS), dim3(512), C::LDS, s, prm,
+                     ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_krylov_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
+                             int n_ranges, hipStream_t s) {
+  if (ct == DT_BF16) {
+    switch (mp) {
+      case 64: return launch_kry_t<64, DT_BF16>(prm, ranges, n_ranges, s);
+      case 128: return launch_kry_t<128, DT_BF16>(prm, ranges, n_ranges, s);
+      case 256: return launch_kry_t<256, DT_BF16>(prm, ranges, n_ranges, s);
+    }
+  } else if (ct == DT_F32) {
+    switch (mp) {
+      case 64: return launch_kry_t<64, DT_F32>(prm, ranges, n_ranges, s);
+      case 128: return launch_kry_t<128, DT_F32>(prm, ranges, n_ranges, s);
+      case 256: return launch_kry_t<256, DT_F32>(prm, ranges, n_ranges, s);
     }
   }
   return hipErrorInvalidValue;

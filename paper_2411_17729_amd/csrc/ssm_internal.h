@@ -19,6 +19,8 @@ struct SeqDev {
   int32_t op;     // operator index
   int32_t last;   // last stage index this sequence runs (0 if no stage acts)
   int32_t p, q;
+  int32_t kry;    // leading stages folded into the input pass by apply (0: none)
+  int32_t reserved;
 };
 
 // One operator (a distinct discretized Abar with its Bbar, C, D).
@@ -36,6 +38,10 @@ struct OpDev {
   int64_t bbar;  // FP64 Bbar (mp x p)
   int64_t minv;  // FP64 (I - delta/2 A)^{-1} (mp x mp)
   int64_t sc_aug, sc_n, sc_b;  // prepare scratch: [M | I] (mp x 2mp), I + hA, delta B
+  int64_t kw;    // FP64 K_j = [Bbar, Abar Bbar, ...] (mp x mp, columns beyond 2^j p zero), or -1
+  int64_t kc;    // K_j in the compute type, same layout, or -1
+  int32_t kry;   // j of this operator (0: none)
+  int32_t kdim;  // 2^j p
   // backward, FP64 gradient workspace offsets
   int64_t g_dp;    // dL/dP_k, k = 0..N (mp x mp each); becomes the squaring adjoint
   int64_t g_dbb;   // dL/dBbar (mp x p)
@@ -77,6 +83,8 @@ struct StageParams {
   int32_t adjoint;    // 0: x_l += P_k x_{l-2^k};  1: g_l += P_k^T g_{l+2^k}
   int32_t flags;
   int32_t n_tiles;
+  int32_t skip_kry;  // stages below a sequence's kry were done by the input pass
+  int32_t reserved;
 };
 
 // A range of rows of one sequence for the resident-power stage kernel.
@@ -204,6 +212,10 @@ hipError_t launch_disc_setup(const OpDev* ops, int n_ops, const OpSrc* src, int 
 hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double* minv,
                                int* status, hipStream_t s);
 
+// Casts K_j (FP64, mp x mp per operator with kw >= 0) to the compute type.
+hipError_t launch_pack_krylov(const OpDev* ops, int n_ops, const double* kw, void* kc, int ct,
+                              int max_mp, hipStream_t s);
+
 // Casts the FP64 powers to the compute type (and transposes when want_t),
 // and fills the small state-type matrices (Bbar, C, D and transposes).
 hipError_t launch_pack(const OpDev* ops, int n_ops, const OpSrc* src, const double* pw,
@@ -217,6 +229,10 @@ bool res_supported(int mp, int ct);
 bool res_splits_rows(int mp, int ct);
 hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
                             int n_ranges, hipStream_t s);
+// Input pass with the leading kry stages folded in: x^(kry)_l = K u-window_l,
+// written to xin (kry even) or xout (kry odd); y at once when kry = last + 1.
+hipError_t launch_krylov_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
+                             int n_ranges, hipStream_t s);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);

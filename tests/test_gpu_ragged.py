@@ -196,3 +196,33 @@ def test_resident_kernel_matches_tiled(compute):
     st_r = state_part(wl, [ref[i] for i in range(len(wl.seqs))], uq)
     for i in range(len(wl.seqs)):
         assert rel_err(st_g[i], st_r[i]) <= (1e-5 if compute == "f32" else 2e-2), i
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_folded_input_stages(compute):
+    # x^(j) = K_j [u_l; ...; u_{l-2^j+1}] replaces the projection and stages
+    # 0..j-1: agreement with the unfolded path and with the oracle, including
+    # sequences whose every stage is folded (the input pass writes y)
+    from paper_2411_17729_amd import cascade as CC
+    rng = np.random.default_rng(17)
+    sets, seqs = [], []
+    for i, (m, p, q, L, N) in enumerate([(256, 8, 8, 3000, 11), (256, 8, 8, 20, 4),
+                                         (128, 4, 2, 900, 9), (64, 2, 3, 33, 5), (100, 3, 1, 500, 8)]):
+        A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, p)) / math.sqrt(m),
+                               rng.standard_normal((q, m)) / math.sqrt(m), np.zeros((q, p))))
+        seqs.append(W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, N, rng.standard_normal((L, p))))
+    wl = W.Workload("fold", sets, seqs)
+    u = CC.pack_u(wl, dtype=torch.float32)
+    folded = CC.plan_for_workload(wl, compute=compute, launch="per_stage")
+    assert folded.info()["input_stages"] >= 5
+    plain = CC.plan_for_workload(wl, compute=compute, launch="per_stage", input_stages=-1)
+    assert plain.info()["input_stages"] == 0
+    ya = CC.unpack_y(wl, folded.apply(u))
+    yb = CC.unpack_y(wl, plain.apply(u))
+    ref = _oracle(wl)
+    tol = 1e-5 if compute == "f32" else 2e-2
+    for i in range(len(wl.seqs)):
+        ea, eb = rel_err(ya[i], ref[i]), rel_err(yb[i], ref[i])
+        print(compute, i, f"folded {ea:.2e} plain {eb:.2e}", flush=True)
+        assert ea <= tol and eb <= tol, (i, ea, eb)
