@@ -46,6 +46,9 @@ def _args():
                     help="skip the other dtype and the recursion comparator")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU oracle sample")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the measurement, run one device-to-device copy of this many MiB "
+                         "(a reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -207,6 +210,15 @@ def main():
             rel[name] = {"y": ey, "state": ex}
         out["rel_err_vs_fp64"] = {k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()} for k, v in rel.items()}
         out["rel_err_sample"] = f"sequences {done}"
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = n * 4
 
     print(json.dumps(out), flush=True)
 

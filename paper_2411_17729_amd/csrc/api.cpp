@@ -500,6 +500,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     n_bbar += (size_t)o.mp * o.p;
     o.minv = (int64_t)n_minv;
     n_minv += mm;
+    n_small = (n_small + 3) & ~(size_t)3;  // 16-byte aligned rows for vector loads
     o.bin = (int64_t)n_small;
     n_small += (size_t)o.mp * o.p;
     o.bt = (int64_t)n_small;

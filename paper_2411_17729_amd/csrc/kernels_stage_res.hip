@@ -31,6 +31,47 @@ struct ResCfg {
   static constexpr int NV = MP / 16;  // float4 pieces of a shifted row held per lane
 };
 
+// Output epilogue on the matrix cores: for the lane's 16-row block,
+//     Y^T[qq, l] = sum_n Cm[qq, n] X^T[n, l] + sum_c Dm[qq, c] V^T[c, l]
+// (y = C x + D u forward, du = Bbar^T g + D^T dy adjoint), 16 outputs at a
+// time with the FP32 16x16x4 MFMA. The state block is used where it lies:
+// accumulator entry v of block nb (state index 16 nb + 4 g + v, time row j)
+// is the B operand of step (nb, v), whose contraction index 4-group is g, so
+// the A operand of lane (i, g) is Cm[q0 + i][16 nb + 4 g + v]. The inputs V
+// enter the same accumulator, four channels per step. The result lane (j, g)
+// holds outputs q0 + 4 g + v of time row l.
+template <int NB>
+__device__ __forceinline__ void res_epilogue(const f32x4 (&acc)[NB], int mp, int64_t l, bool lv,
+                                             const float* cm, const float* dm, int w, int r_in,
+                                             const void* src, int sdt, int64_t src_off,
+                                             float* dst, int64_t dst_off, int j, int g) {
+  for (int q0 = 0; q0 < w; q0 += 16) {
+    const int qi = q0 + j;
+    const bool qv = qi < w;
+    f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const f32x4 cv = qv ? *reinterpret_cast<const f32x4*>(cm + (int64_t)qi * mp + nb * 16 + 4 * g)
+                          : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[v], acc[nb][v], ya, 0, 0, 0);
+    }
+    for (int a = 0; a < (r_in + 3) / 4; ++a) {
+      const int c = 4 * a + g;
+      const float dv = qv && c < r_in ? dm[qi * r_in + c] : 0.f;
+      const float uv = lv && c < r_in ? load_src<float>(src, sdt, src_off + l * r_in + c) : 0.f;
+      ya = __builtin_amdgcn_mfma_f32_16x16x4f32(dv, uv, ya, 0, 0, 0);
+    }
+    if (lv) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int qq = q0 + 4 * g + v;
+        if (qq < w) dst[dst_off + l * w + qq] = ya[v];
+      }
+    }
+  }
+}
+
 template <int MP, int CT>
 __global__ __launch_bounds__(512, 1) void k_stage_res(StageParams prm, const ResRange* ranges) {
   using C = ResCfg<MP, CT>;
@@ -146,32 +187,13 @@ __global__ __launch_bounds__(512, 1) void k_stage_res(StageParams prm, const Res
         if (xfin) *reinterpret_cast<f32x4*>(xfin + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
       }
     }
-    if (epi) {
-      // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint):
-      // partial dot over this lane's entries, then over the four lane groups
-      const int w = adj ? sq.p : sq.q;
-      const int r_in = adj ? sq.q : sq.p;
-      const X* cm = reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout);
-      const X* dm = reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat);
-      const int64_t src_off = adj ? sq.y_off : sq.u_off;
-      const int64_t dst_off = adj ? sq.u_off : sq.y_off;
-      X* dst = reinterpret_cast<X*>(prm.dst);
-      for (int qq = 0; qq < w; ++qq) {
-        float part = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const f32x4 cv = *reinterpret_cast<const f32x4*>(cm + (int64_t)qq * MP + nb * 16 + 4 * g);
-          part += cv[0] * acc[nb][0] + cv[1] * acc[nb][1] + cv[2] * acc[nb][2] + cv[3] * acc[nb][3];
-        }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (g == 0 && lv) {
-          for (int c = 0; c < r_in; ++c)
-            part += dm[qq * r_in + c] * load_src<X>(prm.src, prm.src_dtype, src_off + l * r_in + c);
-          dst[dst_off + l * w + qq] = part;
-        }
-      }
-    }
+    if (epi)  // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
+      res_epilogue<NB>(acc, MP, l, lv,
+                       reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout),
+                       reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat),
+                       adj ? sq.p : sq.q, adj ? sq.q : sq.p, prm.src, prm.src_dtype,
+                       adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
+                       adj ? sq.u_off : sq.y_off, j, g);
   }
 }
 
@@ -257,12 +279,45 @@ __global__ __launch_bounds__(512, 1) void k_krylov_res(StageParams prm, const Re
   X* xo = reinterpret_cast<X*>((sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
-  // u value of window column kk for time row l (zero outside)
-  auto wv = [&](int64_t l, int kk) -> X {
-    if (kk >= kdim) return 0.f;
-    const int64_t lu = l - kk / p;
-    if (lu < 0) return 0.f;
-    return load_src<X>(prm.src, prm.src_dtype, sq.u_off + lu * p + (kk % p));
+  // Window column kk of row l is u[l - kk / p][kk % p] (zero before the start).
+  // A lane's columns come in runs of 8 (BF16) or 4 (FP32) consecutive kk;
+  // each run is walked with one division and then a carried (lag, channel).
+  const void* usrc = prm.src;
+  const int udt = prm.src_dtype;
+  const int64_t uoff = sq.u_off;
+  // FP32 input with 4 | p and 16-byte aligned rows: the runs split into
+  // 16-byte pieces of one input row each.
+  const bool vec4 = udt == DT_F32 && (p & 3) == 0 && (uoff & 3) == 0 &&
+                    (reinterpret_cast<uintptr_t>(usrc) & 15) == 0;
+  auto run = [&](int64_t l, int kk0, float* dstv, int n) {
+    int lag = kk0 / p, ch = kk0 - lag * p;
+    if (vec4) {
+      for (int e = 0; e < n; e += 4) {
+        const int64_t lu = l - lag;
+        const f32x4 v = (kk0 + e < kdim && lu >= 0)
+                            ? *reinterpret_cast<const f32x4*>(
+                                  reinterpret_cast<const float*>(usrc) + uoff + lu * p + ch)
+                            : f32x4{0.f, 0.f, 0.f, 0.f};
+        dstv[e] = v[0];
+        dstv[e + 1] = v[1];
+        dstv[e + 2] = v[2];
+        dstv[e + 3] = v[3];
+        ch += 4;
+        if (ch == p) {
+          ch = 0;
+          ++lag;
+        }
+      }
+      return;
+    }
+    for (int e = 0; e < n; ++e) {
+      const int64_t lu = l - lag;
+      dstv[e] = (kk0 + e < kdim && lu >= 0) ? load_src<X>(usrc, udt, uoff + lu * p + ch) : 0.f;
+      if (++ch == p) {
+        ch = 0;
+        ++lag;
+      }
+    }
   };
   const int nblk = (rg.nrows + 15) / 16;
   for (int b = wave; b < nblk; b += C::WAVES) {
@@ -273,10 +328,14 @@ __global__ __launch_bounds__(512, 1) void k_krylov_res(StageParams prm, const Re
     for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     if constexpr (CT == DT_BF16) {
       for (int c = 0; c < (kdim + 31) / 32; ++c) {
+        float wvals[8];
+        if (lv)
+          run(l, 32 * c + 8 * g, wvals, 8);
+        else
+          for (int e = 0; e < 8; ++e) wvals[e] = 0.f;
         bf16x8 bop;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          bop[e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(lv ? wv(l, 32 * c + 8 * g + e) : 0.f));
+        for (int e = 0; e < 8; ++e) bop[e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(wvals[e]));
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           const bf16x8 aop =
@@ -286,16 +345,18 @@ __global__ __launch_bounds__(512, 1) void k_krylov_res(StageParams prm, const Re
       }
     } else {
       for (int a = 0; a < (kdim + 15) / 16; ++a) {
-        f32x4 bv;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) bv[t] = lv ? wv(l, 16 * a + 4 * g + t) : 0.f;
+        float wvals[4];
+        if (lv)
+          run(l, 16 * a + 4 * g, wvals, 4);
+        else
+          for (int t = 0; t < 4; ++t) wvals[t] = 0.f;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           const f32x4 av =
               *reinterpret_cast<const f32x4*>(Ks + (nb * 16 + j) * SP + 16 * a + 4 * g);
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[t], acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], wvals[t], acc[nb], 0, 0, 0);
         }
       }
     }
@@ -304,27 +365,10 @@ __global__ __launch_bounds__(512, 1) void k_krylov_res(StageParams prm, const Re
       for (int nb = 0; nb < NB; ++nb)
         *reinterpret_cast<f32x4*>(xo + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
     }
-    if (epi) {
-      const int w = sq.q;
-      const X* cm = reinterpret_cast<const X*>(prm.small) + o.cout;
-      const X* dm = reinterpret_cast<const X*>(prm.small) + o.dmat;
-      X* dst = reinterpret_cast<X*>(prm.dst);
-      for (int qq = 0; qq < w; ++qq) {
-        float part = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const f32x4 cv = *reinterpret_cast<const f32x4*>(cm + (int64_t)qq * MP + nb * 16 + 4 * g);
-          part += cv[0] * acc[nb][0] + cv[1] * acc[nb][1] + cv[2] * acc[nb][2] + cv[3] * acc[nb][3];
-        }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (g == 0 && lv) {
-          for (int c = 0; c < p; ++c)
-            part += dm[qq * p + c] * load_src<X>(prm.src, prm.src_dtype, sq.u_off + l * p + c);
-          dst[sq.y_off + l * w + qq] = part;
-        }
-      }
-    }
+    if (epi)
+      res_epilogue<NB>(acc, MP, l, lv, reinterpret_cast<const X*>(prm.small) + o.cout,
+                       reinterpret_cast<const X*>(prm.small) + o.dmat, sq.q, p, usrc, udt, uoff,
+                       reinterpret_cast<X*>(prm.dst), sq.y_off, j, g);
   }
 }
 
