@@ -31,7 +31,9 @@ if ROOT not in sys.path:
 
 METRIC = "output steps/s + MFMA util: cascade vs recursion on one GPU at rel err vs FP64"
 PEAK = {"hbm_GBps": 8000.0, "bf16_TFLOPs": 2500.0, "f32_TFLOPs": 157.3, "f64_TFLOPs": 78.6}
-STAGE_SRC = os.path.join(ROOT, "paper_2411_17729_amd", "csrc", "kernels_stage.hip")
+# stage kernel of each ssm_stage_kernel value: (name, source file)
+STAGE_KERNELS = {1: ("k_stage", "kernels_stage.hip"), 2: ("k_stage_res", "kernels_stage_res.hip"),
+                 3: ("k_stage_chain", "kernels_stage_chain.hip")}
 
 
 def _args():
@@ -52,15 +54,17 @@ def _args():
     return ap.parse_args()
 
 
-def _stage_traffic(workload, dtype):
+def _stage_traffic(workload, dtype, kernel):
     """HBM bytes per stage launch from committed rocprofv3 counter runs, if
-    they were taken on the current stage kernel source."""
+    they were taken on the current source of this stage kernel."""
+    name, src = STAGE_KERNELS[kernel]
     path = os.path.join(ROOT, "profiles", f"stage_traffic_{workload}_{dtype}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(STAGE_SRC, "rb").read()).hexdigest()
-    if rec.get("kernel_sha256") != sha:
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2411_17729_amd", "csrc", src), "rb")
+                         .read()).hexdigest()
+    if rec.get("kernel") != name or rec.get("kernel_sha256") != sha:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -130,7 +134,10 @@ def main():
         intensity = info["stage_flops"] / info["stage_bytes"]
         ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
         bound = "mfma" if intensity > ridge else "hbm"
-        traffic = _stage_traffic(wname, dtype)
+        kid = info["stage_kernel"]
+        if kid == 3 and dtype == "f32" and ps.m > 128:
+            kid = 2  # FP32 m > 128: the chain walk does not apply, the resident kernel runs
+        traffic = _stage_traffic(wname, dtype, kid)
         if bound == "hbm":
             rf = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"],
                   "unit": "GB/s", "frac": round(gbps / PEAK["hbm_GBps"], 4)}
@@ -138,7 +145,7 @@ def main():
             rf = {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak_tf,
                   "unit": "TFLOP/s", "frac": round(tflops / peak_tf, 4)}
         rf["traffic"] = traffic
-        rf.update({"kernel": "k_stage", "launches_timed": n_launch, "avg_launch_ms": round(avg_ms, 5),
+        rf.update({"kernel": STAGE_KERNELS[kid][0], "launches_timed": n_launch, "avg_launch_ms": round(avg_ms, 5),
                    "algorithmic_bytes_per_launch": round(per_launch_bytes),
                    "algorithmic_flops_per_launch": round(per_launch_flops),
                    "mfma_util": round(tflops / peak_tf, 4), "hbm_GBps": round(gbps, 1)})

@@ -88,10 +88,17 @@ typedef enum {
  * default or half of it (the persistent launch always uses the defaults).
  * Defaults: 256, 128, 64, 64 rows for F32/BF16 and 128, 64, 64, 32 for F64. */
 typedef enum {
-  SSM_STAGE_AUTO = 0,     /* resident where supported, tiled otherwise */
+  SSM_STAGE_AUTO = 0,     /* chain where supported, then resident, then tiled */
   SSM_STAGE_TILED = 1,    /* power streamed through LDS in K chunks per row tile */
-  SSM_STAGE_RESIDENT = 2  /* power resident in LDS, waves stream 16-row blocks
+  SSM_STAGE_RESIDENT = 2, /* power resident in LDS, waves stream 16-row blocks
                              (BF16/FP32 operands and padded m of 64..256 only) */
+  SSM_STAGE_CHAIN = 3     /* power resident in LDS; at stages with shift 2^k >= 16
+                             each wave walks a column of 16-row blocks spaced 2^k
+                             apart and reuses each block's input rows as the next
+                             block's shifted operand, so the state is read about
+                             once per stage instead of twice (BF16 at padded m of
+                             64..256, FP32 at 64 and 128; other stages and sizes
+                             use the resident kernel) */
 } ssm_stage_kernel;
 
 typedef struct {
@@ -106,7 +113,11 @@ typedef struct {
    * factors of eq. (2.2) applied to Bbar. 0: automatic (the largest j with
    * 2^j p <= m, if at least 2), -1: none, j > 0: at most j. */
   int32_t input_stages;
-  int32_t reserved[9];   /* must be 0 */
+  /* Chain kernel: 16-row blocks per wave segment (each segment re-reads one
+   * block, its first block's partner). 0: automatic (1..8 from the batch's row
+   * count), otherwise 1..64. */
+  int32_t chain_blocks;
+  int32_t reserved[8];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -145,9 +156,10 @@ typedef struct {
   int64_t total_steps;       /* sum of L over sequences */
   double stage_flops;        /* sum over sequences and run stages of 2 m^2 (L - 2^k) */
   double io_flops;           /* 2 m p L (input) + 2 q (m + p) L (output), summed */
-  double stage_bytes;        /* algorithmic HBM bytes of the stage kernel: per stage and row,
-                                read the row, read its shifted partner (rows that have one)
-                                and write the row; the last stage writes y instead */
+  double stage_bytes;        /* compulsory HBM bytes of the stage launches: per stage and
+                                row, read the row once and write it once (the shifted
+                                partner is a row of the same stage input); the last stage
+                                writes y instead */
   int64_t stage_launches;    /* stage-kernel launches per apply (per-stage mode) */
   int32_t launch;            /* ssm_launch the plan uses (never AUTO) */
   int32_t stage_kernel;      /* ssm_stage_kernel the plan uses (never AUTO) */

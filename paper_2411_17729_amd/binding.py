@@ -24,7 +24,7 @@ SSM_OK, SSM_E_INVALID, SSM_E_UNSUPPORTED, SSM_E_WORKSPACE, SSM_E_HIP, SSM_E_NOT_
 SSM_F64, SSM_F32, SSM_BF16 = 0, 1, 2
 SSM_DISC_TRAPEZOID, SSM_DISC_GIVEN = 0, 1
 SSM_LAUNCH_AUTO, SSM_LAUNCH_PER_STAGE, SSM_LAUNCH_PERSISTENT = 0, 1, 2
-SSM_STAGE_AUTO, SSM_STAGE_TILED, SSM_STAGE_RESIDENT = 0, 1, 2
+SSM_STAGE_AUTO, SSM_STAGE_TILED, SSM_STAGE_RESIDENT, SSM_STAGE_CHAIN = 0, 1, 2, 3
 
 # kernel classes of ssm_cascade_timing_read
 TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION = 0, 1, 2, 3
@@ -54,7 +54,7 @@ class ssm_params(C.Structure):
 
 class ssm_tuning(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
-                ("input_stages", C.c_int32), ("reserved", C.c_int32 * 9)]
+                ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("reserved", C.c_int32 * 8)]
 
 
 class ssm_plan_info(C.Structure):
@@ -69,11 +69,12 @@ class ssm_plan_info(C.Structure):
 
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
-                input_stages=0):
+                input_stages=0, chain_blocks=0):
     t = ssm_tuning()
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
     t.input_stages = int(input_stages)
+    t.chain_blocks = int(chain_blocks)
     for i, r in enumerate(tile_rows):
         t.tile_rows[i] = int(r)
     return t

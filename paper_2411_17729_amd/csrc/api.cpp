@@ -122,6 +122,10 @@ struct ssm_plan_s {
   std::vector<int> class_range_active[4];
   std::vector<int> class_final[4];  // sequences whose last stage is k
   size_t m_ranges = 0;
+  // chain stage kernel: work units per class and stage (empty where unused)
+  std::vector<ChainUnit> chain_units;
+  std::vector<int> chain_start[4], chain_count[4], chain_T[4];
+  size_t m_chain = 0;
   // persistent launch
   std::vector<PItem> items;
   std::vector<int32_t> cnt_off, ntiles;
@@ -192,12 +196,17 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (tuning) tn = *tuning;
   for (size_t i = 0; i < sizeof(tn.reserved) / sizeof(tn.reserved[0]); ++i)
     if (tn.reserved[i] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
-  if (tn.stage_kernel < SSM_STAGE_AUTO || tn.stage_kernel > SSM_STAGE_RESIDENT)
+  if (tn.stage_kernel < SSM_STAGE_AUTO || tn.stage_kernel > SSM_STAGE_CHAIN)
     return fail(SSM_E_INVALID, "unknown stage kernel %d", tn.stage_kernel);
-  if (tn.stage_kernel == SSM_STAGE_RESIDENT && compute == SSM_F64)
-    return fail(SSM_E_UNSUPPORTED, "the resident stage kernel takes BF16 or FP32 operands");
-  P.stage_kernel = tn.stage_kernel == SSM_STAGE_TILED || compute == SSM_F64 ? SSM_STAGE_TILED
-                                                                          : SSM_STAGE_RESIDENT;
+  if ((tn.stage_kernel == SSM_STAGE_RESIDENT || tn.stage_kernel == SSM_STAGE_CHAIN) &&
+      compute == SSM_F64)
+    return fail(SSM_E_UNSUPPORTED, "the resident and chain stage kernels take BF16 or FP32 operands");
+  if (tn.chain_blocks < 0 || tn.chain_blocks > 64)
+    return fail(SSM_E_INVALID, "chain_blocks = %d: supported 0 (automatic) or 1..64", tn.chain_blocks);
+  if (tn.stage_kernel == SSM_STAGE_TILED || compute == SSM_F64)
+    P.stage_kernel = SSM_STAGE_TILED;
+  else
+    P.stage_kernel = tn.stage_kernel == SSM_STAGE_RESIDENT ? SSM_STAGE_RESIDENT : SSM_STAGE_CHAIN;
   if (tn.launch < SSM_LAUNCH_AUTO || tn.launch > SSM_LAUNCH_PERSISTENT)
     return fail(SSM_E_INVALID, "unknown launch mode %d", tn.launch);
   for (int c = 0; c < 4; ++c) {
@@ -307,6 +316,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
 
   // row ranges of the resident-power kernel (about 512 per class)
   P.ranges.clear();
+  P.chain_units.clear();
   for (int c = 0; c < 4; ++c) {
     std::vector<int> ids;
     int64_t rows = 0;
@@ -333,6 +343,31 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       P.class_range_active[c][kk] = cnt;
     }
     for (int i : ids) P.class_final[c][P.seqs[i].last] += 1;
+
+    // chain-kernel units for the stages with 2^k >= 16: per sequence (longest
+    // running first) its segments of T blocks, eight per workgroup
+    P.chain_start[c].assign(ml + 1, 0);
+    P.chain_count[c].assign(ml + 1, 0);
+    P.chain_T[c].assign(ml + 1, 0);
+    if (P.stage_kernel != SSM_STAGE_CHAIN || !chain_supported(kClassMp[c], (int)compute)) continue;
+    for (int kk = 4; kk <= ml; ++kk) {
+      const int64_t sh = (int64_t)1 << kk;
+      int64_t blocks = 0;
+      for (int i : ids)
+        if (P.seqs[i].last >= kk) blocks += (P.seqs[i].L + 15) / 16;
+      const int T = tn.chain_blocks > 0 ? tn.chain_blocks
+                                        : (int)std::min<int64_t>(8, std::max<int64_t>(1, blocks / 4096));
+      P.chain_T[c][kk] = T;
+      P.chain_start[c][kk] = (int)P.chain_units.size();
+      for (int i : ids) {
+        if (P.seqs[i].last < kk) continue;
+        const int64_t ni = (P.seqs[i].L + sh - 1) / sh;
+        const int64_t nseg = (sh / 16) * ((ni + T - 1) / T);
+        for (int64_t g0 = 0; g0 < nseg; g0 += 8)
+          P.chain_units.push_back(ChainUnit{i, (int32_t)g0, T, 0});
+      }
+      P.chain_count[c][kk] = (int)P.chain_units.size() - P.chain_start[c][kk];
+    }
   }
 
   // launch mode: persistent for ragged batches unless asked otherwise
@@ -354,7 +389,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     o.kdim = 0;
     o.kw = o.kc = -1;
     if (tn.input_stages < 0 || P.launch != SSM_LAUNCH_PER_STAGE ||
-        P.stage_kernel != SSM_STAGE_RESIDENT || !res_supported(o.mp, P.compute))
+        P.stage_kernel == SSM_STAGE_TILED || !res_supported(o.mp, P.compute))
       continue;
     int j = 0;
     while (((int64_t)o.p << (j + 1)) <= o.mp && j + 1 <= o.N + 1) ++j;
@@ -444,8 +479,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     xoff += s.L * (int64_t)P.ops[s.op].mp;
   }
   // algorithmic HBM bytes of the stage launches: per stage and row, read the
-  // row and (for rows with a partner) the shifted partner, and write the row
-  // (state element size); the last stage writes y instead of the state.
+  // row once and write it once (state element size); the last stage writes y
+  // instead of the state. The shifted partner of a row is a row of the same
+  // stage input, so it adds no compulsory traffic.
   const double xe = (double)P.x_elem();
   P.stage_launches = 0;
   for (int c = 0; c < 4; ++c)
@@ -462,9 +498,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     for (int kk = s.kry; kk <= s.last; ++kk) {
       const double in_row = (double)m * xe;
       const double out_row = kk == s.last ? (double)s.q * xe : (double)m * xe;
-      const int64_t sh = (int64_t)1 << kk;
-      const double upd_rows = sh < s.L ? (double)(s.L - sh) : 0.0;
-      P.stage_bytes += s.L * (in_row + out_row) + upd_rows * in_row;
+      P.stage_bytes += s.L * (in_row + out_row);
     }
   }
 
@@ -549,6 +583,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   P.sum_x = xoff;
   P.m_ranges = off;
   off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.ranges.size()));
+  P.m_chain = off;
+  off = align_up(off + sizeof(ChainUnit) * std::max<size_t>(1, P.chain_units.size()));
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
     P.m_items = off;
     off = align_up(off + sizeof(PItem) * std::max<size_t>(1, P.items.size()));
@@ -852,15 +888,22 @@ ssm_status check_io(const ssm_plan_s& P, const void* u, ssm_dtype u_dtype, size_
   return SSM_OK;
 }
 
-// One per-stage launch of class c at stage prm.k: the resident-power kernel
-// where the plan uses it and it can apply this stage, the tiled one otherwise.
+// One per-stage launch of class c at stage prm.k: the chain kernel where the
+// plan has units for this stage, else the resident-power kernel where the plan
+// uses it and it can apply this stage, the tiled one otherwise.
 hipError_t launch_stage_any(const ssm_plan_s& P, int c, StageParams prm, hipStream_t stream) {
   const int mp = kClassMp[c];
   const int k = prm.k;
+  if (k < (int)P.chain_count[c].size() && P.chain_count[c][k] > 0) {
+    const ChainUnit* un = reinterpret_cast<const ChainUnit*>(P.ws + P.r_meta.off + P.m_chain) +
+                          P.chain_start[c][k];
+    const bool tail = prm.adjoint ? k == 0 : P.class_final[c][k] > 0;
+    return launch_stage_chain(mp, P.compute, prm, un, P.chain_count[c][k], tail, stream);
+  }
   const bool final_here = (prm.flags & SF_EPILOGUE) &&
                           (prm.adjoint ? k == 0 : (k < (int)P.class_final[c].size() &&
                                                    P.class_final[c][k] > 0));
-  if (P.stage_kernel == SSM_STAGE_RESIDENT && res_supported(mp, P.compute) &&
+  if (P.stage_kernel != SSM_STAGE_TILED && res_supported(mp, P.compute) &&
       !(final_here && res_splits_rows(mp, P.compute))) {
     const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
                          P.class_range_start[c];
@@ -1078,6 +1121,9 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (!P->ranges.empty())
     std::memcpy(P->meta_host.data() + P->m_ranges, P->ranges.data(),
                 sizeof(ResRange) * P->ranges.size());
+  if (!P->chain_units.empty())
+    std::memcpy(P->meta_host.data() + P->m_chain, P->chain_units.data(),
+                sizeof(ChainUnit) * P->chain_units.size());
   if (P->launch == SSM_LAUNCH_PERSISTENT) {
     unsigned char* mh = P->meta_host.data();
     if (!P->items.empty())

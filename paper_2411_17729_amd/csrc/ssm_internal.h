@@ -92,6 +92,12 @@ struct ResRange {
   int32_t seq, row0, nrows, reserved;
 };
 
+// Work of one chain-kernel workgroup at stage k: segments seg0 .. seg0 + 7 of
+// sequence seq (one per wave), each T consecutive 16-row blocks of one column.
+struct ChainUnit {
+  int32_t seq, seg0, T, reserved;
+};
+
 // ---- persistent ragged launch ----
 // One row tile of one stage (k >= 0), or of the input projection (k == -1),
 // of one sequence. Items are ordered by stage level.
@@ -233,6 +239,13 @@ hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRan
 // written to xin (kry even) or xout (kry odd); y at once when kry = last + 1.
 hipError_t launch_krylov_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
                              int n_ranges, hipStream_t s);
+// Chain-walking stage kernel (stages with 2^k >= 16; whole state rows per
+// workgroup): BF16 at padded m of 64..256, FP32 at 64 and 128.
+bool chain_supported(int mp, int ct);
+// tail: some sequence of the launch has its last stage here (the forward
+// epilogue or the final-state copy may be due); false selects the lean variant.
+hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const ChainUnit* units,
+                              int n_units, bool tail, hipStream_t s);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);

@@ -11,11 +11,10 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // FP32 -> bfloat16, round to nearest even (NaN stays NaN).
+// FP32 -> BF16, round to nearest even (NaN stays NaN): the conversion
+// instruction of gfx950 (v_cvt_pk_bf16_f32), branch-free.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {

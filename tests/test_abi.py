@@ -70,8 +70,9 @@ def test_workspace_bytes_grows_with_batch(lib):
     n1 = lib.ssm_cascade_workspace_bytes(one, 1, 0, 1, 0, 0, None)
     n2 = lib.ssm_cascade_workspace_bytes(two, 2, 0, 1, 0, 0, None)
     assert 0 < n1 < n2
-    # the second sequence shares the operator: only the state buffers grow
-    assert n2 - n1 <= 2 * 4096 * 64 * 4 + 4096
+    # the second sequence shares the operator: only the state buffers and the
+    # per-sequence launch tables (tiles, row ranges, chain units) grow
+    assert n2 - n1 <= 2 * 4096 * 64 * 4 + 16384
 
 
 def test_prepare_rejects_on_host(lib):
@@ -110,8 +111,14 @@ def test_null_plan_calls(lib):
 def test_tuning_is_validated(lib):
     from paper_2411_17729_amd import binding as B
     arr = (B.ssm_seq_desc * 1)(_desc())
-    for bad in (B.make_tuning(launch=7), B.make_tuning(tile_rows=(0, 100, 0, 0))):
+    for bad in (B.make_tuning(launch=7), B.make_tuning(tile_rows=(0, 100, 0, 0)),
+                B.make_tuning(stage_kernel=4), B.make_tuning(chain_blocks=65),
+                B.make_tuning(chain_blocks=-1)):
         assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(bad)) == 0
+    for sk in (B.SSM_STAGE_RESIDENT, B.SSM_STAGE_CHAIN):  # FP32 only, not FP64 (compute 0)
+        t = B.make_tuning(stage_kernel=sk, chain_blocks=3)
+        assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
+        assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 0, 0, 0, C.byref(t)) == 0
     t = B.make_tuning(tile_rows=(0, 64, 0, 0))  # half of the default 128 for m <= 64
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
     t = B.make_tuning()

@@ -41,9 +41,10 @@ def _oracle_grads(wl, dys, us):
     return acc, dus
 
 
-def _gpu_grads(wl, compute, dys, ckpt_every=0, u_dtype=None):
+def _gpu_grads(wl, compute, dys, ckpt_every=0, u_dtype=None, **plan_kw):
     from paper_2411_17729_amd import cascade as CC
-    plan = CC.plan_for_workload(wl, compute=compute, with_backward=True, ckpt_every=ckpt_every)
+    plan = CC.plan_for_workload(wl, compute=compute, with_backward=True, ckpt_every=ckpt_every,
+                                **plan_kw)
     sd = plan.state_dtype
     u = CC.pack_u(wl, dtype=u_dtype or sd)
     dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in dys]), device="cuda").to(sd)
@@ -65,12 +66,12 @@ def _gpu_grads(wl, compute, dys, ckpt_every=0, u_dtype=None):
     return dul, gs, us, plan
 
 
-def _compare(wl, compute, ckpt_every=0, tol=None, u_dtype=None):
+def _compare(wl, compute, ckpt_every=0, tol=None, u_dtype=None, **plan_kw):
     rng = np.random.default_rng(123)
     dys = wl.dy if wl.dy is not None else [rng.standard_normal((s.L, wl.sets[s.param_set].q)) for s in wl.seqs]
     if compute != "f64":
         dys = [d.astype(np.float32).astype(np.float64) for d in dys]
-    dul, gs, us, _ = _gpu_grads(wl, compute, dys, ckpt_every, u_dtype)
+    dul, gs, us, _ = _gpu_grads(wl, compute, dys, ckpt_every, u_dtype, **plan_kw)
     ref, dus = _oracle_grads(wl, dys, us)
     tol = TOL[compute] if tol is None else tol
     errs = {"u": max(rel_err(a, b) for a, b in zip(dul, dus))}

@@ -1,0 +1,108 @@
+"""The chain-walking stage kernel: against the FP64 oracle, against the
+resident kernel, across segment lengths (bitwise: every block sees the same
+operands in the same order whatever the segmentation), and in the adjoint
+direction through the backward pass."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2411_17729_amd import workloads as W
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+# (m, p, q, L, N): padded sizes 64, 128 and 256; L not a multiple of 16 or of
+# the shifts; stages whose shift exceeds half of L; a sequence shorter than 16;
+# a window 2^(N+1) = 512 shorter than the sequence (truncated sum)
+SPEC = [(256, 8, 8, 3001, 11), (128, 4, 2, 1999, 10), (64, 2, 3, 777, 9), (100, 3, 1, 500, 8),
+        (200, 1, 5, 33, 5), (48, 2, 2, 15, 3), (256, 8, 8, 4096, 11), (64, 2, 2, 2500, 8)]
+
+
+def _workload(seed=21, zero_d=True):
+    rng = np.random.default_rng(seed)
+    sets, seqs = [], []
+    for i, (m, p, q, L, N) in enumerate(SPEC):
+        A, _ = W.hippo_legs(m)
+        D = np.zeros((q, p)) if zero_d else rng.standard_normal((q, p)) / math.sqrt(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, p)) / math.sqrt(m),
+                               rng.standard_normal((q, m)) / math.sqrt(m), D))
+        seqs.append(W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, N, rng.standard_normal((L, p))))
+    return W.Workload("chain", sets, seqs)
+
+
+def _oracle(wl):
+    out = []
+    for s in wl.seqs:
+        ps = wl.sets[s.param_set]
+        Abar, Bbar = O.trapezoid(ps.A, ps.B, s.delta)
+        u = s.u.astype(np.float32).astype(np.float64)
+        if (1 << (s.N + 1)) >= s.L:
+            y, _ = O.recursion(Abar, Bbar, ps.C, ps.D, u)
+        else:
+            y = O.truncated_sum(Abar, Bbar, ps.C, ps.D, u, s.N)
+        out.append(y)
+    return out
+
+
+def _apply(wl, compute, **kw):
+    from paper_2411_17729_amd import cascade as CC
+    plan = CC.plan_for_workload(wl, compute=compute, launch="per_stage", **kw)
+    info = plan.info()
+    u = CC.pack_u(wl, dtype=torch.float32)
+    y = plan.apply(u).clone()
+    torch.cuda.synchronize()
+    plan.close()
+    return y, info
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+@pytest.mark.parametrize("input_stages", [0, -1])
+def test_chain_matches_oracle(compute, input_stages):
+    # D = 0 (y is the state part alone, so its error is not hidden under D u)
+    # and D != 0 (the epilogue's D u term)
+    from paper_2411_17729_amd import cascade as CC
+    tol = 1e-5 if compute == "f32" else 2e-2
+    for zero_d in (True, False):
+        wl = _workload(zero_d=zero_d)
+        y, info = _apply(wl, compute, stage_kernel="chain", input_stages=input_stages)
+        assert info["stage_kernel"] == 3
+        got = CC.unpack_y(wl, y)
+        ref = _oracle(wl)
+        for i in range(len(wl.seqs)):
+            e = rel_err(got[i], ref[i])
+            print(compute, input_stages, "D=0" if zero_d else "D!=0", "seq", i, f"{e:.2e}",
+                  flush=True)
+            assert e <= tol, (i, zero_d, e)
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_chain_segment_lengths_bitwise(compute):
+    wl = _workload(seed=22)
+    ys = [_apply(wl, compute, stage_kernel="chain", chain_blocks=t)[0] for t in (1, 3, 8, 64)]
+    for y in ys[1:]:
+        assert torch.equal(ys[0], y)
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_chain_matches_resident(compute):
+    from paper_2411_17729_amd import cascade as CC
+    wl = _workload(seed=23)
+    yc, ic = _apply(wl, compute, stage_kernel="chain")
+    yr, ir = _apply(wl, compute, stage_kernel="resident")
+    assert (ic["stage_kernel"], ir["stage_kernel"]) == (3, 2)
+    tol = 2e-6 if compute == "f32" else 1e-2
+    for a, b in zip(CC.unpack_y(wl, yc), CC.unpack_y(wl, yr)):
+        assert rel_err(a, b) <= tol
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+@pytest.mark.parametrize("stage_kernel", ["chain", "resident"])
+def test_backward_per_stage_kernels(compute, stage_kernel):
+    # the adjoint walks the columns the other way (reversed shifts)
+    from tests.test_gpu_backward import _compare
+    wl = W.backward(seed=24, batch=3, m=128, L=1500, N=10, p=4, q=4, delta=5e-3)
+    _compare(wl, compute, launch="per_stage", stage_kernel=stage_kernel)
