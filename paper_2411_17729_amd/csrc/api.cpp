@@ -350,19 +350,25 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     P.chain_count[c].assign(ml + 1, 0);
     P.chain_T[c].assign(ml + 1, 0);
     if (P.stage_kernel != SSM_STAGE_CHAIN || !chain_supported(kClassMp[c], (int)compute)) continue;
+    // the chain kernel addresses a sequence's state with 32-bit byte offsets
+    bool fits = true;
+    for (int i : ids) fits = fits && P.seqs[i].L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
+    if (!fits) continue;
     for (int kk = 4; kk <= ml; ++kk) {
       const int64_t sh = (int64_t)1 << kk;
+      // blocks of 16 rows, numbered column by column (column = rows equal mod 2^k
+      // in 16-row groups); each wave takes T consecutive blocks
       int64_t blocks = 0;
       for (int i : ids)
-        if (P.seqs[i].last >= kk) blocks += (P.seqs[i].L + 15) / 16;
+        if (P.seqs[i].last >= kk) blocks += (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
       const int T = tn.chain_blocks > 0 ? tn.chain_blocks
-                                        : (int)std::min<int64_t>(8, std::max<int64_t>(1, blocks / 4096));
+                                        : (int)std::min<int64_t>(8, std::max<int64_t>(1, blocks / 2048));
       P.chain_T[c][kk] = T;
       P.chain_start[c][kk] = (int)P.chain_units.size();
       for (int i : ids) {
         if (P.seqs[i].last < kk) continue;
-        const int64_t ni = (P.seqs[i].L + sh - 1) / sh;
-        const int64_t nseg = (sh / 16) * ((ni + T - 1) / T);
+        const int64_t nflat = (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
+        const int64_t nseg = (nflat + T - 1) / T;
         for (int64_t g0 = 0; g0 < nseg; g0 += 8)
           P.chain_units.push_back(ChainUnit{i, (int32_t)g0, T, 0});
       }

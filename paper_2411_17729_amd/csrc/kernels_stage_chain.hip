@@ -79,18 +79,18 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int j = lane & 15, g = lane >> 4;
-  const int64_t L = sq.L;
-  const int64_t s = (int64_t)1 << k;
-  const int64_t ncol = s >> 4;
-  const int64_t ni = (L + s - 1) / s;  // blocks per column
+  // 32-bit indices: the host keeps L MP 4 <= 2^31
+  const int L = (int)sq.L;
+  const int ncol = 1 << (k - 4);
+  const int ni = (L + (1 << k) - 1) >> k;  // blocks per column
+  // Blocks are numbered column by column, f = col ni + i; a wave's segment is
+  // T consecutive numbers, so it may run on into the next column (there the
+  // first block has no partner in registers and loads none).
+  const int nflat = ncol * ni;
   const int T = un.T;
-  const int64_t nsegc = (ni + T - 1) / T;
-  const int64_t seg = (int64_t)un.seg0 + wave;
-  if (seg >= ncol * nsegc) return;
-  const int64_t col = seg % ncol;
-  const int64_t i0 = (seg / ncol) * T;
-  const int64_t i1 = i0 + T < ni ? i0 + T : ni;
-  const int64_t rbase = col * 16 + j;
+  const int f0 = (un.seg0 + wave) * T;
+  if (f0 >= nflat) return;
+  const int f1 = f0 + T < nflat ? f0 + T : nflat;
 
   // The sequence's state rows are addressed through buffer resources whose
   // range is exactly its L x MP block: the hardware range check returns zeros
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   // l >= L and partner blocks before the start need no masking. Offsets are
   // 32-bit (the host keeps L MP 4 <= 2^31); an absent partner block is given
   // the offset 2^31, which is out of range.
-  const uint32_t nrec = (uint32_t)(L * MP * (int64_t)sizeof(X));
+  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * sizeof(X));
   const X* xin = reinterpret_cast<const X*>(first && prm.xin_first ? prm.xin_first : prm.xin) +
                  sq.x_off;
   const auto rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<X*>(xin), (short)0, (int)nrec,
@@ -109,12 +109,34 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const auto rfin = __builtin_amdgcn_make_buffer_rsrc(
       fin ? reinterpret_cast<X*>(prm.xfinal) + sq.x_off : reinterpret_cast<X*>(prm.xout),
       (short)0, fin ? (int)nrec : 0, kBufferWord3);
-  const uint32_t lane_off = (uint32_t)(rbase * MP + 4 * g) * (uint32_t)sizeof(X);
-  const uint32_t blk_off = (uint32_t)(s * MP) * (uint32_t)sizeof(X);  // one block step
-
-  auto block_off = [&](int64_t i) -> uint32_t {
-    return (i >= 0 && i < ni) ? lane_off + (uint32_t)i * blk_off : 0x80000000u;
+  const uint32_t lane_off = (uint32_t)(j * MP + 4 * g) * (uint32_t)sizeof(X);
+  // The current block f sits at column fc, step fi; neighbours are found by
+  // stepping (no division per block).
+  int f = adj ? f1 - 1 : f0;
+  int fc = __builtin_amdgcn_readfirstlane(f / ni);  // uniform: keep in scalar registers
+  int fi = f - fc * ni;
+  // first time row of the block d numbers after the current one
+  auto row_at = [&](int d) -> int {  // |d| <= 2
+    int c = fc, i = fi + d;
+    if (ni == 1) {
+      c += d;
+      i = 0;
+    } else if (i >= ni) {  // ni >= 2: one wrap at most
+      i -= ni;
+      ++c;
+    } else if (i < 0) {
+      i += ni;
+      --c;
+    }
+    return (i << k) + c * 16;
   };
+  // byte offset of this lane's piece of block f + d (out of range outside lo..hi-1)
+  auto block_off = [&](int d, int lo, int hi) -> uint32_t {
+    return (f + d >= lo && f + d < hi) ? lane_off + (uint32_t)row_at(d) * (uint32_t)(MP * sizeof(X))
+                                       : 0x80000000u;
+  };
+  // does the current block have a partner block (i >= 1 forward, i <= ni - 2 adjoint)?
+  auto has_partner = [&]() -> bool { return adj ? fi + 1 < ni : fi > 0; };
   // stage input of this lane's row of block i, accumulator layout
   auto load_block = [&](uint32_t off, f32x4(&v)[NB]) {
 #pragma unroll
@@ -124,40 +146,38 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   // shifted operand for the next block: BF16 operand pieces, or FP32 as is
   constexpr int NPV = CT == DT_BF16 ? MP / 32 : NB;
   using PV = typename std::conditional<CT == DT_BF16, bf16x8, f32x4>::type;
-  auto pack = [&](const f32x4(&v)[NB], PV(&pv)[NPV]) {
+  // (zeros when `keep` is false: the next block starts a column and has no partner)
+  auto pack = [&](const f32x4(&v)[NB], bool keep, PV(&pv)[NPV]) {
     if constexpr (CT == DT_BF16) {
 #pragma unroll
       for (int c = 0; c < MP / 32; ++c)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          pv[c][e] = (__bf16)v[2 * c][e];  // round to nearest even
-          pv[c][4 + e] = (__bf16)v[2 * c + 1][e];
+          pv[c][e] = (__bf16)(keep ? v[2 * c][e] : 0.f);  // round to nearest even
+          pv[c][4 + e] = (__bf16)(keep ? v[2 * c + 1][e] : 0.f);
         }
     } else {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) pv[nb] = v[nb];
+      for (int nb = 0; nb < NB; ++nb) pv[nb] = keep ? v[nb] : f32x4{0.f, 0.f, 0.f, 0.f};
     }
   };
 
-  const int64_t step = adj ? -1 : 1;
-  int64_t i = adj ? i1 - 1 : i0;
-  bool have = adj ? i + 1 < ni : i > 0;  // does the first block have a partner block?
-
-  // Blocks are processed with two register sets: while block i is computed
-  // in one, block i + 1 is already in flight in the other. Per block: keep its
-  // input as the next shifted operand (npv); then for each group of four
-  // accumulator pieces add P_k times the shifted rows, store the group and
-  // start loading the same group of block i + 2 into the freed registers.
-  // (A TAIL launch loads block i + 2 after the output epilogue, which needs
-  // the whole block.) The loop is unrolled by two so that the register sets
-  // and the operand sets swap roles without copies.
+  const int step = adj ? -1 : 1;
+  // One block, its rows held in x: keep the block's input as the next block's
+  // shifted operand (npv), then for each group of four accumulator pieces add
+  // P_k times the shifted rows, store the group and load the same group of
+  // the next block into the freed registers, so that the next block arrives
+  // while this one is computed. (A TAIL launch loads the next block after the
+  // output epilogue, which needs the whole block.) The loop is unrolled by two
+  // so that the operand sets swap roles without copies.
   constexpr int G = 4;
-  const int64_t n = i1 - i0;
-  int64_t t = 0;  // blocks done
-  auto body = [&](f32x4(&x)[NB], const PV(&pv)[NPV], PV(&npv)[NPV]) {
-    const uint32_t off = block_off(i);
-    const uint32_t offn = t + 2 < n ? block_off(i + 2 * step) : 0x80000000u;  // nothing past the segment
-    pack(x, npv);
+  const int n = f1 - f0;
+  int t = 0;  // blocks done
+  f32x4 x[NB];
+  auto body = [&](const PV(&pv)[NPV], PV(&npv)[NPV]) {
+    const uint32_t off = block_off(0, 0, nflat);
+    const uint32_t offn = block_off(step, f0, f1);  // nothing past the segment
+    pack(x, adj ? fi > 0 : fi + 1 < ni, npv);  // partner of the next block, if it has one
     // the LDS operand offset is passed through an empty asm so that the
     // compiler re-reads the power fragments each block instead of hoisting
     // them out of the loop into registers
@@ -165,7 +185,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     asm volatile("" : "+v"(lbase));
 #pragma unroll
     for (int n0 = 0; n0 < NB; n0 += G) {
-      if (have) {
+      {  // a block without a partner gets pv = 0
         if constexpr (CT == DT_BF16) {
           // power fragments read one MFMA step ahead of their use
           bf16x8 fa[2][G];
@@ -208,7 +228,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     }
     if constexpr (TAIL) {
       if (epi) {  // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
-        const int64_t l = i * s + rbase;
+        const int64_t l = row_at(0) + j;
         res_epilogue<NB>(x, MP, l, l < L,
                          reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout),
                          reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat),
@@ -218,21 +238,26 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       }
       load_block(offn, x);
     }
-    have = true;
-    i += step;
+    f += step;
+    fi += step;
+    if (fi == ni) {
+      fi = 0;
+      ++fc;
+    } else if (fi < 0) {
+      fi = ni - 1;
+      --fc;
+    }
     ++t;
   };
 
-  f32x4 xa[NB], xb[NB];
   PV pa[NPV], pb[NPV];
-  load_block(block_off(i - step), xa);  // partner of the first block
-  pack(xa, pa);
-  load_block(block_off(i), xa);
-  load_block(n > 1 ? block_off(i + step) : 0x80000000u, xb);
-  while (t < n) {  // unrolled by two: the register and operand sets swap roles
-    body(xa, pa, pb);
+  load_block(has_partner() ? block_off(-step, 0, nflat) : 0x80000000u, x);  // partner (or zeros)
+  pack(x, true, pa);
+  load_block(block_off(0, f0, f1), x);
+  while (t < n) {  // unrolled by two: the operand sets swap roles
+    body(pa, pb);
     if (t >= n) break;
-    body(xb, pb, pa);
+    body(pb, pa);
   }
 }
 

@@ -93,7 +93,8 @@ struct ResRange {
 };
 
 // Work of one chain-kernel workgroup at stage k: segments seg0 .. seg0 + 7 of
-// sequence seq (one per wave), each T consecutive 16-row blocks of one column.
+// sequence seq (one per wave), each T consecutive 16-row blocks in the
+// column-by-column numbering of the stage.
 struct ChainUnit {
   int32_t seq, seg0, T, reserved;
 };
