@@ -111,6 +111,12 @@ def test_hippo_batched_full_size_fp32():
     _check(wl, "f32")
 
 
+def test_hippo_batched_full_size_bf16():
+    # the bench launch configuration: BF16 operands, FP32 u, all 16 sequences in full
+    wl = W.batched(seed=0)
+    _check(wl, "bf16")
+
+
 def test_hippo_batched_full_size_bf16_input():
     wl = W.batched(seed=0, batch=4)
     _check(wl, "bf16", u_dtype=torch.bfloat16)
