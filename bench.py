@@ -42,6 +42,10 @@ def _args():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f32"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "backward", "ragged"],
+                    help="batched: 16 x L=16384, m=256 forward (the headline line); backward: "
+                         "8 x L=8192, m=128 FP32 gradients; ragged: 256 sequences of uneven L and m, "
+                         "BF16, one persistent launch replayed as a HIP graph, forward and backward")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-compare", action="store_true",
@@ -89,6 +93,10 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     B.load()
+    if args.workload == "backward":
+        return bench_backward(args)
+    if args.workload == "ragged":
+        return bench_ragged(args)
 
     wl = W.batched(seed=args.seed)
     s0 = wl.seqs[0]
@@ -227,6 +235,189 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = n * 4
 
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn, steps, warm, stream=None):
+    """Average milliseconds of fn() over `steps` calls after `warm` untimed ones."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def _stage_flops(wl, ks=None):
+    """Sum over sequences and stages of 2 m^2 (L - 2^k) (rows with a partner)."""
+    tot = 0.0
+    for s in wl.seqs:
+        m = wl.sets[s.param_set].m
+        last = min(s.N, (s.L - 1).bit_length() - 1) if s.L > 1 else -1
+        for k in range(last + 1):
+            if ks is None or k in ks:
+                tot += 2.0 * m * m * max(0, s.L - (1 << k))
+    return tot
+
+
+def bench_backward(args):
+    """Gradients of sum(dy * y) for 8 sequences x L = 8192, m = 128 (FP32)."""
+    import numpy as np
+    import torch
+    from paper_2411_17729_amd import binding as B
+    from paper_2411_17729_amd import cascade as CC
+    from paper_2411_17729_amd import workloads as W
+
+    wl = W.backward(seed=args.seed)
+    ps = wl.sets[0]
+    s0 = wl.seqs[0]
+    plan = CC.plan_for_workload(wl, compute="f32", with_backward=True)
+    u = CC.pack_u(wl, dtype=torch.float32)
+    dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in wl.dy]), device="cuda").float()
+    K, Wm = args.steps, args.warmup
+    ms = _timed(lambda: plan.backward(u, dy), K, Wm)
+    plan.timing(True)
+    du, grads = plan.backward(u, dy)
+    torch.cuda.synchronize()
+    plan.timing(False)
+    n_adj, t_adj = plan.timing_read(B.TIMING_ADJOINT)
+    n_fwd, t_fwd = plan.timing_read(B.TIMING_STAGE)
+    n_red, t_red = plan.timing_read(B.TIMING_REDUCE)
+    flops_adj = _stage_flops(wl)  # the adjoint runs every stage once
+    tf = flops_adj / (t_adj * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(wl.total_steps / (ms * 1e-3), 1), "unit": "output steps/s",
+        "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"backward_hippo_m{ps.m}_p{ps.p}_q{ps.q}_B{len(wl.seqs)}_L{s0.L}_N{s0.N}",
+                   "step": "ssm_cascade_backward: forward with checkpoints, recompute, adjoint "
+                           "stages, gradient reductions, FP64 squaring and trapezoid adjoints",
+                   "delta": s0.delta, "seed": args.seed},
+        "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK["f32_TFLOPs"],
+                     "unit": "TFLOP/s", "frac": round(tf / PEAK["f32_TFLOPs"], 4), "traffic": None,
+                     "kernel": "adjoint stages", "launches_timed": n_adj,
+                     "avg_launch_ms": round(t_adj / max(n_adj, 1), 5)},
+        "breakdown_ms": {"forward_and_recompute_stages": round(t_fwd, 4), "adjoint_stages": round(t_adj, 4),
+                         "reductions": round(t_red, 4), "launches": [n_fwd, n_adj, n_red]},
+    }
+    if not args.no_cpu:
+        import time
+        import oracle as O
+        from threadpoolctl import threadpool_limits
+        t_start = time.perf_counter()
+        acc = {k: 0.0 for k in "ABCD"}
+        dus = []
+        with threadpool_limits(limits=1):
+            for s, d in zip(wl.seqs, wl.dy):
+                g = O.grads_full(ps.A, ps.B, ps.C, ps.D, s.delta, s.u.astype(np.float32).astype(np.float64),
+                                 d.astype(np.float32).astype(np.float64), s.N)
+                for k in "ABCD":
+                    acc[k] = acc[k] + g[k]
+                dus.append(g["u"])
+        t_cpu = time.perf_counter() - t_start
+        out["cpu_baseline"] = {"value": round(wl.total_steps / t_cpu, 1), "unit": "output steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"all {len(wl.seqs)} sequences, oracle.grads_full (BPTT + "
+                                         f"trapezoid adjoint), numpy FP64, 1 BLAS thread, {t_cpu:.1f} s"}
+        du_h = du.double().cpu().numpy()
+        rel = {"du": float(np.linalg.norm(du_h - np.concatenate([x.reshape(-1) for x in dus])) /
+                           np.linalg.norm(np.concatenate([x.reshape(-1) for x in dus])))}
+        for j, k in enumerate("ABCD"):
+            gk = grads[0][j].cpu().numpy()
+            rel[f"d{k}"] = float(np.linalg.norm(gk - acc[k]) / np.linalg.norm(acc[k]))
+        out["rel_err_vs_fp64"] = {"f32": {k: float(f"{v:.3e}") for k, v in rel.items()}}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_ragged(args):
+    """256 sequences of uneven L and m (BF16): one persistent launch per apply,
+    captured in a HIP graph and replayed; the backward graph likewise."""
+    import numpy as np
+    import torch
+    from paper_2411_17729_amd import binding as B
+    from paper_2411_17729_amd import cascade as CC
+    from paper_2411_17729_amd import workloads as W
+
+    wl = W.ragged(seed=args.seed)
+    plan = CC.plan_for_workload(wl, compute="bf16", with_backward=True)
+    info = plan.info()
+    u = CC.pack_u(wl, dtype=torch.float32)
+    dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in wl.dy]), device="cuda").float()
+    y = torch.empty(plan.layout.y_numel, dtype=torch.float32, device="cuda")
+    du = torch.empty_like(u)
+    gbuf = torch.empty(B.ssm_cascade_param_grad_numel(plan.plan), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g_fwd = plan.graph_apply(u, y, stream)
+    g_bwd = plan.graph_backward(u, dy, du, gbuf, stream)
+    K, Wm = args.steps, args.warmup
+    with torch.cuda.stream(stream):
+        ms_f = _timed(lambda: CC.CascadePlan.graph_launch(g_fwd, stream), K, Wm, stream)
+        ms_b = _timed(lambda: CC.CascadePlan.graph_launch(g_bwd, stream), max(2, K // 5), 1, stream)
+    # the persistent kernel alone (eager launch with event timing)
+    plan.timing(True)
+    plan.apply(u, out=y)
+    torch.cuda.synchronize()
+    plan.timing(False)
+    n_k, t_k = plan.timing_read(B.TIMING_STAGE)
+    CC.CascadePlan.graph_destroy(g_fwd)
+    CC.CascadePlan.graph_destroy(g_bwd)
+    gbps = info["stage_bytes"] / (t_k / max(n_k, 1) * 1e-3) / 1e9
+    ms_list = sorted({wl.sets[s.param_set].m for s in wl.seqs})
+    out = {
+        "metric": METRIC, "value": round(wl.total_steps / (ms_f * 1e-3), 1), "unit": "output steps/s",
+        "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": round(ms_f, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"ragged_{len(wl.seqs)}seq_L{min(s.L for s in wl.seqs)}-{max(s.L for s in wl.seqs)}"
+                               f"_m{'-'.join(map(str, ms_list))}_p4_q4",
+                   "total_steps": wl.total_steps, "launch": "persistent" if info["launch"] == 2 else "per-stage",
+                   "graph": True, "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                     "frac": round(gbps / PEAK["hbm_GBps"], 4), "traffic": None,
+                     "kernel": "k_persistent" if info["launch"] == 2 else "stage kernels",
+                     "launches_timed": n_k, "avg_launch_ms": round(t_k / max(n_k, 1), 5),
+                     "algorithmic_bytes_per_launch": round(info["stage_bytes"] / max(n_k, 1))},
+        "backward": {"value": round(wl.total_steps / (ms_b * 1e-3), 1), "ms_per_step": round(ms_b, 4),
+                     "graph": True},
+    }
+    if not args.no_cpu:
+        import time
+        import oracle as O
+        from threadpoolctl import threadpool_limits
+        yh = CC.unpack_y(wl, y)
+        order = sorted(range(len(wl.seqs)), key=lambda i: wl.seqs[i].L)
+        t_start = time.perf_counter()
+        done, errs = [], []
+        with threadpool_limits(limits=1):
+            for i in order[::17]:  # a spread of lengths and sizes
+                s = wl.seqs[i]
+                ps = wl.sets[s.param_set]
+                Abar, Bbar = O.trapezoid(ps.A, ps.B, s.delta)
+                uq = s.u.astype(np.float32).astype(np.float64)
+                ref, _ = O.recursion(Abar, Bbar, ps.C, ps.D, uq)
+                done.append(i)
+                st = yh[i] - uq @ ps.D.T
+                sr = ref - uq @ ps.D.T
+                errs.append(float(np.linalg.norm(st - sr) / np.linalg.norm(sr)))
+                if time.perf_counter() - t_start >= args.cpu_seconds:
+                    break
+        t_cpu = time.perf_counter() - t_start
+        steps_cpu = sum(wl.seqs[i].L for i in done)
+        out["cpu_baseline"] = {"value": round(steps_cpu / t_cpu, 1), "unit": "output steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{len(done)} of {len(wl.seqs)} sequences in full (every 17th by "
+                                         f"length), oracle.trapezoid + oracle.recursion, numpy FP64, "
+                                         f"1 BLAS thread, {t_cpu:.1f} s"}
+        out["rel_err_vs_fp64"] = {"bf16": {"state_max": float(f"{max(errs):.3e}")}}
+        out["rel_err_sample"] = f"sequences {done}"
+    plan.close()
     print(json.dumps(out), flush=True)
 
 
