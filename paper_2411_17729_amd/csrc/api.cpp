@@ -132,6 +132,11 @@ struct ssm_plan_s {
   int64_t n_counters = 0;
   int persistent_grid = 0;
   size_t m_items = 0, m_cntoff = 0, m_ntiles = 0, m_counters = 0;
+  // persistent launch on the resident-power code (chain, resident and input-pass items)
+  bool persist_res = false;
+  std::vector<RItem> ritems;
+  std::vector<int32_t> cnt_target;
+  size_t m_ritems = 0, m_cnttarget = 0, persist_lds = 0;
   // backward
   int n_ckpt = 0, n_seg = 0, chunk_rows = 256;
   int64_t sum_x = 0;  // elements of one state buffer (all sequences)
@@ -388,19 +393,32 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
                    ? ((classes > 1 || lmin != lmax) ? SSM_LAUNCH_PERSISTENT : SSM_LAUNCH_PER_STAGE)
                    : tn.launch;
   }
-  // leading stages folded into the input pass (resident kernel, per-stage launches)
+  // The persistent launch runs the resident-power code when every operator
+  // allows it: chain-capable sizes, at least one stage foldable into the input
+  // pass (2p <= padded m) and sequences within 32-bit chain offsets.
+  P.persist_res = false;
+  if (P.launch == SSM_LAUNCH_PERSISTENT && P.stage_kernel != SSM_STAGE_TILED &&
+      tn.input_stages >= 0) {
+    bool ok = true;
+    for (const OpDev& o : P.ops) ok = ok && chain_supported(o.mp, (int)compute) && 2 * o.p <= o.mp;
+    for (const SeqDev& sq : P.seqs)
+      ok = ok && sq.L * (int64_t)P.ops[sq.op].mp * 4 <= ((int64_t)1 << 31);
+    P.persist_res = ok;
+  }
+  // leading stages folded into the input pass (resident kernel, per-stage
+  // launches or the resident persistent launch)
   P.max_kry = 0;
   for (OpDev& o : P.ops) {
     o.kry = 0;
     o.kdim = 0;
     o.kw = o.kc = -1;
-    if (tn.input_stages < 0 || P.launch != SSM_LAUNCH_PER_STAGE ||
+    if (tn.input_stages < 0 || !(P.launch == SSM_LAUNCH_PER_STAGE || P.persist_res) ||
         P.stage_kernel == SSM_STAGE_TILED || !res_supported(o.mp, P.compute))
       continue;
     int j = 0;
     while (((int64_t)o.p << (j + 1)) <= o.mp && j + 1 <= o.N + 1) ++j;
     if (tn.input_stages > 0) j = std::min(j, tn.input_stages);
-    if (j >= 2) {
+    if (j >= (P.persist_res ? 1 : 2)) {  // the persistent items start with an input pass
       o.kry = j;
       o.kdim = o.p << j;
     }
@@ -413,7 +431,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     const OpDev& o = P.ops[sq.op];
     int kr = std::min(o.kry, sq.last + 1);
     if (kr == sq.last + 1 && res_splits_rows(o.mp, P.compute)) kr = sq.last;
-    if (kr < 2) kr = 0;
+    if (kr < (P.persist_res ? 1 : 2)) kr = 0;
     sq.kry = kr;
     P.max_kry = std::max(P.max_kry, kr);
     const int c = class_of(o.mp);
@@ -426,9 +444,67 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // persistent work items, level by level (projection = level -1), longer
   // sequences first inside a level; default tile heights
   P.items.clear();
+  P.ritems.clear();
+  P.cnt_target.clear();
   P.cnt_off.assign(n_seq, 0);
   P.ntiles.assign(n_seq, 0);
-  if (P.launch == SSM_LAUNCH_PERSISTENT) {
+  if (P.launch == SSM_LAUNCH_PERSISTENT && P.persist_res) {
+    // levels kry - 1 (input pass) .. last per sequence, one counter each
+    std::vector<int> order(n_seq);
+    for (int i = 0; i < n_seq; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
+    int64_t cnt = 1;  // counter 0 hands out tickets
+    int maxl = 0;
+    for (int i = 0; i < n_seq; ++i) {
+      P.cnt_off[i] = (int32_t)cnt;
+      cnt += P.seqs[i].last - P.seqs[i].kry + 2;
+      maxl = std::max(maxl, P.seqs[i].last);
+    }
+    P.n_counters = cnt;
+    P.cnt_target.assign((size_t)cnt, 0);
+    const int64_t R = 1024;  // rows per input-pass or resident-stage item
+    for (int lev = -1; lev <= maxl; ++lev) {
+      int64_t blocks = 0;  // chain blocks at this level, for the segment length
+      if (lev >= 4)
+        for (int i = 0; i < n_seq; ++i) {
+          const SeqDev& sq = P.seqs[i];
+          if (lev >= sq.kry && lev <= sq.last)
+            blocks += ((int64_t)1 << (lev - 4)) * ((sq.L + ((int64_t)1 << lev) - 1) >> lev);
+        }
+      const int T = tn.chain_blocks > 0 ? tn.chain_blocks
+                                        : (int)std::min<int64_t>(8, std::max<int64_t>(1, blocks / 2048));
+      for (int i : order) {
+        const SeqDev& sq = P.seqs[i];
+        if (lev < sq.kry - 1 || lev > sq.last) continue;
+        int32_t& target = P.cnt_target[P.cnt_off[i] + (lev - (sq.kry - 1))];
+        if (lev == sq.kry - 1) {
+          for (int64_t r0 = 0; r0 < sq.L; r0 += R) {
+            P.ritems.push_back(RItem{i, -1, RI_INPUT, (int32_t)r0,
+                                     (int32_t)std::min<int64_t>(R, sq.L - r0), lev, 0, 0});
+            ++target;
+          }
+        } else if (lev >= 4) {
+          const int64_t sh = (int64_t)1 << lev;
+          const int64_t nflat = (sh / 16) * ((sq.L + sh - 1) / sh);
+          const int64_t nseg = (nflat + T - 1) / T;
+          for (int64_t g0 = 0; g0 < nseg; g0 += 8) {
+            P.ritems.push_back(RItem{i, lev, RI_CHAIN, (int32_t)g0, T, lev, lev == sq.last ? 1 : 0, 0});
+            ++target;
+          }
+        } else {
+          for (int64_t r0 = 0; r0 < sq.L; r0 += R) {
+            P.ritems.push_back(RItem{i, lev, RI_RES, (int32_t)r0,
+                                     (int32_t)std::min<int64_t>(R, sq.L - r0), lev, 0, 0});
+            ++target;
+          }
+        }
+      }
+    }
+    int max_mp = 32;
+    for (const OpDev& o : P.ops) max_mp = std::max(max_mp, o.mp);
+    P.persist_lds = persist_res_lds((int)compute, max_mp);
+  } else if (P.launch == SSM_LAUNCH_PERSISTENT) {
     std::vector<int> order(n_seq);
     for (int i = 0; i < n_seq; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -592,6 +668,10 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   P.m_chain = off;
   off = align_up(off + sizeof(ChainUnit) * std::max<size_t>(1, P.chain_units.size()));
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
+    P.m_ritems = off;
+    off = align_up(off + sizeof(RItem) * std::max<size_t>(1, P.ritems.size()));
+    P.m_cnttarget = off;
+    off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, P.cnt_target.size()));
     P.m_items = off;
     off = align_up(off + sizeof(PItem) * std::max<size_t>(1, P.items.size()));
     P.m_cntoff = off;
@@ -1134,6 +1214,10 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     unsigned char* mh = P->meta_host.data();
     if (!P->items.empty())
       std::memcpy(mh + P->m_items, P->items.data(), sizeof(PItem) * P->items.size());
+    if (!P->ritems.empty())
+      std::memcpy(mh + P->m_ritems, P->ritems.data(), sizeof(RItem) * P->ritems.size());
+    if (!P->cnt_target.empty())
+      std::memcpy(mh + P->m_cnttarget, P->cnt_target.data(), sizeof(int32_t) * P->cnt_target.size());
     std::memcpy(mh + P->m_cntoff, P->cnt_off.data(), sizeof(int32_t) * P->cnt_off.size());
     std::memcpy(mh + P->m_ntiles, P->ntiles.data(), sizeof(int32_t) * P->ntiles.size());
     int dev = 0, ncu = 0;
@@ -1141,8 +1225,12 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         ncu <= 0)
       ncu = 256;
-    const int64_t g = (int64_t)persistent_blocks_per_cu(P->compute) * ncu;
-    P->persistent_grid = (int)std::min<int64_t>(g, (int64_t)P->items.size());
+    if (P->persist_res) {  // one workgroup of 8 waves per compute unit (LDS and registers)
+      P->persistent_grid = (int)std::min<int64_t>(ncu, (int64_t)P->ritems.size());
+    } else {
+      const int64_t g = (int64_t)persistent_blocks_per_cu(P->compute) * ncu;
+      P->persistent_grid = (int)std::min<int64_t>(g, (int64_t)P->items.size());
+    }
   }
   if (P->with_backward) {
     plan_backward_jobs(*P);
@@ -1234,6 +1322,30 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
   ssm_plan_s& P = *plan;
   ssm_status st = check_io(P, u, u_dtype, u_numel, y, y_numel, "y");
   if (st != SSM_OK) return st;
+  if (P.launch == SSM_LAUNCH_PERSISTENT && P.persist_res) {
+    unsigned char* meta = P.ws + P.r_meta.off;
+    RPersistParams pp{};
+    pp.base = base_params(P, 0);
+    pp.base.tiles = nullptr;
+    pp.base.src = u;
+    pp.base.src_dtype = (int)u_dtype;
+    pp.base.dst = y;
+    pp.base.flags = SF_EPILOGUE;
+    pp.items = reinterpret_cast<const RItem*>(meta + P.m_ritems);
+    pp.n_items = (int32_t)P.ritems.size();
+    pp.counters = reinterpret_cast<int32_t*>(meta + P.m_counters);
+    pp.cnt_off = reinterpret_cast<const int32_t*>(meta + P.m_cntoff);
+    pp.cnt_target = reinterpret_cast<const int32_t*>(meta + P.m_cnttarget);
+    pp.x0 = P.ws + P.r_x0.off;
+    pp.x1 = P.ws + P.r_x1.off;
+    hipError_t e = launch_zero_i32(pp.counters, P.n_counters, stream);
+    if (e != hipSuccess) return hip_fail(e, "counter reset launch");
+    TimedLaunch tl(P, stream, 0);
+    e = launch_persist_res(P.compute, pp, P.persistent_grid, P.persist_lds, stream);
+    if (e != hipSuccess) return hip_fail(e, "persistent launch");
+    tl.done();
+    return SSM_OK;
+  }
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
     unsigned char* meta = P.ws + P.r_meta.off;
     PersistParams pp{};
@@ -1564,11 +1676,14 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->stage_bytes = plan->stage_bytes;
   info->stage_launches = plan->stage_launches;
   info->launch = plan->launch;
-  info->stage_kernel = plan->stage_kernel;
+  // the tiled kernel runs the items of a persistent launch unless the resident items do
+  info->stage_kernel = plan->launch == SSM_LAUNCH_PERSISTENT && !plan->persist_res
+                           ? (int32_t)SSM_STAGE_TILED
+                           : plan->stage_kernel;
   info->input_stages = plan->max_kry;
   for (int c = 0; c < 4; ++c) info->tile_rows[c] = plan->class_bm[c];
   info->persistent_grid = plan->persistent_grid;
-  info->persistent_items = (int64_t)plan->items.size();
+  info->persistent_items = (int64_t)(plan->persist_res ? plan->ritems.size() : plan->items.size());
   return SSM_OK;
 }
 

@@ -363,10 +363,12 @@ __global__ __launch_bounds__(256, 1) void k_persistent(PersistParams pp) {
     const PItem w = pp.items[it];
     if (w.k >= 0) {
       if (threadIdx.x == 0) {
+        // relaxed device-scope spin (bypasses the caches), then one acquire fence
         const int* c = pp.counters + pp.cnt_off[w.seq] + w.k;  // level k-1
         const int target = pp.ntiles[w.seq];
-        while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target)
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
           __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
     }
@@ -391,9 +393,11 @@ __global__ __launch_bounds__(256, 1) void k_persistent(PersistParams pp) {
         default: stage_tile<256, CT>(prm, t, smem); break;
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this item's rows, visible device-wide
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(pp.counters + pp.cnt_off[w.seq] + w.k + 1, 1);
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(pp.counters + pp.cnt_off[w.seq] + w.k + 1, 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -118,6 +118,28 @@ struct PersistParams {
   void* x1;
 };
 
+// ---- persistent launch on the resident-power kernels ----
+// One work item: the input pass over rows [a, a + b) (kind RI_INPUT, which
+// completes level kry - 1 of its sequence), a resident-power stage over rows
+// [a, a + b) (RI_RES), or a chain unit with first segment a and b blocks per
+// segment (RI_CHAIN). An item of level v waits for every item of level v - 1
+// of the same sequence. Items are ordered by level.
+enum { RI_INPUT = 0, RI_RES = 1, RI_CHAIN = 2 };
+struct RItem {
+  int32_t seq, k, kind, a, b, level, tail, reserved;
+};
+struct RPersistParams {
+  StageParams base;            // seqs, ops, P, small, src, dst, src_dtype, flags
+  const RItem* items;
+  int32_t n_items;
+  int32_t reserved;
+  int32_t* counters;           // [0]: ticket counter; then per sequence and level
+  const int32_t* cnt_off;      // per sequence: counter of its level kry - 1
+  const int32_t* cnt_target;   // per counter: items of that (sequence, level)
+  void* x0;
+  void* x1;
+};
+
 // ---- backward ----
 // A chunk of rows of one sequence for the outer-product reductions.
 struct RedChunk {
@@ -252,6 +274,11 @@ hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const Chai
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
 // One persistent launch that runs every item of the plan's forward pass.
 hipError_t launch_persistent(int ct, const PersistParams& pp, int grid, hipStream_t s);
+// Persistent launch whose items run the chain, resident and input-pass code
+// (BF16 at padded m 64..256, FP32 at 64 and 128); lds: dynamic LDS bytes for
+// the largest class present (persist_res_lds).
+size_t persist_res_lds(int ct, int max_mp);
+hipError_t launch_persist_res(int ct, const RPersistParams& pp, int grid, size_t lds, hipStream_t s);
 // Workgroups of the persistent kernel that fit on one compute unit.
 int persistent_blocks_per_cu(int ct);
 

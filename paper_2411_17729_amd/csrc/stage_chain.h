@@ -1,0 +1,265 @@
+// Chain walk of one stage (device code shared by the per-stage kernel and the
+// persistent launch): 16-row blocks spaced by the shift.
+//
+// Stage k couples the rows l and l - 2^k (§3: x_l <- x_l + P_k x_{l-2^k}; the
+// adjoint g_l <- g_l + P_k^T g_{l+2^k}). For 2^k >= 16 the time rows of a
+// sequence fall into columns of 16-row blocks: block i of column c holds rows
+// i 2^k + 16 c + j, j < 16, and the shifted operand of block i is the stage
+// input of block i - 1 of the same column (block i + 1 for the adjoint). Blocks
+// are numbered column by column and a wave takes a segment of T consecutive
+// numbers; it keeps each block's input rows in registers as the shifted
+// operand of the next block, so every state row is read once per stage (plus
+// one extra block per segment) rather than twice as in k_stage_res.
+//
+// The power is resident in LDS as in k_stage_res. The shifted operand now
+// arrives in the accumulator layout (a lane holds entries 16 nb + 4 g + v of
+// its time row), so the contraction index of each MFMA step is assigned to
+// match: for BF16, operand slot 8 g + 4 h + e of step c is state entry
+// 16 (2c + h) + 4 g + e, and the LDS copy of the power has its columns
+// permuted the same way; for FP32, step (a, t) contracts entry 16 a + 4 g + t,
+// which is already the layout.
+#pragma once
+#include <type_traits>
+
+#include "stage_res.h"
+
+namespace ssmc {
+
+// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data
+// format, no swizzle), as used for untyped buffer loads and stores.
+constexpr int kBufferWord3 = 0x00020000;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// TAIL: some sequence of the launch ends at this stage (output epilogue or a
+// copy of the final state may be due); otherwise the lean variant runs, which
+// only stores the stage output.
+template <int MP, int CT, bool TAIL>
+__device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUnit un,
+                                           unsigned char* smem_chain) {
+  using C = ResCfg<MP, CT>;
+  static_assert(C::NS == 1, "a chain walk needs whole state rows in one workgroup");
+  using X = float;
+  using Op = typename C::Op;
+  constexpr int NB = C::NB, SP = C::SP;
+  Op* Ps = reinterpret_cast<Op*>(smem_chain);
+
+  const SeqDev sq = prm.seqs[un.seq];
+  const OpDev o = prm.ops[sq.op];
+  const int k = prm.k;
+  if (k > sq.last) return;
+  if (prm.skip_kry && k < sq.kry) return;
+  const bool adj = prm.adjoint != 0;
+  const bool first = adj ? k == sq.last : k == 0;
+  const bool final_ = adj ? k == 0 : k == sq.last;
+  const bool epi = TAIL && (prm.flags & SF_EPILOGUE) && final_;
+  const bool store = !epi || (prm.flags & SF_STORE_AT_EPI);
+
+  // P_k (or P_k^T) into LDS, contraction columns permuted for BF16
+  {
+    const Op* P =
+        reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP;
+    if constexpr (CT == DT_BF16) {
+      for (int e = threadIdx.x; e < MP * (MP / 8); e += 512) {
+        const int r = e / (MP / 8), n = (e % (MP / 8)) * 8;
+        const uint4 v = *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
+        const int nb = n >> 4, g0 = (n & 15) >> 2;  // entries n..n+3 in group g0, n+4..n+7 in g0+1
+        const int pos = 32 * (nb >> 1) + 8 * g0 + 4 * (nb & 1);
+        *reinterpret_cast<uint2*>(Ps + r * SP + pos) = make_uint2(v.x, v.y);
+        *reinterpret_cast<uint2*>(Ps + r * SP + pos + 8) = make_uint2(v.z, v.w);
+      }
+    } else {
+      for (int e = threadIdx.x; e < MP * (MP / 4); e += 512) {
+        const int r = e / (MP / 4), n = (e % (MP / 4)) * 4;
+        *reinterpret_cast<uint4*>(Ps + r * SP + n) =
+            *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int j = lane & 15, g = lane >> 4;
+  // 32-bit indices: the host keeps L MP 4 <= 2^31
+  const int L = (int)sq.L;
+  const int ncol = 1 << (k - 4);
+  const int ni = (L + (1 << k) - 1) >> k;  // blocks per column
+  // Blocks are numbered column by column, f = col ni + i; a wave's segment is
+  // T consecutive numbers, so it may run on into the next column (there the
+  // first block has no partner in registers and loads none).
+  const int nflat = ncol * ni;
+  const int T = un.T;
+  const int f0 = (un.seg0 + wave) * T;
+  if (f0 >= nflat) return;
+  const int f1 = f0 + T < nflat ? f0 + T : nflat;
+
+  // The sequence's state rows are addressed through buffer resources whose
+  // range is exactly its L x MP block: the hardware range check returns zeros
+  // for loads of rows outside the sequence and drops stores to them, so rows
+  // l >= L and partner blocks before the start need no masking. Offsets are
+  // 32-bit (the host keeps L MP 4 <= 2^31); an absent partner block is given
+  // the offset 2^31, which is out of range.
+  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * sizeof(X));
+  const X* xin = reinterpret_cast<const X*>(first && prm.xin_first ? prm.xin_first : prm.xin) +
+                 sq.x_off;
+  const auto rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<X*>(xin), (short)0, (int)nrec,
+                                                     kBufferWord3);
+  const auto rout = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<X*>(prm.xout) + sq.x_off,
+                                                      (short)0, store ? (int)nrec : 0, kBufferWord3);
+  const bool fin = TAIL && final_ && prm.xfinal;
+  const auto rfin = __builtin_amdgcn_make_buffer_rsrc(
+      fin ? reinterpret_cast<X*>(prm.xfinal) + sq.x_off : reinterpret_cast<X*>(prm.xout),
+      (short)0, fin ? (int)nrec : 0, kBufferWord3);
+  const uint32_t lane_off = (uint32_t)(j * MP + 4 * g) * (uint32_t)sizeof(X);
+  // The current block f sits at column fc, step fi; neighbours are found by
+  // stepping (no division per block).
+  int f = adj ? f1 - 1 : f0;
+  int fc = __builtin_amdgcn_readfirstlane(f / ni);  // uniform: keep in scalar registers
+  int fi = f - fc * ni;
+  // first time row of the block d numbers after the current one
+  auto row_at = [&](int d) -> int {  // |d| <= 2
+    int c = fc, i = fi + d;
+    if (ni == 1) {
+      c += d;
+      i = 0;
+    } else if (i >= ni) {  // ni >= 2: one wrap at most
+      i -= ni;
+      ++c;
+    } else if (i < 0) {
+      i += ni;
+      --c;
+    }
+    return (i << k) + c * 16;
+  };
+  // byte offset of this lane's piece of block f + d (out of range outside lo..hi-1)
+  auto block_off = [&](int d, int lo, int hi) -> uint32_t {
+    return (f + d >= lo && f + d < hi) ? lane_off + (uint32_t)row_at(d) * (uint32_t)(MP * sizeof(X))
+                                       : 0x80000000u;
+  };
+  // does the current block have a partner block (i >= 1 forward, i <= ni - 2 adjoint)?
+  auto has_partner = [&]() -> bool { return adj ? fi + 1 < ni : fi > 0; };
+  // stage input of this lane's row of block i, accumulator layout
+  auto load_block = [&](uint32_t off, f32x4(&v)[NB]) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      v[nb] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + nb * 64, 0, 0));
+  };
+  // shifted operand for the next block: BF16 operand pieces, or FP32 as is
+  constexpr int NPV = CT == DT_BF16 ? MP / 32 : NB;
+  using PV = typename std::conditional<CT == DT_BF16, bf16x8, f32x4>::type;
+  // (zeros when `keep` is false: the next block starts a column and has no partner)
+  auto pack = [&](const f32x4(&v)[NB], bool keep, PV(&pv)[NPV]) {
+    if constexpr (CT == DT_BF16) {
+#pragma unroll
+      for (int c = 0; c < MP / 32; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          pv[c][e] = (__bf16)(keep ? v[2 * c][e] : 0.f);  // round to nearest even
+          pv[c][4 + e] = (__bf16)(keep ? v[2 * c + 1][e] : 0.f);
+        }
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) pv[nb] = keep ? v[nb] : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+
+  const int step = adj ? -1 : 1;
+  // One block, its rows held in x: keep the block's input as the next block's
+  // shifted operand (npv), then for each group of four accumulator pieces add
+  // P_k times the shifted rows, store the group and load the same group of
+  // the next block into the freed registers, so that the next block arrives
+  // while this one is computed. (A TAIL launch loads the next block after the
+  // output epilogue, which needs the whole block.) The loop is unrolled by two
+  // so that the operand sets swap roles without copies.
+  constexpr int G = 4;
+  const int n = f1 - f0;
+  int t = 0;  // blocks done
+  f32x4 x[NB];
+  auto body = [&](const PV(&pv)[NPV], PV(&npv)[NPV]) {
+    const uint32_t off = block_off(0, 0, nflat);
+    const uint32_t offn = block_off(step, f0, f1);  // nothing past the segment
+    pack(x, adj ? fi > 0 : fi + 1 < ni, npv);  // partner of the next block, if it has one
+    // the LDS operand offset is passed through an empty asm so that the
+    // compiler re-reads the power fragments each block instead of hoisting
+    // them out of the loop into registers
+    int lbase = j * SP + (CT == DT_BF16 ? 8 : 4) * g;
+    asm volatile("" : "+v"(lbase));
+#pragma unroll
+    for (int n0 = 0; n0 < NB; n0 += G) {
+      {  // a block without a partner gets pv = 0
+        if constexpr (CT == DT_BF16) {
+          // power fragments read one MFMA step ahead of their use
+          bf16x8 fa[2][G];
+          auto frag = [&](int c, bf16x8(&f)[G]) {
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+              f[e] = *reinterpret_cast<const bf16x8*>(Ps + lbase + (n0 + e) * 16 * SP + 32 * c);
+          };
+          frag(0, fa[0]);
+#pragma unroll
+          for (int c = 0; c < MP / 32; ++c) {
+            if (c + 1 < MP / 32) frag(c + 1, fa[(c + 1) & 1]);
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+              x[n0 + e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[c & 1][e], pv[c], x[n0 + e], 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int a = 0; a < MP / 16; ++a)
+#pragma unroll
+            for (int nb = n0; nb < n0 + G; ++nb) {
+              const f32x4 av = *reinterpret_cast<const f32x4*>(Ps + lbase + nb * 16 * SP + 16 * a);
+#pragma unroll
+              for (int tt = 0; tt < 4; ++tt)
+                x[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt], pv[a][tt], x[nb], 0, 0, 0);
+            }
+        }
+      }
+#pragma unroll
+      for (int nb = n0; nb < n0 + G; ++nb) {
+        const auto v = __builtin_bit_cast(u32x4, x[nb]);
+        __builtin_amdgcn_raw_buffer_store_b128(v, rout, off + nb * 64, 0, 0);
+        if constexpr (TAIL) {
+          __builtin_amdgcn_raw_buffer_store_b128(v, rfin, off + nb * 64, 0, 0);
+        } else {
+          x[nb] = __builtin_bit_cast(
+              f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + nb * 64, 0, 0));
+        }
+      }
+    }
+    if constexpr (TAIL) {
+      if (epi) {  // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
+        const int64_t l = row_at(0) + j;
+        res_epilogue<NB>(x, MP, l, l < L,
+                         reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout),
+                         reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat),
+                         adj ? sq.p : sq.q, adj ? sq.q : sq.p, prm.src, prm.src_dtype,
+                         adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
+                         adj ? sq.u_off : sq.y_off, j, g);
+      }
+      load_block(offn, x);
+    }
+    f += step;
+    fi += step;
+    if (fi == ni) {
+      fi = 0;
+      ++fc;
+    } else if (fi < 0) {
+      fi = ni - 1;
+      --fc;
+    }
+    ++t;
+  };
+
+  PV pa[NPV], pb[NPV];
+  load_block(has_partner() ? block_off(-step, 0, nflat) : 0x80000000u, x);  // partner (or zeros)
+  pack(x, true, pa);
+  load_block(block_off(0, f0, f1), x);
+  while (t < n) {  // unrolled by two: the operand sets swap roles
+    body(pa, pb);
+    if (t >= n) break;
+    body(pb, pa);
+  }
+}
+
+}  // namespace ssmc

@@ -106,3 +106,84 @@ def test_backward_per_stage_kernels(compute, stage_kernel):
     from tests.test_gpu_backward import _compare
     wl = W.backward(seed=24, batch=3, m=128, L=1500, N=10, p=4, q=4, delta=5e-3)
     _compare(wl, compute, launch="per_stage", stage_kernel=stage_kernel)
+
+
+def _ragged_res(seed, compute, one_fold=False):
+    # uneven L (33 .. 5000) and m over the classes the resident persistent launch
+    # takes; p <= m/4 so both launch modes fold the same stages
+    rng = np.random.default_rng(seed)
+    spec = [(64, 4, 2, 5000, 12), (100, 2, 3, 1777, 10), (128, 8, 4, 3001, 11), (48, 4, 1, 33, 5),
+            (60, 4, 4, 700, 6), (64, 16, 2, 1500, 10)]  # the last folds 2 stages: stages 2, 3 by rows
+    if compute == "bf16":
+        spec += [(256, 8, 8, 4100, 12), (200, 4, 2, 999, 9)]
+    if one_fold:  # one stage folded into the input pass (the persistent launch only):
+        # 2p = padded m, and sequences of length 1 and 2
+        spec += [(64, 32, 2, 1000, 9), (64, 2, 2, 2, 1), (128, 4, 4, 1, 0)]
+    sets, seqs = [], []
+    for i, (m, p, q, L, N) in enumerate(spec):
+        A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, p)) / math.sqrt(m),
+                               rng.standard_normal((q, m)) / math.sqrt(m),
+                               rng.standard_normal((q, p)) / math.sqrt(m)))
+        seqs.append(W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, N, rng.standard_normal((L, p))))
+    return W.Workload("ragged_res", sets, seqs)
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_resident_persistent_matches_per_stage(compute):
+    # one persistent launch of input-pass, resident and chain items against the
+    # per-stage launches of the same code: every row sees the same operands in
+    # the same order, so the outputs agree bit for bit
+    from paper_2411_17729_amd import cascade as CC
+    wl = _ragged_res(31, compute)
+    u = CC.pack_u(wl, dtype=torch.float32)
+    pers = CC.plan_for_workload(wl, compute=compute, launch="persistent")
+    info = pers.info()
+    assert info["launch"] == 2 and info["stage_kernel"] == 3 and info["input_stages"] >= 4
+    per = CC.plan_for_workload(wl, compute=compute, launch="per_stage")
+    ya = pers.apply(u).clone()
+    yb = per.apply(u).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb)
+    got = CC.unpack_y(wl, ya)
+    ref = _oracle(wl)
+    tol = 1e-5 if compute == "f32" else 2e-2
+    for i in range(len(wl.seqs)):
+        e = rel_err(got[i], ref[i])
+        assert e <= tol, (i, e)
+
+
+def test_resident_persistent_one_folded_stage():
+    # operators with 2p = padded m, or sequences of one or two steps, fold a
+    # single stage into the input pass
+    from paper_2411_17729_amd import cascade as CC
+    wl = _ragged_res(32, "bf16", one_fold=True)
+    plan = CC.plan_for_workload(wl, compute="bf16", launch="persistent")
+    assert plan.info()["stage_kernel"] == 3
+    got = CC.unpack_y(wl, plan.apply(CC.pack_u(wl, dtype=torch.float32)))
+    ref = _oracle(wl)
+    for i in range(len(wl.seqs)):
+        assert rel_err(got[i], ref[i]) <= 2e-2, i
+
+
+def test_resident_persistent_graph_replays():
+    from paper_2411_17729_amd import cascade as CC
+    wl = _ragged_res(33, "bf16")
+    plan = CC.plan_for_workload(wl, compute="bf16")
+    assert plan.info()["launch"] == 2 and plan.info()["stage_kernel"] == 3
+    stream = torch.cuda.Stream()
+    u = CC.pack_u(wl, dtype=torch.float32)
+    y = torch.empty(plan.layout.y_numel, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    g = plan.graph_apply(u, y, stream)
+    try:
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                u.mul_(0.5 + rep)  # eager work between replays
+            CC.CascadePlan.graph_launch(g, stream)
+            stream.synchronize()
+            ref = plan.apply(u)
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref), rep
+    finally:
+        CC.CascadePlan.graph_destroy(g)
