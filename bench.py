@@ -381,7 +381,8 @@ def bench_ragged(args):
                    "graph": True, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
                      "frac": round(gbps / PEAK["hbm_GBps"], 4), "traffic": None,
-                     "kernel": "k_persistent" if info["launch"] == 2 else "stage kernels",
+                     "kernel": ("k_persist_res" if info["stage_kernel"] == 3 else "k_persistent")
+                               if info["launch"] == 2 else "stage kernels",
                      "launches_timed": n_k, "avg_launch_ms": round(t_k / max(n_k, 1), 5),
                      "algorithmic_bytes_per_launch": round(info["stage_bytes"] / max(n_k, 1))},
         "backward": {"value": round(wl.total_steps / (ms_b * 1e-3), 1), "ms_per_step": round(ms_b, 4),

@@ -19,6 +19,15 @@
 
 namespace ssmc {
 
+// Segments each wave walks side by side in a chain item: about 64 registers of
+// state per wave whatever the state size, so small-m items keep as many bytes
+// in flight as m = 256 ones.
+constexpr int persist_segments(int mp, int ct) {
+  return ct == DT_BF16 ? 256 / mp : (mp == 64 ? 2 : 1);
+}
+
+int chain_segments_persist(int mp, int ct) { return persist_segments(mp, ct); }
+
 template <int MP, int CT>
 __device__ __forceinline__ void persist_item(const StageParams& base, const RItem& w, void* x0,
                                              void* x1, unsigned char* smem) {
@@ -36,9 +45,9 @@ __device__ __forceinline__ void persist_item(const StageParams& base, const RIte
   if (w.kind == RI_RES) {
     res_range<MP, CT>(prm, ResRange{w.seq, w.a, w.b, 0}, 0, smem);
   } else if (w.tail) {
-    chain_unit<MP, CT, true>(prm, ChainUnit{w.seq, w.a, w.b, 0}, smem);
+    chain_unit<MP, CT, true, persist_segments(MP, CT)>(prm, ChainUnit{w.seq, w.a, w.b, 0}, smem);
   } else {
-    chain_unit<MP, CT, false>(prm, ChainUnit{w.seq, w.a, w.b, 0}, smem);
+    chain_unit<MP, CT, false, persist_segments(MP, CT)>(prm, ChainUnit{w.seq, w.a, w.b, 0}, smem);
   }
 }
 

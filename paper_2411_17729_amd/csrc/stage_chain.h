@@ -32,8 +32,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // TAIL: some sequence of the launch ends at this stage (output epilogue or a
 // copy of the final state may be due); otherwise the lean variant runs, which
-// only stores the stage output.
-template <int MP, int CT, bool TAIL>
+// only stores the stage output. S: segments walked side by side by each wave
+// (more loads in flight per wave for small state sizes); the unit covers
+// segments seg0 .. seg0 + 8 S - 1, wave w taking seg0 + w S .. seg0 + w S + S - 1.
+template <int MP, int CT, bool TAIL, int S = 1>
 __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUnit un,
                                            unsigned char* smem_chain) {
   using C = ResCfg<MP, CT>;
@@ -84,14 +86,23 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   const int L = (int)sq.L;
   const int ncol = 1 << (k - 4);
   const int ni = (L + (1 << k) - 1) >> k;  // blocks per column
-  // Blocks are numbered column by column, f = col ni + i; a wave's segment is
-  // T consecutive numbers, so it may run on into the next column (there the
+  // Blocks are numbered column by column, f = col ni + i; a segment is T
+  // consecutive numbers, so it may run on into the next column (there the
   // first block has no partner in registers and loads none).
   const int nflat = ncol * ni;
   const int T = un.T;
-  const int f0 = (un.seg0 + wave) * T;
-  if (f0 >= nflat) return;
-  const int f1 = f0 + T < nflat ? f0 + T : nflat;
+  // per segment: first and end numbers, current block f at column fc, step fi
+  int f0[S], f1[S], f[S], fc[S], fi[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    f0[q] = (un.seg0 + wave * S + q) * T;
+    f1[q] = f0[q] < nflat ? (f0[q] + T < nflat ? f0[q] + T : nflat) : f0[q];
+    f[q] = adj ? f1[q] - 1 : f0[q];
+    fc[q] = f0[q] < nflat ? __builtin_amdgcn_readfirstlane(f[q] / ni) : 0;  // uniform
+    fi[q] = f[q] - fc[q] * ni;
+  }
+  const int n = f1[0] - f0[0];  // the first segment is the longest
+  if (n <= 0) return;
 
   // The sequence's state rows are addressed through buffer resources whose
   // range is exactly its L x MP block: the hardware range check returns zeros
@@ -111,18 +122,11 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
       fin ? reinterpret_cast<X*>(prm.xfinal) + sq.x_off : reinterpret_cast<X*>(prm.xout),
       (short)0, fin ? (int)nrec : 0, kBufferWord3);
   const uint32_t lane_off = (uint32_t)(j * MP + 4 * g) * (uint32_t)sizeof(X);
-  // The current block f sits at column fc, step fi; neighbours are found by
-  // stepping (no division per block).
-  int f = adj ? f1 - 1 : f0;
-  int fc = __builtin_amdgcn_readfirstlane(f / ni);  // uniform: keep in scalar registers
-  int fi = f - fc * ni;
-  // first time row of the block d numbers after the current one
-  auto row_at = [&](int d) -> int {  // |d| <= 2
-    int c = fc, i = fi + d;
-    if (ni == 1) {
-      c += d;
-      i = 0;
-    } else if (i >= ni) {  // ni >= 2: one wrap at most
+  // first time row of the block d numbers after segment q's current one (no
+  // division: stepping from (fc, fi))
+  auto row_at = [&](int q, int d) -> int {  // |d| <= 1
+    int c = fc[q], i = fi[q] + d;
+    if (i >= ni) {
       i -= ni;
       ++c;
     } else if (i < 0) {
@@ -132,13 +136,12 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     return (i << k) + c * 16;
   };
   // byte offset of this lane's piece of block f + d (out of range outside lo..hi-1)
-  auto block_off = [&](int d, int lo, int hi) -> uint32_t {
-    return (f + d >= lo && f + d < hi) ? lane_off + (uint32_t)row_at(d) * (uint32_t)(MP * sizeof(X))
-                                       : 0x80000000u;
+  auto block_off = [&](int q, int d, int lo, int hi) -> uint32_t {
+    return (f[q] + d >= lo && f[q] + d < hi)
+               ? lane_off + (uint32_t)row_at(q, d) * (uint32_t)(MP * sizeof(X))
+               : 0x80000000u;
   };
-  // does the current block have a partner block (i >= 1 forward, i <= ni - 2 adjoint)?
-  auto has_partner = [&]() -> bool { return adj ? fi + 1 < ni : fi > 0; };
-  // stage input of this lane's row of block i, accumulator layout
+  // stage input of this lane's row of a block, accumulator layout
   auto load_block = [&](uint32_t off, f32x4(&v)[NB]) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -164,21 +167,20 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   };
 
   const int step = adj ? -1 : 1;
-  // One block, its rows held in x: keep the block's input as the next block's
-  // shifted operand (npv), then for each group of four accumulator pieces add
-  // P_k times the shifted rows, store the group and load the same group of
-  // the next block into the freed registers, so that the next block arrives
-  // while this one is computed. (A TAIL launch loads the next block after the
-  // output epilogue, which needs the whole block.) The loop is unrolled by two
-  // so that the operand sets swap roles without copies.
-  constexpr int G = 4;
-  const int n = f1 - f0;
-  int t = 0;  // blocks done
-  f32x4 x[NB];
-  auto body = [&](const PV(&pv)[NPV], PV(&npv)[NPV]) {
-    const uint32_t off = block_off(0, 0, nflat);
-    const uint32_t offn = block_off(step, f0, f1);  // nothing past the segment
-    pack(x, adj ? fi > 0 : fi + 1 < ni, npv);  // partner of the next block, if it has one
+  // One block of segment q, its rows held in x[q]: keep the block's input as
+  // the next block's shifted operand (npv), then for each group of four
+  // accumulator pieces add P_k times the shifted rows, store the group and
+  // load the same group of the next block into the freed registers, so that
+  // the next block arrives while this one is computed. (A TAIL launch loads
+  // the next block after the output epilogue, which needs the whole block.)
+  // The loop is unrolled by two so that the operand sets swap roles without
+  // copies.
+  constexpr int G = NB < 4 ? NB : 4;
+  f32x4 x[S][NB];
+  auto body = [&](const int q, const PV(&pv)[NPV], PV(&npv)[NPV]) {
+    const uint32_t off = block_off(q, 0, 0, nflat);
+    const uint32_t offn = block_off(q, step, f0[q], f1[q]);  // nothing past the segment
+    pack(x[q], adj ? fi[q] > 0 : fi[q] + 1 < ni, npv);  // partner of the next block, if any
     // the LDS operand offset is passed through an empty asm so that the
     // compiler re-reads the power fragments each block instead of hoisting
     // them out of the loop into registers
@@ -186,79 +188,86 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     asm volatile("" : "+v"(lbase));
 #pragma unroll
     for (int n0 = 0; n0 < NB; n0 += G) {
-      {  // a block without a partner gets pv = 0
-        if constexpr (CT == DT_BF16) {
-          // power fragments read one MFMA step ahead of their use
-          bf16x8 fa[2][G];
-          auto frag = [&](int c, bf16x8(&f)[G]) {
+      if constexpr (CT == DT_BF16) {  // a block without a partner gets pv = 0
+        // power fragments read one MFMA step ahead of their use
+        bf16x8 fa[2][G];
+        auto frag = [&](int c, bf16x8(&fr)[G]) {
 #pragma unroll
-            for (int e = 0; e < G; ++e)
-              f[e] = *reinterpret_cast<const bf16x8*>(Ps + lbase + (n0 + e) * 16 * SP + 32 * c);
-          };
-          frag(0, fa[0]);
+          for (int e = 0; e < G; ++e)
+            fr[e] = *reinterpret_cast<const bf16x8*>(Ps + lbase + (n0 + e) * 16 * SP + 32 * c);
+        };
+        frag(0, fa[0]);
 #pragma unroll
-          for (int c = 0; c < MP / 32; ++c) {
-            if (c + 1 < MP / 32) frag(c + 1, fa[(c + 1) & 1]);
+        for (int c = 0; c < MP / 32; ++c) {
+          if (c + 1 < MP / 32) frag(c + 1, fa[(c + 1) & 1]);
 #pragma unroll
-            for (int e = 0; e < G; ++e)
-              x[n0 + e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[c & 1][e], pv[c], x[n0 + e], 0, 0, 0);
-          }
-        } else {
-#pragma unroll
-          for (int a = 0; a < MP / 16; ++a)
-#pragma unroll
-            for (int nb = n0; nb < n0 + G; ++nb) {
-              const f32x4 av = *reinterpret_cast<const f32x4*>(Ps + lbase + nb * 16 * SP + 16 * a);
-#pragma unroll
-              for (int tt = 0; tt < 4; ++tt)
-                x[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt], pv[a][tt], x[nb], 0, 0, 0);
-            }
+          for (int e = 0; e < G; ++e)
+            x[q][n0 + e] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[c & 1][e], pv[c], x[q][n0 + e], 0, 0, 0);
         }
+      } else {
+#pragma unroll
+        for (int a = 0; a < MP / 16; ++a)
+#pragma unroll
+          for (int nb = n0; nb < n0 + G; ++nb) {
+            const f32x4 av = *reinterpret_cast<const f32x4*>(Ps + lbase + nb * 16 * SP + 16 * a);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+              x[q][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt], pv[a][tt], x[q][nb], 0, 0, 0);
+          }
       }
 #pragma unroll
       for (int nb = n0; nb < n0 + G; ++nb) {
-        const auto v = __builtin_bit_cast(u32x4, x[nb]);
+        const auto v = __builtin_bit_cast(u32x4, x[q][nb]);
         __builtin_amdgcn_raw_buffer_store_b128(v, rout, off + nb * 64, 0, 0);
         if constexpr (TAIL) {
           __builtin_amdgcn_raw_buffer_store_b128(v, rfin, off + nb * 64, 0, 0);
         } else {
-          x[nb] = __builtin_bit_cast(
+          x[q][nb] = __builtin_bit_cast(
               f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + nb * 64, 0, 0));
         }
       }
     }
     if constexpr (TAIL) {
       if (epi) {  // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
-        const int64_t l = row_at(0) + j;
-        res_epilogue<NB>(x, MP, l, l < L,
+        const int64_t l = row_at(q, 0) + j;
+        res_epilogue<NB>(x[q], MP, l, l < L,
                          reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout),
                          reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat),
                          adj ? sq.p : sq.q, adj ? sq.q : sq.p, prm.src, prm.src_dtype,
                          adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
                          adj ? sq.u_off : sq.y_off, j, g);
       }
-      load_block(offn, x);
+      load_block(offn, x[q]);
     }
-    f += step;
-    fi += step;
-    if (fi == ni) {
-      fi = 0;
-      ++fc;
-    } else if (fi < 0) {
-      fi = ni - 1;
-      --fc;
+    f[q] += step;
+    fi[q] += step;
+    if (fi[q] == ni) {
+      fi[q] = 0;
+      ++fc[q];
+    } else if (fi[q] < 0) {
+      fi[q] = ni - 1;
+      --fc[q];
     }
-    ++t;
   };
 
-  PV pa[NPV], pb[NPV];
-  load_block(has_partner() ? block_off(-step, 0, nflat) : 0x80000000u, x);  // partner (or zeros)
-  pack(x, true, pa);
-  load_block(block_off(0, f0, f1), x);
-  while (t < n) {  // unrolled by two: the operand sets swap roles
-    body(pa, pb);
-    if (t >= n) break;
-    body(pb, pa);
+  PV pa[S][NPV], pb[S][NPV];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const bool partner = f1[q] > f0[q] && (adj ? fi[q] + 1 < ni : fi[q] > 0);
+    load_block(partner ? block_off(q, -step, 0, nflat) : 0x80000000u, x[q]);  // partner or zeros
+    pack(x[q], true, pa[q]);
+    load_block(block_off(q, 0, f0[q], f1[q]), x[q]);
+  }
+  // segments advance in lockstep; a shorter one idles once it is done
+  for (int t = 0; t < n; ++t) {  // unrolled by two: the operand sets swap roles
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (t < f1[q] - f0[q]) body(q, pa[q], pb[q]);
+    if (++t >= n) break;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (t < f1[q] - f0[q]) body(q, pb[q], pa[q]);
   }
 }
 
