@@ -1542,7 +1542,9 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       rp.k = k;
       rp.check_last = k >= 0;
       TimedLaunch tl(P, stream, 2);
-      hipError_t er = launch_outer(mp, P.state_f64, rp, ty, stream);
+      // state by state (dL/dP_k) in FP32: the direct-load kernel
+      const bool ss = a_kind == RS_STATE && b_kind == RS_STATE && !P.state_f64 && mp >= 64;
+      hipError_t er = ss ? launch_outer_ss(mp, rp, stream) : launch_outer(mp, P.state_f64, rp, ty, stream);
       tl.done();
       return er;
     };

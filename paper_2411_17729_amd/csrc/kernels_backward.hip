@@ -8,6 +8,8 @@
 // and dL/dBbar = sum_l g_l^(0) u_l^T. Each workgroup reduces one chunk of rows
 // of one sequence on the matrix cores (FP32 MFMA for FP32 state, FP64 MFMA
 // for FP64 state) into a partial; the partials are then summed in FP64.
+#include <type_traits>
+
 #include "ssm_internal.h"
 
 namespace ssmc {
@@ -179,26 +181,131 @@ hipError_t launch_outer(int mp, int state_f64, const RedParams& prm, int tiles_y
 }
 
 // ---------------------------------------------------------------------------
+// The state-by-state reduction dL/dP_k (FP32 state): partial[slot] = sum over
+// the chunk's rows l of A_l B_{l-s}^T, A and B rows of MP floats. Operands
+// come straight from memory: lane (i, kk) of a wave loads V consecutive entries
+// of row l + kk (a 16- or 8-byte piece, coalesced across the 16 lanes of a
+// row), and entry c of that piece feeds MFMA block c, so block c's output row
+// i is state index base + V i + c. Four rows per FP32 16x16x4 MFMA step; four
+// waves cover a TO x TO output tile.
+// ---------------------------------------------------------------------------
+template <int MP>
+__global__ __launch_bounds__(256) void k_outer_ss(RedParams prm) {
+  constexpr int TO = MP < 128 ? MP : 128;  // output tile edge
+  constexpr int WT = TO / 2;               // per-wave edge (2 x 2 waves)
+  constexpr int V = WT / 16;               // entries per lane load (2 or 4)
+  using VT = typename std::conditional<V == 4, f32x4, float2>::type;
+  const RedChunk ch = prm.chunks[blockIdx.x];
+  const SeqDev sq = prm.seqs[ch.seq];
+  float* part = reinterpret_cast<float*>(prm.partial) + (int64_t)ch.slot * prm.slot_stride;
+  constexpr int ntb = MP / TO;
+  const int ta = blockIdx.y / ntb, tb = blockIdx.y % ntb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lr = lane & 15, kk = lane >> 4;
+  const int abase = ta * TO + wr * WT, bbase = tb * TO + wc * WT;
+
+  f32x4 acc[V][V];
+#pragma unroll
+  for (int a = 0; a < V; ++a)
+#pragma unroll
+    for (int b = 0; b < V; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const bool first = prm.a_first && prm.k >= 0 && prm.k == sq.last;
+  const bool active = !(prm.check_last && prm.k > sq.last);
+  const int64_t sh = prm.k >= 0 ? ((int64_t)1 << prm.k) : 0;
+  int64_t lo = ch.row0;
+  if (lo < sh) lo = sh;  // rows without a partner contribute nothing
+  const int64_t hi = (int64_t)ch.row0 + ch.nrows;
+  if (active && lo < hi) {
+    const float* A = reinterpret_cast<const float*>(first ? prm.a_first : prm.a_base) + sq.x_off +
+                     abase + V * lr;
+    const float* B = reinterpret_cast<const float*>(prm.b_base) + sq.x_off + bbase + V * lr;
+    auto ld = [&](const float* base, int64_t row, bool ok) -> VT {
+      return ok ? *reinterpret_cast<const VT*>(base + row * MP) : VT{};
+    };
+    // two steps of four rows per iteration, the next pair's loads issued first
+    int64_t l = lo;
+    VT a0 = ld(A, l + kk, l + kk < hi), b0 = ld(B, l + kk - sh, l + kk < hi);
+    VT a1 = ld(A, l + 4 + kk, l + 4 + kk < hi), b1 = ld(B, l + 4 + kk - sh, l + 4 + kk < hi);
+    for (; l < hi; l += 8) {
+      const int64_t ln = l + 8;
+      const VT na0 = ld(A, ln + kk, ln + kk < hi), nb0 = ld(B, ln + kk - sh, ln + kk < hi);
+      const VT na1 = ld(A, ln + 4 + kk, ln + 4 + kk < hi), nb1 = ld(B, ln + 4 + kk - sh, ln + 4 + kk < hi);
+#pragma unroll
+      for (int a = 0; a < V; ++a)
+#pragma unroll
+        for (int b = 0; b < V; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[a], b0[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < V; ++a)
+#pragma unroll
+        for (int b = 0; b < V; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[a], b1[b], acc[a][b], 0, 0, 0);
+      a0 = na0;
+      b0 = nb0;
+      a1 = na1;
+      b1 = nb1;
+    }
+  }
+  // accumulator entry v of block (a, b): output row 4 kk + v, column lr
+#pragma unroll
+  for (int a = 0; a < V; ++a)
+#pragma unroll
+    for (int b = 0; b < V; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = abase + V * (4 * kk + v) + a, c = bbase + V * lr + b;
+        part[(int64_t)r * MP + c] = acc[a][b][v];
+      }
+}
+
+hipError_t launch_outer_ss(int mp, const RedParams& prm, hipStream_t s) {
+  if (prm.n_chunks <= 0) return hipSuccess;
+  switch (mp) {
+    case 64: hipLaunchKernelGGL(k_outer_ss<64>, dim3(prm.n_chunks, 1), dim3(256), 0, s, prm); break;
+    case 128: hipLaunchKernelGGL(k_outer_ss<128>, dim3(prm.n_chunks, 1), dim3(256), 0, s, prm); break;
+    case 256: hipLaunchKernelGGL(k_outer_ss<256>, dim3(prm.n_chunks, 4), dim3(256), 0, s, prm); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // FP64 sum of the partials of each job (blockIdx.y = job); the summation
 // order is fixed, so the result is deterministic.
 // ---------------------------------------------------------------------------
 template <typename X>
-__global__ void k_sum(const SumJob* jobs, int k, const X* partial, double* out) {
+__global__ __launch_bounds__(256) void k_sum(const SumJob* jobs, int k, const X* partial, double* out) {
+  // 64 elements per block, the slots split in four interleaved groups whose
+  // FP64 sums are added in a fixed order
+  __shared__ double red[4][64];
   const SumJob jb = jobs[blockIdx.y];
   if (k > jb.kmax) return;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < jb.elems; e += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    const X* p = partial + jb.slot0 * jb.slot_stride + e;
-    for (int c = 0; c < jb.nslots; ++c) acc += (double)p[(int64_t)c * jb.slot_stride];
-    out[jb.out + (int64_t)k * jb.kstride + e] = acc;
+  const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  for (int e0 = blockIdx.x * 64; e0 < jb.elems; e0 += gridDim.x * 64) {
+    const int e = e0 + el;
+    double acc0 = 0.0, acc1 = 0.0;
+    if (e < jb.elems) {
+      const X* p = partial + jb.slot0 * jb.slot_stride + e;
+      int c = grp;
+      for (; c + 4 < jb.nslots; c += 8) {
+        acc0 += (double)p[(int64_t)c * jb.slot_stride];
+        acc1 += (double)p[(int64_t)(c + 4) * jb.slot_stride];
+      }
+      if (c < jb.nslots) acc0 += (double)p[(int64_t)c * jb.slot_stride];
+    }
+    red[grp][el] = acc0 + acc1;
+    __syncthreads();
+    if (grp == 0 && e < jb.elems)
+      out[jb.out + (int64_t)k * jb.kstride + e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
+    __syncthreads();
   }
 }
 
 hipError_t launch_sum(const SumJob* jobs, int n_jobs, int max_elems, int k, const void* partial,
                       int state_f64, double* out, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  int bx = (max_elems + 255) / 256;
-  if (bx > 256) bx = 256;
+  int bx = (max_elems + 63) / 64;
+  if (bx > 1024) bx = 1024;
   if (bx < 1) bx = 1;
   if (state_f64)
     hipLaunchKernelGGL(k_sum<double>, dim3(bx, n_jobs), dim3(256), 0, s, jobs, k,

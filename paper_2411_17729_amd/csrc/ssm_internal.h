@@ -284,6 +284,8 @@ hipError_t launch_persist_res(int ct, const RPersistParams& pp, int grid, size_t
 // Workgroups of the persistent kernel that fit on one compute unit.
 int persistent_blocks_per_cu(int ct);
 
+// dL/dP_k between two FP32 state buffers (a_kind = b_kind = RS_STATE), padded m 64..256.
+hipError_t launch_outer_ss(int mp, const RedParams& prm, hipStream_t s);
 hipError_t launch_outer(int mp, int state_f64, const RedParams& prm, int tiles_y,
                         hipStream_t s);
 hipError_t launch_sum(const SumJob* jobs, int n_jobs, int max_elems, int k,
