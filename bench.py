@@ -143,8 +143,6 @@ def main():
         ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
         bound = "mfma" if intensity > ridge else "hbm"
         kid = info["stage_kernel"]
-        if kid == 3 and dtype == "f32" and ps.m > 128:
-            kid = 2  # FP32 m > 128: the chain walk does not apply, the resident kernel runs
         traffic = _stage_traffic(wname, dtype, kid)
         if bound == "hbm":
             rf = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"],

@@ -96,9 +96,11 @@ typedef enum {
                              each wave walks a column of 16-row blocks spaced 2^k
                              apart and reuses each block's input rows as the next
                              block's shifted operand, so the state is read about
-                             once per stage instead of twice (BF16 at padded m of
-                             64..256, FP32 at 64 and 128; other stages and sizes
-                             use the resident kernel) */
+                             once per stage instead of twice (BF16 and FP32 at
+                             padded m of 64..256; FP32 m = 256 splits each row's
+                             outputs over two workgroups and leaves its last stage
+                             to the resident kernel; other stages and sizes use
+                             the resident kernel) */
 } ssm_stage_kernel;
 
 typedef struct {

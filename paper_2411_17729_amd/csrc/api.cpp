@@ -400,7 +400,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (P.launch == SSM_LAUNCH_PERSISTENT && P.stage_kernel != SSM_STAGE_TILED &&
       tn.input_stages >= 0) {
     bool ok = true;
-    for (const OpDev& o : P.ops) ok = ok && chain_supported(o.mp, (int)compute) && 2 * o.p <= o.mp;
+    for (const OpDev& o : P.ops)
+      ok = ok && chain_supported(o.mp, (int)compute) && !res_splits_rows(o.mp, (int)compute) &&
+           2 * o.p <= o.mp;
     for (const SeqDev& sq : P.seqs)
       ok = ok && sq.L * (int64_t)P.ops[sq.op].mp * 4 <= ((int64_t)1 << 31);
     P.persist_res = ok;
@@ -987,7 +989,8 @@ hipError_t launch_stage_any(const ssm_plan_s& P, int c, StageParams prm, hipStre
     const ChainUnit* un = reinterpret_cast<const ChainUnit*>(P.ws + P.r_meta.off + P.m_chain) +
                           P.chain_start[c][k];
     const bool tail = prm.adjoint ? k == 0 : P.class_final[c][k] > 0;
-    return launch_stage_chain(mp, P.compute, prm, un, P.chain_count[c][k], tail, stream);
+    if (!(tail && res_splits_rows(mp, P.compute)))
+      return launch_stage_chain(mp, P.compute, prm, un, P.chain_count[c][k], tail, stream);
   }
   const bool final_here = (prm.flags & SF_EPILOGUE) &&
                           (prm.adjoint ? k == 0 : (k < (int)P.class_final[c].size() &&

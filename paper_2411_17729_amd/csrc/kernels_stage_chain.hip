@@ -7,7 +7,7 @@ template <int MP, int CT, bool TAIL>
 __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_stage_chain(
     StageParams prm, const ChainUnit* units) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_chain[];
-  chain_unit<MP, CT, TAIL>(prm, units[blockIdx.x], smem_chain);
+  chain_unit<MP, CT, TAIL>(prm, units[blockIdx.x], smem_chain, blockIdx.y);
 }
 
 template <int MP, int CT, bool TAIL>
@@ -21,7 +21,7 @@ static hipError_t launch_chain_v(const StageParams& prm, const ChainUnit* units,
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_stage_chain<MP, CT, TAIL>), dim3(n_units), dim3(512), C::LDS, s, prm,
+  hipLaunchKernelGGL((k_stage_chain<MP, CT, TAIL>), dim3(n_units, C::NS), dim3(512), C::LDS, s, prm,
                      units);
   return hipGetLastError();
 }
@@ -30,14 +30,17 @@ template <int MP, int CT>
 static hipError_t launch_chain_t(const StageParams& prm, const ChainUnit* units, int n_units,
                                  bool tail, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
-  return tail ? launch_chain_v<MP, CT, true>(prm, units, n_units, s)
-              : launch_chain_v<MP, CT, false>(prm, units, n_units, s);
+  if constexpr (ResCfg<MP, CT>::NS > 1) {
+    if (tail) return hipErrorInvalidValue;  // the split walk has no tail variant
+    return launch_chain_v<MP, CT, false>(prm, units, n_units, s);
+  } else {
+    return tail ? launch_chain_v<MP, CT, true>(prm, units, n_units, s)
+                : launch_chain_v<MP, CT, false>(prm, units, n_units, s);
+  }
 }
 
 bool chain_supported(int mp, int ct) {
-  if (ct == DT_BF16) return mp == 64 || mp == 128 || mp == 256;
-  if (ct == DT_F32) return mp == 64 || mp == 128;
-  return false;
+  return (ct == DT_BF16 || ct == DT_F32) && (mp == 64 || mp == 128 || mp == 256);
 }
 
 hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const ChainUnit* units,
@@ -52,6 +55,7 @@ hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const Chai
     switch (mp) {
       case 64: return launch_chain_t<64, DT_F32>(prm, units, n_units, tail, s);
       case 128: return launch_chain_t<128, DT_F32>(prm, units, n_units, tail, s);
+      case 256: return launch_chain_t<256, DT_F32>(prm, units, n_units, tail, s);
     }
   }
   return hipErrorInvalidValue;

@@ -262,8 +262,9 @@ hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRan
 // written to xin (kry even) or xout (kry odd); y at once when kry = last + 1.
 hipError_t launch_krylov_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
                              int n_ranges, hipStream_t s);
-// Chain-walking stage kernel (stages with 2^k >= 16; whole state rows per
-// workgroup): BF16 at padded m of 64..256, FP32 at 64 and 128.
+// Chain-walking stage kernel (stages with 2^k >= 16): BF16 and FP32 at padded
+// m of 64..256; FP32 m = 256 splits the output rows over two workgroups and
+// has no tail variant (tail launches take the resident or tiled kernel).
 bool chain_supported(int mp, int ct);
 // tail: some sequence of the launch has its last stage here (the forward
 // epilogue or the final-state copy may be due); false selects the lean variant.
@@ -275,7 +276,7 @@ hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
 // One persistent launch that runs every item of the plan's forward pass.
 hipError_t launch_persistent(int ct, const PersistParams& pp, int grid, hipStream_t s);
 // Persistent launch whose items run the chain, resident and input-pass code
-// (BF16 at padded m 64..256, FP32 at 64 and 128); lds: dynamic LDS bytes for
+// (BF16 at padded m 64..256, FP32 at 64 and 128: no split rows); lds: dynamic LDS bytes for
 // the largest class present (persist_res_lds).
 size_t persist_res_lds(int ct, int max_mp);
 // Segments per wave of a chain item in that launch (a unit spans 8 times as many).

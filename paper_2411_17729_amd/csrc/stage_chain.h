@@ -35,14 +35,25 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // only stores the stage output. S: segments walked side by side by each wave
 // (more loads in flight per wave for small state sizes); the unit covers
 // segments seg0 .. seg0 + 8 S - 1, wave w taking seg0 + w S .. seg0 + w S + S - 1.
+// When the power does not fit in LDS (FP32, m = 256) two workgroups share a
+// unit, each holding half of P_k's rows (split = 0, 1) and producing half of
+// every output row; both load whole input rows, which the next block needs
+// as its shifted operand. The split form has no output epilogue. To keep
+// register indices static, a split workgroup holds the row's 16-entry pieces
+// rotated by its first output piece nb0 (register piece i is row piece
+// i + nb0 mod 16, its own pieces first), and its LDS copy of P_k has the
+// columns rotated the same way, so MFMA step a still pairs register piece a
+// with the matching columns.
 template <int MP, int CT, bool TAIL, int S = 1>
 __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUnit un,
-                                           unsigned char* smem_chain) {
+                                           unsigned char* smem_chain, int split = 0) {
   using C = ResCfg<MP, CT>;
-  static_assert(C::NS == 1, "a chain walk needs whole state rows in one workgroup");
+  static_assert(C::NS == 1 || (S == 1 && !TAIL), "the split walk runs lean, one segment per wave");
   using X = float;
   using Op = typename C::Op;
-  constexpr int NB = C::NB, SP = C::SP;
+  constexpr int NB = C::NB, SP = C::SP;  // NB: output pieces of 16 entries per workgroup
+  constexpr int NV = MP / 16;            // pieces of a whole row
+  const int nb0 = split * NB;            // first output piece of this workgroup
   Op* Ps = reinterpret_cast<Op*>(smem_chain);
 
   const SeqDev sq = prm.seqs[un.seq];
@@ -56,12 +67,12 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   const bool epi = TAIL && (prm.flags & SF_EPILOGUE) && final_;
   const bool store = !epi || (prm.flags & SF_STORE_AT_EPI);
 
-  // P_k (or P_k^T) into LDS, contraction columns permuted for BF16
+  // rows nb0 16 .. of P_k (or P_k^T) into LDS, contraction columns permuted for BF16
   {
-    const Op* P =
-        reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP;
+    const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP +
+                  (int64_t)nb0 * 16 * MP;
     if constexpr (CT == DT_BF16) {
-      for (int e = threadIdx.x; e < MP * (MP / 8); e += 512) {
+      for (int e = threadIdx.x; e < NB * 16 * (MP / 8); e += 512) {
         const int r = e / (MP / 8), n = (e % (MP / 8)) * 8;
         const uint4 v = *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
         const int nb = n >> 4, g0 = (n & 15) >> 2;  // entries n..n+3 in group g0, n+4..n+7 in g0+1
@@ -70,9 +81,10 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
         *reinterpret_cast<uint2*>(Ps + r * SP + pos + 8) = make_uint2(v.z, v.w);
       }
     } else {
-      for (int e = threadIdx.x; e < MP * (MP / 4); e += 512) {
+      for (int e = threadIdx.x; e < NB * 16 * (MP / 4); e += 512) {
         const int r = e / (MP / 4), n = (e % (MP / 4)) * 4;
-        *reinterpret_cast<uint4*>(Ps + r * SP + n) =
+        const int pos = C::NS > 1 ? ((n - 16 * nb0) & (MP - 1)) : n;  // rotated for a split
+        *reinterpret_cast<uint4*>(Ps + r * SP + pos) =
             *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
       }
     }
@@ -142,16 +154,20 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
                : 0x80000000u;
   };
   // stage input of this lane's row of a block, accumulator layout
-  auto load_block = [&](uint32_t off, f32x4(&v)[NB]) {
+  // byte offset of register piece i within a row (rotated for a split)
+  auto piece = [&](int i) -> uint32_t {
+    return (uint32_t)(C::NS > 1 ? ((i + nb0) & (NV - 1)) : i) * 64u;
+  };
+  auto load_block = [&](uint32_t off, f32x4(&v)[NV]) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      v[nb] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + nb * 64, 0, 0));
+    for (int nb = 0; nb < NV; ++nb)
+      v[nb] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + piece(nb), 0, 0));
   };
   // shifted operand for the next block: BF16 operand pieces, or FP32 as is
-  constexpr int NPV = CT == DT_BF16 ? MP / 32 : NB;
+  constexpr int NPV = CT == DT_BF16 ? MP / 32 : NV;
   using PV = typename std::conditional<CT == DT_BF16, bf16x8, f32x4>::type;
   // (zeros when `keep` is false: the next block starts a column and has no partner)
-  auto pack = [&](const f32x4(&v)[NB], bool keep, PV(&pv)[NPV]) {
+  auto pack = [&](const f32x4(&v)[NV], bool keep, PV(&pv)[NPV]) {
     if constexpr (CT == DT_BF16) {
 #pragma unroll
       for (int c = 0; c < MP / 32; ++c)
@@ -162,7 +178,7 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
         }
     } else {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) pv[nb] = keep ? v[nb] : f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int nb = 0; nb < NV; ++nb) pv[nb] = keep ? v[nb] : f32x4{0.f, 0.f, 0.f, 0.f};
     }
   };
 
@@ -176,11 +192,17 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   // The loop is unrolled by two so that the operand sets swap roles without
   // copies.
   constexpr int G = NB < 4 ? NB : 4;
-  f32x4 x[S][NB];
+  f32x4 x[S][NV];
   auto body = [&](const int q, const PV(&pv)[NPV], PV(&npv)[NPV]) {
     const uint32_t off = block_off(q, 0, 0, nflat);
     const uint32_t offn = block_off(q, step, f0[q], f1[q]);  // nothing past the segment
     pack(x[q], adj ? fi[q] > 0 : fi[q] + 1 < ni, npv);  // partner of the next block, if any
+    if constexpr (C::NS > 1) {  // the other workgroup's pieces: only the next operand needs them
+#pragma unroll
+      for (int nb = NB; nb < NV; ++nb)
+        x[q][nb] = __builtin_bit_cast(
+            f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + piece(nb), 0, 0));
+    }
     // the LDS operand offset is passed through an empty asm so that the
     // compiler re-reads the power fragments each block instead of hoisting
     // them out of the loop into registers
@@ -219,12 +241,12 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
 #pragma unroll
       for (int nb = n0; nb < n0 + G; ++nb) {
         const auto v = __builtin_bit_cast(u32x4, x[q][nb]);
-        __builtin_amdgcn_raw_buffer_store_b128(v, rout, off + nb * 64, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v, rout, off + piece(nb), 0, 0);
         if constexpr (TAIL) {
-          __builtin_amdgcn_raw_buffer_store_b128(v, rfin, off + nb * 64, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(v, rfin, off + piece(nb), 0, 0);
         } else {
           x[q][nb] = __builtin_bit_cast(
-              f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + nb * 64, 0, 0));
+              f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + piece(nb), 0, 0));
         }
       }
     }
