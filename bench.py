@@ -5,12 +5,16 @@ Workload: 16 sequences x L = 16384 of one shared HiPPO-LegS model (m = 256,
 p = q = 8, B, C, D ~ N(0, 1/m)), one step size per sequence (log-uniform in
 [1e-3, 1e-1]), N = 13 (degree 16383), u ~ N(0, 1), all seeded and synthetic.
 
-A step is one full forward pass over the batch: all N+1 stage launches with
-the fused Bbar u input and C x + D u output, inputs already in HBM. The
-headline is the cascade with BF16 MFMA operands (FP32 accumulation, FP32
-state); the FP32-MFMA cascade and the plain FP32 recursion on the same GPU
-are measured beside it, each with its relative error against the FP64
-oracle on a sample of sequences. Prints one JSON line.
+A step is one full forward pass over the batch: the input pass (Bbar u with
+the leading stages folded) and the remaining stage launches with the fused
+C x + D u output, inputs already in HBM, captured once as a HIP graph and
+replayed. The headline is the cascade with BF16 MFMA operands (FP32
+accumulation, FP32 state); the FP32-MFMA cascade and the plain FP32
+recursion on the same GPU are measured beside it, each with its relative
+error against the FP64 oracle. Kernel statistics for the roofline come from
+a separate eager pass with per-launch HIP events. Prints one JSON line.
+--workload backward|ragged measures the gradient pass and the ragged
+persistent batch instead.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype bf16|f32]
 """
@@ -106,26 +110,41 @@ def main():
     u32 = CC.pack_u(wl, dtype=torch.float32)
     K, Wm = args.steps, args.warmup
 
-    def run(plan, fn_name, steps, warm, timing_kind=None):
+    def run(plan, fn_name, steps, warm, timing_kind=None, graph=False):
+        """Average ms per call over `steps` calls (graph: replays of one captured
+        apply on a side stream), then, with timing_kind, a separate eager pass
+        with per-launch HIP events for the kernel statistics."""
         fn = getattr(plan, fn_name)
         y = torch.empty(plan.layout.y_numel, dtype=plan.state_dtype, device="cuda")
+        g = None
+        if graph:
+            stream = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            g = plan.graph_apply(u32, y, stream)
+            launch = lambda: CC.CascadePlan.graph_launch(g, stream)
+        else:
+            stream = torch.cuda.current_stream()
+            launch = lambda: fn(u32, out=y)
         for _ in range(warm):
-            fn(u32, out=y)
+            launch()
         torch.cuda.synchronize()
-        if timing_kind is not None:
-            plan.timing_read(timing_kind)  # clear warm-up records
-            plan.timing(True)
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0.record()
+        t0.record(stream)
         for _ in range(steps):
-            fn(u32, out=y)
-        t1.record()
+            launch()
+        t1.record(stream)
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1)
+        if g is not None:
+            CC.CascadePlan.graph_destroy(g)
         kern = None
         if timing_kind is not None:
+            plan.timing_read(timing_kind)  # clear earlier records
+            plan.timing(True)
+            for _ in range(min(steps, 10)):
+                fn(u32, out=y)
+            torch.cuda.synchronize()
             plan.timing(False)
             kern = plan.timing_read(timing_kind)
         return y, ms / steps, kern
@@ -159,7 +178,7 @@ def main():
 
     # ---------------- headline: the cascade in the chosen dtype ----------------
     plan = CC.plan_for_workload(wl, compute=args.dtype)
-    y_main, ms_main, kern = run(plan, "apply", K, Wm, timing_kind=B.TIMING_STAGE)
+    y_main, ms_main, kern = run(plan, "apply", K, Wm, timing_kind=B.TIMING_STAGE, graph=True)
     value = total_steps / (ms_main * 1e-3)
     rf = roofline(plan, kern, args.dtype, K)
 
@@ -178,7 +197,7 @@ def main():
     if not args.no_compare:
         other = "f32" if args.dtype == "bf16" else "bf16"
         plan_o = CC.plan_for_workload(wl, compute=other)
-        y_o, ms_o, kern_o = run(plan_o, "apply", K, Wm, timing_kind=B.TIMING_STAGE)
+        y_o, ms_o, kern_o = run(plan_o, "apply", K, Wm, timing_kind=B.TIMING_STAGE, graph=True)
         ys[other] = CC.unpack_y(wl, y_o)
         out[f"cascade_{other}"] = {"value": round(total_steps / (ms_o * 1e-3), 1),
                                     "ms_per_step": round(ms_o, 4),

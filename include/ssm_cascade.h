@@ -116,9 +116,9 @@ typedef struct {
    * 2^j p <= m, if at least 2), -1: none, j > 0: at most j. */
   int32_t input_stages;
   /* Chain kernel: 16-row blocks per wave segment (each segment re-reads one
-   * block, its first block's partner). 0: automatic (blocks of the stage /
-   * 2048, capped at 8 for per-stage launches and 32 for the persistent
-   * launch), otherwise 1..64. */
+   * block, its first block's partner). 0: automatic (per-stage launches:
+   * blocks of the stage / 2048, at most 8; the persistent launch: blocks of
+   * the level / 8192, at most 32), otherwise 1..64. */
   int32_t chain_blocks;
   int32_t reserved[8];   /* must be 0 */
 } ssm_tuning;

@@ -474,10 +474,11 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
           if (lev >= sq.kry && lev <= sq.last)
             blocks += ((int64_t)1 << (lev - 4)) * ((sq.L + ((int64_t)1 << lev) - 1) >> lev);
         }
-      // longer segments than the per-stage launch: fewer items, each paying
-      // one power load and one acquire/release
+      // longer segments than the per-stage launch (fewer items, each paying one
+      // power load and one acquire/release) while a level keeps several items
+      // per compute unit
       const int T = tn.chain_blocks > 0 ? tn.chain_blocks
-                                        : (int)std::min<int64_t>(32, std::max<int64_t>(1, blocks / 2048));
+                                        : (int)std::min<int64_t>(32, std::max<int64_t>(1, blocks / 8192));
       for (int i : order) {
         const SeqDev& sq = P.seqs[i];
         if (lev < sq.kry - 1 || lev > sq.last) continue;
@@ -492,7 +493,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
           const int64_t sh = (int64_t)1 << lev;
           const int64_t nflat = (sh / 16) * ((sq.L + sh - 1) / sh);
           const int64_t nseg = (nflat + T - 1) / T;
-          const int per_unit = 8 * chain_segments_persist(P.ops[sq.op].mp, (int)compute);
+          const int per_unit = 8 * chain_segments_persist(P.ops[sq.op].mp, (int)compute, lev == sq.last);
           for (int64_t g0 = 0; g0 < nseg; g0 += per_unit) {
             P.ritems.push_back(RItem{i, lev, RI_CHAIN, (int32_t)g0, T, lev, lev == sq.last ? 1 : 0, 0});
             ++target;

@@ -26,7 +26,10 @@ constexpr int persist_segments(int mp, int ct) {
   return ct == DT_BF16 ? 256 / mp : (mp == 64 ? 2 : 1);
 }
 
-int chain_segments_persist(int mp, int ct) { return persist_segments(mp, ct); }
+int chain_segments_persist(int mp, int ct, bool tail) {
+  (void)tail;
+  return persist_segments(mp, ct);
+}
 
 template <int MP, int CT>
 __device__ __forceinline__ void persist_item(const StageParams& base, const RItem& w, void* x0,

@@ -279,8 +279,9 @@ hipError_t launch_persistent(int ct, const PersistParams& pp, int grid, hipStrea
 // (BF16 at padded m 64..256, FP32 at 64 and 128: no split rows); lds: dynamic LDS bytes for
 // the largest class present (persist_res_lds).
 size_t persist_res_lds(int ct, int max_mp);
-// Segments per wave of a chain item in that launch (a unit spans 8 times as many).
-int chain_segments_persist(int mp, int ct);
+// Segments per wave of a chain item in that launch (a unit spans 8 times as
+// many); an item that ends its sequence (tail) walks one.
+int chain_segments_persist(int mp, int ct, bool tail);
 hipError_t launch_persist_res(int ct, const RPersistParams& pp, int grid, size_t lds, hipStream_t s);
 // Workgroups of the persistent kernel that fit on one compute unit.
 int persistent_blocks_per_cu(int ct);

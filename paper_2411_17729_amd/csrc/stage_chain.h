@@ -25,11 +25,6 @@
 
 namespace ssmc {
 
-// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data
-// format, no swizzle), as used for untyped buffer loads and stores.
-constexpr int kBufferWord3 = 0x00020000;
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 // TAIL: some sequence of the launch ends at this stage (output epilogue or a
 // copy of the final state may be due); otherwise the lean variant runs, which
 // only stores the stage output. S: segments walked side by side by each wave
@@ -67,29 +62,6 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   const bool epi = TAIL && (prm.flags & SF_EPILOGUE) && final_;
   const bool store = !epi || (prm.flags & SF_STORE_AT_EPI);
 
-  // rows nb0 16 .. of P_k (or P_k^T) into LDS, contraction columns permuted for BF16
-  {
-    const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP +
-                  (int64_t)nb0 * 16 * MP;
-    if constexpr (CT == DT_BF16) {
-      for (int e = threadIdx.x; e < NB * 16 * (MP / 8); e += 512) {
-        const int r = e / (MP / 8), n = (e % (MP / 8)) * 8;
-        const uint4 v = *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
-        const int nb = n >> 4, g0 = (n & 15) >> 2;  // entries n..n+3 in group g0, n+4..n+7 in g0+1
-        const int pos = 32 * (nb >> 1) + 8 * g0 + 4 * (nb & 1);
-        *reinterpret_cast<uint2*>(Ps + r * SP + pos) = make_uint2(v.x, v.y);
-        *reinterpret_cast<uint2*>(Ps + r * SP + pos + 8) = make_uint2(v.z, v.w);
-      }
-    } else {
-      for (int e = threadIdx.x; e < NB * 16 * (MP / 4); e += 512) {
-        const int r = e / (MP / 4), n = (e % (MP / 4)) * 4;
-        const int pos = C::NS > 1 ? ((n - 16 * nb0) & (MP - 1)) : n;  // rotated for a split
-        *reinterpret_cast<uint4*>(Ps + r * SP + pos) =
-            *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
-      }
-    }
-    __syncthreads();
-  }
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
@@ -113,8 +85,7 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     fc[q] = f0[q] < nflat ? __builtin_amdgcn_readfirstlane(f[q] / ni) : 0;  // uniform
     fi[q] = f[q] - fc[q] * ni;
   }
-  const int n = f1[0] - f0[0];  // the first segment is the longest
-  if (n <= 0) return;
+  const int n = f1[0] - f0[0];  // the first segment is the longest (n <= 0: no work)
 
   // The sequence's state rows are addressed through buffer resources whose
   // range is exactly its L x MP block: the hardware range check returns zeros
@@ -183,19 +154,25 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   };
 
   const int step = adj ? -1 : 1;
+  // epilogue operands: C (or Bbar^T) rows, D (or D^T), number of outputs
+  const X* ecm = reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout);
+  const X* edm = reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat);
+  const int ew = adj ? sq.p : sq.q;
   // One block of segment q, its rows held in x[q]: keep the block's input as
   // the next block's shifted operand (npv), then for each group of four
   // accumulator pieces add P_k times the shifted rows, store the group and
   // load the same group of the next block into the freed registers, so that
-  // the next block arrives while this one is computed. (A TAIL launch loads
-  // the next block after the output epilogue, which needs the whole block.)
-  // The loop is unrolled by two so that the operand sets swap roles without
-  // copies.
+  // the next block arrives while this one is computed. In a TAIL launch with
+  // at most 16 outputs the epilogue's state part is accumulated group by group
+  // too; with more outputs the epilogue takes the whole block and the next
+  // block is loaded after it. The loop is unrolled by two so that the operand
+  // sets swap roles without copies.
   constexpr int G = NB < 4 ? NB : 4;
   f32x4 x[S][NV];
   auto body = [&](const int q, const PV(&pv)[NPV], PV(&npv)[NPV]) {
     const uint32_t off = block_off(q, 0, 0, nflat);
     const uint32_t offn = block_off(q, step, f0[q], f1[q]);  // nothing past the segment
+    f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};  // outputs of a TAIL block with at most 16 of them
     pack(x[q], adj ? fi[q] > 0 : fi[q] + 1 < ni, npv);  // partner of the next block, if any
     if constexpr (C::NS > 1) {  // the other workgroup's pieces: only the next operand needs them
 #pragma unroll
@@ -242,25 +219,31 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
       for (int nb = n0; nb < n0 + G; ++nb) {
         const auto v = __builtin_bit_cast(u32x4, x[q][nb]);
         __builtin_amdgcn_raw_buffer_store_b128(v, rout, off + piece(nb), 0, 0);
-        if constexpr (TAIL) {
-          __builtin_amdgcn_raw_buffer_store_b128(v, rfin, off + piece(nb), 0, 0);
-        } else {
+        if constexpr (TAIL) __builtin_amdgcn_raw_buffer_store_b128(v, rfin, off + piece(nb), 0, 0);
+      }
+      if constexpr (TAIL) {  // up to 16 outputs: their state part group by group
+        if (epi && ew <= 16) epi_state<G>(ya, &x[q][n0], n0, MP, ecm, j, j < ew, g);
+      }
+      if (!TAIL || !epi || ew <= 16) {  // the group's registers take the next block's rows
+#pragma unroll
+        for (int nb = n0; nb < n0 + G; ++nb)
           x[q][nb] = __builtin_bit_cast(
               f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + piece(nb), 0, 0));
-        }
       }
     }
     if constexpr (TAIL) {
-      if (epi) {  // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
-        const int64_t l = row_at(q, 0) + j;
-        res_epilogue<NB>(x[q], MP, l, l < L,
-                         reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout),
-                         reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat),
-                         adj ? sq.p : sq.q, adj ? sq.q : sq.p, prm.src, prm.src_dtype,
-                         adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
+      // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
+      const int64_t l = row_at(q, 0) + j;
+      if (epi && ew <= 16) {
+        epi_finish(ya, 0, j, j < ew, edm, ew, adj ? sq.q : sq.p, prm.src, prm.src_dtype,
+                   adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
+                   adj ? sq.u_off : sq.y_off, l, l < L, g);
+      } else if (epi) {
+        res_epilogue<NB>(x[q], MP, l, l < L, ecm, edm, ew, adj ? sq.q : sq.p, prm.src,
+                         prm.src_dtype, adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
                          adj ? sq.u_off : sq.y_off, j, g);
+        load_block(offn, x[q]);
       }
-      load_block(offn, x[q]);
     }
     f[q] += step;
     fi[q] += step;
@@ -273,14 +256,42 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     }
   };
 
+  // first loads (each segment's partner block, or zeros, and first block) go
+  // out before the power is staged in LDS, so the two overlap
   PV pa[S][NPV], pb[S][NPV];
+  f32x4 part[S][NV];
 #pragma unroll
   for (int q = 0; q < S; ++q) {
     const bool partner = f1[q] > f0[q] && (adj ? fi[q] + 1 < ni : fi[q] > 0);
-    load_block(partner ? block_off(q, -step, 0, nflat) : 0x80000000u, x[q]);  // partner or zeros
-    pack(x[q], true, pa[q]);
+    load_block(partner ? block_off(q, -step, 0, nflat) : 0x80000000u, part[q]);
     load_block(block_off(q, 0, f0[q], f1[q]), x[q]);
   }
+  // rows nb0 16 .. of P_k (or P_k^T) into LDS, contraction columns permuted for BF16
+  {
+    const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP +
+                  (int64_t)nb0 * 16 * MP;
+    if constexpr (CT == DT_BF16) {
+      for (int e = threadIdx.x; e < NB * 16 * (MP / 8); e += 512) {
+        const int r = e / (MP / 8), n = (e % (MP / 8)) * 8;
+        const uint4 v = *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
+        const int nb = n >> 4, g0 = (n & 15) >> 2;  // entries n..n+3 in group g0, n+4..n+7 in g0+1
+        const int pos = 32 * (nb >> 1) + 8 * g0 + 4 * (nb & 1);
+        *reinterpret_cast<uint2*>(Ps + r * SP + pos) = make_uint2(v.x, v.y);
+        *reinterpret_cast<uint2*>(Ps + r * SP + pos + 8) = make_uint2(v.z, v.w);
+      }
+    } else {
+      for (int e = threadIdx.x; e < NB * 16 * (MP / 4); e += 512) {
+        const int r = e / (MP / 4), n = (e % (MP / 4)) * 4;
+        const int pos = C::NS > 1 ? ((n - 16 * nb0) & (MP - 1)) : n;  // rotated for a split
+        *reinterpret_cast<uint4*>(Ps + r * SP + pos) =
+            *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
+      }
+    }
+    __syncthreads();
+  }
+  if (n <= 0) return;
+#pragma unroll
+  for (int q = 0; q < S; ++q) pack(part[q], true, pa[q]);
   // segments advance in lockstep; a shorter one idles once it is done
   for (int t = 0; t < n; ++t) {  // unrolled by two: the operand sets swap roles
 #pragma unroll

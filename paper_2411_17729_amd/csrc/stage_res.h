@@ -1,8 +1,15 @@
 // Shared pieces of the stage kernels that keep the power resident in LDS.
 #pragma once
+#include <type_traits>
+
 #include "stage_common.h"
 
 namespace ssmc {
+
+// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data
+// format, no swizzle), as used for untyped buffer loads and stores.
+constexpr int kBufferWord3 = 0x00020000;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int MP, int CT>
 struct ResCfg {
@@ -28,6 +35,40 @@ struct ResCfg {
 // the A operand of lane (i, g) is Cm[q0 + i][16 nb + 4 g + v]. The inputs V
 // enter the same accumulator, four channels per step. The result lane (j, g)
 // holds outputs q0 + 4 g + v of time row l.
+// Pieces of the epilogue: the state part for accumulator blocks nb0..nb0+G-1
+// of outputs q0 + i (lane (i, g) supplies row i of Cm) ...
+template <int G>
+__device__ __forceinline__ void epi_state(f32x4& ya, const f32x4* acc, int nb0, int mp,
+                                          const float* cm, int qi, bool qv, int g) {
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const int nb = nb0 + e;
+    const f32x4 cv = qv ? *reinterpret_cast<const f32x4*>(cm + (int64_t)qi * mp + nb * 16 + 4 * g)
+                        : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[v], acc[e][v], ya, 0, 0, 0);
+  }
+}
+// ... and the input part and the store of outputs q0 + 4 g + v of time row l.
+__device__ __forceinline__ void epi_finish(f32x4 ya, int q0, int qi, bool qv, const float* dm,
+                                           int w, int r_in, const void* src, int sdt,
+                                           int64_t src_off, float* dst, int64_t dst_off,
+                                           int64_t l, bool lv, int g) {
+  for (int a = 0; a < (r_in + 3) / 4; ++a) {
+    const int c = 4 * a + g;
+    const float dv = qv && c < r_in ? dm[qi * r_in + c] : 0.f;
+    const float uv = lv && c < r_in ? load_src<float>(src, sdt, src_off + l * r_in + c) : 0.f;
+    ya = __builtin_amdgcn_mfma_f32_16x16x4f32(dv, uv, ya, 0, 0, 0);
+  }
+  if (lv) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int qq = q0 + 4 * g + v;
+      if (qq < w) dst[dst_off + l * w + qq] = ya[v];
+    }
+  }
+}
+
 template <int NB>
 __device__ __forceinline__ void res_epilogue(const f32x4 (&acc)[NB], int mp, int64_t l, bool lv,
                                              const float* cm, const float* dm, int w, int r_in,
@@ -37,26 +78,8 @@ __device__ __forceinline__ void res_epilogue(const f32x4 (&acc)[NB], int mp, int
     const int qi = q0 + j;
     const bool qv = qi < w;
     f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const f32x4 cv = qv ? *reinterpret_cast<const f32x4*>(cm + (int64_t)qi * mp + nb * 16 + 4 * g)
-                          : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[v], acc[nb][v], ya, 0, 0, 0);
-    }
-    for (int a = 0; a < (r_in + 3) / 4; ++a) {
-      const int c = 4 * a + g;
-      const float dv = qv && c < r_in ? dm[qi * r_in + c] : 0.f;
-      const float uv = lv && c < r_in ? load_src<float>(src, sdt, src_off + l * r_in + c) : 0.f;
-      ya = __builtin_amdgcn_mfma_f32_16x16x4f32(dv, uv, ya, 0, 0, 0);
-    }
-    if (lv) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int qq = q0 + 4 * g + v;
-        if (qq < w) dst[dst_off + l * w + qq] = ya[v];
-      }
-    }
+    epi_state<NB>(ya, acc, 0, mp, cm, qi, qv, g);
+    epi_finish(ya, q0, qi, qv, dm, w, r_in, src, sdt, src_off, dst, dst_off, l, lv, g);
   }
 }
 
@@ -261,6 +284,101 @@ __device__ __forceinline__ void krylov_range(const StageParams& prm, const ResRa
     }
   };
   const int nblk = (rg.nrows + 15) / 16;
+  X* dst = reinterpret_cast<X*>(prm.dst);
+  const X* cm = reinterpret_cast<const X*>(prm.small) + o.cout;
+  const X* dm = reinterpret_cast<const X*>(prm.small) + o.dmat;
+  if (vec4 && L * p * 4 <= ((int64_t)1 << 31)) {
+    // Fast path: a block's whole window is fetched with one 16-byte load per
+    // piece (a lane's pieces are fixed offsets from its row's start, so they
+    // are computed once), through a buffer resource over the sequence's u:
+    // rows before the start fall outside its range and read as zeros. The
+    // next block's window is loaded while the current one is computed.
+    constexpr int NW = MP / 16;  // 16-byte pieces per lane and block
+    int32_t koff[NW];
+    bool kval[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int kk0 = CT == DT_BF16 ? 32 * (w >> 1) + 8 * g + 4 * (w & 1) : 16 * w + 4 * g;
+      const int lag = kk0 / p, ch = kk0 - lag * p;
+      kval[w] = kk0 < kdim;
+      koff[w] = (ch - lag * p) * 4;
+    }
+    const auto ru = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(reinterpret_cast<const float*>(usrc) + uoff), (short)0,
+        (int)(uint32_t)(L * p * 4), kBufferWord3);
+    auto gather = [&](int b, f32x4(&wv)[NW]) {
+      const uint32_t base = (uint32_t)(((int64_t)rg.row0 + b * 16 + j) * p * 4);
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        wv[w] = __builtin_bit_cast(
+            f32x4, __builtin_amdgcn_raw_buffer_load_b128(ru, kval[w] ? base + koff[w] : 0x80000000u, 0, 0));
+    };
+    // one block from its window: BF16 operands (already converted) or FP32 pieces
+    using WOP = typename std::conditional<CT == DT_BF16, bf16x8, f32x4>::type;
+    constexpr int NO = CT == DT_BF16 ? MP / 32 : MP / 16;
+    auto block = [&](int b, const WOP(&wo)[NO]) {
+      const int64_t l = (int64_t)rg.row0 + b * 16 + j;
+      const bool lv = l < L && l < (int64_t)rg.row0 + rg.nrows;
+      f32x4 acc[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // the LDS offset goes through an empty asm so that the K fragments are
+      // read per block rather than hoisted out of the block loop into registers
+      int lbase = j * SP + (CT == DT_BF16 ? 8 : 4) * g;
+      asm volatile("" : "+v"(lbase));
+      if constexpr (CT == DT_BF16) {
+#pragma unroll
+        for (int c = 0; c < MP / 32; ++c) {
+          if (32 * c >= kdim) break;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const bf16x8 aop = *reinterpret_cast<const bf16x8*>(Ks + lbase + nb * 16 * SP + 32 * c);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, wo[c], acc[nb], 0, 0, 0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < MP / 16; ++a) {
+          if (16 * a >= kdim) break;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const f32x4 av = *reinterpret_cast<const f32x4*>(Ks + lbase + nb * 16 * SP + 16 * a);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], wo[a][t], acc[nb], 0, 0, 0);
+          }
+        }
+      }
+      if (lv && !epi) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          *reinterpret_cast<f32x4*>(xo + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
+      }
+      if (epi) res_epilogue<NB>(acc, MP, l, lv, cm, dm, sq.q, p, usrc, udt, uoff, dst, sq.y_off, j, g);
+    };
+    f32x4 wv[NW];
+    int b = wave;
+    if (b < nblk) gather(b, wv);
+    for (; b < nblk; b += C::WAVES) {
+      // take this block's window out of wv, then reuse wv for the next block's loads
+      WOP wo[NO];
+      if constexpr (CT == DT_BF16) {
+#pragma unroll
+        for (int c = 0; c < NO; ++c)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            wo[c][e] = (__bf16)wv[2 * c][e];  // round to nearest even
+            wo[c][4 + e] = (__bf16)wv[2 * c + 1][e];
+          }
+      } else {
+#pragma unroll
+        for (int a = 0; a < NO; ++a) wo[a] = wv[a];
+      }
+      if (b + C::WAVES < nblk) gather(b + C::WAVES, wv);
+      block(b, wo);
+    }
+    return;
+  }
   for (int b = wave; b < nblk; b += C::WAVES) {
     const int64_t l = (int64_t)rg.row0 + b * 16 + j;
     const bool lv = l < L && l < (int64_t)rg.row0 + rg.nrows;
@@ -306,10 +424,7 @@ __device__ __forceinline__ void krylov_range(const StageParams& prm, const ResRa
       for (int nb = 0; nb < NB; ++nb)
         *reinterpret_cast<f32x4*>(xo + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
     }
-    if (epi)
-      res_epilogue<NB>(acc, MP, l, lv, reinterpret_cast<const X*>(prm.small) + o.cout,
-                       reinterpret_cast<const X*>(prm.small) + o.dmat, sq.q, p, usrc, udt, uoff,
-                       reinterpret_cast<X*>(prm.dst), sq.y_off, j, g);
+    if (epi) res_epilogue<NB>(acc, MP, l, lv, cm, dm, sq.q, p, usrc, udt, uoff, dst, sq.y_off, j, g);
   }
 }
 
