@@ -35,9 +35,19 @@ if ROOT not in sys.path:
 
 METRIC = "output steps/s + MFMA util: cascade vs recursion on one GPU at rel err vs FP64"
 PEAK = {"hbm_GBps": 8000.0, "bf16_TFLOPs": 2500.0, "f32_TFLOPs": 157.3, "f64_TFLOPs": 78.6}
-# stage kernel of each ssm_stage_kernel value: (name, source file)
-STAGE_KERNELS = {1: ("k_stage", "kernels_stage.hip"), 2: ("k_stage_res", "kernels_stage_res.hip"),
-                 3: ("k_stage_chain", "kernels_stage_chain.hip")}
+# stage kernel of each ssm_stage_kernel value: (name, source files it is built from)
+STAGE_KERNELS = {1: ("k_stage", ("kernels_stage.hip", "stage_common.h")),
+                 2: ("k_stage_res", ("kernels_stage_res.hip", "stage_res.h", "stage_common.h")),
+                 3: ("k_stage_chain", ("kernels_stage_chain.hip", "stage_chain.h", "stage_res.h",
+                                       "stage_common.h"))}
+
+
+def kernel_sha256(kernel):
+    """SHA-256 over the concatenated sources of a stage kernel."""
+    h = hashlib.sha256()
+    for f in STAGE_KERNELS[kernel][1]:
+        h.update(open(os.path.join(ROOT, "paper_2411_17729_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def _args():
@@ -65,14 +75,12 @@ def _args():
 def _stage_traffic(workload, dtype, kernel):
     """HBM bytes per stage launch from committed rocprofv3 counter runs, if
     they were taken on the current source of this stage kernel."""
-    name, src = STAGE_KERNELS[kernel]
+    name = STAGE_KERNELS[kernel][0]
     path = os.path.join(ROOT, "profiles", f"stage_traffic_{workload}_{dtype}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2411_17729_amd", "csrc", src), "rb")
-                         .read()).hexdigest()
-    if rec.get("kernel") != name or rec.get("kernel_sha256") != sha:
+    if rec.get("kernel") != name or rec.get("kernel_sha256") != kernel_sha256(kernel):
         return None
     return rec.get("traffic_bytes_per_launch")
 

@@ -101,13 +101,13 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   }
 }
 
-size_t persist_res_lds(int ct, int max_mp) {
+size_t persist_res_lds(int ct, int max_mp) {  // with room for the tail items' C and D
   if (ct == DT_BF16) {
-    if (max_mp <= 64) return ResCfg<64, DT_BF16>::LDS;
-    if (max_mp <= 128) return ResCfg<128, DT_BF16>::LDS;
-    return ResCfg<256, DT_BF16>::LDS;
+    if (max_mp <= 64) return ResCfg<64, DT_BF16>::LDS_TAIL;
+    if (max_mp <= 128) return ResCfg<128, DT_BF16>::LDS_TAIL;
+    return ResCfg<256, DT_BF16>::LDS_TAIL;
   }
-  return max_mp <= 64 ? ResCfg<64, DT_F32>::LDS : ResCfg<128, DT_F32>::LDS;
+  return max_mp <= 64 ? ResCfg<64, DT_F32>::LDS_TAIL : ResCfg<128, DT_F32>::LDS_TAIL;
 }
 
 template <int CT>

@@ -14,14 +14,15 @@ template <int MP, int CT, bool TAIL>
 static hipError_t launch_chain_v(const StageParams& prm, const ChainUnit* units, int n_units,
                                  hipStream_t s) {
   using C = ResCfg<MP, CT>;
+  constexpr size_t lds = TAIL ? C::LDS_TAIL : C::LDS;  // a tail launch stages C and D too
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_chain<MP, CT, TAIL>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_stage_chain<MP, CT, TAIL>), dim3(n_units, C::NS), dim3(512), C::LDS, s, prm,
+  hipLaunchKernelGGL((k_stage_chain<MP, CT, TAIL>), dim3(n_units, C::NS), dim3(512), lds, s, prm,
                      units);
   return hipGetLastError();
 }

@@ -158,6 +158,11 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   const X* ecm = reinterpret_cast<const X*>(prm.small) + (adj ? o.bt : o.cout);
   const X* edm = reinterpret_cast<const X*>(prm.small) + (adj ? o.dt : o.dmat);
   const int ew = adj ? sq.p : sq.q;
+  const int er = adj ? sq.q : sq.p;  // inputs of the epilogue
+  // epilogue from LDS: at most 16 outputs and 16 inputs (the launch brings the LDS)
+  const bool lepi = TAIL && epi && ew <= 16 && er <= 16;
+  float* Cs = reinterpret_cast<float*>(smem_chain + NB * 16 * SP * sizeof(Op));
+  float* Ds = Cs + 16 * C::EPS;
   // One block of segment q, its rows held in x[q]: keep the block's input as
   // the next block's shifted operand (npv), then for each group of four
   // accumulator pieces add P_k times the shifted rows, store the group and
@@ -173,6 +178,18 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     const uint32_t off = block_off(q, 0, 0, nflat);
     const uint32_t offn = block_off(q, step, f0[q], f1[q]);  // nothing past the segment
     f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};  // outputs of a TAIL block with at most 16 of them
+    float uv[4] = {0.f, 0.f, 0.f, 0.f};   // its inputs, loaded before the next block's rows
+    if constexpr (TAIL) {
+      if (lepi) {
+        const int64_t l = row_at(q, 0) + j;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int c = 4 * a + g;
+          if (l < L && c < er)
+            uv[a] = load_src<float>(prm.src, prm.src_dtype, (adj ? sq.y_off : sq.u_off) + l * er + c);
+        }
+      }
+    }
     pack(x[q], adj ? fi[q] > 0 : fi[q] + 1 < ni, npv);  // partner of the next block, if any
     if constexpr (C::NS > 1) {  // the other workgroup's pieces: only the next operand needs them
 #pragma unroll
@@ -222,9 +239,9 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
         if constexpr (TAIL) __builtin_amdgcn_raw_buffer_store_b128(v, rfin, off + piece(nb), 0, 0);
       }
       if constexpr (TAIL) {  // up to 16 outputs: their state part group by group
-        if (epi && ew <= 16) epi_state<G>(ya, &x[q][n0], n0, MP, ecm, j, j < ew, g);
+        if (lepi) epi_state_lds<G>(ya, &x[q][n0], n0, Cs, C::EPS, j, g);
       }
-      if (!TAIL || !epi || ew <= 16) {  // the group's registers take the next block's rows
+      if (!TAIL || !epi || lepi) {  // the group's registers take the next block's rows
 #pragma unroll
         for (int nb = n0; nb < n0 + G; ++nb)
           x[q][nb] = __builtin_bit_cast(
@@ -234,12 +251,11 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     if constexpr (TAIL) {
       // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
       const int64_t l = row_at(q, 0) + j;
-      if (epi && ew <= 16) {
-        epi_finish(ya, 0, j, j < ew, edm, ew, adj ? sq.q : sq.p, prm.src, prm.src_dtype,
-                   adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
-                   adj ? sq.u_off : sq.y_off, l, l < L, g);
+      if (lepi) {
+        epi_finish_lds(ya, Ds, uv, ew, er, reinterpret_cast<X*>(prm.dst), adj ? sq.u_off : sq.y_off,
+                       l, l < L, j, g);
       } else if (epi) {
-        res_epilogue<NB>(x[q], MP, l, l < L, ecm, edm, ew, adj ? sq.q : sq.p, prm.src,
+        res_epilogue<NB>(x[q], MP, l, l < L, ecm, edm, ew, er, prm.src,
                          prm.src_dtype, adj ? sq.y_off : sq.u_off, reinterpret_cast<X*>(prm.dst),
                          adj ? sq.u_off : sq.y_off, j, g);
         load_block(offn, x[q]);
@@ -285,6 +301,17 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
         const int pos = C::NS > 1 ? ((n - 16 * nb0) & (MP - 1)) : n;  // rotated for a split
         *reinterpret_cast<uint4*>(Ps + r * SP + pos) =
             *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
+      }
+    }
+    if (lepi) {  // C rows (zero beyond ew) and D (16 x 16, zero-padded)
+      for (int e = threadIdx.x; e < 16 * (MP / 4); e += 512) {
+        const int r = e / (MP / 4), n = (e % (MP / 4)) * 4;
+        *reinterpret_cast<f32x4*>(Cs + r * C::EPS + n) =
+            r < ew ? *reinterpret_cast<const f32x4*>(ecm + (int64_t)r * MP + n) : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      for (int e = threadIdx.x; e < 256; e += 512) {
+        const int r = e >> 4, c = e & 15;
+        Ds[e] = r < ew && c < er ? edm[r * er + c] : 0.f;
       }
     }
     __syncthreads();

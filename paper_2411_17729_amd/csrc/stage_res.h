@@ -24,6 +24,10 @@ struct ResCfg {
   static constexpr int WAVES = 8;
   static constexpr size_t LDS = (size_t)NR * SP * sizeof(Op);
   static constexpr int NV = MP / 16;  // float4 pieces of a shifted row held per lane
+  // tail launches of the chain walk also stage the output matrices in LDS:
+  // up to 16 rows of C (or Bbar^T) and of D (or D^T, up to 16 columns)
+  static constexpr int EPS = MP + 4;  // LDS row stride of the C rows (floats)
+  static constexpr size_t LDS_TAIL = LDS + (16 * EPS + 16 * 16) * sizeof(float);
 };
 
 // Output epilogue on the matrix cores: for the lane's 16-row block,
@@ -49,6 +53,35 @@ __device__ __forceinline__ void epi_state(f32x4& ya, const f32x4* acc, int nb0, 
     for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[v], acc[e][v], ya, 0, 0, 0);
   }
 }
+// The same two pieces with C rows and D in LDS (rows beyond w are zero) and
+// the block's inputs already in registers (uv[a] = channel 4 a + g).
+template <int G>
+__device__ __forceinline__ void epi_state_lds(f32x4& ya, const f32x4* acc, int nb0,
+                                              const float* cs, int eps, int j, int g) {
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const f32x4 cv = *reinterpret_cast<const f32x4*>(cs + j * eps + (nb0 + e) * 16 + 4 * g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[v], acc[e][v], ya, 0, 0, 0);
+  }
+}
+__device__ __forceinline__ void epi_finish_lds(f32x4 ya, const float* ds, const float* uv, int w,
+                                               int r_in, float* dst, int64_t dst_off, int64_t l,
+                                               bool lv, int j, int g) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (4 * a >= r_in) break;
+    ya = __builtin_amdgcn_mfma_f32_16x16x4f32(ds[j * 16 + 4 * a + g], uv[a], ya, 0, 0, 0);
+  }
+  if (lv) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int qq = 4 * g + v;
+      if (qq < w) dst[dst_off + l * w + qq] = ya[v];
+    }
+  }
+}
+
 // ... and the input part and the store of outputs q0 + 4 g + v of time row l.
 __device__ __forceinline__ void epi_finish(f32x4 ya, int q0, int qi, bool qv, const float* dm,
                                            int w, int r_in, const void* src, int sdt,
