@@ -35,19 +35,35 @@ if ROOT not in sys.path:
 
 METRIC = "output steps/s + MFMA util: cascade vs recursion on one GPU at rel err vs FP64"
 PEAK = {"hbm_GBps": 8000.0, "bf16_TFLOPs": 2500.0, "f32_TFLOPs": 157.3, "f64_TFLOPs": 78.6}
-# stage kernel of each ssm_stage_kernel value: (name, source files it is built from)
-STAGE_KERNELS = {1: ("k_stage", ("kernels_stage.hip", "stage_common.h")),
-                 2: ("k_stage_res", ("kernels_stage_res.hip", "stage_res.h", "stage_common.h")),
-                 3: ("k_stage_chain", ("kernels_stage_chain.hip", "stage_chain.h", "stage_res.h",
-                                       "stage_common.h"))}
+# stage kernels: the source files each is built from
+STAGE_KERNELS = {"k_stage": ("kernels_stage.hip", "stage_common.h"),
+                 "k_stage_res": ("kernels_stage_res.hip", "stage_res.h", "stage_common.h"),
+                 "k_stage_chain": ("kernels_stage_chain.hip", "stage_chain.h", "stage_res.h",
+                                   "stage_common.h"),
+                 "k_stage_pair": ("kernels_stage_pair.hip", "stage_common.h")}
+# the kernel of each ssm_stage_kernel value
+STAGE_KERNEL_IDS = {1: "k_stage", 2: "k_stage_res", 3: "k_stage_chain"}
 
 
-def kernel_sha256(kernel):
+def kernel_sha256(name):
     """SHA-256 over the concatenated sources of a stage kernel."""
     h = hashlib.sha256()
-    for f in STAGE_KERNELS[kernel][1]:
+    for f in STAGE_KERNELS[name]:
         h.update(open(os.path.join(ROOT, "paper_2411_17729_amd", "csrc", f), "rb").read())
     return h.hexdigest()
+
+
+def dominant_kernel(info):
+    """The stage kernel that moves most of an apply's bytes, with its timing kind,
+    launches, compulsory bytes and flops per apply: the stage-pair kernel when
+    the plan pairs stages, else the plan's per-stage kernel over all stage
+    launches."""
+    from paper_2411_17729_amd import binding as B
+    if info["pair_launches"] > 0:
+        return ("k_stage_pair", B.TIMING_PAIR, info["pair_launches"], info["pair_bytes"],
+                info["pair_flops"])
+    return (STAGE_KERNEL_IDS[info["stage_kernel"]], B.TIMING_STAGE, info["stage_launches"],
+            info["stage_bytes"], info["stage_flops"])
 
 
 def _args():
@@ -72,15 +88,14 @@ def _args():
     return ap.parse_args()
 
 
-def _stage_traffic(workload, dtype, kernel):
-    """HBM bytes per stage launch from committed rocprofv3 counter runs, if
-    they were taken on the current source of this stage kernel."""
-    name = STAGE_KERNELS[kernel][0]
+def _stage_traffic(workload, dtype, name):
+    """HBM bytes per launch of a stage kernel from committed rocprofv3 counter
+    runs, if they were taken on the kernel's current source."""
     path = os.path.join(ROOT, "profiles", f"stage_traffic_{workload}_{dtype}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel") != name or rec.get("kernel_sha256") != kernel_sha256(kernel):
+    if rec.get("kernel") != name or rec.get("kernel_sha256") != kernel_sha256(name):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -158,19 +173,18 @@ def main():
         return y, ms / steps, kern
 
     def roofline(plan, kern, dtype, steps):
-        info = plan.info()
+        name, _, launches, nbytes, flops = dominant_kernel(plan.info())
         n_launch, k_ms = kern
         avg_ms = k_ms / max(n_launch, 1)
-        per_launch_bytes = info["stage_bytes"] / info["stage_launches"]
-        per_launch_flops = info["stage_flops"] / info["stage_launches"]
+        per_launch_bytes = nbytes / launches
+        per_launch_flops = flops / launches
         gbps = per_launch_bytes / (avg_ms * 1e-3) / 1e9
         tflops = per_launch_flops / (avg_ms * 1e-3) / 1e12
         peak_tf = PEAK["bf16_TFLOPs"] if dtype == "bf16" else PEAK["f32_TFLOPs"]
-        intensity = info["stage_flops"] / info["stage_bytes"]
+        intensity = flops / nbytes
         ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
         bound = "mfma" if intensity > ridge else "hbm"
-        kid = info["stage_kernel"]
-        traffic = _stage_traffic(wname, dtype, kid)
+        traffic = _stage_traffic(wname, dtype, name)
         if bound == "hbm":
             rf = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"],
                   "unit": "GB/s", "frac": round(gbps / PEAK["hbm_GBps"], 4)}
@@ -178,7 +192,7 @@ def main():
             rf = {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak_tf,
                   "unit": "TFLOP/s", "frac": round(tflops / peak_tf, 4)}
         rf["traffic"] = traffic
-        rf.update({"kernel": STAGE_KERNELS[kid][0], "launches_timed": n_launch, "avg_launch_ms": round(avg_ms, 5),
+        rf.update({"kernel": name, "launches_timed": n_launch, "avg_launch_ms": round(avg_ms, 5),
                    "algorithmic_bytes_per_launch": round(per_launch_bytes),
                    "algorithmic_flops_per_launch": round(per_launch_flops),
                    "mfma_util": round(tflops / peak_tf, 4), "hbm_GBps": round(gbps, 1)})
@@ -186,7 +200,8 @@ def main():
 
     # ---------------- headline: the cascade in the chosen dtype ----------------
     plan = CC.plan_for_workload(wl, compute=args.dtype)
-    y_main, ms_main, kern = run(plan, "apply", K, Wm, timing_kind=B.TIMING_STAGE, graph=True)
+    y_main, ms_main, kern = run(plan, "apply", K, Wm, timing_kind=dominant_kernel(plan.info())[1],
+                                graph=True)
     value = total_steps / (ms_main * 1e-3)
     rf = roofline(plan, kern, args.dtype, K)
 
@@ -205,7 +220,8 @@ def main():
     if not args.no_compare:
         other = "f32" if args.dtype == "bf16" else "bf16"
         plan_o = CC.plan_for_workload(wl, compute=other)
-        y_o, ms_o, kern_o = run(plan_o, "apply", K, Wm, timing_kind=B.TIMING_STAGE, graph=True)
+        y_o, ms_o, kern_o = run(plan_o, "apply", K, Wm, timing_kind=dominant_kernel(plan_o.info())[1],
+                                graph=True)
         ys[other] = CC.unpack_y(wl, y_o)
         out[f"cascade_{other}"] = {"value": round(total_steps / (ms_o * 1e-3), 1),
                                     "ms_per_step": round(ms_o, 4),

@@ -120,7 +120,21 @@ typedef struct {
    * blocks of the stage / 2048, at most 8; the persistent launch: blocks of
    * the level / 8192, at most 32), otherwise 1..64. */
   int32_t chain_blocks;
-  int32_t reserved[8];   /* must be 0 */
+  /* Stage pairs (forward apply with per-stage launches and the chain kernel;
+   * BF16 at padded m of 128 and 256): two consecutive stages that are lean for
+   * every sequence of a class run as one pass over the state,
+   *   w_l = y_l + P_{k+1} y_{l-2^{k+1}},  y_l = x_l + P_k x_{l-2^k},
+   * which moves each state row through HBM once for both stages. A workgroup
+   * walks a segment of 16-row blocks of one column of stage k; its eight waves
+   * split the state entries and exchange each block's x and y (rounded to
+   * BF16, the operand type) through LDS. 0: automatic (on where supported),
+   * 1: off. */
+  int32_t pair_stages;
+  /* 16-row blocks per workgroup segment of a stage pair (a segment also reads
+   * up to three blocks before it to rebuild its partners). 0: automatic
+   * (blocks of the stage / 256, clamped to 8..64), otherwise 4..256. */
+  int32_t pair_blocks;
+  int32_t reserved[6];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -170,6 +184,12 @@ typedef struct {
   int32_t tile_rows[4];      /* rows per stage tile per padded state size */
   int32_t persistent_grid;   /* workgroups of the persistent launch */
   int64_t persistent_items;  /* work items of the persistent launch */
+  int64_t pair_launches;     /* stage-pair launches per apply (counted once in
+                                stage_launches; their compulsory bytes, one read
+                                and one write of each row for both stages, are
+                                part of stage_bytes) */
+  double pair_bytes;         /* compulsory HBM bytes of the stage-pair launches */
+  double pair_flops;         /* stage flops of the stage-pair launches */
 } ssm_plan_info;
 
 typedef struct ssm_plan_s* ssm_plan;
@@ -261,7 +281,8 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);
  * around every kernel launch (this adds host work; leave it off otherwise).
  * ssm_cascade_timing_read returns, for kernel class `kind`
  * (0 = forward stage, 1 = adjoint stage, 2 = outer-product reduction,
- *  3 = recursion), the number of timed launches and their summed milliseconds,
+ *  3 = recursion, 4 = forward stage pair), the number of timed launches and
+ * their summed milliseconds,
  * after synchronizing the events, and clears the record. */
 ssm_status ssm_cascade_timing_enable(ssm_plan plan, int32_t enable);
 ssm_status ssm_cascade_timing_read(ssm_plan plan, int32_t kind, int64_t* launches,

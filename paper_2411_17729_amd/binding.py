@@ -27,7 +27,7 @@ SSM_LAUNCH_AUTO, SSM_LAUNCH_PER_STAGE, SSM_LAUNCH_PERSISTENT = 0, 1, 2
 SSM_STAGE_AUTO, SSM_STAGE_TILED, SSM_STAGE_RESIDENT, SSM_STAGE_CHAIN = 0, 1, 2, 3
 
 # kernel classes of ssm_cascade_timing_read
-TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION = 0, 1, 2, 3
+TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION, TIMING_PAIR = 0, 1, 2, 3, 4
 
 
 class SSMError(RuntimeError):
@@ -54,7 +54,8 @@ class ssm_params(C.Structure):
 
 class ssm_tuning(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
-                ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
+                ("pair_blocks", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class ssm_plan_info(C.Structure):
@@ -64,17 +65,20 @@ class ssm_plan_info(C.Structure):
         ("stage_bytes", C.c_double), ("stage_launches", C.c_int64), ("launch", C.c_int32),
         ("stage_kernel", C.c_int32), ("input_stages", C.c_int32), ("tile_rows", C.c_int32 * 4),
         ("persistent_grid", C.c_int32),
-        ("persistent_items", C.c_int64),
+        ("persistent_items", C.c_int64), ("pair_launches", C.c_int64), ("pair_bytes", C.c_double),
+        ("pair_flops", C.c_double),
     ]
 
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
-                input_stages=0, chain_blocks=0):
+                input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0):
     t = ssm_tuning()
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
     t.input_stages = int(input_stages)
     t.chain_blocks = int(chain_blocks)
+    t.pair_stages = int(pair_stages)
+    t.pair_blocks = int(pair_blocks)
     for i, r in enumerate(tile_rows):
         t.tile_rows[i] = int(r)
     return t

@@ -126,6 +126,12 @@ struct ssm_plan_s {
   std::vector<ChainUnit> chain_units;
   std::vector<int> chain_start[4], chain_count[4], chain_T[4];
   size_t m_chain = 0;
+  // stage pairs of the forward apply: units per class at the pair's first stage
+  std::vector<PairUnit> pair_units;
+  std::vector<int> pair_start[4], pair_count[4];
+  size_t m_pair = 0;
+  int64_t pair_launches = 0;
+  double pair_bytes = 0, pair_flops = 0;
   // persistent launch
   std::vector<PItem> items;
   std::vector<int32_t> cnt_off, ntiles;
@@ -208,6 +214,10 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     return fail(SSM_E_UNSUPPORTED, "the resident and chain stage kernels take BF16 or FP32 operands");
   if (tn.chain_blocks < 0 || tn.chain_blocks > 64)
     return fail(SSM_E_INVALID, "chain_blocks = %d: supported 0 (automatic) or 1..64", tn.chain_blocks);
+  if (tn.pair_stages < 0 || tn.pair_stages > 1)
+    return fail(SSM_E_INVALID, "pair_stages = %d: supported 0 (automatic) or 1 (off)", tn.pair_stages);
+  if (tn.pair_blocks != 0 && (tn.pair_blocks < 4 || tn.pair_blocks > 256))
+    return fail(SSM_E_INVALID, "pair_blocks = %d: supported 0 (automatic) or 4..256", tn.pair_blocks);
   if (tn.stage_kernel == SSM_STAGE_TILED || compute == SSM_F64)
     P.stage_kernel = SSM_STAGE_TILED;
   else
@@ -443,6 +453,47 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   for (int c = 0; c < 4; ++c)
     if (P.class_min_kry[c] == (1 << 30)) P.class_min_kry[c] = 0;
 
+  // Stage pairs (forward apply, per-stage launches): stages k, k + 1 fused
+  // where every sequence of the class runs both as lean stages, i.e. from the
+  // largest folded stage count on and below the earliest last stage. Units are
+  // segments of T blocks in the numbering of stage k, longest sequences first.
+  P.pair_units.clear();
+  for (int c = 0; c < 4; ++c) {
+    const int ml = P.class_max_last[c];
+    P.pair_start[c].assign(std::max(ml + 1, 0), 0);
+    P.pair_count[c].assign(std::max(ml + 1, 0), 0);
+    if (ml < 0 || tn.pair_stages == 1 || P.launch != SSM_LAUNCH_PER_STAGE ||
+        P.stage_kernel != SSM_STAGE_CHAIN || !pair_supported(kClassMp[c], (int)compute))
+      continue;
+    std::vector<int> ids;
+    int max_kry = 0, min_last = 1 << 30;
+    bool fits = true;
+    for (int i = 0; i < n_seq; ++i)
+      if (P.ops[P.seqs[i].op].mp == kClassMp[c]) {
+        ids.push_back(i);
+        max_kry = std::max(max_kry, P.seqs[i].kry);
+        min_last = std::min(min_last, P.seqs[i].last);
+        fits = fits && P.seqs[i].L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
+      }
+    if (!fits) continue;
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
+    for (int kk = std::max(4, max_kry); kk + 1 < min_last; kk += 2) {
+      const int64_t sh = (int64_t)1 << kk;
+      int64_t blocks = 0;
+      for (int i : ids) blocks += (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
+      const int T = tn.pair_blocks > 0 ? tn.pair_blocks
+                                       : (int)std::min<int64_t>(64, std::max<int64_t>(8, blocks / 256));
+      P.pair_start[c][kk] = (int)P.pair_units.size();
+      for (int i : ids) {
+        const int64_t nflat = (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
+        for (int64_t f0 = 0; f0 < nflat; f0 += T)
+          P.pair_units.push_back(PairUnit{i, (int32_t)f0, T, 0});
+      }
+      P.pair_count[c][kk] = (int)P.pair_units.size() - P.pair_start[c][kk];
+    }
+  }
+
   // persistent work items, level by level (projection = level -1), longer
   // sequences first inside a level; default tile heights
   P.items.clear();
@@ -571,10 +622,21 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // instead of the state. The shifted partner of a row is a row of the same
   // stage input, so it adds no compulsory traffic.
   const double xe = (double)P.x_elem();
+  auto pair_at = [&](int c, int kk) {
+    return kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
+  };
   P.stage_launches = 0;
+  P.pair_launches = 0;
+  P.pair_bytes = P.pair_flops = 0;
   for (int c = 0; c < 4; ++c)
-    if (P.class_max_last[c] >= 0)
+    if (P.class_max_last[c] >= 0) {
       P.stage_launches += std::max(0, P.class_max_last[c] + 1 - P.class_min_kry[c]);
+      for (int kk = 0; kk <= P.class_max_last[c]; ++kk)
+        if (pair_at(c, kk)) {
+          --P.stage_launches;  // two stages, one launch
+          ++P.pair_launches;
+        }
+    }
   P.stage_flops = 0;
   for (int i = 0; i < n_seq; ++i) {
     const SeqDev& s = P.seqs[i];
@@ -583,10 +645,19 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       const int64_t sh = (int64_t)1 << kk;
       if (sh < s.L) P.stage_flops += 2.0 * m * m * (double)(s.L - sh);
     }
+    const int c = class_of(P.ops[s.op].mp);
     for (int kk = s.kry; kk <= s.last; ++kk) {
       const double in_row = (double)m * xe;
       const double out_row = kk == s.last ? (double)s.q * xe : (double)m * xe;
       P.stage_bytes += s.L * (in_row + out_row);
+      if (pair_at(c, kk)) {  // the pair's second stage moves no further rows
+        P.pair_bytes += s.L * (in_row + out_row);
+        for (int h = 0; h < 2; ++h) {
+          const int64_t sh = (int64_t)1 << (kk + h);
+          if (sh < s.L) P.pair_flops += 2.0 * m * m * (double)(s.L - sh);
+        }
+        ++kk;
+      }
     }
   }
 
@@ -673,6 +744,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.ranges.size()));
   P.m_chain = off;
   off = align_up(off + sizeof(ChainUnit) * std::max<size_t>(1, P.chain_units.size()));
+  P.m_pair = off;
+  off = align_up(off + sizeof(PairUnit) * std::max<size_t>(1, P.pair_units.size()));
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
     P.m_ritems = off;
     off = align_up(off + sizeof(RItem) * std::max<size_t>(1, P.ritems.size()));
@@ -1217,6 +1290,9 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (!P->chain_units.empty())
     std::memcpy(P->meta_host.data() + P->m_chain, P->chain_units.data(),
                 sizeof(ChainUnit) * P->chain_units.size());
+  if (!P->pair_units.empty())
+    std::memcpy(P->meta_host.data() + P->m_pair, P->pair_units.data(),
+                sizeof(PairUnit) * P->pair_units.size());
   if (P->launch == SSM_LAUNCH_PERSISTENT) {
     unsigned char* mh = P->meta_host.data();
     if (!P->items.empty())
@@ -1405,15 +1481,28 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       prm.skip_kry = 1;
       k_begin = P.class_min_kry[c];
     }
-    for (int kk = k_begin; kk <= P.class_max_last[c]; ++kk) {
+    // the input of stage kk is in buffer kk % 2 until the first stage pair;
+    // from there on every sequence of the class runs every stage, and the
+    // buffers simply alternate per launch
+    int cur = k_begin & 1;
+    for (int kk = k_begin; kk <= P.class_max_last[c];) {
       prm.k = kk;
-      prm.xin = P.ws + ((kk & 1) ? P.r_x1.off : P.r_x0.off);
-      prm.xout = P.ws + ((kk & 1) ? P.r_x0.off : P.r_x1.off);
+      prm.xin = P.ws + (cur ? P.r_x1.off : P.r_x0.off);
+      prm.xout = P.ws + (cur ? P.r_x0.off : P.r_x1.off);
       prm.n_tiles = P.class_active[c][kk];
-      TimedLaunch tl(P, stream, 0);
-      e = launch_stage_any(P, c, prm, stream);
+      const bool pair = kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
+      TimedLaunch tl(P, stream, pair ? 4 : 0);
+      if (pair) {
+        const PairUnit* un = reinterpret_cast<const PairUnit*>(P.ws + P.r_meta.off + P.m_pair) +
+                             P.pair_start[c][kk];
+        e = launch_stage_pair(kClassMp[c], P.compute, prm, un, P.pair_count[c][kk], stream);
+      } else {
+        e = launch_stage_any(P, c, prm, stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "stage launch");
       tl.done();
+      cur ^= 1;
+      kk += pair ? 2 : 1;
     }
   }
   return SSM_OK;
@@ -1693,6 +1782,9 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   for (int c = 0; c < 4; ++c) info->tile_rows[c] = plan->class_bm[c];
   info->persistent_grid = plan->persistent_grid;
   info->persistent_items = (int64_t)(plan->persist_res ? plan->ritems.size() : plan->items.size());
+  info->pair_launches = plan->pair_launches;
+  info->pair_bytes = plan->pair_bytes;
+  info->pair_flops = plan->pair_flops;
   return SSM_OK;
 }
 

@@ -1,0 +1,234 @@
+// Two consecutive lean stages of the forward cascade in one pass over the state.
+//
+// Stages k and k+1 are two factors of the product of §2 (eq. (2.2)) applied as
+// in §3: with y_l = x_l + P_k x_{l-2^k} they give
+//   w_l = y_l + P_{k+1} y_{l-2^{k+1}},  P_{k+1} = P_k^2.
+// In the column numbering of stage k (16-row blocks spaced 2^k apart; block i
+// of column c holds rows i 2^k + 16 c + r, r < 16) the stage-k partner of
+// block i is block i - 1 of the same column and the stage-(k+1) partner is
+// block i - 2. A workgroup walks T consecutive blocks of the numbering. Its
+// eight waves split the state entries, wave w owning entries w m/8 .. (w+1)
+// m/8 - 1, and keep the rows of P_k and P_{k+1} for them in registers as MFMA
+// A operands; the time rows of a block are the MFMA columns. A block's y needs
+// every wave's share of the previous block's x, and its w the y of two blocks
+// back, so both are exchanged through LDS in BF16, the operand type of the
+// per-stage kernels (which round the FP32 stage input the same way). Three
+// warm-up blocks before the segment, inside its column, rebuild those
+// partners: a segment reads T + 3 blocks (fewer at a column start) and writes
+// T, for two stages.
+//
+// Each block's rows are loaded DP blocks ahead into registers; one barrier
+// per block orders the LDS exchange (x of a block is read by the next block,
+// y two blocks later, and the slots rotate through two and three buffers).
+#include "stage_common.h"
+#include "ssm_internal.h"
+
+#ifndef PAIR_DP
+#define PAIR_DP 4
+#endif
+
+namespace ssmc {
+
+template <int MP>
+struct PairCfg {
+  static constexpr int NW = 8;             // waves of a workgroup
+  static constexpr int DW = MP / NW;       // state entries of a wave
+  static constexpr int NT = DW / 16;       // MFMA output tiles of a wave
+  static constexpr int KS = MP / 32;       // MFMA steps of one contraction
+  static constexpr int RS = MP + 8;        // LDS row stride in BF16 entries (16-byte pad)
+  static constexpr int SLOT = 16 * RS;     // one block of 16 time rows
+  static constexpr int DP = PAIR_DP;  // blocks loaded ahead
+  static constexpr size_t LDS = 5 * SLOT * sizeof(__bf16);  // x: 2 slots, y: 3 slots
+};
+
+template <int MP>
+__global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_stage_pair(
+    StageParams prm, const PairUnit* units) {
+  using C = PairCfg<MP>;
+  constexpr int NT = C::NT, KS = C::KS, DP = C::DP, RS = C::RS, SLOT = C::SLOT;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pair[];
+  __bf16* xs = reinterpret_cast<__bf16*>(smem_pair);
+  __bf16* ys = xs + 2 * SLOT;
+
+  const PairUnit un = units[blockIdx.x];
+  const SeqDev sq = prm.seqs[un.seq];
+  const OpDev o = prm.ops[sq.op];
+  const int k = prm.k;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = lane & 15, g = lane >> 4;
+  // 32-bit indices: the host keeps L MP 4 <= 2^31 and 2^(k+1) < L
+  const int L = (int)sq.L;
+  const int ni = (L + (1 << k) - 1) >> k;  // blocks per column
+  const int nflat = (1 << (k - 4)) * ni;
+  const int f0 = un.f0;
+  const int f1 = min(f0 + un.T, nflat);
+  if (f0 >= f1) return;  // the whole workgroup
+  const int c0 = f0 / ni, i0 = f0 - c0 * ni;
+  const int nw = min(3, i0);      // warm-up blocks (they stay in the segment's first column)
+  const int nit = f1 - f0 + nw;   // blocks visited
+
+  // Rows of P_k and P_{k+1} owned by this wave, as A operands: row index r of
+  // output tile t is state entry ent(t, r). Contraction step s covers entries
+  // 32 s .. 32 s + 31 with operand slot 8 g + 4 h + e holding entry
+  // 32 s + 16 h + 4 g + e, the assignment of the chain kernel, so that every
+  // output sees the same products in the same MFMA steps as there.
+  auto ent = [&](int t, int rr) { return wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3); };
+  bf16x8 pa[2][NT][KS];
+  {
+    const __bf16* P0 = reinterpret_cast<const __bf16*>(prm.P) + o.pc + (int64_t)k * MP * MP;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const __bf16* row = P0 + (int64_t)h * MP * MP + ent(t, r) * MP + 32 * s + 4 * g;
+          const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row);
+          const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 16);
+          pa[h][t][s] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+  }
+
+  // State rows through buffer resources over the sequence's L x MP block:
+  // rows past L read as zero and their stores are dropped; offset 2^31 marks
+  // an absent block.
+  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * 4);
+  const auto rin = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(reinterpret_cast<const float*>(prm.xin)) + sq.x_off, (short)0, (int)nrec,
+      kBufferWord3);
+  const auto rout = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float*>(prm.xout) + sq.x_off,
+                                                      (short)0, (int)nrec, kBufferWord3);
+  // this lane's entries of a block: time row r, entries wave DW + 4 NT g .. + 4 NT - 1
+  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * NT * g) * 4u;
+  auto row_off = [&](int col, int i) -> uint32_t {
+    return lane_off + (uint32_t)((i << k) + 16 * col) * (uint32_t)(MP * 4);
+  };
+
+  // Blocks are loaded DP visits ahead into a ring of registers; a block is
+  // accumulated in place and its registers take the load of the block DP
+  // visits later once it is stored. The visits are padded to a multiple of
+  // DP, and loads and stores are issued on every visit (out of range where
+  // there is nothing to move), so every path has the same memory operations
+  // in flight and the compiler's counter waits stay exact.
+  const int npad = (nit + DP - 1) / DP * DP;
+  f32x4 xr[DP][NT];
+  int lc = c0, li = i0 - nw, nl = 0;  // next block to load and how many were issued
+  auto issue = [&](f32x4(&v)[NT]) {
+    const uint32_t off = nl < nit ? row_off(lc, li) : 0x80000000u;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      v[t] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + 16 * t, 0, 0));
+    ++nl;
+    if (++li == ni) {
+      li = 0;
+      ++lc;
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < DP; ++u) {
+    issue(xr[u]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the ring's loads in visit order
+  }
+
+  // LDS rows hold a block's entries in operand order: entry n at position
+  // 32 (n / 32) + 8 ((n / 4) mod 4) + 4 ((n / 16) mod 2) + n mod 4, so that the
+  // B operand of step s is the 16 bytes at 32 s + 8 g of row r. This lane
+  // writes its 4 NT entries of row r as NT groups of four.
+  auto pos = [](int n) { return 32 * (n >> 5) + 8 * ((n >> 2) & 3) + 4 * ((n >> 4) & 1) + (n & 3); };
+  int wr[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) wr[t] = r * RS + pos(wave * C::DW + 4 * NT * g + 4 * t);
+  const int rd = r * RS + 8 * g;
+  auto put = [&](__bf16* slot, const f32x4(&v)[NT]) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bf16x4 b;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[e] = (__bf16)v[t][e];  // round to nearest even
+      *reinterpret_cast<bf16x4*>(slot + wr[t]) = b;
+    }
+  };
+  auto fetch = [&](const __bf16* slot, bf16x8(&b)[KS]) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b[s] = *reinterpret_cast<const bf16x8*>(slot + rd + 32 * s);
+  };
+  // operands of a visit without that partner are zeros (a select, so stale
+  // LDS contents cannot leak in)
+  auto keep = [&](bool on, bf16x8(&b)[KS]) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b[s] = on ? b[s] : bf16x8{};
+  };
+  auto contract = [&](const bf16x8(&a)[NT][KS], const bf16x8(&b)[KS], f32x4(&acc)[NT]) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][s], b[s], acc[t], 0, 0, 0);
+  };
+
+  int cc = c0, ci = i0 - nw;  // block being computed
+  int ysl = 0;                // its y slot (visit index mod 3)
+  for (int it0 = 0; it0 < npad; it0 += DP) {
+#pragma unroll
+    for (int u = 0; u < DP; ++u) {
+      const int it = it0 + u;
+      const bool real = it < nit;  // padding visits move nothing
+      const bool out = real && it >= nw;
+      const uint32_t off = out ? row_off(cc, ci) : 0x80000000u;
+      const int ysl2 = ysl == 2 ? 0 : ysl + 1;  // slot of the y two blocks back: it - 2 = it + 1 mod 3
+      put(xs + (it & 1) * SLOT, xr[u]);
+      bf16x8 b[KS];
+      fetch(xs + ((it + 1) & 1) * SLOT, b);
+      // y = x + P_k x_prev (no partner at a column's first block; the first of
+      // three warm-up blocks only provides x)
+      keep(real && ci >= 1 && it > nw - 3, b);
+      contract(pa[0], b, xr[u]);
+      put(ys + ysl * SLOT, xr[u]);
+      // w = y + P_{k+1} y_prev2
+      fetch(ys + ysl2 * SLOT, b);
+      keep(out && ci >= 2, b);
+      contract(pa[1], b, xr[u]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, xr[u][t]), rout, off + 16 * t, 0, 0);
+      issue(xr[u]);
+      __syncthreads();
+      ysl = ysl2;
+      if (++ci == ni) {
+        ci = 0;
+        ++cc;
+      }
+    }
+  }
+}
+
+template <int MP>
+static hipError_t launch_pair_t(const StageParams& prm, const PairUnit* units, int n_units,
+                                hipStream_t s) {
+  using C = PairCfg<MP>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_pair<MP>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_stage_pair<MP>), dim3(n_units), dim3(512), C::LDS, s, prm, units);
+  return hipGetLastError();
+}
+
+bool pair_supported(int mp, int ct) { return ct == DT_BF16 && (mp == 128 || mp == 256); }
+
+hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
+                             int n_units, hipStream_t s) {
+  if (n_units <= 0) return hipSuccess;
+  if (ct != DT_BF16 || prm.adjoint) return hipErrorInvalidValue;
+  switch (mp) {
+    case 128: return launch_pair_t<128>(prm, units, n_units, s);
+    case 256: return launch_pair_t<256>(prm, units, n_units, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ssmc

@@ -99,6 +99,12 @@ struct ChainUnit {
   int32_t seq, seg0, T, reserved;
 };
 
+// Work of one stage-pair workgroup at stages k, k+1: blocks f0 .. f0 + T - 1
+// of sequence seq in the column-by-column numbering of stage k.
+struct PairUnit {
+  int32_t seq, f0, T, reserved;
+};
+
 // ---- persistent ragged launch ----
 // One row tile of one stage (k >= 0), or of the input projection (k == -1),
 // of one sequence. Items are ordered by stage level.
@@ -270,6 +276,12 @@ bool chain_supported(int mp, int ct);
 // epilogue or the final-state copy may be due); false selects the lean variant.
 hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const ChainUnit* units,
                               int n_units, bool tail, hipStream_t s);
+// Stages prm.k and prm.k + 1 of the forward cascade in one pass (both lean for
+// every sequence of the units; 2^k >= 16): BF16 at padded m of 128 and 256.
+// prm.xin and prm.xout must be different buffers.
+bool pair_supported(int mp, int ct);
+hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
+                             int n_units, hipStream_t s);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);

@@ -9,8 +9,13 @@ namespace ssmc {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> bfloat16, round to nearest even (NaN stays NaN).
+// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data
+// format, no swizzle), as used for untyped buffer loads and stores.
+constexpr int kBufferWord3 = 0x00020000;
+
 // FP32 -> BF16, round to nearest even (NaN stays NaN): the conversion
 // instruction of gfx950 (v_cvt_pk_bf16_f32), branch-free.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {

@@ -6,11 +6,6 @@
 
 namespace ssmc {
 
-// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data
-// format, no swizzle), as used for untyped buffer loads and stores.
-constexpr int kBufferWord3 = 0x00020000;
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 template <int MP, int CT>
 struct ResCfg {
   using TR = CTraits<CT>;
