@@ -105,3 +105,22 @@ def test_pair_graph_replays():
             assert torch.equal(y, ref), rep
     finally:
         CC.CascadePlan.graph_destroy(g)
+
+
+def test_pair_from_stage4():
+    # 2^5 p > padded m folds four stages: the first pair is (4, 5), whose
+    # columns are single 16-row blocks apart; bitwise equal to the unpaired
+    # plan and within the BF16 bound of the oracle
+    from paper_2411_17729_amd import cascade as CC
+    spec = [(256, 16, 4, 3000, 11), (256, 16, 8, 2049, 11), (128, 8, 2, 1777, 10), (100, 8, 3, 1500, 10)]
+    wl = _workload(45, spec=spec)
+    yp, ip = _apply(wl)
+    yu, iu = _apply(wl, pair_stages=1)
+    assert ip["input_stages"] == 4 and ip["pair_launches"] == 6 and iu["pair_launches"] == 0
+    assert torch.equal(yp, yu)
+    got = CC.unpack_y(wl, yp)
+    ref = _oracle(wl)
+    for i in range(len(wl.seqs)):
+        e = rel_err(got[i], ref[i])
+        print("seq", i, f"{e:.2e}", flush=True)
+        assert e <= 2e-2, (i, e)
