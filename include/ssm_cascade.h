@@ -107,13 +107,14 @@ typedef struct {
   int32_t launch;        /* ssm_launch */
   int32_t tile_rows[4];
   int32_t stage_kernel;  /* ssm_stage_kernel, per-stage launches only */
-  /* Leading stages folded into the input pass (resident kernel, per-stage
-   * launches): after stages 0..j-1 the state is
+  /* Leading stages folded into the input pass (per-stage launches and the
+   * resident persistent launch): after stages 0..j-1 the state is
    *   x_l = sum_{i < 2^j} Abar^i Bbar u_{l-i} = K_j [u_l; u_{l-1}; ...; u_{l-2^j+1}]
    * with K_j = [Bbar, Abar Bbar, ..., Abar^(2^j - 1) Bbar] built by doubling
    * with the powers, K_{i+1} = [K_i | P_i K_i], i.e. the product of the first j
    * factors of eq. (2.2) applied to Bbar. 0: automatic (the largest j with
-   * 2^j p <= m, if at least 2), -1: none, j > 0: at most j. */
+   * 2^j p <= m, if at least 2, or 2^j p <= 2 m for the split input pass), -1:
+   * none, j > 0: at most j. */
   int32_t input_stages;
   /* Chain kernel: 16-row blocks per wave segment (each segment re-reads one
    * block, its first block's partner). 0: automatic (per-stage launches:
@@ -134,7 +135,14 @@ typedef struct {
    * up to three blocks before it to rebuild its partners). 0: automatic
    * (blocks of the stage / 256, clamped to 8..64), otherwise 4..256. */
   int32_t pair_blocks;
-  int32_t reserved[6];   /* must be 0 */
+  /* Split input pass (per-stage launches with the chain kernels; BF16 at
+   * padded m of 128 and 256, p a multiple of 4): the waves split the state
+   * entries and keep the rows of K_j in registers, so the pass folds stages
+   * while 2^j p <= 2 m (the resident pass: 2^j p <= m), for classes whose
+   * sequences all run stages after the folded ones. 0: automatic (on where
+   * supported), 1: off. */
+  int32_t input_split;
+  int32_t reserved[5];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */

@@ -55,7 +55,7 @@ class ssm_params(C.Structure):
 class ssm_tuning(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
                 ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
-                ("pair_blocks", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("pair_blocks", C.c_int32), ("input_split", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class ssm_plan_info(C.Structure):
@@ -71,7 +71,7 @@ class ssm_plan_info(C.Structure):
 
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
-                input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0):
+                input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0):
     t = ssm_tuning()
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
@@ -79,6 +79,7 @@ def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM
     t.chain_blocks = int(chain_blocks)
     t.pair_stages = int(pair_stages)
     t.pair_blocks = int(pair_blocks)
+    t.input_split = int(input_split)
     for i, r in enumerate(tile_rows):
         t.tile_rows[i] = int(r)
     return t

@@ -113,6 +113,12 @@ struct ssm_plan_s {
   int stage_kernel = SSM_STAGE_TILED;
   int class_bm[4] = {0, 0, 0, 0};
   int max_kry = 0;                  // leading stages folded into the input pass
+  // split input pass: row ranges per class (empty where the resident pass runs)
+  std::vector<ResRange> input_units;
+  int class_input_start[4] = {0, 0, 0, 0}, class_input_count[4] = {0, 0, 0, 0};
+  size_t class_input_lds[4] = {0, 0, 0, 0};
+  int class_input_p[4] = {0, 0, 0, 0}, class_input_kdim[4] = {0, 0, 0, 0};
+  size_t m_input = 0;
   int class_min_kry[4] = {0, 0, 0, 0};
   int class_all_kry[4] = {0, 0, 0, 0};  // every sequence of the class is folded
   Region r_kw;
@@ -128,7 +134,8 @@ struct ssm_plan_s {
   size_t m_chain = 0;
   // stage pairs of the forward apply: units per class at the pair's first stage
   std::vector<PairUnit> pair_units;
-  std::vector<int> pair_start[4], pair_count[4];
+  std::vector<int> pair_start[4], pair_count[4], pair_tail[4];
+  std::vector<size_t> pair_lds_bytes[4];
   size_t m_pair = 0;
   int64_t pair_launches = 0;
   double pair_bytes = 0, pair_flops = 0;
@@ -218,6 +225,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     return fail(SSM_E_INVALID, "pair_stages = %d: supported 0 (automatic) or 1 (off)", tn.pair_stages);
   if (tn.pair_blocks != 0 && (tn.pair_blocks < 4 || tn.pair_blocks > 256))
     return fail(SSM_E_INVALID, "pair_blocks = %d: supported 0 (automatic) or 4..256", tn.pair_blocks);
+  if (tn.input_split < 0 || tn.input_split > 1)
+    return fail(SSM_E_INVALID, "input_split = %d: supported 0 (automatic) or 1 (off)", tn.input_split);
   if (tn.stage_kernel == SSM_STAGE_TILED || compute == SSM_F64)
     P.stage_kernel = SSM_STAGE_TILED;
   else
@@ -420,19 +429,57 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // leading stages folded into the input pass (resident kernel, per-stage
   // launches or the resident persistent launch)
   P.max_kry = 0;
-  for (OpDev& o : P.ops) {
+  // The split input pass (K_j rows in registers) folds stages while
+  // 2^j p <= 2 mp, for operators whose sequences all run stages past j and
+  // whole classes of such operators sharing p and j (per-stage launches of the
+  // chain kernels); the resident input pass folds while 2^j p <= mp.
+  const int nops = (int)P.ops.size();
+  std::vector<int> jres(nops, 0), jsplit(nops, 0);
+  bool class_split[4] = {true, true, true, true}, class_has[4] = {false, false, false, false};
+  for (int oi = 0; oi < nops; ++oi) {
+    const OpDev& o = P.ops[oi];
+    int j = 0, jw = 0;
+    while (((int64_t)o.p << (j + 1)) <= o.mp && j + 1 <= o.N + 1) ++j;
+    while (((int64_t)o.p << (jw + 1)) <= 2 * (int64_t)o.mp && jw + 1 <= o.N + 1) ++jw;
+    if (tn.input_stages > 0) {
+      j = std::min(j, tn.input_stages);
+      jw = std::min(jw, tn.input_stages);
+    }
+    jres[oi] = j;
+    bool split = P.launch == SSM_LAUNCH_PER_STAGE && P.stage_kernel == SSM_STAGE_CHAIN &&
+                 tn.input_split != 1 && tn.input_stages >= 0 && jw >= 2 &&
+                 input_split_supported(o.mp, (int)compute, o.p, o.p << jw);
+    for (const SeqDev& sq : P.seqs)
+      if (sq.op == oi) split = split && jw <= sq.last;
+    jsplit[oi] = split ? jw : 0;
+    const int c = class_of(o.mp);
+    if (!class_has[c]) {
+      P.class_input_p[c] = o.p;
+      P.class_input_kdim[c] = o.p << jw;
+    }
+    class_has[c] = true;
+    class_split[c] = class_split[c] && split && o.p == P.class_input_p[c] &&
+                     (o.p << jw) == P.class_input_kdim[c];
+  }
+  for (int oi = 0; oi < nops; ++oi) {
+    OpDev& o = P.ops[oi];
     o.kry = 0;
     o.kdim = 0;
+    o.kst = o.mp;
+    o.ksplit = 0;
     o.kw = o.kc = -1;
     if (tn.input_stages < 0 || !(P.launch == SSM_LAUNCH_PER_STAGE || P.persist_res) ||
         P.stage_kernel == SSM_STAGE_TILED || !res_supported(o.mp, P.compute))
       continue;
-    int j = 0;
-    while (((int64_t)o.p << (j + 1)) <= o.mp && j + 1 <= o.N + 1) ++j;
-    if (tn.input_stages > 0) j = std::min(j, tn.input_stages);
-    if (j >= (P.persist_res ? 1 : 2)) {  // the persistent items start with an input pass
-      o.kry = j;
-      o.kdim = o.p << j;
+    const int c = class_of(o.mp);
+    if (class_has[c] && class_split[c]) {
+      o.kry = jsplit[oi];
+      o.kdim = o.p << o.kry;
+      o.kst = std::max(o.mp, o.kdim);
+      o.ksplit = 1;
+    } else if (jres[oi] >= (P.persist_res ? 1 : 2)) {  // the persistent items start with an input pass
+      o.kry = jres[oi];
+      o.kdim = o.p << o.kry;
     }
   }
   for (int c = 0; c < 4; ++c) {
@@ -453,37 +500,78 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   for (int c = 0; c < 4; ++c)
     if (P.class_min_kry[c] == (1 << 30)) P.class_min_kry[c] = 0;
 
+  // split input pass units: row ranges of R rows (R p elements of input
+  // staged per workgroup, about 256 ranges per class), longest sequences first
+  P.input_units.clear();
+  for (int c = 0; c < 4; ++c) {
+    P.class_input_start[c] = (int)P.input_units.size();
+    P.class_input_count[c] = 0;
+    P.class_input_lds[c] = 0;
+    if (!(class_has[c] && class_split[c])) continue;
+    std::vector<int> ids;
+    int64_t rows = 0;
+    int maxp = 4, maxlag = 0;
+    for (int i = 0; i < n_seq; ++i)
+      if (P.ops[P.seqs[i].op].mp == kClassMp[c]) {
+        ids.push_back(i);
+        rows += P.seqs[i].L;
+        maxp = std::max(maxp, P.seqs[i].p);
+        maxlag = std::max(maxlag, (1 << P.seqs[i].kry) - 1);
+      }
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
+    int64_t R = std::min<int64_t>(1024, std::max<int64_t>(256, (rows / 256 + 15) / 16 * 16));
+    while (R > 16 && (R + maxlag) * maxp * 2 > 65536) R -= 16;
+    for (int i : ids)
+      for (int64_t r0 = 0; r0 < P.seqs[i].L; r0 += R)
+        P.input_units.push_back(ResRange{i, (int32_t)r0, (int32_t)std::min<int64_t>(R, P.seqs[i].L - r0), 0});
+    P.class_input_count[c] = (int)P.input_units.size() - P.class_input_start[c];
+    P.class_input_lds[c] = (size_t)(R + maxlag) * maxp * 2;
+  }
+
   // Stage pairs (forward apply, per-stage launches): stages k, k + 1 fused
   // where every sequence of the class runs both as lean stages, i.e. from the
-  // largest folded stage count on and below the earliest last stage. Units are
-  // segments of T blocks in the numbering of stage k, longest sequences first.
+  // largest folded stage count on and below the earliest last stage; the last
+  // two stages fuse too (tail pair, which forms y) when every sequence of the
+  // class ends at the same stage, q <= 16 and p <= 64. Units are segments of
+  // T blocks in the numbering of stage k, longest sequences first (a tail
+  // segment's inputs are staged in LDS: T 16 p 4 bytes <= 32 KiB).
   P.pair_units.clear();
   for (int c = 0; c < 4; ++c) {
     const int ml = P.class_max_last[c];
     P.pair_start[c].assign(std::max(ml + 1, 0), 0);
     P.pair_count[c].assign(std::max(ml + 1, 0), 0);
+    P.pair_tail[c].assign(std::max(ml + 1, 0), 0);
+    P.pair_lds_bytes[c].assign(std::max(ml + 1, 0), 0);
     if (ml < 0 || tn.pair_stages == 1 || P.launch != SSM_LAUNCH_PER_STAGE ||
         P.stage_kernel != SSM_STAGE_CHAIN || !pair_supported(kClassMp[c], (int)compute))
       continue;
     std::vector<int> ids;
-    int max_kry = 0, min_last = 1 << 30;
-    bool fits = true;
+    int max_kry = 0, min_last = 1 << 30, max_last = -1, max_p = 1;
+    bool fits = true, small_io = true;
     for (int i = 0; i < n_seq; ++i)
       if (P.ops[P.seqs[i].op].mp == kClassMp[c]) {
+        const SeqDev& sq = P.seqs[i];
         ids.push_back(i);
-        max_kry = std::max(max_kry, P.seqs[i].kry);
-        min_last = std::min(min_last, P.seqs[i].last);
-        fits = fits && P.seqs[i].L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
+        max_kry = std::max(max_kry, sq.kry);
+        min_last = std::min(min_last, sq.last);
+        max_last = std::max(max_last, sq.last);
+        max_p = std::max(max_p, sq.p);
+        fits = fits && sq.L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
+        small_io = small_io && sq.q <= 16 && sq.p <= 64;
       }
     if (!fits) continue;
     std::stable_sort(ids.begin(), ids.end(),
                      [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
-    for (int kk = std::max(4, max_kry); kk + 1 < min_last; kk += 2) {
+    for (int kk = std::max(4, max_kry); kk + 1 <= min_last; kk += 2) {
+      const bool tail = kk + 1 == min_last;
+      if (tail && !(min_last == max_last && small_io)) break;
       const int64_t sh = (int64_t)1 << kk;
       int64_t blocks = 0;
       for (int i : ids) blocks += (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
-      const int T = tn.pair_blocks > 0 ? tn.pair_blocks
-                                       : (int)std::min<int64_t>(64, std::max<int64_t>(8, blocks / 256));
+      int T = tn.pair_blocks > 0 ? tn.pair_blocks
+                                 : (int)std::min<int64_t>(64, std::max<int64_t>(8, blocks / 256));
+      if (tail) T = std::max(1, std::min(T, 32768 / (64 * max_p)));
       P.pair_start[c][kk] = (int)P.pair_units.size();
       for (int i : ids) {
         const int64_t nflat = (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
@@ -491,6 +579,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
           P.pair_units.push_back(PairUnit{i, (int32_t)f0, T, 0});
       }
       P.pair_count[c][kk] = (int)P.pair_units.size() - P.pair_start[c][kk];
+      P.pair_tail[c][kk] = tail;
+      P.pair_lds_bytes[c][kk] = pair_lds(kClassMp[c], tail, T, max_p);
     }
   }
 
@@ -647,8 +737,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     }
     const int c = class_of(P.ops[s.op].mp);
     for (int kk = s.kry; kk <= s.last; ++kk) {
+      const int kl = pair_at(c, kk) ? kk + 1 : kk;  // the launch's last stage
       const double in_row = (double)m * xe;
-      const double out_row = kk == s.last ? (double)s.q * xe : (double)m * xe;
+      const double out_row = kl == s.last ? (double)s.q * xe : (double)m * xe;
       P.stage_bytes += s.L * (in_row + out_row);
       if (pair_at(c, kk)) {  // the pair's second stage moves no further rows
         P.pair_bytes += s.L * (in_row + out_row);
@@ -679,9 +770,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     n_pc += (size_t)(o.N + 1) * mm;
     if (o.kry > 0) {
       o.kc = (int64_t)n_pc;
-      n_pc += mm;
+      n_pc += (size_t)o.mp * o.kst;
       o.kw = (int64_t)n_kw;
-      n_kw += mm;
+      n_kw += (size_t)o.mp * o.kst;
     }
     if (P.with_backward) {
       o.pct = (int64_t)n_pc;
@@ -746,6 +837,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + sizeof(ChainUnit) * std::max<size_t>(1, P.chain_units.size()));
   P.m_pair = off;
   off = align_up(off + sizeof(PairUnit) * std::max<size_t>(1, P.pair_units.size()));
+  P.m_input = off;
+  off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.input_units.size()));
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
     P.m_ritems = off;
     off = align_up(off + sizeof(RItem) * std::max<size_t>(1, P.ritems.size()));
@@ -1246,7 +1339,7 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     int start = (int)J.size(), mx = 0, mn = 0;
     for (const OpDev& o : P->ops) {
       if (o.kry <= 0) continue;
-      J.push_back(GemmJob{bbar + o.bbar, nullptr, kw + o.kw, o.mp, o.p, 0, o.p, 0, o.mp, 0, 0, 1.0,
+      J.push_back(GemmJob{bbar + o.bbar, nullptr, kw + o.kw, o.mp, o.p, 0, o.p, 0, o.kst, 0, 0, 1.0,
                           0.0});
       mx = std::max(mx, o.mp);
       mn = std::max(mn, o.p);
@@ -1261,8 +1354,8 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
         if (o.kry <= i) continue;
         const int64_t mm = (int64_t)o.mp * o.mp;
         const int w = o.p << i;
-        J.push_back(GemmJob{pw + o.pw + i * mm, kw + o.kw, kw + o.kw + w, o.mp, w, o.mp, o.mp, o.mp,
-                            o.mp, 0, 0, 1.0, 0.0});
+        J.push_back(GemmJob{pw + o.pw + i * mm, kw + o.kw, kw + o.kw + w, o.mp, w, o.mp, o.mp, o.kst,
+                            o.kst, 0, 0, 1.0, 0.0});
         mx = std::max(mx, o.mp);
         mn = std::max(mn, w);
       }
@@ -1293,6 +1386,9 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (!P->pair_units.empty())
     std::memcpy(P->meta_host.data() + P->m_pair, P->pair_units.data(),
                 sizeof(PairUnit) * P->pair_units.size());
+  if (!P->input_units.empty())
+    std::memcpy(P->meta_host.data() + P->m_input, P->input_units.data(),
+                sizeof(ResRange) * P->input_units.size());
   if (P->launch == SSM_LAUNCH_PERSISTENT) {
     unsigned char* mh = P->meta_host.data();
     if (!P->items.empty())
@@ -1474,9 +1570,16 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       // the leading stages folded into the input pass, x^(kry) in buffer kry % 2
       prm.xin = P.ws + P.r_x0.off;
       prm.xout = P.ws + P.r_x1.off;
-      const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
-                           P.class_range_start[c];
-      e = launch_krylov_res(kClassMp[c], P.compute, prm, rg, P.class_range_count[c], stream);
+      if (P.class_input_count[c] > 0) {
+        const ResRange* un = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_input) +
+                             P.class_input_start[c];
+        e = launch_input_split(kClassMp[c], P.compute, P.class_input_p[c], P.class_input_kdim[c], prm,
+                               un, P.class_input_count[c], P.class_input_lds[c], stream);
+      } else {
+        const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
+                             P.class_range_start[c];
+        e = launch_krylov_res(kClassMp[c], P.compute, prm, rg, P.class_range_count[c], stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "input pass launch");
       prm.skip_kry = 1;
       k_begin = P.class_min_kry[c];
@@ -1495,7 +1598,8 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       if (pair) {
         const PairUnit* un = reinterpret_cast<const PairUnit*>(P.ws + P.r_meta.off + P.m_pair) +
                              P.pair_start[c][kk];
-        e = launch_stage_pair(kClassMp[c], P.compute, prm, un, P.pair_count[c][kk], stream);
+        e = launch_stage_pair(kClassMp[c], P.compute, prm, un, P.pair_count[c][kk],
+                              P.pair_tail[c][kk] != 0, P.pair_lds_bytes[c][kk], stream);
       } else {
         e = launch_stage_any(P, c, prm, stream);
       }

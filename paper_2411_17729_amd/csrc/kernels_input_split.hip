@@ -1,0 +1,175 @@
+// Input pass with the state entries split over the waves (BF16, padded m of
+// 128 and 256, p a multiple of 4).
+//
+// After stages 0..j-1 the state is x_l = K_j w_l with
+//   K_j = [Bbar, Abar Bbar, ..., Abar^(2^j - 1) Bbar],  w_l = [u_l; u_{l-1}; ...; u_{l-2^j+1}]
+// (zero before the start): the product of the first j factors of eq. (2.2)
+// applied to Bbar (§3, first display and eqs. (3.2)-(3.3)). K_j has 2^j p
+// columns. The resident input pass keeps K_j in LDS and takes up to m of
+// them; here wave w owns state entries w m/8 .. (w+1) m/8 - 1 and keeps the
+// rows of K_j for them in registers as MFMA A operands, which takes up to 2 m
+// columns (one more folded stage; 128 VGPRs for 512 columns at m = 256). A
+// workgroup takes a range of rows of one sequence, stages the range's inputs
+// (and the 2^j - 1 before it) once in LDS in BF16, the operand type, with the
+// rows in reverse time order so that the window w_l of every row is one
+// contiguous run, and then computes its 16-row blocks with no further
+// synchronisation: block rows are the MFMA columns, window entries the
+// contraction, and a lane's operand is 16 (8 | p) or twice 8 (p = 4)
+// contiguous bytes of LDS. The kernel is specialised on the number of MFMA
+// steps (2^j p of 128, 256 or 512) and the operand width, so that a block's
+// operand reads all go out before its MFMAs.
+#include "stage_common.h"
+#include "ssm_internal.h"
+
+namespace ssmc {
+
+template <int MP>
+struct InputCfg {
+  static constexpr int NW = 8;          // waves of a workgroup
+  static constexpr int DW = MP / NW;    // state entries of a wave
+  static constexpr int NT = DW / 16;    // MFMA output tiles of a wave
+};
+
+// KS: MFMA steps (2^j p / 32); V16: 8 | p (one 16-byte operand read; else p = 4)
+template <int MP, int KS, bool V16>
+__global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_input_split(
+    StageParams prm, const ResRange* units) {
+  using C = InputCfg<MP>;
+  constexpr int NT = C::NT;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_in[];
+  __bf16* us = reinterpret_cast<__bf16*>(smem_in);
+
+  const ResRange rg = units[blockIdx.x];
+  const SeqDev sq = prm.seqs[rg.seq];
+  const OpDev o = prm.ops[sq.op];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = lane & 15, g = lane >> 4;
+  // 32-bit indices: the host keeps L MP 4 <= 2^31
+  const int L = (int)sq.L, p = sq.p;
+  const int lag = (1 << sq.kry) - 1;  // rows of input before a row that its window reaches
+  const int hi = rg.row0 + rg.nrows;        // rows row0 .. hi - 1 of this unit
+
+  // rows of K_j owned by this wave, A operands: row index r of output tile t
+  // is state entry ent(t, r); step s, lane group g holds columns 32 s + 8 g .. + 7
+  auto ent = [&](int t, int rr) { return wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3); };
+  bf16x8 ka[NT][KS];
+  {
+    const __bf16* K = reinterpret_cast<const __bf16*>(prm.P) + o.kc;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        ka[t][s] = *reinterpret_cast<const bf16x8*>(K + (int64_t)ent(t, r) * o.kst + 32 * s + 8 * g);
+  }
+
+  // inputs of rows row0 - lag .. hi - 1 into LDS, row l at (hi - 1 - l) p,
+  // rounded to BF16 (zeros before the start); four channels per thread step
+  {
+    const int n4 = (rg.nrows + lag) * p / 4;
+    const int64_t ubase = sq.u_off + (int64_t)(rg.row0 - lag) * p;  // element of the first row
+    for (int e = threadIdx.x; e < n4; e += 512) {
+      const int flat = 4 * e;  // element within the staged rows, time-forward
+      const int row = rg.row0 - lag + flat / p, ch = flat % p;
+      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (row >= 0 && row < L) {
+        if (prm.src_dtype == DT_F32) {
+          const float* u = reinterpret_cast<const float*>(prm.src) + ubase + flat;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[c] = u[c];
+        } else {
+          const uint16_t* u = reinterpret_cast<const uint16_t*>(prm.src) + ubase + flat;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[c] = bf16_bits_to_f32(u[c]);
+        }
+      }
+      bf16x4 b;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = (__bf16)v[c];  // round to nearest even
+      *reinterpret_cast<bf16x4*>(us + (hi - 1 - row) * p + ch) = b;
+    }
+    __syncthreads();
+  }
+
+  // x^(j) rows through a buffer resource over the sequence's L x MP block
+  // (stores of rows past L are dropped); buffer kry mod 2 as for the resident
+  // input pass
+  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * 4);
+  float* xo = reinterpret_cast<float*>((sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off;
+  const auto rout = __builtin_amdgcn_make_buffer_rsrc(xo, (short)0, (int)nrec, kBufferWord3);
+  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * NT * g) * 4u;
+  const int nblk = (rg.nrows + 15) / 16;
+  for (int b = 0; b < nblk; ++b) {
+    const int l = rg.row0 + 16 * b + r;
+    // this row's window starts at (hi - 1 - l) p; rows past the unit read
+    // staged rows of the unit's end (their outputs are not stored)
+    const int w0 = (l < hi ? hi - 1 - l : 0) * p + 8 * g;
+    bf16x8 bo[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if constexpr (V16) {
+        bo[s] = *reinterpret_cast<const bf16x8*>(us + w0 + 32 * s);
+      } else {
+        const bf16x4 lo = *reinterpret_cast<const bf16x4*>(us + w0 + 32 * s);
+        const bf16x4 up = *reinterpret_cast<const bf16x4*>(us + w0 + 32 * s + 4);
+        bo[s] = __builtin_shufflevector(lo, up, 0, 1, 2, 3, 4, 5, 6, 7);
+      }
+    }
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[t][s], bo[s], acc[t], 0, 0, 0);
+    // every operand read of the block before its MFMAs (one LDS round trip per block)
+    __builtin_amdgcn_sched_group_barrier(0x100, V16 ? KS : 2 * KS, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, KS * NT, 0);
+    const uint32_t off = l < hi ? lane_off + (uint32_t)(16 * b + rg.row0) * (uint32_t)(MP * 4) : 0x80000000u;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[t]), rout, off + 16 * t, 0, 0);
+  }
+}
+
+template <int MP, int KS, bool V16>
+static hipError_t launch_input_t(const StageParams& prm, const ResRange* units, int n_units,
+                                 size_t lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_input_split<MP, KS, V16>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_input_split<MP, KS, V16>), dim3(n_units), dim3(512), lds, s, prm, units);
+  return hipGetLastError();
+}
+
+template <int MP, int KS>
+static hipError_t launch_input_w(bool v16, const StageParams& prm, const ResRange* units,
+                                 int n_units, size_t lds, hipStream_t s) {
+  return v16 ? launch_input_t<MP, KS, true>(prm, units, n_units, lds, s)
+             : launch_input_t<MP, KS, false>(prm, units, n_units, lds, s);
+}
+
+bool input_split_supported(int mp, int ct, int p, int kdim) {
+  return ct == DT_BF16 && (mp == 128 || mp == 256) && (p == 4 || (p > 0 && (p & 7) == 0)) &&
+         (kdim == 128 || kdim == 256 || (kdim == 512 && mp == 256));
+}
+
+hipError_t launch_input_split(int mp, int ct, int p, int kdim, const StageParams& prm,
+                              const ResRange* units, int n_units, size_t lds, hipStream_t s) {
+  if (n_units <= 0) return hipSuccess;
+  if (!input_split_supported(mp, ct, p, kdim) || lds > 65536) return hipErrorInvalidValue;
+  const bool v16 = (p & 7) == 0;
+  if (mp == 128)
+    return kdim == 128 ? launch_input_w<128, 4>(v16, prm, units, n_units, lds, s)
+                       : launch_input_w<128, 8>(v16, prm, units, n_units, lds, s);
+  return kdim == 128   ? launch_input_w<256, 4>(v16, prm, units, n_units, lds, s)
+         : kdim == 256 ? launch_input_w<256, 8>(v16, prm, units, n_units, lds, s)
+                       : launch_input_w<256, 16>(v16, prm, units, n_units, lds, s);
+}
+
+}  // namespace ssmc

@@ -324,7 +324,7 @@ __global__ void k_pack_powers(const OpDev* ops, const double* pw, void* pc, int 
 __global__ void k_pack_krylov(const OpDev* ops, const double* kw, void* kc, int ct) {
   const OpDev o = ops[blockIdx.y];
   if (o.kw < 0) return;
-  const int64_t n = (int64_t)o.mp * o.mp;
+  const int64_t n = (int64_t)o.mp * o.kst;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const double v = kw[o.kw + e];

@@ -20,12 +20,16 @@
 // Each block's rows are loaded DP blocks ahead into registers; one barrier
 // per block orders the LDS exchange (x of a block is read by the next block,
 // y two blocks later, and the slots rotate through two and three buffers).
+//
+// The tail variant runs the last two stages of every sequence of the launch
+// and forms y_l = C w_l + D u_l (last display of §3; eq. (1.2)) instead of
+// storing w: each wave contracts its share of w with the matching columns of C
+// (FP32 MFMA, C in registers), the eight partial outputs of a block meet in
+// LDS, and wave v adds them for rows 2v and 2v+1 with D u_l. The segment's
+// inputs and D are staged in LDS at the start, so that no load in the walk is
+// waited for out of order.
 #include "stage_common.h"
 #include "ssm_internal.h"
-
-#ifndef PAIR_DP
-#define PAIR_DP 4
-#endif
 
 namespace ssmc {
 
@@ -37,11 +41,15 @@ struct PairCfg {
   static constexpr int KS = MP / 32;       // MFMA steps of one contraction
   static constexpr int RS = MP + 8;        // LDS row stride in BF16 entries (16-byte pad)
   static constexpr int SLOT = 16 * RS;     // one block of 16 time rows
-  static constexpr int DP = PAIR_DP;  // blocks loaded ahead
+  static constexpr int DP = 4;             // blocks loaded ahead
   static constexpr size_t LDS = 5 * SLOT * sizeof(__bf16);  // x: 2 slots, y: 3 slots
+  // tail variant: partial outputs (8 waves x 16 rows x 16 outputs), D (up to
+  // 16 x 64) and the segment's inputs after the slots
+  static constexpr size_t RED = NW * 16 * 16 * sizeof(float);
+  static constexpr size_t DMAX = 16 * 64 * sizeof(float);
 };
 
-template <int MP>
+template <int MP, bool TAIL>
 __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_stage_pair(
     StageParams prm, const PairUnit* units) {
   using C = PairCfg<MP>;
@@ -97,8 +105,38 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const auto rin = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(reinterpret_cast<const float*>(prm.xin)) + sq.x_off, (short)0, (int)nrec,
       kBufferWord3);
+  // (the tail variant stores no state: its range is empty)
   const auto rout = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float*>(prm.xout) + sq.x_off,
-                                                      (short)0, (int)nrec, kBufferWord3);
+                                                      (short)0, TAIL ? 0 : (int)nrec, kBufferWord3);
+
+  // tail: C's columns for this wave's entries as FP32 MFMA A operands (row
+  // index r is output r, zero from q on), D and the inputs of the segment's
+  // blocks (block v of the segment, row rr, channel c at (16 v + rr) p + c)
+  const int q = sq.q, p = sq.p;
+  float ca[NT][4];
+  float* red = reinterpret_cast<float*>(smem_pair + C::LDS);
+  float* Ds = red + C::RED / sizeof(float);
+  float* Us = Ds + C::DMAX / sizeof(float);
+  if constexpr (TAIL) {
+    const float* cm = reinterpret_cast<const float*>(prm.small) + o.cout;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        ca[t][v] = r < q ? cm[r * MP + wave * C::DW + 4 * NT * g + 4 * t + v] : 0.f;
+    const float* dm = reinterpret_cast<const float*>(prm.small) + o.dmat;
+    for (int e = threadIdx.x; e < q * p; e += 512) Ds[e] = dm[e];
+    const int nu = (f1 - f0) * 16 * p;
+    for (int e = threadIdx.x; e < nu; e += 512) {
+      const int v = e / (16 * p), rr = (e / p) & 15, c = e % p;
+      const int f = f0 + v, col = f / ni, row = ((f - col * ni) << k) + 16 * col + rr;
+      Us[e] = row < L ? load_src<float>(prm.src, prm.src_dtype, sq.u_off + (int64_t)row * p + c) : 0.f;
+    }
+    __syncthreads();
+  }
+  const auto ry = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float*>(prm.dst) + sq.y_off, (short)0,
+                                                    TAIL ? (int)((uint32_t)L * (uint32_t)q * 4u) : 0,
+                                                    kBufferWord3);
   // this lane's entries of a block: time row r, entries wave DW + 4 NT g .. + 4 NT - 1
   const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * NT * g) * 4u;
   auto row_off = [&](int col, int i) -> uint32_t {
@@ -192,6 +230,26 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, xr[u][t]), rout, off + 16 * t, 0, 0);
+      if constexpr (TAIL) {
+        // this wave's part of C w: outputs 4 g + v of time row r
+        f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][v], xr[u][t][v], ya, 0, 0, 0);
+        *reinterpret_cast<f32x4*>(red + (wave * 16 + r) * 16 + 4 * g) = ya;
+        __syncthreads();
+        // rows 2 wave, 2 wave + 1: the eight partial sums, then D u
+        const int rr = 2 * wave + ((lane >> 4) & 1), qq = lane & 15;
+        float yv = 0.f;
+#pragma unroll
+        for (int w = 0; w < C::NW; ++w) yv += red[(w * 16 + rr) * 16 + qq];
+        const float* uu = Us + ((out ? it - nw : 0) * 16 + rr) * p;
+        for (int c = 0; c < p; ++c) yv += Ds[(qq < q ? qq : 0) * p + c] * uu[c];
+        const int l = (ci << k) + 16 * cc + rr;
+        const uint32_t yoff = out && lane < 32 && qq < q && l < L ? (uint32_t)(l * q + qq) * 4u : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, yv), ry, yoff, 0, 0);
+      }
       issue(xr[u]);
       __syncthreads();
       ysl = ysl2;
@@ -203,30 +261,37 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   }
 }
 
-template <int MP>
+template <int MP, bool TAIL>
 static hipError_t launch_pair_t(const StageParams& prm, const PairUnit* units, int n_units,
-                                hipStream_t s) {
-  using C = PairCfg<MP>;
+                                size_t lds, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_pair<MP>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_pair<MP, TAIL>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_stage_pair<MP>), dim3(n_units), dim3(512), C::LDS, s, prm, units);
+  hipLaunchKernelGGL((k_stage_pair<MP, TAIL>), dim3(n_units), dim3(512), lds, s, prm, units);
   return hipGetLastError();
 }
 
 bool pair_supported(int mp, int ct) { return ct == DT_BF16 && (mp == 128 || mp == 256); }
 
+size_t pair_lds(int mp, bool tail, int seg_blocks, int p) {
+  const size_t base = mp == 128 ? PairCfg<128>::LDS : PairCfg<256>::LDS;
+  if (!tail) return base;
+  return base + PairCfg<256>::RED + PairCfg<256>::DMAX + (size_t)seg_blocks * 16 * p * sizeof(float);
+}
+
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
-                             int n_units, hipStream_t s) {
+                             int n_units, bool tail, size_t lds, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
-  if (ct != DT_BF16 || prm.adjoint) return hipErrorInvalidValue;
+  if (ct != DT_BF16 || prm.adjoint || lds > 160 * 1024) return hipErrorInvalidValue;
   switch (mp) {
-    case 128: return launch_pair_t<128>(prm, units, n_units, s);
-    case 256: return launch_pair_t<256>(prm, units, n_units, s);
+    case 128: return tail ? launch_pair_t<128, true>(prm, units, n_units, lds, s)
+                          : launch_pair_t<128, false>(prm, units, n_units, lds, s);
+    case 256: return tail ? launch_pair_t<256, true>(prm, units, n_units, lds, s)
+                          : launch_pair_t<256, false>(prm, units, n_units, lds, s);
   }
   return hipErrorInvalidValue;
 }

@@ -38,10 +38,12 @@ struct OpDev {
   int64_t bbar;  // FP64 Bbar (mp x p)
   int64_t minv;  // FP64 (I - delta/2 A)^{-1} (mp x mp)
   int64_t sc_aug, sc_n, sc_b;  // prepare scratch: [M | I] (mp x 2mp), I + hA, delta B
-  int64_t kw;    // FP64 K_j = [Bbar, Abar Bbar, ...] (mp x mp, columns beyond 2^j p zero), or -1
+  int64_t kw;    // FP64 K_j = [Bbar, Abar Bbar, ...] (mp x kst, columns beyond 2^j p zero), or -1
   int64_t kc;    // K_j in the compute type, same layout, or -1
   int32_t kry;   // j of this operator (0: none)
   int32_t kdim;  // 2^j p
+  int32_t kst;   // row stride of K_j: max(mp, 2^j p)
+  int32_t ksplit;  // 1: the split input pass (K_j rows in registers) computes x^(j)
   // backward, FP64 gradient workspace offsets
   int64_t g_dp;    // dL/dP_k, k = 0..N (mp x mp each); becomes the squaring adjoint
   int64_t g_dbb;   // dL/dBbar (mp x p)
@@ -268,6 +270,15 @@ hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRan
 // written to xin (kry even) or xout (kry odd); y at once when kry = last + 1.
 hipError_t launch_krylov_res(int mp, int ct, const StageParams& prm, const ResRange* ranges,
                              int n_ranges, hipStream_t s);
+// Input pass with the state entries split over the waves and K_j rows in
+// registers (BF16, padded m 128 and 256, p = 4 or a multiple of 8, 2^j p of
+// 128, 256 or 512 and at most 2 mp, every sequence with stages after j): x^(j)
+// into xin (j even) or xout (j odd). All operators of a launch share p and
+// 2^j p. units: row ranges; lds: (rows + 2^j - 1) p 2 bytes for the largest
+// unit, at most 64 KiB.
+bool input_split_supported(int mp, int ct, int p, int kdim);
+hipError_t launch_input_split(int mp, int ct, int p, int kdim, const StageParams& prm,
+                              const ResRange* units, int n_units, size_t lds, hipStream_t s);
 // Chain-walking stage kernel (stages with 2^k >= 16): BF16 and FP32 at padded
 // m of 64..256; FP32 m = 256 splits the output rows over two workgroups and
 // has no tail variant (tail launches take the resident or tiled kernel).
@@ -276,12 +287,15 @@ bool chain_supported(int mp, int ct);
 // epilogue or the final-state copy may be due); false selects the lean variant.
 hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const ChainUnit* units,
                               int n_units, bool tail, hipStream_t s);
-// Stages prm.k and prm.k + 1 of the forward cascade in one pass (both lean for
-// every sequence of the units; 2^k >= 16): BF16 at padded m of 128 and 256.
-// prm.xin and prm.xout must be different buffers.
+// Stages prm.k and prm.k + 1 of the forward cascade in one pass (2^k >= 16):
+// BF16 at padded m of 128 and 256. Lean: both stages are lean for every
+// sequence of the units, prm.xin and prm.xout differ. tail: k + 1 is the last
+// stage of every sequence of the units, which get y = C x + D u (q <= 16,
+// p <= 64; no state is stored). lds: pair_lds(mp, tail, largest T, largest p).
 bool pair_supported(int mp, int ct);
+size_t pair_lds(int mp, bool tail, int seg_blocks, int p);
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
-                             int n_units, hipStream_t s);
+                             int n_units, bool tail, size_t lds, hipStream_t s);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);

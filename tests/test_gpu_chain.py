@@ -140,7 +140,7 @@ def test_resident_persistent_matches_per_stage(compute):
     pers = CC.plan_for_workload(wl, compute=compute, launch="persistent")
     info = pers.info()
     assert info["launch"] == 2 and info["stage_kernel"] == 3 and info["input_stages"] >= 4
-    per = CC.plan_for_workload(wl, compute=compute, launch="per_stage", pair_stages=1)
+    per = CC.plan_for_workload(wl, compute=compute, launch="per_stage", pair_stages=1, input_split=1)
     ya = pers.apply(u).clone()
     yb = per.apply(u).clone()
     torch.cuda.synchronize()
