@@ -25,9 +25,10 @@
 // and forms y_l = C w_l + D u_l (last display of §3; eq. (1.2)) instead of
 // storing w: each wave contracts its share of w with the matching columns of C
 // (FP32 MFMA, C in registers), the eight partial outputs of a block meet in
-// LDS, and wave v adds them for rows 2v and 2v+1 with D u_l. The segment's
-// inputs and D are staged in LDS at the start, so that no load in the walk is
-// waited for out of order.
+// LDS (two buffers, so that a block's partials are added up during the next
+// block, behind the same barrier), and wave v adds them for rows 2v and 2v+1
+// with D u_l. The D u_l of the segment's rows are formed at the start into
+// LDS, so that no load in the walk is waited for out of order.
 #include "stage_common.h"
 #include "ssm_internal.h"
 
@@ -43,10 +44,9 @@ struct PairCfg {
   static constexpr int SLOT = 16 * RS;     // one block of 16 time rows
   static constexpr int DP = 4;             // blocks loaded ahead
   static constexpr size_t LDS = 5 * SLOT * sizeof(__bf16);  // x: 2 slots, y: 3 slots
-  // tail variant: partial outputs (8 waves x 16 rows x 16 outputs), D (up to
-  // 16 x 64) and the segment's inputs after the slots
-  static constexpr size_t RED = NW * 16 * 16 * sizeof(float);
-  static constexpr size_t DMAX = 16 * 64 * sizeof(float);
+  // tail variant: two buffers of partial outputs (8 waves x 16 rows x 16
+  // outputs), then D u of the segment's rows after the slots
+  static constexpr size_t RED = 2 * NW * 16 * 16 * sizeof(float);
 };
 
 template <int MP, bool TAIL>
@@ -110,13 +110,12 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                                                       (short)0, TAIL ? 0 : (int)nrec, kBufferWord3);
 
   // tail: C's columns for this wave's entries as FP32 MFMA A operands (row
-  // index r is output r, zero from q on), D and the inputs of the segment's
-  // blocks (block v of the segment, row rr, channel c at (16 v + rr) p + c)
+  // index r is output r, zero from q on), and D u for the segment's rows
+  // (block v of the segment, row rr, output j at (16 v + rr) q + j)
   const int q = sq.q, p = sq.p;
   float ca[NT][4];
   float* red = reinterpret_cast<float*>(smem_pair + C::LDS);
-  float* Ds = red + C::RED / sizeof(float);
-  float* Us = Ds + C::DMAX / sizeof(float);
+  float* du = red + C::RED / sizeof(float);
   if constexpr (TAIL) {
     const float* cm = reinterpret_cast<const float*>(prm.small) + o.cout;
 #pragma unroll
@@ -125,12 +124,15 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       for (int v = 0; v < 4; ++v)
         ca[t][v] = r < q ? cm[r * MP + wave * C::DW + 4 * NT * g + 4 * t + v] : 0.f;
     const float* dm = reinterpret_cast<const float*>(prm.small) + o.dmat;
-    for (int e = threadIdx.x; e < q * p; e += 512) Ds[e] = dm[e];
-    const int nu = (f1 - f0) * 16 * p;
-    for (int e = threadIdx.x; e < nu; e += 512) {
-      const int v = e / (16 * p), rr = (e / p) & 15, c = e % p;
+    const int nd = (f1 - f0) * 16 * q;
+    for (int e = threadIdx.x; e < nd; e += 512) {
+      const int v = e / (16 * q), rr = (e / q) & 15, j = e % q;
       const int f = f0 + v, col = f / ni, row = ((f - col * ni) << k) + 16 * col + rr;
-      Us[e] = row < L ? load_src<float>(prm.src, prm.src_dtype, sq.u_off + (int64_t)row * p + c) : 0.f;
+      float a = 0.f;
+      if (row < L)
+        for (int c = 0; c < p; ++c)
+          a += dm[j * p + c] * load_src<float>(prm.src, prm.src_dtype, sq.u_off + (int64_t)row * p + c);
+      du[e] = a;
     }
     __syncthreads();
   }
@@ -207,6 +209,20 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 
   int cc = c0, ci = i0 - nw;  // block being computed
   int ysl = 0;                // its y slot (visit index mod 3)
+  // tail: y of a block from its partials (buffer pb), first row l0, segment
+  // block v; wave w takes rows 2w and 2w + 1 (lanes below 32, output lane % 16)
+  auto finish = [&](const float* pb, int l0, bool has, int v) {
+    const int rr = 2 * wave + ((lane >> 4) & 1), qq = lane & 15;
+    float yv = 0.f;
+#pragma unroll
+    for (int w = 0; w < C::NW; ++w) yv += pb[(w * 16 + rr) * 16 + qq];
+    yv += du[(v * 16 + rr) * q + (qq < q ? qq : 0)];
+    const int l = l0 + rr;
+    const uint32_t yoff = has && lane < 32 && qq < q && l < L ? (uint32_t)(l * q + qq) * 4u : 0x80000000u;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, yv), ry, yoff, 0, 0);
+  };
+  int pl0 = 0, pv = 0;  // tail: the previous block's first row and segment index
+  bool pout = false;    //       and whether it has outputs
   for (int it0 = 0; it0 < npad; it0 += DP) {
 #pragma unroll
     for (int u = 0; u < DP; ++u) {
@@ -231,24 +247,19 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       for (int t = 0; t < NT; ++t)
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, xr[u][t]), rout, off + 16 * t, 0, 0);
       if constexpr (TAIL) {
-        // this wave's part of C w: outputs 4 g + v of time row r
+        // this wave's part of C w (outputs 4 g + v of time row r) into buffer
+        // it mod 2; the previous block's partials, complete since the last
+        // barrier, become its y
         f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][v], xr[u][t][v], ya, 0, 0, 0);
-        *reinterpret_cast<f32x4*>(red + (wave * 16 + r) * 16 + 4 * g) = ya;
-        __syncthreads();
-        // rows 2 wave, 2 wave + 1: the eight partial sums, then D u
-        const int rr = 2 * wave + ((lane >> 4) & 1), qq = lane & 15;
-        float yv = 0.f;
-#pragma unroll
-        for (int w = 0; w < C::NW; ++w) yv += red[(w * 16 + rr) * 16 + qq];
-        const float* uu = Us + ((out ? it - nw : 0) * 16 + rr) * p;
-        for (int c = 0; c < p; ++c) yv += Ds[(qq < q ? qq : 0) * p + c] * uu[c];
-        const int l = (ci << k) + 16 * cc + rr;
-        const uint32_t yoff = out && lane < 32 && qq < q && l < L ? (uint32_t)(l * q + qq) * 4u : 0x80000000u;
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, yv), ry, yoff, 0, 0);
+        *reinterpret_cast<f32x4*>(red + (it & 1) * (C::NW * 256) + (wave * 16 + r) * 16 + 4 * g) = ya;
+        finish(red + ((it + 1) & 1) * (C::NW * 256), pl0, pout, pv);
+        pl0 = (ci << k) + 16 * cc;
+        pout = out;
+        pv = out ? it - nw : 0;
       }
       issue(xr[u]);
       __syncthreads();
@@ -259,6 +270,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       }
     }
   }
+  if constexpr (TAIL) finish(red + ((npad + 1) & 1) * (C::NW * 256), pl0, pout, pv);  // the last block
 }
 
 template <int MP, bool TAIL>
@@ -277,10 +289,10 @@ static hipError_t launch_pair_t(const StageParams& prm, const PairUnit* units, i
 
 bool pair_supported(int mp, int ct) { return ct == DT_BF16 && (mp == 128 || mp == 256); }
 
-size_t pair_lds(int mp, bool tail, int seg_blocks, int p) {
+size_t pair_lds(int mp, bool tail, int seg_blocks, int q) {
   const size_t base = mp == 128 ? PairCfg<128>::LDS : PairCfg<256>::LDS;
   if (!tail) return base;
-  return base + PairCfg<256>::RED + PairCfg<256>::DMAX + (size_t)seg_blocks * 16 * p * sizeof(float);
+  return base + PairCfg<256>::RED + (size_t)seg_blocks * 16 * q * sizeof(float);
 }
 
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
