@@ -533,9 +533,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // where every sequence of the class runs both as lean stages, i.e. from the
   // largest folded stage count on and below the earliest last stage; the last
   // two stages fuse too (tail pair, which forms y) when every sequence of the
-  // class ends at the same stage and q <= 16. Units are segments of T blocks
+  // class ends at the same stage, q <= 16 and p <= 256. Units are segments of T blocks
   // in the numbering of stage k, longest sequences first (a tail segment's
-  // D u is formed in LDS: T 16 q 4 bytes <= 32 KiB).
+  // inputs and D u are staged in LDS: T 16 (p + q) 4 bytes <= 64 KiB).
   P.pair_units.clear();
   for (int c = 0; c < 4; ++c) {
     const int ml = P.class_max_last[c];
@@ -547,7 +547,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
         P.stage_kernel != SSM_STAGE_CHAIN || !pair_supported(kClassMp[c], (int)compute))
       continue;
     std::vector<int> ids;
-    int max_kry = 0, min_last = 1 << 30, max_last = -1, max_q = 1;
+    int max_kry = 0, min_last = 1 << 30, max_last = -1, max_q = 1, max_p = 1;
     bool fits = true, small_io = true;
     for (int i = 0; i < n_seq; ++i)
       if (P.ops[P.seqs[i].op].mp == kClassMp[c]) {
@@ -557,8 +557,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
         min_last = std::min(min_last, sq.last);
         max_last = std::max(max_last, sq.last);
         max_q = std::max(max_q, sq.q);
+        max_p = std::max(max_p, sq.p);
         fits = fits && sq.L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
-        small_io = small_io && sq.q <= 16;
+        small_io = small_io && sq.q <= 16 && sq.p <= 256;  // the tail's staged inputs fit in LDS
       }
     if (!fits) continue;
     std::stable_sort(ids.begin(), ids.end(),
@@ -571,7 +572,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       for (int i : ids) blocks += (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
       int T = tn.pair_blocks > 0 ? tn.pair_blocks
                                  : (int)std::min<int64_t>(64, std::max<int64_t>(8, blocks / 256));
-      if (tail) T = std::max(1, std::min(T, 32768 / (64 * max_q)));
+      if (tail) T = std::max(1, std::min(T, 65536 / (64 * (max_p + max_q))));
       P.pair_start[c][kk] = (int)P.pair_units.size();
       for (int i : ids) {
         const int64_t nflat = (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
@@ -580,7 +581,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       }
       P.pair_count[c][kk] = (int)P.pair_units.size() - P.pair_start[c][kk];
       P.pair_tail[c][kk] = tail;
-      P.pair_lds_bytes[c][kk] = pair_lds(kClassMp[c], tail, T, max_q);
+      P.pair_lds_bytes[c][kk] = pair_lds(kClassMp[c], tail, T, max_p, max_q);
     }
   }
 

@@ -51,8 +51,10 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const int hi = rg.row0 + rg.nrows;        // rows row0 .. hi - 1 of this unit
 
   // rows of K_j owned by this wave, A operands: row index r of output tile t
-  // is state entry ent(t, r); step s, lane group g holds columns 32 s + 8 g .. + 7
-  auto ent = [&](int t, int rr) { return wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3); };
+  // is state entry wave DW + 16 t + r (a lane's accumulators are entries
+  // 16 t + 4 g .. + 3 of its time row, 64 contiguous bytes of a row per store);
+  // step s, lane group g holds columns 32 s + 8 g .. + 7
+  auto ent = [&](int t, int rr) { return wave * C::DW + 16 * t + rr; };
   bf16x8 ka[NT][KS];
   {
     const __bf16* K = reinterpret_cast<const __bf16*>(prm.P) + o.kc;
@@ -64,29 +66,30 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   }
 
   // inputs of rows row0 - lag .. hi - 1 into LDS, row l at (hi - 1 - l) p,
-  // rounded to BF16 (zeros before the start); four channels per thread step
+  // rounded to BF16 (zeros before the start); four channels per element
+  // group, eight groups per thread loaded before any is stored
   {
     const int n4 = (rg.nrows + lag) * p / 4;
     const int64_t ubase = sq.u_off + (int64_t)(rg.row0 - lag) * p;  // element of the first row
-    for (int e = threadIdx.x; e < n4; e += 512) {
-      const int flat = 4 * e;  // element within the staged rows, time-forward
-      const int row = rg.row0 - lag + flat / p, ch = flat % p;
-      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (row >= 0 && row < L) {
-        if (prm.src_dtype == DT_F32) {
-          const float* u = reinterpret_cast<const float*>(prm.src) + ubase + flat;
+    const bool vec = src4_aligned(prm.src, prm.src_dtype, sq.u_off);  // p is a multiple of 4
+    for (int e0 = 0; e0 < n4; e0 += 8 * 512) {
+      f32x4 v[8];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) v[c] = u[c];
-        } else {
-          const uint16_t* u = reinterpret_cast<const uint16_t*>(prm.src) + ubase + flat;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) v[c] = bf16_bits_to_f32(u[c]);
-        }
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 512 * i + threadIdx.x, row = rg.row0 - lag + 4 * e / p;
+        v[i] = e < n4 && row >= 0 && row < L ? load_src4(prm.src, prm.src_dtype, ubase + 4 * e, vec)
+                                            : f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      bf16x4 b;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = (__bf16)v[c];  // round to nearest even
-      *reinterpret_cast<bf16x4*>(us + (hi - 1 - row) * p + ch) = b;
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 512 * i + threadIdx.x;
+        if (e >= n4) break;
+        const int flat = 4 * e, row = rg.row0 - lag + flat / p, ch = flat % p;
+        bf16x4 b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = (__bf16)v[i][c];  // round to nearest even
+        *reinterpret_cast<bf16x4*>(us + (hi - 1 - row) * p + ch) = b;
+      }
     }
     __syncthreads();
   }
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * 4);
   float* xo = reinterpret_cast<float*>((sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off;
   const auto rout = __builtin_amdgcn_make_buffer_rsrc(xo, (short)0, (int)nrec, kBufferWord3);
-  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * NT * g) * 4u;
+  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * g) * 4u;
   const int nblk = (rg.nrows + 15) / 16;
   for (int b = 0; b < nblk; ++b) {
     const int l = rg.row0 + 16 * b + r;
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const uint32_t off = l < hi ? lane_off + (uint32_t)(16 * b + rg.row0) * (uint32_t)(MP * 4) : 0x80000000u;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[t]), rout, off + 16 * t, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[t]), rout, off + 64 * t, 0, 0);
   }
 }
 

@@ -40,12 +40,13 @@ struct PairCfg {
   static constexpr int DW = MP / NW;       // state entries of a wave
   static constexpr int NT = DW / 16;       // MFMA output tiles of a wave
   static constexpr int KS = MP / 32;       // MFMA steps of one contraction
-  static constexpr int RS = MP + 8;        // LDS row stride in BF16 entries (16-byte pad)
+  static constexpr int RS = MP + 16;       // LDS row stride in BF16 entries (32-byte pad)
   static constexpr int SLOT = 16 * RS;     // one block of 16 time rows
   static constexpr int DP = 4;             // blocks loaded ahead
   static constexpr size_t LDS = 5 * SLOT * sizeof(__bf16);  // x: 2 slots, y: 3 slots
   // tail variant: two buffers of partial outputs (8 waves x 16 rows x 16
-  // outputs), then D u of the segment's rows after the slots
+  // outputs), then D u of the segment's rows, D and the segment's inputs
+  // after the slots
   static constexpr size_t RED = 2 * NW * 16 * 16 * sizeof(float);
 };
 
@@ -77,11 +78,13 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const int nit = f1 - f0 + nw;   // blocks visited
 
   // Rows of P_k and P_{k+1} owned by this wave, as A operands: row index r of
-  // output tile t is state entry ent(t, r). Contraction step s covers entries
-  // 32 s .. 32 s + 31 with operand slot 8 g + 4 h + e holding entry
-  // 32 s + 16 h + 4 g + e, the assignment of the chain kernel, so that every
-  // output sees the same products in the same MFMA steps as there.
-  auto ent = [&](int t, int rr) { return wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3); };
+  // output tile t is state entry ent(t, r) = wave DW + 16 t + r, so a lane's
+  // accumulators are entries 16 t + 4 g .. + 3 of its time row and every
+  // memory instruction moves 64 contiguous bytes of each row. Contraction step
+  // s covers entries 32 s .. 32 s + 31 with operand slot 8 g + 4 h + e holding
+  // entry 32 s + 16 h + 4 g + e, the assignment of the chain kernel, so that
+  // every output sees the same products in the same MFMA steps as there.
+  auto ent = [&](int t, int rr) { return wave * C::DW + 16 * t + rr; };
   bf16x8 pa[2][NT][KS];
   {
     const __bf16* P0 = reinterpret_cast<const __bf16*>(prm.P) + o.pc + (int64_t)k * MP * MP;
@@ -105,13 +108,14 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const auto rin = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(reinterpret_cast<const float*>(prm.xin)) + sq.x_off, (short)0, (int)nrec,
       kBufferWord3);
-  // (the tail variant stores no state: its range is empty)
   const auto rout = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float*>(prm.xout) + sq.x_off,
-                                                      (short)0, TAIL ? 0 : (int)nrec, kBufferWord3);
+                                                      (short)0, (int)nrec, kBufferWord3);
 
   // tail: C's columns for this wave's entries as FP32 MFMA A operands (row
   // index r is output r, zero from q on), and D u for the segment's rows
-  // (block v of the segment, row rr, output j at (16 v + rr) q + j)
+  // (block v of the segment, row rr, output j at (16 v + rr) q + j), formed
+  // from the segment's inputs and D staged in LDS (the loads all go out
+  // before any is waited for)
   const int q = sq.q, p = sq.p;
   float ca[NT][4];
   float* red = reinterpret_cast<float*>(smem_pair + C::LDS);
@@ -122,16 +126,49 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        ca[t][v] = r < q ? cm[r * MP + wave * C::DW + 4 * NT * g + 4 * t + v] : 0.f;
+        ca[t][v] = r < q ? cm[r * MP + wave * C::DW + 16 * t + 4 * g + v] : 0.f;
+    const int nv = f1 - f0;
+    float* Ds = du + nv * 16 * q;
+    float* Us = Ds + ((q * p + 3) & ~3);  // 16-byte aligned
     const float* dm = reinterpret_cast<const float*>(prm.small) + o.dmat;
-    const int nd = (f1 - f0) * 16 * q;
-    for (int e = threadIdx.x; e < nd; e += 512) {
-      const int v = e / (16 * q), rr = (e / q) & 15, j = e % q;
-      const int f = f0 + v, col = f / ni, row = ((f - col * ni) << k) + 16 * col + rr;
+    for (int e = threadIdx.x; e < q * p; e += 512) Ds[e] = dm[e];
+    // the segment's inputs: a block's 16 rows are 16 p contiguous elements;
+    // groups of four, eight per thread loaded before any is stored
+    const int n4 = nv * 4 * p;
+    const bool vec = src4_aligned(prm.src, prm.src_dtype, sq.u_off);  // block starts are 16-row aligned
+    for (int e0 = 0; e0 < n4; e0 += 8 * 512) {
+      f32x4 v4[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 512 * i + threadIdx.x;
+        const int v = e / (4 * p), w = 4 * (e - v * 4 * p);  // block and element within it
+        const int f = f0 + v, col = f / ni, row0 = ((f - col * ni) << k) + 16 * col;
+        const int64_t gi = sq.u_off + (int64_t)row0 * p + w;
+        const bool whole = row0 + (w + 3) / p < L;
+        f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (e < n4) {
+          if (whole && vec) {
+            a = load_src4(prm.src, prm.src_dtype, gi, true);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              if (row0 + (w + c) / p < L) a[c] = load_src<float>(prm.src, prm.src_dtype, gi + c);
+          }
+        }
+        v4[i] = a;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 512 * i + threadIdx.x;
+        if (e >= n4) break;
+        *reinterpret_cast<f32x4*>(Us + 4 * e) = v4[i];
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * 16 * q; e += 512) {
+      const int vr = e / q, j = e - vr * q;
       float a = 0.f;
-      if (row < L)
-        for (int c = 0; c < p; ++c)
-          a += dm[j * p + c] * load_src<float>(prm.src, prm.src_dtype, sq.u_off + (int64_t)row * p + c);
+      for (int c = 0; c < p; ++c) a += Ds[j * p + c] * Us[vr * p + c];
       du[e] = a;
     }
     __syncthreads();
@@ -139,8 +176,8 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const auto ry = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float*>(prm.dst) + sq.y_off, (short)0,
                                                     TAIL ? (int)((uint32_t)L * (uint32_t)q * 4u) : 0,
                                                     kBufferWord3);
-  // this lane's entries of a block: time row r, entries wave DW + 4 NT g .. + 4 NT - 1
-  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * NT * g) * 4u;
+  // this lane's entries of a block: time row r, entries wave DW + 16 t + 4 g .. + 3
+  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * g) * 4u;
   auto row_off = [&](int col, int i) -> uint32_t {
     return lane_off + (uint32_t)((i << k) + 16 * col) * (uint32_t)(MP * 4);
   };
@@ -158,7 +195,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const uint32_t off = nl < nit ? row_off(lc, li) : 0x80000000u;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      v[t] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + 16 * t, 0, 0));
+      v[t] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + 64 * t, 0, 0));
     ++nl;
     if (++li == ni) {
       li = 0;
@@ -174,11 +211,11 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   // LDS rows hold a block's entries in operand order: entry n at position
   // 32 (n / 32) + 8 ((n / 4) mod 4) + 4 ((n / 16) mod 2) + n mod 4, so that the
   // B operand of step s is the 16 bytes at 32 s + 8 g of row r. This lane
-  // writes its 4 NT entries of row r as NT groups of four.
+  // writes its entries of row r as NT groups of four.
   auto pos = [](int n) { return 32 * (n >> 5) + 8 * ((n >> 2) & 3) + 4 * ((n >> 4) & 1) + (n & 3); };
   int wr[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) wr[t] = r * RS + pos(wave * C::DW + 4 * NT * g + 4 * t);
+  for (int t = 0; t < NT; ++t) wr[t] = r * RS + pos(wave * C::DW + 16 * t + 4 * g);
   const int rd = r * RS + 8 * g;
   auto put = [&](__bf16* slot, const f32x4(&v)[NT]) {
 #pragma unroll
@@ -243,9 +280,11 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       fetch(ys + ysl2 * SLOT, b);
       keep(out && ci >= 2, b);
       contract(pa[1], b, xr[u]);
+      if constexpr (!TAIL) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, xr[u][t]), rout, off + 16 * t, 0, 0);
+        for (int t = 0; t < NT; ++t)
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, xr[u][t]), rout, off + 64 * t, 0, 0);
+      }
       if constexpr (TAIL) {
         // this wave's part of C w (outputs 4 g + v of time row r) into buffer
         // it mod 2; the previous block's partials, complete since the last
@@ -289,10 +328,10 @@ static hipError_t launch_pair_t(const StageParams& prm, const PairUnit* units, i
 
 bool pair_supported(int mp, int ct) { return ct == DT_BF16 && (mp == 128 || mp == 256); }
 
-size_t pair_lds(int mp, bool tail, int seg_blocks, int q) {
+size_t pair_lds(int mp, bool tail, int seg_blocks, int p, int q) {
   const size_t base = mp == 128 ? PairCfg<128>::LDS : PairCfg<256>::LDS;
   if (!tail) return base;
-  return base + PairCfg<256>::RED + (size_t)seg_blocks * 16 * q * sizeof(float);
+  return base + PairCfg<256>::RED + ((size_t)seg_blocks * 16 * (q + p) + (size_t)q * p + 3) * sizeof(float);
 }
 
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,

@@ -290,10 +290,10 @@ hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const Chai
 // Stages prm.k and prm.k + 1 of the forward cascade in one pass (2^k >= 16):
 // BF16 at padded m of 128 and 256. Lean: both stages are lean for every
 // sequence of the units, prm.xin and prm.xout differ. tail: k + 1 is the last
-// stage of every sequence of the units, which get y = C x + D u (q <= 16; no
-// state is stored). lds: pair_lds(mp, tail, largest T, largest q).
+// stage of every sequence of the units, which get y = C x + D u (q <= 16, p <=
+// 256; no state is stored). lds: pair_lds(mp, tail, largest T, largest p, largest q).
 bool pair_supported(int mp, int ct);
-size_t pair_lds(int mp, bool tail, int seg_blocks, int q);
+size_t pair_lds(int mp, bool tail, int seg_blocks, int p, int q);
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
                              int n_units, bool tail, size_t lds, hipStream_t s);
 

@@ -83,6 +83,29 @@ __device__ __forceinline__ X load_src(const void* src, int dtype, int64_t i) {
   return (X)bf16_bits_to_f32(((const uint16_t*)src)[i]);
 }
 
+// Elements i .. i+3 of an FP32 or BF16 input as FP32; one 16- or 8-byte load
+// when vec (the caller has checked that element i is 16- or 8-byte aligned).
+__device__ __forceinline__ f32x4 load_src4(const void* src, int dtype, int64_t i, bool vec) {
+  if (dtype == DT_F32) {
+    const float* s = (const float*)src + i;
+    if (vec) return *reinterpret_cast<const f32x4*>(s);
+    return f32x4{s[0], s[1], s[2], s[3]};
+  }
+  const uint16_t* s = (const uint16_t*)src + i;
+  if (vec) {
+    const uint2 w = *reinterpret_cast<const uint2*>(s);
+    return f32x4{__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
+                 __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u)};
+  }
+  return f32x4{bf16_bits_to_f32(s[0]), bf16_bits_to_f32(s[1]), bf16_bits_to_f32(s[2]),
+               bf16_bits_to_f32(s[3])};
+}
+// Whether element i of src may be loaded four at a time by load_src4.
+__device__ __forceinline__ bool src4_aligned(const void* src, int dtype, int64_t i) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(src) + (uintptr_t)i * (dtype == DT_F32 ? 4u : 2u);
+  return (a & (dtype == DT_F32 ? 15u : 7u)) == 0;
+}
+
 // One 16x16 MFMA step for each compute type.
 template <int CT>
 struct Mfma;

@@ -14,14 +14,16 @@ struct ResCfg {
   static constexpr int NS = (size_t)MP * MP * sizeof(Op) > 136 * 1024 ? 2 : 1;
   static constexpr int NR = MP / NS;  // output state rows per workgroup
   static constexpr int NB = NR / 16;  // 16-row output blocks per wave
-  static constexpr int PADP = 16 / (int)sizeof(Op);
+  // LDS rows padded by 32 bytes: 16-byte operand reads of 16 rows at a
+  // stride of 512 + 16 bytes conflict two ways on gfx950, at 512 + 32 bytes not
+  static constexpr int PADP = 32 / (int)sizeof(Op);
   static constexpr int SP = MP + PADP;  // LDS row stride (elements)
   static constexpr int WAVES = 8;
   static constexpr size_t LDS = (size_t)NR * SP * sizeof(Op);
   static constexpr int NV = MP / 16;  // float4 pieces of a shifted row held per lane
   // tail launches of the chain walk also stage the output matrices in LDS:
   // up to 16 rows of C (or Bbar^T) and of D (or D^T, up to 16 columns)
-  static constexpr int EPS = MP + 4;  // LDS row stride of the C rows (floats)
+  static constexpr int EPS = MP + 8;  // LDS row stride of the C rows (floats, 32-byte pad)
   static constexpr size_t LDS_TAIL = LDS + (16 * EPS + 16 * 16) * sizeof(float);
 };
 
