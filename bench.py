@@ -9,14 +9,15 @@ A step is one full forward pass over the batch: the input pass (Bbar u with
 the leading stages folded) and the remaining stage launches with the fused
 C x + D u output, inputs already in HBM, captured once as a HIP graph and
 replayed. The headline is the cascade with BF16 MFMA operands (FP32
-accumulation, FP32 state); the FP32-MFMA cascade and the plain FP32
-recursion on the same GPU are measured beside it, each with its relative
-error against the FP64 oracle. Kernel statistics for the roofline come from
-a separate eager pass with per-launch HIP events. Prints one JSON line.
---workload backward|ragged measures the gradient pass and the ragged
+accumulation) and the state between passes in FP32 (--state bf16: in BF16);
+the same apply with the other state type, the FP32-MFMA cascade and the
+plain FP32 recursion on the same GPU are measured beside it, each with its
+relative error against the FP64 oracle. Kernel statistics for the roofline
+come from a separate eager pass with per-launch HIP events. Prints one JSON
+line. --workload backward|ragged measures the gradient pass and the ragged
 persistent batch instead.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype bf16|f32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype bf16|f32] [--state f32|bf16]
 """
 
 from __future__ import annotations
@@ -72,6 +73,9 @@ def _args():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f32"])
+    ap.add_argument("--state", default="f32", choices=["f32", "bf16"],
+                    help="state kept between the passes of a BF16 apply (bf16: where every pass "
+                         "supports it); the other choice is timed beside it")
     ap.add_argument("--workload", default="batched", choices=["batched", "backward", "ragged"],
                     help="batched: 16 x L=16384, m=256 forward (the headline line); backward: "
                          "8 x L=8192, m=128 FP32 gradients; ragged: 256 sequences of uneven L and m, "
@@ -88,14 +92,21 @@ def _args():
     return ap.parse_args()
 
 
-def _stage_traffic(workload, dtype, name):
+def traffic_path(workload, dtype, state="f32"):
+    suffix = "" if state == "f32" else f"_state_{state}"
+    return os.path.join(ROOT, "profiles", f"stage_traffic_{workload}_{dtype}{suffix}.json")
+
+
+def _stage_traffic(workload, dtype, name, state="f32"):
     """HBM bytes per launch of a stage kernel from committed rocprofv3 counter
-    runs, if they were taken on the kernel's current source."""
-    path = os.path.join(ROOT, "profiles", f"stage_traffic_{workload}_{dtype}.json")
+    runs, if they were taken on the kernel's current source with this state type."""
+    path = traffic_path(workload, dtype, state)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel") != name or rec.get("kernel_sha256") != kernel_sha256(name):
+        return None
+    if rec.get("state", "f32") != state:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -173,7 +184,9 @@ def main():
         return y, ms / steps, kern
 
     def roofline(plan, kern, dtype, steps):
-        name, _, launches, nbytes, flops = dominant_kernel(plan.info())
+        info = plan.info()
+        name, _, launches, nbytes, flops = dominant_kernel(info)
+        state = {B.SSM_F32: "f32", B.SSM_BF16: "bf16", B.SSM_F64: "f64"}[info["state_dtype"]]
         n_launch, k_ms = kern
         avg_ms = k_ms / max(n_launch, 1)
         per_launch_bytes = nbytes / launches
@@ -184,7 +197,7 @@ def main():
         intensity = flops / nbytes
         ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
         bound = "mfma" if intensity > ridge else "hbm"
-        traffic = _stage_traffic(wname, dtype, name)
+        traffic = _stage_traffic(wname, dtype, name, state)
         if bound == "hbm":
             rf = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"],
                   "unit": "GB/s", "frac": round(gbps / PEAK["hbm_GBps"], 4)}
@@ -199,9 +212,11 @@ def main():
         return rf
 
     # ---------------- headline: the cascade in the chosen dtype ----------------
-    plan = CC.plan_for_workload(wl, compute=args.dtype)
+    sb = int(args.dtype == "bf16" and args.state == "bf16")
+    plan = CC.plan_for_workload(wl, compute=args.dtype, state_bf16=sb)
     y_main, ms_main, kern = run(plan, "apply", K, Wm, timing_kind=dominant_kernel(plan.info())[1],
                                 graph=True)
+    state_name = {B.SSM_F32: "f32", B.SSM_BF16: "bf16"}[plan.info()["state_dtype"]]
     value = total_steps / (ms_main * 1e-3)
     rf = roofline(plan, kern, args.dtype, K)
 
@@ -213,11 +228,24 @@ def main():
                    "q": ps.q, "N": s0.N, "delta": "log-uniform [1e-3, 1e-1] per sequence",
                    "A": "HiPPO-LegS (1-based)", "seed": args.seed},
         "roofline": rf,
+        "state": state_name,
     }
     ys = {args.dtype: CC.unpack_y(wl, y_main)}
 
     # ---------------- comparators on the same GPU ----------------
     if not args.no_compare:
+        if args.dtype == "bf16":
+            # the same BF16 apply with the other state type between passes
+            plan_s = CC.plan_for_workload(wl, compute="bf16", state_bf16=1 - sb)
+            sname = {B.SSM_F32: "f32", B.SSM_BF16: "bf16"}[plan_s.info()["state_dtype"]]
+            y_s, ms_s, kern_s = run(plan_s, "apply", K, Wm,
+                                    timing_kind=dominant_kernel(plan_s.info())[1], graph=True)
+            key = f"bf16_state_{sname}"
+            ys[key] = CC.unpack_y(wl, y_s)
+            out[f"cascade_{key}"] = {"value": round(total_steps / (ms_s * 1e-3), 1),
+                                     "ms_per_step": round(ms_s, 4),
+                                     "roofline": roofline(plan_s, kern_s, "bf16", K)}
+            plan_s.close()
         other = "f32" if args.dtype == "bf16" else "bf16"
         plan_o = CC.plan_for_workload(wl, compute=other)
         y_o, ms_o, kern_o = run(plan_o, "apply", K, Wm, timing_kind=dominant_kernel(plan_o.info())[1],

@@ -142,7 +142,15 @@ typedef struct {
    * sequences all run stages after the folded ones. 0: automatic (on where
    * supported), 1: off. */
   int32_t input_split;
-  int32_t reserved[5];   /* must be 0 */
+  /* State kept between the passes of the forward apply (ssm_cascade_apply and
+   * its graph; BF16 plans). 0: FP32. 1: BF16 where every pass is the split
+   * input pass or a stage pair and the last pair forms y: each pass then reads
+   * and writes the state as BF16, still accumulating y_l and w_l in FP32 and
+   * rounding them once (to nearest even) when they are written, which halves
+   * the state traffic for one more rounding of the state per pass; otherwise
+   * FP32 (ssm_plan_info.state_dtype says which). The backward keeps FP32. */
+  int32_t state_bf16;
+  int32_t reserved[4];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -198,6 +206,8 @@ typedef struct {
                                 part of stage_bytes) */
   double pair_bytes;         /* compulsory HBM bytes of the stage-pair launches */
   double pair_flops;         /* stage flops of the stage-pair launches */
+  int32_t state_dtype;       /* ssm_dtype of the state between forward passes */
+  int32_t reserved;
 } ssm_plan_info;
 
 typedef struct ssm_plan_s* ssm_plan;

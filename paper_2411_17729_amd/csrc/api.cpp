@@ -75,6 +75,7 @@ struct ssm_plan_s {
   int n_seq = 0, n_ops = 0, n_sets = 0;
   int compute = DT_F32;  // DT_* of the stage operands
   int state_f64 = 0;     // state / io element is double
+  int state_bf16 = 0;    // the forward apply keeps the state between passes in BF16
   int disc = 0;
   int with_backward = 0, ckpt_every = 1;
   int max_last = 0, max_mp = 32, max_N = 0;
@@ -227,6 +228,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     return fail(SSM_E_INVALID, "pair_blocks = %d: supported 0 (automatic) or 4..256", tn.pair_blocks);
   if (tn.input_split < 0 || tn.input_split > 1)
     return fail(SSM_E_INVALID, "input_split = %d: supported 0 (automatic) or 1 (off)", tn.input_split);
+  if (tn.state_bf16 < 0 || tn.state_bf16 > 1)
+    return fail(SSM_E_INVALID, "state_bf16 = %d: supported 0 (FP32 state) or 1 (BF16 where supported)",
+                tn.state_bf16);
   if (tn.stage_kernel == SSM_STAGE_TILED || compute == SSM_F64)
     P.stage_kernel = SSM_STAGE_TILED;
   else
@@ -585,6 +589,31 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     }
   }
 
+  // BF16 state between the passes of the forward apply: only where every pass
+  // of every class is the split input pass or a stage pair ending in a tail
+  // pair (the only kernels that read and write it)
+  P.state_bf16 = 0;
+  if (tn.state_bf16 == 1) {
+    bool ok = true, any = false;
+    for (int c = 0; c < 4 && ok; ++c) {
+      if (P.class_max_last[c] < 0) continue;
+      any = true;
+      ok = P.class_input_count[c] > 0;
+      int kk = P.class_min_kry[c];
+      bool tail = false;
+      while (ok && kk <= P.class_max_last[c]) {
+        ok = kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
+        if (ok && P.pair_tail[c][kk]) {
+          tail = kk + 1 == P.class_max_last[c];
+          break;
+        }
+        kk += 2;
+      }
+      ok = ok && tail;
+    }
+    P.state_bf16 = ok && any;
+  }
+
   // persistent work items, level by level (projection = level -1), longer
   // sequences first inside a level; default tile heights
   P.items.clear();
@@ -710,9 +739,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   }
   // algorithmic HBM bytes of the stage launches: per stage and row, read the
   // row once and write it once (state element size); the last stage writes y
-  // instead of the state. The shifted partner of a row is a row of the same
-  // stage input, so it adds no compulsory traffic.
-  const double xe = (double)P.x_elem();
+  // (element of y) instead of the state. The shifted partner of a row is a
+  // row of the same stage input, so it adds no compulsory traffic.
+  const double xe = P.state_bf16 ? 2.0 : (double)P.x_elem(), ye = (double)P.x_elem();
   auto pair_at = [&](int c, int kk) {
     return kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
   };
@@ -740,7 +769,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     for (int kk = s.kry; kk <= s.last; ++kk) {
       const int kl = pair_at(c, kk) ? kk + 1 : kk;  // the launch's last stage
       const double in_row = (double)m * xe;
-      const double out_row = kl == s.last ? (double)s.q * xe : (double)m * xe;
+      const double out_row = kl == s.last ? (double)s.q * ye : (double)m * xe;
       P.stage_bytes += s.L * (in_row + out_row);
       if (pair_at(c, kk)) {  // the pair's second stage moves no further rows
         P.pair_bytes += s.L * (in_row + out_row);
@@ -1574,8 +1603,9 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       if (P.class_input_count[c] > 0) {
         const ResRange* un = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_input) +
                              P.class_input_start[c];
-        e = launch_input_split(kClassMp[c], P.compute, P.class_input_p[c], P.class_input_kdim[c], prm,
-                               un, P.class_input_count[c], P.class_input_lds[c], stream);
+        e = launch_input_split(kClassMp[c], P.compute, P.class_input_p[c], P.class_input_kdim[c],
+                               P.state_bf16 != 0, prm, un, P.class_input_count[c], P.class_input_lds[c],
+                               stream);
       } else {
         const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
                              P.class_range_start[c];
@@ -1600,7 +1630,7 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
         const PairUnit* un = reinterpret_cast<const PairUnit*>(P.ws + P.r_meta.off + P.m_pair) +
                              P.pair_start[c][kk];
         e = launch_stage_pair(kClassMp[c], P.compute, prm, un, P.pair_count[c][kk],
-                              P.pair_tail[c][kk] != 0, P.pair_lds_bytes[c][kk], stream);
+                              P.pair_tail[c][kk] != 0, P.state_bf16 != 0, P.pair_lds_bytes[c][kk], stream);
       } else {
         e = launch_stage_any(P, c, prm, stream);
       }
@@ -1890,6 +1920,7 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->pair_launches = plan->pair_launches;
   info->pair_bytes = plan->pair_bytes;
   info->pair_flops = plan->pair_flops;
+  info->state_dtype = plan->state_bf16 ? SSM_BF16 : plan->state_f64 ? SSM_F64 : SSM_F32;
   return SSM_OK;
 }
 

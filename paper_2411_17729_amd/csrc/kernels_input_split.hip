@@ -17,7 +17,8 @@
 // contraction, and a lane's operand is 16 (8 | p) or twice 8 (p = 4)
 // contiguous bytes of LDS. The kernel is specialised on the number of MFMA
 // steps (2^j p of 128, 256 or 512) and the operand width, so that a block's
-// operand reads all go out before its MFMAs.
+// operand reads all go out before its MFMAs. The state it writes is FP32, or
+// BF16 (XB, rounded once from the FP32 accumulators).
 #include "stage_common.h"
 #include "ssm_internal.h"
 
@@ -30,12 +31,14 @@ struct InputCfg {
   static constexpr int NT = DW / 16;    // MFMA output tiles of a wave
 };
 
-// KS: MFMA steps (2^j p / 32); V16: 8 | p (one 16-byte operand read; else p = 4)
-template <int MP, int KS, bool V16>
+// KS: MFMA steps (2^j p / 32); V16: 8 | p (one 16-byte operand read; else p =
+// 4); XB: BF16 state
+template <int MP, int KS, bool V16, bool XB>
 __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_input_split(
     StageParams prm, const ResRange* units) {
   using C = InputCfg<MP>;
   constexpr int NT = C::NT;
+  constexpr int ES = XB ? 2 : 4;  // bytes of a state entry in HBM
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_in[];
   __bf16* us = reinterpret_cast<__bf16*>(smem_in);
 
@@ -51,10 +54,48 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const int hi = rg.row0 + rg.nrows;        // rows row0 .. hi - 1 of this unit
 
   // rows of K_j owned by this wave, A operands: row index r of output tile t
-  // is state entry wave DW + 16 t + r (a lane's accumulators are entries
-  // 16 t + 4 g .. + 3 of its time row, 64 contiguous bytes of a row per store);
-  // step s, lane group g holds columns 32 s + 8 g .. + 7
-  auto ent = [&](int t, int rr) { return wave * C::DW + 16 * t + rr; };
+  // is state entry ent(t, r), and a lane's accumulators are the entries
+  // ent(t, 4 g) .. + 3 of its time row. FP32 state: ent(t, r) = wave DW +
+  // 16 t + r (entries 16 t + 4 g .. + 3, 64 contiguous bytes of a row per
+  // store); BF16 state: ent(t, r) = wave DW + 4 NT (r / 4) + 4 t + r mod 4
+  // (the lane's tiles are 4 NT contiguous entries, one store). Step s, lane
+  // group g holds columns 32 s + 8 g .. + 7.
+  auto ent = [&](int t, int rr) {
+    return XB ? wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3) : wave * C::DW + 16 * t + rr;
+  };
+
+  // inputs of rows row0 - lag .. hi - 1 into LDS, row l at (hi - 1 - l) p,
+  // rounded to BF16 (zeros before the start); four channels per element
+  // group, eight groups per thread loaded before any is stored. The loads of
+  // the first eight groups go out before those of the K_j rows, so that the
+  // two latencies overlap and the staging waits for its own loads only.
+  const int n4 = (rg.nrows + lag) * p / 4;
+  const int64_t ubase = sq.u_off + (int64_t)(rg.row0 - lag) * p;  // element of the first row
+  const bool vec = src4_aligned(prm.src, prm.src_dtype, sq.u_off);  // p is a multiple of 4
+  f32x4 v[8];
+  auto load_groups = [&](int e0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 512 * i + threadIdx.x, row = rg.row0 - lag + 4 * e / p;
+      v[i] = e < n4 && row >= 0 && row < L ? load_src4(prm.src, prm.src_dtype, ubase + 4 * e, vec)
+                                          : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto store_groups = [&](int e0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 512 * i + threadIdx.x;
+      if (e < n4) {
+        const int flat = 4 * e, row = rg.row0 - lag + flat / p, ch = flat % p;
+        bf16x4 b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = (__bf16)v[i][c];  // round to nearest even
+        *reinterpret_cast<bf16x4*>(us + (hi - 1 - row) * p + ch) = b;
+      }
+    }
+  };
+  load_groups(0);
+  __builtin_amdgcn_sched_barrier(0);
   bf16x8 ka[NT][KS];
   {
     const __bf16* K = reinterpret_cast<const __bf16*>(prm.P) + o.kc;
@@ -64,43 +105,22 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       for (int s = 0; s < KS; ++s)
         ka[t][s] = *reinterpret_cast<const bf16x8*>(K + (int64_t)ent(t, r) * o.kst + 32 * s + 8 * g);
   }
-
-  // inputs of rows row0 - lag .. hi - 1 into LDS, row l at (hi - 1 - l) p,
-  // rounded to BF16 (zeros before the start); four channels per element
-  // group, eight groups per thread loaded before any is stored
-  {
-    const int n4 = (rg.nrows + lag) * p / 4;
-    const int64_t ubase = sq.u_off + (int64_t)(rg.row0 - lag) * p;  // element of the first row
-    const bool vec = src4_aligned(prm.src, prm.src_dtype, sq.u_off);  // p is a multiple of 4
-    for (int e0 = 0; e0 < n4; e0 += 8 * 512) {
-      f32x4 v[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int e = e0 + 512 * i + threadIdx.x, row = rg.row0 - lag + 4 * e / p;
-        v[i] = e < n4 && row >= 0 && row < L ? load_src4(prm.src, prm.src_dtype, ubase + 4 * e, vec)
-                                            : f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int e = e0 + 512 * i + threadIdx.x;
-        if (e >= n4) break;
-        const int flat = 4 * e, row = rg.row0 - lag + flat / p, ch = flat % p;
-        bf16x4 b;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = (__bf16)v[i][c];  // round to nearest even
-        *reinterpret_cast<bf16x4*>(us + (hi - 1 - row) * p + ch) = b;
-      }
-    }
-    __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
+  store_groups(0);
+  for (int e0 = 8 * 512; e0 < n4; e0 += 8 * 512) {
+    load_groups(e0);
+    store_groups(e0);
   }
+  __syncthreads();
 
   // x^(j) rows through a buffer resource over the sequence's L x MP block
   // (stores of rows past L are dropped); buffer kry mod 2 as for the resident
   // input pass
-  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * 4);
-  float* xo = reinterpret_cast<float*>((sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off;
+  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * ES);
+  unsigned char* xo =
+      reinterpret_cast<unsigned char*>((sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off * ES;
   const auto rout = __builtin_amdgcn_make_buffer_rsrc(xo, (short)0, (int)nrec, kBufferWord3);
-  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * g) * 4u;
+  const uint32_t lane_off = (uint32_t)(r * MP + ent(0, 4 * g)) * (uint32_t)ES;
   const int nblk = (rg.nrows + 15) / 16;
   for (int b = 0; b < nblk; ++b) {
     const int l = rg.row0 + 16 * b + r;
@@ -129,32 +149,49 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     // every operand read of the block before its MFMAs (one LDS round trip per block)
     __builtin_amdgcn_sched_group_barrier(0x100, V16 ? KS : 2 * KS, 0);
     __builtin_amdgcn_sched_group_barrier(0x008, KS * NT, 0);
-    const uint32_t off = l < hi ? lane_off + (uint32_t)(16 * b + rg.row0) * (uint32_t)(MP * 4) : 0x80000000u;
+    const uint32_t off = l < hi ? lane_off + (uint32_t)(16 * b + rg.row0) * (uint32_t)(MP * ES) : 0x80000000u;
+    if constexpr (!XB) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[t]), rout, off + 64 * t, 0, 0);
+      for (int t = 0; t < NT; ++t)
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[t]), rout, off + 64 * t, 0, 0);
+    } else {
+      bf16x8 xb;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xb[4 * t + e] = (__bf16)acc[t][e];  // round to nearest even
+      const u32x4 w4 = __builtin_bit_cast(u32x4, xb);
+      if constexpr (NT == 2) {
+        __builtin_amdgcn_raw_buffer_store_b128(w4, rout, off, 0, 0);
+      } else {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{w4[0], w4[1]}, rout, off, 0, 0);
+      }
+    }
   }
 }
 
-template <int MP, int KS, bool V16>
+template <int MP, int KS, bool V16, bool XB>
 static hipError_t launch_input_t(const StageParams& prm, const ResRange* units, int n_units,
                                  size_t lds, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_input_split<MP, KS, V16>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_input_split<MP, KS, V16, XB>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_input_split<MP, KS, V16>), dim3(n_units), dim3(512), lds, s, prm, units);
+  hipLaunchKernelGGL((k_input_split<MP, KS, V16, XB>), dim3(n_units), dim3(512), lds, s, prm, units);
   return hipGetLastError();
 }
 
 template <int MP, int KS>
-static hipError_t launch_input_w(bool v16, const StageParams& prm, const ResRange* units,
+static hipError_t launch_input_w(bool v16, bool xb, const StageParams& prm, const ResRange* units,
                                  int n_units, size_t lds, hipStream_t s) {
-  return v16 ? launch_input_t<MP, KS, true>(prm, units, n_units, lds, s)
-             : launch_input_t<MP, KS, false>(prm, units, n_units, lds, s);
+  if (xb)
+    return v16 ? launch_input_t<MP, KS, true, true>(prm, units, n_units, lds, s)
+               : launch_input_t<MP, KS, false, true>(prm, units, n_units, lds, s);
+  return v16 ? launch_input_t<MP, KS, true, false>(prm, units, n_units, lds, s)
+             : launch_input_t<MP, KS, false, false>(prm, units, n_units, lds, s);
 }
 
 bool input_split_supported(int mp, int ct, int p, int kdim) {
@@ -162,17 +199,17 @@ bool input_split_supported(int mp, int ct, int p, int kdim) {
          (kdim == 128 || kdim == 256 || (kdim == 512 && mp == 256));
 }
 
-hipError_t launch_input_split(int mp, int ct, int p, int kdim, const StageParams& prm,
+hipError_t launch_input_split(int mp, int ct, int p, int kdim, bool xb, const StageParams& prm,
                               const ResRange* units, int n_units, size_t lds, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   if (!input_split_supported(mp, ct, p, kdim) || lds > 65536) return hipErrorInvalidValue;
   const bool v16 = (p & 7) == 0;
   if (mp == 128)
-    return kdim == 128 ? launch_input_w<128, 4>(v16, prm, units, n_units, lds, s)
-                       : launch_input_w<128, 8>(v16, prm, units, n_units, lds, s);
-  return kdim == 128   ? launch_input_w<256, 4>(v16, prm, units, n_units, lds, s)
-         : kdim == 256 ? launch_input_w<256, 8>(v16, prm, units, n_units, lds, s)
-                       : launch_input_w<256, 16>(v16, prm, units, n_units, lds, s);
+    return kdim == 128 ? launch_input_w<128, 4>(v16, xb, prm, units, n_units, lds, s)
+                       : launch_input_w<128, 8>(v16, xb, prm, units, n_units, lds, s);
+  return kdim == 128   ? launch_input_w<256, 4>(v16, xb, prm, units, n_units, lds, s)
+         : kdim == 256 ? launch_input_w<256, 8>(v16, xb, prm, units, n_units, lds, s)
+                       : launch_input_w<256, 16>(v16, xb, prm, units, n_units, lds, s);
 }
 
 }  // namespace ssmc

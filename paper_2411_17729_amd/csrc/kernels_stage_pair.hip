@@ -29,6 +29,10 @@
 // block, behind the same barrier), and wave v adds them for rows 2v and 2v+1
 // with D u_l. The D u_l of the segment's rows are formed at the start into
 // LDS, so that no load in the walk is waited for out of order.
+//
+// The state between passes is FP32, or BF16 (XB): then the rows are loaded and
+// stored as BF16, x goes to LDS as loaded, and y and w are still accumulated
+// in FP32 and rounded once, when they are written.
 #include "stage_common.h"
 #include "ssm_internal.h"
 
@@ -50,11 +54,12 @@ struct PairCfg {
   static constexpr size_t RED = 2 * NW * 16 * 16 * sizeof(float);
 };
 
-template <int MP, bool TAIL>
+template <int MP, bool TAIL, bool XB>
 __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_stage_pair(
     StageParams prm, const PairUnit* units) {
   using C = PairCfg<MP>;
   constexpr int NT = C::NT, KS = C::KS, DP = C::DP, RS = C::RS, SLOT = C::SLOT;
+  constexpr int ES = XB ? 2 : 4;  // bytes of a state entry in HBM
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pair[];
   __bf16* xs = reinterpret_cast<__bf16*>(smem_pair);
   __bf16* ys = xs + 2 * SLOT;
@@ -78,13 +83,19 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const int nit = f1 - f0 + nw;   // blocks visited
 
   // Rows of P_k and P_{k+1} owned by this wave, as A operands: row index r of
-  // output tile t is state entry ent(t, r) = wave DW + 16 t + r, so a lane's
-  // accumulators are entries 16 t + 4 g .. + 3 of its time row and every
-  // memory instruction moves 64 contiguous bytes of each row. Contraction step
-  // s covers entries 32 s .. 32 s + 31 with operand slot 8 g + 4 h + e holding
+  // output tile t is state entry ent(t, r), so a lane's accumulators are the
+  // entries ent(t, 4 g) .. + 3 of its time row. FP32 state: ent(t, r) =
+  // wave DW + 16 t + r, entries 16 t + 4 g .. + 3 of the wave's share, and
+  // every memory instruction moves 64 contiguous bytes of each row. BF16
+  // state: ent(t, r) = wave DW + 4 NT (r / 4) + 4 t + r mod 4, so that the
+  // lane's NT tiles are the 4 NT contiguous entries from 4 NT g on and one
+  // instruction moves the wave's whole share of each row. Contraction step s
+  // covers entries 32 s .. 32 s + 31 with operand slot 8 g + 4 h + e holding
   // entry 32 s + 16 h + 4 g + e, the assignment of the chain kernel, so that
   // every output sees the same products in the same MFMA steps as there.
-  auto ent = [&](int t, int rr) { return wave * C::DW + 16 * t + rr; };
+  auto ent = [&](int t, int rr) {
+    return XB ? wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3) : wave * C::DW + 16 * t + rr;
+  };
   bf16x8 pa[2][NT][KS];
   {
     const __bf16* P0 = reinterpret_cast<const __bf16*>(prm.P) + o.pc + (int64_t)k * MP * MP;
@@ -104,11 +115,11 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   // State rows through buffer resources over the sequence's L x MP block:
   // rows past L read as zero and their stores are dropped; offset 2^31 marks
   // an absent block.
-  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * 4);
+  const uint32_t nrec = (uint32_t)L * (uint32_t)(MP * ES);
   const auto rin = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float*>(reinterpret_cast<const float*>(prm.xin)) + sq.x_off, (short)0, (int)nrec,
-      kBufferWord3);
-  const auto rout = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float*>(prm.xout) + sq.x_off,
+      const_cast<unsigned char*>(reinterpret_cast<const unsigned char*>(prm.xin)) + sq.x_off * ES,
+      (short)0, (int)nrec, kBufferWord3);
+  const auto rout = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<unsigned char*>(prm.xout) + sq.x_off * ES,
                                                       (short)0, (int)nrec, kBufferWord3);
 
   // tail: C's columns for this wave's entries as FP32 MFMA A operands (row
@@ -126,7 +137,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        ca[t][v] = r < q ? cm[r * MP + wave * C::DW + 16 * t + 4 * g + v] : 0.f;
+        ca[t][v] = r < q ? cm[r * MP + ent(t, 4 * g + v)] : 0.f;
     const int nv = f1 - f0;
     float* Ds = du + nv * 16 * q;
     float* Us = Ds + ((q * p + 3) & ~3);  // 16-byte aligned
@@ -176,46 +187,86 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const auto ry = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float*>(prm.dst) + sq.y_off, (short)0,
                                                     TAIL ? (int)((uint32_t)L * (uint32_t)q * 4u) : 0,
                                                     kBufferWord3);
-  // this lane's entries of a block: time row r, entries wave DW + 16 t + 4 g .. + 3
-  const uint32_t lane_off = (uint32_t)(r * MP + wave * C::DW + 4 * g) * 4u;
+  // this lane's entries of a block: time row r, from entry ent(0, 4 g) on
+  const uint32_t lane_off = (uint32_t)(r * MP + ent(0, 4 * g)) * (uint32_t)ES;
   auto row_off = [&](int col, int i) -> uint32_t {
-    return lane_off + (uint32_t)((i << k) + 16 * col) * (uint32_t)(MP * 4);
+    return lane_off + (uint32_t)((i << k) + 16 * col) * (uint32_t)(MP * ES);
   };
 
-  // Blocks are loaded DP visits ahead into a ring of registers; a block is
-  // accumulated in place and its registers take the load of the block DP
-  // visits later once it is stored. The visits are padded to a multiple of
-  // DP, and loads and stores are issued on every visit (out of range where
-  // there is nothing to move), so every path has the same memory operations
-  // in flight and the compiler's counter waits stay exact.
+  // Blocks are loaded DP visits ahead into a ring of registers (FP32 state:
+  // a block is accumulated in place); a slot takes the load of the block DP
+  // visits later once its block is stored. The visits are padded to a
+  // multiple of DP, and loads and stores are issued on every visit (out of
+  // range where there is nothing to move), so every path has the same memory
+  // operations in flight and the compiler's counter waits stay exact.
   const int npad = (nit + DP - 1) / DP * DP;
-  f32x4 xr[DP][NT];
+  f32x4 xr[DP][NT];   // FP32 state
+  u32x4 xh[DP];       // BF16 state, NT = 2: entries 8 g .. + 7
+  u32x2 xq[DP];       // BF16 state, NT = 1: entries 4 g .. + 3
   int lc = c0, li = i0 - nw, nl = 0;  // next block to load and how many were issued
-  auto issue = [&](f32x4(&v)[NT]) {
+  auto issue = [&](int u) {
     const uint32_t off = nl < nit ? row_off(lc, li) : 0x80000000u;
+    if constexpr (!XB) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-      v[t] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + 64 * t, 0, 0));
+      for (int t = 0; t < NT; ++t)
+        xr[u][t] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, off + 64 * t, 0, 0));
+    } else if constexpr (NT == 2) {
+      xh[u] = __builtin_amdgcn_raw_buffer_load_b128(rin, off, 0, 0);
+    } else {
+      xq[u] = __builtin_amdgcn_raw_buffer_load_b64(rin, off, 0, 0);
+    }
     ++nl;
     if (++li == ni) {
       li = 0;
       ++lc;
     }
   };
+  // w of a block (lean variant), BF16 rounded to nearest even for XB
+  auto store_w = [&](uint32_t off, const f32x4(&acc)[NT]) {
+    if constexpr (!XB) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[t]), rout, off + 64 * t, 0, 0);
+    } else {
+      bf16x8 wb;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) wb[4 * t + e] = (__bf16)acc[t][e];
+      const u32x4 w4 = __builtin_bit_cast(u32x4, wb);
+      if constexpr (NT == 2) {
+        __builtin_amdgcn_raw_buffer_store_b128(w4, rout, off, 0, 0);
+      } else {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{w4[0], w4[1]}, rout, off, 0, 0);
+      }
+    }
+  };
+  // The ring is filled as DP visits would fill it, each load after the
+  // stores of a visit (out of range here, so nothing is written): the memory
+  // counter then stands at the loop's entry as it does on every later pass,
+  // and the compiler's wait for a slot covers that slot's load only.
 #pragma unroll
   for (int u = 0; u < DP; ++u) {
-    issue(xr[u]);
+    if constexpr (TAIL) {
+      __builtin_amdgcn_raw_buffer_store_b32(0u, ry, 0x80000000u, 0, 0);
+    } else {
+      f32x4 z[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) z[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      store_w(0x80000000u, z);
+    }
+    issue(u);
     __builtin_amdgcn_sched_barrier(0);  // keep the ring's loads in visit order
   }
 
   // LDS rows hold a block's entries in operand order: entry n at position
   // 32 (n / 32) + 8 ((n / 4) mod 4) + 4 ((n / 16) mod 2) + n mod 4, so that the
   // B operand of step s is the 16 bytes at 32 s + 8 g of row r. This lane
-  // writes its entries of row r as NT groups of four.
+  // writes its entries of row r as NT groups of four, ent(t, 4 g) .. + 3.
   auto pos = [](int n) { return 32 * (n >> 5) + 8 * ((n >> 2) & 3) + 4 * ((n >> 4) & 1) + (n & 3); };
   int wr[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) wr[t] = r * RS + pos(wave * C::DW + 16 * t + 4 * g);
+  for (int t = 0; t < NT; ++t) wr[t] = r * RS + pos(ent(t, 4 * g));
   const int rd = r * RS + 8 * g;
   auto put = [&](__bf16* slot, const f32x4(&v)[NT]) {
 #pragma unroll
@@ -225,6 +276,29 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       for (int e = 0; e < 4; ++e) b[e] = (__bf16)v[t][e];  // round to nearest even
       *reinterpret_cast<bf16x4*>(slot + wr[t]) = b;
     }
+  };
+  // BF16 state: x of ring slot u goes to LDS as loaded and is widened to FP32
+  // as the accumulator of y
+  auto put_raw = [&](__bf16* slot, int u) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      u32x2 w2;
+      if constexpr (NT == 2) {
+        w2 = u32x2{xh[u][2 * t], xh[u][2 * t + 1]};
+      } else {
+        w2 = xq[u];
+      }
+      *reinterpret_cast<u32x2*>(slot + wr[t]) = w2;
+    }
+  };
+  auto widen = [&](int u, f32x4(&acc)[NT]) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t w2 = NT == 2 ? xh[u][2 * t + e / 2] : xq[u][e / 2];
+        acc[t][e] = __builtin_bit_cast(float, (e & 1) ? (w2 & 0xffff0000u) : (w2 << 16));
+      }
   };
   auto fetch = [&](const __bf16* slot, bf16x8(&b)[KS]) {
 #pragma unroll
@@ -268,23 +342,29 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       const bool out = real && it >= nw;
       const uint32_t off = out ? row_off(cc, ci) : 0x80000000u;
       const int ysl2 = ysl == 2 ? 0 : ysl + 1;  // slot of the y two blocks back: it - 2 = it + 1 mod 3
-      put(xs + (it & 1) * SLOT, xr[u]);
-      bf16x8 b[KS];
+      // both partners, complete since the last barrier, are read before this
+      // block's x and y go to their own slots, so that all the operand reads
+      // of the visit are in flight together
+      bf16x8 b[KS], b2[KS];
       fetch(xs + ((it + 1) & 1) * SLOT, b);
+      fetch(ys + ysl2 * SLOT, b2);
+      f32x4 xw[NT];  // BF16 state: the block's accumulators
+      f32x4(&acc)[NT] = XB ? xw : xr[u];
+      if constexpr (XB) {
+        put_raw(xs + (it & 1) * SLOT, u);
+        widen(u, xw);
+      } else {
+        put(xs + (it & 1) * SLOT, xr[u]);
+      }
       // y = x + P_k x_prev (no partner at a column's first block; the first of
       // three warm-up blocks only provides x)
       keep(real && ci >= 1 && it > nw - 3, b);
-      contract(pa[0], b, xr[u]);
-      put(ys + ysl * SLOT, xr[u]);
+      contract(pa[0], b, acc);
+      put(ys + ysl * SLOT, acc);
       // w = y + P_{k+1} y_prev2
-      fetch(ys + ysl2 * SLOT, b);
-      keep(out && ci >= 2, b);
-      contract(pa[1], b, xr[u]);
-      if constexpr (!TAIL) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, xr[u][t]), rout, off + 64 * t, 0, 0);
-      }
+      keep(out && ci >= 2, b2);
+      contract(pa[1], b2, acc);
+      if constexpr (!TAIL) store_w(off, acc);
       if constexpr (TAIL) {
         // this wave's part of C w (outputs 4 g + v of time row r) into buffer
         // it mod 2; the previous block's partials, complete since the last
@@ -293,15 +373,18 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][v], xr[u][t][v], ya, 0, 0, 0);
+          for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][v], acc[t][v], ya, 0, 0, 0);
         *reinterpret_cast<f32x4*>(red + (it & 1) * (C::NW * 256) + (wave * 16 + r) * 16 + 4 * g) = ya;
         finish(red + ((it + 1) & 1) * (C::NW * 256), pl0, pout, pv);
         pl0 = (ci << k) + 16 * cc;
         pout = out;
         pv = out ? it - nw : 0;
       }
-      issue(xr[u]);
+      issue(u);
       __syncthreads();
+      // a visit's work stays in it: hoisted, the widening of the next slot
+      // would wait for that slot's load a visit early
+      __builtin_amdgcn_sched_barrier(0);
       ysl = ysl2;
       if (++ci == ni) {
         ci = 0;
@@ -312,18 +395,25 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   if constexpr (TAIL) finish(red + ((npad + 1) & 1) * (C::NW * 256), pl0, pout, pv);  // the last block
 }
 
-template <int MP, bool TAIL>
-static hipError_t launch_pair_t(const StageParams& prm, const PairUnit* units, int n_units,
+template <int MP, bool TAIL, bool XB>
+static hipError_t launch_pair_v(const StageParams& prm, const PairUnit* units, int n_units,
                                 size_t lds, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_pair<MP, TAIL>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_pair<MP, TAIL, XB>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_stage_pair<MP, TAIL>), dim3(n_units), dim3(512), lds, s, prm, units);
+  hipLaunchKernelGGL((k_stage_pair<MP, TAIL, XB>), dim3(n_units), dim3(512), lds, s, prm, units);
   return hipGetLastError();
+}
+
+template <int MP, bool TAIL>
+static hipError_t launch_pair_t(bool xb, const StageParams& prm, const PairUnit* units, int n_units,
+                                size_t lds, hipStream_t s) {
+  return xb ? launch_pair_v<MP, TAIL, true>(prm, units, n_units, lds, s)
+            : launch_pair_v<MP, TAIL, false>(prm, units, n_units, lds, s);
 }
 
 bool pair_supported(int mp, int ct) { return ct == DT_BF16 && (mp == 128 || mp == 256); }
@@ -335,14 +425,14 @@ size_t pair_lds(int mp, bool tail, int seg_blocks, int p, int q) {
 }
 
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
-                             int n_units, bool tail, size_t lds, hipStream_t s) {
+                             int n_units, bool tail, bool xb, size_t lds, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   if (ct != DT_BF16 || prm.adjoint || lds > 160 * 1024) return hipErrorInvalidValue;
   switch (mp) {
-    case 128: return tail ? launch_pair_t<128, true>(prm, units, n_units, lds, s)
-                          : launch_pair_t<128, false>(prm, units, n_units, lds, s);
-    case 256: return tail ? launch_pair_t<256, true>(prm, units, n_units, lds, s)
-                          : launch_pair_t<256, false>(prm, units, n_units, lds, s);
+    case 128: return tail ? launch_pair_t<128, true>(xb, prm, units, n_units, lds, s)
+                          : launch_pair_t<128, false>(xb, prm, units, n_units, lds, s);
+    case 256: return tail ? launch_pair_t<256, true>(xb, prm, units, n_units, lds, s)
+                          : launch_pair_t<256, false>(xb, prm, units, n_units, lds, s);
   }
   return hipErrorInvalidValue;
 }

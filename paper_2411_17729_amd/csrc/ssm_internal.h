@@ -275,9 +275,10 @@ hipError_t launch_krylov_res(int mp, int ct, const StageParams& prm, const ResRa
 // 128, 256 or 512 and at most 2 mp, every sequence with stages after j): x^(j)
 // into xin (j even) or xout (j odd). All operators of a launch share p and
 // 2^j p. units: row ranges; lds: (rows + 2^j - 1) p 2 bytes for the largest
-// unit, at most 64 KiB.
+// unit, at most 64 KiB. xb: the state is stored as BF16 (element offsets
+// x_off as for FP32, two bytes each).
 bool input_split_supported(int mp, int ct, int p, int kdim);
-hipError_t launch_input_split(int mp, int ct, int p, int kdim, const StageParams& prm,
+hipError_t launch_input_split(int mp, int ct, int p, int kdim, bool xb, const StageParams& prm,
                               const ResRange* units, int n_units, size_t lds, hipStream_t s);
 // Chain-walking stage kernel (stages with 2^k >= 16): BF16 and FP32 at padded
 // m of 64..256; FP32 m = 256 splits the output rows over two workgroups and
@@ -291,11 +292,12 @@ hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const Chai
 // BF16 at padded m of 128 and 256. Lean: both stages are lean for every
 // sequence of the units, prm.xin and prm.xout differ. tail: k + 1 is the last
 // stage of every sequence of the units, which get y = C x + D u (q <= 16, p <=
-// 256; no state is stored). lds: pair_lds(mp, tail, largest T, largest p, largest q).
+// 256; no state is stored). xb: the state read (and written) is BF16. lds:
+// pair_lds(mp, tail, largest T, largest p, largest q).
 bool pair_supported(int mp, int ct);
 size_t pair_lds(int mp, bool tail, int seg_blocks, int p, int q);
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
-                             int n_units, bool tail, size_t lds, hipStream_t s);
+                             int n_units, bool tail, bool xb, size_t lds, hipStream_t s);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
