@@ -472,6 +472,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     o.kst = o.mp;
     o.ksplit = 0;
     o.kw = o.kc = -1;
+    o.cpw = o.cpc = -1;
+    o.cpl = -1;
     if (tn.input_stages < 0 || !(P.launch == SSM_LAUNCH_PER_STAGE || P.persist_res) ||
         P.stage_kernel == SSM_STAGE_TILED || !res_supported(o.mp, P.compute))
       continue;
@@ -586,6 +588,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       P.pair_count[c][kk] = (int)P.pair_units.size() - P.pair_start[c][kk];
       P.pair_tail[c][kk] = tail;
       P.pair_lds_bytes[c][kk] = pair_lds(kClassMp[c], tail, T, max_p, max_q);
+      if (tail)  // the tail pair forms C P_{k+1} y_{l-2^{k+1}} with C P_{k+1} precomputed
+        for (OpDev& o : P.ops)
+          if (class_of(o.mp) == c) o.cpl = kk + 1;
     }
   }
 
@@ -804,6 +809,12 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       o.kw = (int64_t)n_kw;
       n_kw += (size_t)o.mp * o.kst;
     }
+    if (o.cpl >= 0) {
+      o.cpc = (int64_t)n_pc;
+      n_pc += (size_t)16 * o.mp;
+      o.cpw = (int64_t)n_kw;
+      n_kw += (size_t)16 * o.mp;
+    }
     if (P.with_backward) {
       o.pct = (int64_t)n_pc;
       n_pc += (size_t)(o.N + 1) * mm;
@@ -857,7 +868,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + 16);
   // jobs: 2 per operator (discretization) + one per operator and squaring
   size_t n_jobs = 2 * P.ops.size();
-  for (const OpDev& o : P.ops) n_jobs += (size_t)o.N + (o.kry > 0 ? 1 + o.kry : 0);
+  for (const OpDev& o : P.ops) n_jobs += (size_t)o.N + (o.kry > 0 ? 1 + o.kry : 0) + (o.cpl >= 0);
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
   P.sum_x = xoff;
@@ -1397,6 +1408,29 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     }
   }
 
+  // C P_l for the tail pairs: C (q x m, the caller's FP64 matrix) times the
+  // power of the last stage
+  bool any_cp = false;
+  {
+    double* kw = P->at<double>(P->r_kw);
+    int start = (int)J.size(), mx = 0, mn = 0;
+    for (int i = 0; i < P->n_ops; ++i) {
+      const OpDev& o = P->ops[i];
+      if (o.cpl < 0) continue;
+      const int64_t mm = (int64_t)o.mp * o.mp;
+      J.push_back(GemmJob{P->src[i].C, pw + o.pw + o.cpl * mm, kw + o.cpw, o.q, o.mp, o.m, o.m, o.mp,
+                          o.mp, 0, 0, 1.0, 0.0});
+      mx = std::max(mx, o.q);
+      mn = std::max(mn, o.mp);
+    }
+    if ((int)J.size() > start) {
+      P->job_groups.push_back({start, (int)J.size() - start});
+      P->job_dims.push_back({mx, mn});
+      P->job_kind.push_back(0);
+      any_cp = true;
+    }
+  }
+
   // host image of the meta region
   P->meta_host.assign(P->meta_bytes, 0);
   std::memcpy(P->meta_host.data() + P->m_seqs, P->seqs.data(), sizeof(SeqDev) * P->seqs.size());
@@ -1504,7 +1538,7 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                           P->job_dims[g].second, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "squaring GEMM launch"));
   }
-  if (P->max_kry > 0) {
+  if (P->max_kry > 0 || any_cp) {
     e = launch_pack_krylov(ops_d, P->n_ops, P->at<double>(P->r_kw), P->ws + P->r_pc.off, P->compute,
                            P->max_mp, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "Krylov pack launch"));

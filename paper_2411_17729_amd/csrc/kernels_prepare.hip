@@ -323,18 +323,20 @@ __global__ void k_pack_powers(const OpDev* ops, const double* pw, void* pc, int 
 
 __global__ void k_pack_krylov(const OpDev* ops, const double* kw, void* kc, int ct) {
   const OpDev o = ops[blockIdx.y];
-  if (o.kw < 0) return;
-  const int64_t n = (int64_t)o.mp * o.kst;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const double v = kw[o.kw + e];
-    if (ct == DT_BF16)
-      ((uint16_t*)kc)[o.kc + e] = f64_to_bf16_bits(v);
-    else if (ct == DT_F32)
-      ((float*)kc)[o.kc + e] = (float)v;
-    else
-      ((double*)kc)[o.kc + e] = v;
-  }
+  auto cast = [&](int64_t from, int64_t to, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const double v = kw[from + e];
+      if (ct == DT_BF16)
+        ((uint16_t*)kc)[to + e] = f64_to_bf16_bits(v);
+      else if (ct == DT_F32)
+        ((float*)kc)[to + e] = (float)v;
+      else
+        ((double*)kc)[to + e] = v;
+    }
+  };
+  if (o.kw >= 0) cast(o.kw, o.kc, (int64_t)o.mp * o.kst);  // K_j
+  if (o.cpl >= 0) cast(o.cpw, o.cpc, (int64_t)16 * o.mp);  // C P_l of the tail pair
 }
 
 hipError_t launch_pack_krylov(const OpDev* ops, int n_ops, const double* kw, void* kc, int ct,

@@ -23,12 +23,15 @@
 //
 // The tail variant runs the last two stages of every sequence of the launch
 // and forms y_l = C w_l + D u_l (last display of §3; eq. (1.2)) instead of
-// storing w: each wave contracts its share of w with the matching columns of C
-// (FP32 MFMA, C in registers), the eight partial outputs of a block meet in
-// LDS (two buffers, so that a block's partials are added up during the next
-// block, behind the same barrier), and wave v adds them for rows 2v and 2v+1
-// with D u_l. The D u_l of the segment's rows are formed at the start into
-// LDS, so that no load in the walk is waited for out of order.
+// storing w. Since C w_l = C y_l + (C P_{k+1}) y_{l-2^{k+1}}, the second stage
+// needs no m x m contraction: with the q x m product C P_{k+1} formed once
+// (FP64, then rounded to the operand type), each wave contracts its share of
+// y (FP32 MFMA, C's columns in registers) and its share of the y two blocks
+// back (one MFMA against its columns of C P_{k+1}); the eight partial outputs
+// of a block meet in LDS (two buffers, so that a block's partials are added up
+// during the next block, behind the same barrier), and wave v adds them for
+// rows 2v and 2v+1 with D u_l. The D u_l of the segment's rows are formed at
+// the start into LDS, so that no load in the walk is waited for out of order.
 //
 // The state between passes is FP32, or BF16 (XB): then the rows are loaded and
 // stored as BF16, x goes to LDS as loaded, and y and w are still accumulated
@@ -97,10 +100,15 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     return XB ? wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3) : wave * C::DW + 16 * t + rr;
   };
   bf16x8 pa[2][NT][KS];
+  // tail: contraction step cps (columns 32 cps .. + 31) of C P_{k+1}, row r:
+  // step `wave` for the first KS waves, nothing for the others (padded m 128)
+  const int cps = wave < KS ? wave : 0;
+  const bool has_cps = wave < KS;
+  bf16x8 cpa;
   {
     const __bf16* P0 = reinterpret_cast<const __bf16*>(prm.P) + o.pc + (int64_t)k * MP * MP;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < (TAIL ? 1 : 2); ++h)
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -110,6 +118,12 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
           const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 16);
           pa[h][t][s] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
         }
+    if constexpr (TAIL) {
+      const __bf16* row = reinterpret_cast<const __bf16*>(prm.P) + o.cpc + r * MP + 32 * cps + 4 * g;
+      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row);
+      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 16);
+      cpa = has_cps ? __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7) : bf16x8{};
+    }
   }
 
   // State rows through buffer resources over the sequence's L x MP block:
@@ -320,16 +334,22 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 
   int cc = c0, ci = i0 - nw;  // block being computed
   int ysl = 0;                // its y slot (visit index mod 3)
-  // tail: y of a block from its partials (buffer pb), first row l0, segment
-  // block v; wave w takes rows 2w and 2w + 1 (lanes below 32, output lane % 16)
-  auto finish = [&](const float* pb, int l0, bool has, int v) {
-    const int rr = 2 * wave + ((lane >> 4) & 1), qq = lane & 15;
+  // tail: y of a block from its partials (buffer pb) and D u (segment block
+  // v), first row l0; wave w takes rows 2w and 2w + 1 (lanes below 32, output
+  // lane % 16). gather reads them into registers at the start of a visit,
+  // finish stores their sum at its end.
+  const int frr = 2 * wave + ((lane >> 4) & 1), fqq = lane & 15;
+  auto gather = [&](const float* pb, int v, float(&fin)[C::NW + 1]) {
+#pragma unroll
+    for (int w = 0; w < C::NW; ++w) fin[w] = pb[(w * 16 + frr) * 16 + fqq];
+    fin[C::NW] = du[(v * 16 + frr) * q + (fqq < q ? fqq : 0)];
+  };
+  auto finish = [&](const float(&fin)[C::NW + 1], int l0, bool has) {
     float yv = 0.f;
 #pragma unroll
-    for (int w = 0; w < C::NW; ++w) yv += pb[(w * 16 + rr) * 16 + qq];
-    yv += du[(v * 16 + rr) * q + (qq < q ? qq : 0)];
-    const int l = l0 + rr;
-    const uint32_t yoff = has && lane < 32 && qq < q && l < L ? (uint32_t)(l * q + qq) * 4u : 0x80000000u;
+    for (int w = 0; w <= C::NW; ++w) yv += fin[w];
+    const int l = l0 + frr;
+    const uint32_t yoff = has && lane < 32 && fqq < q && l < L ? (uint32_t)(l * q + fqq) * 4u : 0x80000000u;
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, yv), ry, yoff, 0, 0);
   };
   int pl0 = 0, pv = 0;  // tail: the previous block's first row and segment index
@@ -345,9 +365,17 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       // both partners, complete since the last barrier, are read before this
       // block's x and y go to their own slots, so that all the operand reads
       // of the visit are in flight together
-      bf16x8 b[KS], b2[KS];
+      // (tail: only the columns of step cps of the y two blocks back)
+      bf16x8 b[KS], b2[TAIL ? 1 : KS];
       fetch(xs + ((it + 1) & 1) * SLOT, b);
-      fetch(ys + ysl2 * SLOT, b2);
+      if constexpr (TAIL) {
+        b2[0] = *reinterpret_cast<const bf16x8*>(ys + ysl2 * SLOT + rd + 32 * cps);
+      } else {
+        fetch(ys + ysl2 * SLOT, b2);
+      }
+      // tail: the previous block's partials, complete since the last barrier
+      float fin[C::NW + 1];
+      if constexpr (TAIL) gather(red + ((it + 1) & 1) * (C::NW * 256), pv, fin);
       f32x4 xw[NT];  // BF16 state: the block's accumulators
       f32x4(&acc)[NT] = XB ? xw : xr[u];
       if constexpr (XB) {
@@ -361,21 +389,30 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       keep(real && ci >= 1 && it > nw - 3, b);
       contract(pa[0], b, acc);
       put(ys + ysl * SLOT, acc);
-      // w = y + P_{k+1} y_prev2
-      keep(out && ci >= 2, b2);
-      contract(pa[1], b2, acc);
-      if constexpr (!TAIL) store_w(off, acc);
+      if constexpr (!TAIL) {
+        // w = y + P_{k+1} y_prev2
+        keep(out && ci >= 2, b2);
+        contract(pa[1], b2, acc);
+        store_w(off, acc);
+      }
       if constexpr (TAIL) {
-        // this wave's part of C w (outputs 4 g + v of time row r) into buffer
-        // it mod 2; the previous block's partials, complete since the last
-        // barrier, become its y
-        f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};
+        // this wave's part of C w = C y + (C P_{k+1}) y_prev2 (outputs 4 g + v
+        // of time row r; one accumulator chain per tile of y) into buffer it
+        // mod 2; the previous block's partials become its y
+        f32x4 yp[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t) {
+          yp[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int v = 0; v < 4; ++v) ya = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][v], acc[t][v], ya, 0, 0, 0);
+          for (int v = 0; v < 4; ++v) yp[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][v], acc[t][v], yp[t], 0, 0, 0);
+        }
+        f32x4 ya = yp[0];
+#pragma unroll
+        for (int t = 1; t < NT; ++t) ya += yp[t];
+        const bf16x8 yb = has_cps && out && ci >= 2 ? b2[0] : bf16x8{};
+        ya = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cpa, yb, ya, 0, 0, 0);
         *reinterpret_cast<f32x4*>(red + (it & 1) * (C::NW * 256) + (wave * 16 + r) * 16 + 4 * g) = ya;
-        finish(red + ((it + 1) & 1) * (C::NW * 256), pl0, pout, pv);
+        finish(fin, pl0, pout);
         pl0 = (ci << k) + 16 * cc;
         pout = out;
         pv = out ? it - nw : 0;
@@ -392,7 +429,11 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       }
     }
   }
-  if constexpr (TAIL) finish(red + ((npad + 1) & 1) * (C::NW * 256), pl0, pout, pv);  // the last block
+  if constexpr (TAIL) {  // the last block
+    float fin[C::NW + 1];
+    gather(red + ((npad + 1) & 1) * (C::NW * 256), pv, fin);
+    finish(fin, pl0, pout);
+  }
 }
 
 template <int MP, bool TAIL, bool XB>

@@ -52,6 +52,11 @@ struct OpDev {
   int64_t g_db;    // dL/dB of this operator (mp x p)
   int32_t mp, m, p, q, N, set;
   double delta;
+  // tail pair (stages cpl - 1 and cpl, every sequence of the operator ending at
+  // cpl): C P_cpl, 16 x mp (rows from q on zero), FP64 at cpw and in the
+  // compute type at cpc; cpl = -1 if the operator has no tail pair
+  int64_t cpw, cpc;
+  int32_t cpl, reserved;
 };
 
 // A row tile of one sequence for the stage kernel.

@@ -66,9 +66,10 @@ def _paired_vs_unpaired(wl, tail_seqs, **kw):
     # Every state row of a pair sees the operands of two chain launches (the
     # FP32 stage input rounded to BF16, the same entries in the same operand
     # slots of the same MFMA steps, accumulated onto the same FP32 row), so
-    # outputs formed by the chain kernel agree bit for bit. A tail pair sums
-    # y = C w + D u in another FP32 order (per-wave partial sums), which moves y
-    # by rounding only.
+    # outputs formed by the chain kernel agree bit for bit. A tail pair forms
+    # C w = C y + (C P_{k+1}) y_prev2 with the product C P_{k+1} rounded once to
+    # BF16 (the unpaired path rounds P_{k+1} and multiplies by C in FP32), so
+    # its outputs differ by one BF16 rounding of that term.
     from paper_2411_17729_amd import cascade as CC
     yp, ip = _apply(wl, **kw)
     yu, iu = _apply(wl, pair_stages=1, **kw)
@@ -78,7 +79,7 @@ def _paired_vs_unpaired(wl, tail_seqs, **kw):
         e = rel_err(a, b)
         print("seq", i, f"{e:.2e}", flush=True)
         if i in tail_seqs:
-            assert e <= 1e-6, (i, e)
+            assert e <= 2e-3, (i, e)
         else:
             assert np.array_equal(a, b), i
     return yp, ip
