@@ -16,8 +16,9 @@
 // synchronisation: block rows are the MFMA columns, window entries the
 // contraction, and a lane's operand is 16 (8 | p) or twice 8 (p = 4)
 // contiguous bytes of LDS. The kernel is specialised on the number of MFMA
-// steps (2^j p of 128, 256 or 512) and the operand width, so that a block's
-// operand reads all go out before its MFMAs. The state it writes is FP32, or
+// steps (2^j p of 128, 256 or 512) and the operand width; each step's operand
+// register takes the next block's operand right after its MFMAs, so that the
+// LDS reads overlap the MFMAs. The state it writes is FP32, or
 // BF16 (XB, rounded once from the FP32 accumulators).
 #include "stage_common.h"
 #include "ssm_internal.h"
@@ -122,33 +123,43 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   const auto rout = __builtin_amdgcn_make_buffer_rsrc(xo, (short)0, (int)nrec, kBufferWord3);
   const uint32_t lane_off = (uint32_t)(r * MP + ent(0, 4 * g)) * (uint32_t)ES;
   const int nblk = (rg.nrows + 15) / 16;
+  // operand of step s for block b: this lane's row l = row0 + 16 b + r has its
+  // window at (hi - 1 - l) p; rows past the unit read staged rows of the unit's
+  // end (their outputs are not stored)
+  auto operand = [&](int b, int s) -> bf16x8 {
+    const int l = rg.row0 + 16 * b + r;
+    const int w0 = (l < hi ? hi - 1 - l : 0) * p + 8 * g + 32 * s;
+    if constexpr (V16) {
+      return *reinterpret_cast<const bf16x8*>(us + w0);
+    } else {
+      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(us + w0);
+      const bf16x4 up = *reinterpret_cast<const bf16x4*>(us + w0 + 4);
+      return __builtin_shufflevector(lo, up, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
+  };
+  bf16x8 bo[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) bo[s] = operand(0, s);
   for (int b = 0; b < nblk; ++b) {
     const int l = rg.row0 + 16 * b + r;
-    // this row's window starts at (hi - 1 - l) p; rows past the unit read
-    // staged rows of the unit's end (their outputs are not stored)
-    const int w0 = (l < hi ? hi - 1 - l : 0) * p + 8 * g;
-    bf16x8 bo[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      if constexpr (V16) {
-        bo[s] = *reinterpret_cast<const bf16x8*>(us + w0 + 32 * s);
-      } else {
-        const bf16x4 lo = *reinterpret_cast<const bf16x4*>(us + w0 + 32 * s);
-        const bf16x4 up = *reinterpret_cast<const bf16x4*>(us + w0 + 32 * s + 4);
-        bo[s] = __builtin_shufflevector(lo, up, 0, 1, 2, 3, 4, 5, 6, 7);
-      }
-    }
+    // each step's operand register takes the next block's operand right
+    // after its MFMAs, so the LDS reads of a block overlap the MFMAs of the
+    // one before
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[t][s], bo[s], acc[t], 0, 0, 0);
-    // every operand read of the block before its MFMAs (one LDS round trip per block)
-    __builtin_amdgcn_sched_group_barrier(0x100, V16 ? KS : 2 * KS, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, KS * NT, 0);
+      bo[s] = operand(b + 1, s);
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);           // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x100, V16 ? 1 : 2, 0);  // DS read
+    }
     const uint32_t off = l < hi ? lane_off + (uint32_t)(16 * b + rg.row0) * (uint32_t)(MP * ES) : 0x80000000u;
     if constexpr (!XB) {
 #pragma unroll

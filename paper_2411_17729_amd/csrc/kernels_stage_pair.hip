@@ -18,8 +18,13 @@
 // T, for two stages.
 //
 // Each block's rows are loaded DP blocks ahead into registers; one barrier
-// per block orders the LDS exchange (x of a block is read by the next block,
-// y two blocks later, and the slots rotate through two and three buffers).
+// per block orders the LDS exchange. The exchange runs one block ahead: a
+// block is contracted with partners read during the previous visit, and each
+// operand register, once its MFMAs are issued, is refilled with the same
+// piece of the next block's partner (x of this block, y of the previous one,
+// both complete since the last barrier), so the LDS reads overlap the MFMAs;
+// x of the next block goes to its slot during the visit. x and y of block i
+// take slot i mod 2 of two buffers each.
 //
 // The tail variant runs the last two stages of every sequence of the launch
 // and forms y_l = C w_l + D u_l (last display of §3; eq. (1.2)) instead of
@@ -50,7 +55,7 @@ struct PairCfg {
   static constexpr int RS = MP + 16;       // LDS row stride in BF16 entries (32-byte pad)
   static constexpr int SLOT = 16 * RS;     // one block of 16 time rows
   static constexpr int DP = 4;             // blocks loaded ahead
-  static constexpr size_t LDS = 5 * SLOT * sizeof(__bf16);  // x: 2 slots, y: 3 slots
+  static constexpr size_t LDS = 4 * SLOT * sizeof(__bf16);  // x and y: 2 slots each
   // tail variant: two buffers of partial outputs (8 waves x 16 rows x 16
   // outputs), then D u of the segment's rows, D and the segment's inputs
   // after the slots
@@ -314,26 +319,39 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         acc[t][e] = __builtin_bit_cast(float, (e & 1) ? (w2 & 0xffff0000u) : (w2 << 16));
       }
   };
-  auto fetch = [&](const __bf16* slot, bf16x8(&b)[KS]) {
-#pragma unroll
-    for (int s = 0; s < KS; ++s) b[s] = *reinterpret_cast<const bf16x8*>(slot + rd + 32 * s);
-  };
   // operands of a visit without that partner are zeros (a select, so stale
   // LDS contents cannot leak in)
   auto keep = [&](bool on, bf16x8(&b)[KS]) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) b[s] = on ? b[s] : bf16x8{};
   };
-  auto contract = [&](const bf16x8(&a)[NT][KS], const bf16x8(&b)[KS], f32x4(&acc)[NT]) {
+  // one contraction; operand step s is refilled from the next partner's row
+  // (at src) right after its MFMAs
+  auto contract_refill = [&](const bf16x8(&a)[NT][KS], bf16x8(&b)[KS], f32x4(&acc)[NT], const __bf16* src) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][s], b[s], acc[t], 0, 0, 0);
+      b[s] = *reinterpret_cast<const bf16x8*>(src + 32 * s);
+    }
   };
 
   int cc = c0, ci = i0 - nw;  // block being computed
-  int ysl = 0;                // its y slot (visit index mod 3)
+  // x of the first block to its slot; the partners of the first visit are
+  // absent (zeros)
+  if constexpr (XB) {
+    put_raw(xs, 0);
+  } else {
+    put(xs, xr[0]);
+  }
+  __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
+  bf16x8 b[KS], b2[TAIL ? 1 : KS];  // partners of the visit: x of the previous block, y two back
+#pragma unroll
+  for (int s = 0; s < KS; ++s) b[s] = bf16x8{};
+#pragma unroll
+  for (int s = 0; s < (TAIL ? 1 : KS); ++s) b2[s] = bf16x8{};
   // tail: y of a block from its partials (buffer pb) and D u (segment block
   // v), first row l0; wave w takes rows 2w and 2w + 1 (lanes below 32, output
   // lane % 16). gather reads them into registers at the start of a visit,
@@ -361,39 +379,39 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       const bool real = it < nit;  // padding visits move nothing
       const bool out = real && it >= nw;
       const uint32_t off = out ? row_off(cc, ci) : 0x80000000u;
-      const int ysl2 = ysl == 2 ? 0 : ysl + 1;  // slot of the y two blocks back: it - 2 = it + 1 mod 3
-      // both partners, complete since the last barrier, are read before this
-      // block's x and y go to their own slots, so that all the operand reads
-      // of the visit are in flight together
-      // (tail: only the columns of step cps of the y two blocks back)
-      bf16x8 b[KS], b2[TAIL ? 1 : KS];
-      fetch(xs + ((it + 1) & 1) * SLOT, b);
-      if constexpr (TAIL) {
-        b2[0] = *reinterpret_cast<const bf16x8*>(ys + ysl2 * SLOT + rd + 32 * cps);
-      } else {
-        fetch(ys + ysl2 * SLOT, b2);
-      }
+      // the next visit's partners: x of this block and y of the previous one
+      // (tail: only the columns of step cps of that y)
+      const __bf16* nx = xs + (it & 1) * SLOT + rd;
+      const __bf16* ny = ys + ((it + 1) & 1) * SLOT + rd;
       // tail: the previous block's partials, complete since the last barrier
       float fin[C::NW + 1];
       if constexpr (TAIL) gather(red + ((it + 1) & 1) * (C::NW * 256), pv, fin);
+      // x of the next block to its slot
       f32x4 xw[NT];  // BF16 state: the block's accumulators
       f32x4(&acc)[NT] = XB ? xw : xr[u];
       if constexpr (XB) {
-        put_raw(xs + (it & 1) * SLOT, u);
+        put_raw(xs + ((it + 1) & 1) * SLOT, (u + 1) % DP);
         widen(u, xw);
       } else {
-        put(xs + (it & 1) * SLOT, xr[u]);
+        put(xs + ((it + 1) & 1) * SLOT, xr[(u + 1) % DP]);
       }
       // y = x + P_k x_prev (no partner at a column's first block; the first of
       // three warm-up blocks only provides x)
       keep(real && ci >= 1 && it > nw - 3, b);
-      contract(pa[0], b, acc);
-      put(ys + ysl * SLOT, acc);
+      contract_refill(pa[0], b, acc, nx);
+      put(ys + (it & 1) * SLOT, acc);
       if constexpr (!TAIL) {
         // w = y + P_{k+1} y_prev2
         keep(out && ci >= 2, b2);
-        contract(pa[1], b2, acc);
+        contract_refill(pa[1], b2, acc, ny);
         store_w(off, acc);
+        // each step's refill right behind its MFMAs (left to itself the
+        // scheduler sinks the reads below the contractions)
+#pragma unroll
+        for (int i = 0; i < 2 * KS; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);  // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+        }
       }
       if constexpr (TAIL) {
         // this wave's part of C w = C y + (C P_{k+1}) y_prev2 (outputs 4 g + v
@@ -411,6 +429,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         for (int t = 1; t < NT; ++t) ya += yp[t];
         const bf16x8 yb = has_cps && out && ci >= 2 ? b2[0] : bf16x8{};
         ya = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cpa, yb, ya, 0, 0, 0);
+        b2[0] = *reinterpret_cast<const bf16x8*>(ny + 32 * cps);
         *reinterpret_cast<f32x4*>(red + (it & 1) * (C::NW * 256) + (wave * 16 + r) * 16 + 4 * g) = ya;
         finish(fin, pl0, pout);
         pl0 = (ci << k) + 16 * cc;
@@ -422,7 +441,6 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       // a visit's work stays in it: hoisted, the widening of the next slot
       // would wait for that slot's load a visit early
       __builtin_amdgcn_sched_barrier(0);
-      ysl = ysl2;
       if (++ci == ni) {
         ci = 0;
         ++cc;
