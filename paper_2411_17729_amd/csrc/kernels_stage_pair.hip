@@ -260,21 +260,24 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       }
     }
   };
-  // The ring is filled as DP visits would fill it, each load after the
-  // stores of a visit (out of range here, so nothing is written): the memory
-  // counter then stands at the loop's entry as it does on every later pass,
-  // and the compiler's wait for a slot covers that slot's load only.
+  // The ring is filled as DP visits would fill it, with the stores of a visit
+  // (out of range here, so nothing is written) in their place: a lean visit
+  // stores w and then loads, a tail visit loads first (its slot is free once
+  // the accumulators are set) and stores y at its end. The memory counter then
+  // stands at the loop's entry as it does on every later pass, and the
+  // compiler's wait for a slot covers that slot's load only.
 #pragma unroll
   for (int u = 0; u < DP; ++u) {
     if constexpr (TAIL) {
+      issue(u);
       __builtin_amdgcn_raw_buffer_store_b32(0u, ry, 0x80000000u, 0, 0);
     } else {
       f32x4 z[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) z[t] = f32x4{0.f, 0.f, 0.f, 0.f};
       store_w(0x80000000u, z);
+      issue(u);
     }
-    issue(u);
     __builtin_amdgcn_sched_barrier(0);  // keep the ring's loads in visit order
   }
 
@@ -387,14 +390,21 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       float fin[C::NW + 1];
       if constexpr (TAIL) gather(red + ((it + 1) & 1) * (C::NW * 256), pv, fin);
       // x of the next block to its slot
-      f32x4 xw[NT];  // BF16 state: the block's accumulators
-      f32x4(&acc)[NT] = XB ? xw : xr[u];
+      // the block's accumulators: the ring slot itself (lean, FP32 state) or
+      // a copy, after which a tail visit reloads the slot at once
+      f32x4 xw[NT];
+      f32x4(&acc)[NT] = XB || TAIL ? xw : xr[u];
       if constexpr (XB) {
         put_raw(xs + ((it + 1) & 1) * SLOT, (u + 1) % DP);
         widen(u, xw);
       } else {
         put(xs + ((it + 1) & 1) * SLOT, xr[(u + 1) % DP]);
+        if constexpr (TAIL) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) xw[t] = xr[u][t];
+        }
       }
+      if constexpr (TAIL) issue(u);
       // y = x + P_k x_prev (no partner at a column's first block; the first of
       // three warm-up blocks only provides x)
       keep(real && ci >= 1 && it > nw - 3, b);
@@ -436,7 +446,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         pout = out;
         pv = out ? it - nw : 0;
       }
-      issue(u);
+      if constexpr (!TAIL) issue(u);
       __syncthreads();
       // a visit's work stays in it: hoisted, the widening of the next slot
       // would wait for that slot's load a visit early
