@@ -150,7 +150,19 @@ typedef struct {
    * the state traffic for one more rounding of the state per pass; otherwise
    * FP32 (ssm_plan_info.state_dtype says which). The backward keeps FP32. */
   int32_t state_bf16;
-  int32_t reserved[4];   /* must be 0 */
+  /* Output pass with the last s stages folded in (forward apply with
+   * per-stage launches and the chain kernels; BF16 at padded m of 128 and 256;
+   * classes whose sequences all end at the same stage and share the folded
+   * input stages, q <= 16, p <= 64). The last s factors of eq. (2.2) multiply
+   * out to sum_{j < 2^s} z^{-j 2^k0} Abar^(j 2^k0), k0 the first folded stage,
+   * so y_l = sum_j G_j x_{l - j 2^k0} + D u_l with G_j = C Abar^(j 2^k0) (q x m,
+   * FP64 during prepare, then rounded once to BF16), x the state after the
+   * stages before k0: one pass that reads the state once and writes y in place
+   * of the last s stages. 0: automatic (the largest s the LDS holds, 4 at
+   * padded m 256 and 5 at 128, with the stages before it pairing up), -1: off,
+   * 2..5: at most that many. */
+  int32_t fold_stages;
+  int32_t reserved[3];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -187,7 +199,9 @@ typedef struct {
   int32_t compute;           /* ssm_dtype of the stage contractions */
   int32_t max_stage;         /* largest stage index run by any sequence */
   int64_t total_steps;       /* sum of L over sequences */
-  double stage_flops;        /* sum over sequences and run stages of 2 m^2 (L - 2^k) */
+  double stage_flops;        /* sum over sequences and stages run as stage contractions
+                                (not those folded into the input or output pass) of
+                                2 m^2 (L - 2^k) */
   double io_flops;           /* 2 m p L (input) + 2 q (m + p) L (output), summed */
   double stage_bytes;        /* compulsory HBM bytes of the stage launches: per stage and
                                 row, read the row once and write it once (the shifted
@@ -207,7 +221,12 @@ typedef struct {
   double pair_bytes;         /* compulsory HBM bytes of the stage-pair launches */
   double pair_flops;         /* stage flops of the stage-pair launches */
   int32_t state_dtype;       /* ssm_dtype of the state between forward passes */
-  int32_t reserved;
+  int32_t fold_stages;       /* largest number of stages folded into an output pass (0: none) */
+  int64_t fold_launches;     /* output-fold launches per apply (counted once in stage_launches;
+                                their compulsory bytes, one read of every state row and one
+                                write of y, are part of stage_bytes) */
+  double fold_bytes;         /* compulsory HBM bytes of the output folds */
+  double fold_flops;         /* flops of the output folds: 2 q m per row and lag */
 } ssm_plan_info;
 
 typedef struct ssm_plan_s* ssm_plan;
@@ -299,7 +318,7 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);
  * around every kernel launch (this adds host work; leave it off otherwise).
  * ssm_cascade_timing_read returns, for kernel class `kind`
  * (0 = forward stage, 1 = adjoint stage, 2 = outer-product reduction,
- *  3 = recursion, 4 = forward stage pair), the number of timed launches and
+ *  3 = recursion, 4 = forward stage pair, 5 = output fold), the number of timed launches and
  * their summed milliseconds,
  * after synchronizing the events, and clears the record. */
 ssm_status ssm_cascade_timing_enable(ssm_plan plan, int32_t enable);

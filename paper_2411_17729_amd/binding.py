@@ -27,7 +27,7 @@ SSM_LAUNCH_AUTO, SSM_LAUNCH_PER_STAGE, SSM_LAUNCH_PERSISTENT = 0, 1, 2
 SSM_STAGE_AUTO, SSM_STAGE_TILED, SSM_STAGE_RESIDENT, SSM_STAGE_CHAIN = 0, 1, 2, 3
 
 # kernel classes of ssm_cascade_timing_read
-TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION, TIMING_PAIR = 0, 1, 2, 3, 4
+TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION, TIMING_PAIR, TIMING_FOLD = 0, 1, 2, 3, 4, 5
 
 
 class SSMError(RuntimeError):
@@ -56,7 +56,7 @@ class ssm_tuning(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
                 ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
                 ("pair_blocks", C.c_int32), ("input_split", C.c_int32), ("state_bf16", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("fold_stages", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class ssm_plan_info(C.Structure):
@@ -67,13 +67,14 @@ class ssm_plan_info(C.Structure):
         ("stage_kernel", C.c_int32), ("input_stages", C.c_int32), ("tile_rows", C.c_int32 * 4),
         ("persistent_grid", C.c_int32),
         ("persistent_items", C.c_int64), ("pair_launches", C.c_int64), ("pair_bytes", C.c_double),
-        ("pair_flops", C.c_double), ("state_dtype", C.c_int32), ("reserved", C.c_int32),
+        ("pair_flops", C.c_double), ("state_dtype", C.c_int32), ("fold_stages", C.c_int32),
+        ("fold_launches", C.c_int64), ("fold_bytes", C.c_double), ("fold_flops", C.c_double),
     ]
 
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
                 input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                state_bf16=0):
+                state_bf16=0, fold_stages=0):
     t = ssm_tuning()
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
@@ -83,6 +84,7 @@ def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM
     t.pair_blocks = int(pair_blocks)
     t.input_split = int(input_split)
     t.state_bf16 = int(state_bf16)
+    t.fold_stages = int(fold_stages)
     for i, r in enumerate(tile_rows):
         t.tile_rows[i] = int(r)
     return t
@@ -229,7 +231,6 @@ def ssm_cascade_plan_info(plan):
     _check(load().ssm_cascade_plan_info(plan, C.byref(info)), "ssm_cascade_plan_info")
     out = {f: getattr(info, f) for f, _ in ssm_plan_info._fields_}
     out["tile_rows"] = list(info.tile_rows)
-    del out["reserved"]
     return out
 
 

@@ -140,6 +140,15 @@ struct ssm_plan_s {
   size_t m_pair = 0;
   int64_t pair_launches = 0;
   double pair_bytes = 0, pair_flops = 0;
+  // output pass with the last stages folded in: per class the first folded
+  // stage and their number (0: none), workgroup units, LDS bytes
+  int fold_k0[4] = {0, 0, 0, 0}, fold_s[4] = {0, 0, 0, 0};
+  std::vector<FoldUnit> fold_units;
+  int fold_start[4] = {0, 0, 0, 0}, fold_count[4] = {0, 0, 0, 0};
+  size_t fold_lds_bytes[4] = {0, 0, 0, 0};
+  size_t m_fold = 0;
+  int64_t fold_launches = 0;
+  double fold_bytes = 0, fold_flops = 0;
   // persistent launch
   std::vector<PItem> items;
   std::vector<int32_t> cnt_off, ntiles;
@@ -228,6 +237,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     return fail(SSM_E_INVALID, "pair_blocks = %d: supported 0 (automatic) or 4..256", tn.pair_blocks);
   if (tn.input_split < 0 || tn.input_split > 1)
     return fail(SSM_E_INVALID, "input_split = %d: supported 0 (automatic) or 1 (off)", tn.input_split);
+  if (tn.fold_stages < -1 || tn.fold_stages == 1 || tn.fold_stages > 5)
+    return fail(SSM_E_INVALID, "fold_stages = %d: supported 0 (automatic), -1 (off) or 2..5", tn.fold_stages);
   if (tn.state_bf16 < 0 || tn.state_bf16 > 1)
     return fail(SSM_E_INVALID, "state_bf16 = %d: supported 0 (FP32 state) or 1 (BF16 where supported)",
                 tn.state_bf16);
@@ -535,6 +546,38 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     P.class_input_lds[c] = (size_t)(R + maxlag) * maxp * 2;
   }
 
+  // Output pass with the last s stages folded in (forward apply, per-stage
+  // launches of the chain kernels, BF16 at padded m 128 and 256): for classes
+  // whose sequences all end at the same stage and share the folded input
+  // stages, q <= 16 and p <= 64; s as large as the LDS holds the 2^s G_j and
+  // such that the stages between the input pass and the fold pair up.
+  for (int c = 0; c < 4; ++c) {
+    P.fold_s[c] = P.fold_k0[c] = 0;
+    if (P.class_max_last[c] < 0 || tn.fold_stages == -1 || P.launch != SSM_LAUNCH_PER_STAGE ||
+        P.stage_kernel != SSM_STAGE_CHAIN || !fold_supported(kClassMp[c], (int)compute, 2))
+      continue;
+    int min_last = 1 << 30, max_last = -1, kmin = 1 << 30, kmax = -1;
+    bool ok = true;
+    for (const SeqDev& sq : P.seqs)
+      if (P.ops[sq.op].mp == kClassMp[c]) {
+        min_last = std::min(min_last, sq.last);
+        max_last = std::max(max_last, sq.last);
+        kmin = std::min(kmin, sq.kry);
+        kmax = std::max(kmax, sq.kry);
+        ok = ok && sq.q <= 16 && sq.p <= 64 && sq.L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
+      }
+    if (!ok || min_last != max_last || kmin != kmax) continue;
+    const int smax = std::min(fold_max_stages(kClassMp[c]), tn.fold_stages > 0 ? tn.fold_stages : 99);
+    for (int sf = smax; sf >= 2; --sf) {
+      const int k0 = max_last - sf + 1, kp = std::max(4, kmin);
+      if (k0 < 4 || k0 < kmin) continue;
+      if (tn.pair_stages != 1 && pair_supported(kClassMp[c], (int)compute) && (k0 - kp) % 2 != 0) continue;
+      P.fold_s[c] = sf;
+      P.fold_k0[c] = k0;
+      break;
+    }
+  }
+
   // Stage pairs (forward apply, per-stage launches): stages k, k + 1 fused
   // where every sequence of the class runs both as lean stages, i.e. from the
   // largest folded stage count on and below the earliest last stage; the last
@@ -570,8 +613,10 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     if (!fits) continue;
     std::stable_sort(ids.begin(), ids.end(),
                      [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
-    for (int kk = std::max(4, max_kry); kk + 1 <= min_last; kk += 2) {
-      const bool tail = kk + 1 == min_last;
+    // (with a fold, the pairs stop at its first stage and there is no tail pair)
+    const int pair_end = P.fold_s[c] > 0 ? P.fold_k0[c] - 1 : min_last;
+    for (int kk = std::max(4, max_kry); kk + 1 <= pair_end; kk += 2) {
+      const bool tail = P.fold_s[c] == 0 && kk + 1 == min_last;
       if (tail && !(min_last == max_last && small_io)) break;
       const int64_t sh = (int64_t)1 << kk;
       int64_t blocks = 0;
@@ -594,9 +639,45 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     }
   }
 
+  // fold operators, units (four columns of stage k0 per workgroup, longest
+  // sequences first) and LDS
+  P.fold_units.clear();
+  for (OpDev& o : P.ops) {
+    o.fold_s = 0;
+    o.fold_k0 = 0;
+  }
+  for (int c = 0; c < 4; ++c) {
+    P.fold_start[c] = (int)P.fold_units.size();
+    P.fold_count[c] = 0;
+    P.fold_lds_bytes[c] = 0;
+    if (P.fold_s[c] == 0) continue;
+    std::vector<int> ids;
+    int max_p = 1, max_q = 1;
+    for (int i = 0; i < n_seq; ++i)
+      if (P.ops[P.seqs[i].op].mp == kClassMp[c]) {
+        ids.push_back(i);
+        max_p = std::max(max_p, P.seqs[i].p);
+        max_q = std::max(max_q, P.seqs[i].q);
+      }
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
+    const int ncol = (1 << P.fold_k0[c]) / 16;
+    for (int i : ids)
+      for (int c0 = 0; c0 < ncol; c0 += 4)
+        P.fold_units.push_back(FoldUnit{i, c0, std::min(4, ncol - c0), 0});
+    P.fold_count[c] = (int)P.fold_units.size() - P.fold_start[c];
+    P.fold_lds_bytes[c] = fold_lds(kClassMp[c], P.fold_s[c], max_p, max_q);
+    for (OpDev& o : P.ops)
+      if (class_of(o.mp) == c) {
+        o.fold_s = P.fold_s[c];
+        o.fold_k0 = P.fold_k0[c];
+      }
+  }
+
   // BF16 state between the passes of the forward apply: only where every pass
-  // of every class is the split input pass or a stage pair ending in a tail
-  // pair (the only kernels that read and write it)
+  // of every class is the split input pass, a stage pair, or the output fold
+  // after them, and the last pass forms y (the only kernels that read and
+  // write it)
   P.state_bf16 = 0;
   if (tn.state_bf16 == 1) {
     bool ok = true, any = false;
@@ -607,6 +688,10 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       int kk = P.class_min_kry[c];
       bool tail = false;
       while (ok && kk <= P.class_max_last[c]) {
+        if (P.fold_s[c] > 0 && kk == P.fold_k0[c]) {
+          tail = true;
+          break;
+        }
         ok = kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
         if (ok && P.pair_tail[c][kk]) {
           tail = kk + 1 == P.class_max_last[c];
@@ -753,6 +838,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   P.stage_launches = 0;
   P.pair_launches = 0;
   P.pair_bytes = P.pair_flops = 0;
+  P.fold_launches = 0;
+  P.fold_bytes = P.fold_flops = 0;
   for (int c = 0; c < 4; ++c)
     if (P.class_max_last[c] >= 0) {
       P.stage_launches += std::max(0, P.class_max_last[c] + 1 - P.class_min_kry[c]);
@@ -761,17 +848,34 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
           --P.stage_launches;  // two stages, one launch
           ++P.pair_launches;
         }
+      if (P.fold_s[c] > 0) {  // the folded stages, one launch
+        P.stage_launches -= P.fold_s[c] - 1;
+        ++P.fold_launches;
+      }
     }
   P.stage_flops = 0;
   for (int i = 0; i < n_seq; ++i) {
     const SeqDev& s = P.seqs[i];
     const int m = P.ops[s.op].m;
-    for (int kk = s.kry; kk <= s.last; ++kk) {
+    const int c = class_of(P.ops[s.op].mp);
+    // stages run as stage contractions: after the input pass, before a fold
+    const int kend = P.fold_s[c] > 0 ? P.fold_k0[c] - 1 : s.last;
+    for (int kk = s.kry; kk <= kend; ++kk) {
       const int64_t sh = (int64_t)1 << kk;
       if (sh < s.L) P.stage_flops += 2.0 * m * m * (double)(s.L - sh);
     }
-    const int c = class_of(P.ops[s.op].mp);
-    for (int kk = s.kry; kk <= s.last; ++kk) {
+    if (P.fold_s[c] > 0) {
+      // the fold reads every state row once and writes y; row l takes
+      // min(2^s, l / 2^k0 + 1) products with the q x m G_j
+      const double in_row = (double)m * xe, out_row = (double)s.q * ye;
+      P.stage_bytes += s.L * (in_row + out_row);
+      P.fold_bytes += s.L * (in_row + out_row);
+      const int64_t band = (int64_t)1 << P.fold_k0[c];
+      for (int64_t b = 0; b * band < s.L; ++b)
+        P.fold_flops += 2.0 * s.q * m * (double)std::min<int64_t>((int64_t)1 << P.fold_s[c], b + 1) *
+                        (double)std::min<int64_t>(band, s.L - b * band);
+    }
+    for (int kk = s.kry; kk <= kend; ++kk) {
       const int kl = pair_at(c, kk) ? kk + 1 : kk;  // the launch's last stage
       const double in_row = (double)m * xe;
       const double out_row = kl == s.last ? (double)s.q * ye : (double)m * xe;
@@ -814,6 +918,14 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       n_pc += (size_t)16 * o.mp;
       o.cpw = (int64_t)n_kw;
       n_kw += (size_t)16 * o.mp;
+    }
+    o.fold_gw = o.fold_gc = -1;
+    if (o.fold_s > 0) {
+      const size_t ng = ((size_t)16 << o.fold_s) * o.mp;
+      o.fold_gc = (int64_t)n_pc;
+      n_pc += ng;
+      o.fold_gw = (int64_t)n_kw;
+      n_kw += ng;
     }
     if (P.with_backward) {
       o.pct = (int64_t)n_pc;
@@ -868,7 +980,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + 16);
   // jobs: 2 per operator (discretization) + one per operator and squaring
   size_t n_jobs = 2 * P.ops.size();
-  for (const OpDev& o : P.ops) n_jobs += (size_t)o.N + (o.kry > 0 ? 1 + o.kry : 0) + (o.cpl >= 0);
+  for (const OpDev& o : P.ops)
+    n_jobs += (size_t)o.N + (o.kry > 0 ? 1 + o.kry : 0) + (o.cpl >= 0) + (o.fold_s > 0 ? 1 + o.fold_s : 0);
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
   P.sum_x = xoff;
@@ -880,6 +993,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + sizeof(PairUnit) * std::max<size_t>(1, P.pair_units.size()));
   P.m_input = off;
   off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.input_units.size()));
+  P.m_fold = off;
+  off = align_up(off + sizeof(FoldUnit) * std::max<size_t>(1, P.fold_units.size()));
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
     P.m_ritems = off;
     off = align_up(off + sizeof(RItem) * std::max<size_t>(1, P.ritems.size()));
@@ -1431,6 +1546,45 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     }
   }
 
+  // G_j = C Abar^(j 2^k0), j < 2^s, for the output folds: G_0 = C, then by
+  // doubling, [G_{2^t} .. G_{2^{t+1}-1}] = [G_0 .. G_{2^t - 1}] P_{k0+t}
+  bool any_fold = false;
+  {
+    double* kw = P->at<double>(P->r_kw);
+    int start = (int)J.size(), mx = 0, mn = 0;
+    for (int i = 0; i < P->n_ops; ++i) {
+      const OpDev& o = P->ops[i];
+      if (o.fold_s <= 0) continue;
+      J.push_back(GemmJob{P->src[i].C, nullptr, kw + o.fold_gw, o.q, o.m, 0, o.m, 0, o.mp, 0, 0, 1.0, 0.0});
+      mx = std::max(mx, o.q);
+      mn = std::max(mn, o.m);
+    }
+    if ((int)J.size() > start) {
+      P->job_groups.push_back({start, (int)J.size() - start});
+      P->job_dims.push_back({mx, mn});
+      P->job_kind.push_back(1);
+      any_fold = true;
+    }
+    for (int t = 0; t < 5; ++t) {
+      start = (int)J.size();
+      mx = mn = 0;
+      for (const OpDev& o : P->ops) {
+        if (o.fold_s <= t) continue;
+        const int64_t mm = (int64_t)o.mp * o.mp;
+        const int rows = 16 << t;
+        J.push_back(GemmJob{kw + o.fold_gw, pw + o.pw + (o.fold_k0 + t) * mm, kw + o.fold_gw + (int64_t)rows * o.mp,
+                            rows, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 0, 1.0, 0.0});
+        mx = std::max(mx, rows);
+        mn = std::max(mn, o.mp);
+      }
+      if ((int)J.size() > start) {
+        P->job_groups.push_back({start, (int)J.size() - start});
+        P->job_dims.push_back({mx, mn});
+        P->job_kind.push_back(0);
+      }
+    }
+  }
+
   // host image of the meta region
   P->meta_host.assign(P->meta_bytes, 0);
   std::memcpy(P->meta_host.data() + P->m_seqs, P->seqs.data(), sizeof(SeqDev) * P->seqs.size());
@@ -1453,6 +1607,9 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (!P->input_units.empty())
     std::memcpy(P->meta_host.data() + P->m_input, P->input_units.data(),
                 sizeof(ResRange) * P->input_units.size());
+  if (!P->fold_units.empty())
+    std::memcpy(P->meta_host.data() + P->m_fold, P->fold_units.data(),
+                sizeof(FoldUnit) * P->fold_units.size());
   if (P->launch == SSM_LAUNCH_PERSISTENT) {
     unsigned char* mh = P->meta_host.data();
     if (!P->items.empty())
@@ -1542,6 +1699,10 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     e = launch_pack_krylov(ops_d, P->n_ops, P->at<double>(P->r_kw), P->ws + P->r_pc.off, P->compute,
                            P->max_mp, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "Krylov pack launch"));
+  }
+  if (any_fold) {
+    e = launch_pack_fold(ops_d, P->n_ops, P->at<double>(P->r_kw), P->ws + P->r_pc.off, P->compute, stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "fold pack launch"));
   }
   e = launch_pack(ops_d, P->n_ops, src_d, pw, bbar, P->ws + P->r_pc.off, P->compute,
                   P->with_backward, P->ws + P->r_small.off, P->state_f64, P->max_mp, P->max_N,
@@ -1658,6 +1819,15 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       prm.xin = P.ws + (cur ? P.r_x1.off : P.r_x0.off);
       prm.xout = P.ws + (cur ? P.r_x0.off : P.r_x1.off);
       prm.n_tiles = P.class_active[c][kk];
+      if (P.fold_s[c] > 0 && kk == P.fold_k0[c]) {  // the remaining stages and y in one pass
+        TimedLaunch tl(P, stream, 5);
+        const FoldUnit* un = reinterpret_cast<const FoldUnit*>(P.ws + P.r_meta.off + P.m_fold) + P.fold_start[c];
+        e = launch_output_fold(kClassMp[c], P.compute, P.fold_s[c], P.state_bf16 != 0, prm, un, P.fold_count[c],
+                               P.fold_lds_bytes[c], stream);
+        if (e != hipSuccess) return hip_fail(e, "output fold launch");
+        tl.done();
+        break;
+      }
       const bool pair = kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
       TimedLaunch tl(P, stream, pair ? 4 : 0);
       if (pair) {
@@ -1955,6 +2125,11 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->pair_bytes = plan->pair_bytes;
   info->pair_flops = plan->pair_flops;
   info->state_dtype = plan->state_bf16 ? SSM_BF16 : plan->state_f64 ? SSM_F64 : SSM_F32;
+  info->fold_launches = plan->fold_launches;
+  info->fold_bytes = plan->fold_bytes;
+  info->fold_flops = plan->fold_flops;
+  info->fold_stages = 0;
+  for (int c = 0; c < 4; ++c) info->fold_stages = std::max(info->fold_stages, plan->fold_s[c]);
   return SSM_OK;
 }
 

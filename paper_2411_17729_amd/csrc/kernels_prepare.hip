@@ -348,6 +348,32 @@ hipError_t launch_pack_krylov(const OpDev* ops, int n_ops, const double* kw, voi
   return hipGetLastError();
 }
 
+// G_j (16 x mp FP64 blocks, j < 2^fold_s) into operand order: chunk (j, t,
+// lane) holds G_j[lane % 16][32 t + 8 (lane / 16) .. + 7], eight values of the
+// compute type (BF16 only).
+__global__ void k_pack_fold(const OpDev* ops, const double* gw, uint16_t* gc) {
+  const OpDev o = ops[blockIdx.y];
+  if (o.fold_s <= 0) return;
+  const int mp = o.mp, ks = mp / 32;
+  const int64_t n = ((int64_t)1 << o.fold_s) * 16 * mp;  // elements
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int v = (int)(e & 7);
+    const int64_t chunk = e >> 3;
+    const int lane = (int)(chunk & 63);
+    const int64_t jt = chunk >> 6;
+    const int t = (int)(jt % ks), j = (int)(jt / ks);
+    const int row = j * 16 + (lane & 15), col = 32 * t + 8 * (lane >> 4) + v;
+    gc[o.fold_gc + e] = f64_to_bf16_bits(gw[o.fold_gw + (int64_t)row * mp + col]);
+  }
+}
+
+hipError_t launch_pack_fold(const OpDev* ops, int n_ops, const double* gw, void* gc, int ct, hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  if (ct != DT_BF16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_fold, dim3(128, n_ops), dim3(256), 0, s, ops, gw, (uint16_t*)gc);
+  return hipGetLastError();
+}
+
 template <typename X>
 __global__ void k_pack_small(const OpDev* ops, const OpSrc* src, const double* bbar, X* sm) {
   const OpDev o = ops[blockIdx.y];

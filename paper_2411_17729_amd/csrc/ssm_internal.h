@@ -56,7 +56,14 @@ struct OpDev {
   // cpl): C P_cpl, 16 x mp (rows from q on zero), FP64 at cpw and in the
   // compute type at cpc; cpl = -1 if the operator has no tail pair
   int64_t cpw, cpc;
-  int32_t cpl, reserved;
+  int32_t cpl;
+  // output pass with stages fold_k0 .. fold_k0 + fold_s - 1 folded in (every
+  // sequence of the operator ending there): G_j = C Abar^(j 2^fold_k0), j <
+  // 2^fold_s, as 16 x mp blocks (rows from q on zero), FP64 at fold_gw and
+  // packed in operand order in the compute type at fold_gc; fold_s = 0 if none
+  int32_t fold_s;
+  int64_t fold_gw, fold_gc;
+  int32_t fold_k0, reserved2;
 };
 
 // A row tile of one sequence for the stage kernel.
@@ -110,6 +117,12 @@ struct ChainUnit {
 // of sequence seq in the column-by-column numbering of stage k.
 struct PairUnit {
   int32_t seq, f0, T, reserved;
+};
+
+// Work of one output-fold workgroup: columns col0 .. col0 + ncol - 1 (ncol <=
+// 4, one per wave) of sequence seq in the numbering of its fold stage.
+struct FoldUnit {
+  int32_t seq, col0, ncol, reserved;
 };
 
 // ---- persistent ragged launch ----
@@ -303,6 +316,19 @@ bool pair_supported(int mp, int ct);
 size_t pair_lds(int mp, bool tail, int seg_blocks, int p, int q);
 hipError_t launch_stage_pair(int mp, int ct, const StageParams& prm, const PairUnit* units,
                              int n_units, bool tail, bool xb, size_t lds, hipStream_t s);
+
+// Output pass with the stages from o.fold_k0 on folded in (BF16 at padded m
+// of 128 and 256, q <= 16, p <= 64; s = 2 .. fold_max_stages(mp)): y = sum_j
+// G_j x_{l - j 2^k0} + D u from the state prm.xin. xb: that state is BF16.
+// lds: fold_lds(mp, s, largest p, largest q).
+int fold_max_stages(int mp);
+bool fold_supported(int mp, int ct, int s);
+size_t fold_lds(int mp, int s, int p, int q);
+hipError_t launch_output_fold(int mp, int ct, int s, bool xb, const StageParams& prm, const FoldUnit* units,
+                              int n_units, size_t lds, hipStream_t st);
+// Packs the FP64 G_j of every operator with a fold (16 x mp blocks) into the
+// compute type in operand order.
+hipError_t launch_pack_fold(const OpDev* ops, int n_ops, const double* gw, void* gc, int ct, hipStream_t s);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);

@@ -49,7 +49,9 @@ def _oracle(wl):
 
 
 def _apply(wl, compute, **kw):
+    # (the chain kernels run every stage: no output fold)
     from paper_2411_17729_amd import cascade as CC
+    kw.setdefault("fold_stages", -1)
     plan = CC.plan_for_workload(wl, compute=compute, launch="per_stage", **kw)
     info = plan.info()
     u = CC.pack_u(wl, dtype=torch.float32)
@@ -140,7 +142,8 @@ def test_resident_persistent_matches_per_stage(compute):
     pers = CC.plan_for_workload(wl, compute=compute, launch="persistent")
     info = pers.info()
     assert info["launch"] == 2 and info["stage_kernel"] == 3 and info["input_stages"] >= 4
-    per = CC.plan_for_workload(wl, compute=compute, launch="per_stage", pair_stages=1, input_split=1)
+    per = CC.plan_for_workload(wl, compute=compute, launch="per_stage", pair_stages=1, input_split=1,
+                               fold_stages=-1)
     ya = pers.apply(u).clone()
     yb = per.apply(u).clone()
     torch.cuda.synchronize()

@@ -38,7 +38,9 @@ def _workload(seed, zero_d=False, spec=SPEC):
 
 
 def _apply(wl, **kw):
+    # (the pairs run to the last stage: no output fold)
     from paper_2411_17729_amd import cascade as CC
+    kw.setdefault("fold_stages", -1)
     plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", **kw)
     info = plan.info()
     y = plan.apply(CC.pack_u(wl, dtype=torch.float32)).clone()
@@ -101,7 +103,7 @@ def test_pair_segment_lengths_bitwise():
 def test_pair_graph_replays():
     from paper_2411_17729_amd import cascade as CC
     wl = _workload(44)
-    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage")
+    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", fold_stages=-1)
     assert plan.info()["pair_launches"] == 4
     stream = torch.cuda.Stream()
     u = CC.pack_u(wl, dtype=torch.float32)
@@ -156,7 +158,7 @@ SPLIT_SPECS = {
 def test_split_input_matches_oracle(j, u_dtype, zero_d):
     from paper_2411_17729_amd import cascade as CC
     wl = _workload(46, zero_d=zero_d, spec=SPLIT_SPECS[j])
-    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage")
+    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", fold_stages=-1)
     info = plan.info()
     # j: the largest with 2^j p <= 2 padded m (the resident pass: 2^j p <= m)
     assert info["input_stages"] == j, info["input_stages"]
@@ -221,7 +223,7 @@ def test_tail_pair_edges(case):
             "bf16_u": [(256, 8, 8, 3000, 11), (256, 8, 3, 2500, 11)],
             "q17": [(256, 8, 17, 3000, 11), (256, 8, 4, 2500, 11)]}[case]
     wl = _workload(49, spec=spec)
-    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage")
+    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", fold_stages=-1)
     info = plan.info()
     dt = torch.bfloat16 if case == "bf16_u" else torch.float32
     u = CC.pack_u(wl, dtype=dt)

@@ -41,7 +41,7 @@ def test_bf16_state_matches_oracle(u_dtype, zero_d):
     u = CC.pack_u(wl, dtype=dt)
     outs = {}
     for sb in (1, 0):
-        plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", state_bf16=sb)
+        plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", state_bf16=sb, fold_stages=-1)
         info = plan.info()
         assert info["state_dtype"] == (B.SSM_BF16 if sb else B.SSM_F32)
         assert info["input_stages"] == 6 and info["pair_launches"] == 5
@@ -88,7 +88,7 @@ def test_bf16_state_segment_lengths_bitwise():
 def test_bf16_state_graph_replays():
     from paper_2411_17729_amd import cascade as CC
     wl = _workload(64, spec=SPEC)
-    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", state_bf16=1)
+    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", state_bf16=1, fold_stages=-1)
     assert plan.info()["state_dtype"] == B.SSM_BF16
     stream = torch.cuda.Stream()
     u = CC.pack_u(wl, dtype=torch.float32)
