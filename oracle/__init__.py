@@ -11,6 +11,8 @@ library (no kernels, headers, helpers or constant tables) and it never imports
 from .ssm_oracle import (  # noqa: F401
     trapezoid,
     trapezoid_adjoint,
+    zoh,
+    zoh_adjoint,
     recursion,
     powers,
     impulse_response,

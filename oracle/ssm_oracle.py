@@ -7,6 +7,8 @@ Everything here is numpy float64 on the CPU, one sequence at a time, written
 for a reader holding the paper (Beylkin, arXiv 2411.17729) next to it:
 
 * ``trapezoid``        -- the trapezoidal discretization of §1 (after eq. (1.2)).
+* ``zoh``              -- the exponential discretization named in §5:
+  Abar = exp(delta A) and the matching Bbar (reading below).
 * ``recursion``        -- the discrete LTI recursion, eq. (1.2), x_{-1} = 0.
 * ``powers``           -- Abar, Abar^2, Abar^4, ... by repeated squaring (end of §2).
 * ``impulse_response`` / ``truncated_sum`` -- the convolution sum eq. (3.1)
@@ -16,9 +18,9 @@ for a reader holding the paper (Beylkin, arXiv 2411.17729) next to it:
   and the general step, followed by the output y = C v + D u.
 * ``transfer`` / ``transfer_truncated`` -- H(z) of eq. (1.3) and H_N(z) of
   eq. (2.2) evaluated at a point z of the unit circle.
-* ``grads_*`` / ``trapezoid_adjoint`` -- reverse-mode derivatives of the maps
-  above (not in the paper; derived by the chain rule, pinned by finite
-  differences in the tests).
+* ``grads_*`` / ``trapezoid_adjoint`` / ``zoh_adjoint`` -- reverse-mode
+  derivatives of the maps above (not in the paper; derived by the chain rule,
+  pinned by finite differences in the tests).
 
 Readings of points where the paper is loose (each also listed in the design
 notes of the repository):
@@ -31,6 +33,11 @@ notes of the repository):
   eq. (1.2) and the final step of §3 both add D u_l once, which is used here.
 * Boundary. Columns l < 2^n are copied unchanged at stage n (x_{-1} = 0,
   §3); a stage whose shift reaches past the sequence changes nothing.
+* Exponential discretization. §5 prints Bbar = (delta A)^{-1} [exp(delta A) - I]
+  delta A, which is m x m and cannot multiply u; the factor on the right is
+  read as delta B, the zero-order hold: Bbar = int_0^delta exp(s A) ds B,
+  which equals (delta A)^{-1} [exp(delta A) - I] delta B when A is invertible
+  and stays defined when it is not.
 """
 
 from __future__ import annotations
@@ -40,6 +47,8 @@ import numpy as np
 __all__ = [
     "trapezoid",
     "trapezoid_adjoint",
+    "zoh",
+    "zoh_adjoint",
     "recursion",
     "powers",
     "impulse_response",
@@ -112,6 +121,57 @@ def trapezoid_adjoint(A, B, delta, gAbar, gBbar):
     gA += 0.5 * delta * np.linalg.solve(M.T, gBbar @ Bbar.T)
     gB = delta * np.linalg.solve(M.T, gBbar)
     return gA, gB
+
+
+# --------------------------------------------------------------------------
+# Exponential discretization (§5, the choice Abar = exp(delta A) discussed
+# for structured representations of the HiPPO matrix)
+# --------------------------------------------------------------------------
+def _zoh_augmented(A, B, delta):
+    A = _f64(A)
+    B = _f64(B)
+    if B.ndim == 1:
+        B = B[:, None]
+    m, p = A.shape[0], B.shape[1]
+    E = np.zeros((m + p, m + p))
+    E[:m, :m] = delta * A
+    E[:m, m:] = delta * B
+    return E, m
+
+
+def zoh(A, B, delta):
+    """Abar = exp(delta A),  Bbar = int_0^delta exp(s A) ds B.
+
+    Both are blocks of one matrix exponential: for E = [[delta A, delta B],
+    [0, 0]], exp(E) = [[exp(delta A), Bbar], [0, I]] (the series of exp(E)
+    has upper-right block sum_k (delta A)^k delta B / (k+1)!, the series of
+    the integral). The exponential is the library step (scipy.linalg.expm).
+    """
+    from scipy.linalg import expm
+
+    E, m = _zoh_augmented(A, B, delta)
+    F = expm(E)
+    return F[:m, :m], F[:m, m:]
+
+
+def zoh_adjoint(A, B, delta, gAbar, gBbar):
+    """Gradients of a scalar loss w.r.t. A and B given its gradients w.r.t. Abar, Bbar.
+
+    With F = exp(E) and E the augmented matrix of ``zoh``, dF = L(E, dE), the
+    Frechet derivative of the exponential, L(E, X) = int_0^1 exp(sE) X
+    exp((1-s)E) ds. Its adjoint under the trace inner product is L(E^T, .),
+    so gE = L(E^T, G) with G = [[gAbar, gBbar], [0, 0]]; E holds delta A and
+    delta B, hence gA = delta gE[:m, :m] and gB = delta gE[:m, m:]. L is the
+    library step (scipy.linalg.expm_frechet).
+    """
+    from scipy.linalg import expm_frechet
+
+    E, m = _zoh_augmented(A, B, delta)
+    G = np.zeros_like(E)
+    G[:m, :m] = _f64(gAbar)
+    G[:m, m:] = _f64(gBbar).reshape(m, -1)
+    _, gE = expm_frechet(E.T, G)
+    return delta * gE[:m, :m], delta * gE[:m, m:]
 
 
 # --------------------------------------------------------------------------
@@ -361,17 +421,18 @@ def grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N):
     return {"u": gu, "Abar": gA, "Bbar": gB, "C": gC, "D": gD}
 
 
-def grads_full(A, B, C, D, delta, u, dy, N=None):
+def grads_full(A, B, C, D, delta, u, dy, N=None, disc="trapezoid"):
     """Gradients of sum(dy * y) w.r.t. (u, A, B, C, D) through the trapezoidal
-    discretization. Uses BPTT when N is None or 2^(N+1) >= L, else brute force.
+    (disc = "trapezoid") or exponential ("zoh") discretization. Uses BPTT when
+    N is None or 2^(N+1) >= L, else brute force.
     """
-    Abar, Bbar = trapezoid(A, B, delta)
+    Abar, Bbar = (trapezoid if disc == "trapezoid" else zoh)(A, B, delta)
     u = _as_matrix_u(u)
     L = u.shape[0]
     if N is None or (1 << (N + 1)) >= L:
         g = grads_recursion(Abar, Bbar, C, D, u, dy)
     else:
         g = grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N)
-    gA, gB = trapezoid_adjoint(A, B, delta, g["Abar"], g["Bbar"])
+    gA, gB = (trapezoid_adjoint if disc == "trapezoid" else zoh_adjoint)(A, B, delta, g["Abar"], g["Bbar"])
     return {"u": g["u"], "A": gA, "B": gB, "C": g["C"], "D": g["D"],
             "Abar": g["Abar"], "Bbar": g["Bbar"]}
