@@ -27,7 +27,8 @@
  *    plan lives.
  *  - Work is enqueued on the given stream (0 = the legacy default stream).
  *    Apart from ssm_cascade_prepare (which synchronizes the stream once to
- *    report numerical failure of the discretization), no entry point blocks
+ *    report numerical failure of the discretization, twice for
+ *    SSM_DISC_ZOH), no entry point blocks
  *    the host, so apply, backward and recursion may be captured into a HIP
  *    graph. A plan must be used on one stream at a time.
  *  - Every argument is checked on the host before anything is enqueued;
@@ -59,7 +60,8 @@ typedef enum {
   SSM_E_WORKSPACE = 3,    /* workspace smaller than ssm_cascade_workspace_bytes() */
   SSM_E_HIP = 4,          /* a HIP runtime call or kernel launch failed */
   SSM_E_NOT_PREPARED = 5, /* plan is null or was prepared without what the call needs */
-  SSM_E_NUMERIC = 6       /* I - delta/2 A is singular to working precision */
+  SSM_E_NUMERIC = 6       /* I - delta/2 A is singular to working precision, or the
+                             exponential's scaling is out of range (SSM_DISC_ZOH) */
 } ssm_status;
 
 typedef enum {
@@ -73,7 +75,17 @@ typedef enum {
    *   Abar = (I - delta/2 A)^{-1} (I + delta/2 A),  Bbar = delta (I - delta/2 A)^{-1} B. */
   SSM_DISC_TRAPEZOID = 0,
   /* A and B are already the discrete Abar and Bbar of eq. (1.2); delta is ignored. */
-  SSM_DISC_GIVEN = 1
+  SSM_DISC_GIVEN = 1,
+  /* Exponential discretization (the choice Abar = exp(delta A) of §5), with
+   * Bbar the zero-order hold int_0^delta exp(s A) ds B (the paper's printed
+   * "(delta A)^{-1} [exp(delta A) - I] delta A" is read with delta B as its
+   * last factor, which it equals for invertible A). Both come from one FP64
+   * exponential of [[delta A, delta B], [0, 0]] on the GPU: scaled by 2^-s so
+   * that its 1-norm is at most 1/2, an 18-term Taylor polynomial, then s
+   * squarings. Prepare reads the norms back (a second synchronization of the
+   * stream) to fix s per operator; a non-finite norm or s > 60 returns
+   * SSM_E_NUMERIC. */
+  SSM_DISC_ZOH = 2
 } ssm_disc;
 
 typedef enum {
@@ -170,7 +182,7 @@ typedef struct {
   int32_t m, p, q;     /* state, input and output sizes; must equal its parameter set's */
   int32_t N;           /* highest cascade stage: stages k = 0..N, degree 2^{N+1}-1 (eq. (2.2)) */
   int64_t L;           /* number of time steps */
-  double delta;        /* trapezoidal step size (> 0); ignored for SSM_DISC_GIVEN */
+  double delta;        /* step size (> 0) of the discretization; ignored for SSM_DISC_GIVEN */
   int32_t param_set;   /* index into the ssm_params array */
   int32_t reserved;    /* must be 0 */
   int64_t u_offset;    /* element offset of this sequence's (L x p) input block */
@@ -253,8 +265,10 @@ size_t ssm_cascade_workspace_bytes(const ssm_seq_desc* seqs, int32_t n_seq,
  * SSM_DISC_GIVEN). ws: device workspace of ws_bytes >=
  * ssm_cascade_workspace_bytes(seqs, n_seq, disc, compute, with_backward,
  * ckpt_every, tuning) with the same tuning. On success *out receives a new plan (free it with
- * ssm_cascade_destroy). Synchronizes `stream` once at the end; returns
- * SSM_E_NUMERIC if some I - delta/2 A was singular to working precision. */
+ * ssm_cascade_destroy). Synchronizes `stream` once at the end (SSM_DISC_ZOH:
+ * also once after the norms of delta [A B] are formed); returns
+ * SSM_E_NUMERIC if some I - delta/2 A was singular to working precision, or
+ * (SSM_DISC_ZOH) some delta [A B] has a non-finite or too large norm. */
 ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq,
                                const ssm_params* sets, int32_t n_sets,
                                ssm_disc disc, ssm_dtype compute,

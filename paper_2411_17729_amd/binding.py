@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libssm_cascade.so")
 
 SSM_OK, SSM_E_INVALID, SSM_E_UNSUPPORTED, SSM_E_WORKSPACE, SSM_E_HIP, SSM_E_NOT_PREPARED, SSM_E_NUMERIC = range(7)
 SSM_F64, SSM_F32, SSM_BF16 = 0, 1, 2
-SSM_DISC_TRAPEZOID, SSM_DISC_GIVEN = 0, 1
+SSM_DISC_TRAPEZOID, SSM_DISC_GIVEN, SSM_DISC_ZOH = 0, 1, 2
 SSM_LAUNCH_AUTO, SSM_LAUNCH_PER_STAGE, SSM_LAUNCH_PERSISTENT = 0, 1, 2
 SSM_STAGE_AUTO, SSM_STAGE_TILED, SSM_STAGE_RESIDENT, SSM_STAGE_CHAIN = 0, 1, 2, 3
 

@@ -69,7 +69,10 @@ class CascadePlan:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         self.compute = dtype_code(compute)
-        self.disc = B.SSM_DISC_GIVEN if disc == "given" else B.SSM_DISC_TRAPEZOID
+        discs = {"trapezoid": B.SSM_DISC_TRAPEZOID, "given": B.SSM_DISC_GIVEN, "zoh": B.SSM_DISC_ZOH}
+        if disc not in discs:
+            raise ValueError(f"discretization {disc!r}: one of {sorted(discs)}")
+        self.disc = discs[disc]
         self.state_dtype = torch.float64 if self.compute == B.SSM_F64 else torch.float32
         # parameters as contiguous FP64 device tensors (kept alive for prepare)
         self.params = []
@@ -191,7 +194,7 @@ class CascadePlan:
         # operators are numbered by first appearance of (param_set, delta)
         seen = []
         for d in self.layout.descs:
-            key = (d.param_set, d.delta if self.disc == B.SSM_DISC_TRAPEZOID else 0.0)
+            key = (d.param_set, d.delta if self.disc != B.SSM_DISC_GIVEN else 0.0)
             if key not in seen:
                 seen.append(key)
                 if len(seen) - 1 == op:
@@ -221,12 +224,15 @@ class CascadePlan:
 def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, device="cuda",
                       launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto", input_stages=0,
                       chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0, state_bf16=0,
-                      fold_stages=0):
-    """Builds the layout and plan of a ``workloads.Workload``."""
+                      fold_stages=0, disc=None):
+    """Builds the layout and plan of a ``workloads.Workload`` (discretization:
+    the workload's, "given" or "trapezoid", unless ``disc`` names one)."""
     dims = [(ps.m, ps.p, ps.q) for ps in wl.sets]
     layout = make_layout(wl.seqs, dims)
     params = [(ps.A, ps.B, ps.C, ps.D) for ps in wl.sets]
-    return CascadePlan(layout, params, disc="given" if wl.given else "trapezoid", compute=compute,
+    if disc is None:
+        disc = "given" if wl.given else "trapezoid"
+    return CascadePlan(layout, params, disc=disc, compute=compute,
                        with_backward=with_backward, ckpt_every=ckpt_every, device=device,
                        launch=launch, tile_rows=tile_rows, stage_kernel=stage_kernel,
                        input_stages=input_stages, chain_blocks=chain_blocks,

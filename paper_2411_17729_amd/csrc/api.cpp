@@ -48,6 +48,10 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 inline int pad_m(int m) { return m <= 32 ? 32 : m <= 64 ? 64 : m <= 128 ? 128 : 256; }
 inline int class_of(int mp) { return mp == 32 ? 0 : mp == 64 ? 1 : mp == 128 ? 2 : 3; }
 constexpr int kClassMp[4] = {32, 64, 128, 256};
+// exponential discretization: Taylor terms after scaling to 1-norm <= 1/2
+// (remainder below 0.5^19 e^0.5 / 19! < 2e-23), and the most squarings
+constexpr int kZohTaylor = 18;
+constexpr int kZohMaxSq = 60;
 
 inline size_t dt_size(int dt) { return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2; }
 
@@ -95,6 +99,13 @@ struct ssm_plan_s {
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   Region r_meta, r_pw, r_pc, r_bbar, r_minv, r_small, r_aug, r_nmat, r_bsc, r_x0, r_x1;
+  // exponential discretization: per-operator scratch, the identity (z_nid x
+  // z_nid) and the norms (element offsets in r_zoh); its jobs, made once the
+  // norms are read back, in a meta area of z_cap jobs at m_zjobs
+  Region r_zoh;
+  int64_t z_id = 0, z_norm = 0;
+  int z_nid = 0;
+  size_t m_zjobs = 0, z_cap = 0;
   size_t m_seqs = 0, m_ops = 0, m_src = 0, m_tiles = 0, m_status = 0, m_jobs = 0;
   std::vector<GemmJob> jobs;            // prepare jobs, in launch order
   std::vector<std::pair<int, int>> job_groups;  // (start, count) per launch
@@ -255,8 +266,10 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       return fail(SSM_E_INVALID, "tile_rows[%d] = %d: supported %d or %d", c, r, d, d / 2);
     P.class_bm[c] = r ? r : d;
   }
-  if (disc != SSM_DISC_TRAPEZOID && disc != SSM_DISC_GIVEN)
+  if (disc != SSM_DISC_TRAPEZOID && disc != SSM_DISC_GIVEN && disc != SSM_DISC_ZOH)
     return fail(SSM_E_INVALID, "unknown discretization %d", (int)disc);
+  if (disc == SSM_DISC_ZOH && with_backward)
+    return fail(SSM_E_UNSUPPORTED, "the backward through the exponential discretization is not built");
   if (compute != SSM_F64 && compute != SSM_F32 && compute != SSM_BF16)
     return fail(SSM_E_INVALID, "unknown compute dtype %d", (int)compute);
   if (ckpt_every < 0) return fail(SSM_E_INVALID, "ckpt_every must be >= 0");
@@ -274,10 +287,11 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   int n_sets = 0;
   for (int i = 0; i < n_seq; ++i) {
     const ssm_seq_desc& d = seqs[i];
-    if (disc == SSM_DISC_TRAPEZOID && !(d.delta > 0.0 && std::isfinite(d.delta)))
+    const bool uses_delta = disc == SSM_DISC_TRAPEZOID || disc == SSM_DISC_ZOH;
+    if (uses_delta && !(d.delta > 0.0 && std::isfinite(d.delta)))
       return fail(SSM_E_INVALID, "seq %d: delta must be positive and finite", i);
     uint64_t dbits = 0;
-    if (disc == SSM_DISC_TRAPEZOID) std::memcpy(&dbits, &d.delta, 8);
+    if (uses_delta) std::memcpy(&dbits, &d.delta, 8);
     auto key = std::make_pair(d.param_set, dbits);
     int op;
     auto it = key2op.find(key);
@@ -291,7 +305,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       o.p = d.p;
       o.q = d.q;
       o.set = d.param_set;
-      o.delta = disc == SSM_DISC_TRAPEZOID ? d.delta : 0.0;
+      o.delta = uses_delta ? d.delta : 0.0;
       o.N = lst;
       P.ops.push_back(o);
     } else {
@@ -900,7 +914,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // ---- workspace layout ----
   const size_t ce = dt_size(P.compute);
   size_t n_pw = 0, n_pc = 0, n_bbar = 0, n_minv = 0, n_small = 0, n_aug = 0, n_nmat = 0,
-         n_bsc = 0, n_kw = 0;
+         n_bsc = 0, n_kw = 0, n_zoh = 0;
   for (OpDev& o : P.ops) {
     const size_t mm = (size_t)o.mp * o.mp;
     o.pw = (int64_t)n_pw;
@@ -960,6 +974,20 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     } else {
       o.sc_aug = o.sc_n = o.sc_b = -1;
     }
+    o.zx = -1;
+    o.zn = o.zsq = 0;
+    if (disc == SSM_DISC_ZOH) {
+      o.zn = o.m + o.p;
+      o.zx = (int64_t)n_zoh;
+      n_zoh += 3 * (size_t)o.zn * o.zn;
+      P.z_nid = std::max(P.z_nid, o.zn);
+    }
+  }
+  if (disc == SSM_DISC_ZOH) {
+    P.z_id = (int64_t)n_zoh;
+    n_zoh += (size_t)P.z_nid * P.z_nid;
+    P.z_norm = (int64_t)n_zoh;
+    n_zoh += P.ops.size();
   }
   // prepare GEMM jobs (pointers are patched once the workspace is known)
   P.jobs.clear();
@@ -984,6 +1012,11 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     n_jobs += (size_t)o.N + (o.kry > 0 ? 1 + o.kry : 0) + (o.cpl >= 0) + (o.fold_s > 0 ? 1 + o.fold_s : 0);
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
+  // exponential discretization: per operator the scaling, the first Taylor
+  // term, two jobs per Taylor step, up to kZohMaxSq squarings and two copies
+  P.z_cap = disc == SSM_DISC_ZOH ? P.ops.size() * (size_t)(4 + 2 * kZohTaylor + kZohMaxSq) : 0;
+  P.m_zjobs = off;
+  off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, P.z_cap));
   P.sum_x = xoff;
   P.m_ranges = off;
   off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.ranges.size()));
@@ -1046,6 +1079,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   take(P.r_aug, n_aug * 8);
   take(P.r_nmat, n_nmat * 8);
   take(P.r_bsc, n_bsc * 8);
+  take(P.r_zoh, n_zoh * 8);
   take(P.r_x0, (size_t)xoff * P.x_elem());
   take(P.r_x1, (size_t)xoff * P.x_elem());
   if (P.with_backward) {
@@ -1336,6 +1370,119 @@ StageParams base_params(const ssm_plan_s& P, int c) {
   prm.P = P.ws + P.r_pc.off;
   prm.small = P.ws + P.r_small.off;
   return prm;
+}
+
+// Exponential discretization (§5) of every operator: exp(E), E = delta [[A,
+// B], [0, 0]], whose blocks are Abar = exp(delta A) and Bbar = int_0^delta
+// exp(sA) ds B. The norms of E come back to the host, which fixes per operator
+// the squarings s with |E|_1 / 2^s <= 1/2; then X = E / 2^s, the Taylor
+// polynomial by Horner steps S <- I + X S / k (k = kZohTaylor .. 1), s
+// squarings, and the copies of the blocks into P_0 and Bbar, each step one
+// launch over all operators (FP64 GEMM and axpy jobs).
+ssm_status zoh_discretize(ssm_plan_s& P, const OpDev* ops_d, const OpSrc* src_d, hipStream_t stream) {
+  double* zs = P.at<double>(P.r_zoh);
+  double* pw = P.at<double>(P.r_pw);
+  double* bbar = P.at<double>(P.r_bbar);
+  int max_n = 0;
+  for (const OpDev& o : P.ops) max_n = std::max(max_n, o.zn);
+  hipError_t e = launch_zoh_setup(ops_d, P.n_ops, src_d, zs, zs + P.z_id, P.z_nid, zs + P.z_norm, pw, bbar,
+                                  max_n, stream);
+  if (e != hipSuccess) return hip_fail(e, "exponential setup launch");
+  std::vector<double> norms(P.ops.size());
+  e = hipMemcpyAsync(norms.data(), zs + P.z_norm, sizeof(double) * norms.size(), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_fail(e, "norm read");
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "norm synchronization");
+  for (size_t i = 0; i < P.ops.size(); ++i) {
+    const double nv = norms[i];
+    if (!std::isfinite(nv)) return fail(SSM_E_NUMERIC, "operator %zu: delta [A B] has a non-finite norm", i);
+    int sq = 0;
+    while (sq <= kZohMaxSq && std::ldexp(nv, -sq) > 0.5) ++sq;
+    if (sq > kZohMaxSq)
+      return fail(SSM_E_NUMERIC, "operator %zu: |delta [A B]|_1 = %g needs more than %d squarings", i, nv,
+                  kZohMaxSq);
+    P.ops[i].zsq = sq;
+  }
+  // jobs (X, S, T: the three scratch matrices of an operator; S and T swap)
+  std::vector<GemmJob> J;
+  std::vector<std::pair<int, int>> groups, dims;
+  std::vector<int> kinds;
+  const double* I = zs + P.z_id;
+  const int nid = P.z_nid;
+  std::vector<double*> S(P.ops.size()), T(P.ops.size());
+  auto group = [&](int kind, auto&& fill) {
+    const int start = (int)J.size();
+    int mx = 0, mn = 0;
+    for (size_t i = 0; i < P.ops.size(); ++i) {
+      const size_t before = J.size();
+      fill(i);
+      for (size_t j = before; j < J.size(); ++j) {
+        mx = std::max(mx, J[j].M);
+        mn = std::max(mn, J[j].N);
+      }
+    }
+    if ((int)J.size() > start) {
+      groups.push_back({start, (int)J.size() - start});
+      dims.push_back({mx, mn});
+      kinds.push_back(kind);
+    }
+  };
+  for (size_t i = 0; i < P.ops.size(); ++i) {
+    const OpDev& o = P.ops[i];
+    const int64_t nn = (int64_t)o.zn * o.zn;
+    S[i] = zs + o.zx + nn;
+    T[i] = zs + o.zx + 2 * nn;
+  }
+  group(1, [&](size_t i) {  // X = E / 2^s;  S = I
+    const OpDev& o = P.ops[i];
+    double* X = zs + o.zx;
+    J.push_back(GemmJob{X, nullptr, X, o.zn, o.zn, 0, o.zn, 0, o.zn, 0, 0, std::ldexp(1.0, -o.zsq), 0.0});
+    J.push_back(GemmJob{I, nullptr, S[i], o.zn, o.zn, 0, nid, 0, o.zn, 0, 0, 1.0, 0.0});
+  });
+  for (int k = kZohTaylor; k >= 1; --k) {
+    group(1, [&](size_t i) {  // T = I
+      const OpDev& o = P.ops[i];
+      J.push_back(GemmJob{I, nullptr, T[i], o.zn, o.zn, 0, nid, 0, o.zn, 0, 0, 1.0, 0.0});
+    });
+    group(0, [&](size_t i) {  // T = X S / k + T
+      const OpDev& o = P.ops[i];
+      J.push_back(GemmJob{zs + o.zx, S[i], T[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 0, 0, 1.0 / k, 1.0});
+    });
+    for (size_t i = 0; i < P.ops.size(); ++i) std::swap(S[i], T[i]);
+  }
+  int max_sq = 0;
+  for (const OpDev& o : P.ops) max_sq = std::max(max_sq, o.zsq);
+  for (int t = 0; t < max_sq; ++t) {
+    group(0, [&](size_t i) {  // T = S S
+      const OpDev& o = P.ops[i];
+      if (o.zsq <= t) return;
+      J.push_back(GemmJob{S[i], S[i], T[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 0, 0, 1.0, 0.0});
+    });
+    for (size_t i = 0; i < P.ops.size(); ++i)
+      if (P.ops[i].zsq > t) std::swap(S[i], T[i]);
+  }
+  group(1, [&](size_t i) {  // P_0 = exp(E)[:m, :m], Bbar = exp(E)[:m, m:]
+    const OpDev& o = P.ops[i];
+    J.push_back(GemmJob{S[i], nullptr, pw + o.pw, o.m, o.m, 0, o.zn, 0, o.mp, 0, 0, 1.0, 0.0});
+    J.push_back(GemmJob{S[i] + o.m, nullptr, bbar + o.bbar, o.m, o.p, 0, o.zn, 0, o.p, 0, 0, 1.0, 0.0});
+  });
+  if (J.size() > P.z_cap) return fail(SSM_E_INVALID, "exponential job table overflow");
+  unsigned char* meta = P.ws + P.r_meta.off;
+  std::memcpy(P.meta_host.data() + P.m_zjobs, J.data(), sizeof(GemmJob) * J.size());
+  e = hipMemcpyAsync(meta + P.m_zjobs, P.meta_host.data() + P.m_zjobs, sizeof(GemmJob) * J.size(),
+                     hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "upload of the exponential jobs");
+  // the squarings chosen above, for the operator table on the device
+  e = hipMemcpyAsync(meta + P.m_ops, P.ops.data(), sizeof(OpDev) * P.ops.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "upload of the operator table");
+  const GemmJob* jd = reinterpret_cast<const GemmJob*>(meta + P.m_zjobs);
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const auto& gr = groups[gi];
+    e = kinds[gi] == 1 ? launch_axpy(jd + gr.first, gr.second, dims[gi].first, dims[gi].second, stream)
+                       : launch_gemm_f64(jd + gr.first, gr.second, dims[gi].first, dims[gi].second, stream);
+    if (e != hipSuccess) return hip_fail(e, "exponential launch");
+  }
+  return SSM_OK;
 }
 
 }  // namespace
@@ -1672,11 +1819,16 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     e = launch_zero_i32(P->at<int32_t>(P->r_kw), (int64_t)(P->r_kw.bytes / 4), stream);
     if (e != hipSuccess) return bail(hip_fail(e, "zero fill"));
   }
-  e = launch_disc_setup(ops_d, P->n_ops, src_d, given, P->at<double>(P->r_aug), nmat, bsc, pw,
-                        bbar, P->max_mp, stream);
-  if (e != hipSuccess) return bail(hip_fail(e, "discretization setup launch"));
   size_t g = 0;
-  if (!given) {
+  if (disc == SSM_DISC_ZOH) {
+    const ssm_status zs = zoh_discretize(*P, ops_d, src_d, stream);
+    if (zs != SSM_OK) return bail(zs);
+  } else {
+    e = launch_disc_setup(ops_d, P->n_ops, src_d, given, P->at<double>(P->r_aug), nmat, bsc, pw,
+                          bbar, P->max_mp, stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "discretization setup launch"));
+  }
+  if (disc == SSM_DISC_TRAPEZOID) {
     e = launch_gauss_jordan(ops_d, P->n_ops, P->at<double>(P->r_aug), minv, status_d, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "Gauss-Jordan launch"));
     const auto& grp = P->job_groups[g];

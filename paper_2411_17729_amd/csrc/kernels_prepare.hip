@@ -47,6 +47,62 @@ __global__ void k_disc_setup(const OpDev* ops, const OpSrc* src, int given, doub
   }
 }
 
+// Exponential discretization (§5): the augmented matrix E = delta [[A, B], [0,
+// 0]] ((m + p) x (m + p), row-major, at zx of the scratch), its 1-norm (the
+// largest column sum of |E|) for the choice of the scaling, and zeros in the
+// padded slots of Abar (P_0) and Bbar that the exponential fills. Workgroup
+// (x, op); workgroup (0, 0) also writes the identity of size nid used by the
+// Taylor steps.
+__global__ void k_zoh_setup(const OpDev* ops, const OpSrc* src, double* zs, double* zid, int nid,
+                            double* norms, double* pw, double* bbar) {
+  const OpDev o = ops[blockIdx.y];
+  const OpSrc sp = src[blockIdx.y];
+  const int m = o.m, p = o.p, n = o.zn, mp = o.mp;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double* X = zs + o.zx;
+  for (int64_t e = e0; e < (int64_t)n * n; e += stride) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    const double v = r >= m ? 0.0 : c < m ? sp.A[(int64_t)r * m + c] : sp.B[(int64_t)r * p + (c - m)];
+    X[e] = o.delta * v;
+  }
+  for (int64_t e = e0; e < (int64_t)mp * mp; e += stride) pw[o.pw + e] = 0.0;
+  for (int64_t e = e0; e < (int64_t)mp * p; e += stride) bbar[o.bbar + e] = 0.0;
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int64_t e = threadIdx.x; e < (int64_t)nid * nid; e += blockDim.x)
+      zid[e] = (e / nid) == (e % nid) ? 1.0 : 0.0;
+  if (blockIdx.x == 0) {
+    // column sums from the sources (not from X, which other workgroups write)
+    double best = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      double sum = 0.0;
+      for (int r = 0; r < m; ++r) sum += fabs(c < m ? sp.A[(int64_t)r * m + c] : sp.B[(int64_t)r * p + (c - m)]);
+      sum *= fabs(o.delta);
+      best = (sum > best || sum != sum) ? sum : best;  // a NaN wins
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) {
+        const double v = red[threadIdx.x + h];
+        if (v > red[threadIdx.x] || v != v) red[threadIdx.x] = v;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) norms[blockIdx.y] = red[0];
+  }
+}
+
+hipError_t launch_zoh_setup(const OpDev* ops, int n_ops, const OpSrc* src, double* zs, double* zid, int nid,
+                            double* norms, double* pw, double* bbar, int max_n, hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  const int blocks = (max_n * max_n + 255) / 256;
+  hipLaunchKernelGGL(k_zoh_setup, dim3(blocks < 256 ? blocks : 256, n_ops), dim3(256), 0, s, ops, src, zs, zid,
+                     nid, norms, pw, bbar);
+  return hipGetLastError();
+}
+
 hipError_t launch_disc_setup(const OpDev* ops, int n_ops, const OpSrc* src, int given,
                              double* aug, double* nmat, double* bsc, double* pw,
                              double* bbar, int max_mp, hipStream_t s) {

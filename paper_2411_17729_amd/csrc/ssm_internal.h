@@ -64,6 +64,11 @@ struct OpDev {
   int32_t fold_s;
   int64_t fold_gw, fold_gc;
   int32_t fold_k0, reserved2;
+  // exponential discretization: scratch of three zn x zn FP64 matrices at zx
+  // (zn = m + p; the augmented matrix, then the Taylor and squaring
+  // ping-pong), and the squarings zsq chosen from its norm; zx = -1 if none
+  int64_t zx;
+  int32_t zn, zsq;
 };
 
 // A row tile of one sequence for the stage kernel.
@@ -258,6 +263,8 @@ hipError_t launch_axpy(const GemmJob* jobs_dev, int n_jobs, int max_m, int max_n
 // Builds, per operator, the trapezoid system [I - h A | I] (aug, mp x 2mp),
 // I + h A (nmat, mp x mp) and delta*B (bsc, mp x p); for given parameters
 // writes Abar into the k = 0 power slot and Bbar into bbar directly.
+hipError_t launch_zoh_setup(const OpDev* ops, int n_ops, const OpSrc* src, double* zs, double* zid, int nid,
+                            double* norms, double* pw, double* bbar, int max_n, hipStream_t s);
 hipError_t launch_disc_setup(const OpDev* ops, int n_ops, const OpSrc* src, int given,
                              double* aug, double* nmat, double* bsc, double* pw,
                              double* bbar, int max_mp, hipStream_t s);

@@ -13,14 +13,16 @@ def rel_err(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def discretized(wl, seq):
+def discretized(wl, seq, disc=None):
     ps = wl.sets[seq.param_set]
-    if wl.given:
+    if disc is None:
+        disc = "given" if wl.given else "trapezoid"
+    if disc == "given":
         return ps.A, ps.B
-    return O.trapezoid(ps.A, ps.B, seq.delta)
+    return (O.zoh if disc == "zoh" else O.trapezoid)(ps.A, ps.B, seq.delta)
 
 
-def oracle_outputs(wl, u_override=None, method="auto"):
+def oracle_outputs(wl, u_override=None, method="auto", disc=None):
     """Per-sequence FP64 outputs (L, q). ``method``: 'truncated', 'recursion'
     or 'auto' (recursion when the window covers the sequence, else the
     truncated sum)."""
@@ -29,7 +31,7 @@ def oracle_outputs(wl, u_override=None, method="auto"):
     for i, s in enumerate(wl.seqs):
         key = (s.param_set, s.delta)
         if key not in cache:
-            cache[key] = discretized(wl, s)
+            cache[key] = discretized(wl, s, disc)
         Abar, Bbar = cache[key]
         ps = wl.sets[s.param_set]
         u = s.u if u_override is None else u_override[i]
