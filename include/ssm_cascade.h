@@ -81,10 +81,13 @@ typedef enum {
    * "(delta A)^{-1} [exp(delta A) - I] delta A" is read with delta B as its
    * last factor, which it equals for invertible A). Both come from one FP64
    * exponential of [[delta A, delta B], [0, 0]] on the GPU: scaled by 2^-s so
-   * that its 1-norm is at most 1/2, an 18-term Taylor polynomial, then s
-   * squarings. Prepare reads the norms back (a second synchronization of the
-   * stream) to fix s per operator; a non-finite norm or s > 60 returns
-   * SSM_E_NUMERIC. */
+   * that its 1- and infinity-norms are at most 1/2, an 18-term Taylor
+   * polynomial, then s squarings. Prepare reads the norms back (a second
+   * synchronization of the stream) to fix s per operator; a non-finite norm
+   * or s > 60 returns SSM_E_NUMERIC. The backward carries the gradient
+   * through it with the adjoint of the exponential's derivative, the
+   * upper-right block of the exponential of [[E^T, G], [0, E^T]], formed the
+   * same way. */
   SSM_DISC_ZOH = 2
 } ssm_disc;
 

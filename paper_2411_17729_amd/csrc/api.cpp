@@ -106,6 +106,11 @@ struct ssm_plan_s {
   int64_t z_id = 0, z_norm = 0;
   int z_nid = 0;
   size_t m_zjobs = 0, z_cap = 0;
+  // its adjoint (backward plans): jobs at m_zbjobs (capacity zb_cap), groups
+  std::vector<GemmJob> zbjobs;
+  std::vector<std::pair<int, int>> zbgroups, zbdims;
+  std::vector<int> zbkind;
+  size_t m_zbjobs = 0, zb_cap = 0;
   size_t m_seqs = 0, m_ops = 0, m_src = 0, m_tiles = 0, m_status = 0, m_jobs = 0;
   std::vector<GemmJob> jobs;            // prepare jobs, in launch order
   std::vector<std::pair<int, int>> job_groups;  // (start, count) per launch
@@ -268,8 +273,6 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   }
   if (disc != SSM_DISC_TRAPEZOID && disc != SSM_DISC_GIVEN && disc != SSM_DISC_ZOH)
     return fail(SSM_E_INVALID, "unknown discretization %d", (int)disc);
-  if (disc == SSM_DISC_ZOH && with_backward)
-    return fail(SSM_E_UNSUPPORTED, "the backward through the exponential discretization is not built");
   if (compute != SSM_F64 && compute != SSM_F32 && compute != SSM_BF16)
     return fail(SSM_E_INVALID, "unknown compute dtype %d", (int)compute);
   if (ckpt_every < 0) return fail(SSM_E_INVALID, "ckpt_every must be >= 0");
@@ -979,7 +982,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     if (disc == SSM_DISC_ZOH) {
       o.zn = o.m + o.p;
       o.zx = (int64_t)n_zoh;
-      n_zoh += 3 * (size_t)o.zn * o.zn;
+      n_zoh += (P.with_backward ? 6 : 3) * (size_t)o.zn * o.zn;
       P.z_nid = std::max(P.z_nid, o.zn);
     }
   }
@@ -1017,6 +1020,12 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   P.z_cap = disc == SSM_DISC_ZOH ? P.ops.size() * (size_t)(4 + 2 * kZohTaylor + kZohMaxSq) : 0;
   P.m_zjobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, P.z_cap));
+  // its adjoint: per operator five set-up jobs, four per Taylor step, three
+  // per squaring and two copies
+  P.zb_cap = disc == SSM_DISC_ZOH && P.with_backward
+                 ? P.ops.size() * (size_t)(7 + 4 * kZohTaylor + 3 * kZohMaxSq) : 0;
+  P.m_zbjobs = off;
+  off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, P.zb_cap));
   P.sum_x = xoff;
   P.m_ranges = off;
   off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.ranges.size()));
@@ -1273,7 +1282,7 @@ void plan_backward_jobs(ssm_plan_s& P) {
                                 o.p, 1, 0, o.delta, 0.0});
     }
     close_group(start, 0);
-  } else {
+  } else if (P.disc == SSM_DISC_GIVEN) {
     for (const OpDev& o : P.ops) {
       P.bjobs.push_back(GemmJob{G + o.g_dp, nullptr, G + o.g_da, o.mp, o.mp, 0, o.mp, 0, o.mp, 0, 0,
                                 1.0, 0.0});
@@ -1372,6 +1381,112 @@ StageParams base_params(const ssm_plan_s& P, int c) {
   return prm;
 }
 
+// Jobs of the adjoint of the exponential discretization, run by the backward
+// after the squaring adjoint has left dL/dAbar in g_dp (k = 0) and dL/dBbar in
+// g_dbb. For F = exp(E), the adjoint of dF = L(E, dE) is G -> L(E^T, G), the
+// upper-right block of exp([[E^T, G], [0, E^T]]); with G = [[dL/dAbar,
+// dL/dBbar], [0, 0]] and E = delta [[A, B], [0, 0]], dL/dA = delta L[:m, :m]
+// and dL/dB = delta L[:m, m:]. The block upper-triangular exponential is
+// carried as its pair of blocks (D, F): the same scaling by 2^-s as the
+// forward (X = E / 2^s is still in the scratch, used transposed), Horner steps
+// (D, F) <- (I + X^T D / k, (X^T F + Y D) / k) with Y = G / 2^s, and s
+// squarings (D, F) <- (D D, D F + F D).
+ssm_status zoh_adjoint_jobs(ssm_plan_s& P) {
+  double* zs = P.at<double>(P.r_zoh);
+  double* G = P.at<double>(P.r_g);
+  const double* I = zs + P.z_id;
+  const int nid = P.z_nid;
+  P.zbjobs.clear();
+  P.zbgroups.clear();
+  P.zbdims.clear();
+  P.zbkind.clear();
+  std::vector<GemmJob>& J = P.zbjobs;
+  const size_t nops = P.ops.size();
+  std::vector<double*> Sd(nops), Td(nops), Sf(nops), Tf(nops), Y(nops), X(nops);
+  for (size_t i = 0; i < nops; ++i) {
+    const OpDev& o = P.ops[i];
+    const int64_t nn = (int64_t)o.zn * o.zn;
+    X[i] = zs + o.zx;
+    Sd[i] = X[i] + nn;
+    Td[i] = X[i] + 2 * nn;
+    Sf[i] = X[i] + 3 * nn;
+    Tf[i] = X[i] + 4 * nn;
+    Y[i] = X[i] + 5 * nn;
+  }
+  auto group = [&](int kind, auto&& fill) {
+    const int start = (int)J.size();
+    int mx = 0, mn = 0;
+    for (size_t i = 0; i < nops; ++i) fill(i);
+    for (size_t j = start; j < J.size(); ++j) {
+      mx = std::max(mx, J[j].M);
+      mn = std::max(mn, J[j].N);
+    }
+    if ((int)J.size() > start) {
+      P.zbgroups.push_back({start, (int)J.size() - start});
+      P.zbdims.push_back({mx, mn});
+      P.zbkind.push_back(kind);
+    }
+  };
+  group(1, [&](size_t i) {  // Y = 0, D = I, F = 0 (zeros as 0 times the identity)
+    const OpDev& o = P.ops[i];
+    J.push_back(GemmJob{I, nullptr, Y[i], o.zn, o.zn, 0, nid, 0, o.zn, 0, 0, 0.0, 0.0});
+    J.push_back(GemmJob{I, nullptr, Sd[i], o.zn, o.zn, 0, nid, 0, o.zn, 0, 0, 1.0, 0.0});
+    J.push_back(GemmJob{I, nullptr, Sf[i], o.zn, o.zn, 0, nid, 0, o.zn, 0, 0, 0.0, 0.0});
+  });
+  group(1, [&](size_t i) {  // Y = [[dL/dAbar, dL/dBbar], [0, 0]] / 2^s
+    const OpDev& o = P.ops[i];
+    const double sc = std::ldexp(1.0, -o.zsq);
+    J.push_back(GemmJob{G + o.g_dp, nullptr, Y[i], o.m, o.m, 0, o.mp, 0, o.zn, 0, 0, sc, 0.0});
+    J.push_back(GemmJob{G + o.g_dbb, nullptr, Y[i] + o.m, o.m, o.p, 0, o.p, 0, o.zn, 0, 0, sc, 0.0});
+  });
+  for (int k = kZohTaylor; k >= 1; --k) {
+    group(1, [&](size_t i) {  // T_D = I
+      const OpDev& o = P.ops[i];
+      J.push_back(GemmJob{I, nullptr, Td[i], o.zn, o.zn, 0, nid, 0, o.zn, 0, 0, 1.0, 0.0});
+    });
+    group(0, [&](size_t i) {  // T_D = X^T S_D / k + T_D;  T_F = X^T S_F / k
+      const OpDev& o = P.ops[i];
+      J.push_back(GemmJob{X[i], Sd[i], Td[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 1, 0, 1.0 / k, 1.0});
+      J.push_back(GemmJob{X[i], Sf[i], Tf[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 1, 0, 1.0 / k, 0.0});
+    });
+    group(0, [&](size_t i) {  // T_F = Y S_D / k + T_F
+      const OpDev& o = P.ops[i];
+      J.push_back(GemmJob{Y[i], Sd[i], Tf[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 0, 0, 1.0 / k, 1.0});
+    });
+    for (size_t i = 0; i < nops; ++i) {
+      std::swap(Sd[i], Td[i]);
+      std::swap(Sf[i], Tf[i]);
+    }
+  }
+  int max_sq = 0;
+  for (const OpDev& o : P.ops) max_sq = std::max(max_sq, o.zsq);
+  for (int t = 0; t < max_sq; ++t) {
+    group(0, [&](size_t i) {  // T_D = S_D S_D;  T_F = S_D S_F
+      const OpDev& o = P.ops[i];
+      if (o.zsq <= t) return;
+      J.push_back(GemmJob{Sd[i], Sd[i], Td[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 0, 0, 1.0, 0.0});
+      J.push_back(GemmJob{Sd[i], Sf[i], Tf[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 0, 0, 1.0, 0.0});
+    });
+    group(0, [&](size_t i) {  // T_F = S_F S_D + T_F
+      const OpDev& o = P.ops[i];
+      if (o.zsq <= t) return;
+      J.push_back(GemmJob{Sf[i], Sd[i], Tf[i], o.zn, o.zn, o.zn, o.zn, o.zn, o.zn, 0, 0, 1.0, 1.0});
+    });
+    for (size_t i = 0; i < nops; ++i)
+      if (P.ops[i].zsq > t) {
+        std::swap(Sd[i], Td[i]);
+        std::swap(Sf[i], Tf[i]);
+      }
+  }
+  group(1, [&](size_t i) {  // dL/dA = delta F[:m, :m], dL/dB = delta F[:m, m:]
+    const OpDev& o = P.ops[i];
+    J.push_back(GemmJob{Sf[i], nullptr, G + o.g_da, o.m, o.m, 0, o.zn, 0, o.mp, 0, 0, o.delta, 0.0});
+    J.push_back(GemmJob{Sf[i] + o.m, nullptr, G + o.g_db, o.m, o.p, 0, o.zn, 0, o.p, 0, 0, o.delta, 0.0});
+  });
+  if (J.size() > P.zb_cap) return fail(SSM_E_INVALID, "exponential adjoint job table overflow");
+  return SSM_OK;
+}
+
 // Exponential discretization (§5) of every operator: exp(E), E = delta [[A,
 // B], [0, 0]], whose blocks are Abar = exp(delta A) and Bbar = int_0^delta
 // exp(sA) ds B. The norms of E come back to the host, which fixes per operator
@@ -1467,6 +1582,10 @@ ssm_status zoh_discretize(ssm_plan_s& P, const OpDev* ops_d, const OpSrc* src_d,
     J.push_back(GemmJob{S[i] + o.m, nullptr, bbar + o.bbar, o.m, o.p, 0, o.zn, 0, o.p, 0, 0, 1.0, 0.0});
   });
   if (J.size() > P.z_cap) return fail(SSM_E_INVALID, "exponential job table overflow");
+  if (P.with_backward) {
+    const ssm_status bs = zoh_adjoint_jobs(P);
+    if (bs != SSM_OK) return bs;
+  }
   unsigned char* meta = P.ws + P.r_meta.off;
   std::memcpy(P.meta_host.data() + P.m_zjobs, J.data(), sizeof(GemmJob) * J.size());
   e = hipMemcpyAsync(meta + P.m_zjobs, P.meta_host.data() + P.m_zjobs, sizeof(GemmJob) * J.size(),
@@ -1475,6 +1594,12 @@ ssm_status zoh_discretize(ssm_plan_s& P, const OpDev* ops_d, const OpSrc* src_d,
   // the squarings chosen above, for the operator table on the device
   e = hipMemcpyAsync(meta + P.m_ops, P.ops.data(), sizeof(OpDev) * P.ops.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "upload of the operator table");
+  if (!P.zbjobs.empty()) {
+    std::memcpy(P.meta_host.data() + P.m_zbjobs, P.zbjobs.data(), sizeof(GemmJob) * P.zbjobs.size());
+    e = hipMemcpyAsync(meta + P.m_zbjobs, P.meta_host.data() + P.m_zbjobs, sizeof(GemmJob) * P.zbjobs.size(),
+                       hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "upload of the exponential adjoint jobs");
+  }
   const GemmJob* jd = reinterpret_cast<const GemmJob*>(meta + P.m_zjobs);
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const auto& gr = groups[gi];
@@ -2213,6 +2338,15 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
     else
       e = launch_axpy(bj_d + gr.first, gr.second, P.bdims[gi].first, P.bdims[gi].second, stream);
     if (e != hipSuccess) return hip_fail(e, "FP64 adjoint launch");
+  }
+  if (P.disc == SSM_DISC_ZOH) {
+    const GemmJob* zj = reinterpret_cast<const GemmJob*>(meta + P.m_zbjobs);
+    for (size_t gi = 0; gi < P.zbgroups.size(); ++gi) {
+      const auto& gr = P.zbgroups[gi];
+      e = P.zbkind[gi] == 0 ? launch_gemm_f64(zj + gr.first, gr.second, P.zbdims[gi].first, P.zbdims[gi].second, stream)
+                            : launch_axpy(zj + gr.first, gr.second, P.zbdims[gi].first, P.zbdims[gi].second, stream);
+      if (e != hipSuccess) return hip_fail(e, "exponential adjoint launch");
+    }
   }
   e = launch_scatter(reinterpret_cast<const ScatterJob*>(meta + P.m_scat), (int)P.scat.size(),
                      reinterpret_cast<const int32_t*>(meta + P.m_set_ops),

@@ -48,8 +48,9 @@ __global__ void k_disc_setup(const OpDev* ops, const OpSrc* src, int given, doub
 }
 
 // Exponential discretization (§5): the augmented matrix E = delta [[A, B], [0,
-// 0]] ((m + p) x (m + p), row-major, at zx of the scratch), its 1-norm (the
-// largest column sum of |E|) for the choice of the scaling, and zeros in the
+// 0]] ((m + p) x (m + p), row-major, at zx of the scratch), the larger of its
+// 1- and infinity-norms (largest column and row sums of |E|; the adjoint uses
+// E^T) for the choice of the scaling, and zeros in the
 // padded slots of Abar (P_0) and Bbar that the exponential fills. Workgroup
 // (x, op); workgroup (0, 0) also writes the identity of size nid used by the
 // Taylor steps.
@@ -72,13 +73,21 @@ __global__ void k_zoh_setup(const OpDev* ops, const OpSrc* src, double* zs, doub
     for (int64_t e = threadIdx.x; e < (int64_t)nid * nid; e += blockDim.x)
       zid[e] = (e / nid) == (e % nid) ? 1.0 : 0.0;
   if (blockIdx.x == 0) {
-    // column sums from the sources (not from X, which other workgroups write)
+    // column and row sums from the sources (not from X, which other
+    // workgroups write)
     double best = 0.0;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
       double sum = 0.0;
       for (int r = 0; r < m; ++r) sum += fabs(c < m ? sp.A[(int64_t)r * m + c] : sp.B[(int64_t)r * p + (c - m)]);
       sum *= fabs(o.delta);
       best = (sum > best || sum != sum) ? sum : best;  // a NaN wins
+    }
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+      double sum = 0.0;
+      for (int c = 0; c < m; ++c) sum += fabs(sp.A[(int64_t)r * m + c]);
+      for (int c = 0; c < p; ++c) sum += fabs(sp.B[(int64_t)r * p + c]);
+      sum *= fabs(o.delta);
+      best = (sum > best || sum != sum) ? sum : best;
     }
     __shared__ double red[256];
     red[threadIdx.x] = best;

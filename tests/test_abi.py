@@ -134,6 +134,23 @@ def test_tuning_is_validated(lib):
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
 
 
+def test_discretizations_on_host(lib):
+    # trapezoid, given and exponential are accepted; the exponential needs its
+    # scratch (three (m + p)^2 FP64 matrices per operator, six with the
+    # backward); an unknown value is rejected
+    from paper_2411_17729_amd import binding as B
+    arr = (B.ssm_seq_desc * 1)(_desc(m=100, p=3))
+    n = {d: lib.ssm_cascade_workspace_bytes(arr, 1, d, 1, 0, 0, None) for d in (0, 1, 2)}
+    nb = {d: lib.ssm_cascade_workspace_bytes(arr, 1, d, 1, 1, 0, None) for d in (0, 2)}
+    assert all(v > 0 for v in n.values()) and all(v > 0 for v in nb.values())
+    assert n[2] >= n[1] + 3 * 103 * 103 * 8 and nb[2] >= n[2] + 3 * 103 * 103 * 8
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 3, 1, 0, 0, None) == 0
+    assert "discretization" in lib.ssm_last_error().decode()
+    # the exponential needs a positive finite step, as the trapezoidal rule does
+    bad = (B.ssm_seq_desc * 1)(_desc(m=100, p=3, delta=0.0))
+    assert lib.ssm_cascade_workspace_bytes(bad, 1, 2, 1, 0, 0, None) == 0
+
+
 def test_graph_calls_reject_on_host(lib):
     from paper_2411_17729_amd import binding as B
     g = C.c_void_p()

@@ -19,8 +19,9 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 2e-2}
 
 
-def _oracle_grads(wl, dys, us):
-    """Per-set sums of the oracle gradients and per-sequence du."""
+def _oracle_grads(wl, dys, us, disc="trapezoid"):
+    """Per-set sums of the oracle gradients and per-sequence du (``disc``: the
+    discretization of a workload that is not given)."""
     nS = len(wl.sets)
     acc = [dict(A=0.0, B=0.0, C=0.0, D=0.0) for _ in range(nS)]
     dus = []
@@ -34,7 +35,7 @@ def _oracle_grads(wl, dys, us):
                 g = O.grads_truncated_bruteforce(ps.A, ps.B, ps.C, ps.D, u, dy, s.N)
             g = dict(u=g["u"], A=g["Abar"], B=g["Bbar"], C=g["C"], D=g["D"])
         else:
-            g = O.grads_full(ps.A, ps.B, ps.C, ps.D, s.delta, u, dy, s.N)
+            g = O.grads_full(ps.A, ps.B, ps.C, ps.D, s.delta, u, dy, s.N, disc=disc)
         for k in "ABCD":
             acc[s.param_set][k] = acc[s.param_set][k] + g[k]
         dus.append(g["u"])
@@ -66,13 +67,15 @@ def _gpu_grads(wl, compute, dys, ckpt_every=0, u_dtype=None, **plan_kw):
     return dul, gs, us, plan
 
 
-def _compare(wl, compute, ckpt_every=0, tol=None, u_dtype=None, **plan_kw):
+def _compare(wl, compute, ckpt_every=0, tol=None, u_dtype=None, disc="trapezoid", **plan_kw):
     rng = np.random.default_rng(123)
     dys = wl.dy if wl.dy is not None else [rng.standard_normal((s.L, wl.sets[s.param_set].q)) for s in wl.seqs]
     if compute != "f64":
         dys = [d.astype(np.float32).astype(np.float64) for d in dys]
+    if disc != "trapezoid":
+        plan_kw["disc"] = disc
     dul, gs, us, _ = _gpu_grads(wl, compute, dys, ckpt_every, u_dtype, **plan_kw)
-    ref, dus = _oracle_grads(wl, dys, us)
+    ref, dus = _oracle_grads(wl, dys, us, disc)
     tol = TOL[compute] if tol is None else tol
     errs = {"u": max(rel_err(a, b) for a, b in zip(dul, dus))}
     for si in range(len(wl.sets)):

@@ -1,8 +1,9 @@
 """The exponential discretization (Abar = exp(delta A) of §5, Bbar the
 zero-order hold) on the GPU, through the C ABI: Abar, Bbar and the powers
 against the FP64 oracle, the cascade on them against the oracle's recursion
-or truncated sum at the FP64, FP32 and BF16 bounds, and the host-side
-refusals (non-finite norm, the backward)."""
+or truncated sum at the FP64, FP32 and BF16 bounds, the host-side refusal of
+a non-finite norm, and the gradients through it against the oracle's and
+against central finite differences of the FP64 GPU forward."""
 
 import numpy as np
 import pytest
@@ -58,12 +59,19 @@ def test_zoh_abar_bbar_and_powers(case):
     ea = _rel_max(plan.power(0, 0).cpu().numpy(), Abar)
     eb = _rel_max(plan.bbar(0, m, p).cpu().numpy(), Bbar)
     ep = [_rel_max(plan.power(0, k).cpu().numpy(), P[k]) for k in range(N + 1)]
-    print(f"{label}: Abar {ea:.2e} Bbar {eb:.2e} powers {max(ep):.2e}", flush=True)
-    # FP64 on both sides; the squarings and Taylor steps round differently from
-    # scipy's Pade approximant. A relative difference d in Abar becomes up to
-    # 2^k d in Abar^(2^k) (first order), hence the bound on the powers.
-    assert ea < 1e-12 and eb < 1e-12, (ea, eb)
-    assert all(e < (1 << k) * 1e-11 for k, e in enumerate(ep)), ep
+    # FP64 on both sides, by different methods (Taylor steps and s squarings
+    # here, scipy's Pade approximant with its own scaling there). A rounding
+    # error before t remaining squarings grows up to 2^t times (first order),
+    # so the bound scales with 2^s, s the squarings of the scaling to norm 1/2;
+    # Abar^(2^k) adds another factor 2^k.
+    E = np.zeros((m + p, m + p))
+    E[:m, :m], E[:m, m:] = delta * A, delta * Bm
+    nrm = max(np.abs(E).sum(0).max(), np.abs(E).sum(1).max())
+    sq = max(0, int(np.ceil(np.log2(nrm / 0.5))))
+    tol = max(2.0 ** sq, 64.0) * 2 * np.finfo(float).eps
+    print(f"{label}: s {sq} tol {tol:.1e}  Abar {ea:.2e} Bbar {eb:.2e} powers {max(ep):.2e}", flush=True)
+    assert ea < tol and eb < tol, (ea, eb, tol)
+    assert all(e < (1 << k) * tol for k, e in enumerate(ep)), (ep, tol)
 
 
 @pytest.mark.parametrize("compute", ["f64", "f32", "bf16"])
@@ -108,7 +116,7 @@ def test_zoh_differs_from_trapezoid():
     assert d > 1e-8, d
 
 
-def test_zoh_rejects_nonfinite_and_backward():
+def test_zoh_rejects_nonfinite():
     from paper_2411_17729_amd import cascade as CC
     m, p = 8, 1
     A = -np.eye(m)
@@ -119,6 +127,61 @@ def test_zoh_rejects_nonfinite_and_backward():
         CC.CascadePlan(layout, [(A, np.ones((m, p)), np.ones((1, m)), np.zeros((1, p)))], compute="f32",
                        disc="zoh")
     assert ei.value.status == B.SSM_E_NUMERIC and "non-finite" in str(ei.value)
-    with pytest.raises(B.SSMError, match="backward through the exponential"):
-        CC.CascadePlan(layout, [(-np.eye(m), np.ones((m, p)), np.ones((1, m)), np.zeros((1, p)))],
-                       compute="f32", disc="zoh", with_backward=True)
+
+
+# ---- the backward through the exponential ----------------------------------
+
+@pytest.mark.parametrize("compute", ["f64", "f32", "bf16"])
+def test_zoh_backward_matches_oracle(compute):
+    from tests.test_gpu_backward import _compare
+    wl = W.backward(seed=1, batch=3, m=24, L=300, N=8, p=2, q=3, delta=2e-2)
+    _compare(wl, compute, disc="zoh")
+
+
+def test_zoh_backward_per_sequence_delta_and_classes():
+    # operators of two size classes, one step size per sequence, a large step
+    # (several squarings in the adjoint)
+    from tests.test_gpu_backward import _compare
+    rng = np.random.default_rng(21)
+    sets, seqs = [], []
+    for i, (m, p, q, L, N, d) in enumerate([(40, 3, 2, 257, 8, 1e-2), (40, 3, 2, 200, 7, 0.3),
+                                            (130, 4, 3, 96, 6, 5e-3)]):
+        A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, p)) / m, rng.standard_normal((q, m)) / m,
+                               rng.standard_normal((q, p))))
+        s = W.Sequence(i, d, L, N, None)
+        s.u = rng.standard_normal((L, p))
+        seqs.append(s)
+    dy = [rng.standard_normal((s.L, sets[s.param_set].q)) for s in seqs]
+    wl = W.Workload("zoh_ragged", sets, seqs, dy=dy)
+    _compare(wl, "f64", disc="zoh")
+
+
+def test_zoh_backward_finite_differences_fp64_gpu():
+    # central differences (h = 1e-6) of <dy, y> through the FP64 GPU forward
+    # with the exponential discretization
+    from paper_2411_17729_amd import cascade as CC
+    from tests.test_gpu_backward import _gpu_grads
+    wl = W.backward(seed=6, batch=2, m=32, L=400, N=8, p=2, q=2, delta=5e-2)
+    ps = wl.sets[0]
+    _, gs, _, _ = _gpu_grads(wl, "f64", wl.dy, disc="zoh")
+    dyt = np.concatenate([d.reshape(-1) for d in wl.dy])
+    rng = np.random.default_rng(0)
+
+    def f(A, Bm):
+        w2 = W.Workload("fd", [W.ParamSet(A, Bm, ps.C, ps.D)], wl.seqs)
+        plan = CC.plan_for_workload(w2, compute="f64", disc="zoh")
+        y = plan.apply(CC.pack_u(w2, dtype=torch.float64)).cpu().numpy()
+        return float(np.dot(dyt, y))
+
+    h = 1e-6
+    for j, (name, X) in enumerate((("A", ps.A), ("B", ps.B))):
+        V = rng.standard_normal(X.shape)
+        args_p = [ps.A, ps.B]
+        args_m = [ps.A, ps.B]
+        args_p[j] = X + h * V
+        args_m[j] = X - h * V
+        fd = (f(*args_p) - f(*args_m)) / (2 * h)
+        an = float(np.sum(gs[0][j] * V))
+        print(name, fd, an, flush=True)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, fd, an)
