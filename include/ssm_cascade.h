@@ -173,9 +173,14 @@ typedef struct {
    * so y_l = sum_j G_j x_{l - j 2^k0} + D u_l with G_j = C Abar^(j 2^k0) (q x m,
    * FP64 during prepare, then rounded once to BF16), x the state after the
    * stages before k0: one pass that reads the state once and writes y in place
-   * of the last s stages. 0: automatic (the largest s the LDS holds, 4 at
-   * padded m 256 and 5 at 128, with the stages before it pairing up), -1: off,
-   * 2..5: at most that many. */
+   * of the last s stages. At padded m 256 with q <= 8, s = 6: two lags share
+   * an MFMA operand (G_{2i} over G_{2i+1}), the 64 lags run as two ranges of
+   * 32 in separate workgroups, and both add into y after it is zeroed (at
+   * most two additions onto zero per output, so the sum does not depend on
+   * their order); the range from lag 32 reads only the blocks it needs.
+   * 0: automatic (the largest s the LDS holds: 6 at padded m 256 and q <= 8,
+   * else 4; 5 at 128; with the stages before it pairing up), -1: off, 2..6:
+   * at most that many. */
   int32_t fold_stages;
   int32_t reserved[3];   /* must be 0 */
 } ssm_tuning;

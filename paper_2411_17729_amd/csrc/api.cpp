@@ -159,6 +159,7 @@ struct ssm_plan_s {
   // output pass with the last stages folded in: per class the first folded
   // stage and their number (0: none), workgroup units, LDS bytes
   int fold_k0[4] = {0, 0, 0, 0}, fold_s[4] = {0, 0, 0, 0};
+  bool fold_wide[4] = {false, false, false, false};  // six stages, paired lags, two ranges
   std::vector<FoldUnit> fold_units;
   int fold_start[4] = {0, 0, 0, 0}, fold_count[4] = {0, 0, 0, 0};
   size_t fold_lds_bytes[4] = {0, 0, 0, 0};
@@ -253,8 +254,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     return fail(SSM_E_INVALID, "pair_blocks = %d: supported 0 (automatic) or 4..256", tn.pair_blocks);
   if (tn.input_split < 0 || tn.input_split > 1)
     return fail(SSM_E_INVALID, "input_split = %d: supported 0 (automatic) or 1 (off)", tn.input_split);
-  if (tn.fold_stages < -1 || tn.fold_stages == 1 || tn.fold_stages > 5)
-    return fail(SSM_E_INVALID, "fold_stages = %d: supported 0 (automatic), -1 (off) or 2..5", tn.fold_stages);
+  if (tn.fold_stages < -1 || tn.fold_stages == 1 || tn.fold_stages > 6)
+    return fail(SSM_E_INVALID, "fold_stages = %d: supported 0 (automatic), -1 (off) or 2..6", tn.fold_stages);
   if (tn.state_bf16 < 0 || tn.state_bf16 > 1)
     return fail(SSM_E_INVALID, "state_bf16 = %d: supported 0 (FP32 state) or 1 (BF16 where supported)",
                 tn.state_bf16);
@@ -570,10 +571,11 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // such that the stages between the input pass and the fold pair up.
   for (int c = 0; c < 4; ++c) {
     P.fold_s[c] = P.fold_k0[c] = 0;
+    P.fold_wide[c] = false;
     if (P.class_max_last[c] < 0 || tn.fold_stages == -1 || P.launch != SSM_LAUNCH_PER_STAGE ||
         P.stage_kernel != SSM_STAGE_CHAIN || !fold_supported(kClassMp[c], (int)compute, 2))
       continue;
-    int min_last = 1 << 30, max_last = -1, kmin = 1 << 30, kmax = -1;
+    int min_last = 1 << 30, max_last = -1, kmin = 1 << 30, kmax = -1, max_q = 1, max_p = 1;
     bool ok = true;
     for (const SeqDev& sq : P.seqs)
       if (P.ops[sq.op].mp == kClassMp[c]) {
@@ -581,16 +583,20 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
         max_last = std::max(max_last, sq.last);
         kmin = std::min(kmin, sq.kry);
         kmax = std::max(kmax, sq.kry);
+        max_q = std::max(max_q, sq.q);
+        max_p = std::max(max_p, sq.p);
         ok = ok && sq.q <= 16 && sq.p <= 64 && sq.L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
       }
     if (!ok || min_last != max_last || kmin != kmax) continue;
-    const int smax = std::min(fold_max_stages(kClassMp[c]), tn.fold_stages > 0 ? tn.fold_stages : 99);
+    const bool wide_ok = fold_wide_supported(kClassMp[c], (int)compute, max_q, max_p);
+    const int smax = std::min(wide_ok ? 6 : fold_max_stages(kClassMp[c]), tn.fold_stages > 0 ? tn.fold_stages : 99);
     for (int sf = smax; sf >= 2; --sf) {
       const int k0 = max_last - sf + 1, kp = std::max(4, kmin);
       if (k0 < 4 || k0 < kmin) continue;
       if (tn.pair_stages != 1 && pair_supported(kClassMp[c], (int)compute) && (k0 - kp) % 2 != 0) continue;
       P.fold_s[c] = sf;
       P.fold_k0[c] = k0;
+      P.fold_wide[c] = sf == 6;
       break;
     }
   }
@@ -662,6 +668,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   for (OpDev& o : P.ops) {
     o.fold_s = 0;
     o.fold_k0 = 0;
+    o.fold_paired = 0;
   }
   for (int c = 0; c < 4; ++c) {
     P.fold_start[c] = (int)P.fold_units.size();
@@ -679,15 +686,26 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     std::stable_sort(ids.begin(), ids.end(),
                      [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
     const int ncol = (1 << P.fold_k0[c]) / 16;
-    for (int i : ids)
-      for (int c0 = 0; c0 < ncol; c0 += 4)
-        P.fold_units.push_back(FoldUnit{i, c0, std::min(4, ncol - c0), 0});
+    if (P.fold_wide[c]) {
+      // two columns per workgroup (one workgroup per compute unit for the
+      // LDS), the range from lag 0 first (it has the most work)
+      for (int h = 0; h < 2; ++h)
+        for (int i : ids)
+          for (int c0 = 0; c0 < ncol; c0 += 2)
+            P.fold_units.push_back(FoldUnit{i, c0, std::min(2, ncol - c0), 32 * h});
+      P.fold_lds_bytes[c] = fold_wide_lds();
+    } else {
+      for (int i : ids)
+        for (int c0 = 0; c0 < ncol; c0 += 4)
+          P.fold_units.push_back(FoldUnit{i, c0, std::min(4, ncol - c0), 0});
+      P.fold_lds_bytes[c] = fold_lds(kClassMp[c], P.fold_s[c], max_p, max_q);
+    }
     P.fold_count[c] = (int)P.fold_units.size() - P.fold_start[c];
-    P.fold_lds_bytes[c] = fold_lds(kClassMp[c], P.fold_s[c], max_p, max_q);
     for (OpDev& o : P.ops)
       if (class_of(o.mp) == c) {
         o.fold_s = P.fold_s[c];
         o.fold_k0 = P.fold_k0[c];
+        o.fold_paired = P.fold_wide[c] ? 1 : 0;
       }
   }
 
@@ -2099,8 +2117,10 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       if (P.fold_s[c] > 0 && kk == P.fold_k0[c]) {  // the remaining stages and y in one pass
         TimedLaunch tl(P, stream, 5);
         const FoldUnit* un = reinterpret_cast<const FoldUnit*>(P.ws + P.r_meta.off + P.m_fold) + P.fold_start[c];
-        e = launch_output_fold(kClassMp[c], P.compute, P.fold_s[c], P.state_bf16 != 0, prm, un, P.fold_count[c],
-                               P.fold_lds_bytes[c], stream);
+        e = P.fold_wide[c] ? launch_output_fold_wide(kClassMp[c], P.compute, P.state_bf16 != 0, prm, un,
+                                                     P.fold_count[c], stream)
+                           : launch_output_fold(kClassMp[c], P.compute, P.fold_s[c], P.state_bf16 != 0, prm, un,
+                                                P.fold_count[c], P.fold_lds_bytes[c], stream);
         if (e != hipSuccess) return hip_fail(e, "output fold launch");
         tl.done();
         break;

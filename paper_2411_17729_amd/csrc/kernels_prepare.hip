@@ -420,14 +420,17 @@ __global__ void k_pack_fold(const OpDev* ops, const double* gw, uint16_t* gc) {
   const OpDev o = ops[blockIdx.y];
   if (o.fold_s <= 0) return;
   const int mp = o.mp, ks = mp / 32;
-  const int64_t n = ((int64_t)1 << o.fold_s) * 16 * mp;  // elements
+  // elements: 2^s G_j of 16 x mp, or half as many paired operands
+  const int64_t n = (((int64_t)1 << o.fold_s) * 16 * mp) >> (o.fold_paired ? 1 : 0);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int v = (int)(e & 7);
     const int64_t chunk = e >> 3;
     const int lane = (int)(chunk & 63);
     const int64_t jt = chunk >> 6;
     const int t = (int)(jt % ks), j = (int)(jt / ks);
-    const int row = j * 16 + (lane & 15), col = 32 * t + 8 * (lane >> 4) + v;
+    // operand j: G_j, or G_{2j} (rows 0..7) over G_{2j+1} (rows 8..15)
+    const int row = o.fold_paired ? (2 * j + ((lane & 15) >> 3)) * 16 + (lane & 7) : j * 16 + (lane & 15);
+    const int col = 32 * t + 8 * (lane >> 4) + v;
     gc[o.fold_gc + e] = f64_to_bf16_bits(gw[o.fold_gw + (int64_t)row * mp + col]);
   }
 }

@@ -63,7 +63,10 @@ struct OpDev {
   // packed in operand order in the compute type at fold_gc; fold_s = 0 if none
   int32_t fold_s;
   int64_t fold_gw, fold_gc;
-  int32_t fold_k0, reserved2;
+  int32_t fold_k0;
+  // 1: the G_j are packed two lags to an operand (rows 0..7 G_{2i}, rows 8..15
+  // G_{2i+1}; q <= 8) for the six-stage fold of two 32-lag ranges
+  int32_t fold_paired;
   // exponential discretization: scratch of three zn x zn FP64 matrices at zx
   // (zn = m + p; the augmented matrix, then the Taylor and squaring
   // ping-pong), and the squarings zsq chosen from its norm; zx = -1 if none
@@ -336,6 +339,14 @@ hipError_t launch_output_fold(int mp, int ct, int s, bool xb, const StageParams&
 // Packs the FP64 G_j of every operator with a fold (16 x mp blocks) into the
 // compute type in operand order.
 hipError_t launch_pack_fold(const OpDev* ops, int n_ops, const double* gw, void* gc, int ct, hipStream_t s);
+// Output pass with six stages folded in (padded m 256, q <= 8, p <= 64, BF16):
+// 64 lags as two ranges of 32, G_j paired two to an operand; units carry the
+// range's first lag (0 or 32) in their last field and y is zeroed first (so
+// the launch is a fill kernel and the fold, on the same stream).
+bool fold_wide_supported(int mp, int ct, int q, int p);
+size_t fold_wide_lds();
+hipError_t launch_output_fold_wide(int mp, int ct, bool xb, const StageParams& prm, const FoldUnit* units,
+                                   int n_units, hipStream_t st);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);

@@ -17,9 +17,9 @@ from tests.test_gpu_pair import _workload
 
 pytestmark = pytest.mark.gpu
 
-# (m, p, q, L, N): padded m 256 (input pass to stage 5, the pair (6, 7), the
-# fold of 8..11: 16 lags of 256 rows) and 128 (input pass to stage 5, the fold
-# of 6..9); L not a multiple of 16, m below the padded size
+# (m, p, q, L, N): padded m 256 (input pass to stage 5, then q <= 8: the fold
+# of 6..11, 64 lags of 64 rows in two ranges) and 128 (input pass to stage 5,
+# the fold of 6..9); L not a multiple of 16, m below the padded size
 SPEC = [(256, 8, 8, 4096, 11), (256, 8, 8, 3001, 11), (200, 8, 4, 2500, 11),
         (128, 4, 3, 1500, 9), (100, 4, 2, 1999, 9)]
 
@@ -53,7 +53,7 @@ def test_fold_matches_oracle(u_dtype, zero_d):
     yu, iu, _ = _run(wl, u_dtype, fold_stages=-1)
     print("fold stages", info["fold_stages"], "launches", info["fold_launches"], "pairs",
           info["pair_launches"], flush=True)
-    assert info["fold_stages"] == 4 and info["fold_launches"] == 2 and info["pair_launches"] == 1
+    assert info["fold_stages"] == 6 and info["fold_launches"] == 2 and info["pair_launches"] == 0
     assert iu["fold_launches"] == 0 and iu["pair_launches"] == 5
     if u_dtype == "bf16":
         _bf16_inputs(wl, u)
@@ -69,14 +69,20 @@ def test_fold_matches_oracle(u_dtype, zero_d):
 
 # fold depths: (spec, tuning, expected (fold_stages, fold k0 of the class))
 DEPTHS = {
-    # padded m 256, last stage 13, input pass to 5: s = 4 at k0 = 10 after the
-    # pairs (6, 7), (8, 9); s = 2 at k0 = 12 after three pairs
-    "s4": ([(256, 8, 8, 9000, 13), (230, 8, 5, 8500, 13)], {}, 4),
+    # padded m 256, last stage 13, input pass to 5: q <= 8 takes s = 6 at k0 =
+    # 8 after the pair (6, 7); s = 4 at k0 = 10 after the pairs (6, 7), (8, 9);
+    # s = 2 at k0 = 12 after three pairs; q = 9 stops at s = 4
+    "s6": ([(256, 8, 8, 9000, 13), (230, 8, 5, 8500, 13)], {}, 6),
+    "s4": ([(256, 8, 8, 9000, 13), (230, 8, 5, 8500, 13)], {"fold_stages": 4}, 4),
+    "s4_q9": ([(256, 8, 9, 9000, 13), (230, 8, 5, 8500, 13)], {}, 4),
     "s2": ([(256, 8, 8, 9000, 13), (230, 8, 5, 8500, 13)], {"fold_stages": 2}, 2),
     # padded m 128, last stage 10: s = 5 at k0 = 6, 32 lags of 64 rows
     "s5": ([(128, 4, 3, 2000, 10), (90, 4, 16, 1100, 10)], {}, 5),
     # pairs off: s = 3 at k0 = 10 after single stages 6..9
     "s3_no_pairs": ([(256, 8, 8, 5000, 12), (256, 8, 2, 4800, 12)], {"fold_stages": 3, "pair_stages": 1}, 3),
+    # s = 6 at k0 = 6 straight after the input pass; columns of 33 to 47
+    # blocks (the range from lag 32 reads the 1 to 15 blocks that reach it)
+    "s6_short": ([(256, 8, 8, 3001, 11), (256, 8, 1, 2100, 11), (200, 8, 7, 2500, 11)], {}, 6),
 }
 
 
@@ -107,12 +113,13 @@ def test_fold_bf16_state():
         assert e <= 2e-2 and d <= 1e-2, (i, e, d)
 
 
-@pytest.mark.parametrize("case", ["q16_p64", "q1_p1", "p65"])
+@pytest.mark.parametrize("case", ["q16_p64", "q1_p1", "q8_p64", "p65"])
 def test_fold_limits(case):
-    # q = 16 and p = 64 (the largest the fold takes), q = p = 1, and p = 65,
-    # where the class keeps its tail pair
+    # q = 16 and p = 64 (the largest the fold takes), q = p = 1 and q = 8, p = 64
+    # (six stages), and p = 65, where the class keeps its tail pair
     spec = {"q16_p64": [(256, 64, 16, 3000, 11), (250, 64, 16, 2100, 11)],
             "q1_p1": [(256, 1, 1, 3000, 11), (256, 1, 1, 2050, 11)],
+            "q8_p64": [(256, 64, 8, 3000, 11), (256, 64, 8, 2050, 11)],
             "p65": [(256, 65, 4, 3000, 11), (256, 65, 4, 2500, 11)]}[case]
     wl = _workload(74, spec=spec)
     y, info, _ = _run(wl)
@@ -156,9 +163,9 @@ def test_fold_plan_accounting():
     nbytes = flops = 0.0
     for s_ in wl.seqs:
         m, q = wl.sets[s_.param_set].m, wl.sets[s_.param_set].C.shape[0]
-        k0 = 8 if m > 128 else 6
+        k0, nl = 6, 64 if m > 128 else 16  # six stages at padded m 256 (q <= 8), four at 128
         nbytes += s_.L * (4 * m + 4 * q)
-        lags = np.minimum(16, np.arange(s_.L) // (1 << k0) + 1)
+        lags = np.minimum(nl, np.arange(s_.L) // (1 << k0) + 1)
         flops += 2.0 * q * m * float(lags.sum())
     assert math.isclose(info["fold_bytes"], nbytes, rel_tol=1e-12)
     assert math.isclose(info["fold_flops"], flops, rel_tol=1e-12)
