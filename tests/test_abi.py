@@ -117,11 +117,11 @@ def test_tuning_is_validated(lib):
                 B.make_tuning(pair_stages=-1), B.make_tuning(pair_blocks=3),
                 B.make_tuning(pair_blocks=257), B.make_tuning(input_split=2),
                 B.make_tuning(state_bf16=2), B.make_tuning(state_bf16=-1),
-                B.make_tuning(fold_stages=1), B.make_tuning(fold_stages=6), B.make_tuning(fold_stages=-2)):
+                B.make_tuning(fold_stages=1), B.make_tuning(fold_stages=7), B.make_tuning(fold_stages=-2)):
         assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(bad)) == 0
     for t in (B.make_tuning(pair_stages=1), B.make_tuning(pair_blocks=4), B.make_tuning(pair_blocks=256),
               B.make_tuning(input_split=1), B.make_tuning(state_bf16=1), B.make_tuning(fold_stages=-1),
-              B.make_tuning(fold_stages=2), B.make_tuning(fold_stages=5)):
+              B.make_tuning(fold_stages=2), B.make_tuning(fold_stages=5), B.make_tuning(fold_stages=6)):
         assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
     for sk in (B.SSM_STAGE_RESIDENT, B.SSM_STAGE_CHAIN):  # FP32 only, not FP64 (compute 0)
         t = B.make_tuning(stage_kernel=sk, chain_blocks=3)
