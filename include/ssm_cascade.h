@@ -174,10 +174,9 @@ typedef struct {
    * FP64 during prepare, then rounded once to BF16), x the state after the
    * stages before k0: one pass that reads the state once and writes y in place
    * of the last s stages. At padded m 256 with q <= 8, s = 6: two lags share
-   * an MFMA operand (G_{2i} over G_{2i+1}), the 64 lags run as two ranges of
-   * 32 in separate workgroups, and both add into y after it is zeroed (at
-   * most two additions onto zero per output, so the sum does not depend on
-   * their order); the range from lag 32 reads only the blocks it needs.
+   * an MFMA operand (G_{2i} over G_{2i+1}) and the 64 lags are split over
+   * the waves of one workgroup, which add their partial outputs in a fixed
+   * order (so the result does not depend on timing) before y is stored.
    * 0: automatic (the largest s the LDS holds: 6 at padded m 256 and q <= 8,
    * else 4; 5 at 128; with the stages before it pairing up), -1: off, 2..6:
    * at most that many. */

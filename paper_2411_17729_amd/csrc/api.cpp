@@ -159,7 +159,7 @@ struct ssm_plan_s {
   // output pass with the last stages folded in: per class the first folded
   // stage and their number (0: none), workgroup units, LDS bytes
   int fold_k0[4] = {0, 0, 0, 0}, fold_s[4] = {0, 0, 0, 0};
-  bool fold_wide[4] = {false, false, false, false};  // six stages, paired lags, two ranges
+  bool fold_wide[4] = {false, false, false, false};  // six stages, paired lags, lags split over waves
   std::vector<FoldUnit> fold_units;
   int fold_start[4] = {0, 0, 0, 0}, fold_count[4] = {0, 0, 0, 0};
   size_t fold_lds_bytes[4] = {0, 0, 0, 0};
@@ -687,12 +687,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
                      [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
     const int ncol = (1 << P.fold_k0[c]) / 16;
     if (P.fold_wide[c]) {
-      // two columns per workgroup (one workgroup per compute unit for the
-      // LDS), the range from lag 0 first (it has the most work)
-      for (int h = 0; h < 2; ++h)
-        for (int i : ids)
-          for (int c0 = 0; c0 < ncol; c0 += 2)
-            P.fold_units.push_back(FoldUnit{i, c0, std::min(2, ncol - c0), 32 * h});
+      // one column per workgroup: its eight waves split the 64 lags
+      for (int i : ids)
+        for (int c0 = 0; c0 < ncol; ++c0) P.fold_units.push_back(FoldUnit{i, c0, 1, 0});
       P.fold_lds_bytes[c] = fold_wide_lds();
     } else {
       for (int i : ids)
@@ -1855,7 +1852,11 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
       P->job_kind.push_back(1);
       any_fold = true;
     }
-    for (int t = 0; t < 5; ++t) {
+    // G_{2^t .. 2^(t+1) - 1} = G_{0 .. 2^t - 1} P_{k0 + t}, one doubling per
+    // folded stage (up to six)
+    int max_fold = 0;
+    for (const OpDev& o : P->ops) max_fold = std::max(max_fold, (int)o.fold_s);
+    for (int t = 0; t < max_fold; ++t) {
       start = (int)J.size();
       mx = mn = 0;
       for (const OpDev& o : P->ops) {

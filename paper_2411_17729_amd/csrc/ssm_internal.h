@@ -65,7 +65,7 @@ struct OpDev {
   int64_t fold_gw, fold_gc;
   int32_t fold_k0;
   // 1: the G_j are packed two lags to an operand (rows 0..7 G_{2i}, rows 8..15
-  // G_{2i+1}; q <= 8) for the six-stage fold of two 32-lag ranges
+  // G_{2i+1}; q <= 8) for the six-stage fold
   int32_t fold_paired;
   // exponential discretization: scratch of three zn x zn FP64 matrices at zx
   // (zn = m + p; the augmented matrix, then the Taylor and squaring
@@ -340,9 +340,9 @@ hipError_t launch_output_fold(int mp, int ct, int s, bool xb, const StageParams&
 // compute type in operand order.
 hipError_t launch_pack_fold(const OpDev* ops, int n_ops, const double* gw, void* gc, int ct, hipStream_t s);
 // Output pass with six stages folded in (padded m 256, q <= 8, p <= 64, BF16):
-// 64 lags as two ranges of 32, G_j paired two to an operand; units carry the
-// range's first lag (0 or 32) in their last field and y is zeroed first (so
-// the launch is a fill kernel and the fold, on the same stream).
+// one column per workgroup, G_j paired two to an operand and the 64 lags split
+// over its eight waves, which sum their partial outputs in LDS before y is
+// stored once.
 bool fold_wide_supported(int mp, int ct, int q, int p);
 size_t fold_wide_lds();
 hipError_t launch_output_fold_wide(int mp, int ct, bool xb, const StageParams& prm, const FoldUnit* units,

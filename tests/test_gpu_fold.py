@@ -113,6 +113,26 @@ def test_fold_bf16_state():
         assert e <= 2e-2 and d <= 1e-2, (i, e, d)
 
 
+@pytest.mark.parametrize("p", [8, 64])
+def test_fold_six_long_memory(p):
+    # small step (long memory): G_j for j >= 32 of the six-stage fold (lags
+    # 2048 .. 4032 at k0 = 6) are far from zero, and with D = 0 the rows they
+    # reach (l >= 2048) carry only the state part, checked on their own
+    from paper_2411_17729_amd import workloads as W
+    rng = np.random.default_rng(75)
+    m, q, L, N = 256, 8, 3000, 11
+    A, _ = W.hippo_legs(m)
+    ps = W.ParamSet(A, rng.standard_normal((m, p)) / math.sqrt(m), rng.standard_normal((q, m)) / math.sqrt(m),
+                    np.zeros((q, p)))
+    wl = W.Workload("fold6", [ps], [W.Sequence(0, 1e-3, L, N, rng.standard_normal((L, p)))])
+    y, info, _ = _run(wl)
+    assert info["fold_stages"] == 6 and info["fold_launches"] == 1
+    ref = _oracle(wl)[0]
+    late = rel_err(y[0][2048:], ref[2048:])
+    print("p", p, "rel", f"{rel_err(y[0], ref):.2e}", "rows from 2048", f"{late:.2e}", flush=True)
+    assert late <= 2e-2 and rel_err(y[0], ref) <= 2e-2
+
+
 @pytest.mark.parametrize("case", ["q16_p64", "q1_p1", "q8_p64", "p65"])
 def test_fold_limits(case):
     # q = 16 and p = 64 (the largest the fold takes), q = p = 1 and q = 8, p = 64
