@@ -9,7 +9,8 @@ for a reader holding the paper (Beylkin, arXiv 2411.17729) next to it:
 * ``trapezoid``        -- the trapezoidal discretization of §1 (after eq. (1.2)).
 * ``zoh``              -- the exponential discretization named in §5:
   Abar = exp(delta A) and the matching Bbar (reading below).
-* ``recursion``        -- the discrete LTI recursion, eq. (1.2), x_{-1} = 0.
+* ``recursion``        -- the discrete LTI recursion, eq. (1.2), from x_{-1} = 0 or a
+  given initial state.
 * ``powers``           -- Abar, Abar^2, Abar^4, ... by repeated squaring (end of §2).
 * ``impulse_response`` / ``truncated_sum`` -- the convolution sum eq. (3.1)
   restricted to the lags that the degree-(2^{N+1}-1) polynomial H_N of
@@ -177,16 +178,18 @@ def zoh_adjoint(A, B, delta, gAbar, gBbar):
 # --------------------------------------------------------------------------
 # The recursion, eq. (1.2)
 # --------------------------------------------------------------------------
-def recursion(Abar, Bbar, C, D, u):
-    """x_n = Abar x_{n-1} + Bbar u_n, y_n = C x_n + D u_n, with x_{-1} = 0.
+def recursion(Abar, Bbar, C, D, u, x0=None):
+    """x_n = Abar x_{n-1} + Bbar u_n, y_n = C x_n + D u_n, eq. (1.2).
 
+    The state before the first step is x_{-1} = x0 (zero when x0 is None), the
+    initial condition that the problem statement of §1 sets to zero.
     Returns (y, x) with y of shape (L, q) and x of shape (L, m).
     """
     Abar, Bbar, C, D = _f64(Abar), _f64(Bbar), _f64(C), _f64(D)
     u = _as_matrix_u(u)
     L = u.shape[0]
     m = Abar.shape[0]
-    x = np.zeros(m)
+    x = np.zeros(m) if x0 is None else _f64(x0).reshape(m).copy()
     xs = np.empty((L, m))
     for n in range(L):
         x = Abar @ x + Bbar @ u[n]
@@ -239,12 +242,32 @@ def impulse_response(Abar, Bbar, C, T):
     return h
 
 
-def truncated_sum(Abar, Bbar, C, D, u, N):
+def free_response(Abar, C, x0, L, N):
+    """z_l = C Abar^(l+1) x0 for l < min(L, T), zero from T on, T = 2^(N+1).
+
+    The part of the output that an initial state x_{-1} = x0 contributes. Unrolling
+    eq. (1.2) gives x_l = Abar^(l+1) x_{-1} + sum_{j<=l} Abar^j Bbar u_{l-j}, i.e.
+    x_{-1} acts as one more input Abar x_{-1} at l = 0, and the degree-(T-1)
+    polynomial H_N of eq. (2.2) keeps its lags l < T. Computed by
+    w_0 = Abar x0, w_{l+1} = Abar w_l.
+    """
+    Abar, C = _f64(Abar), _f64(C)
+    m = Abar.shape[0]
+    z = np.zeros((L, C.shape[0]))
+    w = Abar @ _f64(x0).reshape(m)
+    for l in range(min(L, 1 << (N + 1))):
+        z[l] = C @ w
+        w = Abar @ w
+    return z
+
+
+def truncated_sum(Abar, Bbar, C, D, u, N, x0=None):
     """y_l = sum_{j=0}^{min(l, T-1)} C Abar^j Bbar u_{l-j} + D u_l with T = 2^(N+1).
 
     This is eq. (3.1) with the lags cut where the polynomial H_N of
     eq. (2.2)/(2.3) stops (degree T-1). When T >= L nothing is cut and this
-    equals ``recursion``.
+    equals ``recursion``. With an initial state x0, ``free_response`` is added
+    (then with T >= L this equals ``recursion`` from x_{-1} = x0).
     """
     u = _as_matrix_u(u)
     L = u.shape[0]
@@ -254,6 +277,8 @@ def truncated_sum(Abar, Bbar, C, D, u, N):
     y = u @ _f64(D).T
     for j in range(Tu):
         y[j:] += u[: L - j] @ h[j].T
+    if x0 is not None:
+        y += free_response(Abar, C, x0, L, N)
     return y
 
 
