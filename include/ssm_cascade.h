@@ -311,6 +311,25 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
 /* Number of doubles of the flat parameter-gradient buffer of a plan. */
 size_t ssm_cascade_param_grad_numel(ssm_plan plan);
 
+/* Forward apply from a nonzero initial state x_{-1} = x0 (eq. (1.2), whose
+ * problem statement in §1 takes x_{-1} = 0; ssm_cascade_apply is this with
+ * x0 = 0). Unrolled, x_l = Abar^(l+1) x_{-1} + sum_{j<=l} Abar^j Bbar u_{l-j},
+ * so x_{-1} enters as one more input Abar x_{-1} at l = 0 and the cascade
+ * keeps its lags l < 2^{N+1}: y_l gains C Abar^(l+1) x0 for l < 2^{N+1}, and
+ * equals the recursion from x0 whenever L <= 2^{N+1}.
+ *   x0: device, the plan's state type (double for SSM_F64 plans, float
+ *       otherwise), the sequences' states packed in sequence order, m_s
+ *       entries each; x0_numel must be their sum. Read during the call only.
+ *   u, y: as for ssm_cascade_apply.
+ * Errors: SSM_E_INVALID (x0 NULL or x0_numel wrong, and the checks of
+ * ssm_cascade_apply), SSM_E_UNSUPPORTED for persistent plans and plans that
+ * keep a BF16 state, SSM_E_HIP on a launch failure. Cost: one extra small
+ * launch of min(2^kry, L) dependent FP64 matvecs per sequence (kry: the
+ * stages folded into the plan's input pass). */
+ssm_status ssm_cascade_apply_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                const void* x0, size_t x0_numel, void* y, size_t y_numel,
+                                hipStream_t stream);
+
 /* The plain recursion x_n = Abar x_{n-1} + Bbar u_n, y_n = C x_n + D u_n of
  * eq. (1.2) on the GPU (one workgroup per sequence, L dependent steps), for
  * comparison with the cascade. Same arguments as ssm_cascade_apply; runs in

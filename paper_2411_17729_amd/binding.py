@@ -93,7 +93,7 @@ def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM
 _lib = None
 
 EXPORTS = [
-    "ssm_cascade_workspace_bytes", "ssm_cascade_prepare", "ssm_cascade_apply",
+    "ssm_cascade_workspace_bytes", "ssm_cascade_prepare", "ssm_cascade_apply", "ssm_cascade_apply_x0",
     "ssm_cascade_backward", "ssm_cascade_param_grad_numel", "ssm_cascade_recursion",
     "ssm_cascade_get_power", "ssm_cascade_get_bbar", "ssm_cascade_plan_info",
     "ssm_cascade_timing_enable", "ssm_cascade_timing_read", "ssm_cascade_destroy",
@@ -128,6 +128,8 @@ def load(path=LIB_PATH):
     lib.ssm_cascade_graph_destroy.argtypes = [vp]
     lib.ssm_cascade_apply.restype = i32
     lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
+    lib.ssm_cascade_apply_x0.restype = i32
+    lib.ssm_cascade_apply_x0.argtypes = [vp, vp, i32, sz, vp, sz, vp, sz, vp]
     lib.ssm_cascade_recursion.restype = i32
     lib.ssm_cascade_recursion.argtypes = [vp, vp, i32, sz, vp, sz, vp]
     lib.ssm_cascade_backward.restype = i32
@@ -201,6 +203,11 @@ def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every,
 def ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
     _check(load().ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
            "ssm_cascade_apply")
+
+
+def ssm_cascade_apply_x0(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, y_ptr, y_numel, stream):
+    _check(load().ssm_cascade_apply_x0(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, y_ptr, y_numel,
+                                       stream), "ssm_cascade_apply_x0")
 
 
 def ssm_cascade_recursion(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):

@@ -104,12 +104,20 @@ class CascadePlan:
         self.with_backward = with_backward
 
     # -- forward ---------------------------------------------------------
-    def apply(self, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def apply(self, u: torch.Tensor, out: Optional[torch.Tensor] = None,
+              x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y of every sequence; x0 (optional) holds x_{-1} of each sequence, packed."""
         u = self._check_u(u)
         if out is None:
             out = torch.empty(self.layout.y_numel, dtype=self.state_dtype, device=self.device)
-        B.ssm_cascade_apply(self.plan, u.data_ptr(), self._u_code(u), u.numel(), out.data_ptr(),
-                            out.numel(), _stream())
+        if x0 is None:
+            B.ssm_cascade_apply(self.plan, u.data_ptr(), self._u_code(u), u.numel(), out.data_ptr(),
+                                out.numel(), _stream())
+        else:
+            if x0.dtype != self.state_dtype or not x0.is_contiguous() or x0.device != self.device:
+                raise ValueError("x0 must be a contiguous device tensor of the state dtype")
+            B.ssm_cascade_apply_x0(self.plan, u.data_ptr(), self._u_code(u), u.numel(), x0.data_ptr(),
+                                   x0.numel(), out.data_ptr(), out.numel(), _stream())
         return out
 
     def recursion(self, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:

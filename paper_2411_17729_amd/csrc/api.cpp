@@ -2015,13 +2015,25 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   return SSM_OK;
 }
 
-ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
-                             void* y, size_t y_numel, hipStream_t stream) {
+// the forward apply; x0 (nullable) is x_{-1} of every sequence, packed in
+// sequence order, m of each, in the plan's state type
+static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel, const void* x0,
+                             size_t x0_numel, void* y, size_t y_numel, hipStream_t stream) {
   g_last_error.clear();
   if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
   ssm_plan_s& P = *plan;
   ssm_status st = check_io(P, u, u_dtype, u_numel, y, y_numel, "y");
   if (st != SSM_OK) return st;
+  if (x0) {
+    size_t want = 0;
+    for (int i = 0; i < P.n_seq; ++i) want += (size_t)P.ops[P.seqs[i].op].m;
+    if (x0_numel != want)
+      return fail(SSM_E_INVALID, "x0_numel %zu, the sequences' states need %zu", x0_numel, want);
+    if (P.launch == SSM_LAUNCH_PERSISTENT)
+      return fail(SSM_E_UNSUPPORTED, "an initial state needs per-stage launches (the plan is persistent)");
+    if (P.state_bf16)
+      return fail(SSM_E_UNSUPPORTED, "an initial state needs an FP32 or FP64 state (the plan keeps BF16)");
+  }
   if (P.launch == SSM_LAUNCH_PERSISTENT && P.persist_res) {
     unsigned char* meta = P.ws + P.r_meta.off;
     RPersistParams pp{};
@@ -2106,6 +2118,13 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       prm.skip_kry = 1;
       k_begin = P.class_min_kry[c];
     }
+    if (x0) {  // x_{-1}: Abar^(l+1) x0 into the rows the first pass has finished
+      unsigned char* meta = P.ws + P.r_meta.off;
+      e = launch_inject_x0(kClassMp[c], P.state_f64 != 0, reinterpret_cast<const SeqDev*>(meta + P.m_seqs), P.n_seq,
+                           reinterpret_cast<const OpDev*>(meta + P.m_ops), P.at<double>(P.r_pw), x0,
+                           P.ws + P.r_x0.off, P.ws + P.r_x1.off, stream);
+      if (e != hipSuccess) return hip_fail(e, "initial state launch");
+    }
     // the input of stage kk is in buffer kk % 2 until the first stage pair;
     // from there on every sequence of the class runs every stage, and the
     // buffers simply alternate per launch
@@ -2143,6 +2162,21 @@ ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     }
   }
   return SSM_OK;
+}
+
+ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                             void* y, size_t y_numel, hipStream_t stream) {
+  return apply_impl(plan, u, u_dtype, u_numel, nullptr, 0, y, y_numel, stream);
+}
+
+ssm_status ssm_cascade_apply_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                const void* x0, size_t x0_numel, void* y, size_t y_numel,
+                                hipStream_t stream) {
+  if (!x0) {
+    g_last_error.clear();
+    return fail(SSM_E_INVALID, "x0 is NULL (ssm_cascade_apply runs from a zero state)");
+  }
+  return apply_impl(plan, u, u_dtype, u_numel, x0, x0_numel, y, y_numel, stream);
 }
 
 ssm_status ssm_cascade_recursion(ssm_plan plan, const void* u, ssm_dtype u_dtype,
