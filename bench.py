@@ -73,9 +73,10 @@ def _args():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f32"])
-    ap.add_argument("--state", default="f32", choices=["f32", "bf16"],
+    ap.add_argument("--state", default="bf16", choices=["f32", "bf16"],
                     help="state kept between the passes of a BF16 apply (bf16: where every pass "
-                         "supports it); the other choice is timed beside it")
+                         "supports it, the default: within the BF16 tolerance, errors in the line); "
+                         "the other choice is timed beside it")
     ap.add_argument("--workload", default="batched", choices=["batched", "backward", "ragged"],
                     help="batched: 16 x L=16384, m=256 forward (the headline line); backward: "
                          "8 x L=8192, m=128 FP32 gradients; ragged: 256 sequences of uneven L and m, "
