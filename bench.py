@@ -9,13 +9,16 @@ A step is one full forward pass over the batch: the input pass (Bbar u with
 the leading stages folded) and the remaining stage launches with the fused
 C x + D u output, inputs already in HBM, captured once as a HIP graph and
 replayed. The headline is the cascade with BF16 MFMA operands (FP32
-accumulation) and the state between passes in FP32 (--state bf16: in BF16);
+accumulation) and the state between passes in BF16 (--state f32: in FP32);
 the same apply with the other state type, the FP32-MFMA cascade and the
 plain FP32 recursion on the same GPU are measured beside it, each with its
-relative error against the FP64 oracle. Kernel statistics for the roofline
-come from a separate eager pass with per-launch HIP events. Prints one JSON
-line. --workload backward|ragged measures the gradient pass and the ragged
-persistent batch instead.
+relative error against the FP64 oracle, and the FP32 cascade is compared
+with the FP32 recursion at the same accuracy. Prepare (discretization and
+squarings) is timed on its own and end to end. Kernel statistics for the
+roofline come from a separate eager pass with per-launch HIP events. The
+CPU oracle leg runs first, in forked worker processes, before the GPU is
+initialised. Prints one JSON line. --workload backward|ragged measures the
+gradient pass and the ragged persistent batch instead.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype bf16|f32] [--state f32|bf16]
 """
@@ -93,6 +96,55 @@ def _args():
     return ap.parse_args()
 
 
+def _host_workers():
+    """Worker processes for the CPU oracle leg: the host's cores available to
+    this process, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_recursion_job(job):
+    """One sequence through the oracle: trapezoid discretization and the
+    recursion, numpy FP64, one BLAS thread (the pool supplies the parallelism)."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    A, Bm, C, D, delta, u = job
+    with threadpool_limits(limits=1):
+        Abar, Bbar = O.trapezoid(A, Bm, delta)
+        y, _ = O.recursion(Abar, Bbar, C, D, u)
+    return y
+
+
+def _oracle_grads_job(job):
+    """One sequence's gradients through the oracle (BPTT and the trapezoid adjoint)."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    A, Bm, C, D, delta, u, dy, N = job
+    with threadpool_limits(limits=1):
+        return O.grads_full(A, Bm, C, D, delta, u, dy, N)
+
+
+def cpu_oracle_leg(fn, jobs, seconds, workers):
+    """Runs fn over jobs in a pool of `workers` forked processes, a round of
+    `workers` jobs at a time, until the jobs run out or `seconds` have passed
+    after a round. Call before anything initialises the GPU (the children are
+    forked). Returns (results by job index, wall seconds, workers)."""
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    res = {}
+    with mp.get_context("fork").Pool(workers) as pool:
+        for r0 in range(0, len(jobs), workers):
+            idx = list(range(r0, min(len(jobs), r0 + workers)))
+            for i, out in zip(idx, pool.map(fn, [jobs[i] for i in idx], chunksize=1)):
+                res[i] = out
+            if time.perf_counter() - t0 >= seconds:
+                break
+    return res, time.perf_counter() - t0, workers
+
+
 def traffic_path(workload, dtype, state="f32"):
     suffix = "" if state == "f32" else f"_state_{state}"
     return os.path.join(ROOT, "profiles", f"stage_traffic_{workload}_{dtype}{suffix}.json")
@@ -123,21 +175,30 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2411_17729_amd import binding as B
-    from paper_2411_17729_amd import cascade as CC
     from paper_2411_17729_amd import workloads as W
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a ROCm GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    B.load()
     if args.workload == "backward":
         return bench_backward(args)
     if args.workload == "ragged":
         return bench_ragged(args)
 
     wl = W.batched(seed=args.seed)
+    # the CPU oracle leg runs first, in forked workers, before the GPU is touched
+    cpu = None
+    if not args.no_cpu:
+        ps0 = wl.sets[0]
+        jobs = [(ps0.A, ps0.B, ps0.C, ps0.D, s.delta, s.u.astype(np.float32).astype(np.float64))
+                for s in wl.seqs]
+        cpu = cpu_oracle_leg(_oracle_recursion_job, jobs, args.cpu_seconds, _host_workers())
+
+    from paper_2411_17729_amd import binding as B
+    from paper_2411_17729_amd import cascade as CC
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    B.load()
     s0 = wl.seqs[0]
     ps = wl.sets[0]
     wname = f"hippo_m{ps.m}_p{ps.p}_q{ps.q}_B{len(wl.seqs)}_L{s0.L}_N{s0.N}"
@@ -214,7 +275,11 @@ def main():
 
     # ---------------- headline: the cascade in the chosen dtype ----------------
     sb = int(args.dtype == "bf16" and args.state == "bf16")
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
     plan = CC.plan_for_workload(wl, compute=args.dtype, state_bf16=sb)
+    torch.cuda.synchronize()
+    plan_ms_first = (time.perf_counter() - t_plan) * 1e3
     y_main, ms_main, kern = run(plan, "apply", K, Wm, timing_kind=dominant_kernel(plan.info())[1],
                                 graph=True)
     state_name = {B.SSM_F32: "f32", B.SSM_BF16: "bf16"}[plan.info()["state_dtype"]]
@@ -232,6 +297,25 @@ def main():
         "state": state_name,
     }
     ys = {args.dtype: CC.unpack_y(wl, y_main)}
+
+    # prepare (discretization, squarings, packing; FP64 on the GPU, one
+    # synchronization at its end): host wall time of ssm_cascade_prepare on the
+    # plan's workspace, median of 5, and the first plan built end to end
+    # (workspace allocation and parameter upload included)
+    prep = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t_p = time.perf_counter()
+        plan.prepare_again()
+        prep.append((time.perf_counter() - t_p) * 1e3)
+    prep_ms = sorted(prep)[len(prep) // 2]
+    out["prepare_ms"] = round(prep_ms, 3)
+    out["prepare"] = {"median_ms": round(prep_ms, 3), "runs_ms": [round(x, 3) for x in prep],
+                      "first_plan_ms": round(plan_ms_first, 3),
+                      "end_to_end_ms": round(prep_ms + ms_main, 4),
+                      "end_to_end_output_steps_per_s": round(total_steps / ((prep_ms + ms_main) * 1e-3), 1),
+                      "note": "ssm_cascade_prepare on the plan's own workspace (host wall time, it "
+                              "synchronizes its stream); end_to_end = prepare + one apply"}
 
     # ---------------- comparators on the same GPU ----------------
     if not args.no_compare:
@@ -261,40 +345,35 @@ def main():
         ys["recursion_f32"] = CC.unpack_y(wl, y_r)
         out["recursion_f32"] = {"value": round(total_steps / (ms_r * 1e-3), 1),
                                 "ms_per_step": round(ms_r, 4), "steps": rsteps}
-        out["speedup_vs_recursion"] = round(ms_r / ms_main, 2)
+        # the FP32 cascade against the FP32 recursion: the same operand precision
+        # and comparable error against FP64 (both in rel_err_vs_fp64)
+        ms_f32 = ms_o if other == "f32" else ms_main
+        out["speedup_vs_recursion_same_accuracy"] = round(ms_r / ms_f32, 2)
+        if args.dtype != "f32":
+            # the headline (BF16 operands) against the FP32 recursion: different accuracies
+            out["speedup_vs_recursion_cross_dtype"] = round(ms_r / ms_main, 2)
 
     # ---------------- CPU oracle: baseline timing and FP64 reference ----------------
-    if not args.no_cpu:
-        import oracle as O
-        from threadpoolctl import threadpool_limits
-
-        t_start = time.perf_counter()
-        done = []
-        refs = {}
-        with threadpool_limits(limits=1):
-            for i, s in enumerate(wl.seqs):
-                Abar, Bbar = O.trapezoid(ps.A, ps.B, s.delta)
-                yref, _ = O.recursion(Abar, Bbar, ps.C, ps.D, s.u.astype(np.float32).astype(np.float64))
-                refs[i] = yref
-                done.append(i)
-                if time.perf_counter() - t_start >= args.cpu_seconds:
-                    break
-        t_cpu = time.perf_counter() - t_start
+    if cpu is not None:
+        refs, t_cpu, workers = cpu
+        done = sorted(refs)
         steps_cpu = sum(wl.seqs[i].L for i in done)
         out["cpu_baseline"] = {
-            "value": round(steps_cpu / t_cpu, 1), "unit": "output steps/s", "cores": 1,
+            "value": round(steps_cpu / t_cpu, 1), "unit": "output steps/s", "cores": workers,
             "kind": "oracle",
-            "sample": f"{len(done)} of {len(wl.seqs)} sequences in full (L={s0.L}), "
-                      f"oracle.trapezoid + oracle.recursion, numpy FP64, 1 BLAS thread, {t_cpu:.1f} s"}
+            "sample": f"{len(done)} of {len(wl.seqs)} sequences in full (L={s0.L}), oracle.trapezoid + "
+                      f"oracle.recursion, numpy FP64, one sequence per worker process with one BLAS "
+                      f"thread, {workers} workers, {t_cpu:.2f} s wall"}
         rel = {}
         for name, yl in ys.items():
             ey = max(float(np.linalg.norm(yl[i] - refs[i]) / np.linalg.norm(refs[i])) for i in done)
             du = {i: wl.seqs[i].u.astype(np.float32).astype(np.float64) @ ps.D.T for i in done}
             ex = max(float(np.linalg.norm((yl[i] - du[i]) - (refs[i] - du[i])) /
                            np.linalg.norm(refs[i] - du[i])) for i in done)
-            rel[name] = {"y": ey, "state": ex}
+            rel[name] = {"y": ey, "Cx": ex}
         out["rel_err_vs_fp64"] = {k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()} for k, v in rel.items()}
-        out["rel_err_sample"] = f"sequences {done}"
+        out["rel_err_sample"] = (f"sequences {done}; y: the output, Cx: y - D u (the part that "
+                                 f"passes through the state)")
 
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -336,17 +415,33 @@ def _stage_flops(wl, ks=None):
     return tot
 
 
+def _gpu_init():
+    import torch
+    from paper_2411_17729_amd import binding as B
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    B.load()
+
+
 def bench_backward(args):
     """Gradients of sum(dy * y) for 8 sequences x L = 8192, m = 128 (FP32)."""
     import numpy as np
     import torch
-    from paper_2411_17729_amd import binding as B
-    from paper_2411_17729_amd import cascade as CC
     from paper_2411_17729_amd import workloads as W
 
     wl = W.backward(seed=args.seed)
     ps = wl.sets[0]
     s0 = wl.seqs[0]
+    cpu = None
+    if not args.no_cpu:  # before the GPU is touched (forked workers)
+        jobs = [(ps.A, ps.B, ps.C, ps.D, s.delta, s.u.astype(np.float32).astype(np.float64),
+                 d.astype(np.float32).astype(np.float64), s.N) for s, d in zip(wl.seqs, wl.dy)]
+        cpu = cpu_oracle_leg(_oracle_grads_job, jobs, args.cpu_seconds, _host_workers())
+    _gpu_init()
+    from paper_2411_17729_amd import binding as B
+    from paper_2411_17729_amd import cascade as CC
     plan = CC.plan_for_workload(wl, compute="f32", with_backward=True)
     u = CC.pack_u(wl, dtype=torch.float32)
     dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in wl.dy]), device="cuda").float()
@@ -376,31 +471,27 @@ def bench_backward(args):
         "breakdown_ms": {"forward_and_recompute_stages": round(t_fwd, 4), "adjoint_stages": round(t_adj, 4),
                          "reductions": round(t_red, 4), "launches": [n_fwd, n_adj, n_red]},
     }
-    if not args.no_cpu:
-        import time
-        import oracle as O
-        from threadpoolctl import threadpool_limits
-        t_start = time.perf_counter()
-        acc = {k: 0.0 for k in "ABCD"}
-        dus = []
-        with threadpool_limits(limits=1):
-            for s, d in zip(wl.seqs, wl.dy):
-                g = O.grads_full(ps.A, ps.B, ps.C, ps.D, s.delta, s.u.astype(np.float32).astype(np.float64),
-                                 d.astype(np.float32).astype(np.float64), s.N)
-                for k in "ABCD":
-                    acc[k] = acc[k] + g[k]
-                dus.append(g["u"])
-        t_cpu = time.perf_counter() - t_start
-        out["cpu_baseline"] = {"value": round(wl.total_steps / t_cpu, 1), "unit": "output steps/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"all {len(wl.seqs)} sequences, oracle.grads_full (BPTT + "
-                                         f"trapezoid adjoint), numpy FP64, 1 BLAS thread, {t_cpu:.1f} s"}
+    if cpu is not None:
+        res, t_cpu, workers = cpu
+        done = sorted(res)
+        out["cpu_baseline"] = {"value": round(sum(wl.seqs[i].L for i in done) / t_cpu, 1),
+                               "unit": "output steps/s", "cores": workers, "kind": "oracle",
+                               "sample": f"{len(done)} of {len(wl.seqs)} sequences, oracle.grads_full "
+                                         f"(BPTT + trapezoid adjoint), numpy FP64, one sequence per worker "
+                                         f"process with one BLAS thread, {workers} workers, {t_cpu:.2f} s wall"}
         du_h = du.double().cpu().numpy()
-        rel = {"du": float(np.linalg.norm(du_h - np.concatenate([x.reshape(-1) for x in dus])) /
-                           np.linalg.norm(np.concatenate([x.reshape(-1) for x in dus])))}
-        for j, k in enumerate("ABCD"):
-            gk = grads[0][j].cpu().numpy()
-            rel[f"d{k}"] = float(np.linalg.norm(gk - acc[k]) / np.linalg.norm(acc[k]))
+        off, rel = 0, {"du": 0.0}
+        for i, s in enumerate(wl.seqs):
+            n = s.L * ps.p
+            if i in res:
+                ref = res[i]["u"].reshape(-1)
+                rel["du"] = max(rel["du"], float(np.linalg.norm(du_h[off:off + n] - ref) / np.linalg.norm(ref)))
+            off += n
+        if len(done) == len(wl.seqs):  # the parameter gradients are sums over every sequence
+            for j, k in enumerate("ABCD"):
+                acc = sum(res[i][k] for i in done)
+                gk = grads[0][j].cpu().numpy()
+                rel[f"d{k}"] = float(np.linalg.norm(gk - acc) / np.linalg.norm(acc))
         out["rel_err_vs_fp64"] = {"f32": {k: float(f"{v:.3e}") for k, v in rel.items()}}
     plan.close()
     print(json.dumps(out), flush=True)
@@ -411,11 +502,29 @@ def bench_ragged(args):
     captured in a HIP graph and replayed; the backward graph likewise."""
     import numpy as np
     import torch
-    from paper_2411_17729_amd import binding as B
-    from paper_2411_17729_amd import cascade as CC
     from paper_2411_17729_amd import workloads as W
 
     wl = W.ragged(seed=args.seed)
+    order = sorted(range(len(wl.seqs)), key=lambda i: wl.seqs[i].L)
+    fwd_sample = order[::17]  # a spread of lengths and sizes
+    bwd_sample = sorted({order[0], order[len(order) // 3], order[2 * len(order) // 3], order[-1]})
+    cpu = cpu_bwd = None
+    if not args.no_cpu:  # before the GPU is touched (forked workers)
+        jobs, gjobs = [], []
+        for i in fwd_sample:
+            s = wl.seqs[i]
+            ps = wl.sets[s.param_set]
+            jobs.append((ps.A, ps.B, ps.C, ps.D, s.delta, s.u.astype(np.float32).astype(np.float64)))
+        for i in bwd_sample:
+            s = wl.seqs[i]
+            ps = wl.sets[s.param_set]
+            gjobs.append((ps.A, ps.B, ps.C, ps.D, s.delta, s.u.astype(np.float32).astype(np.float64),
+                          wl.dy[i].astype(np.float32).astype(np.float64), s.N))
+        cpu = cpu_oracle_leg(_oracle_recursion_job, jobs, args.cpu_seconds, _host_workers())
+        cpu_bwd = cpu_oracle_leg(_oracle_grads_job, gjobs, 1e9, _host_workers())
+    _gpu_init()
+    from paper_2411_17729_amd import binding as B
+    from paper_2411_17729_amd import cascade as CC
     plan = CC.plan_for_workload(wl, compute="bf16", with_backward=True)
     info = plan.info()
     u = CC.pack_u(wl, dtype=torch.float32)
@@ -431,6 +540,9 @@ def bench_ragged(args):
     with torch.cuda.stream(stream):
         ms_f = _timed(lambda: CC.CascadePlan.graph_launch(g_fwd, stream), K, Wm, stream)
         ms_b = _timed(lambda: CC.CascadePlan.graph_launch(g_bwd, stream), max(2, K // 5), 1, stream)
+    torch.cuda.synchronize()
+    du_h = du.double().cpu().numpy()
+    grads = [[t.cpu().numpy() for t in parts] for parts in plan.split_param_grads(gbuf)]
     # the persistent kernel alone (eager launch with event timing)
     plan.timing(True)
     plan.apply(u, out=y)
@@ -458,36 +570,41 @@ def bench_ragged(args):
         "backward": {"value": round(wl.total_steps / (ms_b * 1e-3), 1), "ms_per_step": round(ms_b, 4),
                      "graph": True},
     }
-    if not args.no_cpu:
-        import time
-        import oracle as O
-        from threadpoolctl import threadpool_limits
+    if cpu is not None:
         yh = CC.unpack_y(wl, y)
-        order = sorted(range(len(wl.seqs)), key=lambda i: wl.seqs[i].L)
-        t_start = time.perf_counter()
-        done, errs = [], []
-        with threadpool_limits(limits=1):
-            for i in order[::17]:  # a spread of lengths and sizes
-                s = wl.seqs[i]
-                ps = wl.sets[s.param_set]
-                Abar, Bbar = O.trapezoid(ps.A, ps.B, s.delta)
-                uq = s.u.astype(np.float32).astype(np.float64)
-                ref, _ = O.recursion(Abar, Bbar, ps.C, ps.D, uq)
-                done.append(i)
-                st = yh[i] - uq @ ps.D.T
-                sr = ref - uq @ ps.D.T
-                errs.append(float(np.linalg.norm(st - sr) / np.linalg.norm(sr)))
-                if time.perf_counter() - t_start >= args.cpu_seconds:
-                    break
-        t_cpu = time.perf_counter() - t_start
+        res, t_cpu, workers = cpu
+        done = [fwd_sample[j] for j in sorted(res)]
+        errs = []
+        for j in sorted(res):
+            i = fwd_sample[j]
+            s = wl.seqs[i]
+            ps = wl.sets[s.param_set]
+            du_i = s.u.astype(np.float32).astype(np.float64) @ ps.D.T
+            st, sr = yh[i] - du_i, res[j] - du_i
+            errs.append(float(np.linalg.norm(st - sr) / np.linalg.norm(sr)))
         steps_cpu = sum(wl.seqs[i].L for i in done)
-        out["cpu_baseline"] = {"value": round(steps_cpu / t_cpu, 1), "unit": "output steps/s", "cores": 1,
+        out["cpu_baseline"] = {"value": round(steps_cpu / t_cpu, 1), "unit": "output steps/s", "cores": workers,
                                "kind": "oracle",
                                "sample": f"{len(done)} of {len(wl.seqs)} sequences in full (every 17th by "
-                                         f"length), oracle.trapezoid + oracle.recursion, numpy FP64, "
-                                         f"1 BLAS thread, {t_cpu:.1f} s"}
-        out["rel_err_vs_fp64"] = {"bf16": {"state_max": float(f"{max(errs):.3e}")}}
-        out["rel_err_sample"] = f"sequences {done}"
+                                         f"length), oracle.trapezoid + oracle.recursion, numpy FP64, one "
+                                         f"sequence per worker process with one BLAS thread, {workers} "
+                                         f"workers, {t_cpu:.2f} s wall"}
+        rel = {"Cx_max": float(f"{max(errs):.3e}")}
+        gres, _, _ = cpu_bwd
+        uoff = np.cumsum([0] + [s.L * wl.sets[s.param_set].p for s in wl.seqs])
+        berr = {}
+        for j, i in enumerate(bwd_sample):
+            g = gres[j]
+            s = wl.seqs[i]
+            e = {"du": float(np.linalg.norm(du_h[uoff[i]:uoff[i + 1]] - g["u"].reshape(-1)) /
+                             np.linalg.norm(g["u"]))}
+            for jj, k in enumerate("ABCD"):
+                e[f"d{k}"] = float(np.linalg.norm(grads[s.param_set][jj] - g[k]) / np.linalg.norm(g[k]))
+            for k, v in e.items():
+                berr[k] = max(berr.get(k, 0.0), v)
+        rel["backward_max"] = {k: float(f"{v:.3e}") for k, v in berr.items()}
+        out["rel_err_vs_fp64"] = {"bf16": rel}
+        out["rel_err_sample"] = f"forward: sequences {done}; backward: sequences {bwd_sample}"
     plan.close()
     print(json.dumps(out), flush=True)
 

@@ -98,10 +98,23 @@ class CascadePlan:
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) // 256 * 256
+        self._cparams = cparams
+        self._ckpt_every = ckpt_every
+        self._nbytes = nbytes
         self.plan = B.ssm_cascade_prepare(layout.descs, cparams, self.disc, self.compute,
                                           with_backward, ckpt_every, self.tuning, self.ws_ptr,
                                           nbytes, _stream())
         self.with_backward = with_backward
+
+    def prepare_again(self):
+        """Runs ssm_cascade_prepare once more on this plan's parameters and
+        workspace (the discretization, squarings and packing are recomputed in
+        place, to the same values) and replaces the plan handle."""
+        old = self.plan
+        self.plan = B.ssm_cascade_prepare(self.layout.descs, self._cparams, self.disc, self.compute,
+                                          self.with_backward, self._ckpt_every, self.tuning,
+                                          self.ws_ptr, self._nbytes, _stream())
+        B.ssm_cascade_destroy(old)
 
     # -- forward ---------------------------------------------------------
     def apply(self, u: torch.Tensor, out: Optional[torch.Tensor] = None,

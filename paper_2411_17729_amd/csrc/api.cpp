@@ -2122,7 +2122,7 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       unsigned char* meta = P.ws + P.r_meta.off;
       e = launch_inject_x0(kClassMp[c], P.state_f64 != 0, reinterpret_cast<const SeqDev*>(meta + P.m_seqs), P.n_seq,
                            reinterpret_cast<const OpDev*>(meta + P.m_ops), P.at<double>(P.r_pw), x0,
-                           P.ws + P.r_x0.off, P.ws + P.r_x1.off, stream);
+                           P.ws + P.r_x0.off, P.ws + P.r_x1.off, P.ws + P.r_small.off, y, stream);
       if (e != hipSuccess) return hip_fail(e, "initial state launch");
     }
     // the input of stage kk is in buffer kk % 2 until the first stage pair;

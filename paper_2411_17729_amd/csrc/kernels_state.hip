@@ -9,13 +9,18 @@
 // remaining stages, linear in the state, carry it on like the rest. This pass
 // adds those rows: one workgroup per sequence forms w_0 = Abar x0, w_{l+1} =
 // Abar w_l in FP64 (thread e owns entry e) and adds w_l to row l of the state.
+// Where the first pass already ran every stage of a sequence and formed its
+// output (kry = last + 1), no later pass reads that state, so the free
+// response goes straight into the output instead: y_l += C w_l, y = C x + D u
+// being linear in the state.
 #include "ssm_internal.h"
 
 namespace ssmc {
 
 template <typename X>
 __global__ __launch_bounds__(256) void k_inject_x0(const SeqDev* seqs, const OpDev* ops, const double* pw,
-                                                   const X* x0, int mp_class, X* buf0, X* buf1) {
+                                                   const X* x0, int mp_class, X* buf0, X* buf1,
+                                                   const X* small, X* y) {
   __shared__ double w[2][256];
   const int s = blockIdx.x;
   const SeqDev sq = seqs[s];
@@ -28,6 +33,10 @@ __global__ __launch_bounds__(256) void k_inject_x0(const SeqDev* seqs, const OpD
   const int64_t R = sq.L < ((int64_t)1 << sq.kry) ? sq.L : ((int64_t)1 << sq.kry);
   const double* A = pw + o.pw;  // Abar, mp x mp, zero padded
   X* xb = (sq.kry & 1 ? buf1 : buf0) + sq.x_off;
+  // (kry = 0 never ends a sequence: its stages and output are still to run)
+  const bool to_y = sq.kry > 0 && sq.kry == sq.last + 1;
+  const X* cm = small + o.cout;  // C, q x mp, in the state type
+  X* yb = y + sq.y_off;
   w[0][e] = e < m ? (double)x0[off + e] : 0.0;
   __syncthreads();
   for (int64_t l = 0; l < R; ++l) {
@@ -36,26 +45,36 @@ __global__ __launch_bounds__(256) void k_inject_x0(const SeqDev* seqs, const OpD
     if (e < m) {
       const double* row = A + (int64_t)e * mp;
       for (int k = 0; k < m; ++k) acc = fma(row[k], src[k], acc);
-      X* dst = xb + l * mp + e;
-      *dst = (X)((double)*dst + acc);
+      if (!to_y) {
+        X* dst = xb + l * mp + e;
+        *dst = (X)((double)*dst + acc);
+      }
     }
     w[(l + 1) & 1][e] = acc;
     __syncthreads();
+    if (to_y && e < sq.q) {  // w_l is complete in w[(l + 1) & 1]
+      const double* wl = w[(l + 1) & 1];
+      double a = 0.0;
+      for (int k = 0; k < m; ++k) a = fma((double)cm[(int64_t)e * mp + k], wl[k], a);
+      X* dst = yb + l * sq.q + e;
+      *dst = (X)((double)*dst + a);
+    }
   }
 }
 
 hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
-                            const double* pw, const void* x0, void* buf0, void* buf1, hipStream_t st) {
+                            const double* pw, const void* x0, void* buf0, void* buf1, const void* small,
+                            void* y, hipStream_t st) {
   if (n_seq <= 0) return hipSuccess;
   if (mp_class > 256) return hipErrorInvalidValue;
   if (f64)
     hipLaunchKernelGGL(k_inject_x0<double>, dim3(n_seq), dim3(256), 0, st, seqs, ops, pw,
                        static_cast<const double*>(x0), mp_class, static_cast<double*>(buf0),
-                       static_cast<double*>(buf1));
+                       static_cast<double*>(buf1), static_cast<const double*>(small), static_cast<double*>(y));
   else
     hipLaunchKernelGGL(k_inject_x0<float>, dim3(n_seq), dim3(256), 0, st, seqs, ops, pw,
                        static_cast<const float*>(x0), mp_class, static_cast<float*>(buf0),
-                       static_cast<float*>(buf1));
+                       static_cast<float*>(buf1), static_cast<const float*>(small), static_cast<float*>(y));
   return hipGetLastError();
 }
 

@@ -374,10 +374,13 @@ hipError_t launch_scatter(const ScatterJob* jobs, int n_jobs, const int32_t* set
                           hipStream_t s);
 
 // Initial state: adds Abar^(l+1) x0 to rows l < min(2^kry, L) of each sequence
-// of padded size mp_class in buffer kry % 2 (after the first pass of an apply);
-// x0 and the buffers in the plan's state type (FP64 when f64, else FP32).
+// of padded size mp_class in buffer kry % 2 (after the first pass of an apply),
+// or C Abar^(l+1) x0 to those rows of y where that pass formed y (kry = last + 1);
+// x0, the buffers, the small matrices and y in the plan's state type (FP64
+// when f64, else FP32).
 hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
-                            const double* pw, const void* x0, void* buf0, void* buf1, hipStream_t st);
+                            const double* pw, const void* x0, void* buf0, void* buf1, const void* small,
+                            void* y, hipStream_t st);
 hipError_t launch_recursion(int mp, int ct, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const double* bbar, const void* u,
                             int u_dtype, void* xout, hipStream_t s);

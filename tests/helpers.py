@@ -5,12 +5,43 @@ import numpy as np
 import oracle as O
 
 
+# A parity check bounds the error of a whole result (relative Frobenius
+# norm) and of every row of it: row l of a time-major result may be off by at
+# most ROW_SLACK times the tolerance, measured against the RMS row norm of
+# the reference. The Frobenius norm alone lets a few entirely wrong rows of a
+# long sequence through (at 2e-2 about 6 of 16384 rows); the row bound does
+# not, while rows whose error is merely larger than average (a factor of a
+# few) still pass.
+ROW_SLACK = 5.0
+
+
 def rel_err(a, b):
     """||a - b||_F / ||b||_F (b is the reference)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def row_err(a, b):
+    """max over rows l of ||a_l - b_l|| / RMS_l ||b_l|| for (L, n) results."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    rms = np.sqrt(np.mean(np.sum(b * b, axis=1)))
+    return float(np.max(np.linalg.norm(a - b, axis=1)) / (rms if rms > 0 else 1.0))
+
+
+def parity_err(a, b):
+    """The error a parity test holds to its tolerance: the relative Frobenius
+    error, or the worst row error over ROW_SLACK if that is larger (2-D
+    results with more than one row; a 1-D result is a single row)."""
+    e = rel_err(a, b)
+    a = np.asarray(a)
+    if a.ndim == 2 and a.shape[0] > 1:
+        e = max(e, row_err(a, b) / ROW_SLACK)
+    return e
 
 
 def discretized(wl, seq, disc=None):
@@ -55,4 +86,4 @@ def state_part(wl, ys, u_override=None):
 
 
 def max_rel(got, ref):
-    return max(rel_err(g, r) for g, r in zip(got, ref))
+    return max(parity_err(g, r) for g, r in zip(got, ref))

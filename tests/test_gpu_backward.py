@@ -12,7 +12,7 @@ import torch
 
 import oracle as O
 from paper_2411_17729_amd import workloads as W
-from tests.helpers import rel_err
+from tests.helpers import parity_err
 
 pytestmark = pytest.mark.gpu
 
@@ -77,12 +77,12 @@ def _compare(wl, compute, ckpt_every=0, tol=None, u_dtype=None, disc="trapezoid"
     dul, gs, us, _ = _gpu_grads(wl, compute, dys, ckpt_every, u_dtype, **plan_kw)
     ref, dus = _oracle_grads(wl, dys, us, disc)
     tol = TOL[compute] if tol is None else tol
-    errs = {"u": max(rel_err(a, b) for a, b in zip(dul, dus))}
+    errs = {"u": max(parity_err(a, b) for a, b in zip(dul, dus))}
     for si in range(len(wl.sets)):
         if not any(s.param_set == si for s in wl.seqs):
             continue
         for j, k in enumerate("ABCD"):
-            errs[f"{k}{si}"] = max(errs.get(f"{k}{si}", 0.0), rel_err(gs[si][j], ref[si][k]))
+            errs[f"{k}{si}"] = max(errs.get(f"{k}{si}", 0.0), parity_err(gs[si][j], ref[si][k]))
     print(wl.name, compute, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, bad
@@ -147,6 +147,42 @@ def test_backward_full_size_fp32():
     _compare(wl, "f32")
 
 
+def test_backward_bf16_m256():
+    # BF16 operands at padded m 256 (the bench's state size), two sequences
+    # sharing one HiPPO model, p = q = 8
+    wl = W.backward(seed=8, batch=2, m=256, L=4096, N=11, p=8, q=8, delta=1e-2)
+    _compare(wl, "bf16")
+
+
+def test_backward_ragged_256_bf16_sampled():
+    # the ragged batch of 256 sequences (every sequence its own HiPPO model of
+    # m in {64, 128, 256}, L log-uniform in [512, 65536], N = ceil(log2 L) - 1),
+    # BF16, the gradients of the whole batch in one backward call, checked
+    # against the oracle on the longest and shortest sequences and a
+    # mid-length one of each other size class
+    wl = W.ragged(seed=0)
+    dys = [d.astype(np.float32).astype(np.float64) for d in wl.dy]
+    dul, gs, us, plan = _gpu_grads(wl, "bf16", dys)
+    assert plan.info()["launch"] == 2
+    Ls = [s.L for s in wl.seqs]
+    ms = [wl.sets[s.param_set].m for s in wl.seqs]
+    sample = {int(np.argmax(Ls)), int(np.argmin(Ls))}
+    for m in (64, 128, 256):
+        idx = sorted((i for i in range(len(Ls)) if ms[i] == m), key=lambda i: Ls[i])
+        if not any(ms[i] == m for i in sample):
+            sample.add(idx[len(idx) // 2])
+    for i in sorted(sample):
+        s = wl.seqs[i]
+        ps = wl.sets[s.param_set]
+        g = O.grads_full(ps.A, ps.B, ps.C, ps.D, s.delta, us[i], dys[i], s.N)
+        errs = {"u": parity_err(dul[i], g["u"])}
+        for j, k in enumerate("ABCD"):
+            errs[k] = parity_err(gs[s.param_set][j], g[k])
+        print("seq", i, "L", s.L, "m", ps.m, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        bad = {k: v for k, v in errs.items() if not v <= TOL["bf16"]}
+        assert not bad, (i, bad)
+
+
 def test_finite_differences_fp64_gpu():
     # central differences (h = 1e-6) of <dy, y> through the FP64 GPU forward
     from paper_2411_17729_amd import cascade as CC
@@ -189,6 +225,6 @@ def test_autograd_function():
     dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in wl.dy]), device="cuda")
     (y * dy).sum().backward()
     ref, dus = _oracle_grads(wl, wl.dy, [s.u for s in wl.seqs])
-    assert rel_err(u.grad.cpu().numpy(), np.concatenate([d.reshape(-1) for d in dus])) < 1e-10
+    assert parity_err(u.grad.cpu().numpy(), np.concatenate([d.reshape(-1) for d in dus])) < 1e-10
     for t, k in zip(params, "ABCD"):
-        assert rel_err(t.grad.cpu().numpy(), ref[0][k]) < 1e-10, k
+        assert parity_err(t.grad.cpu().numpy(), ref[0][k]) < 1e-10, k

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from paper_2411_17729_amd import binding as B
-from tests.helpers import rel_err
+from tests.helpers import parity_err
 from tests.test_gpu_chain import _oracle
 from tests.test_gpu_pair import _workload
 
@@ -59,7 +59,7 @@ def test_fold_matches_oracle(u_dtype, zero_d):
         _bf16_inputs(wl, u)
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e, eu, d = rel_err(y[i], ref[i]), rel_err(yu[i], ref[i]), rel_err(y[i], yu[i])
+        e, eu, d = parity_err(y[i], ref[i]), parity_err(yu[i], ref[i]), parity_err(y[i], yu[i])
         print(u_dtype, "D=0" if zero_d else "D!=0", "seq", i,
               f"fold {e:.2e}  stages {eu:.2e}  between {d:.2e}", flush=True)
         assert e <= 2e-2, (i, e)
@@ -95,7 +95,7 @@ def test_fold_depths(case):
     assert info["fold_launches"] == 1
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e = rel_err(y[i], ref[i])
+        e = parity_err(y[i], ref[i])
         print(case, "seq", i, f"{e:.2e}", flush=True)
         assert e <= 2e-2, (i, e)
 
@@ -108,7 +108,7 @@ def test_fold_bf16_state():
     assert if_["state_dtype"] == B.SSM_F32
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e, d = rel_err(yb[i], ref[i]), rel_err(yb[i], yf[i])
+        e, d = parity_err(yb[i], ref[i]), parity_err(yb[i], yf[i])
         print("seq", i, f"bf16 state {e:.2e} between {d:.2e}", flush=True)
         assert e <= 2e-2 and d <= 1e-2, (i, e, d)
 
@@ -128,9 +128,9 @@ def test_fold_six_long_memory(p):
     y, info, _ = _run(wl)
     assert info["fold_stages"] == 6 and info["fold_launches"] == 1
     ref = _oracle(wl)[0]
-    late = rel_err(y[0][2048:], ref[2048:])
-    print("p", p, "rel", f"{rel_err(y[0], ref):.2e}", "rows from 2048", f"{late:.2e}", flush=True)
-    assert late <= 2e-2 and rel_err(y[0], ref) <= 2e-2
+    late = parity_err(y[0][2048:], ref[2048:])
+    print("p", p, "rel", f"{parity_err(y[0], ref):.2e}", "rows from 2048", f"{late:.2e}", flush=True)
+    assert late <= 2e-2 and parity_err(y[0], ref) <= 2e-2
 
 
 @pytest.mark.parametrize("case", ["q16_p64", "q1_p1", "q8_p64", "p65"])
@@ -146,7 +146,7 @@ def test_fold_limits(case):
     assert info["fold_launches"] == (0 if case == "p65" else 1), info["fold_launches"]
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e = rel_err(y[i], ref[i])
+        e = parity_err(y[i], ref[i])
         print(case, "seq", i, f"{e:.2e}", flush=True)
         assert e <= 2e-2, (i, e)
 

@@ -11,16 +11,16 @@ import torch
 
 import oracle as O
 from paper_2411_17729_amd import workloads as W
-from tests.helpers import max_rel, oracle_outputs, rel_err, state_part
+from tests.helpers import max_rel, oracle_outputs, parity_err, state_part
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2}
 
 
-def _run(wl, compute, u_dtype=None, recursion=False):
+def _run(wl, compute, u_dtype=None, recursion=False, **plan_kw):
     from paper_2411_17729_amd import cascade as CC
-    plan = CC.plan_for_workload(wl, compute=compute)
+    plan = CC.plan_for_workload(wl, compute=compute, **plan_kw)
     if u_dtype is None:
         u_dtype = torch.float64 if compute == "f64" else torch.float32
     u = CC.pack_u(wl, dtype=u_dtype)
@@ -37,15 +37,15 @@ def _run(wl, compute, u_dtype=None, recursion=False):
     return CC.unpack_y(wl, y), uq, plan
 
 
-def _check(wl, compute, u_dtype=None, tol=None, recursion=False):
-    got, uq, _ = _run(wl, compute, u_dtype, recursion)
+def _check(wl, compute, u_dtype=None, tol=None, recursion=False, **plan_kw):
+    got, uq, plan = _run(wl, compute, u_dtype, recursion, **plan_kw)
     ref = oracle_outputs(wl, u_override=uq, method="recursion" if recursion else "auto")
     tol = TOL[compute] if tol is None else tol
     e_y = max_rel(got, ref)
     e_x = max_rel(state_part(wl, got, uq), state_part(wl, ref, uq))
     print(f"{wl.name} {compute} rel_y={e_y:.3e} rel_state={e_x:.3e}", flush=True)
     assert e_y <= tol and e_x <= tol, (e_y, e_x)
-    return e_y, e_x
+    return e_y, e_x, plan
 
 
 def test_powers_and_bbar_fp64_worked_example():
@@ -112,9 +112,26 @@ def test_hippo_batched_full_size_fp32():
 
 
 def test_hippo_batched_full_size_bf16():
-    # the bench launch configuration: BF16 operands, FP32 u, all 16 sequences in full
+    # BF16 operands with the state kept in FP32 between passes (the bench's
+    # second line), FP32 u, all 16 sequences in full
     wl = W.batched(seed=0)
-    _check(wl, "bf16")
+    _check(wl, "bf16", state_bf16=0)
+
+
+def test_hippo_batched_headline_plan():
+    # the exact plan the headline bench line times: BF16 operands, the state
+    # in BF16 between passes, the split input pass folding stages 0-5, one
+    # stage pair (6, 7) and the six-stage output fold (8-13), on all 16
+    # sequences of 16384 rows against the FP64 recursion (with the per-row
+    # bound of parity_err)
+    from paper_2411_17729_amd import binding as B
+    wl = W.batched(seed=0)
+    e_y, e_x, plan = _check(wl, "bf16", state_bf16=1)
+    info = plan.info()
+    assert info["state_dtype"] == B.SSM_BF16
+    assert info["fold_stages"] == 6 and info["input_stages"] == 6
+    assert info["pair_launches"] == 1 and info["fold_launches"] == 1
+    assert info["stage_launches"] == 2  # the pair and the fold (the input pass is not a stage launch)
 
 
 def test_hippo_batched_full_size_bf16_input():

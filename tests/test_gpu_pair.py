@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from paper_2411_17729_amd import workloads as W
-from tests.helpers import rel_err
+from tests.helpers import parity_err
 from tests.test_gpu_chain import _oracle
 
 pytestmark = pytest.mark.gpu
@@ -59,7 +59,7 @@ def test_pair_matches_oracle(zero_d):
     got = CC.unpack_y(wl, y)
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e = rel_err(got[i], ref[i])
+        e = parity_err(got[i], ref[i])
         print("seq", i, f"{e:.2e}", flush=True)
         assert e <= 2e-2, (i, e)
 
@@ -78,7 +78,7 @@ def _paired_vs_unpaired(wl, tail_seqs, **kw):
     assert iu["pair_launches"] == 0
     assert iu["stage_launches"] == ip["stage_launches"] + ip["pair_launches"]
     for i, (a, b) in enumerate(zip(CC.unpack_y(wl, yp), CC.unpack_y(wl, yu))):
-        e = rel_err(a, b)
+        e = parity_err(a, b)
         print("seq", i, f"{e:.2e}", flush=True)
         if i in tail_seqs:
             assert e <= 2e-3, (i, e)
@@ -136,7 +136,7 @@ def test_pair_from_stage4():
     got = CC.unpack_y(wl, yp)
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e = rel_err(got[i], ref[i])
+        e = parity_err(got[i], ref[i])
         print("seq", i, f"{e:.2e}", flush=True)
         assert e <= 2e-2, (i, e)
 
@@ -176,7 +176,7 @@ def test_split_input_matches_oracle(j, u_dtype, zero_d):
             off += n
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e = rel_err(got[i], ref[i])
+        e = parity_err(got[i], ref[i])
         print(u_dtype, "D=0" if zero_d else "D!=0", "seq", i, f"{e:.2e}", flush=True)
         assert e <= 2e-2, (i, e)
 
@@ -192,7 +192,7 @@ def test_split_input_matches_resident_input():
     yr, ire = _apply(wl, input_stages=5, input_split=1)
     assert isp["input_stages"] == ire["input_stages"] == 5
     for i, (a, b) in enumerate(zip(CC.unpack_y(wl, ys), CC.unpack_y(wl, yr))):
-        e = rel_err(a, b)
+        e = parity_err(a, b)
         print("seq", i, f"{e:.2e}", flush=True)
         assert e <= 2e-3, (i, e)
 
@@ -210,7 +210,7 @@ def test_split_input_falls_back(case):
     got = CC.unpack_y(wl, y)
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        assert rel_err(got[i], ref[i]) <= 2e-2, i
+        assert parity_err(got[i], ref[i]) <= 2e-2, i
 
 
 @pytest.mark.parametrize("case", ["q16_p64", "bf16_u", "q17"])
@@ -241,6 +241,6 @@ def test_tail_pair_edges(case):
             off += n
     ref = _oracle(wl)
     for i in range(len(wl.seqs)):
-        e = rel_err(got[i], ref[i])
+        e = parity_err(got[i], ref[i])
         print(case, "seq", i, f"{e:.2e}", flush=True)
         assert e <= 2e-2, (i, e)
