@@ -181,7 +181,16 @@ typedef struct {
    * else 4; 5 at 128; with the stages before it pairing up), -1: off, 2..6:
    * at most that many. */
   int32_t fold_stages;
-  int32_t reserved[3];   /* must be 0 */
+  /* Persistent launch: an item waits for the items of the level before it
+   * (device-scope counters) and gives up after spin_limit sleeps of about 64
+   * clocks each (0: the default, 2^25, about a second on MI355X), or at once
+   * when another workgroup has given up. A workgroup that gives up skips the
+   * rest of its work but still signals it, so the grid always drains and the
+   * kernel returns; the give-up is reported by ssm_cascade_device_status. A
+   * valid plan never comes near the default; a tiny limit forces the give-up
+   * path (for tests). Must be >= 0. */
+  int32_t spin_limit;
+  int32_t reserved[2];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -349,6 +358,14 @@ ssm_status ssm_cascade_get_power(ssm_plan plan, int32_t op, int32_t k,
 /* Copies Bbar (m x p) of operator `op` into dst (device, FP64). */
 ssm_status ssm_cascade_get_bbar(ssm_plan plan, int32_t op, double* dst,
                                 hipStream_t stream);
+
+/* Synchronizes `stream` and reports whether the last persistent launch of the
+ * plan (apply or its graph) gave up a wait for the items it depends on (see
+ * ssm_tuning.spin_limit): SSM_E_HIP if it did (its output is not valid; the
+ * next apply clears the record), SSM_OK otherwise and for plans that do not
+ * launch persistently. Also returns SSM_E_HIP if the synchronization reports
+ * an earlier asynchronous failure. */
+ssm_status ssm_cascade_device_status(ssm_plan plan, hipStream_t stream);
 
 /* Host-side summary of a plan. */
 ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);

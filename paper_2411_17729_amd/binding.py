@@ -56,7 +56,7 @@ class ssm_tuning(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
                 ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
                 ("pair_blocks", C.c_int32), ("input_split", C.c_int32), ("state_bf16", C.c_int32),
-                ("fold_stages", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("fold_stages", C.c_int32), ("spin_limit", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class ssm_plan_info(C.Structure):
@@ -74,8 +74,9 @@ class ssm_plan_info(C.Structure):
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
                 input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                state_bf16=0, fold_stages=0):
+                state_bf16=0, fold_stages=0, spin_limit=0):
     t = ssm_tuning()
+    t.spin_limit = int(spin_limit)
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
     t.input_stages = int(input_stages)
@@ -98,7 +99,7 @@ EXPORTS = [
     "ssm_cascade_get_power", "ssm_cascade_get_bbar", "ssm_cascade_plan_info",
     "ssm_cascade_timing_enable", "ssm_cascade_timing_read", "ssm_cascade_destroy",
     "ssm_cascade_graph_apply", "ssm_cascade_graph_backward", "ssm_cascade_graph_launch",
-    "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error",
+    "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error", "ssm_cascade_device_status",
 ]
 
 
@@ -147,6 +148,8 @@ def load(path=LIB_PATH):
     lib.ssm_cascade_timing_read.restype = i32
     lib.ssm_cascade_timing_read.argtypes = [vp, i32, P(i64), P(dbl)]
     lib.ssm_cascade_destroy.restype = i32
+    lib.ssm_cascade_device_status.argtypes = [vp, vp]
+    lib.ssm_cascade_device_status.restype = i32
     lib.ssm_cascade_destroy.argtypes = [vp]
     lib.ssm_status_string.restype = C.c_char_p
     lib.ssm_status_string.argtypes = [i32]
@@ -251,6 +254,10 @@ def ssm_cascade_timing_read(plan, kind):
     _check(load().ssm_cascade_timing_read(plan, kind, C.byref(n), C.byref(ms)),
            "ssm_cascade_timing_read")
     return n.value, ms.value
+
+
+def ssm_cascade_device_status(plan, stream):
+    _check(_lib.ssm_cascade_device_status(plan, stream), "ssm_cascade_device_status")
 
 
 def ssm_cascade_destroy(plan):

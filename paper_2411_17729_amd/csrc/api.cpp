@@ -171,6 +171,7 @@ struct ssm_plan_s {
   std::vector<int32_t> cnt_off, ntiles;
   int64_t n_counters = 0;
   int persistent_grid = 0;
+  int32_t spin_limit = 0;  // bound of a persistent item's wait (0: the default)
   size_t m_items = 0, m_cntoff = 0, m_ntiles = 0, m_counters = 0;
   // persistent launch on the resident-power code (chain, resident and input-pass items)
   bool persist_res = false;
@@ -241,6 +242,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (tuning) tn = *tuning;
   for (size_t i = 0; i < sizeof(tn.reserved) / sizeof(tn.reserved[0]); ++i)
     if (tn.reserved[i] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.spin_limit < 0) return fail(SSM_E_INVALID, "spin_limit = %d: must be >= 0", tn.spin_limit);
+  P.spin_limit = tn.spin_limit;
   if (tn.stage_kernel < SSM_STAGE_AUTO || tn.stage_kernel > SSM_STAGE_CHAIN)
     return fail(SSM_E_INVALID, "unknown stage kernel %d", tn.stage_kernel);
   if ((tn.stage_kernel == SSM_STAGE_RESIDENT || tn.stage_kernel == SSM_STAGE_CHAIN) &&
@@ -1064,7 +1067,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     P.m_ntiles = off;
     off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, P.ntiles.size()));
     P.m_counters = off;
-    off = align_up(off + sizeof(int32_t) * (size_t)P.n_counters);
+    off = align_up(off + sizeof(int32_t) * ((size_t)P.n_counters + 1));  // + the give-up flag
   }
   if (P.with_backward) {
     plan_backward(P);
@@ -2050,7 +2053,9 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     pp.cnt_target = reinterpret_cast<const int32_t*>(meta + P.m_cnttarget);
     pp.x0 = P.ws + P.r_x0.off;
     pp.x1 = P.ws + P.r_x1.off;
-    hipError_t e = launch_zero_i32(pp.counters, P.n_counters, stream);
+    pp.flag = pp.counters + P.n_counters;
+    pp.spin_limit = P.spin_limit;
+    hipError_t e = launch_zero_i32(pp.counters, P.n_counters + 1, stream);
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");
     TimedLaunch tl(P, stream, 0);
     e = launch_persist_res(P.compute, pp, P.persistent_grid, P.persist_lds, stream);
@@ -2074,7 +2079,9 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     pp.ntiles = reinterpret_cast<const int32_t*>(meta + P.m_ntiles);
     pp.x0 = P.ws + P.r_x0.off;
     pp.x1 = P.ws + P.r_x1.off;
-    hipError_t e = launch_zero_i32(pp.counters, P.n_counters, stream);
+    pp.flag = pp.counters + P.n_counters;
+    pp.spin_limit = P.spin_limit;
+    hipError_t e = launch_zero_i32(pp.counters, P.n_counters + 1, stream);
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");
     TimedLaunch tl(P, stream, 0);
     e = launch_persistent(P.compute, pp, P.persistent_grid, stream);
@@ -2438,6 +2445,22 @@ ssm_status ssm_cascade_get_bbar(ssm_plan plan, int32_t op, double* dst, hipStrea
   const double* srcp = plan->at<double>(plan->r_bbar) + o.bbar;
   HIP_TRY(hipMemcpyAsync(dst, srcp, (size_t)o.m * o.p * 8, hipMemcpyDeviceToDevice, stream),
           "Bbar copy");
+  return SSM_OK;
+}
+
+ssm_status ssm_cascade_device_status(ssm_plan plan, hipStream_t stream) {
+  g_last_error.clear();
+  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  ssm_plan_s& P = *plan;
+  HIP_TRY(hipStreamSynchronize(stream), "synchronization");
+  if (P.launch != SSM_LAUNCH_PERSISTENT) return SSM_OK;
+  int32_t* flag = reinterpret_cast<int32_t*>(P.ws + P.r_meta.off + P.m_counters) + P.n_counters;
+  int32_t h = 0;
+  HIP_TRY(hipMemcpy(&h, flag, sizeof h, hipMemcpyDeviceToHost), "give-up flag read");
+  if (h != 0)
+    return fail(SSM_E_HIP, "a persistent launch gave up waiting for the items it depends on "
+                           "(spin limit %d); its output is not valid",
+                P.spin_limit > 0 ? P.spin_limit : (int)kPersistSpinLimit);
   return SSM_OK;
 }
 

@@ -184,12 +184,9 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 template <int MP, int KS, bool V16, bool XB>
 static hipError_t launch_input_t(const StageParams& prm, const ResRange* units, int n_units,
                                  size_t lds, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_input_split<MP, KS, V16, XB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_input_split<MP, KS, V16, XB>), (size_t)(65536));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((k_input_split<MP, KS, V16, XB>), dim3(n_units), dim3(512), lds, s, prm, units);
   return hipGetLastError();

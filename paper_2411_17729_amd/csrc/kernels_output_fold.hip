@@ -251,12 +251,9 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 template <int MP, int S, bool XB>
 static hipError_t launch_fold_t(const StageParams& prm, const FoldUnit* units, int n_units, size_t lds,
                                 hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_output_fold<MP, S, XB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_output_fold<MP, S, XB>), (size_t)(160 * 1024));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((k_output_fold<MP, S, XB>), dim3(n_units), dim3(256), lds, s, prm, units);
   return hipGetLastError();

@@ -260,12 +260,9 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 
 template <bool XB>
 static hipError_t launch_wide_t(const StageParams& prm, const FoldUnit* units, int n_units, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_output_fold_wide<XB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_output_fold_wide<XB>), (size_t)(160 * 1024));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((k_output_fold_wide<XB>), dim3(n_units), dim3(512), fold_wide_lds(), s, prm, units);
   return hipGetLastError();

@@ -58,7 +58,8 @@ template <int CT>
 __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_persist_res(
     RPersistParams pp) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_p[];
-  __shared__ int s_item;
+  __shared__ int s_item, s_ok;
+  int32_t* flag = pp.flag;
   for (;;) {
     __syncthreads();  // the previous item's waves are done with LDS
     if (threadIdx.x == 0) s_item = atomicAdd(pp.counters, 1);
@@ -69,20 +70,22 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const SeqDev sq = pp.base.seqs[w.seq];
     const int first_level = sq.kry - 1;
     const int base = pp.cnt_off[w.seq];
-    if (w.level > first_level) {
-      if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      bool ok = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+      if (ok && w.level > first_level) {
         // spin on relaxed device-scope loads (they bypass the caches), then one
         // acquire fence before the stage input is read
         const int c = base + (w.level - 1 - first_level);
-        const int target = pp.cnt_target[c];
-        while (__hip_atomic_load(pp.counters + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
-          __builtin_amdgcn_s_sleep(1);
+        ok = persist_wait(pp.counters + c, pp.cnt_target[c], flag, pp.spin_limit);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      __syncthreads();
+      s_ok = ok;
     }
+    __syncthreads();
     const int mp = pp.base.ops[sq.op].mp;
-    if (mp == 64) {
+    if (!s_ok) {
+      // a wait gave up: skip the work, still signal the item below
+    } else if (mp == 64) {
       persist_item<64, CT>(pp.base, w, pp.x0, pp.x1, smem_p);
     } else if (mp == 128) {
       persist_item<128, CT>(pp.base, w, pp.x0, pp.x1, smem_p);
@@ -112,12 +115,9 @@ size_t persist_res_lds(int ct, int max_mp) {  // with room for the tail items' C
 
 template <int CT>
 static hipError_t launch_pr(const RPersistParams& pp, int grid, size_t lds, hipStream_t s) {
-  static size_t attr = 0;
-  if (attr < lds) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist_res<CT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_persist_res<CT>), lds);
     if (e != hipSuccess) return e;
-    attr = lds;
   }
   hipLaunchKernelGGL(k_persist_res<CT>, dim3(grid), dim3(512), lds, s, pp);
   return hipGetLastError();

@@ -353,7 +353,8 @@ template <int CT>
 __global__ __launch_bounds__(256, 1) void k_persistent(PersistParams pp) {
   using X = typename CTraits<CT>::X;
   __shared__ __attribute__((aligned(16))) unsigned char smem[PersistLds<CT>::LDS];
-  __shared__ int s_item;
+  __shared__ int s_item, s_ok;
+  int32_t* flag = pp.flag;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = atomicAdd(pp.counters, 1);
@@ -361,20 +362,22 @@ __global__ __launch_bounds__(256, 1) void k_persistent(PersistParams pp) {
     const int it = s_item;
     if (it >= pp.n_items) break;
     const PItem w = pp.items[it];
-    if (w.k >= 0) {
-      if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      bool ok = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+      if (ok && w.k >= 0) {
         // relaxed device-scope spin (bypasses the caches), then one acquire fence
-        const int* c = pp.counters + pp.cnt_off[w.seq] + w.k;  // level k-1
-        const int target = pp.ntiles[w.seq];
-        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
-          __builtin_amdgcn_s_sleep(1);
+        const int32_t* c = pp.counters + pp.cnt_off[w.seq] + w.k;  // level k-1
+        ok = persist_wait(c, pp.ntiles[w.seq], flag, pp.spin_limit);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      __syncthreads();
+      s_ok = ok;
     }
+    __syncthreads();
     StageParams prm = pp.base;
     const Tile t{w.seq, w.row0};
-    if (w.k < 0) {
+    if (!s_ok) {
+      // a wait gave up: skip the work, still signal the item below
+    } else if (w.k < 0) {
       prm.xout = pp.x0;
       switch (w.mp) {
         case 32: project_tile<32, X>(prm, t, stage_bm(32, CT), smem); break;

@@ -15,12 +15,9 @@ static hipError_t launch_chain_v(const StageParams& prm, const ChainUnit* units,
                                  hipStream_t s) {
   using C = ResCfg<MP, CT>;
   constexpr size_t lds = TAIL ? C::LDS_TAIL : C::LDS;  // a tail launch stages C and D too
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_chain<MP, CT, TAIL>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage_chain<MP, CT, TAIL>), (size_t)((int)lds));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((k_stage_chain<MP, CT, TAIL>), dim3(n_units, C::NS), dim3(512), lds, s, prm,
                      units);

@@ -467,12 +467,9 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 template <int MP, bool TAIL, bool XB>
 static hipError_t launch_pair_v(const StageParams& prm, const PairUnit* units, int n_units,
                                 size_t lds, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_pair<MP, TAIL, XB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage_pair<MP, TAIL, XB>), (size_t)(160 * 1024));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((k_stage_pair<MP, TAIL, XB>), dim3(n_units), dim3(512), lds, s, prm, units);
   return hipGetLastError();

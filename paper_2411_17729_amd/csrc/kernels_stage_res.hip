@@ -27,12 +27,9 @@ static hipError_t launch_res_t(const StageParams& prm, const ResRange* ranges, i
                                hipStream_t s) {
   using C = ResCfg<MP, CT>;
   if (n_ranges <= 0) return hipSuccess;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_res<MP, CT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage_res<MP, CT>), (size_t)((int)C::LDS));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((k_stage_res<MP, CT>), dim3(n_ranges, C::NS), dim3(512), C::LDS, s, prm,
                      ranges);
@@ -83,12 +80,9 @@ static hipError_t launch_kry_t(const StageParams& prm, const ResRange* ranges, i
                                hipStream_t s) {
   using C = ResCfg<MP, CT>;
   if (n_ranges <= 0) return hipSuccess;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_krylov_res<MP, CT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+  {
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_krylov_res<MP, CT>), (size_t)((int)C::LDS));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((k_krylov_res<MP, CT>), dim3(n_ranges, C::NS), dim3(512), C::LDS, s, prm,
                      ranges);

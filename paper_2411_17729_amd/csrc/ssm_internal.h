@@ -144,12 +144,13 @@ struct PersistParams {
   StageParams base;        // seqs, ops, P, small, src, dst, src_dtype, flags
   const PItem* items;
   int32_t n_items;
-  int32_t reserved;
+  int32_t spin_limit;      // sleeps a wait may take before it gives up (see persist_wait)
   int32_t* counters;       // [0]: ticket counter; then (last+2) completion counters per sequence
   const int32_t* cnt_off;  // per sequence: index of its first completion counter
   const int32_t* ntiles;   // per sequence: number of row tiles
   void* x0;
   void* x1;
+  int32_t* flag;           // give-up flag (the entry after the last counter)
 };
 
 // ---- persistent launch on the resident-power kernels ----
@@ -166,13 +167,38 @@ struct RPersistParams {
   StageParams base;            // seqs, ops, P, small, src, dst, src_dtype, flags
   const RItem* items;
   int32_t n_items;
-  int32_t reserved;
+  int32_t spin_limit;          // sleeps a wait may take before it gives up (see persist_wait)
   int32_t* counters;           // [0]: ticket counter; then per sequence and level
   const int32_t* cnt_off;      // per sequence: counter of its level kry - 1
   const int32_t* cnt_target;   // per counter: items of that (sequence, level)
   void* x0;
   void* x1;
+  int32_t* flag;               // give-up flag (the entry after the last counter)
 };
+
+// Default bound of a persistent item's wait for its predecessors: about one
+// second of s_sleep(1) at the MI355X clock, far above any wait a valid plan
+// produces (a whole ragged forward pass takes milliseconds).
+constexpr int32_t kPersistSpinLimit = 1 << 25;
+
+// One thread of a workgroup waits until *cnt >= target. It gives up after
+// `limit` sleeps, or at once when another workgroup has given up (*flag set),
+// and then sets *flag. Returns true if the wait ended normally. A workgroup
+// whose wait gave up skips its item's work but still signals the item done, so
+// every later wait ends too and the grid drains.
+__device__ __forceinline__ bool persist_wait(const int32_t* cnt, int32_t target, int32_t* flag,
+                                             int32_t limit) {
+  if (limit <= 0) limit = kPersistSpinLimit;
+  int32_t n = 0;
+  while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++n > limit || __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
 
 // ---- backward ----
 // A chunk of rows of one sequence for the outer-product reductions.
@@ -384,5 +410,10 @@ hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_se
 hipError_t launch_recursion(int mp, int ct, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const double* bbar, const void* u,
                             int u_dtype, void* xout, hipStream_t s);
+
+// Raises the dynamic LDS limit of `kernel` to at least `bytes` on the current
+// device. The limit is a per-device function attribute, so the setting is
+// remembered per (kernel, device); safe to call from several threads.
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
 
 }  // namespace ssmc

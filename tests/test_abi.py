@@ -130,8 +130,12 @@ def test_tuning_is_validated(lib):
     t = B.make_tuning(tile_rows=(0, 64, 0, 0))  # half of the default 128 for m <= 64
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
     t = B.make_tuning()
-    t.reserved[2] = 1
+    t.reserved[1] = 1
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
+    t = B.make_tuning(spin_limit=-1)
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
+    t = B.make_tuning(spin_limit=1)
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
 
 
 def test_discretizations_on_host(lib):

@@ -161,6 +161,38 @@ def test_graph_replay_backward():
         CC.CascadePlan.graph_destroy(gr)
 
 
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_persistent_wait_gives_up_from_the_host(compute):
+    # a spin limit of one sleep makes the items of the second level give up
+    # their wait (the first level is still running): the kernel still exits
+    # normally, the give-up is reported by ssm_cascade_device_status, and a
+    # plan with the default limit on the same data is unaffected
+    from paper_2411_17729_amd import binding as B
+    from paper_2411_17729_amd import cascade as CC
+    wl = W.batched(seed=21, batch=3, m=128, L=40000, N=15, p=4, q=4)
+    wl.seqs[1].L = 30000  # ragged, so the persistent launch is chosen
+    wl.seqs[1].u = wl.seqs[1].u[:30000]
+    u = CC.pack_u(wl, dtype=torch.float32)
+    bad = CC.plan_for_workload(wl, compute=compute, spin_limit=1)
+    assert bad.info()["launch"] == 2
+    bad.apply(u)
+    with pytest.raises(B.SSMError) as ei:
+        bad.device_status()
+    assert ei.value.status == B.SSM_E_HIP
+    good = CC.plan_for_workload(wl, compute=compute)
+    y = CC.unpack_y(wl, good.apply(u))
+    good.device_status()
+    ref = _oracle(wl)
+    uq = [s.u.astype(np.float32).astype(np.float64) for s in wl.seqs]
+    st_g = state_part(wl, y, uq)
+    st_r = state_part(wl, [ref[i] for i in range(len(wl.seqs))], uq)
+    tol = 1e-5 if compute == "f32" else 2e-2
+    for i in range(len(wl.seqs)):
+        e = parity_err(st_g[i], st_r[i])
+        print(compute, i, f"{e:.2e}", flush=True)
+        assert e <= tol, (i, e)
+
+
 def test_autotuner_picks_a_measured_candidate(tmp_path):
     from paper_2411_17729_amd import tune
     wl = _ragged_small(11)
