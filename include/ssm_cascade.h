@@ -190,7 +190,14 @@ typedef struct {
    * valid plan never comes near the default; a tiny limit forces the give-up
    * path (for tests). Must be >= 0. */
   int32_t spin_limit;
-  int32_t reserved[2];   /* must be 0 */
+  /* 1: the workspace leaves out the two state buffers of the forward apply
+   * (ssm_cascade_workspace_bytes shrinks by that much), and the plan is
+   * applied only through ssm_cascade_apply_noalloc, which takes them from the
+   * library's static device scratch; ssm_cascade_apply, _apply_x0,
+   * _recursion and _graph_apply then return SSM_E_NOT_PREPARED. Not with
+   * with_backward (SSM_E_UNSUPPORTED). 0: the default. */
+  int32_t static_state;
+  int32_t reserved;      /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -338,6 +345,26 @@ size_t ssm_cascade_param_grad_numel(ssm_plan plan);
 ssm_status ssm_cascade_apply_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
                                 const void* x0, size_t x0_numel, void* y, size_t y_numel,
                                 hipStream_t stream);
+
+/* ssm_cascade_apply without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, checks, kernels and results as
+ * ssm_cascade_apply, bit for bit; the two state buffers the passes ping-pong
+ * between come from a static device array of the library (64 MiB, reserved
+ * on every device the library runs on until the process ends) instead of the
+ * plan's workspace, so a plan prepared with ssm_tuning.static_state = 1 needs
+ * no workspace for them. The call makes no HIP allocation and records no
+ * timing events.
+ * Limit: the plan's two state buffers (sum over sequences of L * padded m
+ * elements of 4 bytes, 8 for F64 plans, each) must fit in the 64 MiB;
+ * otherwise SSM_E_WORKSPACE and nothing is enqueued.
+ * Every call on one device shares that device's array and leaves its last
+ * contents there: calls that overlap on one device (two streams, two host
+ * threads, or a graph replay beside an eager call) race and corrupt each
+ * other's results. Serialize them. */
+ssm_status ssm_cascade_apply_noalloc(ssm_plan plan, const void* u, ssm_dtype u_dtype,
+                                     size_t u_numel, void* y, size_t y_numel,
+                                     hipStream_t stream);
 
 /* The plain recursion x_n = Abar x_{n-1} + Bbar u_n, y_n = C x_n + D u_n of
  * eq. (1.2) on the GPU (one workgroup per sequence, L dependent steps), for

@@ -56,7 +56,8 @@ class ssm_tuning(C.Structure):
     _fields_ = [("launch", C.c_int32), ("tile_rows", C.c_int32 * 4), ("stage_kernel", C.c_int32),
                 ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
                 ("pair_blocks", C.c_int32), ("input_split", C.c_int32), ("state_bf16", C.c_int32),
-                ("fold_stages", C.c_int32), ("spin_limit", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("fold_stages", C.c_int32), ("spin_limit", C.c_int32), ("static_state", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ssm_plan_info(C.Structure):
@@ -74,9 +75,10 @@ class ssm_plan_info(C.Structure):
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
                 input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                state_bf16=0, fold_stages=0, spin_limit=0):
+                state_bf16=0, fold_stages=0, spin_limit=0, static_state=0):
     t = ssm_tuning()
     t.spin_limit = int(spin_limit)
+    t.static_state = int(static_state)
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
     t.input_stages = int(input_stages)
@@ -100,6 +102,7 @@ EXPORTS = [
     "ssm_cascade_timing_enable", "ssm_cascade_timing_read", "ssm_cascade_destroy",
     "ssm_cascade_graph_apply", "ssm_cascade_graph_backward", "ssm_cascade_graph_launch",
     "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error", "ssm_cascade_device_status",
+    "ssm_cascade_apply_noalloc",
 ]
 
 
@@ -129,6 +132,8 @@ def load(path=LIB_PATH):
     lib.ssm_cascade_graph_destroy.argtypes = [vp]
     lib.ssm_cascade_apply.restype = i32
     lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
+    lib.ssm_cascade_apply_noalloc.restype = i32
+    lib.ssm_cascade_apply_noalloc.argtypes = [vp, vp, i32, sz, vp, sz, vp]
     lib.ssm_cascade_apply_x0.restype = i32
     lib.ssm_cascade_apply_x0.argtypes = [vp, vp, i32, sz, vp, sz, vp, sz, vp]
     lib.ssm_cascade_recursion.restype = i32
@@ -206,6 +211,11 @@ def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every,
 def ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
     _check(load().ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
            "ssm_cascade_apply")
+
+
+def ssm_cascade_apply_noalloc(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
+    _check(load().ssm_cascade_apply_noalloc(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
+           "ssm_cascade_apply_noalloc")
 
 
 def ssm_cascade_apply_x0(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, y_ptr, y_numel, stream):

@@ -59,7 +59,7 @@ class CascadePlan:
                  compute: str = "f32", with_backward: bool = False, ckpt_every: int = 0,
                  device="cuda", launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto",
                  input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                 state_bf16=0, fold_stages=0, spin_limit=0):
+                 state_bf16=0, fold_stages=0, spin_limit=0, static_state=0):
         if not torch.cuda.is_available():
             raise RuntimeError("the fast-cascade library needs a ROCm GPU")
         B.load()
@@ -92,7 +92,8 @@ class CascadePlan:
               "resident": B.SSM_STAGE_RESIDENT, "chain": B.SSM_STAGE_CHAIN}[stage_kernel] \
             if isinstance(stage_kernel, str) else int(stage_kernel)
         self.tuning = B.make_tuning(mode, tile_rows, sk, input_stages, chain_blocks, pair_stages,
-                                    pair_blocks, input_split, state_bf16, fold_stages, spin_limit)
+                                    pair_blocks, input_split, state_bf16, fold_stages, spin_limit,
+                                    static_state)
         nbytes = B.ssm_cascade_workspace_bytes(layout.descs, self.disc, self.compute,
                                                with_backward, ckpt_every, self.tuning)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -131,6 +132,14 @@ class CascadePlan:
                 raise ValueError("x0 must be a contiguous device tensor of the state dtype")
             B.ssm_cascade_apply_x0(self.plan, u.data_ptr(), self._u_code(u), u.numel(), x0.data_ptr(),
                                    x0.numel(), out.data_ptr(), out.numel(), _stream())
+        return out
+
+    def apply_noalloc(self, u: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """apply() with the state buffers taken from the library's static
+        device scratch: ``out`` must be given, nothing is allocated."""
+        u = self._check_u(u)
+        B.ssm_cascade_apply_noalloc(self.plan, u.data_ptr(), self._u_code(u), u.numel(), out.data_ptr(),
+                                    out.numel(), _stream())
         return out
 
     def recursion(self, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -250,7 +259,7 @@ class CascadePlan:
 def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, device="cuda",
                       launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto", input_stages=0,
                       chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0, state_bf16=0,
-                      fold_stages=0, disc=None, spin_limit=0):
+                      fold_stages=0, disc=None, spin_limit=0, static_state=0):
     """Builds the layout and plan of a ``workloads.Workload`` (discretization:
     the workload's, "given" or "trapezoid", unless ``disc`` names one)."""
     dims = [(ps.m, ps.p, ps.q) for ps in wl.sets]
@@ -263,7 +272,8 @@ def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, devi
                        launch=launch, tile_rows=tile_rows, stage_kernel=stage_kernel,
                        input_stages=input_stages, chain_blocks=chain_blocks,
                        pair_stages=pair_stages, pair_blocks=pair_blocks, input_split=input_split,
-                       state_bf16=state_bf16, fold_stages=fold_stages, spin_limit=spin_limit)
+                       state_bf16=state_bf16, fold_stages=fold_stages, spin_limit=spin_limit,
+                       static_state=static_state)
 
 
 def pack_u(wl, dtype=torch.float32, device="cuda"):

@@ -80,6 +80,8 @@ struct ssm_plan_s {
   int compute = DT_F32;  // DT_* of the stage operands
   int state_f64 = 0;     // state / io element is double
   int state_bf16 = 0;    // the forward apply keeps the state between passes in BF16
+  int static_state = 0;  // the workspace holds no state buffers (ssm_cascade_apply_noalloc only)
+  size_t x_buf_bytes = 0;  // bytes of one state buffer
   int disc = 0;
   int with_backward = 0, ckpt_every = 1;
   int max_last = 0, max_mp = 32, max_N = 0;
@@ -240,8 +242,12 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (st != SSM_OK) return st;
   ssm_tuning tn{};
   if (tuning) tn = *tuning;
-  for (size_t i = 0; i < sizeof(tn.reserved) / sizeof(tn.reserved[0]); ++i)
-    if (tn.reserved[i] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.reserved != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.static_state < 0 || tn.static_state > 1)
+    return fail(SSM_E_INVALID, "static_state = %d: supported 0 or 1", tn.static_state);
+  if (tn.static_state && with_backward)
+    return fail(SSM_E_UNSUPPORTED, "static_state: the backward needs the state buffers in the workspace");
+  P.static_state = tn.static_state;
   if (tn.spin_limit < 0) return fail(SSM_E_INVALID, "spin_limit = %d: must be >= 0", tn.spin_limit);
   P.spin_limit = tn.spin_limit;
   if (tn.stage_kernel < SSM_STAGE_AUTO || tn.stage_kernel > SSM_STAGE_CHAIN)
@@ -1107,8 +1113,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   take(P.r_nmat, n_nmat * 8);
   take(P.r_bsc, n_bsc * 8);
   take(P.r_zoh, n_zoh * 8);
-  take(P.r_x0, (size_t)xoff * P.x_elem());
-  take(P.r_x1, (size_t)xoff * P.x_elem());
+  P.x_buf_bytes = (size_t)xoff * P.x_elem();
+  take(P.r_x0, P.static_state ? 0 : P.x_buf_bytes);
+  take(P.r_x1, P.static_state ? 0 : P.x_buf_bytes);
   if (P.with_backward) {
     const size_t xb = (size_t)xoff * P.x_elem();
     take(P.r_ckpt, xb * P.n_ckpt);
@@ -1316,9 +1323,11 @@ struct TimedLaunch {
   ssm_plan_s& P;
   hipStream_t s;
   int kind;
+  bool on;
   hipEvent_t a = nullptr, b = nullptr;
-  TimedLaunch(ssm_plan_s& P_, hipStream_t s_, int kind_) : P(P_), s(s_), kind(kind_) {
-    if (P.timing) {
+  TimedLaunch(ssm_plan_s& P_, hipStream_t s_, int kind_, bool allowed = true)
+      : P(P_), s(s_), kind(kind_), on(P_.timing && allowed) {
+    if (on) {
       a = take();
       b = take();
       (void)hipEventRecord(a, s);
@@ -1335,7 +1344,7 @@ struct TimedLaunch {
     return e;
   }
   void done() {
-    if (P.timing) {
+    if (on) {
       (void)hipEventRecord(b, s);
       P.trec.push_back(TimingRec{kind, a, b});
     }
@@ -2020,10 +2029,11 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
 
 // the forward apply; x0 (nullable) is x_{-1} of every sequence, packed in
 // sequence order, m of each, in the plan's state type
+// xb0, xb1: the two state buffers (the plan's own, or the static scratch of
+// ssm_cascade_apply_noalloc); timed: record timing events if timing is on
 static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel, const void* x0,
-                             size_t x0_numel, void* y, size_t y_numel, hipStream_t stream) {
-  g_last_error.clear();
-  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+                             size_t x0_numel, void* y, size_t y_numel, hipStream_t stream,
+                             unsigned char* xb0, unsigned char* xb1, bool timed) {
   ssm_plan_s& P = *plan;
   ssm_status st = check_io(P, u, u_dtype, u_numel, y, y_numel, "y");
   if (st != SSM_OK) return st;
@@ -2051,13 +2061,13 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     pp.counters = reinterpret_cast<int32_t*>(meta + P.m_counters);
     pp.cnt_off = reinterpret_cast<const int32_t*>(meta + P.m_cntoff);
     pp.cnt_target = reinterpret_cast<const int32_t*>(meta + P.m_cnttarget);
-    pp.x0 = P.ws + P.r_x0.off;
-    pp.x1 = P.ws + P.r_x1.off;
+    pp.x0 = xb0;
+    pp.x1 = xb1;
     pp.flag = pp.counters + P.n_counters;
     pp.spin_limit = P.spin_limit;
     hipError_t e = launch_zero_i32(pp.counters, P.n_counters + 1, stream);
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");
-    TimedLaunch tl(P, stream, 0);
+    TimedLaunch tl(P, stream, 0, timed);
     e = launch_persist_res(P.compute, pp, P.persistent_grid, P.persist_lds, stream);
     if (e != hipSuccess) return hip_fail(e, "persistent launch");
     tl.done();
@@ -2077,13 +2087,13 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     pp.counters = reinterpret_cast<int32_t*>(meta + P.m_counters);
     pp.cnt_off = reinterpret_cast<const int32_t*>(meta + P.m_cntoff);
     pp.ntiles = reinterpret_cast<const int32_t*>(meta + P.m_ntiles);
-    pp.x0 = P.ws + P.r_x0.off;
-    pp.x1 = P.ws + P.r_x1.off;
+    pp.x0 = xb0;
+    pp.x1 = xb1;
     pp.flag = pp.counters + P.n_counters;
     pp.spin_limit = P.spin_limit;
     hipError_t e = launch_zero_i32(pp.counters, P.n_counters + 1, stream);
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");
-    TimedLaunch tl(P, stream, 0);
+    TimedLaunch tl(P, stream, 0, timed);
     e = launch_persistent(P.compute, pp, P.persistent_grid, stream);
     if (e != hipSuccess) return hip_fail(e, "persistent launch");
     tl.done();
@@ -2099,7 +2109,7 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     hipError_t e = hipSuccess;
     if (!P.class_all_kry[c]) {
       // V^(0) = Bbar U into the first state buffer
-      prm.xout = P.ws + P.r_x0.off;
+      prm.xout = xb0;
       prm.n_tiles = P.class_tile_count[c];
       e = launch_project(kClassMp[c], P.state_f64, P.class_bm[c], prm, stream);
       if (e != hipSuccess) return hip_fail(e, "projection launch");
@@ -2108,8 +2118,8 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     int k_begin = 0;
     if (P.max_kry > 0 && res_supported(kClassMp[c], P.compute)) {
       // the leading stages folded into the input pass, x^(kry) in buffer kry % 2
-      prm.xin = P.ws + P.r_x0.off;
-      prm.xout = P.ws + P.r_x1.off;
+      prm.xin = xb0;
+      prm.xout = xb1;
       if (P.class_input_count[c] > 0) {
         const ResRange* un = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_input) +
                              P.class_input_start[c];
@@ -2129,7 +2139,7 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       unsigned char* meta = P.ws + P.r_meta.off;
       e = launch_inject_x0(kClassMp[c], P.state_f64 != 0, reinterpret_cast<const SeqDev*>(meta + P.m_seqs), P.n_seq,
                            reinterpret_cast<const OpDev*>(meta + P.m_ops), P.at<double>(P.r_pw), x0,
-                           P.ws + P.r_x0.off, P.ws + P.r_x1.off, P.ws + P.r_small.off, y, stream);
+                           xb0, xb1, P.ws + P.r_small.off, y, stream);
       if (e != hipSuccess) return hip_fail(e, "initial state launch");
     }
     // the input of stage kk is in buffer kk % 2 until the first stage pair;
@@ -2138,11 +2148,11 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
     int cur = k_begin & 1;
     for (int kk = k_begin; kk <= P.class_max_last[c];) {
       prm.k = kk;
-      prm.xin = P.ws + (cur ? P.r_x1.off : P.r_x0.off);
-      prm.xout = P.ws + (cur ? P.r_x0.off : P.r_x1.off);
+      prm.xin = (cur ? xb1 : xb0);
+      prm.xout = (cur ? xb0 : xb1);
       prm.n_tiles = P.class_active[c][kk];
       if (P.fold_s[c] > 0 && kk == P.fold_k0[c]) {  // the remaining stages and y in one pass
-        TimedLaunch tl(P, stream, 5);
+        TimedLaunch tl(P, stream, 5, timed);
         const FoldUnit* un = reinterpret_cast<const FoldUnit*>(P.ws + P.r_meta.off + P.m_fold) + P.fold_start[c];
         e = P.fold_wide[c] ? launch_output_fold_wide(kClassMp[c], P.compute, P.state_bf16 != 0, prm, un,
                                                      P.fold_count[c], stream)
@@ -2153,7 +2163,7 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
         break;
       }
       const bool pair = kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
-      TimedLaunch tl(P, stream, pair ? 4 : 0);
+      TimedLaunch tl(P, stream, pair ? 4 : 0, timed);
       if (pair) {
         const PairUnit* un = reinterpret_cast<const PairUnit*>(P.ws + P.r_meta.off + P.m_pair) +
                              P.pair_start[c][kk];
@@ -2171,27 +2181,62 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
   return SSM_OK;
 }
 
+// the plan's own state buffers, or an error for a plan prepared without them
+static ssm_status own_state(ssm_plan plan, const char* what) {
+  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  if (plan->static_state)
+    return fail(SSM_E_NOT_PREPARED,
+                "%s: the plan was prepared with static_state (no state buffers in its workspace); "
+                "apply it with ssm_cascade_apply_noalloc", what);
+  return SSM_OK;
+}
+
 ssm_status ssm_cascade_apply(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
                              void* y, size_t y_numel, hipStream_t stream) {
-  return apply_impl(plan, u, u_dtype, u_numel, nullptr, 0, y, y_numel, stream);
+  g_last_error.clear();
+  ssm_status st = own_state(plan, "ssm_cascade_apply");
+  if (st != SSM_OK) return st;
+  return apply_impl(plan, u, u_dtype, u_numel, nullptr, 0, y, y_numel, stream, plan->ws + plan->r_x0.off,
+                    plan->ws + plan->r_x1.off, true);
 }
 
 ssm_status ssm_cascade_apply_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
                                 const void* x0, size_t x0_numel, void* y, size_t y_numel,
                                 hipStream_t stream) {
-  if (!x0) {
-    g_last_error.clear();
-    return fail(SSM_E_INVALID, "x0 is NULL (ssm_cascade_apply runs from a zero state)");
-  }
-  return apply_impl(plan, u, u_dtype, u_numel, x0, x0_numel, y, y_numel, stream);
+  g_last_error.clear();
+  if (!x0) return fail(SSM_E_INVALID, "x0 is NULL (ssm_cascade_apply runs from a zero state)");
+  ssm_status st = own_state(plan, "ssm_cascade_apply_x0");
+  if (st != SSM_OK) return st;
+  return apply_impl(plan, u, u_dtype, u_numel, x0, x0_numel, y, y_numel, stream, plan->ws + plan->r_x0.off,
+                    plan->ws + plan->r_x1.off, true);
+}
+
+ssm_status ssm_cascade_apply_noalloc(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                     void* y, size_t y_numel, hipStream_t stream) {
+  g_last_error.clear();
+  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  ssm_plan_s& P = *plan;
+  const size_t one = align_up(P.x_buf_bytes);
+  const size_t cap = static_scratch_bytes();
+  if (2 * one > cap)
+    return fail(SSM_E_WORKSPACE,
+                "ssm_cascade_apply_noalloc: the plan's two state buffers need %zu bytes, the static "
+                "scratch holds %zu",
+                2 * one, cap);
+  void* base = nullptr;
+  hipError_t e = static_scratch(&base);
+  if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+  unsigned char* b0 = static_cast<unsigned char*>(base);
+  return apply_impl(plan, u, u_dtype, u_numel, nullptr, 0, y, y_numel, stream, b0, b0 + one, false);
 }
 
 ssm_status ssm_cascade_recursion(ssm_plan plan, const void* u, ssm_dtype u_dtype,
                                  size_t u_numel, void* y, size_t y_numel, hipStream_t stream) {
   g_last_error.clear();
-  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  ssm_status st = own_state(plan, "ssm_cascade_recursion");
+  if (st != SSM_OK) return st;
   ssm_plan_s& P = *plan;
-  ssm_status st = check_io(P, u, u_dtype, u_numel, y, y_numel, "y");
+  st = check_io(P, u, u_dtype, u_numel, y, y_numel, "y");
   if (st != SSM_OK) return st;
   unsigned char* meta = P.ws + P.r_meta.off;
   const SeqDev* seqs_d = reinterpret_cast<const SeqDev*>(meta + P.m_seqs);

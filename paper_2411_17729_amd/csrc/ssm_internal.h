@@ -416,4 +416,10 @@ hipError_t launch_recursion(int mp, int ct, const SeqDev* seqs, int n_seq, const
 // remembered per (kernel, device); safe to call from several threads.
 hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
 
+// The library's static device scratch (state buffers of the allocation-free
+// apply): its size, and its address on the current device (looked up once
+// per device).
+size_t static_scratch_bytes();
+hipError_t static_scratch(void** out);
+
 }  // namespace ssmc
