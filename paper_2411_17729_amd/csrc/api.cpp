@@ -602,6 +602,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     for (int sf = smax; sf >= 2; --sf) {
       const int k0 = max_last - sf + 1, kp = std::max(4, kmin);
       if (k0 < 4 || k0 < kmin) continue;
+      if (sf < 6 && sf > fold_max_stages(kClassMp[c])) continue;  // only the wide kernel folds six
       if (tn.pair_stages != 1 && pair_supported(kClassMp[c], (int)compute) && (k0 - kp) % 2 != 0) continue;
       P.fold_s[c] = sf;
       P.fold_k0[c] = k0;

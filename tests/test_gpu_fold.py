@@ -189,3 +189,18 @@ def test_fold_plan_accounting():
         flops += 2.0 * q * m * float(lags.sum())
     assert math.isclose(info["fold_bytes"], nbytes, rel_tol=1e-12)
     assert math.isclose(info["fold_flops"], flops, rel_tol=1e-12)
+
+
+def test_fold_depth_within_the_narrow_kernel():
+    # p = q = 1 at m = 256: the resident input pass folds stages 0-7, so with
+    # N = 14 a six-stage fold would leave stage 8 unpaired; the planner must
+    # then pick a depth the four-column kernel takes (at most 4 at m = 256),
+    # not five
+    from paper_2411_17729_amd import workloads as W
+    wl = W.batched(seed=8, batch=1, m=256, L=20000, N=14, p=1, q=1)
+    y, info, u = _run(wl)
+    print("fold stages", info["fold_stages"], "input stages", info["input_stages"], flush=True)
+    assert info["input_stages"] == 8 and 2 <= info["fold_stages"] <= 4
+    ref = _oracle(wl)
+    e = max(parity_err(g, r) for g, r in zip(y, ref))
+    assert e <= 2e-2, e
