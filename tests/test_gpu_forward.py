@@ -145,6 +145,14 @@ def test_recursion_matches_oracle(compute):
     _check(wl, compute, recursion=True, tol=1e-12 if compute == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("m,p,L", [(20, 20, 300), (64, 1, 1000), (200, 200, 129), (256, 8, 2500)])
+def test_recursion_fp32_sizes(m, p, L):
+    # every padded size of the FP32 recursion kernel, the widest input (p = m:
+    # the shortest chunks of Bbar u), chunk tails, one and several sequences
+    wl = W.batched(seed=9, batch=2, m=m, L=L, N=max(1, math.ceil(math.log2(L)) - 1), p=p, q=3)
+    _check(wl, "f32", recursion=True, tol=1e-4)
+
+
 def test_stability_given_small():
     # discrete diagonal-plus-rank-2 Abar with one eigenvalue 1 + 1e-5
     wl = W.stability(seed=0, batch=2, m=128, L=4096, N=11)
