@@ -197,7 +197,14 @@ typedef struct {
    * _recursion and _graph_apply then return SSM_E_NOT_PREPARED. Not with
    * with_backward (SSM_E_UNSUPPORTED). 0: the default. */
   int32_t static_state;
-  int32_t reserved;      /* must be 0 */
+  /* 1: the forward apply leaves every sequence's final state x^(N+1) in the
+   * state buffers, so that ssm_cascade_apply_state can return the state of
+   * its last row (to start the next chunk of a stream from it). The passes
+   * that form y without that state (stage pairs, the output fold, BF16 state
+   * between passes) are then not used, and the plan launches per stage
+   * (SSM_LAUNCH_PERSISTENT returns SSM_E_UNSUPPORTED). 0: the default. */
+  int32_t final_state;
+  int32_t reserved[2];   /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -345,6 +352,29 @@ size_t ssm_cascade_param_grad_numel(ssm_plan plan);
 ssm_status ssm_cascade_apply_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
                                 const void* x0, size_t x0_numel, void* y, size_t y_numel,
                                 hipStream_t stream);
+
+/* Forward apply of one chunk of a stream: from the initial state x0 (as
+ * ssm_cascade_apply_x0; NULL for x_{-1} = 0), and returning the state of the
+ * last row, x_last = x_{L-1} of each sequence (eq. (1.2) unrolled: x_{L-1} =
+ * Abar^L x0 + sum_{j<L} Abar^j Bbar u_{L-1-j} when L <= 2^{N+1}). Passing one
+ * chunk's x_last as the next chunk's x0 continues the recursion of eq. (1.2)
+ * across chunks of at most 2^{N+1} rows each, exactly up to rounding.
+ * (Chunks longer than 2^{N+1} rows carry the truncated state of the
+ * cascade instead. The truncated operator H_N itself is streamed without
+ * any carried state by prepending the previous 2^{N+1} - 1 inputs to each
+ * chunk and keeping the last outputs.)
+ *   x0: device, the plan's state type (double for F64 plans, float
+ *       otherwise), the sequences' states packed in sequence order, m_s
+ *       entries each, x0_numel their sum; or NULL (then x0_numel is ignored).
+ *   x_last: device output in the same layout, or NULL. Needs a plan
+ *       prepared with ssm_tuning.final_state = 1 (SSM_E_NOT_PREPARED
+ *       otherwise); may be the same buffer as x0 (x0 is read before x_last
+ *       is written, on the same stream).
+ *   u, y: as for ssm_cascade_apply.
+ * Errors: as ssm_cascade_apply_x0, and SSM_E_INVALID for a wrong x_last_numel. */
+ssm_status ssm_cascade_apply_state(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                   const void* x0, size_t x0_numel, void* y, size_t y_numel,
+                                   void* x_last, size_t x_last_numel, hipStream_t stream);
 
 /* ssm_cascade_apply without any device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses that

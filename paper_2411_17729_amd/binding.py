@@ -57,7 +57,7 @@ class ssm_tuning(C.Structure):
                 ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
                 ("pair_blocks", C.c_int32), ("input_split", C.c_int32), ("state_bf16", C.c_int32),
                 ("fold_stages", C.c_int32), ("spin_limit", C.c_int32), ("static_state", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("final_state", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class ssm_plan_info(C.Structure):
@@ -75,10 +75,11 @@ class ssm_plan_info(C.Structure):
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
                 input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                state_bf16=0, fold_stages=0, spin_limit=0, static_state=0):
+                state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0):
     t = ssm_tuning()
     t.spin_limit = int(spin_limit)
     t.static_state = int(static_state)
+    t.final_state = int(final_state)
     t.launch = int(launch)
     t.stage_kernel = int(stage_kernel)
     t.input_stages = int(input_stages)
@@ -102,7 +103,7 @@ EXPORTS = [
     "ssm_cascade_timing_enable", "ssm_cascade_timing_read", "ssm_cascade_destroy",
     "ssm_cascade_graph_apply", "ssm_cascade_graph_backward", "ssm_cascade_graph_launch",
     "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error", "ssm_cascade_device_status",
-    "ssm_cascade_apply_noalloc",
+    "ssm_cascade_apply_noalloc", "ssm_cascade_apply_state",
 ]
 
 
@@ -132,6 +133,8 @@ def load(path=LIB_PATH):
     lib.ssm_cascade_graph_destroy.argtypes = [vp]
     lib.ssm_cascade_apply.restype = i32
     lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
+    lib.ssm_cascade_apply_state.restype = i32
+    lib.ssm_cascade_apply_state.argtypes = [vp, vp, i32, sz, vp, sz, vp, sz, vp, sz, vp]
     lib.ssm_cascade_apply_noalloc.restype = i32
     lib.ssm_cascade_apply_noalloc.argtypes = [vp, vp, i32, sz, vp, sz, vp]
     lib.ssm_cascade_apply_x0.restype = i32
@@ -211,6 +214,12 @@ def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every,
 def ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
     _check(load().ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
            "ssm_cascade_apply")
+
+
+def ssm_cascade_apply_state(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, y_ptr, y_numel, xl_ptr, xl_numel,
+                            stream):
+    _check(load().ssm_cascade_apply_state(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, y_ptr, y_numel,
+                                          xl_ptr, xl_numel, stream), "ssm_cascade_apply_state")
 
 
 def ssm_cascade_apply_noalloc(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):

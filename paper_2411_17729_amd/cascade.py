@@ -59,7 +59,7 @@ class CascadePlan:
                  compute: str = "f32", with_backward: bool = False, ckpt_every: int = 0,
                  device="cuda", launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto",
                  input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                 state_bf16=0, fold_stages=0, spin_limit=0, static_state=0):
+                 state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0):
         if not torch.cuda.is_available():
             raise RuntimeError("the fast-cascade library needs a ROCm GPU")
         B.load()
@@ -93,7 +93,7 @@ class CascadePlan:
             if isinstance(stage_kernel, str) else int(stage_kernel)
         self.tuning = B.make_tuning(mode, tile_rows, sk, input_stages, chain_blocks, pair_stages,
                                     pair_blocks, input_split, state_bf16, fold_stages, spin_limit,
-                                    static_state)
+                                    static_state, final_state)
         nbytes = B.ssm_cascade_workspace_bytes(layout.descs, self.disc, self.compute,
                                                with_backward, ckpt_every, self.tuning)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -133,6 +133,28 @@ class CascadePlan:
             B.ssm_cascade_apply_x0(self.plan, u.data_ptr(), self._u_code(u), u.numel(), x0.data_ptr(),
                                    x0.numel(), out.data_ptr(), out.numel(), _stream())
         return out
+
+    def state_numel(self) -> int:
+        """Entries of the packed per-sequence states (x0, x_last): m of each."""
+        return sum(int(d.m) for d in self.layout.descs)
+
+    def apply_state(self, u: torch.Tensor, x0: Optional[torch.Tensor] = None,
+                    out: Optional[torch.Tensor] = None, x_last: Optional[torch.Tensor] = None):
+        """One chunk of a stream: y from the initial states x0 (packed, or
+        None for zero), and the states of the sequences' last rows (needs a
+        plan made with final_state=1). Returns (y, x_last)."""
+        u = self._check_u(u)
+        if out is None:
+            out = torch.empty(self.layout.y_numel, dtype=self.state_dtype, device=self.device)
+        if x_last is None:
+            x_last = torch.empty(self.state_numel(), dtype=self.state_dtype, device=self.device)
+        for t in ((x0,) if x0 is not None else ()) + (x_last,):
+            if t.dtype != self.state_dtype or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("x0 and x_last must be contiguous device tensors of the state dtype")
+        B.ssm_cascade_apply_state(self.plan, u.data_ptr(), self._u_code(u), u.numel(),
+                                  x0.data_ptr() if x0 is not None else None, x0.numel() if x0 is not None else 0,
+                                  out.data_ptr(), out.numel(), x_last.data_ptr(), x_last.numel(), _stream())
+        return out, x_last
 
     def apply_noalloc(self, u: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
         """apply() with the state buffers taken from the library's static
@@ -259,7 +281,7 @@ class CascadePlan:
 def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, device="cuda",
                       launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto", input_stages=0,
                       chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0, state_bf16=0,
-                      fold_stages=0, disc=None, spin_limit=0, static_state=0):
+                      fold_stages=0, disc=None, spin_limit=0, static_state=0, final_state=0):
     """Builds the layout and plan of a ``workloads.Workload`` (discretization:
     the workload's, "given" or "trapezoid", unless ``disc`` names one)."""
     dims = [(ps.m, ps.p, ps.q) for ps in wl.sets]
@@ -273,7 +295,7 @@ def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, devi
                        input_stages=input_stages, chain_blocks=chain_blocks,
                        pair_stages=pair_stages, pair_blocks=pair_blocks, input_split=input_split,
                        state_bf16=state_bf16, fold_stages=fold_stages, spin_limit=spin_limit,
-                       static_state=static_state)
+                       static_state=static_state, final_state=final_state)
 
 
 def pack_u(wl, dtype=torch.float32, device="cuda"):

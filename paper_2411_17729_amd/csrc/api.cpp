@@ -81,6 +81,7 @@ struct ssm_plan_s {
   int state_f64 = 0;     // state / io element is double
   int state_bf16 = 0;    // the forward apply keeps the state between passes in BF16
   int static_state = 0;  // the workspace holds no state buffers (ssm_cascade_apply_noalloc only)
+  int final_state = 0;   // the forward apply leaves each sequence's final state in the buffers
   size_t x_buf_bytes = 0;  // bytes of one state buffer
   int disc = 0;
   int with_backward = 0, ckpt_every = 1;
@@ -242,7 +243,20 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (st != SSM_OK) return st;
   ssm_tuning tn{};
   if (tuning) tn = *tuning;
-  if (tn.reserved != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.reserved[0] != 0 || tn.reserved[1] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.final_state < 0 || tn.final_state > 1)
+    return fail(SSM_E_INVALID, "final_state = %d: supported 0 or 1", tn.final_state);
+  if (tn.final_state) {
+    // the final state is kept by the per-stage kernels' epilogues only: no
+    // stage pairs, output fold or BF16 state, and per-stage launches
+    if (tn.launch == SSM_LAUNCH_PERSISTENT)
+      return fail(SSM_E_UNSUPPORTED, "final_state needs per-stage launches (launch is persistent)");
+    tn.launch = SSM_LAUNCH_PER_STAGE;
+    tn.pair_stages = 1;
+    tn.fold_stages = -1;
+    tn.state_bf16 = 0;
+  }
+  P.final_state = tn.final_state;
   if (tn.static_state < 0 || tn.static_state > 1)
     return fail(SSM_E_INVALID, "static_state = %d: supported 0 or 1", tn.static_state);
   if (tn.static_state && with_backward)
@@ -2034,13 +2048,21 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
 // ssm_cascade_apply_noalloc); timed: record timing events if timing is on
 static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel, const void* x0,
                              size_t x0_numel, void* y, size_t y_numel, hipStream_t stream,
-                             unsigned char* xb0, unsigned char* xb1, bool timed) {
+                             unsigned char* xb0, unsigned char* xb1, bool timed, void* x_last = nullptr,
+                             size_t x_last_numel = 0) {
   ssm_plan_s& P = *plan;
   ssm_status st = check_io(P, u, u_dtype, u_numel, y, y_numel, "y");
   if (st != SSM_OK) return st;
+  size_t want_state = 0;
+  for (int i = 0; i < P.n_seq; ++i) want_state += (size_t)P.ops[P.seqs[i].op].m;
+  if (x_last) {
+    if (!P.final_state)
+      return fail(SSM_E_NOT_PREPARED, "x_last needs a plan prepared with ssm_tuning.final_state = 1");
+    if (x_last_numel != want_state)
+      return fail(SSM_E_INVALID, "x_last_numel %zu, the sequences' states need %zu", x_last_numel, want_state);
+  }
   if (x0) {
-    size_t want = 0;
-    for (int i = 0; i < P.n_seq; ++i) want += (size_t)P.ops[P.seqs[i].op].m;
+    const size_t want = want_state;
     if (x0_numel != want)
       return fail(SSM_E_INVALID, "x0_numel %zu, the sequences' states need %zu", x0_numel, want);
     if (P.launch == SSM_LAUNCH_PERSISTENT)
@@ -2115,7 +2137,8 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       e = launch_project(kClassMp[c], P.state_f64, P.class_bm[c], prm, stream);
       if (e != hipSuccess) return hip_fail(e, "projection launch");
     }
-    prm.flags = SF_EPILOGUE;
+    // (final_state: every epilogue also stores the state rows it finishes)
+    prm.flags = SF_EPILOGUE | (P.final_state ? SF_STORE_AT_EPI : 0);
     int k_begin = 0;
     if (P.max_kry > 0 && res_supported(kClassMp[c], P.compute)) {
       // the leading stages folded into the input pass, x^(kry) in buffer kry % 2
@@ -2140,7 +2163,7 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       unsigned char* meta = P.ws + P.r_meta.off;
       e = launch_inject_x0(kClassMp[c], P.state_f64 != 0, reinterpret_cast<const SeqDev*>(meta + P.m_seqs), P.n_seq,
                            reinterpret_cast<const OpDev*>(meta + P.m_ops), P.at<double>(P.r_pw), x0,
-                           xb0, xb1, P.ws + P.r_small.off, y, stream);
+                           xb0, xb1, P.ws + P.r_small.off, y, P.final_state != 0, stream);
       if (e != hipSuccess) return hip_fail(e, "initial state launch");
     }
     // the input of stage kk is in buffer kk % 2 until the first stage pair;
@@ -2179,6 +2202,12 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       kk += pair ? 2 : 1;
     }
   }
+  if (x_last) {  // row L - 1 of each sequence's final state (buffer (last + 1) mod 2)
+    unsigned char* meta = P.ws + P.r_meta.off;
+    hipError_t e = launch_gather_last(P.state_f64 != 0, reinterpret_cast<const SeqDev*>(meta + P.m_seqs), P.n_seq,
+                                      reinterpret_cast<const OpDev*>(meta + P.m_ops), xb0, xb1, x_last, stream);
+    if (e != hipSuccess) return hip_fail(e, "final state launch");
+  }
   return SSM_OK;
 }
 
@@ -2210,6 +2239,16 @@ ssm_status ssm_cascade_apply_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype,
   if (st != SSM_OK) return st;
   return apply_impl(plan, u, u_dtype, u_numel, x0, x0_numel, y, y_numel, stream, plan->ws + plan->r_x0.off,
                     plan->ws + plan->r_x1.off, true);
+}
+
+ssm_status ssm_cascade_apply_state(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                   const void* x0, size_t x0_numel, void* y, size_t y_numel, void* x_last,
+                                   size_t x_last_numel, hipStream_t stream) {
+  g_last_error.clear();
+  ssm_status st = own_state(plan, "ssm_cascade_apply_state");
+  if (st != SSM_OK) return st;
+  return apply_impl(plan, u, u_dtype, u_numel, x0, x0 ? x0_numel : 0, y, y_numel, stream,
+                    plan->ws + plan->r_x0.off, plan->ws + plan->r_x1.off, true, x_last, x_last_numel);
 }
 
 ssm_status ssm_cascade_apply_noalloc(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,

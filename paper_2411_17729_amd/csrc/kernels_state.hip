@@ -12,7 +12,8 @@
 // Where the first pass already ran every stage of a sequence and formed its
 // output (kry = last + 1), no later pass reads that state, so the free
 // response goes straight into the output instead: y_l += C w_l, y = C x + D u
-// being linear in the state.
+// being linear in the state (and, when the plan keeps final states, into the
+// state rows as well).
 #include "ssm_internal.h"
 
 namespace ssmc {
@@ -20,7 +21,7 @@ namespace ssmc {
 template <typename X>
 __global__ __launch_bounds__(256) void k_inject_x0(const SeqDev* seqs, const OpDev* ops, const double* pw,
                                                    const X* x0, int mp_class, X* buf0, X* buf1,
-                                                   const X* small, X* y) {
+                                                   const X* small, X* y, int keep_state) {
   __shared__ double w[2][256];
   const int s = blockIdx.x;
   const SeqDev sq = seqs[s];
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void k_inject_x0(const SeqDev* seqs, const OpD
     if (e < m) {
       const double* row = A + (int64_t)e * mp;
       for (int k = 0; k < m; ++k) acc = fma(row[k], src[k], acc);
-      if (!to_y) {
+      if (!to_y || keep_state) {
         X* dst = xb + l * mp + e;
         *dst = (X)((double)*dst + acc);
       }
@@ -64,17 +65,51 @@ __global__ __launch_bounds__(256) void k_inject_x0(const SeqDev* seqs, const OpD
 
 hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const void* x0, void* buf0, void* buf1, const void* small,
-                            void* y, hipStream_t st) {
+                            void* y, bool keep_state, hipStream_t st) {
   if (n_seq <= 0) return hipSuccess;
   if (mp_class > 256) return hipErrorInvalidValue;
   if (f64)
     hipLaunchKernelGGL(k_inject_x0<double>, dim3(n_seq), dim3(256), 0, st, seqs, ops, pw,
                        static_cast<const double*>(x0), mp_class, static_cast<double*>(buf0),
-                       static_cast<double*>(buf1), static_cast<const double*>(small), static_cast<double*>(y));
+                       static_cast<double*>(buf1), static_cast<const double*>(small), static_cast<double*>(y),
+                       (int)keep_state);
   else
     hipLaunchKernelGGL(k_inject_x0<float>, dim3(n_seq), dim3(256), 0, st, seqs, ops, pw,
                        static_cast<const float*>(x0), mp_class, static_cast<float*>(buf0),
-                       static_cast<float*>(buf1), static_cast<const float*>(small), static_cast<float*>(y));
+                       static_cast<float*>(buf1), static_cast<const float*>(small), static_cast<float*>(y),
+                       (int)keep_state);
+  return hipGetLastError();
+}
+
+// The state of a sequence's last row, x_{L-1}, for the next chunk of a
+// stream. With final states kept, the epilogue of a sequence's last stage
+// (or of its input pass, when that pass runs every stage) has stored the
+// state after that stage, and the state after stage k lives in buffer
+// (k + 1) mod 2 (V^(0) = Bbar u, "after stage -1", in buffer 0). One
+// workgroup per sequence copies row L - 1 (its m entries) into x_last.
+template <typename X>
+__global__ __launch_bounds__(256) void k_gather_last(const SeqDev* seqs, const OpDev* ops, const X* buf0,
+                                                     const X* buf1, X* x_last) {
+  const int s = blockIdx.x;
+  const SeqDev sq = seqs[s];
+  const OpDev o = ops[sq.op];
+  int64_t off = 0;
+  for (int i = 0; i < s; ++i) off += ops[seqs[i].op].m;
+  const X* src = ((sq.last + 1) & 1 ? buf1 : buf0) + sq.x_off + (sq.L - 1) * o.mp;
+  for (int e = threadIdx.x; e < o.m; e += 256) x_last[off + e] = src[e];
+}
+
+hipError_t launch_gather_last(bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops, const void* buf0,
+                              const void* buf1, void* x_last, hipStream_t st) {
+  if (n_seq <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_gather_last<double>, dim3(n_seq), dim3(256), 0, st, seqs, ops,
+                       static_cast<const double*>(buf0), static_cast<const double*>(buf1),
+                       static_cast<double*>(x_last));
+  else
+    hipLaunchKernelGGL(k_gather_last<float>, dim3(n_seq), dim3(256), 0, st, seqs, ops,
+                       static_cast<const float*>(buf0), static_cast<const float*>(buf1),
+                       static_cast<float*>(x_last));
   return hipGetLastError();
 }
 

@@ -406,7 +406,12 @@ hipError_t launch_scatter(const ScatterJob* jobs, int n_jobs, const int32_t* set
 // when f64, else FP32).
 hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const void* x0, void* buf0, void* buf1, const void* small,
-                            void* y, hipStream_t st);
+                            void* y, bool keep_state, hipStream_t st);
+// Row L - 1 of each sequence's final state, left by a plan with the final
+// state kept in buffer (last + 1) mod 2, packed into x_last (m entries per
+// sequence, in sequence order), in the plan's state type.
+hipError_t launch_gather_last(bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops, const void* buf0,
+                              const void* buf1, void* x_last, hipStream_t st);
 hipError_t launch_recursion(int mp, int ct, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const double* bbar, const void* u,
                             int u_dtype, void* xout, hipStream_t s);

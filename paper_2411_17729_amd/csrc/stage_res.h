@@ -379,7 +379,7 @@ __device__ __forceinline__ void krylov_range(const StageParams& prm, const ResRa
           }
         }
       }
-      if (lv && !epi) {
+      if (lv && (!epi || (prm.flags & SF_STORE_AT_EPI))) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
           *reinterpret_cast<f32x4*>(xo + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];
@@ -449,7 +449,7 @@ __device__ __forceinline__ void krylov_range(const StageParams& prm, const ResRa
         }
       }
     }
-    if (lv && !epi) {
+    if (lv && (!epi || (prm.flags & SF_STORE_AT_EPI))) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
         *reinterpret_cast<f32x4*>(xo + l * MP + n0 + nb * 16 + 4 * g) = acc[nb];

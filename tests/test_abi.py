@@ -104,6 +104,7 @@ def test_null_plan_calls(lib):
     assert lib.ssm_cascade_apply(None, None, 1, 0, None, 0, None) == B.SSM_E_NOT_PREPARED
     assert lib.ssm_cascade_recursion(None, None, 1, 0, None, 0, None) == B.SSM_E_NOT_PREPARED
     assert lib.ssm_cascade_apply_noalloc(None, None, 1, 0, None, 0, None) == B.SSM_E_NOT_PREPARED
+    assert lib.ssm_cascade_apply_state(None, None, 1, 0, None, 0, None, 0, None, 0, None) == B.SSM_E_NOT_PREPARED
     assert lib.ssm_cascade_destroy(None) == B.SSM_OK
     assert lib.ssm_cascade_param_grad_numel(None) == 0
     assert "INVALID" in lib.ssm_status_string(B.SSM_E_INVALID).decode()
@@ -131,8 +132,14 @@ def test_tuning_is_validated(lib):
     t = B.make_tuning(tile_rows=(0, 64, 0, 0))  # half of the default 128 for m <= 64
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
     t = B.make_tuning()
-    t.reserved = 1
+    t.reserved[1] = 1
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
+    # final_state: 0 or 1, not with an explicitly persistent launch
+    for bad in (B.make_tuning(final_state=2), B.make_tuning(final_state=-1),
+                B.make_tuning(final_state=1, launch=B.SSM_LAUNCH_PERSISTENT)):
+        assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(bad)) == 0
+    t = B.make_tuning(final_state=1)
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
     # static_state: 0 or 1, the workspace without the two state buffers
     # (4096 rows of 64 FP32 entries each), not with the backward
     for bad in (B.make_tuning(static_state=2), B.make_tuning(static_state=-1)):

@@ -204,3 +204,33 @@ def test_fold_depth_within_the_narrow_kernel():
     ref = _oracle(wl)
     e = max(parity_err(g, r) for g, r in zip(y, ref))
     assert e <= 2e-2, e
+
+
+# The six-stage fold with BF16 state over a range of input widths. (m, p, q,
+# L, N, u type), each a plan with the split input pass, so that the state can
+# be BF16: odd L, p = 16, p = 4 in BF16 (16-byte pieces of u straddle rows),
+# q not a multiple of 4 (scalar y stores), and p = 32.
+STREAM_SPEC = [(256, 16, 8, 8191, 12, "f32"), (256, 16, 3, 8191, 12, "bf16"), (256, 4, 5, 20001, 14, "bf16"),
+               (256, 8, 5, 12001, 13, "f32"), (250, 32, 8, 4001, 11, "f32")]
+
+
+@pytest.mark.parametrize("spec", STREAM_SPEC, ids=lambda s: "m{}_p{}_q{}_L{}_N{}_{}".format(*s))
+def test_fold_bf16_state_input_widths(spec):
+    from paper_2411_17729_amd import workloads as W
+    m, p, q, L, N, ut = spec
+    wl = W.batched(seed=81 + p, batch=2, m=m, L=L, N=N, p=p, q=q)
+    y, info, u = _run(wl, ut, state_bf16=1)
+    print("spec", spec, "fold", info["fold_stages"], "state", info["state_dtype"], flush=True)
+    assert info["fold_stages"] == 6 and info["state_dtype"] == B.SSM_BF16
+    if ut == "bf16":
+        _bf16_inputs(wl, u)
+    ref = _oracle(wl)
+    e = max(parity_err(g, r) for g, r in zip(y, ref))
+    Dref = [r - s.u.astype(np.float32).astype(np.float64) @ wl.sets[0].D.T for r, s in zip(ref, wl.seqs)]
+    Dgot = [g - s.u.astype(np.float32).astype(np.float64) @ wl.sets[0].D.T for g, s in zip(y, wl.seqs)]
+    e_x = max(parity_err(g, r) for g, r in zip(Dgot, Dref))
+    print("rel err y", e, "state part", e_x, flush=True)
+    assert e <= 2e-2 and e_x <= 2e-2, (e, e_x)
+    # D u row by row near the end of each sequence (the inputs' last pieces)
+    for g_, r_ in zip(y, ref):
+        assert np.allclose(g_[-40:], r_[-40:], rtol=0, atol=2e-2 * np.abs(r_).max())
