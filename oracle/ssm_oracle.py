@@ -372,16 +372,17 @@ def transfer_truncated(Abar, Bbar, C, D, z, N):
 # --------------------------------------------------------------------------
 # Reverse-mode derivatives (not in the paper)
 # --------------------------------------------------------------------------
-def grads_recursion(Abar, Bbar, C, D, u, dy):
-    """Gradients of sum(dy * y) for y = recursion(...), by backpropagation in time.
+def grads_recursion(Abar, Bbar, C, D, u, dy, x0=None):
+    """Gradients of sum(dy * y) for y = recursion(..., x0), by backpropagation in time.
 
     lambda_l = C^T dy_l + Abar^T lambda_{l+1}  (lambda_L = 0),
-    gAbar = sum_{l>=1} lambda_l x_{l-1}^T,  gBbar = sum_l lambda_l u_l^T,
-    gC = sum_l dy_l x_l^T,  gD = sum_l dy_l u_l^T,  gu_l = Bbar^T lambda_l + D^T dy_l.
+    gAbar = sum_{l>=0} lambda_l x_{l-1}^T (x_{-1} = x0),  gBbar = sum_l lambda_l u_l^T,
+    gC = sum_l dy_l x_l^T,  gD = sum_l dy_l u_l^T,  gu_l = Bbar^T lambda_l + D^T dy_l,
+    gx0 = Abar^T lambda_0 (the initial state enters only through x_0 = Abar x0 + ...).
 
     When 2^(N+1) >= L the cascade output equals the recursion output, so these
     are also the cascade's gradients.
-    Returns dict(u, Abar, Bbar, C, D).
+    Returns dict(u, Abar, Bbar, C, D, x0); x0 is None when x0 is None.
     """
     Abar, Bbar, C, D = _f64(Abar), _f64(Bbar), _f64(C), _f64(D)
     if Bbar.ndim == 1:
@@ -390,7 +391,7 @@ def grads_recursion(Abar, Bbar, C, D, u, dy):
     dy = _as_matrix_u(dy)
     L = u.shape[0]
     m = Abar.shape[0]
-    _, xs = recursion(Abar, Bbar, C, D, u)
+    _, xs = recursion(Abar, Bbar, C, D, u, x0)
     lam = np.zeros(m)
     gA = np.zeros((m, m))
     gB = np.zeros_like(Bbar)
@@ -399,20 +400,26 @@ def grads_recursion(Abar, Bbar, C, D, u, dy):
         lam = C.T @ dy[n] + Abar.T @ lam
         if n >= 1:
             gA += np.outer(lam, xs[n - 1])
+        elif x0 is not None:
+            gA += np.outer(lam, _f64(x0).reshape(m))
         gB += np.outer(lam, u[n])
         gu[n] = Bbar.T @ lam + D.T @ dy[n]
     gC = dy.T @ xs
     gD = dy.T @ u
-    return {"u": gu, "Abar": gA, "Bbar": gB, "C": gC, "D": gD}
+    gx0 = Abar.T @ lam if x0 is not None else None
+    return {"u": gu, "Abar": gA, "Bbar": gB, "C": gC, "D": gD, "x0": gx0}
 
 
-def grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N):
-    """Gradients of sum(dy * y) for y = truncated_sum(..., N), by brute force.
+def grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N, x0=None):
+    """Gradients of sum(dy * y) for y = truncated_sum(..., N, x0), by brute force.
 
     With T = 2^(N+1) and x_l = sum_{j<=min(l,T-1)} Abar^j Bbar u_{l-j}:
     d(Abar^j) = sum_{a+b=j-1} Abar^a dAbar Abar^b, so
         gAbar = sum_l sum_{1<=j<=min(l,T-1)} sum_{a+b=j-1} (Abar^T)^a g_l (Abar^b Bbar u_{l-j})^T
-    with g_l = C^T dy_l. Cost O(L T^2 m^3): tiny inputs only.
+    with g_l = C^T dy_l. An initial state adds Abar^(l+1) x0 to x_l for l < T
+    (``free_response``): gx0 = sum_{l<T} (Abar^(l+1))^T g_l and
+    gAbar += sum_{l<T} sum_{a+b=l} (Abar^T)^a g_l (Abar^b x0)^T.
+    Cost O(L T^2 m^3): tiny inputs only.
     """
     Abar, Bbar, C, D = _f64(Abar), _f64(Bbar), _f64(C), _f64(D)
     if Bbar.ndim == 1:
@@ -440,24 +447,33 @@ def grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N):
             for a in range(j):
                 b = j - 1 - a
                 gA += np.outer(pw[a].T @ g[l], pw[b] @ Bbar @ u[l - j])
+    gx0 = None
+    if x0 is not None:
+        x0 = _f64(x0).reshape(m)
+        gx0 = np.zeros(m)
+        for l in range(min(L, T)):
+            xs[l] += pw[l + 1] @ x0
+            gx0 += pw[l + 1].T @ g[l]
+            for a in range(l + 1):
+                gA += np.outer(pw[a].T @ g[l], pw[l - a] @ x0)
     gu += dy @ D
     gC = dy.T @ xs
     gD = dy.T @ u
-    return {"u": gu, "Abar": gA, "Bbar": gB, "C": gC, "D": gD}
+    return {"u": gu, "Abar": gA, "Bbar": gB, "C": gC, "D": gD, "x0": gx0}
 
 
-def grads_full(A, B, C, D, delta, u, dy, N=None, disc="trapezoid"):
-    """Gradients of sum(dy * y) w.r.t. (u, A, B, C, D) through the trapezoidal
-    (disc = "trapezoid") or exponential ("zoh") discretization. Uses BPTT when
-    N is None or 2^(N+1) >= L, else brute force.
+def grads_full(A, B, C, D, delta, u, dy, N=None, disc="trapezoid", x0=None):
+    """Gradients of sum(dy * y) w.r.t. (u, A, B, C, D, and x0 when given)
+    through the trapezoidal (disc = "trapezoid") or exponential ("zoh")
+    discretization. Uses BPTT when N is None or 2^(N+1) >= L, else brute force.
     """
     Abar, Bbar = (trapezoid if disc == "trapezoid" else zoh)(A, B, delta)
     u = _as_matrix_u(u)
     L = u.shape[0]
     if N is None or (1 << (N + 1)) >= L:
-        g = grads_recursion(Abar, Bbar, C, D, u, dy)
+        g = grads_recursion(Abar, Bbar, C, D, u, dy, x0)
     else:
-        g = grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N)
+        g = grads_truncated_bruteforce(Abar, Bbar, C, D, u, dy, N, x0)
     gA, gB = (trapezoid_adjoint if disc == "trapezoid" else zoh_adjoint)(A, B, delta, g["Abar"], g["Bbar"])
     return {"u": g["u"], "A": gA, "B": gB, "C": g["C"], "D": g["D"],
-            "Abar": g["Abar"], "Bbar": g["Bbar"]}
+            "Abar": g["Abar"], "Bbar": g["Bbar"], "x0": g["x0"]}

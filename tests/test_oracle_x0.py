@@ -80,3 +80,68 @@ def test_truncated_sum_with_state_is_the_cascade_window():
     # (x0 treated as an input) fails the brute force
     zb = O.free_response(A, C, B @ np.ones(3), 30, 4)
     assert np.abs(zb[0] - C @ A @ x0).max() > 1e-3
+
+
+def _loss(A, B, C, D, u, dy, N, x0, truncated):
+    if truncated:
+        y = O.truncated_sum(A, B, C, D, u, N, x0=x0)
+    else:
+        y, _ = O.recursion(A, B, C, D, u, x0=x0)
+    return float(np.sum(dy * y))
+
+
+def _fd(f, X, h=1e-6):
+    g = np.zeros_like(X)
+    for idx in np.ndindex(X.shape):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[idx] += h
+        Xm[idx] -= h
+        g[idx] = (f(Xp) - f(Xm)) / (2 * h)
+    return g
+
+
+def test_initial_state_gradients_by_finite_differences():
+    # d sum(dy * y) / d(x0, Abar, C) with a nonzero initial state, for the
+    # recursion (BPTT) and for the truncated sum with T < L (brute force):
+    # central differences (h = 1e-6, FP64) of the forward oracles
+    rng = np.random.default_rng(7)
+    A, B, C, D = _system(rng, m=4, p=2, q=3)
+    u = rng.standard_normal((11, 2))
+    dy = rng.standard_normal((11, 3))
+    x0 = rng.standard_normal(4)
+    for N, truncated in ((None, False), (1, True)):  # T = 4 < L = 11
+        g = O.grads_recursion(A, B, C, D, u, dy, x0) if not truncated else \
+            O.grads_truncated_bruteforce(A, B, C, D, u, dy, N, x0)
+        fx = _fd(lambda X: _loss(A, B, C, D, u, dy, N, X, truncated), x0)
+        fa = _fd(lambda X: _loss(X, B, C, D, u, dy, N, x0, truncated), A)
+        fc = _fd(lambda X: _loss(A, B, X, D, u, dy, N, x0, truncated), C)
+        fb = _fd(lambda X: _loss(A, X, C, D, u, dy, N, x0, truncated), B)
+        np.testing.assert_allclose(g["x0"], fx, rtol=1e-6, atol=1e-8)
+        np.testing.assert_allclose(g["Abar"], fa, rtol=1e-6, atol=1e-8)
+        np.testing.assert_allclose(g["C"], fc, rtol=1e-6, atol=1e-8)
+        np.testing.assert_allclose(g["Bbar"], fb, rtol=1e-6, atol=1e-8)
+        # planted mistakes: x0's gradient without the leading Abar^T, and
+        # gAbar without the x0 term, both miss the differences
+        lam0 = np.linalg.solve(A.T, g["x0"])
+        assert np.abs(lam0 - fx).max() > 1e-3
+        if not truncated:
+            assert np.abs((g["Abar"] - np.outer(lam0, x0)) - fa).max() > 1e-3
+    # with x0 = None the x0 entry is absent and the rest is unchanged
+    g0 = O.grads_recursion(A, B, C, D, u, dy)
+    gz = O.grads_recursion(A, B, C, D, u, dy, np.zeros(4))
+    assert g0["x0"] is None
+    np.testing.assert_allclose(g0["Abar"], gz["Abar"], rtol=0, atol=1e-14)
+
+
+def test_initial_state_gradient_diagonal_closed_form():
+    # Abar = diag(lam), C = I, D = 0: y_l = lam^(l+1) x0 + ..., so
+    # d sum(dy * y) / dx0 = sum_{l < min(L, T)} lam^(l+1) dy_l
+    lam = np.array([0.9, -0.5, 0.7])
+    L, N = 9, 2  # T = 8 < L: the last row's free response is cut
+    dy = np.random.default_rng(8).standard_normal((L, 3))
+    u = np.zeros((L, 1))
+    g = O.grads_truncated_bruteforce(np.diag(lam), np.zeros((3, 1)), np.eye(3), np.zeros((3, 1)), u, dy, N,
+                                     x0=np.ones(3))
+    l = np.arange(8)[:, None]
+    want = np.sum(lam[None, :] ** (l + 1) * dy[:8], axis=0)
+    np.testing.assert_allclose(g["x0"], want, rtol=1e-14, atol=1e-15)
