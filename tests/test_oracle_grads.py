@@ -44,10 +44,15 @@ def test_grads_full_match_central_differences(L, N):
 def test_bptt_equals_bruteforce_when_window_covers_sequence():
     wl = W.random_small(seed=4, m=4, p=2, q=2, L=15, N=3)
     ps, s = wl.sets[0], wl.seqs[0]
-    a = O.grads_recursion(ps.A, ps.B, ps.C, ps.D, s.u, wl.dy[0])
-    b = O.grads_truncated_bruteforce(ps.A, ps.B, ps.C, ps.D, s.u, wl.dy[0], 3)
-    for k in a:
-        assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-12), k
+    # with and without an initial state (then also its gradient)
+    for x0 in (None, np.random.default_rng(5).standard_normal(4)):
+        a = O.grads_recursion(ps.A, ps.B, ps.C, ps.D, s.u, wl.dy[0], x0)
+        b = O.grads_truncated_bruteforce(ps.A, ps.B, ps.C, ps.D, s.u, wl.dy[0], 3, x0)
+        for k in a:
+            if a[k] is None:
+                assert x0 is None and b[k] is None, k
+                continue
+            assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-12), k
 
 
 def test_truncated_grads_differ_from_bptt_when_truncating():
