@@ -331,6 +331,22 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
                                 void* du, double* grad_params, size_t grad_numel,
                                 hipStream_t stream);
 
+/* ssm_cascade_backward for the apply from an initial state x_{-1} = x0
+ * (ssm_cascade_apply_x0 / _apply_state): the initial state enters the
+ * forward as the input Abar x0 at row 0 (eq. (1.2) unrolled), so with g =
+ * dL/dV^(0) from the adjoint cascade, dL/dx0 = Abar^T g_0, dL/dAbar gains
+ * g_0 x0^T, and dL/dC sees the free response through the recomputed
+ * states.
+ *   x0: device, packed states as for ssm_cascade_apply_x0, or NULL (zero).
+ *   dx0: device output in the same layout (the state type), or NULL.
+ *   the rest: as ssm_cascade_backward.
+ * Errors: as ssm_cascade_backward, and SSM_E_INVALID for a wrong x0_numel
+ * or dx0_numel. */
+ssm_status ssm_cascade_backward_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                   const void* x0, size_t x0_numel, const void* dy, size_t dy_numel,
+                                   void* du, void* dx0, size_t dx0_numel, double* grad_params,
+                                   size_t grad_numel, hipStream_t stream);
+
 /* Number of doubles of the flat parameter-gradient buffer of a plan. */
 size_t ssm_cascade_param_grad_numel(ssm_plan plan);
 

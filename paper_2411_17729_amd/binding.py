@@ -103,7 +103,7 @@ EXPORTS = [
     "ssm_cascade_timing_enable", "ssm_cascade_timing_read", "ssm_cascade_destroy",
     "ssm_cascade_graph_apply", "ssm_cascade_graph_backward", "ssm_cascade_graph_launch",
     "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error", "ssm_cascade_device_status",
-    "ssm_cascade_apply_noalloc", "ssm_cascade_apply_state",
+    "ssm_cascade_apply_noalloc", "ssm_cascade_apply_state", "ssm_cascade_backward_x0",
 ]
 
 
@@ -133,6 +133,8 @@ def load(path=LIB_PATH):
     lib.ssm_cascade_graph_destroy.argtypes = [vp]
     lib.ssm_cascade_apply.restype = i32
     lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
+    lib.ssm_cascade_backward_x0.restype = i32
+    lib.ssm_cascade_backward_x0.argtypes = [vp, vp, i32, sz, vp, sz, vp, sz, vp, vp, sz, vp, sz, vp]
     lib.ssm_cascade_apply_state.restype = i32
     lib.ssm_cascade_apply_state.argtypes = [vp, vp, i32, sz, vp, sz, vp, sz, vp, sz, vp]
     lib.ssm_cascade_apply_noalloc.restype = i32
@@ -214,6 +216,12 @@ def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every,
 def ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
     _check(load().ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
            "ssm_cascade_apply")
+
+
+def ssm_cascade_backward_x0(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, dy_ptr, dy_numel, du_ptr, dx0_ptr,
+                            dx0_numel, grad_ptr, grad_numel, stream):
+    _check(load().ssm_cascade_backward_x0(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, dy_ptr, dy_numel, du_ptr,
+                                          dx0_ptr, dx0_numel, grad_ptr, grad_numel, stream), "ssm_cascade_backward_x0")
 
 
 def ssm_cascade_apply_state(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, y_ptr, y_numel, xl_ptr, xl_numel,

@@ -173,18 +173,32 @@ class CascadePlan:
         return out
 
     # -- backward --------------------------------------------------------
-    def backward(self, u: torch.Tensor, dy: torch.Tensor, want_du=True, want_params=True):
+    def backward(self, u: torch.Tensor, dy: torch.Tensor, want_du=True, want_params=True,
+                 x0: Optional[torch.Tensor] = None, want_dx0=False):
+        """Gradients of sum(dy * y) for y = apply(u) (from the packed initial
+        states x0 when given). Returns (du, param grads), and dx0 third when
+        want_dx0."""
         u = self._check_u(u)
         if dy.dtype != self.state_dtype or not dy.is_contiguous() or dy.device != self.device:
             raise ValueError("dy must be a contiguous device tensor of the state dtype")
         du = torch.empty(self.layout.u_numel, dtype=self.state_dtype, device=self.device) if want_du else None
         ng = B.ssm_cascade_param_grad_numel(self.plan)
         g = torch.empty(ng, dtype=torch.float64, device=self.device) if want_params else None
-        B.ssm_cascade_backward(self.plan, u.data_ptr(), self._u_code(u), u.numel(), dy.data_ptr(),
-                               dy.numel(), du.data_ptr() if du is not None else None,
-                               g.data_ptr() if g is not None else None, ng if g is not None else 0,
-                               _stream())
-        return du, (self.split_param_grads(g) if g is not None else None)
+        if x0 is None and not want_dx0:
+            B.ssm_cascade_backward(self.plan, u.data_ptr(), self._u_code(u), u.numel(), dy.data_ptr(),
+                                   dy.numel(), du.data_ptr() if du is not None else None,
+                                   g.data_ptr() if g is not None else None, ng if g is not None else 0,
+                                   _stream())
+            return du, (self.split_param_grads(g) if g is not None else None)
+        if x0 is not None and (x0.dtype != self.state_dtype or not x0.is_contiguous() or x0.device != self.device):
+            raise ValueError("x0 must be a contiguous device tensor of the state dtype")
+        dx0 = torch.empty(self.state_numel(), dtype=self.state_dtype, device=self.device) if want_dx0 else None
+        B.ssm_cascade_backward_x0(self.plan, u.data_ptr(), self._u_code(u), u.numel(),
+                                  x0.data_ptr() if x0 is not None else None, x0.numel() if x0 is not None else 0,
+                                  dy.data_ptr(), dy.numel(), du.data_ptr() if du is not None else None,
+                                  dx0.data_ptr() if dx0 is not None else None, dx0.numel() if dx0 is not None else 0,
+                                  g.data_ptr() if g is not None else None, ng if g is not None else 0, _stream())
+        return du, (self.split_param_grads(g) if g is not None else None), dx0
 
     def split_param_grads(self, g):
         out = []

@@ -2305,9 +2305,11 @@ ssm_status ssm_cascade_recursion(ssm_plan plan, const void* u, ssm_dtype u_dtype
   return SSM_OK;
 }
 
-ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
-                                const void* dy, size_t dy_numel, void* du, double* grad_params,
-                                size_t grad_numel, hipStream_t stream) {
+// the backward; x0 (nullable) is x_{-1} of every sequence and dx0 (nullable)
+// receives dL/dx_{-1}, both packed in sequence order, m of each
+static ssm_status backward_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel, const void* x0,
+                                size_t x0_numel, const void* dy, size_t dy_numel, void* du, void* dx0,
+                                size_t dx0_numel, double* grad_params, size_t grad_numel, hipStream_t stream) {
   g_last_error.clear();
   if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
   ssm_plan_s& P = *plan;
@@ -2318,6 +2320,14 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
   if (grad_params && grad_numel < P.grad_numel)
     return fail(SSM_E_INVALID, "grad_params has %zu elements, needs %zu", grad_numel,
                 P.grad_numel);
+  {
+    size_t want = 0;
+    for (int i = 0; i < P.n_seq; ++i) want += (size_t)P.ops[P.seqs[i].op].m;
+    if (x0 && x0_numel != want)
+      return fail(SSM_E_INVALID, "x0_numel %zu, the sequences' states need %zu", x0_numel, want);
+    if (dx0 && dx0_numel != want)
+      return fail(SSM_E_INVALID, "dx0_numel %zu, the sequences' states need %zu", dx0_numel, want);
+  }
   unsigned char* meta = P.ws + P.r_meta.off;
   const RedChunk* chunks_d = reinterpret_cast<const RedChunk*>(meta + P.m_chunks);
   const SumJob* sj_d = reinterpret_cast<const SumJob*>(meta + P.m_sj);
@@ -2355,6 +2365,11 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
     prm.n_tiles = P.class_tile_count[cl];
     e = launch_project(mp, P.state_f64, P.class_bm[cl], prm, stream);
     if (e != hipSuccess) return hip_fail(e, "projection launch");
+    if (x0) {  // x_{-1} as the input Abar x_{-1} at row 0
+      e = launch_input_x0(mp, P.state_f64 != 0, prm.seqs, P.n_seq, prm.ops, P.at<double>(P.r_pw), x0, loc(0),
+                          stream);
+      if (e != hipSuccess) return hip_fail(e, "initial state launch");
+    }
     prm.flags = 0;
     prm.xfinal = xfinal;
     for (int k = 0; k <= ml; ++k) {
@@ -2475,6 +2490,13 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       if (e != hipSuccess) return hip_fail(e, "dBbar sum launch");
     }
   }
+  if (dx0 || (x0 && grad_params)) {  // dL/dx_{-1} and the x_{-1} part of dL/dP_0, from g^(0) in W[0]
+    unsigned char* meta = P.ws + P.r_meta.off;
+    e = launch_x0_grads(P.state_f64 != 0, reinterpret_cast<const SeqDev*>(meta + P.m_seqs), P.n_seq,
+                        reinterpret_cast<const OpDev*>(meta + P.m_ops), P.n_ops, P.at<double>(P.r_pw), x0, W[0], dx0,
+                        x0 && grad_params ? G : nullptr, stream);
+    if (e != hipSuccess) return hip_fail(e, "initial state gradient launch");
+  }
   if (!grad_params) return SSM_OK;
   // ---- FP64: squaring adjoint, discretization adjoint, per-set sums ----
   for (size_t gi = 0; gi < P.bgroups.size(); ++gi) {
@@ -2501,6 +2523,21 @@ ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype,
                      stream);
   if (e != hipSuccess) return hip_fail(e, "gradient scatter launch");
   return SSM_OK;
+}
+
+ssm_status ssm_cascade_backward(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                const void* dy, size_t dy_numel, void* du, double* grad_params,
+                                size_t grad_numel, hipStream_t stream) {
+  return backward_impl(plan, u, u_dtype, u_numel, nullptr, 0, dy, dy_numel, du, nullptr, 0, grad_params,
+                       grad_numel, stream);
+}
+
+ssm_status ssm_cascade_backward_x0(ssm_plan plan, const void* u, ssm_dtype u_dtype, size_t u_numel,
+                                   const void* x0, size_t x0_numel, const void* dy, size_t dy_numel, void* du,
+                                   void* dx0, size_t dx0_numel, double* grad_params, size_t grad_numel,
+                                   hipStream_t stream) {
+  return backward_impl(plan, u, u_dtype, u_numel, x0, x0_numel, dy, dy_numel, du, dx0, dx0_numel, grad_params,
+                       grad_numel, stream);
 }
 
 size_t ssm_cascade_param_grad_numel(ssm_plan plan) {

@@ -81,6 +81,94 @@ hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_se
   return hipGetLastError();
 }
 
+// The backward from an initial state recomputes the forward from V^(0) =
+// Bbar u: the initial state is the input Abar x_{-1} added to row 0 of V^(0)
+// (one workgroup per sequence, FP64 matvec).
+template <typename X>
+__global__ __launch_bounds__(256) void k_input_x0(const SeqDev* seqs, const OpDev* ops, const double* pw,
+                                                  const X* x0, int mp_class, X* v0) {
+  const int s = blockIdx.x;
+  const SeqDev sq = seqs[s];
+  const OpDev o = ops[sq.op];
+  if (o.mp != mp_class) return;
+  int64_t off = 0;
+  for (int i = 0; i < s; ++i) off += ops[seqs[i].op].m;
+  __shared__ double xs[256];
+  const int e = threadIdx.x, m = o.m;
+  xs[e] = e < m ? (double)x0[off + e] : 0.0;
+  __syncthreads();
+  if (e < m) {
+    const double* row = pw + o.pw + (int64_t)e * o.mp;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc = fma(row[k], xs[k], acc);
+    X* dst = v0 + sq.x_off + e;
+    *dst = (X)((double)*dst + acc);
+  }
+}
+
+hipError_t launch_input_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
+                           const double* pw, const void* x0, void* v0, hipStream_t st) {
+  if (n_seq <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_input_x0<double>, dim3(n_seq), dim3(256), 0, st, seqs, ops, pw,
+                       static_cast<const double*>(x0), mp_class, static_cast<double*>(v0));
+  else
+    hipLaunchKernelGGL(k_input_x0<float>, dim3(n_seq), dim3(256), 0, st, seqs, ops, pw,
+                       static_cast<const float*>(x0), mp_class, static_cast<float*>(v0));
+  return hipGetLastError();
+}
+
+// Gradients of the initial state: with g = dL/dV^(0) (the adjoint cascade's
+// result, row 0 of every sequence in g0), dL/dx_{-1} = Abar^T g_0 and the
+// direct part of dL/dAbar is g_0 x_{-1}^T, added to dL/dP_0 before the
+// squaring adjoint. One workgroup per operator walks its sequences in order,
+// so the sum over sequences sharing the operator has a fixed order; thread e
+// owns row e (FP64).
+template <typename X>
+__global__ __launch_bounds__(256) void k_x0_grads(const SeqDev* seqs, int n_seq, const OpDev* ops,
+                                                  const double* pw, const X* x0, const X* g0, X* dx0,
+                                                  double* G) {
+  const int op = blockIdx.x;
+  const OpDev o = ops[op];
+  const int e = threadIdx.x, m = o.m, mp = o.mp;
+  __shared__ double gs[256], xs[256];
+  int64_t off = 0;
+  for (int s = 0; s < n_seq; ++s) {
+    const SeqDev sq = seqs[s];
+    const int ms = ops[sq.op].m;
+    if (sq.op == op) {
+      __syncthreads();
+      gs[e] = e < m ? (double)g0[sq.x_off + e] : 0.0;
+      xs[e] = e < m && x0 ? (double)x0[off + e] : 0.0;
+      __syncthreads();
+      if (e < m) {
+        if (dx0) {
+          double acc = 0.0;
+          for (int k = 0; k < m; ++k) acc = fma(pw[o.pw + (int64_t)k * mp + e], gs[k], acc);
+          dx0[off + e] = (X)acc;
+        }
+        if (G) {
+          double* row = G + o.g_dp + (int64_t)e * mp;
+          for (int k = 0; k < m; ++k) row[k] = fma(gs[e], xs[k], row[k]);
+        }
+      }
+    }
+    off += ms;
+  }
+}
+
+hipError_t launch_x0_grads(bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops, int n_ops, const double* pw,
+                           const void* x0, const void* g0, void* dx0, double* G, hipStream_t st) {
+  if (n_ops <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_x0_grads<double>, dim3(n_ops), dim3(256), 0, st, seqs, n_seq, ops, pw,
+                       static_cast<const double*>(x0), static_cast<const double*>(g0), static_cast<double*>(dx0), G);
+  else
+    hipLaunchKernelGGL(k_x0_grads<float>, dim3(n_ops), dim3(256), 0, st, seqs, n_seq, ops, pw,
+                       static_cast<const float*>(x0), static_cast<const float*>(g0), static_cast<float*>(dx0), G);
+  return hipGetLastError();
+}
+
 // The state of a sequence's last row, x_{L-1}, for the next chunk of a
 // stream. With final states kept, the epilogue of a sequence's last stage
 // (or of its input pass, when that pass runs every stage) has stored the

@@ -407,6 +407,14 @@ hipError_t launch_scatter(const ScatterJob* jobs, int n_jobs, const int32_t* set
 hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const void* x0, void* buf0, void* buf1, const void* small,
                             void* y, bool keep_state, hipStream_t st);
+// Adds Abar x_{-1} to row 0 of V^(0) (the backward's recomputed input).
+hipError_t launch_input_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
+                           const double* pw, const void* x0, void* v0, hipStream_t st);
+// dL/dx_{-1} = Abar^T g_0 into dx0 (nullable) and g_0 x_{-1}^T added to
+// dL/dP_0 in the FP64 gradient workspace G (nullable), g0 the buffer holding
+// dL/dV^(0).
+hipError_t launch_x0_grads(bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops, int n_ops, const double* pw,
+                           const void* x0, const void* g0, void* dx0, double* G, hipStream_t st);
 // Row L - 1 of each sequence's final state, left by a plan with the final
 // state kept in buffer (last + 1) mod 2, packed into x_last (m entries per
 // sequence, in sequence order), in the plan's state type.
