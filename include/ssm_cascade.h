@@ -39,7 +39,8 @@
  *    ssm_last_error() returns a thread-local message describing the most
  *    recent failure. Nothing throws across this ABI.
  *  - Supported sizes: 1 <= m <= 256, 1 <= p <= m, 1 <= q <= m, L >= 1,
- *    0 <= N <= 62. Internally the state is padded to 32, 64, 128 or 256.
+ *    0 <= N <= 62 or -30 <= N <= -1 (automatic). Internally the state is
+ *    padded to 32, 64, 128 or 256.
  */
 #ifndef SSM_CASCADE_H
 #define SSM_CASCADE_H
@@ -210,7 +211,12 @@ typedef struct {
 /* One sequence of a (possibly ragged) batch. Host memory. */
 typedef struct {
   int32_t m, p, q;     /* state, input and output sizes; must equal its parameter set's */
-  int32_t N;           /* highest cascade stage: stages k = 0..N, degree 2^{N+1}-1 (eq. (2.2)) */
+  int32_t N;           /* highest cascade stage: stages k = 0..N, degree 2^{N+1}-1 (eq. (2.2));
+                          or automatic, N = -e with e in 1..30: prepare takes the
+                          smallest N with |Abar^(2^(N+1))|_F <= 10^-e (the first power
+                          the polynomial leaves out, §2, as in the choice of N in §4),
+                          at most ceil(log2 L) - 1, where the window covers the
+                          sequence and the cascade equals the recursion */
   int64_t L;           /* number of time steps */
   double delta;        /* step size (> 0) of the discretization; ignored for SSM_DISC_GIVEN */
   int32_t param_set;   /* index into the ssm_params array */
@@ -296,7 +302,14 @@ size_t ssm_cascade_workspace_bytes(const ssm_seq_desc* seqs, int32_t n_seq,
  * ssm_cascade_workspace_bytes(seqs, n_seq, disc, compute, with_backward,
  * ckpt_every, tuning) with the same tuning. On success *out receives a new plan (free it with
  * ssm_cascade_destroy). Synchronizes `stream` once at the end (SSM_DISC_ZOH:
- * also once after the norms of delta [A B] are formed); returns
+ * also once after the norms of delta [A B] are formed). With an automatic N
+ * (N < 0 in some descriptor) it runs twice: first with every automatic N at
+ * its cap, then, once the norms of the powers are read back (one more
+ * synchronization), with the N chosen (ssm_cascade_plan_stages reports
+ * them); ssm_cascade_workspace_bytes sizes the workspace for the caps and
+ * for every N reached by lowering all automatic N together (in either launch
+ * mode), and a choice outside those that needs more returns SSM_E_WORKSPACE
+ * with the size in ssm_last_error(). Returns
  * SSM_E_NUMERIC if some I - delta/2 A was singular to working precision, or
  * (SSM_DISC_ZOH) some delta [A B] has a non-finite or too large norm. */
 ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq,
@@ -439,6 +452,10 @@ ssm_status ssm_cascade_get_bbar(ssm_plan plan, int32_t op, double* dst,
  * launch persistently. Also returns SSM_E_HIP if the synchronization reports
  * an earlier asynchronous failure. */
 ssm_status ssm_cascade_device_status(ssm_plan plan, hipStream_t stream);
+
+/* The N of every sequence of the plan (after an automatic choice), into the
+ * host array N of n = n_seq entries. */
+ssm_status ssm_cascade_plan_stages(ssm_plan plan, int32_t* N, int32_t n);
 
 /* Host-side summary of a plan. */
 ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);

@@ -25,4 +25,6 @@ from .ssm_oracle import (  # noqa: F401
     grads_truncated_bruteforce,
     grads_full,
     effective_stages,
+    auto_stages,
+    free_response,
 )

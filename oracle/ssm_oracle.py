@@ -209,6 +209,23 @@ def powers(Abar, N):
     return P
 
 
+def auto_stages(Abar, L, tol):
+    """N chosen for a sequence of length L at tolerance tol: the smallest N
+    whose first left-out power, Abar^(2^(N+1)) (the polynomial of eq. (2.2)
+    keeps Abar^j for j < 2^(N+1)), has Frobenius norm at most tol, the way §4
+    picks N from the size of that power; at most the smallest N whose window
+    2^(N+1) covers L (there the cascade is the recursion itself).
+    """
+    cap = 0
+    while (1 << (cap + 1)) < L:
+        cap += 1
+    P = powers(Abar, cap)
+    for n in range(cap):
+        if np.linalg.norm(P[n + 1], "fro") <= tol:
+            return n
+    return cap
+
+
 def effective_stages(N, L):
     """Number of cascade stages that change anything for a length-L sequence.
 

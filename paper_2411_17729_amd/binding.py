@@ -104,6 +104,7 @@ EXPORTS = [
     "ssm_cascade_graph_apply", "ssm_cascade_graph_backward", "ssm_cascade_graph_launch",
     "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error", "ssm_cascade_device_status",
     "ssm_cascade_apply_noalloc", "ssm_cascade_apply_state", "ssm_cascade_backward_x0",
+    "ssm_cascade_plan_stages",
 ]
 
 
@@ -133,6 +134,8 @@ def load(path=LIB_PATH):
     lib.ssm_cascade_graph_destroy.argtypes = [vp]
     lib.ssm_cascade_apply.restype = i32
     lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
+    lib.ssm_cascade_plan_stages.restype = i32
+    lib.ssm_cascade_plan_stages.argtypes = [vp, P(i32), i32]
     lib.ssm_cascade_backward_x0.restype = i32
     lib.ssm_cascade_backward_x0.argtypes = [vp, vp, i32, sz, vp, sz, vp, sz, vp, vp, sz, vp, sz, vp]
     lib.ssm_cascade_apply_state.restype = i32
@@ -216,6 +219,12 @@ def ssm_cascade_prepare(descs, params, disc, compute, with_backward, ckpt_every,
 def ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream):
     _check(load().ssm_cascade_apply(plan, u_ptr, u_dtype, u_numel, y_ptr, y_numel, stream),
            "ssm_cascade_apply")
+
+
+def ssm_cascade_plan_stages(plan, n_seq):
+    arr = (C.c_int32 * n_seq)()
+    _check(load().ssm_cascade_plan_stages(plan, arr, n_seq), "ssm_cascade_plan_stages")
+    return [int(v) for v in arr]
 
 
 def ssm_cascade_backward_x0(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, dy_ptr, dy_numel, du_ptr, dx0_ptr,

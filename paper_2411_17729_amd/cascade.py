@@ -134,6 +134,10 @@ class CascadePlan:
                                    x0.numel(), out.data_ptr(), out.numel(), _stream())
         return out
 
+    def stages(self):
+        """N of every sequence (after an automatic choice)."""
+        return B.ssm_cascade_plan_stages(self.plan, len(self.layout.descs))
+
     def state_numel(self) -> int:
         """Entries of the packed per-sequence states (x0, x_last): m of each."""
         return sum(int(d.m) for d in self.layout.descs)

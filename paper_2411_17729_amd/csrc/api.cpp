@@ -102,6 +102,10 @@ struct ssm_plan_s {
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   Region r_meta, r_pw, r_pc, r_bbar, r_minv, r_small, r_aug, r_nmat, r_bsc, r_x0, r_x1;
+  // automatic N: the Frobenius norms of every operator's powers, (N + 1) per
+  // operator in operator order (only while choosing N)
+  Region r_norms;
+  int64_t n_norms = 0;
   // exponential discretization: per-operator scratch, the identity (z_nid x
   // z_nid) and the norms (element offsets in r_zoh); its jobs, made once the
   // norms are read back, in a meta area of z_cap jobs at m_zjobs
@@ -221,7 +225,8 @@ ssm_status validate_seqs(const ssm_seq_desc* seqs, int32_t n_seq) {
       return fail(SSM_E_UNSUPPORTED, "seq %d: m=%d outside 1..256", i, d.m);
     if (d.p < 1 || d.p > d.m) return fail(SSM_E_INVALID, "seq %d: p=%d outside 1..m", i, d.p);
     if (d.q < 1 || d.q > d.m) return fail(SSM_E_INVALID, "seq %d: q=%d outside 1..m", i, d.q);
-    if (d.N < 0 || d.N > 62) return fail(SSM_E_INVALID, "seq %d: N=%d outside 0..62", i, d.N);
+    if (d.N < -30 || d.N > 62)
+      return fail(SSM_E_INVALID, "seq %d: N=%d outside -30..62 (negative: automatic)", i, d.N);
     if (d.L < 1 || d.L > ((int64_t)1 << 31) - 1)
       return fail(SSM_E_INVALID, "seq %d: L=%lld outside 1..2^31-1", i, (long long)d.L);
     if (d.param_set < 0) return fail(SSM_E_INVALID, "seq %d: negative param_set", i);
@@ -235,12 +240,35 @@ ssm_status validate_seqs(const ssm_seq_desc* seqs, int32_t n_seq) {
 void plan_backward(ssm_plan_s& P);
 void plan_backward_jobs(ssm_plan_s& P);
 
+// Automatic N (a sequence given N < 0, tolerance 10^N): the largest it can
+// take is the smallest N whose window 2^(N+1) covers the sequence, where the
+// cascade is exact (ceil(log2 L) - 1; 0 for L <= 2).
+int auto_cap(int64_t L) {
+  int n = 0;
+  while (((int64_t)1 << (n + 1)) < L) ++n;
+  return n;
+}
+
+// The descriptors with every automatic N at its cap; *any says whether one was.
+std::vector<ssm_seq_desc> with_caps(const ssm_seq_desc* seqs, int32_t n_seq, bool* any) {
+  std::vector<ssm_seq_desc> d(seqs, seqs + std::max(n_seq, 0));
+  *any = false;
+  for (ssm_seq_desc& x : d)
+    if (x.N < 0) {
+      *any = true;
+      x.N = auto_cap(x.L);
+    }
+  return d;
+}
+
 // Builds sequences, operators, tiles, info and the workspace layout.
 ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ssm_disc disc,
                       ssm_dtype compute, int32_t with_backward, int32_t ckpt_every,
-                      const ssm_tuning* tuning) {
+                      const ssm_tuning* tuning, bool norms_region = false) {
   ssm_status st = validate_seqs(seqs, n_seq);
   if (st != SSM_OK) return st;
+  for (int i = 0; i < n_seq; ++i)
+    if (seqs[i].N < 0) return fail(SSM_E_INVALID, "seq %d: automatic N not resolved", i);
   ssm_tuning tn{};
   if (tuning) tn = *tuning;
   if (tn.reserved[0] != 0 || tn.reserved[1] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
@@ -1128,6 +1156,10 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   take(P.r_nmat, n_nmat * 8);
   take(P.r_bsc, n_bsc * 8);
   take(P.r_zoh, n_zoh * 8);
+  P.n_norms = 0;
+  if (norms_region)
+    for (const OpDev& o : P.ops) P.n_norms += o.N + 1;
+  take(P.r_norms, (size_t)P.n_norms * 8);
   P.x_buf_bytes = (size_t)xoff * P.x_elem();
   take(P.r_x0, P.static_state ? 0 : P.x_buf_bytes);
   take(P.r_x1, P.static_state ? 0 : P.x_buf_bytes);
@@ -1677,11 +1709,52 @@ const char* ssm_last_error(void) { return g_last_error.c_str(); }
 size_t ssm_cascade_workspace_bytes(const ssm_seq_desc* seqs, int32_t n_seq, ssm_disc disc,
                                    ssm_dtype compute, int32_t with_backward,
                                    int32_t ckpt_every, const ssm_tuning* tuning) {
+  g_last_error.clear();
+  if (validate_seqs(seqs, n_seq) != SSM_OK) return 0;
+  bool any = false;
+  const std::vector<ssm_seq_desc> d = with_caps(seqs, n_seq, &any);
   ssm_plan_s P;
-  if (build_plan(P, seqs, n_seq, disc, compute, with_backward, ckpt_every, tuning) != SSM_OK)
+  if (build_plan(P, d.data(), n_seq, disc, compute, with_backward, ckpt_every, tuning, any) != SSM_OK)
     return 0;
-  return P.ws_bytes;
+  if (!any) return P.ws_bytes;
+  // automatic N: the plan of the chosen N must fit as well. Its layout
+  // depends on N through the launch mode (sequences ending at different
+  // stages launch persistently) and the fused passes, so take the largest
+  // over every uniform step down from the caps, in both launch modes unless
+  // the tuning fixes one.
+  size_t most = P.ws_bytes;
+  int maxcap = 0;
+  for (const ssm_seq_desc& x : d) maxcap = std::max(maxcap, x.N);
+  ssm_tuning tn{};
+  if (tuning) tn = *tuning;
+  for (int delta = 0; delta <= maxcap; ++delta) {
+    std::vector<ssm_seq_desc> dd(seqs, seqs + n_seq);
+    for (int i = 0; i < n_seq; ++i)
+      if (seqs[i].N < 0) dd[i].N = std::max(0, d[i].N - delta);
+    for (int mode : {SSM_LAUNCH_PER_STAGE, SSM_LAUNCH_PERSISTENT}) {
+      if (tn.launch != SSM_LAUNCH_AUTO && tn.launch != mode) continue;
+      if (mode == SSM_LAUNCH_PERSISTENT && tn.final_state) continue;
+      ssm_tuning t2 = tn;
+      t2.launch = mode;
+      ssm_plan_s Q;
+      if (build_plan(Q, dd.data(), n_seq, disc, compute, with_backward, ckpt_every, &t2) == SSM_OK)
+        most = std::max(most, Q.ws_bytes);
+    }
+  }
+  g_last_error.clear();
+  return most;
 }
+
+}  // extern "C"
+
+// the precomputation for descriptors whose N are all resolved
+static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ssm_params* sets,
+                               int32_t n_sets, ssm_disc disc, ssm_dtype compute,
+                               int32_t with_backward, int32_t ckpt_every,
+                               const ssm_tuning* tuning, void* ws, size_t ws_bytes,
+                               hipStream_t stream, bool norms_region, ssm_plan* out);
+
+extern "C" {
 
 ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ssm_params* sets,
                                int32_t n_sets, ssm_disc disc, ssm_dtype compute,
@@ -1691,11 +1764,72 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   g_last_error.clear();
   if (!out) return fail(SSM_E_INVALID, "out is NULL");
   *out = nullptr;
+  ssm_status st = validate_seqs(seqs, n_seq);
+  if (st != SSM_OK) return st;
+  bool any = false;
+  const std::vector<ssm_seq_desc> d1 = with_caps(seqs, n_seq, &any);
+  if (!any)
+    return prepare_impl(seqs, n_seq, sets, n_sets, disc, compute, with_backward, ckpt_every, tuning, ws, ws_bytes,
+                        stream, false, out);
+  // automatic N: the powers up to each sequence's cap, their Frobenius norms
+  // read back (one more synchronization), then the plan with the chosen N
+  ssm_plan p1 = nullptr;
+  st = prepare_impl(d1.data(), n_seq, sets, n_sets, disc, compute, with_backward, ckpt_every, tuning, ws, ws_bytes,
+                    stream, true, &p1);
+  if (st != SSM_OK) return st;
+  std::vector<double> nrm((size_t)p1->n_norms);
+  std::vector<int64_t> base(p1->ops.size(), 0);
+  {
+    int64_t off = 0;
+    for (size_t i = 0; i < p1->ops.size(); ++i) {
+      base[i] = off;
+      off += p1->ops[i].N + 1;
+    }
+    unsigned char* meta = p1->ws + p1->r_meta.off;
+    hipError_t e = launch_power_norms(reinterpret_cast<const OpDev*>(meta + p1->m_ops), (int)p1->ops.size(),
+                                      p1->max_N, p1->at<double>(p1->r_pw), p1->at<double>(p1->r_norms), stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(nrm.data(), p1->ws + p1->r_norms.off, nrm.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      ssm_cascade_destroy(p1);
+      return hip_fail(e, "norms of the powers");
+    }
+  }
+  // N: the smallest n with |Abar^(2^(n+1))|_F <= 10^N given, else the cap
+  std::vector<ssm_seq_desc> d2(seqs, seqs + n_seq);
+  for (int i = 0; i < n_seq; ++i) {
+    if (seqs[i].N >= 0) continue;
+    const int op = p1->seqs[i].op;
+    const double tol = std::pow(10.0, (double)seqs[i].N);
+    int n = d1[i].N;
+    for (int c = 0; c < d1[i].N; ++c)
+      if (nrm[(size_t)(base[op] + c + 1)] <= tol) {
+        n = c;
+        break;
+      }
+    d2[i].N = n;
+  }
+  ssm_cascade_destroy(p1);
+  return prepare_impl(d2.data(), n_seq, sets, n_sets, disc, compute, with_backward, ckpt_every, tuning, ws, ws_bytes,
+                      stream, false, out);
+}
+
+}  // extern "C"
+
+static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ssm_params* sets,
+                               int32_t n_sets, ssm_disc disc, ssm_dtype compute,
+                               int32_t with_backward, int32_t ckpt_every,
+                               const ssm_tuning* tuning, void* ws, size_t ws_bytes,
+                               hipStream_t stream, bool norms_region, ssm_plan* out) {
+  if (!out) return fail(SSM_E_INVALID, "out is NULL");
+  *out = nullptr;
   if (!sets) return fail(SSM_E_INVALID, "sets is NULL");
   if (!ws) return fail(SSM_E_INVALID, "workspace is NULL");
   ssm_plan_s* P = new (std::nothrow) ssm_plan_s();
   if (!P) return fail(SSM_E_INVALID, "out of host memory");
-  ssm_status st = build_plan(*P, seqs, n_seq, disc, compute, with_backward, ckpt_every, tuning);
+  ssm_status st = build_plan(*P, seqs, n_seq, disc, compute, with_backward, ckpt_every, tuning, norms_region);
   if (st != SSM_OK) {
     delete P;
     return st;
@@ -2041,6 +2175,8 @@ ssm_status ssm_cascade_prepare(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   *out = P;
   return SSM_OK;
 }
+
+extern "C" {
 
 // the forward apply; x0 (nullable) is x_{-1} of every sequence, packed in
 // sequence order, m of each, in the plan's state type
@@ -2583,6 +2719,14 @@ ssm_status ssm_cascade_device_status(ssm_plan plan, hipStream_t stream) {
     return fail(SSM_E_HIP, "a persistent launch gave up waiting for the items it depends on "
                            "(spin limit %d); its output is not valid",
                 P.spin_limit > 0 ? P.spin_limit : (int)kPersistSpinLimit);
+  return SSM_OK;
+}
+
+ssm_status ssm_cascade_plan_stages(ssm_plan plan, int32_t* N, int32_t n) {
+  g_last_error.clear();
+  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  if (!N || n != plan->n_seq) return fail(SSM_E_INVALID, "N must hold the plan's %d sequences", plan->n_seq);
+  for (int i = 0; i < n; ++i) N[i] = plan->desc[i].N;
   return SSM_OK;
 }
 

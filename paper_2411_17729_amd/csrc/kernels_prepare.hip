@@ -216,6 +216,37 @@ __global__ __launch_bounds__(GJ_THREADS) void k_gauss_jordan(const OpDev* ops, d
     minv[o.minv + e] = a[(int64_t)(e / mp) * W + mp + (e % mp)];
 }
 
+// Frobenius norms of the powers Abar^(2^k), k = 0..N of every operator (for
+// the automatic choice of N), into norms at (sum of N + 1 over the operators
+// before) + k. Workgroup (k, op); the sum of squares is reduced in a fixed
+// order.
+__global__ __launch_bounds__(256) void k_power_norms(const OpDev* ops, const double* pw, double* norms) {
+  const int k = blockIdx.x, op = blockIdx.y;
+  const OpDev o = ops[op];
+  if (k > o.N) return;
+  int64_t base = 0;
+  for (int i = 0; i < op; ++i) base += ops[i].N + 1;
+  const int64_t mm = (int64_t)o.mp * o.mp;
+  const double* Pk = pw + o.pw + k * mm;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < mm; e += 256) acc = fma(Pk[e], Pk[e], acc);
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norms[base + k] = sqrt(red[0]);
+}
+
+hipError_t launch_power_norms(const OpDev* ops, int n_ops, int max_N, const double* pw, double* norms,
+                              hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_power_norms, dim3(max_N + 1, n_ops), dim3(256), 0, s, ops, pw, norms);
+  return hipGetLastError();
+}
+
 hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double* minv,
                                int* status, hipStream_t s) {
   if (n_ops <= 0) return hipSuccess;

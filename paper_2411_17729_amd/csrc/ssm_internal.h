@@ -407,6 +407,9 @@ hipError_t launch_scatter(const ScatterJob* jobs, int n_jobs, const int32_t* set
 hipError_t launch_inject_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
                             const double* pw, const void* x0, void* buf0, void* buf1, const void* small,
                             void* y, bool keep_state, hipStream_t st);
+// Frobenius norms of every operator's powers P_0..P_N (automatic N).
+hipError_t launch_power_norms(const OpDev* ops, int n_ops, int max_N, const double* pw, double* norms,
+                              hipStream_t s);
 // Adds Abar x_{-1} to row 0 of V^(0) (the backward's recomputed input).
 hipError_t launch_input_x0(int mp_class, bool f64, const SeqDev* seqs, int n_seq, const OpDev* ops,
                            const double* pw, const void* x0, void* v0, hipStream_t st);

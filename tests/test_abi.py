@@ -53,7 +53,7 @@ def _desc(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(m=0), dict(m=300), dict(p=0), dict(p=65), dict(q=65),
-                                 dict(N=-1), dict(N=63), dict(L=0), dict(param_set=-1),
+                                 dict(N=-31), dict(N=63), dict(L=0), dict(param_set=-1),
                                  dict(reserved=1), dict(u_offset=-1), dict(delta=0.0),
                                  dict(delta=float("nan"))])
 def test_workspace_bytes_rejects_bad_descriptors(lib, bad):

@@ -331,3 +331,27 @@ def test_fft_truncated_sum_matches_direct_sum():
         a = O.truncated_sum(Abar, Bbar, C, D, u, N)
         b = O.truncated_sum_fft(Abar, Bbar, C, D, u, N)
         assert np.max(np.abs(a - b)) < 1e-10 * max(1.0, np.max(np.abs(a)))
+
+
+def test_auto_stages_closed_forms_and_worked_example():
+    # diagonal Abar: |Abar^(2^(n+1))|_F = sqrt(sum_i lam_i^(2^(n+2))) by hand
+    lam = np.array([0.5, 0.25])
+    A = np.diag(lam)
+    # n = 0: 0.25^2 + ... ; the norms for n + 1 = 1..5 are
+    # sqrt(0.5^(2^(k+1)) + 0.25^(2^(k+1))), k = n + 1
+    norms = [np.sqrt(0.5 ** (2 ** (k + 1)) + 0.25 ** (2 ** (k + 1))) for k in range(1, 7)]
+    for tol in (1e-2, 1e-6, 1e-12):
+        want = next(n for n in range(6) if norms[n] <= tol)
+        assert O.auto_stages(A, 1 << 20, tol) == want
+    # the cap: the smallest N whose window 2^(N+1) covers L
+    for L, cap in ((1, 0), (2, 0), (3, 1), (8, 2), (9, 3), (10, 3), (4096, 11), (4097, 12)):
+        assert O.auto_stages(np.eye(2), L, 1e-300) == cap  # the identity never decays
+    # §4 (m = 100, delta = 5e-4, 1-based HiPPO): |P_15|_F ~ 1.0e-9 and
+    # |P_14|_F ~ 7.8e-3, so tolerances between give the paper's N = 14, and
+    # 1e-14 needs one stage more (|P_16|_F ~ 5.9e-24)
+    A4, b4 = W.hippo_legs(100)
+    Ab, _ = O.trapezoid(A4, b4[:, None], 5e-4)
+    assert O.auto_stages(Ab, 1 << 20, 1e-8) == 14
+    assert O.auto_stages(Ab, 1 << 20, 1e-14) == 15
+    assert O.auto_stages(Ab, (1 << 15) + 1, 1e-14) == 15  # at the cap
+    assert O.auto_stages(Ab, 1 << 12, 1e-14) == 11        # the cap decides
