@@ -118,7 +118,7 @@ struct ssm_plan_s {
   std::vector<std::pair<int, int>> zbgroups, zbdims;
   std::vector<int> zbkind;
   size_t m_zbjobs = 0, zb_cap = 0;
-  size_t m_seqs = 0, m_ops = 0, m_src = 0, m_tiles = 0, m_status = 0, m_jobs = 0;
+  size_t m_seqs = 0, m_ops = 0, m_src = 0, m_tiles = 0, m_status = 0, m_jobs = 0, m_tri = 0, m_tri_scale = 0;
   std::vector<GemmJob> jobs;            // prepare jobs, in launch order
   std::vector<std::pair<int, int>> job_groups;  // (start, count) per launch
   std::vector<std::pair<int, int>> job_dims;    // (max M, max N) per launch
@@ -1076,10 +1076,19 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + sizeof(Tile) * std::max<size_t>(1, P.tiles.size()));
   P.m_status = off;
   off = align_up(off + 16);
+  // lower-triangular test per operator: int flags, then FP64 scales
+  P.m_tri = off;
+  off = align_up(off + 4 * P.ops.size());
+  P.m_tri_scale = off;
+  off = align_up(off + 8 * P.ops.size());
   // jobs: 2 per operator (discretization) + one per operator and squaring
   size_t n_jobs = 2 * P.ops.size();
   for (const OpDev& o : P.ops)
     n_jobs += (size_t)o.N + (o.kry > 0 ? 1 + o.kry : 0) + (o.cpl >= 0) + (o.fold_s > 0 ? 1 + o.fold_s : 0);
+  // doubling GEMMs of the triangular inverse: 2 (mp / 2s) per level s
+  if (disc == SSM_DISC_TRAPEZOID)
+    for (const OpDev& o : P.ops)
+      for (int sz = 32; sz < o.mp; sz *= 2) n_jobs += 2 * (o.mp / (2 * sz));
   P.m_jobs = off;
   off = align_up(off + sizeof(GemmJob) * std::max<size_t>(1, n_jobs));
   // exponential discretization: per operator the scaling, the first Taylor
@@ -1909,6 +1918,34 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   std::vector<GemmJob>& J = P->jobs;
   P->job_kind.clear();
   if (disc == SSM_DISC_TRAPEZOID) {
+    // triangular inverse: per level, Y X^-1 into the scratch right half of
+    // aug, then -Z^-1 (Y X^-1) into the block of minv (kind 2 groups, gated
+    // on the operator's triangular flag)
+    double* augp = P->at<double>(P->r_aug);
+    const int32_t* tri_d = reinterpret_cast<const int32_t*>(P->ws + P->r_meta.off + P->m_tri);
+    for (int sz = 32; sz < P->max_mp; sz *= 2) {
+      for (int half = 0; half < 2; ++half) {
+        int start = (int)J.size();
+        for (size_t oi = 0; oi < P->ops.size(); ++oi) {
+          const OpDev& o = P->ops[oi];
+          const int mp = o.mp, W = 2 * mp;
+          for (int r0 = 0; r0 + 2 * sz <= mp && sz < mp; r0 += 2 * sz) {
+            double* Y = augp + o.sc_aug + (int64_t)(r0 + sz) * W + r0;
+            double* T = augp + o.sc_aug + (int64_t)(r0 + sz) * W + mp + r0;
+            const double* Xi = minv + o.minv + (int64_t)r0 * mp + r0;
+            const double* Zi = minv + o.minv + (int64_t)(r0 + sz) * mp + (r0 + sz);
+            double* out = minv + o.minv + (int64_t)(r0 + sz) * mp + r0;
+            GemmJob jb = half == 0 ? GemmJob{Y, Xi, T, sz, sz, sz, W, mp, W, 0, 0, 1.0, 0.0}
+                                   : GemmJob{Zi, T, out, sz, sz, sz, mp, W, mp, 0, 0, -1.0, 0.0};
+            jb.gate = tri_d + oi;
+            J.push_back(jb);
+          }
+        }
+        P->job_groups.push_back({start, (int)J.size() - start});
+        P->job_dims.push_back({sz, sz});
+        P->job_kind.push_back(2);
+      }
+    }
     int start = (int)J.size(), mx = 0, mxn = 0;
     for (const OpDev& o : P->ops) {
       // Abar = M^{-1} (I + h A)
@@ -2134,7 +2171,20 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     if (e != hipSuccess) return bail(hip_fail(e, "discretization setup launch"));
   }
   if (disc == SSM_DISC_TRAPEZOID) {
-    e = launch_gauss_jordan(ops_d, P->n_ops, P->at<double>(P->r_aug), minv, status_d, stream);
+    // M^{-1}: blockwise for lower-triangular M, Gauss-Jordan otherwise
+    int32_t* tri_d = reinterpret_cast<int32_t*>(meta + P->m_tri);
+    double* tscale_d = reinterpret_cast<double*>(meta + P->m_tri_scale);
+    e = launch_tri_check(ops_d, P->n_ops, src_d, tri_d, tscale_d, stream);
+    if (e == hipSuccess)
+      e = launch_tri_diag_inv(ops_d, P->n_ops, P->max_mp, P->at<double>(P->r_aug), minv, tri_d, tscale_d, status_d,
+                              stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "triangular inverse launch"));
+    for (; g < P->job_groups.size() && P->job_kind[g] == 2; ++g) {
+      const auto& grp = P->job_groups[g];
+      e = launch_gemm_f64(jobs_d + grp.first, grp.second, P->job_dims[g].first, P->job_dims[g].second, stream);
+      if (e != hipSuccess) return bail(hip_fail(e, "triangular inverse GEMM launch"));
+    }
+    e = launch_gauss_jordan(ops_d, P->n_ops, P->at<double>(P->r_aug), minv, status_d, tri_d, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "Gauss-Jordan launch"));
     const auto& grp = P->job_groups[g];
     e = launch_gemm_f64(jobs_d + grp.first, grp.second, P->job_dims[g].first,

@@ -161,7 +161,8 @@ __device__ void block_argmax(double v, int idx, double* sv, int* si, double* out
 }
 
 __global__ __launch_bounds__(GJ_THREADS) void k_gauss_jordan(const OpDev* ops, double* aug,
-                                                             double* minv, int* status) {
+                                                             double* minv, int* status, const int32_t* tri) {
+  if (tri[blockIdx.x]) return;  // inverted by the triangular path
   const OpDev o = ops[blockIdx.x];
   const int mp = o.mp, W = 2 * mp;
   double* a = aug + o.sc_aug;
@@ -248,10 +249,106 @@ hipError_t launch_power_norms(const OpDev* ops, int n_ops, int max_N, const doub
 }
 
 hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double* minv,
-                               int* status, hipStream_t s) {
+                               int* status, const int32_t* tri, hipStream_t s) {
   if (n_ops <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gauss_jordan, dim3(n_ops), dim3(GJ_THREADS), 0, s, ops, aug, minv,
-                     status);
+                     status, tri);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lower-triangular M = I - h A. Its inverse is lower triangular, found block
+// by block: the 32 x 32 diagonal blocks by forward substitution, then by
+// doubling the block size, [[X, 0], [Y, Z]]^{-1} = [[X^-1, 0], [-Z^-1 Y X^-1,
+// Z^-1]], two FP64 GEMMs per level (jobs gated on tri).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_tri_check(const OpDev* ops, const OpSrc* src, int32_t* tri,
+                                                    double* scale) {
+  const OpDev o = ops[blockIdx.x];
+  const OpSrc sp = src[blockIdx.x];
+  const int m = o.m;
+  const double h = 0.5 * o.delta;
+  // thread (ty, tx): column tx of rows ty, ty + 4, ... (one coalesced row per step)
+  const int tx = threadIdx.x & 255, ty = threadIdx.x >> 8;
+  int upper = 0;
+  double mx = 0.0;
+  if (tx < m)
+    for (int r = ty; r < m; r += 4) {
+      const double a = sp.A[(int64_t)r * m + tx];
+      if (tx > r && a != 0.0) upper = 1;
+      mx = fmax(mx, fabs((r == tx ? 1.0 : 0.0) - h * a));
+    }
+  __shared__ int su[1024];
+  __shared__ double sm[1024];
+  su[threadIdx.x] = upper;
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      su[threadIdx.x] |= su[threadIdx.x + w];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tri[blockIdx.x] = su[0] ? 0 : 1;
+    scale[blockIdx.x] = fmax(sm[0], 1.0);  // the padding adds ones to the diagonal
+  }
+}
+
+hipError_t launch_tri_check(const OpDev* ops, int n_ops, const OpSrc* src, int32_t* tri, double* scale,
+                            hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tri_check, dim3(n_ops), dim3(1024), 0, s, ops, src, tri, scale);
+  return hipGetLastError();
+}
+
+// Workgroup (block row b, operator): thread j < 32 walks column j of the
+// block's inverse in registers, x_i = (delta_ij - sum_{k < i} M_ik x_k) /
+// M_ii (the x_k above row j are zero, so the sum needs no lower limit).
+__global__ __launch_bounds__(64) void k_tri_diag_inv(const OpDev* ops, const double* aug, double* minv,
+                                                     const int32_t* tri, const double* scale, int* status) {
+  const int op = blockIdx.y, b = blockIdx.x;
+  if (!tri[op]) return;
+  const OpDev o = ops[op];
+  const int mp = o.mp;
+  if (32 * b >= mp) return;
+  const int r0 = 32 * b, W = 2 * mp;
+  __shared__ double Mb[32][33];
+  __shared__ double Xb[32][33];
+  for (int e = threadIdx.x; e < 32 * 32; e += 64) {
+    const int r = e / 32, c = e % 32;
+    Mb[r][c] = aug[o.sc_aug + (int64_t)(r0 + r) * W + r0 + c];
+  }
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j < 32) {
+    double x[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      double acc = i == j ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc = fma(-Mb[i][k], x[k], acc);
+      x[i] = acc / Mb[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) Xb[i][j] = x[i];
+    const double thresh = (double)mp * DBL_EPSILON * scale[op];
+    if (!(fabs(Mb[j][j]) > thresh)) atomicOr(status, 1);
+  }
+  __syncthreads();
+  // the block row of the inverse: the diagonal block and zeros to its right
+  // (the blocks to its left come from the doubling GEMMs)
+  for (int e = threadIdx.x; e < 32 * (mp - r0); e += 64) {
+    const int r = e / (mp - r0), c = r0 + e % (mp - r0);
+    minv[o.minv + (int64_t)(r0 + r) * mp + c] = c < r0 + 32 ? Xb[r][c - r0] : 0.0;
+  }
+}
+
+hipError_t launch_tri_diag_inv(const OpDev* ops, int n_ops, int max_mp, const double* aug, double* minv,
+                               const int32_t* tri, const double* scale, int* status, hipStream_t s) {
+  if (n_ops <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tri_diag_inv, dim3(max_mp / 32, n_ops), dim3(64), 0, s, ops, aug, minv, tri, scale, status);
   return hipGetLastError();
 }
 
@@ -266,50 +363,70 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_gemm_f64(const GemmJob* jobs) {
   const GemmJob jb = jobs[blockIdx.z];
+  if (jb.gate && *jb.gate == 0) return;
   const int tm = blockIdx.y * 64, tn = blockIdx.x * 64;
   if (tm >= jb.M || tn >= jb.N) return;
-  constexpr int KT = 16;
-  __shared__ double As[64][KT + 1];  // As[i][k] = op(A)(tm+i, k0+k)
-  __shared__ double Bs[64][KT + 1];  // Bs[j][k] = op(B)(k0+k, tn+j)
+  // K in chunks of KT; the next chunk's elements are loaded into registers
+  // while the current one is contracted from LDS
+  constexpr int KT = 32;
+  constexpr int PER = 64 * KT / 256;  // elements of A (and of B) per thread and chunk
+  __shared__ double As[64][KT + 1];   // As[i][k] = op(A)(tm+i, k0+k)
+  __shared__ double Bs[64][KT + 1];   // Bs[j][k] = op(B)(k0+k, tn+j)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   f64x4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-
-  for (int k0 = 0; k0 < jb.K; k0 += KT) {
-    __syncthreads();
-    for (int e = tid; e < 64 * KT; e += 256) {
-      int i, kk;
-      if (jb.transA) {  // A stored K x M: consecutive i contiguous
-        i = e % 64;
-        kk = e / 64;
-      } else {
-        i = e / KT;
-        kk = e % KT;
-      }
+  // element e of a chunk: (i, kk) of A and (j, kk) of B, consecutive e along
+  // the operand's contiguous direction
+  auto a_pos = [&](int e, int& i, int& kk) {
+    if (jb.transA) {  // A stored K x M: consecutive i contiguous
+      i = e % 64;
+      kk = e / 64;
+    } else {
+      i = e / KT;
+      kk = e % KT;
+    }
+  };
+  auto b_pos = [&](int e, int& j, int& kk) {
+    if (jb.transB) {  // B stored N x K: consecutive k contiguous
+      j = e / KT;
+      kk = e % KT;
+    } else {
+      j = e % 64;
+      kk = e / 64;
+    }
+  };
+  double ra[PER], rb[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      int i, j, kk;
+      const int e = tid + 256 * t;
+      a_pos(e, i, kk);
       const int gi = tm + i, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < jb.M && gk < jb.K)
-        v = jb.transA ? jb.A[(int64_t)gk * jb.lda + gi] : jb.A[(int64_t)gi * jb.lda + gk];
-      As[i][kk] = v;
+      ra[t] = gi < jb.M && gk < jb.K ? (jb.transA ? jb.A[(int64_t)gk * jb.lda + gi] : jb.A[(int64_t)gi * jb.lda + gk])
+                                     : 0.0;
+      b_pos(e, j, kk);
+      const int gj = tn + j, gk2 = k0 + kk;
+      rb[t] = gj < jb.N && gk2 < jb.K ? (jb.transB ? jb.B[(int64_t)gj * jb.ldb + gk2] : jb.B[(int64_t)gk2 * jb.ldb + gj])
+                                      : 0.0;
     }
-    for (int e = tid; e < 64 * KT; e += 256) {
-      int j, kk;
-      if (jb.transB) {  // B stored N x K: consecutive k contiguous
-        j = e / KT;
-        kk = e % KT;
-      } else {
-        j = e % 64;
-        kk = e / 64;
-      }
-      const int gj = tn + j, gk = k0 + kk;
-      double v = 0.0;
-      if (gj < jb.N && gk < jb.K)
-        v = jb.transB ? jb.B[(int64_t)gj * jb.ldb + gk] : jb.B[(int64_t)gk * jb.ldb + gj];
-      Bs[j][kk] = v;
+  };
+  load(0);
+  for (int k0 = 0; k0 < jb.K; k0 += KT) {
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      int i, j, kk;
+      const int e = tid + 256 * t;
+      a_pos(e, i, kk);
+      As[i][kk] = ra[t];
+      b_pos(e, j, kk);
+      Bs[j][kk] = rb[t];
     }
     __syncthreads();
+    if (k0 + KT < jb.K) load(k0 + KT);
 #pragma unroll
     for (int ks = 0; ks < KT; ks += 4) {
       const int kk = ks + (lane >> 4);

@@ -257,6 +257,7 @@ struct GemmJob {
   int32_t lda, ldb, ldc;
   int32_t transA, transB;
   double alpha, beta;
+  const int32_t* gate;  // if set, the job runs only where *gate != 0
 };
 
 // Rows per workgroup tile of the stage kernel for a padded state size and
@@ -299,9 +300,22 @@ hipError_t launch_disc_setup(const OpDev* ops, int n_ops, const OpSrc* src, int 
                              double* bbar, int max_mp, hipStream_t s);
 
 // Gauss-Jordan elimination with partial pivoting of aug -> minv, one
-// workgroup per operator. Sets *status to 1 if a pivot is negligible.
+// workgroup per operator, skipped for operators whose tri flag is set (their
+// inverse comes from the triangular path). Sets *status to 1 if a pivot is
+// negligible.
 hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double* minv,
-                               int* status, hipStream_t s);
+                               int* status, const int32_t* tri, hipStream_t s);
+
+// Lower-triangular I - h A (the HiPPO matrices of §4 are lower triangular):
+// tri[op] = 1 if A has no entry above the diagonal, scale[op] = max |I - h A|.
+hipError_t launch_tri_check(const OpDev* ops, int n_ops, const OpSrc* src, int32_t* tri, double* scale,
+                            hipStream_t s);
+// Inverses of the 32 x 32 diagonal blocks of the lower-triangular M (left
+// half of aug) into minv by forward substitution, zeros right of each block
+// row's diagonal block; status |= 1 for a diagonal entry below mp eps scale.
+// Only for operators with tri[op] set.
+hipError_t launch_tri_diag_inv(const OpDev* ops, int n_ops, int max_mp, const double* aug, double* minv,
+                               const int32_t* tri, const double* scale, int* status, hipStream_t s);
 
 // Casts K_j (FP64, mp x mp per operator with kw >= 0) to the compute type.
 hipError_t launch_pack_krylov(const OpDev* ops, int n_ops, const double* kw, void* kc, int ct,
