@@ -1,24 +1,32 @@
-"""Autotuner of the stage-kernel tiling, the launch mode and (on request) the
-state type kept between passes.
+"""Autotuner of the plan choices that shape the hot path.
 
-For a batch of sequences it times the candidate plans on the GPU (per-stage
-launches with every combination of tile heights over the size classes
-present, and the single persistent launch) and keeps the fastest. With
-allow_bf16_state, BF16 plans are also timed with the state kept in BF16
-between passes; such a candidate counts only if the plan can keep it and its
-outputs on the tuning input stay within state_tol (relative, per sequence)
-of the same plan with FP32 state. Results are cached in a JSON file keyed by
-device architecture, compute type, the size classes present, the batch's row
-count (rounded to a power of two) and whether BF16 state was allowed, so a
-later plan of the same shape reuses the choice.
+For a batch of sequences it times plans on the GPU and keeps the fastest, by
+coordinate descent from the library's defaults over the choices that the
+plan actually uses (a choice the plan ignores is not timed):
+
+  launch        per-stage launches or the one persistent launch
+  input_stages  automatic (fold leading stages into the input pass) or none
+  chain_blocks  16-row blocks per wave segment of the chain kernel
+  pair_blocks   16-row blocks per workgroup segment of a stage pair
+  fold_stages   stages folded into the output pass (automatic, none, 4, 5)
+  state_bf16    BF16 state between passes (BF16 plans, when allowed)
+  tile_rows     rows per tile of the tiled stage kernel (plans that use it)
+
+Every candidate's output on the tuning input is compared with the default
+plan's; a candidate further away than the tolerance of its compute type
+(BF16 5e-3, FP32 1e-6, FP64 1e-12, relative per sequence) is rejected, so a
+choice that changes the rounding (BF16 state, the output fold) is kept only
+within that bound. Results are cached in a JSON file (``SSM_TUNING_CACHE`` or
+``tuning_cache.json`` next to this file) keyed by device architecture,
+compute type, size classes, the batch's row count (rounded to a power of
+two), whether it is ragged and whether BF16 state was allowed.
 
     from paper_2411_17729_amd import tune
-    tuning = tune.best_tuning(workload, compute="bf16")   # dict for CascadePlan
+    kw = tune.best_tuning(workload, compute="bf16")   # keyword arguments for plan_for_workload
 """
 
 from __future__ import annotations
 
-import itertools
 import json
 import math
 import os
@@ -28,14 +36,15 @@ import torch
 from . import binding as B
 from . import cascade as CC
 
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+CACHE = os.environ.get("SSM_TUNING_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json"))
 CLASS_MP = (32, 64, 128, 256)
+TOL = {"bf16": 5e-3, "f32": 1e-6, "f64": 1e-12}
 
 
 def default_rows(mp, compute):
     """Default rows per stage tile (mirrors the library's defaults)."""
-    f64 = compute == "f64"
-    if f64:
+    if compute == "f64":
         return {256: 32, 128: 64, 64: 64, 32: 128}[mp]
     return {256: 64, 128: 64, 64: 128, 32: 256}[mp]
 
@@ -44,30 +53,45 @@ def _pad(m):
     return 32 if m <= 32 else 64 if m <= 64 else 128 if m <= 128 else 256
 
 
+def _classes(wl):
+    return sorted({_pad(wl.sets[s.param_set].m) for s in wl.seqs})
+
+
 def signature(wl, compute, allow_bf16_state=False):
     arch = "unknown"
     if torch.cuda.is_available():
         arch = getattr(torch.cuda.get_device_properties(0), "gcnArchName", "gpu").split(":")[0]
-    classes = sorted({_pad(wl.sets[s.param_set].m) for s in wl.seqs})
+    classes = _classes(wl)
     rows = sum(s.L for s in wl.seqs)
     ragged = len(classes) > 1 or len({(s.L, s.N) for s in wl.seqs}) > 1
     return f"{arch}/{compute}/mp{'-'.join(map(str, classes))}/rows2^{int(math.log2(max(rows, 1)))}" \
            f"/{'ragged' if ragged else 'uniform'}" + ("/bf16state" if allow_bf16_state else "")
 
 
-def candidates(wl, compute, allow_bf16_state=False):
-    classes = sorted({_pad(wl.sets[s.param_set].m) for s in wl.seqs})
-    opts = []
-    for combo in itertools.product(*[(default_rows(mp, compute), default_rows(mp, compute) // 2)
-                                     for mp in classes]):
-        rows = [0, 0, 0, 0]
-        for mp, r in zip(classes, combo):
-            rows[CLASS_MP.index(mp)] = r
-        opts.append({"launch": "per_stage", "tile_rows": rows, "state_bf16": 0})
-        if allow_bf16_state and compute == "bf16":
-            opts.append({"launch": "per_stage", "tile_rows": rows, "state_bf16": 1})
-    opts.append({"launch": "persistent", "tile_rows": [0, 0, 0, 0], "state_bf16": 0})
-    return opts
+def defaults():
+    return {"launch": "auto", "input_stages": 0, "chain_blocks": 0, "pair_blocks": 0, "fold_stages": 0,
+            "state_bf16": 0, "tile_rows": (0, 0, 0, 0)}
+
+
+def knob_values(wl, compute, info, allow_bf16_state):
+    """The values worth timing for each choice the plan described by info uses."""
+    vals = {"launch": ["per_stage", "persistent"], "input_stages": [0, -1]}
+    if info["stage_kernel"] == B.SSM_STAGE_CHAIN and info["launch"] == B.SSM_LAUNCH_PER_STAGE:
+        vals["chain_blocks"] = [0, 2, 4, 8, 16, 32]
+    if info["pair_launches"] > 0:
+        vals["pair_blocks"] = [0, 8, 16, 32, 64, 128]
+    if compute == "bf16" and info["launch"] == B.SSM_LAUNCH_PER_STAGE:
+        vals["fold_stages"] = [0, -1, 4, 5]
+        if allow_bf16_state:
+            vals["state_bf16"] = [0, 1]
+    if info["stage_kernel"] == B.SSM_STAGE_TILED:
+        rows = []
+        for mp in _classes(wl):
+            r = [0, 0, 0, 0]
+            r[CLASS_MP.index(mp)] = default_rows(mp, compute) // 2
+            rows.append(tuple(r))
+        vals["tile_rows"] = [(0, 0, 0, 0)] + rows
+    return vals
 
 
 def _max_rel_diff(wl, y, ref):
@@ -80,7 +104,8 @@ def _max_rel_diff(wl, y, ref):
     return worst
 
 
-def time_plan(plan, u, reps=5, warm=2):
+def time_plan(plan, u, reps=7, warm=2):
+    """Median milliseconds of one apply (eager)."""
     y = torch.empty(plan.layout.y_numel, dtype=plan.state_dtype, device=u.device)
     for _ in range(warm):
         plan.apply(u, out=y)
@@ -98,20 +123,47 @@ def time_plan(plan, u, reps=5, warm=2):
     return ts[len(ts) // 2]
 
 
-def tune(wl, compute="bf16", reps=5, verbose=False, allow_bf16_state=False, state_tol=5e-3):
-    """Times every candidate on the current GPU; returns (best, table). A
-    BF16-state candidate is kept only if the plan can keep the state in BF16
-    and its outputs stay within state_tol of the same candidate with FP32
-    state (the one before it in the candidate list)."""
+def _plan(wl, compute, kw, with_backward=False):
+    k = dict(kw)
+    k["tile_rows"] = tuple(k["tile_rows"])
+    return CC.plan_for_workload(wl, compute=compute, with_backward=with_backward, **k)
+
+
+def tune(wl, compute="bf16", reps=7, verbose=False, allow_bf16_state=False, tol=None):
+    """Coordinate descent from the defaults; returns (best keyword arguments,
+    best ms, table of every timed candidate)."""
+    tol = TOL[compute] if tol is None else tol
     u = CC.pack_u(wl, dtype=torch.float64 if compute == "f64" else torch.float32)
-    table = []
-    ref = None  # outputs of the last FP32-state candidate
-    for cand in candidates(wl, compute, allow_bf16_state):
-        plan = CC.plan_for_workload(wl, compute=compute, launch=cand["launch"],
-                                    tile_rows=tuple(cand["tile_rows"]), state_bf16=cand["state_bf16"])
-        row = dict(cand)
-        if cand["state_bf16"]:
-            if plan.info()["state_dtype"] != B.SSM_BF16:
+    cur = defaults()
+    plan = _plan(wl, compute, cur)
+    info = plan.info()
+    ref = plan.apply(u).clone()
+    torch.cuda.synchronize()
+    best_ms = time_plan(plan, u, reps)
+    plan.close()
+    table = [dict(cur, ms=best_ms)]
+    # the launch mode first; the other choices are those the plan of the
+    # chosen mode uses
+    order = ["launch", "input_stages", "chain_blocks", "pair_blocks", "fold_stages", "state_bf16", "tile_rows"]
+    for knob in order:
+        if knob != "launch":
+            plan = _plan(wl, compute, cur)
+            info = plan.info()
+            plan.close()
+        values = knob_values(wl, compute, info, allow_bf16_state).get(knob, [])
+        for v in values:
+            if v == cur[knob] or (knob == "launch" and v == "auto"):
+                continue
+            cand = dict(cur)
+            cand[knob] = v
+            row = dict(cand)
+            try:
+                plan = _plan(wl, compute, cand)
+            except B.SSMError as e:
+                row["rejected"] = str(e)
+                table.append(row)
+                continue
+            if knob == "state_bf16" and plan.info()["state_dtype"] != B.SSM_BF16:
                 plan.close()
                 row["rejected"] = "the plan keeps FP32 state"
                 table.append(row)
@@ -119,44 +171,45 @@ def tune(wl, compute="bf16", reps=5, verbose=False, allow_bf16_state=False, stat
             y = plan.apply(u).clone()
             torch.cuda.synchronize()
             row["rel_diff"] = _max_rel_diff(wl, y, ref)
-            if row["rel_diff"] > state_tol:
+            if row["rel_diff"] > tol:
                 plan.close()
-                row["rejected"] = f"outputs differ by {row['rel_diff']:.2e} > {state_tol:.1e}"
+                row["rejected"] = f"outputs differ by {row['rel_diff']:.2e} > {tol:.1e}"
                 table.append(row)
                 continue
-        elif cand["launch"] == "per_stage":
-            ref = plan.apply(u).clone()
-            torch.cuda.synchronize()
-        row["ms"] = time_plan(plan, u, reps=reps)
-        plan.close()
-        table.append(row)
-        if verbose:
-            print(f"tune {row}", flush=True)
-    best = min((r for r in table if "ms" in r), key=lambda r: r["ms"])
-    return best, table
+            row["ms"] = time_plan(plan, u, reps)
+            plan.close()
+            table.append(row)
+            if verbose:
+                print(f"tune {row}", flush=True)
+            if row["ms"] < best_ms:
+                best_ms = row["ms"]
+                cur = cand
+    return cur, best_ms, table
 
 
-def load_cache(path=CACHE):
+def load_cache(path=None):
+    path = path or CACHE
     if os.path.exists(path):
         with open(path) as f:
             return json.load(f)
     return {}
 
 
-def best_tuning(wl, compute="bf16", path=CACHE, retune=False, save=True, allow_bf16_state=False,
-                state_tol=5e-3):
-    """Cached choice for this batch shape, tuning on a miss."""
+def best_tuning(wl, compute="bf16", path=None, retune=False, save=True, allow_bf16_state=False, tol=None):
+    """Cached choice for this batch shape (keyword arguments for
+    plan_for_workload), tuning on a miss."""
+    path = path or CACHE
     key = signature(wl, compute, allow_bf16_state)
     cache = load_cache(path)
     if not retune and key in cache:
-        c = cache[key]
-        return {"launch": c["launch"], "tile_rows": tuple(c["tile_rows"]),
-                "state_bf16": c.get("state_bf16", 0)}
-    best, table = tune(wl, compute, allow_bf16_state=allow_bf16_state, state_tol=state_tol)
-    cache[key] = {"launch": best["launch"], "tile_rows": list(best["tile_rows"]),
-                  "state_bf16": best["state_bf16"], "ms": best["ms"], "candidates": table}
+        c = cache[key]["choice"]
+        c["tile_rows"] = tuple(c["tile_rows"])
+        return c
+    best, ms, table = tune(wl, compute, allow_bf16_state=allow_bf16_state, tol=tol)
+    cache[key] = {"choice": dict(best, tile_rows=list(best["tile_rows"])), "ms": ms, "candidates": table}
     if save:
         with open(path, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
-    return {"launch": best["launch"], "tile_rows": tuple(best["tile_rows"]),
-            "state_bf16": best["state_bf16"]}
+            json.dump(cache, f, indent=1, sort_keys=True, default=list)
+    best = dict(best)
+    best["tile_rows"] = tuple(best["tile_rows"])
+    return best
