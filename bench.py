@@ -90,6 +90,9 @@ def _args():
                     help="skip the other dtype and the recursion comparator")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU oracle sample")
+    ap.add_argument("--stream-probe-mib", type=int, default=0,
+                    help="only time plain streams over buffers of this size (torch's fill, sum and "
+                         "copy kernels: write-only, read-only, read+write) and print their rates")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the measurement, run one device-to-device copy of this many MiB "
                          "(a reference for hardware byte counters)")
@@ -164,6 +167,33 @@ def _stage_traffic(workload, dtype, name, state="f32"):
     return rec.get("traffic_bytes_per_launch")
 
 
+def stream_probe(mib, reps=20):
+    """Rates of plain HBM streams with torch's own kernels on buffers of mib
+    MiB: the write, read and read+write rates a simple kernel reaches here."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    acc = torch.empty((), dtype=torch.float32, device="cuda")
+    cases = {"write (fill)": (lambda: a.fill_(2.0), n * 4),
+             "read (sum)": (lambda: torch.sum(a, dim=0, out=acc), n * 4),
+             "read+write (copy)": (lambda: b.copy_(a), 2 * n * 4)}
+    res = {}
+    for name, (fn, nbytes) in cases.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": round(ms, 4), "GBps": round(nbytes / ms / 1e6, 1)}
+    return {"stream_probe_MiB": mib, "reps": reps, "rates": res}
+
+
 def main():
     args = _args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -177,6 +207,9 @@ def main():
 
     from paper_2411_17729_amd import workloads as W
 
+    if args.stream_probe_mib > 0:
+        print(json.dumps(stream_probe(args.stream_probe_mib)), flush=True)
+        return
     if args.workload == "backward":
         return bench_backward(args)
     if args.workload == "ragged":
