@@ -170,6 +170,8 @@ struct ssm_plan_s {
   std::vector<FoldUnit> fold_units;
   int fold_start[4] = {0, 0, 0, 0}, fold_count[4] = {0, 0, 0, 0};
   size_t fold_lds_bytes[4] = {0, 0, 0, 0};
+  int fold_max_p[4] = {0, 0, 0, 0};  // widest input of the class's folded sequences
+  bool fold_q4[4] = {false, false, false, false};  // every q and y offset of the class a multiple of 4
   size_t m_fold = 0;
   int64_t fold_launches = 0;
   double fold_bytes = 0, fold_flops = 0;
@@ -729,11 +731,13 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     if (P.fold_s[c] == 0) continue;
     std::vector<int> ids;
     int max_p = 1, max_q = 1;
+    bool q4 = true;
     for (int i = 0; i < n_seq; ++i)
       if (P.ops[P.seqs[i].op].mp == kClassMp[c]) {
         ids.push_back(i);
         max_p = std::max(max_p, P.seqs[i].p);
         max_q = std::max(max_q, P.seqs[i].q);
+        q4 = q4 && P.seqs[i].q % 4 == 0 && P.seqs[i].y_off % 4 == 0;
       }
     std::stable_sort(ids.begin(), ids.end(),
                      [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
@@ -750,6 +754,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       P.fold_lds_bytes[c] = fold_lds(kClassMp[c], P.fold_s[c], max_p, max_q);
     }
     P.fold_count[c] = (int)P.fold_units.size() - P.fold_start[c];
+    P.fold_max_p[c] = max_p;
+    P.fold_q4[c] = q4;
     for (OpDev& o : P.ops)
       if (class_of(o.mp) == c) {
         o.fold_s = P.fold_s[c];
@@ -2364,8 +2370,8 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
       if (P.fold_s[c] > 0 && kk == P.fold_k0[c]) {  // the remaining stages and y in one pass
         TimedLaunch tl(P, stream, 5, timed);
         const FoldUnit* un = reinterpret_cast<const FoldUnit*>(P.ws + P.r_meta.off + P.m_fold) + P.fold_start[c];
-        e = P.fold_wide[c] ? launch_output_fold_wide(kClassMp[c], P.compute, P.state_bf16 != 0, prm, un,
-                                                     P.fold_count[c], stream)
+        e = P.fold_wide[c] ? launch_output_fold_wide(kClassMp[c], P.compute, P.state_bf16 != 0, P.fold_max_p[c], P.fold_q4[c],
+                                                     prm, un, P.fold_count[c], stream)
                            : launch_output_fold(kClassMp[c], P.compute, P.fold_s[c], P.state_bf16 != 0, prm, un,
                                                 P.fold_count[c], P.fold_lds_bytes[c], stream);
         if (e != hipSuccess) return hip_fail(e, "output fold launch");

@@ -385,8 +385,8 @@ hipError_t launch_pack_fold(const OpDev* ops, int n_ops, const double* gw, void*
 // stored once.
 bool fold_wide_supported(int mp, int ct, int q, int p);
 size_t fold_wide_lds();
-hipError_t launch_output_fold_wide(int mp, int ct, bool xb, const StageParams& prm, const FoldUnit* units,
-                                   int n_units, hipStream_t st);
+hipError_t launch_output_fold_wide(int mp, int ct, bool xb, int max_p, bool q4, const StageParams& prm,
+                                   const FoldUnit* units, int n_units, hipStream_t st);
 
 // Zeroes n int32 counters (a kernel, so that graph capture records no memset).
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
