@@ -2605,9 +2605,14 @@ static ssm_status backward_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       rp.k = k;
       rp.check_last = k >= 0;
       TimedLaunch tl(P, stream, 2);
-      // state by state (dL/dP_k) in FP32: the direct-load kernel
+      // state by state (dL/dP_k) with FP32 state: on the BF16 matrix cores
+      // where the stages themselves contract in BF16 (padded m 128, 256),
+      // else the FP32 direct-load kernel
       const bool ss = a_kind == RS_STATE && b_kind == RS_STATE && !P.state_f64 && mp >= 64;
-      hipError_t er = ss ? launch_outer_ss(mp, rp, stream) : launch_outer(mp, P.state_f64, rp, ty, stream);
+      const bool sb = ss && P.compute == DT_BF16 && mp >= 128;
+      hipError_t er = sb   ? launch_outer_bf16(mp, rp, stream)
+                      : ss ? launch_outer_ss(mp, rp, stream)
+                           : launch_outer(mp, P.state_f64, rp, ty, stream);
       tl.done();
       return er;
     };

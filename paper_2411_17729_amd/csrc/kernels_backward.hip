@@ -16,6 +16,7 @@ namespace ssmc {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename X>
 __device__ __forceinline__ X red_load(const void* p, int dtype, int64_t i) {
@@ -264,6 +265,141 @@ hipError_t launch_outer_ss(int mp, const RedParams& prm, hipStream_t s) {
     case 64: hipLaunchKernelGGL(k_outer_ss<64>, dim3(prm.n_chunks, 1), dim3(256), 0, s, prm); break;
     case 128: hipLaunchKernelGGL(k_outer_ss<128>, dim3(prm.n_chunks, 1), dim3(256), 0, s, prm); break;
     case 256: hipLaunchKernelGGL(k_outer_ss<256>, dim3(prm.n_chunks, 4), dim3(256), 0, s, prm); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The same reduction for plans whose stage contractions run in BF16: the
+// products of dL/dP_k on the BF16 matrix cores, from the FP32 state rounded
+// to BF16 (the operand type of the stages themselves), accumulated in FP32
+// within a chunk and in FP64 across chunks. One workgroup of eight waves
+// takes one chunk and the whole MP x MP output, so every state row is read
+// once; waves split it 2 (rows) x 4 (columns). The time rows are the MFMA
+// contraction (32 per step); a step's 32 rows of both operands are loaded
+// (a step ahead), rounded and written to LDS transposed, entry-major, so a
+// lane's operand (8 consecutive time rows of one entry) is 16 contiguous
+// bytes. Thread t loads rows 2 (t % 16) and 2 (t % 16) + 1 of entries
+// MP / 32 (t / 16) .. + MP / 32 - 1 and writes each entry's row pair as one
+// 32-bit word; the entry order is rotated by half a group for odd groups so
+// that the two half-waves of a write fall in different banks.
+// ---------------------------------------------------------------------------
+template <int MP>
+__global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_outer_bf16(RedParams prm) {
+  static_assert(MP == 128 || MP == 256, "16-byte loads of MP / 32 entries per thread");
+  constexpr int KR = 32;                 // time rows per step
+  constexpr int RS = KR + 8;             // LDS row stride (BF16 entries; 80 bytes)
+  constexpr int EG = MP / 32;            // entries of a thread's load group
+  constexpr int BA = MP / 32, BB = MP / 64;  // MFMA blocks of a wave (rows, columns)
+  constexpr int OPS = MP * RS;           // one operand buffer (BF16 entries)
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_obf[];
+  __bf16* lds = reinterpret_cast<__bf16*>(smem_obf);  // [2 steps][A, B][MP][RS]
+
+  const RedChunk ch = prm.chunks[blockIdx.x];
+  const SeqDev sq = prm.seqs[ch.seq];
+  float* part = reinterpret_cast<float*>(prm.partial) + (int64_t)ch.slot * prm.slot_stride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int aw0 = (wave >> 2) * (MP / 2), bw0 = (wave & 3) * (MP / 4);
+
+  f32x4 acc[BA][BB];
+#pragma unroll
+  for (int a = 0; a < BA; ++a)
+#pragma unroll
+    for (int b = 0; b < BB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const bool first = prm.a_first && prm.k >= 0 && prm.k == sq.last;
+  const bool active = !(prm.check_last && prm.k > sq.last);
+  const int64_t sh = prm.k >= 0 ? ((int64_t)1 << prm.k) : 0;
+  int64_t lo = ch.row0;
+  if (lo < sh) lo = sh;  // rows without a partner contribute nothing
+  const int64_t hi = (int64_t)ch.row0 + ch.nrows;
+  if (active && lo < hi) {
+    const float* A = reinterpret_cast<const float*>(first ? prm.a_first : prm.a_base) + sq.x_off;
+    const float* B = reinterpret_cast<const float*>(prm.b_base) + sq.x_off;
+    const int rp = threadIdx.x & 15, eg = threadIdx.x >> 4;
+    const int e0 = eg * EG;
+    constexpr int NV = EG / 4;  // 16-byte loads per row of a thread's group
+    f32x4 ra[2][NV], rb[2][NV];
+    auto load = [&](int64_t l0) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t l = l0 + 2 * rp + h;
+        const bool ok = l < hi;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          ra[h][v] = ok ? *reinterpret_cast<const f32x4*>(A + l * MP + e0 + 4 * v) : f32x4{0.f, 0.f, 0.f, 0.f};
+          rb[h][v] = ok ? *reinterpret_cast<const f32x4*>(B + (l - sh) * MP + e0 + 4 * v) : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    };
+    auto stage = [&](int buf) {
+      __bf16* la = lds + (size_t)buf * 2 * OPS;
+      __bf16* lb = la + OPS;
+#pragma unroll
+      for (int i = 0; i < EG; ++i) {
+        const int ei = (i + (eg & 1) * (EG / 2)) % EG;  // rotated entry order
+        const int e = e0 + ei;
+        const float a0 = ra[0][ei / 4][ei % 4], a1 = ra[1][ei / 4][ei % 4];
+        const float b0 = rb[0][ei / 4][ei % 4], b1 = rb[1][ei / 4][ei % 4];
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        const bf16x2 pa{(__bf16)a0, (__bf16)a1}, pb{(__bf16)b0, (__bf16)b1};  // round to nearest even
+        *reinterpret_cast<bf16x2*>(la + e * RS + 2 * rp) = pa;
+        *reinterpret_cast<bf16x2*>(lb + e * RS + 2 * rp) = pb;
+      }
+    };
+    int64_t l0 = lo;
+    load(l0);
+    int buf = 0;
+    for (; l0 < hi; l0 += KR) {
+      stage(buf);
+      if (l0 + KR < hi) load(l0 + KR);  // (uniform) the next step, in flight during this one
+      __syncthreads();
+      const __bf16* la = lds + (size_t)buf * 2 * OPS;
+      const __bf16* lb = la + OPS;
+      bf16x8 bo[BB];
+#pragma unroll
+      for (int b = 0; b < BB; ++b) bo[b] = *reinterpret_cast<const bf16x8*>(lb + (bw0 + 16 * b + r) * RS + 8 * g);
+#pragma unroll
+      for (int a = 0; a < BA; ++a) {
+        const bf16x8 ao = *reinterpret_cast<const bf16x8*>(la + (aw0 + 16 * a + r) * RS + 8 * g);
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao, bo[b], acc[a][b], 0, 0, 0);
+      }
+      buf ^= 1;
+    }
+  }
+  // accumulator entry v of block (a, b): output row 4 g + v, column r
+#pragma unroll
+  for (int a = 0; a < BA; ++a)
+#pragma unroll
+    for (int b = 0; b < BB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ro = aw0 + 16 * a + 4 * g + v, co = bw0 + 16 * b + r;
+        part[(int64_t)ro * MP + co] = acc[a][b][v];
+      }
+}
+
+size_t outer_bf16_lds(int mp) { return (size_t)2 * 2 * mp * (32 + 8) * sizeof(__bf16); }
+
+hipError_t launch_outer_bf16(int mp, const RedParams& prm, hipStream_t s) {
+  if (prm.n_chunks <= 0) return hipSuccess;
+  const size_t lds = outer_bf16_lds(mp);
+  switch (mp) {
+    case 128: {
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_outer_bf16<128>), lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_outer_bf16<128>, dim3(prm.n_chunks), dim3(512), lds, s, prm);
+      break;
+    }
+    case 256: {
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_outer_bf16<256>), lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_outer_bf16<256>, dim3(prm.n_chunks), dim3(512), lds, s, prm);
+      break;
+    }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -18,8 +18,13 @@
 // contiguous bytes of LDS. The kernel is specialised on the number of MFMA
 // steps (2^j p of 128, 256 or 512) and the operand width; each step's operand
 // register takes the next block's operand right after its MFMAs, so that the
-// LDS reads overlap the MFMAs. The state it writes is FP32, or
-// BF16 (XB, rounded once from the FP32 accumulators).
+// LDS reads overlap the MFMAs. The window of a row 16 rows on is the window
+// of the row shifted by 16 p entries, i.e. p / 2 MFMA steps (SH): step s >= SH
+// of a block takes the operand of step s - SH of the block before, so with
+// SH < KS the operands live in a ring of KS + SH registers and a block reads
+// only SH of them from LDS (KS / SH times fewer LDS reads), a block ahead of
+// their use. The state it writes is FP32, or BF16 (XB, rounded once from the
+// FP32 accumulators).
 #include "stage_common.h"
 #include "ssm_internal.h"
 
@@ -33,8 +38,9 @@ struct InputCfg {
 };
 
 // KS: MFMA steps (2^j p / 32); V16: 8 | p (one 16-byte operand read; else p =
-// 4); XB: BF16 state
-template <int MP, int KS, bool V16, bool XB>
+// 4); XB: BF16 state; SH: p / 2 when operands are reused across blocks (SH <
+// KS, SH divides KS), else 0
+template <int MP, int KS, bool V16, bool XB, int SH>
 __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_input_split(
     StageParams prm, const ResRange* units) {
   using C = InputCfg<MP>;
@@ -137,29 +143,8 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       return __builtin_shufflevector(lo, up, 0, 1, 2, 3, 4, 5, 6, 7);
     }
   };
-  bf16x8 bo[KS];
-#pragma unroll
-  for (int s = 0; s < KS; ++s) bo[s] = operand(0, s);
-  for (int b = 0; b < nblk; ++b) {
+  auto store_block = [&](int b, const f32x4(&acc)[NT]) {
     const int l = rg.row0 + 16 * b + r;
-    // each step's operand register takes the next block's operand right
-    // after its MFMAs, so the LDS reads of a block overlap the MFMAs of the
-    // one before
-    f32x4 acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[t][s], bo[s], acc[t], 0, 0, 0);
-      bo[s] = operand(b + 1, s);
-    }
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);           // MFMA
-      __builtin_amdgcn_sched_group_barrier(0x100, V16 ? 1 : 2, 0);  // DS read
-    }
     const uint32_t off = l < hi ? lane_off + (uint32_t)(16 * b + rg.row0) * (uint32_t)(MP * ES) : 0x80000000u;
     if constexpr (!XB) {
 #pragma unroll
@@ -178,28 +163,116 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         __builtin_amdgcn_raw_buffer_store_b64(u32x2{w4[0], w4[1]}, rout, off, 0, 0);
       }
     }
+  };
+  bf16x8 bo[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) bo[s] = operand(0, s);
+  if constexpr (SH == 0) {
+    for (int b = 0; b < nblk; ++b) {
+      // each step's operand register takes the next block's operand right
+      // after its MFMAs, so the LDS reads of a block overlap the MFMAs of the
+      // one before
+      f32x4 acc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[t][s], bo[s], acc[t], 0, 0, 0);
+        bo[s] = operand(b + 1, s);
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);           // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, V16 ? 1 : 2, 0);  // DS read
+      }
+      store_block(b, acc);
+    }
+  } else {
+    // operand ring of KS + SH registers: step s of block b sits in register
+    // (s - b SH) mod (KS + SH). The SH registers block b does not use take
+    // the next block's first SH operands (read from LDS at the start of block
+    // b, a block ahead of use); the rest of the next block's operands are
+    // this block's. NR blocks bring the ring back to its start. A block's
+    // accumulators are rounded and stored after the next block's MFMAs are
+    // issued (two accumulator sets), so no wave waits for its own results.
+    constexpr int RG = KS + SH, NR = RG / SH, NR2 = 2 * NR;
+    static_assert(SH > 0 && KS % SH == 0 && KS > SH, "operand reuse needs SH < KS dividing KS");
+    bf16x8 ring[RG];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) ring[s] = bo[s];
+    f32x4 acc[2][NT];
+    for (int b0 = 0; b0 < nblk; b0 += NR2) {
+#pragma unroll
+      for (int rr = 0; rr < NR2; ++rr) {
+        const int b = b0 + rr;
+        if (b < nblk) {
+          // the next block's first SH operands into the registers this block
+          // leaves free
+#pragma unroll
+          for (int i = 0; i < SH; ++i) ring[(i - (rr + 1) * SH + NR2 * RG) % RG] = operand(b + 1, i);
+          __builtin_amdgcn_sched_barrier(0);  // (left alone, the reads sink to the block's end)
+          f32x4(&a)[NT] = acc[rr & 1];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) a[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < KS; ++s) {
+            const bf16x8 bop = ring[(s - rr * SH + NR2 * RG) % RG];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) a[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[t][s], bop, a[t], 0, 0, 0);
+          }
+          if (b > 0) store_block(b - 1, acc[(rr + 1) & 1]);
+        }
+      }
+    }
+    if (nblk > 0) {
+      if ((nblk - 1) & 1)
+        store_block(nblk - 1, acc[1]);
+      else
+        store_block(nblk - 1, acc[0]);
+    }
   }
 }
 
-template <int MP, int KS, bool V16, bool XB>
+template <int MP, int KS, bool V16, bool XB, int SH>
 static hipError_t launch_input_t(const StageParams& prm, const ResRange* units, int n_units,
                                  size_t lds, hipStream_t s) {
   {
-    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_input_split<MP, KS, V16, XB>), (size_t)(65536));
+    hipError_t e =
+        ensure_dynamic_lds(reinterpret_cast<const void*>(&k_input_split<MP, KS, V16, XB, SH>), (size_t)(65536));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_input_split<MP, KS, V16, XB>), dim3(n_units), dim3(512), lds, s, prm, units);
+  hipLaunchKernelGGL((k_input_split<MP, KS, V16, XB, SH>), dim3(n_units), dim3(512), lds, s, prm, units);
   return hipGetLastError();
 }
 
+// operand reuse across blocks (SH = p / 2 steps) where the window spans more
+// than one block of rows: p = 4 (two 8-byte reads per operand) shifts by 2
+// steps, p = 8 by 4, p = 16 by 8
+template <int MP, int KS, bool XB>
+static hipError_t launch_input_x(int p, const StageParams& prm, const ResRange* units, int n_units, size_t lds,
+                                 hipStream_t s) {
+  if (p == 4) {
+    if constexpr (KS > 2) return launch_input_t<MP, KS, false, XB, 2>(prm, units, n_units, lds, s);
+    return launch_input_t<MP, KS, false, XB, 0>(prm, units, n_units, lds, s);
+  }
+  if (p == 8) {
+    if constexpr (KS > 4) return launch_input_t<MP, KS, true, XB, 4>(prm, units, n_units, lds, s);
+    return launch_input_t<MP, KS, true, XB, 0>(prm, units, n_units, lds, s);
+  }
+  if (p == 16) {
+    if constexpr (KS > 8) return launch_input_t<MP, KS, true, XB, 8>(prm, units, n_units, lds, s);
+    return launch_input_t<MP, KS, true, XB, 0>(prm, units, n_units, lds, s);
+  }
+  return launch_input_t<MP, KS, true, XB, 0>(prm, units, n_units, lds, s);
+}
+
 template <int MP, int KS>
-static hipError_t launch_input_w(bool v16, bool xb, const StageParams& prm, const ResRange* units,
+static hipError_t launch_input_w(int p, bool xb, const StageParams& prm, const ResRange* units,
                                  int n_units, size_t lds, hipStream_t s) {
-  if (xb)
-    return v16 ? launch_input_t<MP, KS, true, true>(prm, units, n_units, lds, s)
-               : launch_input_t<MP, KS, false, true>(prm, units, n_units, lds, s);
-  return v16 ? launch_input_t<MP, KS, true, false>(prm, units, n_units, lds, s)
-             : launch_input_t<MP, KS, false, false>(prm, units, n_units, lds, s);
+  return xb ? launch_input_x<MP, KS, true>(p, prm, units, n_units, lds, s)
+            : launch_input_x<MP, KS, false>(p, prm, units, n_units, lds, s);
 }
 
 bool input_split_supported(int mp, int ct, int p, int kdim) {
@@ -211,13 +284,12 @@ hipError_t launch_input_split(int mp, int ct, int p, int kdim, bool xb, const St
                               const ResRange* units, int n_units, size_t lds, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   if (!input_split_supported(mp, ct, p, kdim) || lds > 65536) return hipErrorInvalidValue;
-  const bool v16 = (p & 7) == 0;
   if (mp == 128)
-    return kdim == 128 ? launch_input_w<128, 4>(v16, xb, prm, units, n_units, lds, s)
-                       : launch_input_w<128, 8>(v16, xb, prm, units, n_units, lds, s);
-  return kdim == 128   ? launch_input_w<256, 4>(v16, xb, prm, units, n_units, lds, s)
-         : kdim == 256 ? launch_input_w<256, 8>(v16, xb, prm, units, n_units, lds, s)
-                       : launch_input_w<256, 16>(v16, xb, prm, units, n_units, lds, s);
+    return kdim == 128 ? launch_input_w<128, 4>(p, xb, prm, units, n_units, lds, s)
+                       : launch_input_w<128, 8>(p, xb, prm, units, n_units, lds, s);
+  return kdim == 128   ? launch_input_w<256, 4>(p, xb, prm, units, n_units, lds, s)
+         : kdim == 256 ? launch_input_w<256, 8>(p, xb, prm, units, n_units, lds, s)
+                       : launch_input_w<256, 16>(p, xb, prm, units, n_units, lds, s);
 }
 
 }  // namespace ssmc

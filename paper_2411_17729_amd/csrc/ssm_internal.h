@@ -405,6 +405,8 @@ int persistent_blocks_per_cu(int ct);
 
 // dL/dP_k between two FP32 state buffers (a_kind = b_kind = RS_STATE), padded m 64..256.
 hipError_t launch_outer_ss(int mp, const RedParams& prm, hipStream_t s);
+// dL/dP_k on the BF16 matrix cores (plans computing in BF16), mp of 128 and 256
+hipError_t launch_outer_bf16(int mp, const RedParams& prm, hipStream_t s);
 hipError_t launch_outer(int mp, int state_f64, const RedParams& prm, int tiles_y,
                         hipStream_t s);
 hipError_t launch_sum(const SumJob* jobs, int n_jobs, int max_elems, int k,
