@@ -85,6 +85,9 @@ def _args():
                          "8 x L=8192, m=128 FP32 gradients; ragged: 256 sequences of uneven L and m, "
                          "BF16, one persistent launch replayed as a HIP graph, forward and backward")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--ckpt-every", type=int, default=1,
+                    help="backward workloads: stage inputs kept every this many stages (1: every "
+                         "stage, no recompute; 0: the library's automatic sqrt rule)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other dtype and the recursion comparator")
@@ -485,7 +488,7 @@ def bench_backward(args):
     _gpu_init()
     from paper_2411_17729_amd import binding as B
     from paper_2411_17729_amd import cascade as CC
-    plan = CC.plan_for_workload(wl, compute="f32", with_backward=True)
+    plan = CC.plan_for_workload(wl, compute="f32", with_backward=True, ckpt_every=args.ckpt_every)
     u = CC.pack_u(wl, dtype=torch.float32)
     dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in wl.dy]), device="cuda").float()
     K, Wm = args.steps, args.warmup
@@ -506,7 +509,8 @@ def bench_backward(args):
         "config": {"workload": f"backward_hippo_m{ps.m}_p{ps.p}_q{ps.q}_B{len(wl.seqs)}_L{s0.L}_N{s0.N}",
                    "step": "ssm_cascade_backward: forward with checkpoints, recompute, adjoint "
                            "stages, gradient reductions, FP64 squaring and trapezoid adjoints",
-                   "delta": s0.delta, "seed": args.seed},
+                   "delta": s0.delta, "seed": args.seed, "ckpt_every": args.ckpt_every,
+                   "workspace_GiB": round(plan._nbytes / 2**30, 2)},
         "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK["f32_TFLOPs"],
                      "unit": "TFLOP/s", "frac": round(tf / PEAK["f32_TFLOPs"], 4), "traffic": None,
                      "kernel": "adjoint stages", "launches_timed": n_adj,
@@ -572,7 +576,7 @@ def bench_ragged(args):
     tkey = tune.signature(wl, "bf16", allow_bf16_state=True)
     cached = tkey in tune.load_cache()
     tn = tune.best_tuning(wl, compute="bf16", allow_bf16_state=True)
-    plan = CC.plan_for_workload(wl, compute="bf16", with_backward=True, **tn)
+    plan = CC.plan_for_workload(wl, compute="bf16", with_backward=True, ckpt_every=args.ckpt_every, **tn)
     info = plan.info()
     u = CC.pack_u(wl, dtype=torch.float32)
     dy = torch.as_tensor(np.concatenate([d.reshape(-1) for d in wl.dy]), device="cuda").float()
@@ -613,7 +617,8 @@ def bench_ragged(args):
         "config": {"workload": f"ragged_{len(wl.seqs)}seq_L{min(s.L for s in wl.seqs)}-{max(s.L for s in wl.seqs)}"
                                f"_m{'-'.join(map(str, ms_list))}_p4_q4",
                    "total_steps": wl.total_steps, "launch": "persistent" if info["launch"] == 2 else "per-stage",
-                   "graph": True, "seed": args.seed},
+                   "graph": True, "seed": args.seed, "ckpt_every": args.ckpt_every,
+                   "workspace_GiB": round(plan._nbytes / 2**30, 2)},
         "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
                      "frac": round(gbps / PEAK["hbm_GBps"], 4), "traffic": None,
                      "kernel": ("k_persist_res" if info["stage_kernel"] == 3 else "k_persistent")

@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "ssm_internal.h"
+#include "stage_common.h"
 
 namespace ssmc {
 
@@ -219,32 +220,58 @@ __global__ __launch_bounds__(256) void k_outer_ss(RedParams prm) {
   if (lo < sh) lo = sh;  // rows without a partner contribute nothing
   const int64_t hi = (int64_t)ch.row0 + ch.nrows;
   if (active && lo < hi) {
-    const float* A = reinterpret_cast<const float*>(first ? prm.a_first : prm.a_base) + sq.x_off +
-                     abase + V * lr;
-    const float* B = reinterpret_cast<const float*>(prm.b_base) + sq.x_off + bbase + V * lr;
-    auto ld = [&](const float* base, int64_t row, bool ok) -> VT {
-      return ok ? *reinterpret_cast<const VT*>(base + row * MP) : VT{};
+    // rows through buffer resources over the sequence's L x MP block (the
+    // host keeps L MP 4 < 2^31): rows from hi on get an offset past the end
+    // and read as zero, with no branch (a branch would make the compiler wait
+    // for each load where it is issued)
+    const uint32_t nrec = (uint32_t)sq.L * (uint32_t)(MP * 4);
+    const auto rA = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(reinterpret_cast<const float*>(first ? prm.a_first : prm.a_base) + sq.x_off), (short)0,
+        (int)nrec, kBufferWord3);
+    const auto rB = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(reinterpret_cast<const float*>(prm.b_base) + sq.x_off), (short)0, (int)nrec, kBufferWord3);
+    const uint32_t ca = (uint32_t)(abase + V * lr) * 4u, cb = (uint32_t)(bbase + V * lr) * 4u;
+    auto ld = [&](const __amdgpu_buffer_rsrc_t& rs, uint32_t col, int64_t row, bool ok) -> VT {
+      const uint32_t off = ((uint32_t)row * (uint32_t)(MP * 4) + col) | (ok ? 0u : 0x80000000u);
+      if constexpr (V == 4) {
+        return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+      } else {
+        return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+      }
     };
-    // two steps of four rows per iteration, the next pair's loads issued first
-    int64_t l = lo;
-    VT a0 = ld(A, l + kk, l + kk < hi), b0 = ld(B, l + kk - sh, l + kk < hi);
-    VT a1 = ld(A, l + 4 + kk, l + 4 + kk < hi), b1 = ld(B, l + 4 + kk - sh, l + 4 + kk < hi);
-    for (; l < hi; l += 8) {
-      const int64_t ln = l + 8;
-      const VT na0 = ld(A, ln + kk, ln + kk < hi), nb0 = ld(B, ln + kk - sh, ln + kk < hi);
-      const VT na1 = ld(A, ln + 4 + kk, ln + 4 + kk < hi), nb1 = ld(B, ln + 4 + kk - sh, ln + 4 + kk < hi);
+    // eight rows (two MFMA steps of four) per register set; two sets in
+    // turn, each loaded while the other is contracted (unrolled so that no
+    // register is copied, which would wait for its load where it is issued)
+    VT xa[2][2], xb[2][2];
+    auto load8 = [&](int set, int64_t l) {
 #pragma unroll
-      for (int a = 0; a < V; ++a)
+      for (int h = 0; h < 2; ++h) {
+        const int64_t row = l + 4 * h + kk;
+        xa[set][h] = ld(rA, ca, row, row < hi);
+        xb[set][h] = ld(rB, cb, row - sh, row < hi);
+      }
+    };
+    auto mfma8 = [&](int set) {
 #pragma unroll
-        for (int b = 0; b < V; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[a], b0[b], acc[a][b], 0, 0, 0);
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int a = 0; a < V; ++a)
+        for (int a = 0; a < V; ++a)
 #pragma unroll
-        for (int b = 0; b < V; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[a], b1[b], acc[a][b], 0, 0, 0);
-      a0 = na0;
-      b0 = nb0;
-      a1 = na1;
-      b1 = nb1;
+          for (int b = 0; b < V; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[set][h][a], xb[set][h][b], acc[a][b], 0, 0, 0);
+    };
+    // the scheduling fences keep each set's loads ahead of the other set's
+    // products (left alone, the compiler sinks them next to their use)
+    load8(0, lo);
+    for (int64_t l = lo; l < hi; l += 16) {
+      load8(1, l + 8);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma8(0);
+      __builtin_amdgcn_sched_barrier(0);
+      load8(0, l + 16);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma8(1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   // accumulator entry v of block (a, b): output row 4 kk + v, column lr
@@ -316,8 +343,16 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   if (lo < sh) lo = sh;  // rows without a partner contribute nothing
   const int64_t hi = (int64_t)ch.row0 + ch.nrows;
   if (active && lo < hi) {
-    const float* A = reinterpret_cast<const float*>(first ? prm.a_first : prm.a_base) + sq.x_off;
-    const float* B = reinterpret_cast<const float*>(prm.b_base) + sq.x_off;
+    // rows through buffer resources over the sequence's L x MP block (the
+    // host keeps L MP 4 < 2^31): rows from hi on get an offset past the end
+    // and read as zero, with no branch (a branch would make the compiler
+    // wait for each step's loads where they are issued)
+    const uint32_t nrec = (uint32_t)sq.L * (uint32_t)(MP * 4);
+    const auto ra_ = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(reinterpret_cast<const float*>(first ? prm.a_first : prm.a_base) + sq.x_off), (short)0,
+        (int)nrec, kBufferWord3);
+    const auto rb_ = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(reinterpret_cast<const float*>(prm.b_base) + sq.x_off), (short)0, (int)nrec, kBufferWord3);
     const int rp = threadIdx.x & 15, eg = threadIdx.x >> 4;
     const int e0 = eg * EG;
     constexpr int NV = EG / 4;  // 16-byte loads per row of a thread's group
@@ -326,11 +361,13 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int64_t l = l0 + 2 * rp + h;
-        const bool ok = l < hi;
+        const uint32_t oob = l < hi ? 0u : 0x80000000u;
+        const uint32_t oa = ((uint32_t)l * (uint32_t)MP + (uint32_t)e0) * 4u | oob;
+        const uint32_t ob = ((uint32_t)(l - sh) * (uint32_t)MP + (uint32_t)e0) * 4u | oob;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          ra[h][v] = ok ? *reinterpret_cast<const f32x4*>(A + l * MP + e0 + 4 * v) : f32x4{0.f, 0.f, 0.f, 0.f};
-          rb[h][v] = ok ? *reinterpret_cast<const f32x4*>(B + (l - sh) * MP + e0 + 4 * v) : f32x4{0.f, 0.f, 0.f, 0.f};
+          ra[h][v] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra_, oa + 16 * v, 0, 0));
+          rb[h][v] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb_, ob + 16 * v, 0, 0));
         }
       }
     };
