@@ -28,3 +28,12 @@ from .ssm_oracle import (  # noqa: F401
     auto_stages,
     free_response,
 )
+from .ssm_plr import (  # noqa: F401
+    plr_compress,
+    plr_dense,
+    plr_apply,
+    plr_ranks,
+    plr_flops,
+    plr_error_bound,
+    cascade_plr,
+)
