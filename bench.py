@@ -80,10 +80,12 @@ def _args():
                     help="state kept between the passes of a BF16 apply (bf16: where every pass "
                          "supports it, the default: within the BF16 tolerance, errors in the line); "
                          "the other choice is timed beside it")
-    ap.add_argument("--workload", default="batched", choices=["batched", "backward", "ragged"],
+    ap.add_argument("--workload", default="batched", choices=["batched", "backward", "ragged", "plr"],
                     help="batched: 16 x L=16384, m=256 forward (the headline line); backward: "
                          "8 x L=8192, m=128 FP32 gradients; ragged: 256 sequences of uneven L and m, "
-                         "BF16, one persistent launch replayed as a HIP graph, forward and backward")
+                         "BF16, one persistent launch replayed as a HIP graph, forward and backward; "
+                         "plr: the batched workload in FP32 and FP64 with partitioned low-rank powers "
+                         "against the dense stages")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--ckpt-every", type=int, default=1,
                     help="backward workloads: stage inputs kept every this many stages (1: every "
@@ -217,6 +219,8 @@ def main():
         return bench_backward(args)
     if args.workload == "ragged":
         return bench_ragged(args)
+    if args.workload == "plr":
+        return bench_plr(args)
 
     wl = W.batched(seed=args.seed)
     # the CPU oracle leg runs first, in forked workers, before the GPU is touched
@@ -666,6 +670,102 @@ def bench_ragged(args):
         out["rel_err_vs_fp64"] = {"bf16": rel}
         out["rel_err_sample"] = f"forward: sequences {done}; backward: sequences {bwd_sample}"
     plan.close()
+    print(json.dumps(out), flush=True)
+
+
+
+
+def bench_plr(args):
+    """The batched workload (16 x L=16384, m=256 HiPPO, p=q=8, N=13) in FP32 and
+    FP64, each applied with dense stages and with partitioned low-rank powers
+    (§5) where they halve the matrix-core steps: apply times (HIP graph
+    replays), the PLR stage launches' roofline (compulsory bytes: a read of the
+    stage input rows, of their partners and a write, per launch), the ranks
+    behind them, and the error of both against the FP64 oracle on two sampled
+    sequences."""
+    import numpy as np
+    import torch
+    from paper_2411_17729_amd import binding as B
+    from paper_2411_17729_amd import cascade as CC
+    from paper_2411_17729_amd import workloads as W
+    wl = W.batched(seed=args.seed)
+    sample = [0, len(wl.seqs) - 1]
+    refs = None
+    if not args.no_cpu:
+        ps0 = wl.sets[0]
+        jobs = [(ps0.A, ps0.B, ps0.C, ps0.D, wl.seqs[i].delta, wl.seqs[i].u) for i in sample]
+        res, _, _ = cpu_oracle_leg(_oracle_recursion_job, jobs, 1e9, len(jobs))
+        refs = [res[j] for j in range(len(jobs))]
+    _gpu_init()
+    s0, ps = wl.seqs[0], wl.sets[0]
+    wname = f"hippo_m{ps.m}_p{ps.p}_q{ps.q}_B{len(wl.seqs)}_L{s0.L}_N{s0.N}"
+    K, Wm = args.steps, args.warmup
+    out = {"metric": METRIC, "unit": "output steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": wname + "_plr", "sequences": len(wl.seqs), "L": s0.L, "m": ps.m,
+                      "p": ps.p, "q": ps.q, "N": s0.N, "seed": args.seed}}
+    legs = {}
+    for dt, digits in (("f32", 7), ("f64", 12)):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        u = CC.pack_u(wl, dtype=tdt)
+        steps = K if dt == "f32" else max(2, K // 5)
+        leg = {"plr_digits": digits}
+        ys = {}
+        for name, dg in (("dense", 0), ("plr", digits)):
+            plan = CC.plan_for_workload(wl, compute=dt, plr_digits=dg)
+            y = torch.empty(plan.layout.y_numel, dtype=tdt, device="cuda")
+            stream = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            g = plan.graph_apply(u, y, stream)
+            ms = _timed(lambda: CC.CascadePlan.graph_launch(g, stream), steps, Wm, stream)
+            CC.CascadePlan.graph_destroy(g)
+            info = plan.info()
+            ent = {"ms_per_step": round(ms, 4), "value": round(wl.total_steps / (ms * 1e-3), 1)}
+            if dg:
+                plan.timing_read(B.TIMING_PLR)
+                plan.timing(True)
+                for _ in range(min(steps, 10)):
+                    plan.apply(u, out=y)
+                torch.cuda.synchronize()
+                plan.timing(False)
+                n_l, k_ms = plan.timing_read(B.TIMING_PLR)
+                used = [k for k in range(s0.N + 1) if plan.plr_ranks(0, k)[1]]
+                ent["plr_stages"] = used
+                ent["ranks_op0"] = {k: max(plan.plr_ranks(0, k)[0]) for k in used}
+                if n_l > 0:
+                    per_apply = n_l / min(steps, 10)
+                    avg = k_ms / n_l
+                    rows = sum(max(0, s.L - (1 << k)) for s in wl.seqs for k in used)
+                    es = 8 if dt == "f64" else 4
+                    nbytes = sum(s.L for s in wl.seqs) * ps.m * es * 3 * len(used) / per_apply
+                    gbps = nbytes / (avg * 1e-3) / 1e9
+                    flops = info["plr_flops"] / per_apply
+                    peak_tf = PEAK["f64_TFLOPs"] if dt == "f64" else PEAK["f32_TFLOPs"]
+                    tf = flops / (avg * 1e-3) / 1e12
+                    ent["roofline"] = {
+                        "bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                        "frac": round(gbps / PEAK["hbm_GBps"], 4), "traffic": None, "kernel": "k_stage_plr",
+                        "launches_timed": n_l, "avg_launch_ms": round(avg, 5),
+                        "algorithmic_bytes_per_launch": round(nbytes),
+                        "plr_flops_per_launch": round(flops), "plr_TFLOPs": round(tf, 2),
+                        "plr_flops_frac_of_peak": round(tf / peak_tf, 4),
+                        "dense_flops_of_the_same_rows": round(info["plr_dense_flops"] / per_apply),
+                        "rows_per_apply": rows}
+            ys[name] = CC.unpack_y(wl, y)
+            leg[name] = ent
+            plan.close()
+        leg["speedup_plr_vs_dense"] = round(leg["dense"]["ms_per_step"] / leg["plr"]["ms_per_step"], 3)
+        if refs is not None:
+            leg["rel_err_vs_fp64"] = {
+                name: float(f"{max(float(np.linalg.norm(yy[i] - r) / np.linalg.norm(r)) for i, r in zip(sample, refs)):.3e}")
+                for name, yy in ys.items()}
+        legs[dt] = leg
+    out["dtype"] = "f32"
+    out["value"] = legs["f32"]["plr"]["value"]
+    out["ms_per_step"] = legs["f32"]["plr"]["ms_per_step"]
+    out["roofline"] = legs["f32"]["plr"].get("roofline")
+    out["legs"] = legs
+    out["rel_err_sample"] = f"sequences {sample}, oracle.trapezoid + oracle.recursion (FP64)"
     print(json.dumps(out), flush=True)
 
 

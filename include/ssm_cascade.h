@@ -205,7 +205,21 @@ typedef struct {
    * between passes) are then not used, and the plan launches per stage
    * (SSM_LAUNCH_PERSISTENT returns SSM_E_UNSUPPORTED). 0: the default. */
   int32_t final_state;
-  int32_t reserved[2];   /* must be 0 */
+  /* Partitioned low-rank powers (§5). d in 1..15: at prepare every power
+   * P_k = Abar^{2^k} of a padded size 64..256 is also built in PLR form: the
+   * dyadic partition down to 16 x 16 diagonal leaves, each off-diagonal block
+   * replaced by Q (Q^T B) with Q from pivoted Gram-Schmidt, of the smallest
+   * rank it reaches with ||B - Q Q^T B||_F <= 10^-d (absolute; at most 32 per
+   * block). Then ||P_k - PLR(P_k)||_2 <= 2 D 10^-d over the D levels. A stage
+   * of the forward apply runs in PLR form where, for every operator of its
+   * padded size, the ranks fit and the form takes at most half the matrix-core
+   * steps of the dense product; the stage must not be the last of any of those
+   * sequences (that stage forms y densely), nor one the input pass covers.
+   * ssm_cascade_plr_ranks reports the ranks and the stages chosen. FP32 and
+   * FP64 plans, forward only: with_backward, BF16 compute and persistent
+   * launches return SSM_E_UNSUPPORTED. 0: off (the default). */
+  int32_t plr_digits;
+  int32_t reserved;      /* must be 0 */
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */
@@ -275,6 +289,12 @@ typedef struct {
                                 write of y, are part of stage_bytes) */
   double fold_bytes;         /* compulsory HBM bytes of the output folds */
   double fold_flops;         /* flops of the output folds: 2 q m per row and lag */
+  int32_t plr_stages;        /* (padded size, stage) launches run in PLR form per apply */
+  int32_t plr_reserved;
+  double plr_flops;          /* flops of those launches over the rows a stage updates:
+                                per row 2 (16 mp + sum over the off-diagonal blocks of
+                                2 r s) with the ranks found at prepare */
+  double plr_dense_flops;    /* the same rows and stages as dense products, 2 mp^2 per row */
 } ssm_plan_info;
 
 typedef struct ssm_plan_s* ssm_plan;
@@ -457,6 +477,17 @@ ssm_status ssm_cascade_device_status(ssm_plan plan, hipStream_t stream);
  * host array N of n = n_seq entries. */
 ssm_status ssm_cascade_plan_stages(ssm_plan plan, int32_t* N, int32_t n);
 
+/* Partitioned low-rank powers (ssm_tuning.plr_digits): for operator `op` and
+ * stage k (0..N_op), the ranks of the off-diagonal blocks of P_k found at
+ * prepare into the host array ranks of n >= 32 entries, entry
+ * 2 (2^(d-1) - 1) + 2 g + side for level d (block size m_pad / 2^d), node g
+ * and side 0 (lower block) or 1 (upper block); 33 marks a block whose rank
+ * exceeds 32; entries past 2 (2^D - 1) are 0. *used = 1 if the forward apply
+ * runs stage k of this operator's padded size in PLR form. SSM_E_UNSUPPORTED
+ * for a plan prepared without PLR powers or an operator of padded size 32. */
+ssm_status ssm_cascade_plr_ranks(ssm_plan plan, int32_t op, int32_t k, int32_t* ranks, int32_t n,
+                                 int32_t* used);
+
 /* Host-side summary of a plan. */
 ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);
 
@@ -465,7 +496,8 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info);
  * around every kernel launch (this adds host work; leave it off otherwise).
  * ssm_cascade_timing_read returns, for kernel class `kind`
  * (0 = forward stage, 1 = adjoint stage, 2 = outer-product reduction,
- *  3 = recursion, 4 = forward stage pair, 5 = output fold), the number of timed launches and
+ *  3 = recursion, 4 = forward stage pair, 5 = output fold, 6 = forward stage in
+ *  PLR form), the number of timed launches and
  * their summed milliseconds,
  * after synchronizing the events, and clears the record. */
 ssm_status ssm_cascade_timing_enable(ssm_plan plan, int32_t enable);

@@ -28,6 +28,7 @@ SSM_STAGE_AUTO, SSM_STAGE_TILED, SSM_STAGE_RESIDENT, SSM_STAGE_CHAIN = 0, 1, 2, 
 
 # kernel classes of ssm_cascade_timing_read
 TIMING_STAGE, TIMING_ADJOINT, TIMING_REDUCE, TIMING_RECURSION, TIMING_PAIR, TIMING_FOLD = 0, 1, 2, 3, 4, 5
+TIMING_PLR = 6
 
 
 class SSMError(RuntimeError):
@@ -57,7 +58,7 @@ class ssm_tuning(C.Structure):
                 ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
                 ("pair_blocks", C.c_int32), ("input_split", C.c_int32), ("state_bf16", C.c_int32),
                 ("fold_stages", C.c_int32), ("spin_limit", C.c_int32), ("static_state", C.c_int32),
-                ("final_state", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("final_state", C.c_int32), ("plr_digits", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ssm_plan_info(C.Structure):
@@ -70,13 +71,16 @@ class ssm_plan_info(C.Structure):
         ("persistent_items", C.c_int64), ("pair_launches", C.c_int64), ("pair_bytes", C.c_double),
         ("pair_flops", C.c_double), ("state_dtype", C.c_int32), ("fold_stages", C.c_int32),
         ("fold_launches", C.c_int64), ("fold_bytes", C.c_double), ("fold_flops", C.c_double),
+        ("plr_stages", C.c_int32), ("plr_reserved", C.c_int32), ("plr_flops", C.c_double),
+        ("plr_dense_flops", C.c_double),
     ]
 
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
                 input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0):
+                state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0, plr_digits=0):
     t = ssm_tuning()
+    t.plr_digits = int(plr_digits)
     t.spin_limit = int(spin_limit)
     t.static_state = int(static_state)
     t.final_state = int(final_state)
@@ -104,7 +108,7 @@ EXPORTS = [
     "ssm_cascade_graph_apply", "ssm_cascade_graph_backward", "ssm_cascade_graph_launch",
     "ssm_cascade_graph_destroy", "ssm_status_string", "ssm_last_error", "ssm_cascade_device_status",
     "ssm_cascade_apply_noalloc", "ssm_cascade_apply_state", "ssm_cascade_backward_x0",
-    "ssm_cascade_plan_stages",
+    "ssm_cascade_plan_stages", "ssm_cascade_plr_ranks",
 ]
 
 
@@ -136,6 +140,8 @@ def load(path=LIB_PATH):
     lib.ssm_cascade_apply.argtypes = [vp, vp, i32, sz, vp, sz, vp]
     lib.ssm_cascade_plan_stages.restype = i32
     lib.ssm_cascade_plan_stages.argtypes = [vp, P(i32), i32]
+    lib.ssm_cascade_plr_ranks.restype = i32
+    lib.ssm_cascade_plr_ranks.argtypes = [vp, i32, i32, P(i32), i32, P(i32)]
     lib.ssm_cascade_backward_x0.restype = i32
     lib.ssm_cascade_backward_x0.argtypes = [vp, vp, i32, sz, vp, sz, vp, sz, vp, vp, sz, vp, sz, vp]
     lib.ssm_cascade_apply_state.restype = i32
@@ -225,6 +231,15 @@ def ssm_cascade_plan_stages(plan, n_seq):
     arr = (C.c_int32 * n_seq)()
     _check(load().ssm_cascade_plan_stages(plan, arr, n_seq), "ssm_cascade_plan_stages")
     return [int(v) for v in arr]
+
+
+def ssm_cascade_plr_ranks(plan, op, k):
+    """(ranks of the 32 rank-table slots of P_k of operator op, whether the apply
+    runs that stage in PLR form)."""
+    arr = (C.c_int32 * 32)()
+    used = C.c_int32(0)
+    _check(load().ssm_cascade_plr_ranks(plan, op, k, arr, 32, C.byref(used)), "ssm_cascade_plr_ranks")
+    return [int(v) for v in arr], bool(used.value)
 
 
 def ssm_cascade_backward_x0(plan, u_ptr, u_dtype, u_numel, x0_ptr, x0_numel, dy_ptr, dy_numel, du_ptr, dx0_ptr,

@@ -59,7 +59,8 @@ class CascadePlan:
                  compute: str = "f32", with_backward: bool = False, ckpt_every: int = 0,
                  device="cuda", launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto",
                  input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                 state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0):
+                 state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0,
+                 plr_digits=0):
         if not torch.cuda.is_available():
             raise RuntimeError("the fast-cascade library needs a ROCm GPU")
         B.load()
@@ -93,7 +94,7 @@ class CascadePlan:
             if isinstance(stage_kernel, str) else int(stage_kernel)
         self.tuning = B.make_tuning(mode, tile_rows, sk, input_stages, chain_blocks, pair_stages,
                                     pair_blocks, input_split, state_bf16, fold_stages, spin_limit,
-                                    static_state, final_state)
+                                    static_state, final_state, plr_digits)
         nbytes = B.ssm_cascade_workspace_bytes(layout.descs, self.disc, self.compute,
                                                with_backward, ckpt_every, self.tuning)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -254,6 +255,11 @@ class CascadePlan:
     def info(self):
         return B.ssm_cascade_plan_info(self.plan)
 
+    def plr_ranks(self, op: int, k: int):
+        """(rank table of P_k of operator op in PLR form, whether the apply runs
+        stage k of its padded size in that form)."""
+        return B.ssm_cascade_plr_ranks(self.plan, op, k)
+
     def device_status(self):
         """Synchronizes the stream and raises SSMError (SSM_E_HIP) if the last
         persistent launch gave up waiting for the items it depends on."""
@@ -299,7 +305,8 @@ class CascadePlan:
 def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, device="cuda",
                       launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto", input_stages=0,
                       chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0, state_bf16=0,
-                      fold_stages=0, disc=None, spin_limit=0, static_state=0, final_state=0):
+                      fold_stages=0, disc=None, spin_limit=0, static_state=0, final_state=0,
+                      plr_digits=0):
     """Builds the layout and plan of a ``workloads.Workload`` (discretization:
     the workload's, "given" or "trapezoid", unless ``disc`` names one)."""
     dims = [(ps.m, ps.p, ps.q) for ps in wl.sets]
@@ -313,7 +320,7 @@ def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, devi
                        input_stages=input_stages, chain_blocks=chain_blocks,
                        pair_stages=pair_stages, pair_blocks=pair_blocks, input_split=input_split,
                        state_bf16=state_bf16, fold_stages=fold_stages, spin_limit=spin_limit,
-                       static_state=static_state, final_state=final_state)
+                       static_state=static_state, final_state=final_state, plr_digits=plr_digits)
 
 
 def pack_u(wl, dtype=torch.float32, device="cuda"):

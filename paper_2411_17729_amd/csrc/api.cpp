@@ -15,6 +15,7 @@
 
 #include "../../include/ssm_cascade.h"
 #include "ssm_internal.h"
+#include "plr.h"
 
 using namespace ssmc;
 
@@ -175,6 +176,22 @@ struct ssm_plan_s {
   size_t m_fold = 0;
   int64_t fold_launches = 0;
   double fold_bytes = 0, fold_flops = 0;
+  // partitioned low-rank powers: records (compute type) per operator and
+  // stage, their rank table, FP64 scratch of the compression, compression
+  // jobs, stage units per class, the stages each class may run in PLR form
+  // and (once the ranks are read back at prepare) those it does
+  int plr_digits = 0;
+  Region r_plr, r_plr_rank, r_plr_q;
+  std::vector<PlrJob> plr_jobs;
+  std::vector<int64_t> plr_rec_off;
+  std::vector<int32_t> plr_rank_off;
+  std::vector<PlrUnit> plr_units;
+  int plr_start[4] = {0, 0, 0, 0}, plr_count[4] = {0, 0, 0, 0};
+  std::vector<int> plr_ok[4], plr_use[4];
+  std::vector<int32_t> plr_ranks_host;
+  int plr_max_s = 0, plr_stages = 0;
+  double plr_flops = 0, plr_dense_flops = 0;
+  size_t m_plr_jobs = 0, m_plr_recoff = 0, m_plr_rankoff = 0, m_plr_units = 0;
   // persistent launch
   std::vector<PItem> items;
   std::vector<int32_t> cnt_off, ntiles;
@@ -241,6 +258,8 @@ ssm_status validate_seqs(const ssm_seq_desc* seqs, int32_t n_seq) {
 
 void plan_backward(ssm_plan_s& P);
 void plan_backward_jobs(ssm_plan_s& P);
+void plan_plr(ssm_plan_s& P);
+void plr_select(ssm_plan_s& P);
 
 // Automatic N (a sequence given N < 0, tolerance 10^N): the largest it can
 // take is the smallest N whose window 2^(N+1) covers the sequence, where the
@@ -273,7 +292,19 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     if (seqs[i].N < 0) return fail(SSM_E_INVALID, "seq %d: automatic N not resolved", i);
   ssm_tuning tn{};
   if (tuning) tn = *tuning;
-  if (tn.reserved[0] != 0 || tn.reserved[1] != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.reserved != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.plr_digits < 0 || tn.plr_digits > 15)
+    return fail(SSM_E_INVALID, "plr_digits = %d: supported 0 (off) or 1..15", tn.plr_digits);
+  if (tn.plr_digits > 0) {
+    // the PLR stage runs FP32 or FP64 products, in the forward apply, per stage
+    if (compute == SSM_BF16)
+      return fail(SSM_E_UNSUPPORTED, "PLR powers: FP32 or FP64 compute (BF16 plans keep the fused dense passes)");
+    if (with_backward) return fail(SSM_E_UNSUPPORTED, "PLR powers: forward only (with_backward is set)");
+    if (tn.launch == SSM_LAUNCH_PERSISTENT)
+      return fail(SSM_E_UNSUPPORTED, "PLR powers need per-stage launches (launch is persistent)");
+    tn.launch = SSM_LAUNCH_PER_STAGE;
+  }
+  P.plr_digits = norms_region ? 0 : tn.plr_digits;
   if (tn.final_state < 0 || tn.final_state > 1)
     return fail(SSM_E_INVALID, "final_state = %d: supported 0 or 1", tn.final_state);
   if (tn.final_state) {
@@ -794,6 +825,8 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     P.state_bf16 = ok && any;
   }
 
+  plan_plr(P);
+
   // persistent work items, level by level (projection = level -1), longer
   // sequences first inside a level; default tile heights
   P.items.clear();
@@ -1119,6 +1152,14 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   off = align_up(off + sizeof(ResRange) * std::max<size_t>(1, P.input_units.size()));
   P.m_fold = off;
   off = align_up(off + sizeof(FoldUnit) * std::max<size_t>(1, P.fold_units.size()));
+  P.m_plr_jobs = off;
+  off = align_up(off + sizeof(PlrJob) * std::max<size_t>(1, P.plr_jobs.size()));
+  P.m_plr_recoff = off;
+  off = align_up(off + sizeof(int64_t) * std::max<size_t>(1, P.plr_rec_off.size()));
+  P.m_plr_rankoff = off;
+  off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, P.plr_rank_off.size()));
+  P.m_plr_units = off;
+  off = align_up(off + sizeof(PlrUnit) * std::max<size_t>(1, P.plr_units.size()));
   if (P.launch == SSM_LAUNCH_PERSISTENT) {
     P.m_ritems = off;
     off = align_up(off + sizeof(RItem) * std::max<size_t>(1, P.ritems.size()));
@@ -1175,6 +1216,9 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   if (norms_region)
     for (const OpDev& o : P.ops) P.n_norms += o.N + 1;
   take(P.r_norms, (size_t)P.n_norms * 8);
+  take(P.r_plr, P.r_plr.bytes);
+  take(P.r_plr_rank, P.r_plr_rank.bytes);
+  take(P.r_plr_q, P.r_plr_q.bytes);
   P.x_buf_bytes = (size_t)xoff * P.x_elem();
   take(P.r_x0, P.static_state ? 0 : P.x_buf_bytes);
   take(P.r_x1, P.static_state ? 0 : P.x_buf_bytes);
@@ -1191,6 +1235,154 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   return SSM_OK;
 }
 
+
+// Partitioned low-rank powers: the stages each padded-size class may run in
+// PLR form (per-stage launches of the forward apply, padded m 64..256, at or
+// after every folded input stage of the class, before its earliest last stage
+// so that no sequence forms y there, outside stage pairs and the output fold,
+// every sequence's L mp bytes below 2^31), the row units of those classes,
+// the records and rank slots of every operator of padded size >= 64, and a
+// compression job per off-diagonal block (plus one for the leaves) of every
+// eligible stage.
+void plan_plr(ssm_plan_s& P) {
+  P.plr_jobs.clear();
+  P.plr_units.clear();
+  P.plr_rec_off.assign(P.ops.size(), -1);
+  P.plr_rank_off.assign(P.ops.size(), -1);
+  P.plr_max_s = 0;
+  for (int c = 0; c < 4; ++c) {
+    P.plr_ok[c].clear();
+    P.plr_use[c].clear();
+    P.plr_start[c] = P.plr_count[c] = 0;
+  }
+  if (P.plr_digits <= 0 || P.launch != SSM_LAUNCH_PER_STAGE) return;
+  const int64_t es = (int64_t)P.x_elem();
+  for (int c = 1; c < 4; ++c) {
+    const int mp = kClassMp[c];
+    if (P.class_max_last[c] < 0) continue;
+    int kmax = 0, lmin = 1 << 30;
+    bool fits = true;
+    std::vector<int> ids;
+    for (int i = 0; i < P.n_seq; ++i) {
+      const SeqDev& sq = P.seqs[i];
+      if (P.ops[sq.op].mp != mp) continue;
+      ids.push_back(i);
+      kmax = std::max(kmax, sq.kry);
+      lmin = std::min(lmin, sq.last);
+      fits = fits && sq.L * mp * es < ((int64_t)1 << 31);
+    }
+    if (!fits) continue;
+    P.plr_ok[c].assign(P.class_max_last[c] + 1, 0);
+    P.plr_use[c].assign(P.class_max_last[c] + 1, 0);
+    bool any = false;
+    for (int k = kmax; k < lmin; ++k) {
+      const bool paired = (k < (int)P.pair_count[c].size() && P.pair_count[c][k] > 0) ||
+                          (k > 0 && k - 1 < (int)P.pair_count[c].size() && P.pair_count[c][k - 1] > 0);
+      const bool folded = P.fold_s[c] > 0 && k >= P.fold_k0[c];
+      if (paired || folded) continue;
+      P.plr_ok[c][k] = 1;
+      any = true;
+    }
+    if (!any) continue;
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
+    P.plr_start[c] = (int)P.plr_units.size();
+    const int rows = plr_unit_rows(P.compute);
+    for (int i : ids)
+      for (int64_t r0 = 0; r0 < P.seqs[i].L; r0 += rows) P.plr_units.push_back(PlrUnit{i, (int32_t)r0});
+    P.plr_count[c] = (int)P.plr_units.size() - P.plr_start[c];
+  }
+  int64_t rec = 0, rk = 0;
+  for (size_t oi = 0; oi < P.ops.size(); ++oi) {
+    const OpDev& o = P.ops[oi];
+    const int c = class_of(o.mp);
+    if (o.mp < 64 || P.plr_ok[c].empty()) continue;
+    P.plr_rec_off[oi] = rec;
+    P.plr_rank_off[oi] = (int32_t)rk;
+    rec += (int64_t)(o.N + 1) * plr_rec_elems(o.mp);
+    rk += (int64_t)(o.N + 1) * kPlrRankSlots;
+    const int D = plr_levels(o.mp);
+    for (int k = 0; k <= o.N && k < (int)P.plr_ok[c].size(); ++k) {
+      if (!P.plr_ok[c][k]) continue;
+      P.plr_jobs.push_back(PlrJob{(int32_t)oi, k, 0, 0, 0, {0, 0, 0}});
+      for (int d = 1; d <= D; ++d)
+        for (int g = 0; g < (1 << (d - 1)); ++g)
+          for (int side = 0; side < 2; ++side) P.plr_jobs.push_back(PlrJob{(int32_t)oi, k, d, g, side, {0, 0, 0}});
+      P.plr_max_s = std::max(P.plr_max_s, o.mp / 2);
+    }
+  }
+  P.r_plr.bytes = (size_t)rec * (P.compute == DT_F64 ? 8 : 4);
+  P.r_plr_rank.bytes = (size_t)rk * 4;
+  P.r_plr_q.bytes = P.plr_jobs.size() * (size_t)kPlrRC * kPlrMaxS * 8;
+  P.plr_ranks_host.assign((size_t)rk, 0);
+}
+
+// Matrix-core steps (16 x 16 x 4) per 16 rows of one stage of operator o in
+// PLR form with the ranks found at prepare: phase A ceil(r / 16) s / 4 per
+// block of rank r > 0, phase B 4 per leaf plus ceil(r / 4) for every level's
+// block over the leaf; -1 if a rank exceeds the cap.
+static int64_t plr_steps(const int32_t* rk, int mp) {
+  const int D = plr_levels(mp), NL = mp / kPlrLeaf;
+  int64_t steps = 0;
+  for (int d = 1; d <= D; ++d)
+    for (int g = 0; g < (1 << (d - 1)); ++g)
+      for (int side = 0; side < 2; ++side) {
+        const int r = rk[plr_rank_index(d, g, side)];
+        if (r > kPlrRC) return -1;
+        if (r > 0) steps += (int64_t)((r + 15) / 16) * ((mp >> d) / 4);
+      }
+  for (int f = 0; f < NL; ++f) {
+    steps += 4;
+    for (int d = 1; d <= D; ++d) {
+      const int h = NL >> d, hi = f / h;
+      const int r = rk[plr_rank_index(d, hi >> 1, (hi & 1) ? 0 : 1)];
+      steps += (r + 3) / 4;
+    }
+  }
+  return steps;
+}
+
+// per row flops of the PLR form as applied: 2 (16 mp + sum over blocks 2 r s)
+static double plr_row_flops(const int32_t* rk, int mp) {
+  const int D = plr_levels(mp);
+  double f = 16.0 * mp;
+  for (int d = 1; d <= D; ++d)
+    for (int g = 0; g < (1 << (d - 1)); ++g)
+      for (int side = 0; side < 2; ++side) f += 2.0 * rk[plr_rank_index(d, g, side)] * (mp >> d);
+  return 2.0 * f;
+}
+
+// After the ranks are read back: a class runs stage k in PLR form if every
+// operator of the class fits the rank cap there and needs at most half the
+// matrix-core steps of the dense product (mp / 16 output blocks of mp / 4).
+void plr_select(ssm_plan_s& P) {
+  P.plr_stages = 0;
+  P.plr_flops = P.plr_dense_flops = 0;
+  for (int c = 1; c < 4; ++c) {
+    const int mp = kClassMp[c];
+    for (int k = 0; k < (int)P.plr_ok[c].size(); ++k) {
+      P.plr_use[c][k] = 0;
+      if (!P.plr_ok[c][k]) continue;
+      bool ok = true;
+      for (size_t oi = 0; oi < P.ops.size() && ok; ++oi) {
+        const OpDev& o = P.ops[oi];
+        if (o.mp != mp || P.plr_rank_off[oi] < 0) continue;
+        const int64_t st = plr_steps(P.plr_ranks_host.data() + P.plr_rank_off[oi] + k * kPlrRankSlots, mp);
+        ok = st >= 0 && 2 * st <= (int64_t)(mp / 16) * (mp / 4);
+      }
+      if (!ok) continue;
+      P.plr_use[c][k] = 1;
+      ++P.plr_stages;
+      for (const SeqDev& sq : P.seqs) {
+        const OpDev& o = P.ops[sq.op];
+        if (o.mp != mp) continue;
+        const double rows = (double)std::max<int64_t>(0, sq.L - ((int64_t)1 << k));
+        const int32_t* rk = P.plr_ranks_host.data() + P.plr_rank_off[sq.op] + k * kPlrRankSlots;
+        P.plr_flops += rows * plr_row_flops(rk, mp);
+        P.plr_dense_flops += rows * 2.0 * mp * mp;
+      }
+    }
+  }
+}
 
 // Backward planning: checkpoint layout, reduction chunks, sum / GEMM /
 // scatter job lists and the FP64 gradient workspace. Offsets of the
@@ -2105,6 +2297,14 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (!P->fold_units.empty())
     std::memcpy(P->meta_host.data() + P->m_fold, P->fold_units.data(),
                 sizeof(FoldUnit) * P->fold_units.size());
+  if (!P->plr_jobs.empty()) {
+    unsigned char* mh = P->meta_host.data();
+    std::memcpy(mh + P->m_plr_jobs, P->plr_jobs.data(), sizeof(PlrJob) * P->plr_jobs.size());
+    std::memcpy(mh + P->m_plr_recoff, P->plr_rec_off.data(), sizeof(int64_t) * P->plr_rec_off.size());
+    std::memcpy(mh + P->m_plr_rankoff, P->plr_rank_off.data(), sizeof(int32_t) * P->plr_rank_off.size());
+    if (!P->plr_units.empty())
+      std::memcpy(mh + P->m_plr_units, P->plr_units.data(), sizeof(PlrUnit) * P->plr_units.size());
+  }
   if (P->launch == SSM_LAUNCH_PERSISTENT) {
     unsigned char* mh = P->meta_host.data();
     if (!P->items.empty())
@@ -2221,6 +2421,25 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                   P->with_backward, P->ws + P->r_small.off, P->state_f64, P->max_mp, P->max_N,
                   stream);
   if (e != hipSuccess) return bail(hip_fail(e, "pack launch"));
+  if (!P->plr_jobs.empty()) {
+    // PLR forms of the eligible stages' powers, and their ranks read back
+    PlrCompressParams cp{};
+    cp.ops = ops_d;
+    cp.jobs = reinterpret_cast<const PlrJob*>(meta + P->m_plr_jobs);
+    cp.pw = pw;
+    cp.rec = P->ws + P->r_plr.off;
+    cp.rec_off = reinterpret_cast<const int64_t*>(meta + P->m_plr_recoff);
+    cp.ranks = P->at<int32_t>(P->r_plr_rank);
+    cp.rank_off = reinterpret_cast<const int32_t*>(meta + P->m_plr_rankoff);
+    cp.qs = P->at<double>(P->r_plr_q);
+    const double tol = std::pow(10.0, -(double)P->plr_digits);
+    cp.tol2 = tol * tol;
+    e = launch_zero_i32(cp.ranks, (int64_t)(P->r_plr_rank.bytes / 4), stream);
+    if (e == hipSuccess) e = launch_plr_compress(P->compute, cp, (int)P->plr_jobs.size(), P->plr_max_s, stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "PLR compression launch"));
+    e = hipMemcpyAsync(P->plr_ranks_host.data(), cp.ranks, P->r_plr_rank.bytes, hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "PLR rank read"));
+  }
   int status_h[4] = {0, 0, 0, 0};
   e = hipMemcpyAsync(status_h, status_d, sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return bail(hip_fail(e, "status read"));
@@ -2228,6 +2447,7 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (e != hipSuccess) return bail(hip_fail(e, "prepare synchronization"));
   if (status_h[0] != 0)
     return bail(fail(SSM_E_NUMERIC, "I - delta/2 A is singular to working precision"));
+  if (!P->plr_jobs.empty()) plr_select(*P);
   *out = P;
   return SSM_OK;
 }
@@ -2377,6 +2597,27 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
         if (e != hipSuccess) return hip_fail(e, "output fold launch");
         tl.done();
         break;
+      }
+      if (kk < (int)P.plr_use[c].size() && P.plr_use[c][kk]) {  // P_k in PLR form
+        TimedLaunch tl(P, stream, 6, timed);
+        unsigned char* meta = P.ws + P.r_meta.off;
+        PlrStageParams sp{};
+        sp.seqs = prm.seqs;
+        sp.units = reinterpret_cast<const PlrUnit*>(meta + P.m_plr_units) + P.plr_start[c];
+        sp.n_units = P.plr_count[c];
+        sp.k = kk;
+        sp.rec = P.ws + P.r_plr.off;
+        sp.rec_off = reinterpret_cast<const int64_t*>(meta + P.m_plr_recoff);
+        sp.ranks = P.at<int32_t>(P.r_plr_rank);
+        sp.rank_off = reinterpret_cast<const int32_t*>(meta + P.m_plr_rankoff);
+        sp.xin = prm.xin;
+        sp.xout = prm.xout;
+        e = launch_stage_plr(kClassMp[c], P.compute, sp, stream);
+        if (e != hipSuccess) return hip_fail(e, "PLR stage launch");
+        tl.done();
+        cur ^= 1;
+        ++kk;
+        continue;
       }
       const bool pair = kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0;
       TimedLaunch tl(P, stream, pair ? 4 : 0, timed);
@@ -2821,6 +3062,28 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->fold_flops = plan->fold_flops;
   info->fold_stages = 0;
   for (int c = 0; c < 4; ++c) info->fold_stages = std::max(info->fold_stages, plan->fold_s[c]);
+  info->plr_stages = plan->plr_stages;
+  info->plr_reserved = 0;
+  info->plr_flops = plan->plr_flops;
+  info->plr_dense_flops = plan->plr_dense_flops;
+  return SSM_OK;
+}
+
+ssm_status ssm_cascade_plr_ranks(ssm_plan plan, int32_t op, int32_t k, int32_t* ranks, int32_t n,
+                                 int32_t* used) {
+  g_last_error.clear();
+  if (!plan) return fail(SSM_E_NOT_PREPARED, "plan is NULL");
+  if (!ranks || !used || n < kPlrRankSlots) return fail(SSM_E_INVALID, "ranks must hold %d entries", kPlrRankSlots);
+  if (op < 0 || op >= plan->n_ops) return fail(SSM_E_INVALID, "op %d outside 0..%d", op, plan->n_ops - 1);
+  const OpDev& o = plan->ops[op];
+  if (k < 0 || k > o.N) return fail(SSM_E_INVALID, "k %d outside 0..%d", k, o.N);
+  if (plan->plr_digits <= 0 || plan->plr_rank_off.empty() || plan->plr_rank_off[op] < 0)
+    return fail(SSM_E_UNSUPPORTED, "operator %d has no PLR powers (plr_digits 0, padded m 32 or no eligible stage)",
+                op);
+  const int c = class_of(o.mp);
+  for (int i = 0; i < kPlrRankSlots; ++i)
+    ranks[i] = plan->plr_ranks_host[(size_t)plan->plr_rank_off[op] + (size_t)k * kPlrRankSlots + i];
+  *used = k < (int)plan->plr_use[c].size() ? plan->plr_use[c][k] : 0;
   return SSM_OK;
 }
 

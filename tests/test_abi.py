@@ -132,7 +132,7 @@ def test_tuning_is_validated(lib):
     t = B.make_tuning(tile_rows=(0, 64, 0, 0))  # half of the default 128 for m <= 64
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
     t = B.make_tuning()
-    t.reserved[1] = 1
+    t.reserved = 1
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
     # final_state: 0 or 1, not with an explicitly persistent launch
     for bad in (B.make_tuning(final_state=2), B.make_tuning(final_state=-1),
@@ -179,3 +179,34 @@ def test_graph_calls_reject_on_host(lib):
     assert lib.ssm_cascade_graph_apply(None, None, 1, 0, None, 0, None, C.byref(g)) == B.SSM_E_NOT_PREPARED
     assert lib.ssm_cascade_graph_launch(None, None) == B.SSM_E_INVALID
     assert lib.ssm_cascade_graph_destroy(None) == B.SSM_OK
+
+
+def test_plr_tuning_is_validated(lib):
+    """PLR powers: digits 0..15; FP32 or FP64 compute, forward only, per-stage
+    launches; the records, rank table and compression scratch enlarge the
+    workspace of a plan with an eligible stage."""
+    from paper_2411_17729_amd import binding as B
+    d = _desc()
+    d.m, d.N, d.L = 256, 8, 4096
+    arr = (B.ssm_seq_desc * 1)(d)
+    for bad in (B.make_tuning(plr_digits=-1), B.make_tuning(plr_digits=16)):
+        assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(bad)) == 0
+    t = B.make_tuning(plr_digits=6)
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 2, 0, 0, C.byref(t)) == 0  # BF16
+    assert "PLR" in lib.ssm_last_error().decode()
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 1, 1, C.byref(t)) == 0  # backward
+    t2 = B.make_tuning(plr_digits=6, launch=B.SSM_LAUNCH_PERSISTENT)
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t2)) == 0
+    off = lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, None)
+    for compute in (0, 1):  # FP64, FP32
+        on = lib.ssm_cascade_workspace_bytes(arr, 1, 0, compute, 0, 0, C.byref(t))
+        assert on > lib.ssm_cascade_workspace_bytes(arr, 1, 0, compute, 0, 0, None) > 0
+    assert off > 0
+
+
+def test_plr_ranks_rejects_on_host(lib):
+    from paper_2411_17729_amd import binding as B
+    r = (C.c_int32 * 32)()
+    used = C.c_int32(0)
+    assert lib.ssm_cascade_plr_ranks(None, 0, 0, r, 32, C.byref(used)) == B.SSM_E_NOT_PREPARED
+
