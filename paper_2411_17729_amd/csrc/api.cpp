@@ -168,6 +168,18 @@ struct ssm_plan_s {
   // stage and their number (0: none), workgroup units, LDS bytes
   int fold_k0[4] = {0, 0, 0, 0}, fold_s[4] = {0, 0, 0, 0};
   bool fold_wide[4] = {false, false, false, false};  // six stages, paired lags, lags split over waves
+  // classes whose sequences end at different stages (ragged batches): each
+  // sequence folds its own last seq_fold_s stages from seq_fold_k0 on, after
+  // stage pairs from the input pass up to there; the folds run as launches
+  // grouped by kernel, depth and the state buffer holding their input
+  bool fold_mixed[4] = {false, false, false, false};
+  std::vector<int> seq_fold_s, seq_fold_k0;
+  struct FoldLaunch {
+    int c, wide, s, buf, start, count, max_p;
+    bool q4;
+    size_t lds;
+  };
+  std::vector<FoldLaunch> mixed_folds;
   std::vector<FoldUnit> fold_units;
   int fold_start[4] = {0, 0, 0, 0}, fold_count[4] = {0, 0, 0, 0};
   size_t fold_lds_bytes[4] = {0, 0, 0, 0};
@@ -653,9 +665,13 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   // whose sequences all end at the same stage and share the folded input
   // stages, q <= 16 and p <= 64; s as large as the LDS holds the 2^s G_j and
   // such that the stages between the input pass and the fold pair up.
+  P.seq_fold_s.assign(n_seq, 0);
+  P.seq_fold_k0.assign(n_seq, 0);
+  P.mixed_folds.clear();
   for (int c = 0; c < 4; ++c) {
     P.fold_s[c] = P.fold_k0[c] = 0;
     P.fold_wide[c] = false;
+    P.fold_mixed[c] = false;
     if (P.class_max_last[c] < 0 || tn.fold_stages == -1 || P.launch != SSM_LAUNCH_PER_STAGE ||
         P.stage_kernel != SSM_STAGE_CHAIN || !fold_supported(kClassMp[c], (int)compute, 2))
       continue;
@@ -671,6 +687,46 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
         max_p = std::max(max_p, sq.p);
         ok = ok && sq.q <= 16 && sq.p <= 64 && sq.L * (int64_t)kClassMp[c] * 4 <= ((int64_t)1 << 31);
       }
+    if (ok && min_last != max_last && kmin == kmax && kmin >= 4 && tn.pair_stages != 1 &&
+        pair_supported(kClassMp[c], (int)compute)) {
+      // ragged class: every sequence's own fold depth s_i (the largest the
+      // kernels take with last - s_i + 1 - kry even, so that stage pairs from
+      // the input pass end right before it); operators shared by sequences
+      // that would fold differently keep the class on single stages
+      const int mp = kClassMp[c];
+      const int cap = tn.fold_stages > 0 ? tn.fold_stages : 6;
+      std::map<int, std::pair<int, int>> op_fold;
+      bool all = true;
+      std::vector<std::pair<int, int>> pick(n_seq, {0, 0});
+      for (int i = 0; i < n_seq && all; ++i) {
+        const SeqDev& sq = P.seqs[i];
+        if (P.ops[sq.op].mp != mp) continue;
+        const int rem = sq.last - kmin + 1;
+        int sf = 0;
+        for (int t = std::min(rem, cap); t >= 2 && !sf; --t) {
+          if ((rem - t) % 2) continue;
+          if (t == 6 ? fold_wide_supported(mp, (int)compute, sq.q, sq.p) : t <= fold_max_stages(mp)) sf = t;
+        }
+        if (!sf) {
+          all = false;
+          break;
+        }
+        const std::pair<int, int> f{sf, sq.last - sf + 1};
+        auto it = op_fold.find(sq.op);
+        if (it != op_fold.end() && it->second != f) all = false;
+        op_fold[sq.op] = f;
+        pick[i] = f;
+      }
+      if (all) {
+        P.fold_mixed[c] = true;
+        for (int i = 0; i < n_seq; ++i)
+          if (P.ops[P.seqs[i].op].mp == mp) {
+            P.seq_fold_s[i] = pick[i].first;
+            P.seq_fold_k0[i] = pick[i].second;
+          }
+      }
+      continue;
+    }
     if (!ok || min_last != max_last || kmin != kmax) continue;
     const bool wide_ok = fold_wide_supported(kClassMp[c], (int)compute, max_q, max_p);
     const int smax = std::min(wide_ok ? 6 : fold_max_stages(kClassMp[c]), tn.fold_stages > 0 ? tn.fold_stages : 99);
@@ -721,19 +777,28 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     if (!fits) continue;
     std::stable_sort(ids.begin(), ids.end(),
                      [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
-    // (with a fold, the pairs stop at its first stage and there is no tail pair)
-    const int pair_end = P.fold_s[c] > 0 ? P.fold_k0[c] - 1 : min_last;
+    // (with a fold, the pairs stop at its first stage and there is no tail
+    // pair; a ragged class with per-sequence folds pairs each sequence up to
+    // its own fold)
+    int pair_end = P.fold_s[c] > 0 ? P.fold_k0[c] - 1 : min_last;
+    if (P.fold_mixed[c]) {
+      pair_end = 0;
+      for (int i : ids) pair_end = std::max(pair_end, P.seq_fold_k0[i] - 1);
+    }
+    auto pairs_at = [&](int i, int kk) { return !P.fold_mixed[c] || kk + 2 <= P.seq_fold_k0[i]; };
     for (int kk = std::max(4, max_kry); kk + 1 <= pair_end; kk += 2) {
-      const bool tail = P.fold_s[c] == 0 && kk + 1 == min_last;
+      const bool tail = P.fold_s[c] == 0 && !P.fold_mixed[c] && kk + 1 == min_last;
       if (tail && !(min_last == max_last && small_io)) break;
       const int64_t sh = (int64_t)1 << kk;
       int64_t blocks = 0;
-      for (int i : ids) blocks += (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
+      for (int i : ids)
+        if (pairs_at(i, kk)) blocks += (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
       int T = tn.pair_blocks > 0 ? tn.pair_blocks
                                  : (int)std::min<int64_t>(64, std::max<int64_t>(8, blocks / 256));
       if (tail) T = std::max(1, std::min(T, 65536 / (64 * (max_p + max_q))));
       P.pair_start[c][kk] = (int)P.pair_units.size();
       for (int i : ids) {
+        if (!pairs_at(i, kk)) continue;
         const int64_t nflat = (sh / 16) * ((P.seqs[i].L + sh - 1) / sh);
         for (int64_t f0 = 0; f0 < nflat; f0 += T)
           P.pair_units.push_back(PairUnit{i, (int32_t)f0, T, 0});
@@ -759,6 +824,49 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     P.fold_start[c] = (int)P.fold_units.size();
     P.fold_count[c] = 0;
     P.fold_lds_bytes[c] = 0;
+    if (P.fold_mixed[c]) {
+      // one launch per (kernel, depth, state buffer of the fold's input):
+      // after the input pass (its output in buffer kry mod 2) each pair
+      // moves a sequence to the other buffer, (k0 - kry) / 2 pairs in all
+      std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+      for (int i = 0; i < n_seq; ++i) {
+        const SeqDev& sq = P.seqs[i];
+        if (class_of(P.ops[sq.op].mp) != c) continue;
+        const int sf = P.seq_fold_s[i], k0 = P.seq_fold_k0[i];
+        const int buf = (sq.kry & 1) ^ (((k0 - sq.kry) / 2) & 1);
+        groups[std::make_tuple(sf == 6 ? 1 : 0, sf, buf)].push_back(i);
+        OpDev& o = P.ops[sq.op];
+        o.fold_s = sf;
+        o.fold_k0 = k0;
+        o.fold_paired = sf == 6 ? 1 : 0;
+      }
+      for (auto& g : groups) {
+        std::vector<int>& ids = g.second;
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return P.seqs[a].L > P.seqs[b].L; });
+        ssm_plan_s::FoldLaunch fl{};
+        fl.c = c;
+        fl.wide = std::get<0>(g.first);
+        fl.s = std::get<1>(g.first);
+        fl.buf = std::get<2>(g.first);
+        fl.start = (int)P.fold_units.size();
+        fl.max_p = 1;
+        fl.q4 = true;
+        int max_q = 1;
+        for (int i : ids) {
+          const SeqDev& sq = P.seqs[i];
+          fl.max_p = std::max(fl.max_p, sq.p);
+          max_q = std::max(max_q, sq.q);
+          fl.q4 = fl.q4 && sq.q % 4 == 0 && sq.y_off % 4 == 0;
+          const int ncol = (1 << P.seq_fold_k0[i]) / 16;
+          for (int c0 = 0; c0 < ncol; c0 += fl.wide ? 1 : 4)
+            P.fold_units.push_back(FoldUnit{i, c0, fl.wide ? 1 : std::min(4, ncol - c0), 0});
+        }
+        fl.count = (int)P.fold_units.size() - fl.start;
+        fl.lds = fl.wide ? fold_wide_lds() : fold_lds(kClassMp[c], fl.s, fl.max_p, max_q);
+        P.mixed_folds.push_back(fl);
+      }
+      continue;
+    }
     if (P.fold_s[c] == 0) continue;
     std::vector<int> ids;
     int max_p = 1, max_q = 1;
@@ -806,6 +914,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       if (P.class_max_last[c] < 0) continue;
       any = true;
       ok = P.class_input_count[c] > 0;
+      if (P.fold_mixed[c]) continue;  // the split input pass, pairs and every sequence's fold
       int kk = P.class_min_kry[c];
       bool tail = false;
       while (ok && kk <= P.class_max_last[c]) {
@@ -964,7 +1073,18 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
   P.fold_launches = 0;
   P.fold_bytes = P.fold_flops = 0;
   for (int c = 0; c < 4; ++c)
-    if (P.class_max_last[c] >= 0) {
+    if (P.class_max_last[c] >= 0 && P.fold_mixed[c]) {  // pairs, then the grouped folds
+      for (int kk = 0; kk <= P.class_max_last[c]; ++kk)
+        if (pair_at(c, kk)) {
+          ++P.stage_launches;
+          ++P.pair_launches;
+        }
+      for (const auto& fl : P.mixed_folds)
+        if (fl.c == c) {
+          ++P.stage_launches;
+          ++P.fold_launches;
+        }
+    } else if (P.class_max_last[c] >= 0) {
       P.stage_launches += std::max(0, P.class_max_last[c] + 1 - P.class_min_kry[c]);
       for (int kk = 0; kk <= P.class_max_last[c]; ++kk)
         if (pair_at(c, kk)) {
@@ -982,20 +1102,22 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     const int m = P.ops[s.op].m;
     const int c = class_of(P.ops[s.op].mp);
     // stages run as stage contractions: after the input pass, before a fold
-    const int kend = P.fold_s[c] > 0 ? P.fold_k0[c] - 1 : s.last;
+    const int fs = P.fold_mixed[c] ? P.seq_fold_s[i] : P.fold_s[c];
+    const int fk0 = P.fold_mixed[c] ? P.seq_fold_k0[i] : P.fold_k0[c];
+    const int kend = fs > 0 ? fk0 - 1 : s.last;
     for (int kk = s.kry; kk <= kend; ++kk) {
       const int64_t sh = (int64_t)1 << kk;
       if (sh < s.L) P.stage_flops += 2.0 * m * m * (double)(s.L - sh);
     }
-    if (P.fold_s[c] > 0) {
+    if (fs > 0) {
       // the fold reads every state row once and writes y; row l takes
       // min(2^s, l / 2^k0 + 1) products with the q x m G_j
       const double in_row = (double)m * xe, out_row = (double)s.q * ye;
       P.stage_bytes += s.L * (in_row + out_row);
       P.fold_bytes += s.L * (in_row + out_row);
-      const int64_t band = (int64_t)1 << P.fold_k0[c];
+      const int64_t band = (int64_t)1 << fk0;
       for (int64_t b = 0; b * band < s.L; ++b)
-        P.fold_flops += 2.0 * s.q * m * (double)std::min<int64_t>((int64_t)1 << P.fold_s[c], b + 1) *
+        P.fold_flops += 2.0 * s.q * m * (double)std::min<int64_t>((int64_t)1 << fs, b + 1) *
                         (double)std::min<int64_t>(band, s.L - b * band);
     }
     for (int kk = s.kry; kk <= kend; ++kk) {
@@ -2578,6 +2700,39 @@ static ssm_status apply_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype, si
                            xb0, xb1, P.ws + P.r_small.off, y, P.final_state != 0, stream);
       if (e != hipSuccess) return hip_fail(e, "initial state launch");
     }
+    if (P.fold_mixed[c]) {
+      // ragged class: stage pairs from the input pass on (each sequence up to
+      // its own fold), then the folds, each group reading the buffer its
+      // sequences' last pair wrote
+      int cur = k_begin & 1;
+      for (int kk = k_begin; kk < (int)P.pair_count[c].size() && P.pair_count[c][kk] > 0; kk += 2) {
+        prm.k = kk;
+        prm.xin = (cur ? xb1 : xb0);
+        prm.xout = (cur ? xb0 : xb1);
+        TimedLaunch tl(P, stream, 4, timed);
+        const PairUnit* un = reinterpret_cast<const PairUnit*>(P.ws + P.r_meta.off + P.m_pair) +
+                             P.pair_start[c][kk];
+        e = launch_stage_pair(kClassMp[c], P.compute, prm, un, P.pair_count[c][kk], false, P.state_bf16 != 0,
+                              P.pair_lds_bytes[c][kk], stream);
+        if (e != hipSuccess) return hip_fail(e, "stage pair launch");
+        tl.done();
+        cur ^= 1;
+      }
+      for (const auto& fl : P.mixed_folds) {
+        if (fl.c != c) continue;
+        prm.xin = (fl.buf ? xb1 : xb0);
+        prm.xout = (fl.buf ? xb0 : xb1);
+        TimedLaunch tl(P, stream, 5, timed);
+        const FoldUnit* un = reinterpret_cast<const FoldUnit*>(P.ws + P.r_meta.off + P.m_fold) + fl.start;
+        e = fl.wide ? launch_output_fold_wide(kClassMp[c], P.compute, P.state_bf16 != 0, fl.max_p, fl.q4, prm, un,
+                                              fl.count, stream)
+                    : launch_output_fold(kClassMp[c], P.compute, fl.s, P.state_bf16 != 0, prm, un, fl.count,
+                                         fl.lds, stream);
+        if (e != hipSuccess) return hip_fail(e, "output fold launch");
+        tl.done();
+      }
+      continue;
+    }
     // the input of stage kk is in buffer kk % 2 until the first stage pair;
     // from there on every sequence of the class runs every stage, and the
     // buffers simply alternate per launch
@@ -3062,6 +3217,7 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->fold_flops = plan->fold_flops;
   info->fold_stages = 0;
   for (int c = 0; c < 4; ++c) info->fold_stages = std::max(info->fold_stages, plan->fold_s[c]);
+  for (int f : plan->seq_fold_s) info->fold_stages = std::max(info->fold_stages, f);
   info->plr_stages = plan->plr_stages;
   info->plr_reserved = 0;
   info->plr_flops = plan->plr_flops;

@@ -270,3 +270,49 @@ def test_folded_input_stages(compute):
         ea, eb = parity_err(ya[i], ref[i]), parity_err(yb[i], ref[i])
         print(compute, i, f"folded {ea:.2e} plain {eb:.2e}", flush=True)
         assert ea <= tol and eb <= tol, (i, ea, eb)
+
+
+def _ragged_mixed_lasts(seed, with_small_class):
+    # classes of padded size 128 and 256 whose sequences end at different
+    # stages (N = ceil(log2 L) - 1), p = q = 4 as in the ragged workload
+    rng = np.random.default_rng(seed)
+    spec = [(256, 600), (256, 1500), (200, 3000), (256, 5000), (256, 9000), (256, 20000),
+            (128, 700), (100, 2100), (128, 4200), (128, 9000)]
+    if with_small_class:
+        spec += [(64, 1000), (50, 3000)]
+    sets, seqs = [], []
+    for i, (m, L) in enumerate(spec):
+        A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, 4)) / m, rng.standard_normal((4, m)) / m,
+                               rng.standard_normal((4, 4)) / m))
+        N = max(0, int(math.ceil(math.log2(L))) - 1)
+        seqs.append(W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, N, rng.standard_normal((L, 4))))
+    return W.Workload("ragged_mixed", sets, seqs)
+
+
+@pytest.mark.parametrize("state_bf16,small", [(0, True), (1, False)])
+def test_ragged_per_sequence_folds(state_bf16, small):
+    """Per-stage BF16 plan of a ragged batch: every sequence of the padded 128
+    and 256 classes is paired up to its own output fold (depth and first stage
+    per sequence, folds grouped by kernel, depth and input buffer). Against
+    the oracle at the BF16 bound and against the plan without folds."""
+    from paper_2411_17729_amd import cascade as CC
+    wl = _ragged_mixed_lasts(5, small)
+    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", state_bf16=state_bf16)
+    info = plan.info()
+    assert info["fold_launches"] >= 3 and info["pair_launches"] >= 2, info
+    assert info["state_dtype"] == (2 if state_bf16 else 1)
+    u = CC.pack_u(wl, dtype=torch.float32)
+    y = CC.unpack_y(wl, plan.apply(u))
+    plain = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", fold_stages=-1)
+    assert plain.info()["fold_launches"] == 0
+    yp = CC.unpack_y(wl, plain.apply(u))
+    torch.cuda.synchronize()
+    ref = _oracle(wl)
+    for i, s in enumerate(wl.seqs):
+        uq = s.u.astype(np.float32).astype(np.float64)
+        D = wl.sets[s.param_set].D
+        e = parity_err(y[i] - uq @ D.T, ref[i] - uq @ D.T)
+        ep = parity_err(y[i], yp[i])
+        print("seq", i, "L", s.L, "m", wl.sets[s.param_set].m, f"state {e:.3e} vs unfolded {ep:.3e}", flush=True)
+        assert e <= 2e-2 and ep <= 2e-2, (i, e, ep)
