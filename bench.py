@@ -610,6 +610,18 @@ def bench_ragged(args):
     reads = [plan.timing_read(kind) for kind in (B.TIMING_STAGE, B.TIMING_PAIR, B.TIMING_FOLD)]
     n_k = sum(r[0] for r in reads)
     t_k = sum(r[1] for r in reads)
+    # one eager backward with event timing: its forward stages (inputs of
+    # every stage kept), the adjoint stages and the gradient reductions
+    plan.timing(True)
+    plan.backward(u, dy)
+    torch.cuda.synchronize()
+    plan.timing(False)
+    b_fwd, b_adj, b_red = (plan.timing_read(kind) for kind in (B.TIMING_STAGE, B.TIMING_ADJOINT, B.TIMING_REDUCE))
+    # compulsory bytes of the adjoint stages: each reads and writes every
+    # adjoint row (FP32, m entries) once per stage the sequence runs
+    adj_bytes = sum(8.0 * wl.sets[s.param_set].m * s.L * (min(s.N, (s.L - 1).bit_length() - 1) + 1)
+                    for s in wl.seqs if s.L > 1)
+    adj_gbps = adj_bytes / (b_adj[1] * 1e-3) / 1e9
     CC.CascadePlan.graph_destroy(g_fwd)
     CC.CascadePlan.graph_destroy(g_bwd)
     gbps = info["stage_bytes"] / (t_k * 1e-3) / 1e9
@@ -630,7 +642,18 @@ def bench_ragged(args):
                      "launches_timed": n_k, "apply_kernel_ms": round(t_k, 5),
                      "algorithmic_bytes_per_apply": round(info["stage_bytes"])},
         "backward": {"value": round(wl.total_steps / (ms_b * 1e-3), 1), "ms_per_step": round(ms_b, 4),
-                     "graph": True},
+                     "graph": True,
+                     "breakdown_ms": {"forward_stages": round(b_fwd[1], 3), "adjoint_stages": round(b_adj[1], 3),
+                                      "reductions": round(b_red[1], 3),
+                                      "launches": [b_fwd[0], b_adj[0], b_red[0]],
+                                      "note": "one eager backward with per-launch events; the rest of "
+                                              "ms_per_step is FP64 squaring and discretization adjoints, "
+                                              "sums, copies and launch gaps"},
+                     "roofline": {"bound": "hbm", "achieved": round(adj_gbps, 1), "peak": PEAK["hbm_GBps"],
+                                  "unit": "GB/s", "frac": round(adj_gbps / PEAK["hbm_GBps"], 4), "traffic": None,
+                                  "kernel": "adjoint stages of one backward, together",
+                                  "launches_timed": b_adj[0], "kernel_ms": round(b_adj[1], 4),
+                                  "algorithmic_bytes": round(adj_bytes)}},
         "tuning": {"choice": {k: (list(v) if isinstance(v, tuple) else v) for k, v in tn.items()},
                    "cache_key": tkey, "from_cache": cached},
     }

@@ -3006,9 +3006,13 @@ static ssm_status backward_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       // else the FP32 direct-load kernel
       const bool ss = a_kind == RS_STATE && b_kind == RS_STATE && !P.state_f64 && mp >= 64;
       const bool sb = ss && P.compute == DT_BF16 && mp >= 128;
-      hipError_t er = sb   ? launch_outer_bf16(mp, rp, stream)
-                      : ss ? launch_outer_ss(mp, rp, stream)
-                           : launch_outer(mp, P.state_f64, rp, ty, stream);
+      // one side dy (width q) or u (width p) of at most 16: the thin kernel
+      const int narrow = a_kind == RS_DY ? qm : a_kind == RS_U ? pm : b_kind == RS_U ? pm : b_kind == RS_DY ? qm : 1 << 30;
+      const bool thin = !(a_kind == RS_STATE && b_kind == RS_STATE) && narrow <= 16;
+      hipError_t er = sb     ? launch_outer_bf16(mp, rp, stream)
+                      : ss   ? launch_outer_ss(mp, rp, stream)
+                      : thin ? launch_outer_thin(mp, P.state_f64, rp, stream)
+                             : launch_outer(mp, P.state_f64, rp, ty, stream);
       tl.done();
       return er;
     };

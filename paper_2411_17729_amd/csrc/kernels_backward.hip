@@ -167,6 +167,79 @@ static hipError_t launch_outer_t(const RedParams& prm, int tiles_y, hipStream_t 
   return hipGetLastError();
 }
 
+// Thin reductions (dC = sum dy x^T, dD = sum dy u^T, dL/dBbar = sum g u^T):
+// one side of the outer product is at most 16 wide. Thread t takes column
+// t mod W' of the wide side (W' the power of two >= its width) and every
+// (256 / W')-th row of the chunk, so a row of the wide side is read with one
+// coalesced access per thread and the narrow row (the same for every thread
+// of a row) comes from the cache; each thread keeps 16 sums, added over the
+// row phases through LDS at the end.
+template <int MP, typename X>
+__global__ __launch_bounds__(256) void k_outer_thin(RedParams prm) {
+  constexpr int NN = 16;
+  __shared__ X red[NN][256];
+  const RedChunk ch = prm.chunks[blockIdx.x];
+  const SeqDev sq = prm.seqs[ch.seq];
+  const bool first = prm.a_first && prm.k >= 0 && prm.k == sq.last;
+  const RowSrc<X> A = row_src<MP, X>(prm, sq, prm.a_kind, first ? prm.a_first : prm.a_base);
+  const RowSrc<X> B = row_src<MP, X>(prm, sq, prm.b_kind, prm.b_base);
+  const bool a_narrow = prm.a_kind != RS_STATE;
+  const RowSrc<X>& Nw = a_narrow ? A : B;  // narrow side
+  const RowSrc<X>& Ww = a_narrow ? B : A;  // wide side
+  const int nw = Nw.width, ww = Ww.width;
+  int wp = 1;
+  while (wp < ww) wp <<= 1;
+  const int phases = 256 / wp;
+  const int t = threadIdx.x, c = t % wp, ph = t / wp;
+  X acc[NN];
+#pragma unroll
+  for (int j = 0; j < NN; ++j) acc[j] = (X)0;
+  const bool active = !(prm.check_last && prm.k > sq.last);
+  const int64_t s = prm.k >= 0 ? ((int64_t)1 << prm.k) : 0;
+  int64_t lo = ch.row0;
+  if (lo < s) lo = s;
+  const int64_t hi = (int64_t)ch.row0 + ch.nrows;
+  if (active && c < ww) {
+    // B rows are shifted by s: the wide side's when A is narrow, else the narrow side's
+    const int64_t sw = a_narrow ? s : 0, sn = a_narrow ? 0 : s;
+    for (int64_t l = lo + ph; l < hi; l += phases) {
+      const X wv = Ww.at(l - sw, c);
+#pragma unroll
+      for (int j = 0; j < NN; ++j)
+        if (j < nw) acc[j] += Nw.at(l - sn, j) * wv;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NN; ++j) red[j][t] = acc[j];
+  __syncthreads();
+  X* part = reinterpret_cast<X*>(prm.partial) + (int64_t)ch.slot * prm.slot_stride;
+  for (int e = t; e < nw * ww; e += 256) {
+    const int j = e / ww, cc = e % ww;
+    X v = (X)0;
+    for (int q = 0; q < phases; ++q) v += red[j][q * wp + cc];
+    // output rows follow A: (narrow j, wide cc) when A is narrow, else (cc, j)
+    if (a_narrow) part[(int64_t)j * B.width + cc] = v;
+    else part[(int64_t)cc * B.width + j] = v;
+  }
+}
+
+template <int MP, typename X>
+static hipError_t launch_outer_thin_t(const RedParams& prm, hipStream_t s) {
+  if (prm.n_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_outer_thin<MP, X>), dim3(prm.n_chunks), dim3(256), 0, s, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_thin(int mp, int state_f64, const RedParams& prm, hipStream_t s) {
+  switch (mp) {
+    case 32: return state_f64 ? launch_outer_thin_t<32, double>(prm, s) : launch_outer_thin_t<32, float>(prm, s);
+    case 64: return state_f64 ? launch_outer_thin_t<64, double>(prm, s) : launch_outer_thin_t<64, float>(prm, s);
+    case 128: return state_f64 ? launch_outer_thin_t<128, double>(prm, s) : launch_outer_thin_t<128, float>(prm, s);
+    case 256: return state_f64 ? launch_outer_thin_t<256, double>(prm, s) : launch_outer_thin_t<256, float>(prm, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_outer(int mp, int state_f64, const RedParams& prm, int tiles_y,
                         hipStream_t s) {
   switch (mp) {

@@ -407,6 +407,9 @@ int persistent_blocks_per_cu(int ct);
 hipError_t launch_outer_ss(int mp, const RedParams& prm, hipStream_t s);
 // dL/dP_k on the BF16 matrix cores (plans computing in BF16), mp of 128 and 256
 hipError_t launch_outer_bf16(int mp, const RedParams& prm, hipStream_t s);
+// outer products with one side at most 16 wide (dy or u against a state, dy
+// against u): rows read once, coalesced, sums per thread
+hipError_t launch_outer_thin(int mp, int state_f64, const RedParams& prm, hipStream_t s);
 hipError_t launch_outer(int mp, int state_f64, const RedParams& prm, int tiles_y,
                         hipStream_t s);
 hipError_t launch_sum(const SumJob* jobs, int n_jobs, int max_elems, int k,
