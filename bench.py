@@ -425,6 +425,15 @@ def main():
         out["rel_err_sample"] = (f"sequences {done}; y: the output, Cx: y - D u (the part that "
                                  f"passes through the state)")
 
+    _copy_probe(args, out)
+
+    print(json.dumps(out), flush=True)
+
+
+def _copy_probe(args, out):
+    """One device-to-device copy of --copy-probe-mib MiB after the measurement:
+    a transfer of known size beside the kernels in a counter run."""
+    import torch
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -433,8 +442,6 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = n * 4
-
-    print(json.dumps(out), flush=True)
 
 
 def _timed(fn, steps, warm, stream=None):
@@ -789,6 +796,7 @@ def bench_plr(args):
     out["roofline"] = legs["f32"]["plr"].get("roofline")
     out["legs"] = legs
     out["rel_err_sample"] = f"sequences {sample}, oracle.trapezoid + oracle.recursion (FP64)"
+    _copy_probe(args, out)
     print(json.dumps(out), flush=True)
 
 

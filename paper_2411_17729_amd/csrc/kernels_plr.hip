@@ -206,25 +206,25 @@ __device__ __forceinline__ f64x4 mfma4(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One PLR stage over a unit of 4 NT 16 rows of one sequence: each wave owns NT
-// blocks of 16 consecutive rows and computes them alone (no LDS). In the
-// 16 x 16 x 4 products the time rows are the N side; K runs over the 16
-// columns of a leaf or an off-diagonal block's columns (phase A, lane group a
-// taking columns 4a .. 4a + 3 of every 16) and over ranks (phase B).
-//   Phase A: Z = X_s[:, J] V (rows of the product are ranks; the A-row to rank
-//            map is chosen so that lane group a holds ranks a + 4v, v < 4).
-//   Phase B: y[:, I] = x[:, I] + X_s[:, I] L^T + sum over levels of Z U^T, the
-//            Z registers used as B operands as they are; the A-row to output
-//            map makes lane group a hold outputs 4a .. 4a + 3.
-// Leaves are visited in order; at level d the Z of the block whose rows hold
-// the current leaf is formed when the leaf opens that block's row range.
+// One PLR stage over a unit of 4 NT 16 rows of one sequence (NT = 2 for FP32,
+// 1 for FP64): each wave owns NT blocks of 16 consecutive rows and computes
+// them alone (no LDS). In the 16 x 16 x 4 products the time rows are the N
+// side; K runs over 16 columns of a leaf or of an off-diagonal block (lane
+// group a taking columns 4a .. 4a + 3) and over ranks.
+//   Z = X_s[:, J] V: the rows of the product are ranks; the A-row to rank map
+//       is chosen so that lane group a holds ranks a + 4v, v < 4.
+//   y[:, I] = x[:, I] + X_s[:, I] L^T + sum over levels of Z U^T, the Z
+//       registers used as B operands as they are; the A-row to output map
+//       makes lane group a hold outputs 4a .. 4a + 3.
+// Leaves are visited in order. Lower-triangular forms take one sweep (below);
+// otherwise the Z of a block is formed when the leaf sweep opens its row range.
 template <int MP, typename X>
 __global__ __launch_bounds__(kPlrThreads) void k_stage_plr(PlrStageParams prm) {
   using V4 = typename Row4<X>::T;
   using Acc = V4;
   constexpr bool F64 = sizeof(X) == 8;
   constexpr int D = plr_levels(MP), NL = MP / kPlrLeaf;
-  constexpr int NT = F64 ? 2 : 4;
+  constexpr int NT = F64 ? 1 : 2;
   constexpr uint32_t ES = sizeof(X);
   const PlrUnit un = prm.units[blockIdx.x];
   const SeqDev sq = prm.seqs[un.seq];
@@ -257,6 +257,78 @@ __global__ __launch_bounds__(kPlrThreads) void k_stage_plr(PlrStageParams prm) {
   for (int d = 0; d < D; ++d)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) z[d][nt][0] = z[d][nt][1] = Acc{};
+
+  // Lower-triangular forms (every upper block empty, as for all powers of a
+  // lower-triangular Abar): one sweep over the leaves reads each 16-column
+  // chunk of X_s once. At level d the chunk adds into the Z of the node whose
+  // left half holds it; a leaf in a right half uses the Z its node finished
+  // over the left half, so one Z per level is live.
+  bool lower = true;
+#pragma unroll
+  for (int d = 1; d <= D; ++d)
+    for (int g = 0; g < (1 << (d - 1)); ++g) lower = lower && rk[plr_rank_index(d, g, 1)] == 0;
+  if (lower) {
+    for (int f = 0; f < NL; ++f) {
+      const int i0 = f * kPlrLeaf;
+      const uint32_t cb = (uint32_t)(i0 + 4 * ga) * ES;
+      Acc y[NT];
+      V4 xs[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        y[nt] = Row4<X>::ld(rin, orow[nt] + cb);
+        xs[nt] = Row4<X>::ld(rin, osh[nt] + cb);
+      }
+      const V4 la = ld4(rec + plr_leaf_off(MP) + (int64_t)f * kPlrLeaf * kPlrLeaf + sigB * kPlrLeaf + 4 * ga);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) y[nt] = mfma4(la[v], xs[nt][v], y[nt]);
+#pragma unroll
+      for (int d = 1; d <= D; ++d) {  // right halves: y += U Z
+        const int h = NL >> d, hi = f / h;
+        if (!(hi & 1)) continue;
+        const int r = rk[plr_rank_index(d, hi >> 1, 0)];
+        if (r <= 0 || r > kPlrRC) continue;
+        const X* U = rec + plr_block_off(MP, d, hi >> 1, 0) + (int64_t)((f % h) * kPlrLeaf + sigB) * kPlrRC;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if (16 * b >= r) break;
+          const V4 ua = ld4(U + 16 * b + 4 * ga);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if (16 * b + 4 * v >= r) break;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) y[nt] = mfma4(ua[v], z[d - 1][nt][b][v], y[nt]);
+          }
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) Row4<X>::st(y[nt], rout, orow[nt] + cb);
+#pragma unroll
+      for (int d = 1; d <= D; ++d) {  // left halves: Z += X_s[:, chunk] V[chunk, :]
+        const int h = NL >> d, hi = f / h;
+        if (hi & 1) continue;
+        if (f % h == 0) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) z[d - 1][nt][0] = z[d - 1][nt][1] = Acc{};
+        }
+        const int r = rk[plr_rank_index(d, hi >> 1, 0)];
+        if (r <= 0 || r > kPlrRC) continue;
+        const int s = MP >> d;
+        const X* Vt = rec + plr_block_off(MP, d, hi >> 1, 0) + (int64_t)s * kPlrRC + (f % h) * kPlrLeaf + 4 * ga;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if (16 * b >= r) break;
+          const V4 va = ld4(Vt + (int64_t)(16 * b + sigA) * s);
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) z[d - 1][nt][b] = mfma4(va[v], xs[nt][v], z[d - 1][nt][b]);
+        }
+      }
+    }
+    return;
+  }
 
   for (int f = 0; f < NL; ++f) {
     // phase A: blocks whose row range opens at leaf f

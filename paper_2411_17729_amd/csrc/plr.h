@@ -46,7 +46,7 @@ struct PlrCompressParams {
   double tol2;             // squared Frobenius tolerance per block
 };
 
-// Rows [row0, row0 + 4 NT 16) of sequence seq (NT = 4 for FP32, 2 for FP64).
+// Rows [row0, row0 + plr_unit_rows) of sequence seq (4 waves of NT 16-row blocks).
 struct PlrUnit {
   int32_t seq, row0;
 };
@@ -65,7 +65,7 @@ struct PlrStageParams {
 };
 
 // rows of one PLR stage workgroup
-constexpr int plr_unit_rows(int compute) { return compute == DT_F64 ? 128 : 256; }
+constexpr int plr_unit_rows(int compute) { return compute == DT_F64 ? 64 : 128; }
 
 size_t plr_compress_lds(int max_s);
 hipError_t launch_plr_compress(int compute, const PlrCompressParams& prm, int n_jobs, int max_s,

@@ -28,7 +28,7 @@ def _bound(wl, seq, eps):
     most eps in the 2-norm: e_k <= (1 + ||P_k||) e_{k-1} + eps max_l ||v_l^(k)||,
     then ||C|| e (all stages counted, a superset of those run in PLR form)."""
     ps = wl.sets[seq.param_set]
-    Abar, Bbar = O.trapezoid(ps.A, ps.B, seq.delta)
+    Abar, Bbar = (ps.A, ps.B) if wl.given else O.trapezoid(ps.A, ps.B, seq.delta)
     P = O.powers(Abar, seq.N)
     _, st = O.cascade(Abar, Bbar, ps.C, np.zeros_like(ps.D), seq.u, seq.N, return_stages=True)
     e = 0.0
@@ -191,3 +191,27 @@ def test_plr_graph_replays():
             assert torch.equal(y, ref), rep
     finally:
         CC.CascadePlan.graph_destroy(g)
+
+
+def test_plr_two_sided_forms():
+    """Abar = diag(lambda) + a rank-1 term: off-diagonal blocks on both sides
+    of the diagonal (rank 1 at stage 0, at most 2^k later), so the stage runs
+    the general path (Z of each block formed when its row range opens)."""
+    rng = np.random.default_rng(12)
+    m, p, q, L = 256, 2, 2, 1500  # (at padded 128 a rank-1 pair of blocks per node does not pay)
+    a, b = rng.standard_normal(m), rng.standard_normal(m)
+    A = np.diag(rng.uniform(0.5, 0.95, m)) + 0.05 * np.outer(a, b) / (np.linalg.norm(a) * np.linalg.norm(b))
+    ps = W.ParamSet(A, rng.standard_normal((m, p)) / m, rng.standard_normal((q, m)) / m,
+                    rng.standard_normal((q, p)) / m)
+    seqs = []
+    for _ in range(2):
+        s_ = W.Sequence(0, 0.1, L, 9, None)
+        s_.u = rng.standard_normal((L, p))
+        seqs.append(s_)
+    wl = W.Workload("two_sided_m256", [ps], seqs, given=True)
+    plan, info, got, worst = _check(wl, "f32", 7, input_stages=-1)
+    assert info["plr_stages"] > 0
+    ranks, used = plan.plr_ranks(0, 0)
+    assert used and ranks[1] == 1 and ranks[0] == 1  # level 1: lower and upper blocks of rank 1
+    assert worst <= TOL["f32"]
+
