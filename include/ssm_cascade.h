@@ -219,7 +219,14 @@ typedef struct {
    * FP64 plans, forward only: with_backward, BF16 compute and persistent
    * launches return SSM_E_UNSUPPORTED. 0: off (the default). */
   int32_t plr_digits;
-  int32_t reserved;      /* must be 0 */
+  /* Smallest padded state size: 0 (the default: m padded to 32, 64, 128 or
+   * 256) or 64, 128, 256, every operator padded to at least this size. The
+   * padding is exact (the padded part of Abar is the identity on a state that
+   * no input reaches, and C ignores it). Padding m <= 64 to 128 lets a ragged
+   * BF16 batch run every class through the fused passes (input pass, stage
+   * pairs, output folds) and keep its state in BF16; the padded rows cost
+   * their share of flops and bytes. */
+  int32_t min_padded_m;
 } ssm_tuning;
 
 /* One sequence of a (possibly ragged) batch. Host memory. */

@@ -58,7 +58,7 @@ class ssm_tuning(C.Structure):
                 ("input_stages", C.c_int32), ("chain_blocks", C.c_int32), ("pair_stages", C.c_int32),
                 ("pair_blocks", C.c_int32), ("input_split", C.c_int32), ("state_bf16", C.c_int32),
                 ("fold_stages", C.c_int32), ("spin_limit", C.c_int32), ("static_state", C.c_int32),
-                ("final_state", C.c_int32), ("plr_digits", C.c_int32), ("reserved", C.c_int32)]
+                ("final_state", C.c_int32), ("plr_digits", C.c_int32), ("min_padded_m", C.c_int32)]
 
 
 class ssm_plan_info(C.Structure):
@@ -78,9 +78,11 @@ class ssm_plan_info(C.Structure):
 
 def make_tuning(launch=SSM_LAUNCH_AUTO, tile_rows=(0, 0, 0, 0), stage_kernel=SSM_STAGE_AUTO,
                 input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
-                state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0, plr_digits=0):
+                state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0, plr_digits=0,
+                min_padded_m=0):
     t = ssm_tuning()
     t.plr_digits = int(plr_digits)
+    t.min_padded_m = int(min_padded_m)
     t.spin_limit = int(spin_limit)
     t.static_state = int(static_state)
     t.final_state = int(final_state)

@@ -60,7 +60,7 @@ class CascadePlan:
                  device="cuda", launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto",
                  input_stages=0, chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0,
                  state_bf16=0, fold_stages=0, spin_limit=0, static_state=0, final_state=0,
-                 plr_digits=0):
+                 plr_digits=0, min_padded_m=0):
         if not torch.cuda.is_available():
             raise RuntimeError("the fast-cascade library needs a ROCm GPU")
         B.load()
@@ -94,7 +94,7 @@ class CascadePlan:
             if isinstance(stage_kernel, str) else int(stage_kernel)
         self.tuning = B.make_tuning(mode, tile_rows, sk, input_stages, chain_blocks, pair_stages,
                                     pair_blocks, input_split, state_bf16, fold_stages, spin_limit,
-                                    static_state, final_state, plr_digits)
+                                    static_state, final_state, plr_digits, min_padded_m)
         nbytes = B.ssm_cascade_workspace_bytes(layout.descs, self.disc, self.compute,
                                                with_backward, ckpt_every, self.tuning)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -306,7 +306,7 @@ def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, devi
                       launch="auto", tile_rows=(0, 0, 0, 0), stage_kernel="auto", input_stages=0,
                       chain_blocks=0, pair_stages=0, pair_blocks=0, input_split=0, state_bf16=0,
                       fold_stages=0, disc=None, spin_limit=0, static_state=0, final_state=0,
-                      plr_digits=0):
+                      plr_digits=0, min_padded_m=0):
     """Builds the layout and plan of a ``workloads.Workload`` (discretization:
     the workload's, "given" or "trapezoid", unless ``disc`` names one)."""
     dims = [(ps.m, ps.p, ps.q) for ps in wl.sets]
@@ -320,7 +320,8 @@ def plan_for_workload(wl, compute="f32", with_backward=False, ckpt_every=0, devi
                        input_stages=input_stages, chain_blocks=chain_blocks,
                        pair_stages=pair_stages, pair_blocks=pair_blocks, input_split=input_split,
                        state_bf16=state_bf16, fold_stages=fold_stages, spin_limit=spin_limit,
-                       static_state=static_state, final_state=final_state, plr_digits=plr_digits)
+                       static_state=static_state, final_state=final_state, plr_digits=plr_digits,
+                       min_padded_m=min_padded_m)
 
 
 def pack_u(wl, dtype=torch.float32, device="cuda"):

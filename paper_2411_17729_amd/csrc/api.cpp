@@ -87,6 +87,7 @@ struct ssm_plan_s {
   int disc = 0;
   int with_backward = 0, ckpt_every = 1;
   int max_last = 0, max_mp = 32, max_N = 0;
+  int min_mp = 32;  // smallest padded state size (ssm_tuning.min_padded_m)
   // host copies
   std::vector<ssm_seq_desc> desc;
   std::vector<SeqDev> seqs;
@@ -304,7 +305,10 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
     if (seqs[i].N < 0) return fail(SSM_E_INVALID, "seq %d: automatic N not resolved", i);
   ssm_tuning tn{};
   if (tuning) tn = *tuning;
-  if (tn.reserved != 0) return fail(SSM_E_INVALID, "tuning.reserved must be 0");
+  if (tn.min_padded_m != 0 && tn.min_padded_m != 32 && tn.min_padded_m != 64 && tn.min_padded_m != 128 &&
+      tn.min_padded_m != 256)
+    return fail(SSM_E_INVALID, "min_padded_m = %d: supported 0, 32, 64, 128 or 256", tn.min_padded_m);
+  P.min_mp = tn.min_padded_m > 0 ? tn.min_padded_m : 32;
   if (tn.plr_digits < 0 || tn.plr_digits > 15)
     return fail(SSM_E_INVALID, "plr_digits = %d: supported 0 (off) or 1..15", tn.plr_digits);
   if (tn.plr_digits > 0) {
@@ -401,7 +405,7 @@ ssm_status build_plan(ssm_plan_s& P, const ssm_seq_desc* seqs, int32_t n_seq, ss
       key2op[key] = op;
       OpDev o{};
       o.m = d.m;
-      o.mp = pad_m(d.m);
+      o.mp = std::max(pad_m(d.m), P.min_mp);
       o.p = d.p;
       o.q = d.q;
       o.set = d.param_set;
@@ -1609,7 +1613,7 @@ void plan_backward(ssm_plan_s& P) {
     j.op_first = set_op_first[st];
     j.n_ops = (int)ops_of_set[st].size();
     j.m = std::max(0, P.set_m[st]);
-    j.mp = j.m ? pad_m(j.m) : 0;
+    j.mp = j.m ? std::max(pad_m(j.m), P.min_mp) : 0;
     j.p = std::max(0, P.set_p[st]);
     j.q = std::max(0, P.set_q[st]);
     j.dC = set_dc[st];
@@ -2203,7 +2207,7 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
           j.op_first = 0;
           j.n_ops = 0;
           j.m = sets[st].m;
-          j.mp = j.m ? pad_m(j.m) : 0;
+          j.mp = j.m ? std::max(pad_m(j.m), P->min_mp) : 0;
           j.p = sets[st].p;
           j.q = sets[st].q;
           j.dC = -1;

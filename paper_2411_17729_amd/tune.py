@@ -10,6 +10,9 @@ plan actually uses (a choice the plan ignores is not timed):
   pair_blocks   16-row blocks per workgroup segment of a stage pair
   fold_stages   stages folded into the output pass (automatic, none, 4, 5)
   state_bf16    BF16 state between passes (BF16 plans, when allowed)
+  min_padded_m  operators of m <= 64 padded to 128 (ragged BF16 batches with
+                larger classes too: every class then runs the fused passes),
+                timed with FP32 state and, when allowed, with BF16 state
   tile_rows     rows per tile of the tiled stage kernel (plans that use it)
 
 Every candidate's output on the tuning input is compared with the default
@@ -70,7 +73,7 @@ def signature(wl, compute, allow_bf16_state=False):
 
 def defaults():
     return {"launch": "auto", "input_stages": 0, "chain_blocks": 0, "pair_blocks": 0, "fold_stages": 0,
-            "state_bf16": 0, "tile_rows": (0, 0, 0, 0)}
+            "state_bf16": 0, "min_padded_m": 0, "tile_rows": (0, 0, 0, 0)}
 
 
 def knob_values(wl, compute, info, allow_bf16_state):
@@ -84,6 +87,9 @@ def knob_values(wl, compute, info, allow_bf16_state):
         vals["fold_stages"] = [0, -1, 4, 5]
         if allow_bf16_state:
             vals["state_bf16"] = [0, 1]
+        cls = _classes(wl)
+        if min(cls) <= 64 and max(cls) >= 128:
+            vals["min_padded_m"] = [0, 128]
     if info["stage_kernel"] == B.SSM_STAGE_TILED:
         rows = []
         for mp in _classes(wl):
@@ -144,18 +150,24 @@ def tune(wl, compute="bf16", reps=7, verbose=False, allow_bf16_state=False, tol=
     table = [dict(cur, ms=best_ms)]
     # the launch mode first; the other choices are those the plan of the
     # chosen mode uses
-    order = ["launch", "input_stages", "chain_blocks", "pair_blocks", "fold_stages", "state_bf16", "tile_rows"]
+    order = ["launch", "input_stages", "chain_blocks", "pair_blocks", "fold_stages", "state_bf16", "min_padded_m",
+             "tile_rows"]
     for knob in order:
         if knob != "launch":
             plan = _plan(wl, compute, cur)
             info = plan.info()
             plan.close()
         values = knob_values(wl, compute, info, allow_bf16_state).get(knob, [])
+        cands = []
         for v in values:
             if v == cur[knob] or (knob == "launch" and v == "auto"):
                 continue
             cand = dict(cur)
             cand[knob] = v
+            cands.append(cand)
+            if knob == "min_padded_m" and allow_bf16_state and not cur["state_bf16"]:
+                cands.append(dict(cand, state_bf16=1))  # the padding is what lets the state be BF16
+        for cand in cands:
             row = dict(cand)
             try:
                 plan = _plan(wl, compute, cand)
@@ -163,7 +175,7 @@ def tune(wl, compute="bf16", reps=7, verbose=False, allow_bf16_state=False, tol=
                 row["rejected"] = str(e)
                 table.append(row)
                 continue
-            if knob == "state_bf16" and plan.info()["state_dtype"] != B.SSM_BF16:
+            if cand["state_bf16"] and plan.info()["state_dtype"] != B.SSM_BF16:
                 plan.close()
                 row["rejected"] = "the plan keeps FP32 state"
                 table.append(row)

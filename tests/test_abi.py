@@ -131,9 +131,13 @@ def test_tuning_is_validated(lib):
         assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 0, 0, 0, C.byref(t)) == 0
     t = B.make_tuning(tile_rows=(0, 64, 0, 0))  # half of the default 128 for m <= 64
     assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) > 0
-    t = B.make_tuning()
-    t.reserved = 1
-    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
+    for bad in (1, 100, 512, -64):
+        t = B.make_tuning(min_padded_m=bad)
+        assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) == 0
+    # padding m = 64 to 128 doubles the state buffers of the 4096 rows
+    small = lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, None)
+    t = B.make_tuning(min_padded_m=128)
+    assert lib.ssm_cascade_workspace_bytes(arr, 1, 0, 1, 0, 0, C.byref(t)) >= small + 2 * 4096 * 64 * 4
     # final_state: 0 or 1, not with an explicitly persistent launch
     for bad in (B.make_tuning(final_state=2), B.make_tuning(final_state=-1),
                 B.make_tuning(final_state=1, launch=B.SSM_LAUNCH_PERSISTENT)):

@@ -139,6 +139,8 @@ def test_backward_ragged_classes():
     wl = W.Workload("ragged_small", sets, seqs)
     _compare(wl, "f32")
     _compare(wl, "f64")
+    # every operator padded to 256 (the padding is exact; gradients are cropped to m)
+    _compare(wl, "f32", min_padded_m=256)
 
 
 def test_backward_full_size_fp32():

@@ -290,15 +290,17 @@ def _ragged_mixed_lasts(seed, with_small_class):
     return W.Workload("ragged_mixed", sets, seqs)
 
 
-@pytest.mark.parametrize("state_bf16,small", [(0, True), (1, False)])
-def test_ragged_per_sequence_folds(state_bf16, small):
+@pytest.mark.parametrize("state_bf16,small,pad", [(0, True, 0), (1, False, 0), (1, True, 128)])
+def test_ragged_per_sequence_folds(state_bf16, small, pad):
     """Per-stage BF16 plan of a ragged batch: every sequence of the padded 128
     and 256 classes is paired up to its own output fold (depth and first stage
-    per sequence, folds grouped by kernel, depth and input buffer). Against
-    the oracle at the BF16 bound and against the plan without folds."""
+    per sequence, folds grouped by kernel, depth and input buffer). With m <= 64
+    padded to 128 every class is fused and the state is BF16. Against the
+    oracle at the BF16 bound and against the plan without folds."""
     from paper_2411_17729_amd import cascade as CC
     wl = _ragged_mixed_lasts(5, small)
-    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", state_bf16=state_bf16)
+    plan = CC.plan_for_workload(wl, compute="bf16", launch="per_stage", state_bf16=state_bf16,
+                                min_padded_m=pad)
     info = plan.info()
     assert info["fold_launches"] >= 3 and info["pair_launches"] >= 2, info
     assert info["state_dtype"] == (2 if state_bf16 else 1)
