@@ -215,3 +215,73 @@ def test_plr_two_sided_forms():
     assert used and ranks[1] == 1 and ranks[0] == 1  # level 1: lower and upper blocks of rank 1
     assert worst <= TOL["f32"]
 
+
+
+def test_plr_from_an_initial_state():
+    """apply_x0 on a plan with PLR stages: the free response enters before the
+    stages, so the PLR stages carry it like any other state."""
+    from paper_2411_17729_amd import cascade as CC
+    rng = np.random.default_rng(31)
+    sets, seqs, x0 = [], [], []
+    for i, (m, L) in enumerate([(256, 2000), (200, 1300), (128, 1700)]):
+        A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, 2)) / m, rng.standard_normal((2, m)) / m,
+                               np.zeros((2, 2))))
+        s_ = W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, 10, None)
+        s_.u = rng.standard_normal((L, 2))
+        seqs.append(s_)
+        x0.append(rng.standard_normal(m))
+    wl = W.Workload("plr_x0", sets, seqs)
+    plan = CC.plan_for_workload(wl, compute="f32", plr_digits=7, input_stages=-1, launch="per_stage")
+    assert plan.info()["plr_stages"] > 0
+    u = CC.pack_u(wl, dtype=torch.float32)
+    xt = torch.from_numpy(np.concatenate(x0)).float().cuda()
+    y = CC.unpack_y(wl, plan.apply(u, x0=xt))
+    torch.cuda.synchronize()
+    for i, (s_, x) in enumerate(zip(wl.seqs, x0)):
+        ps = wl.sets[s_.param_set]
+        Abar, Bbar = O.trapezoid(ps.A, ps.B, s_.delta)
+        ref, _ = O.recursion(Abar, Bbar, ps.C, ps.D, s_.u.astype(np.float32).astype(np.float64), x0=x)
+        e = parity_err(y[i], ref)
+        print("seq", i, f"{e:.3e}", flush=True)
+        assert e <= TOL["f32"], (i, e)
+
+
+def test_plr_with_the_final_state():
+    """A plan that keeps the final state (stream chunks) with PLR stages: y and
+    the last row's state against the oracle's recursion."""
+    from paper_2411_17729_amd import cascade as CC
+    wl = _batched(14, 256, 1500, 10, batch=2)
+    plan = CC.plan_for_workload(wl, compute="f32", plr_digits=7, input_stages=-1, final_state=1)
+    assert plan.info()["plr_stages"] > 0
+    u = CC.pack_u(wl, dtype=torch.float32)
+    y, xl = plan.apply_state(u)
+    torch.cuda.synchronize()
+    y = CC.unpack_y(wl, y)
+    xl = xl.double().cpu().numpy().reshape(len(wl.seqs), -1)
+    for i, s_ in enumerate(wl.seqs):
+        ps = wl.sets[s_.param_set]
+        Abar, Bbar = O.trapezoid(ps.A, ps.B, s_.delta)
+        ref, xs = O.recursion(Abar, Bbar, ps.C, ps.D, s_.u.astype(np.float32).astype(np.float64))
+        last = np.asarray(xs)[-1]  # the state after row L - 1
+        assert parity_err(y[i], ref) <= TOL["f32"]
+        assert np.linalg.norm(xl[i] - last) / np.linalg.norm(last) <= TOL["f32"]
+
+
+def test_plr_full_size_fp32_sampled():
+    """The bench workload (16 x L = 16384, m = 256, p = q = 8, N = 13) in FP32
+    with PLR stages at d = 7, two sequences against the oracle."""
+    from paper_2411_17729_amd import cascade as CC
+    wl = W.batched(seed=0)
+    plan = CC.plan_for_workload(wl, compute="f32", plr_digits=7)
+    assert plan.info()["plr_stages"] > 0
+    y = CC.unpack_y(wl, plan.apply(CC.pack_u(wl, dtype=torch.float32)))
+    torch.cuda.synchronize()
+    for i in (0, 15):
+        s_ = wl.seqs[i]
+        ps = wl.sets[s_.param_set]
+        Abar, Bbar = O.trapezoid(ps.A, ps.B, s_.delta)
+        ref, _ = O.recursion(Abar, Bbar, ps.C, ps.D, s_.u.astype(np.float32).astype(np.float64))
+        e = parity_err(y[i], ref)
+        print("seq", i, f"{e:.3e}", flush=True)
+        assert e <= TOL["f32"], (i, e)
