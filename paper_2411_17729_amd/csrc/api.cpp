@@ -1294,8 +1294,37 @@ static ssm_status backward_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       if (e != hipSuccess) return hip_fail(e, "initial state launch");
     }
     prm.flags = 0;
+    // the stage inputs x^(1) .. x^(J) straight from u by the resident input
+    // pass (x^(j) = K_j [u_l; ...; u_{l-2^j+1}], K_j the first 2^j p columns
+    // of the operator's K): one write of the state each instead of a stage's
+    // read and write. J: at most every sequence's folded input stages and its
+    // last stage (so that the stages from J on still leave its final state),
+    // 2^J p <= mp; none with x_{-1}.
+    int J = 0;
+    if (!x0 && P.stage_kernel != SSM_STAGE_TILED && res_supported(mp, P.compute) && P.class_range_count[cl] > 0) {
+      J = 1 << 30;
+      for (const SeqDev& s : P.seqs) {
+        if (P.ops[s.op].mp != mp) continue;
+        int j = std::min(s.kry, s.last);
+        while (j > 0 && (s.p << j) > mp) --j;
+        J = std::min(J, j);
+      }
+      if (J == (1 << 30)) J = 0;
+    }
+    if (J > 0) {
+      const ResRange* rg = reinterpret_cast<const ResRange*>(meta + P.m_ranges) + P.class_range_start[cl];
+      for (int k = 1; k <= J; ++k) {
+        prm.kry_override = k;
+        prm.xout = loc(k);
+        TimedLaunch tl(P, stream, 0);
+        e = launch_krylov_res(mp, P.compute, prm, rg, P.class_range_count[cl], stream);
+        if (e != hipSuccess) return hip_fail(e, "input pass launch");
+        tl.done();
+      }
+      prm.kry_override = 0;
+    }
     prm.xfinal = xfinal;
-    for (int k = 0; k <= ml; ++k) {
+    for (int k = J; k <= ml; ++k) {
       prm.k = k;
       prm.xin = loc(k);
       prm.xout = loc(k + 1);
@@ -1373,12 +1402,23 @@ static ssm_status backward_impl(ssm_plan plan, const void* u, ssm_dtype u_dtype,
       prm.flags = 0;
       prm.xin_first = nullptr;
       for (int k = kb; k < ke; ++k) {
-        prm.k = k;
-        prm.xin = loc(k);
-        prm.xout = loc(k + 1);
-        prm.n_tiles = P.class_active[cl][k];
         TimedLaunch tl(P, stream, 0);
-        e = launch_stage_any(P, cl, prm, stream);
+        if (k + 1 <= J) {  // as in the forward: x^(k+1) by the input pass (the same bits)
+          StageParams kp = prm;  // (prm.src may hold dy from an adjoint segment above)
+          kp.src = u;
+          kp.src_dtype = (int)u_dtype;
+          kp.kry_override = k + 1;
+          kp.xout = loc(k + 1);
+          e = launch_krylov_res(mp, P.compute, kp,
+                                reinterpret_cast<const ResRange*>(meta + P.m_ranges) + P.class_range_start[cl],
+                                P.class_range_count[cl], stream);
+        } else {
+          prm.k = k;
+          prm.xin = loc(k);
+          prm.xout = loc(k + 1);
+          prm.n_tiles = P.class_active[cl][k];
+          e = launch_stage_any(P, cl, prm, stream);
+        }
         if (e != hipSuccess) return hip_fail(e, "recompute stage launch");
         tl.done();
       }

@@ -106,7 +106,7 @@ struct StageParams {
   int32_t flags;
   int32_t n_tiles;
   int32_t skip_kry;  // stages below a sequence's kry were done by the input pass
-  int32_t reserved;
+  int32_t kry_override;  // resident input pass: j > 0 writes x^(j) (j <= the sequence's kry) to xout
 };
 
 // A range of rows of one sequence for the resident-power stage kernel.

@@ -252,24 +252,32 @@ __device__ __forceinline__ void krylov_range(const StageParams& prm, const ResRa
 
   const SeqDev sq = prm.seqs[rg.seq];
   const OpDev o = prm.ops[sq.op];
-  if (sq.kry <= 0) return;
+  // x^(jj): the sequence's own input stages, or (kry_override) an earlier
+  // x^(j) from the first 2^j p columns of K (K_{i+1} = [K_i | P_i K_i]),
+  // written to xout and never forming y
+  const int jo = prm.kry_override;
+  const int jj = jo > 0 ? jo : sq.kry;
+  if (jj <= 0 || jj > sq.kry || (jo > 0 && ((1 << jj) * sq.p) > MP)) return;
   const int n0 = split * NR;
   const int64_t L = sq.L;
   const int p = sq.p;
-  const int kdim = (1 << sq.kry) * p;
-  const bool final_ = sq.kry == sq.last + 1;
+  const int kdim = (1 << jj) * p;
+  const bool final_ = jo <= 0 && sq.kry == sq.last + 1;
   const bool epi = (prm.flags & SF_EPILOGUE) && final_ && C::NS == 1;
   {
-    const Op* K = reinterpret_cast<const Op*>(prm.P) + o.kc + (int64_t)n0 * MP;
+    // K rows (state entries n0 ..) have stride kst >= MP; columns from kdim on
+    // meet only zero window entries
+    const Op* K = reinterpret_cast<const Op*>(prm.P) + o.kc + (int64_t)n0 * o.kst;
     constexpr int VO = 16 / (int)sizeof(Op);
     for (int e = threadIdx.x; e < NR * (MP / VO); e += 512) {
       const int r = e / (MP / VO), c = (e % (MP / VO)) * VO;
       *reinterpret_cast<uint4*>(Ks + r * SP + c) =
-          *reinterpret_cast<const uint4*>(K + (int64_t)r * MP + c);
+          *reinterpret_cast<const uint4*>(K + (int64_t)r * o.kst + c);
     }
     __syncthreads();
   }
-  X* xo = reinterpret_cast<X*>((sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off;
+  X* xo = reinterpret_cast<X*>(jo > 0 ? prm.xout
+                                      : (sq.kry & 1) ? prm.xout : const_cast<void*>(prm.xin)) + sq.x_off;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int j = lane & 15, g = lane >> 4;

@@ -108,6 +108,14 @@ def test_backward_checkpoint_interval(ckpt):
     _compare(wl, "f64", ckpt_every=ckpt)
 
 
+@pytest.mark.parametrize("compute,ckpt", [("f32", 1), ("f32", 3), ("bf16", 1), ("bf16", 4)])
+def test_backward_input_pass_stage_inputs(compute, ckpt):
+    # m = 128, p = 4: the stage inputs x^(1) .. x^(5) come from the resident
+    # input pass (also when a checkpoint segment recomputes them)
+    wl = W.backward(seed=6, batch=2, m=128, L=1500, N=10, p=4, q=4)
+    _compare(wl, compute, ckpt_every=ckpt)
+
+
 def test_backward_checkpointing_is_exact():
     # recomputing stage inputs from checkpoints reproduces them bit for bit
     from paper_2411_17729_amd import cascade as CC
