@@ -302,6 +302,11 @@ typedef struct {
                                 per row 2 (16 mp + sum over the off-diagonal blocks of
                                 2 r s) with the ranks found at prepare */
   double plr_dense_flops;    /* the same rows and stages as dense products, 2 mp^2 per row */
+  int32_t lower_ops;         /* operators whose Abar (so every power) is lower triangular, as
+                                prepare found on the GPU; the FP32 chain stage kernel skips the
+                                zero blocks of their powers (stage_flops still counts the dense
+                                2 m^2 per row) */
+  int32_t lower_reserved;
 } ssm_plan_info;
 
 typedef struct ssm_plan_s* ssm_plan;

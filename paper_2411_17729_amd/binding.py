@@ -72,7 +72,7 @@ class ssm_plan_info(C.Structure):
         ("pair_flops", C.c_double), ("state_dtype", C.c_int32), ("fold_stages", C.c_int32),
         ("fold_launches", C.c_int64), ("fold_bytes", C.c_double), ("fold_flops", C.c_double),
         ("plr_stages", C.c_int32), ("plr_reserved", C.c_int32), ("plr_flops", C.c_double),
-        ("plr_dense_flops", C.c_double),
+        ("plr_dense_flops", C.c_double), ("lower_ops", C.c_int32), ("lower_reserved", C.c_int32),
     ]
 
 

@@ -865,6 +865,8 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                           P->job_dims[g].second, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "squaring GEMM launch"));
   }
+  e = launch_mark_lower(reinterpret_cast<OpDev*>(meta + P->m_ops), P->n_ops, pw, stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "triangular mark launch"));
   if (P->max_kry > 0 || any_cp) {
     e = launch_pack_krylov(ops_d, P->n_ops, P->at<double>(P->r_kw), P->ws + P->r_pc.off, P->compute,
                            P->max_mp, stream);
@@ -900,10 +902,15 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   int status_h[4] = {0, 0, 0, 0};
   e = hipMemcpyAsync(status_h, status_d, sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return bail(hip_fail(e, "status read"));
+  // the operator table as the device left it (the lower-triangular marks)
+  std::vector<OpDev> ops_back(P->ops.size());
+  e = hipMemcpyAsync(ops_back.data(), ops_d, sizeof(OpDev) * ops_back.size(), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "operator table read"));
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return bail(hip_fail(e, "prepare synchronization"));
   if (status_h[0] != 0)
     return bail(fail(SSM_E_NUMERIC, "I - delta/2 A is singular to working precision"));
+  for (size_t i = 0; i < P->ops.size(); ++i) P->ops[i].lower = ops_back[i].lower;
   if (!P->plr_jobs.empty()) plr_select(*P);
   *out = P;
   return SSM_OK;
@@ -1597,8 +1604,11 @@ ssm_status ssm_cascade_plan_info(ssm_plan plan, ssm_plan_info* info) {
   info->fold_stages = 0;
   for (int c = 0; c < 4; ++c) info->fold_stages = std::max(info->fold_stages, plan->fold_s[c]);
   for (int f : plan->seq_fold_s) info->fold_stages = std::max(info->fold_stages, f);
+  info->lower_ops = 0;
+  for (const OpDev& o : plan->ops) info->lower_ops += o.lower != 0;
   info->plr_stages = plan->plr_stages;
   info->plr_reserved = 0;
+  info->lower_reserved = 0;
   info->plr_flops = plan->plr_flops;
   info->plr_dense_flops = plan->plr_dense_flops;
   return SSM_OK;

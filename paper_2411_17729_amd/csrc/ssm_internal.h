@@ -72,6 +72,10 @@ struct OpDev {
   // ping-pong), and the squarings zsq chosen from its norm; zx = -1 if none
   int64_t zx;
   int32_t zn, zsq;
+  // 1 when Abar, and so every power, is lower triangular (set on the device at
+  // prepare from the FP64 Abar): the stage contractions then skip the blocks
+  // above the diagonal (below it for the transposed powers of the adjoint)
+  int32_t lower;
 };
 
 // A row tile of one sequence for the stage kernel.
@@ -308,6 +312,7 @@ hipError_t launch_gauss_jordan(const OpDev* ops, int n_ops, double* aug, double*
 
 // Lower-triangular I - h A (the HiPPO matrices of §4 are lower triangular):
 // tri[op] = 1 if A has no entry above the diagonal, scale[op] = max |I - h A|.
+hipError_t launch_mark_lower(OpDev* ops, int n_ops, const double* pw, hipStream_t s);
 hipError_t launch_tri_check(const OpDev* ops, int n_ops, const OpSrc* src, int32_t* tri, double* scale,
                             hipStream_t s);
 // Inverses of the 32 x 32 diagonal blocks of the lower-triangular M (left

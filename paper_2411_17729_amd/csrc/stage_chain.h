@@ -57,6 +57,7 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   if (k > sq.last) return;
   if (prm.skip_kry && k < sq.kry) return;
   const bool adj = prm.adjoint != 0;
+  const bool lower = o.lower != 0;  // skip the zero blocks of a lower-triangular power (FP32)
   const bool first = adj ? k == sq.last : k == 0;
   const bool final_ = adj ? k == 0 : k == sq.last;
   const bool epi = TAIL && (prm.flags & SF_EPILOGUE) && final_;
@@ -226,6 +227,10 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
         for (int a = 0; a < MP / 16; ++a)
 #pragma unroll
           for (int nb = n0; nb < n0 + G; ++nb) {
+            // a lower-triangular P_k has no entries from input piece ri above
+            // output piece ro (P_k^T of the adjoint none below)
+            const int ro = nb + nb0, ri = (a + nb0) & (NV - 1);
+            if (lower && (adj ? ri < ro : ri > ro)) continue;
             const f32x4 av = *reinterpret_cast<const f32x4*>(Ps + lbase + nb * 16 * SP + 16 * a);
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt)

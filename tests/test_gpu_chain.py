@@ -190,3 +190,21 @@ def test_resident_persistent_graph_replays():
             assert torch.equal(y, ref), rep
     finally:
         CC.CascadePlan.graph_destroy(g)
+
+
+def test_lower_triangular_powers_are_marked():
+    """Prepare marks operators whose Abar is lower triangular (every HiPPO
+    operator; none of a dense random one); the FP32 chain kernel then skips the
+    zero blocks of their powers, with the same results as the oracle."""
+    from paper_2411_17729_amd import cascade as CC
+    wl = W.batched(seed=2, batch=2, m=128, L=3000, N=10, p=4, q=4)
+    plan = CC.plan_for_workload(wl, compute="f32", launch="per_stage")
+    info = plan.info()
+    assert info["lower_ops"] == info["n_ops"] == 2
+    y = CC.unpack_y(wl, plan.apply(CC.pack_u(wl, dtype=torch.float32)))
+    torch.cuda.synchronize()
+    ref = _oracle(wl)
+    for i in range(len(wl.seqs)):
+        assert parity_err(y[i], ref[i]) <= 1e-5, i
+    dense = W.random_small(seed=1, m=64, p=2, q=2, L=500, N=7, n_seq=1, contraction=0.9)
+    assert CC.plan_for_workload(dense, compute="f32").info()["lower_ops"] == 0
