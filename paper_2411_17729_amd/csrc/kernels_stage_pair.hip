@@ -101,8 +101,18 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   // covers entries 32 s .. 32 s + 31 with operand slot 8 g + 4 h + e holding
   // entry 32 s + 16 h + 4 g + e, the assignment of the chain kernel, so that
   // every output sees the same products in the same MFMA steps as there.
+  // The share of wave w is share wp = w for the first half of the waves and
+  // NW - 1 - (w - NW / 2) for the second, so that the two waves of a SIMD (w
+  // and w + NW / 2) hold one low and one high share: with a lower-triangular
+  // P (every power of a lower-triangular Abar) a share needs the contraction
+  // steps up to its last entry only, and the two waves of a SIMD then run
+  // about the same number of steps.
+  const int wp = wave < C::NW / 2 ? wave : C::NW - 1 - (wave - C::NW / 2);
+  // (BF16 state only: with FP32 state the extra branches cost registers the
+  // variant does not have)
+  const int nsteps = XB && o.lower ? (wp * C::DW + C::DW - 1) / 32 + 1 : KS;  // steps s < nsteps
   auto ent = [&](int t, int rr) {
-    return XB ? wave * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3) : wave * C::DW + 16 * t + rr;
+    return XB ? wp * C::DW + 4 * NT * (rr >> 2) + 4 * t + (rr & 3) : wp * C::DW + 16 * t + rr;
   };
   bf16x8 pa[2][NT][KS];
   // tail: contraction step cps (columns 32 cps .. + 31) of C P_{k+1}, row r:
@@ -333,6 +343,7 @@ __global__ __launch_bounds__(512, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   auto contract_refill = [&](const bf16x8(&a)[NT][KS], bf16x8(&b)[KS], f32x4(&acc)[NT], const __bf16* src) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
+      if (s >= nsteps) break;  // the share's entries see no input past its own
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][s], b[s], acc[t], 0, 0, 0);
