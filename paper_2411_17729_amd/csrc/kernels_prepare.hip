@@ -299,13 +299,17 @@ __global__ __launch_bounds__(1024) void k_tri_check(const OpDev* ops, const OpSr
 // ops[i].lower = 1 when the FP64 Abar of operator i (its power k = 0) has no
 // nonzero entry above the diagonal; then every power Abar^(2^k) is lower
 // triangular too.
-__global__ __launch_bounds__(256) void k_mark_lower(OpDev* ops, const double* pw) {
+__global__ __launch_bounds__(1024) void k_mark_lower(OpDev* ops, const double* pw) {
   const OpDev o = ops[blockIdx.x];
   const double* A = pw + o.pw;
+  const int mp = o.mp, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave w reads rows w, w + 16, ... whole (coalesced, no data-dependent
+  // branch, so the loads of several rows are in flight together)
   int upper = 0;
-  for (int e = threadIdx.x; e < o.mp * o.mp; e += 256) {
-    const int r = e / o.mp, c = e - r * o.mp;
-    if (c > r && A[e] != 0.0) upper = 1;
+#pragma unroll 4
+  for (int r = wave; r < mp; r += 16) {
+    const double* row = A + (int64_t)r * mp;
+    for (int c = lane; c < mp; c += 64) upper |= (c > r) & (row[c] != 0.0);
   }
   upper = __syncthreads_or(upper);
   if (threadIdx.x == 0) ops[blockIdx.x].lower = upper ? 0 : 1;
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(256) void k_mark_lower(OpDev* ops, const double* pw
 
 hipError_t launch_mark_lower(OpDev* ops, int n_ops, const double* pw, hipStream_t s) {
   if (n_ops <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_lower, dim3(n_ops), dim3(256), 0, s, ops, pw);
+  hipLaunchKernelGGL(k_mark_lower, dim3(n_ops), dim3(1024), 0, s, ops, pw);
   return hipGetLastError();
 }
 
