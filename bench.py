@@ -389,13 +389,16 @@ def main():
                                      "roofline": roofline(plan_s, kern_s, "bf16", K)}
             plan_s.close()
         other = "f32" if args.dtype == "bf16" else "bf16"
-        plan_o = CC.plan_for_workload(wl, compute=other)
+        tn_o = tune.best_tuning(wl, compute=other)  # the autotuner's choice, cached
+        plan_o = CC.plan_for_workload(wl, compute=other, **tn_o)
         y_o, ms_o, kern_o = run(plan_o, "apply", K, Wm, timing_kind=dominant_kernel(plan_o.info())[1],
                                 graph=True)
         ys[other] = CC.unpack_y(wl, y_o)
         out[f"cascade_{other}"] = {"value": round(total_steps / (ms_o * 1e-3), 1),
                                     "ms_per_step": round(ms_o, 4),
-                                    "roofline": roofline(plan_o, kern_o, other, K)}
+                                    "roofline": roofline(plan_o, kern_o, other, K),
+                                    "tuning": {k: (list(v) if isinstance(v, tuple) else v)
+                                               for k, v in tn_o.items()}}
         plan_r = plan_o if other == "f32" else plan
         rsteps = max(2, K // 10)
         y_r, ms_r, _ = run(plan_r, "recursion", rsteps, 1)

@@ -93,8 +93,9 @@ hipError_t launch_stage_any(const ssm_plan_s& P, int c, StageParams prm, hipStre
     const ChainUnit* un = reinterpret_cast<const ChainUnit*>(P.ws + P.r_meta.off + P.m_chain) +
                           P.chain_start[c][k];
     const bool tail = prm.adjoint ? k == 0 : P.class_final[c][k] > 0;
+    const int tri = P.compute == DT_F32 && P.class_lower[c] ? (prm.adjoint ? 2 : 1) : 0;
     if (!(tail && res_splits_rows(mp, P.compute)))
-      return launch_stage_chain(mp, P.compute, prm, un, P.chain_count[c][k], tail, stream);
+      return launch_stage_chain(mp, P.compute, prm, un, P.chain_count[c][k], tail, tri, stream);
   }
   const bool final_here = (prm.flags & SF_EPILOGUE) &&
                           (prm.adjoint ? k == 0 : (k < (int)P.class_final[c].size() &&
@@ -911,6 +912,11 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
   if (status_h[0] != 0)
     return bail(fail(SSM_E_NUMERIC, "I - delta/2 A is singular to working precision"));
   for (size_t i = 0; i < P->ops.size(); ++i) P->ops[i].lower = ops_back[i].lower;
+  for (int c = 0; c < 4; ++c) {
+    P->class_lower[c] = 1;
+    for (const OpDev& o : P->ops)
+      if (o.mp == kClassMp[c] && !o.lower) P->class_lower[c] = 0;
+  }
   if (!P->plr_jobs.empty()) plr_select(*P);
   *out = P;
   return SSM_OK;

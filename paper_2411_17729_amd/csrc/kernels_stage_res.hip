@@ -11,15 +11,17 @@
 // from HBM into registers (B operand), and every lane's accumulators hold 4
 // consecutive state entries of one time row: the unshifted rows are read and
 // the result rows written as 16-byte vectors. When P_k does not fit (FP32,
-// m = 256) the state rows are split between two workgroups (blockIdx.y).
+// m = 256) the state rows are split between two workgroups on one XCD (split_item).
 #include "stage_res.h"
 
 namespace ssmc {
 
 template <int MP, int CT>
-__global__ __launch_bounds__(512, 1) void k_stage_res(StageParams prm, const ResRange* ranges) {
+__global__ __launch_bounds__(512, 1) void k_stage_res(StageParams prm, const ResRange* ranges, int n_ranges) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_res[];
-  res_range<MP, CT>(prm, ranges[blockIdx.x], blockIdx.y, smem_res);
+  int r, half;
+  if (!split_item<ResCfg<MP, CT>::NS>(n_ranges, r, half)) return;
+  res_range<MP, CT>(prm, ranges[r], half, smem_res);
 }
 
 template <int MP, int CT>
@@ -31,8 +33,8 @@ static hipError_t launch_res_t(const StageParams& prm, const ResRange* ranges, i
     hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage_res<MP, CT>), (size_t)((int)C::LDS));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_stage_res<MP, CT>), dim3(n_ranges, C::NS), dim3(512), C::LDS, s, prm,
-                     ranges);
+  hipLaunchKernelGGL((k_stage_res<MP, CT>), dim3(split_grid(n_ranges, C::NS)), dim3(512), C::LDS, s, prm,
+                     ranges, n_ranges);
   return hipGetLastError();
 }
 
@@ -70,9 +72,11 @@ hipError_t launch_stage_res(int mp, int ct, const StageParams& prm, const ResRan
 // with K_j resident in LDS like P_k above and w_l gathered from u.
 // ---------------------------------------------------------------------------
 template <int MP, int CT>
-__global__ __launch_bounds__(512, 1) void k_krylov_res(StageParams prm, const ResRange* ranges) {
+__global__ __launch_bounds__(512, 1) void k_krylov_res(StageParams prm, const ResRange* ranges, int n_ranges) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_res[];
-  krylov_range<MP, CT>(prm, ranges[blockIdx.x], blockIdx.y, smem_res);
+  int r, half;
+  if (!split_item<ResCfg<MP, CT>::NS>(n_ranges, r, half)) return;
+  krylov_range<MP, CT>(prm, ranges[r], half, smem_res);
 }
 
 template <int MP, int CT>
@@ -84,8 +88,8 @@ static hipError_t launch_kry_t(const StageParams& prm, const ResRange* ranges, i
     hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_krylov_res<MP, CT>), (size_t)((int)C::LDS));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_krylov_res<MP, CT>), dim3(n_ranges, C::NS), dim3(512), C::LDS, s, prm,
-                     ranges);
+  hipLaunchKernelGGL((k_krylov_res<MP, CT>), dim3(split_grid(n_ranges, C::NS)), dim3(512), C::LDS, s, prm,
+                     ranges, n_ranges);
   return hipGetLastError();
 }
 

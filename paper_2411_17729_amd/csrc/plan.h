@@ -191,6 +191,9 @@ struct ssm_plan_s {
   std::vector<PlrUnit> plr_units;
   int plr_start[4] = {0, 0, 0, 0}, plr_count[4] = {0, 0, 0, 0};
   std::vector<int> plr_ok[4], plr_use[4];
+  // (after prepare) every operator of class c has lower-triangular powers, so
+  // the FP32 chain stages of the class leave out the zero blocks
+  int class_lower[4] = {0, 0, 0, 0};
   std::vector<int32_t> plr_ranks_host;
   int plr_max_s = 0, plr_stages = 0;
   double plr_flops = 0, plr_dense_flops = 0;

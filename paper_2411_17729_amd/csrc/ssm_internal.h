@@ -359,8 +359,11 @@ hipError_t launch_input_split(int mp, int ct, int p, int kdim, bool xb, const St
 bool chain_supported(int mp, int ct);
 // tail: some sequence of the launch has its last stage here (the forward
 // epilogue or the final-state copy may be due); false selects the lean variant.
+// tri (FP32 operands; ignored for BF16): 1 when every operator of the launch
+// has lower-triangular powers, 2 for the adjoint of such a launch, 0 otherwise
+// (a launch with tri != 0 over a power that is not triangular is wrong).
 hipError_t launch_stage_chain(int mp, int ct, const StageParams& prm, const ChainUnit* units,
-                              int n_units, bool tail, hipStream_t s);
+                              int n_units, bool tail, int tri, hipStream_t s);
 // Stages prm.k and prm.k + 1 of the forward cascade in one pass (2^k >= 16):
 // BF16 at padded m of 128 and 256. Lean: both stages are lean for every
 // sequence of the units, prm.xin and prm.xout differ. tail: k + 1 is the last

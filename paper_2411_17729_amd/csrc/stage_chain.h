@@ -31,15 +31,24 @@ namespace ssmc {
 // (more loads in flight per wave for small state sizes); the unit covers
 // segments seg0 .. seg0 + 8 S - 1, wave w taking seg0 + w S .. seg0 + w S + S - 1.
 // When the power does not fit in LDS (FP32, m = 256) two workgroups share a
-// unit, each holding half of P_k's rows (split = 0, 1) and producing half of
-// every output row; both load whole input rows, which the next block needs
-// as its shifted operand. The split form has no output epilogue. To keep
-// register indices static, a split workgroup holds the row's 16-entry pieces
-// rotated by its first output piece nb0 (register piece i is row piece
-// i + nb0 mod 16, its own pieces first), and its LDS copy of P_k has the
-// columns rotated the same way, so MFMA step a still pairs register piece a
-// with the matching columns.
-template <int MP, int CT, bool TAIL, int S = 1>
+// unit, each holding half of P_k's rows and producing half of every output
+// row: half h the 16-entry pieces 2 e + h, e < 8. Both load whole input rows,
+// which the next block needs as its shifted operand. The split form has no
+// output epilogue. To keep register indices static, a split workgroup holds
+// its own pieces first: register piece i is row piece 2 (i mod 8) + h for
+// i < 8 and 2 (i mod 8) + 1 - h after, and its LDS copy of P_k has the columns
+// permuted the same way, so MFMA step a still pairs register piece a with the
+// matching columns.
+//
+// TRI (FP32): 1 when every power of the launch is lower triangular (the
+// adjoint's P_k^T upper triangular: TRI 2), and the contraction leaves out the
+// 16 x 16 blocks that are zero; the host chooses it, so the unrolled loop has
+// no branches. Output piece o needs input pieces up to o (from o for the
+// adjoint); with the interleaved halves both halves take register pieces a
+// with a mod 8 <= e for their e-th own piece (>= e for the adjoint), which
+// includes one zero block per own piece for one of the halves but keeps a
+// single pattern for both, and splits the 136 nonzero blocks 72 / 72.
+template <int MP, int CT, bool TAIL, int S = 1, int TRI = 0>
 __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUnit un,
                                            unsigned char* smem_chain, int split = 0) {
   using C = ResCfg<MP, CT>;
@@ -48,7 +57,8 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   using Op = typename C::Op;
   constexpr int NB = C::NB, SP = C::SP;  // NB: output pieces of 16 entries per workgroup
   constexpr int NV = MP / 16;            // pieces of a whole row
-  const int nb0 = split * NB;            // first output piece of this workgroup
+  static_assert(TRI == 0 || CT != DT_BF16, "the triangular skip is for FP32 operands");
+  const int half = C::NS > 1 ? split : 0;
   Op* Ps = reinterpret_cast<Op*>(smem_chain);
 
   const SeqDev sq = prm.seqs[un.seq];
@@ -57,7 +67,6 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   if (k > sq.last) return;
   if (prm.skip_kry && k < sq.kry) return;
   const bool adj = prm.adjoint != 0;
-  const bool lower = o.lower != 0;  // skip the zero blocks of a lower-triangular power (FP32)
   const bool first = adj ? k == sq.last : k == 0;
   const bool final_ = adj ? k == 0 : k == sq.last;
   const bool epi = TAIL && (prm.flags & SF_EPILOGUE) && final_;
@@ -126,9 +135,9 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
                : 0x80000000u;
   };
   // stage input of this lane's row of a block, accumulator layout
-  // byte offset of register piece i within a row (rotated for a split)
+  // byte offset of register piece i within a row (interleaved for a split)
   auto piece = [&](int i) -> uint32_t {
-    return (uint32_t)(C::NS > 1 ? ((i + nb0) & (NV - 1)) : i) * 64u;
+    return (uint32_t)(C::NS > 1 ? (((i & 7) << 1) | (half ^ (i >> 3))) : i) * 64u;
   };
   auto load_block = [&](uint32_t off, f32x4(&v)[NV]) {
 #pragma unroll
@@ -175,7 +184,7 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   // sets swap roles without copies.
   constexpr int G = NB < 4 ? NB : 4;
   f32x4 x[S][NV];
-  auto body = [&](const int q, const PV(&pv)[NPV], PV(&npv)[NPV]) {
+  auto body = [&](const int q, PV(&pv)[NPV], PV(&npv)[NPV]) {
     const uint32_t off = block_off(q, 0, 0, nflat);
     const uint32_t offn = block_off(q, step, f0[q], f1[q]);  // nothing past the segment
     f32x4 ya = f32x4{0.f, 0.f, 0.f, 0.f};  // outputs of a TAIL block with at most 16 of them
@@ -191,13 +200,16 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
         }
       }
     }
-    pack(x[q], adj ? fi[q] > 0 : fi[q] + 1 < ni, npv);  // partner of the next block, if any
-    if constexpr (C::NS > 1) {  // the other workgroup's pieces: only the next operand needs them
+    if constexpr (C::NS > 1) {
+      // own pieces of this block's input; its other pieces are in npv already
+      // (loaded there at the end of the previous block)
+      const bool keep = adj ? fi[q] > 0 : fi[q] + 1 < ni;
 #pragma unroll
-      for (int nb = NB; nb < NV; ++nb)
-        x[q][nb] = __builtin_bit_cast(
-            f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + piece(nb), 0, 0));
+      for (int nb = 0; nb < NB; ++nb) npv[nb] = keep ? x[q][nb] : f32x4{0.f, 0.f, 0.f, 0.f};
+    } else {
+      pack(x[q], adj ? fi[q] > 0 : fi[q] + 1 < ni, npv);  // partner of the next block, if any
     }
+    if constexpr (CT != DT_BF16) __builtin_amdgcn_sched_barrier(0);
     // the LDS operand offset is passed through an empty asm so that the
     // compiler re-reads the power fragments each block instead of hoisting
     // them out of the loop into registers
@@ -223,19 +235,34 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
                 __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[c & 1][e], pv[c], x[q][n0 + e], 0, 0, 0);
         }
       } else {
+        // a lower-triangular P_k has no entries from input piece ri above
+        // output piece ro (P_k^T of the adjoint none below); the test folds
+        // to a constant once the loops are unrolled
+        auto on = [&](int a, int nb) {
+          const int ai = C::NS > 1 ? (a & 7) : a;
+          return TRI == 0 || (TRI == 1 ? ai <= nb : ai >= nb);
+        };
+        // power fragments of step a + 1 read while step a is contracted; the
+        // scheduling fence keeps the reads from running further ahead
+        f32x4 fr[2][G];
+        auto frag = [&](int a, f32x4(&f)[G]) {
 #pragma unroll
-        for (int a = 0; a < MP / 16; ++a)
+          for (int e = 0; e < G; ++e)
+            if (on(a, n0 + e)) f[e] = *reinterpret_cast<const f32x4*>(Ps + lbase + (n0 + e) * 16 * SP + 16 * a);
+        };
+        frag(0, fr[0]);
 #pragma unroll
-          for (int nb = n0; nb < n0 + G; ++nb) {
-            // a lower-triangular P_k has no entries from input piece ri above
-            // output piece ro (P_k^T of the adjoint none below)
-            const int ro = nb + nb0, ri = (a + nb0) & (NV - 1);
-            if (lower && (adj ? ri < ro : ri > ro)) continue;
-            const f32x4 av = *reinterpret_cast<const f32x4*>(Ps + lbase + nb * 16 * SP + 16 * a);
+        for (int a = 0; a < MP / 16; ++a) {
+          if (a + 1 < MP / 16) frag(a + 1, fr[(a + 1) & 1]);
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt)
-              x[q][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt], pv[a][tt], x[q][nb], 0, 0, 0);
-          }
+          for (int e = 0; e < G; ++e)
+            if (on(a, n0 + e))
+#pragma unroll
+              for (int tt = 0; tt < 4; ++tt)
+                x[q][n0 + e] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(fr[a & 1][e][tt], pv[a][tt], x[q][n0 + e], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
 #pragma unroll
       for (int nb = n0; nb < n0 + G; ++nb) {
@@ -252,6 +279,21 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
           x[q][nb] = __builtin_bit_cast(
               f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offn + piece(nb), 0, 0));
       }
+      // (FP32: the loads stay behind this group's contractions, as the
+      // registers they fill are only free after them)
+      if constexpr (CT != DT_BF16) __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (C::NS > 1) {
+      // the next block's pieces of the other workgroup are only its input,
+      // the shifted operand two blocks on: they go straight into this block's
+      // operand registers, free now (zero, through an out-of-range offset,
+      // when that block has no partner)
+      const int fa = fi[q] + step, fn = fa == ni ? 0 : (fa < 0 ? ni - 1 : fa);
+      const bool keepn = adj ? fn > 0 : fn + 1 < ni;
+      const uint32_t offk = offn | (keepn ? 0u : 0x80000000u);
+#pragma unroll
+      for (int nb = NB; nb < NV; ++nb)
+        pv[nb] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rin, offk + piece(nb), 0, 0));
     }
     if constexpr (TAIL) {
       // y_l = C x_l + D u_l (forward) or du_l = Bbar^T g_l + D^T dy_l (adjoint)
@@ -287,14 +329,18 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     load_block(partner ? block_off(q, -step, 0, nflat) : 0x80000000u, part[q]);
     load_block(block_off(q, 0, f0[q], f1[q]), x[q]);
   }
-  // rows nb0 16 .. of P_k (or P_k^T) into LDS, contraction columns permuted for BF16
+  // this workgroup's rows of P_k (or P_k^T) into LDS (for a split, row
+  // piece e is P's piece 2 e + half), contraction columns permuted for BF16
+  // and for a split
   {
-    const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP +
-                  (int64_t)nb0 * 16 * MP;
+    const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP;
+    auto prow = [&](int r) -> int64_t {
+      return (int64_t)(C::NS > 1 ? 16 * (2 * (r >> 4) + half) + (r & 15) : r) * MP;
+    };
     if constexpr (CT == DT_BF16) {
       for (int e = threadIdx.x; e < NB * 16 * (MP / 8); e += 512) {
         const int r = e / (MP / 8), n = (e % (MP / 8)) * 8;
-        const uint4 v = *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
+        const uint4 v = *reinterpret_cast<const uint4*>(P + prow(r) + n);
         const int nb = n >> 4, g0 = (n & 15) >> 2;  // entries n..n+3 in group g0, n+4..n+7 in g0+1
         const int pos = 32 * (nb >> 1) + 8 * g0 + 4 * (nb & 1);
         *reinterpret_cast<uint2*>(Ps + r * SP + pos) = make_uint2(v.x, v.y);
@@ -303,9 +349,10 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     } else {
       for (int e = threadIdx.x; e < NB * 16 * (MP / 4); e += 512) {
         const int r = e / (MP / 4), n = (e % (MP / 4)) * 4;
-        const int pos = C::NS > 1 ? ((n - 16 * nb0) & (MP - 1)) : n;  // rotated for a split
+        const int ri = n >> 4;  // register piece of input piece ri (see piece())
+        const int pos = C::NS > 1 ? 16 * ((ri >> 1) | (((ri & 1) ^ half) << 3)) + (n & 15) : n;
         *reinterpret_cast<uint4*>(Ps + r * SP + pos) =
-            *reinterpret_cast<const uint4*>(P + (int64_t)r * MP + n);
+            *reinterpret_cast<const uint4*>(P + prow(r) + n);
       }
     }
     if (lepi) {  // C rows (zero beyond ew) and D (16 x 16, zero-padded)
@@ -323,7 +370,14 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
   }
   if (n <= 0) return;
 #pragma unroll
-  for (int q = 0; q < S; ++q) pack(part[q], true, pa[q]);
+  for (int q = 0; q < S; ++q) {
+    pack(part[q], true, pa[q]);
+    if constexpr (C::NS > 1) {  // the first block's other pieces (see body)
+      const bool keep = adj ? fi[q] > 0 : fi[q] + 1 < ni;
+#pragma unroll
+      for (int nb = NB; nb < NV; ++nb) pb[q][nb] = keep ? x[q][nb] : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
   // segments advance in lockstep; a shorter one idles once it is done
   for (int t = 0; t < n; ++t) {  // unrolled by two: the operand sets swap roles
 #pragma unroll

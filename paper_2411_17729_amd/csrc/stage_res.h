@@ -27,6 +27,29 @@ struct ResCfg {
   static constexpr size_t LDS_TAIL = LDS + (16 * EPS + 16 * 16) * sizeof(float);
 };
 
+// Workgroup -> (item, half) for launches whose items are shared by NS
+// workgroups. Workgroups are dispatched to the eight XCDs in turn (workgroup b
+// on XCD b mod 8), so with NS = 2 the halves of item i are workgroups
+// 16 (i / 8) + i mod 8 and that + 8: both on one XCD, whose L2 serves the
+// second read of the rows that both load, and dispatched together. Returns
+// false for the padding workgroups past the last item.
+template <int NS>
+__device__ __forceinline__ bool split_item(int n, int& item, int& half) {
+  static_assert(NS == 1 || NS == 2, "one or two workgroups per item");
+  const int b = blockIdx.x;
+  if constexpr (NS == 1) {
+    item = b;
+    half = 0;
+  } else {
+    half = (b >> 3) & 1;
+    item = ((b >> 4) << 3) | (b & 7);
+  }
+  return item < n;
+}
+
+// workgroups of a launch of n items with NS workgroups each
+inline unsigned split_grid(int n, int NS) { return NS == 1 ? (unsigned)n : 2u * (unsigned)((n + 7) & ~7); }
+
 // Output epilogue on the matrix cores: for the lane's 16-row block,
 //     Y^T[qq, l] = sum_n Cm[qq, n] X^T[n, l] + sum_c Dm[qq, c] V^T[c, l]
 // (y = C x + D u forward, du = Bbar^T g + D^T dy adjoint), 16 outputs at a

@@ -208,3 +208,31 @@ def test_lower_triangular_powers_are_marked():
         assert parity_err(y[i], ref[i]) <= 1e-5, i
     dense = W.random_small(seed=1, m=64, p=2, q=2, L=500, N=7, n_seq=1, contraction=0.9)
     assert CC.plan_for_workload(dense, compute="f32").info()["lower_ops"] == 0
+
+
+@pytest.mark.parametrize("mix", [False, True])
+def test_fp32_split_halves(mix):
+    """FP32 at padded m 256: two workgroups share each chain unit, holding the
+    interleaved halves of P_k's rows. With every operator of the class lower
+    triangular the launches leave out the zero blocks (forward and adjoint);
+    a dense operator in the class (mix) turns that off for the whole class.
+    Forward against the FP64 oracle, gradients against the oracle's."""
+    from paper_2411_17729_amd import cascade as CC
+    from tests.test_gpu_backward import _compare
+    rng = np.random.default_rng(31)
+    sets, seqs = [], []
+    for i, (m, p, q, L, N) in enumerate([(256, 4, 4, 3001, 11), (200, 2, 3, 1500, 10)]):
+        if mix and i == 1:  # stable, dense: Abar has entries above the diagonal
+            A = rng.standard_normal((m, m)) / math.sqrt(m) - 1.5 * np.eye(m)
+        else:
+            A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, p)) / math.sqrt(m),
+                               rng.standard_normal((q, m)) / math.sqrt(m),
+                               rng.standard_normal((q, p)) / math.sqrt(m)))
+        seqs.append(W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, N, rng.standard_normal((L, p))))
+    wl = W.Workload("split_halves", sets, seqs)
+    y, info = _apply(wl, "f32")
+    assert info["n_ops"] == 2 and info["lower_ops"] == (1 if mix else 2)
+    for a, b in zip(CC.unpack_y(wl, y), _oracle(wl)):
+        assert parity_err(a, b) <= 1e-5
+    _compare(wl, "f32", launch="per_stage", stage_kernel="chain")
