@@ -85,26 +85,52 @@ ssm_status check_io(const ssm_plan_s& P, const void* u, ssm_dtype u_dtype, size_
 
 // One per-stage launch of class c at stage prm.k: the chain kernel where the
 // plan has units for this stage, else the resident-power kernel where the plan
-// uses it and it can apply this stage, the tiled one otherwise.
+// uses it and it can apply this stage, the tiled one otherwise. Where the
+// resident kernels split the state rows between workgroups (FP32, padded m
+// 256) they have no output epilogue: a last stage then runs lean and
+// k_output_proj forms the output from the rows it stored.
 hipError_t launch_stage_any(const ssm_plan_s& P, int c, StageParams prm, hipStream_t stream) {
   const int mp = kClassMp[c];
   const int k = prm.k;
+  const bool splits = res_splits_rows(mp, P.compute);
+  const bool final_here = (prm.flags & SF_EPILOGUE) &&
+                          (prm.adjoint ? k == 0 : (k < (int)P.class_final[c].size() &&
+                                                   P.class_final[c][k] > 0));
+  // lean stage + k_output_proj: every sequence of the class within that
+  // kernel's sizes and 32-bit row offsets, and no final-state copy asked for
+  bool proj = splits && final_here && !prm.xfinal && !(prm.flags & SF_NOUPDATE) &&
+              P.stage_kernel != SSM_STAGE_TILED;
+  for (int i = 0; proj && i < P.n_seq; ++i) {
+    const SeqDev& sq = P.seqs[i];
+    if (P.ops[sq.op].mp != mp) continue;
+    proj = output_proj_supported(mp, P.compute, prm.adjoint ? sq.p : sq.q, prm.adjoint ? sq.q : sq.p) &&
+           sq.L * (int64_t)mp * 4 < ((int64_t)1 << 31);
+  }
+  const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
+                       P.class_range_start[c];
+  StageParams lean = prm;
+  lean.flags &= ~(SF_EPILOGUE | SF_STORE_AT_EPI);
   if (k < (int)P.chain_count[c].size() && P.chain_count[c][k] > 0) {
     const ChainUnit* un = reinterpret_cast<const ChainUnit*>(P.ws + P.r_meta.off + P.m_chain) +
                           P.chain_start[c][k];
     const bool tail = prm.adjoint ? k == 0 : P.class_final[c][k] > 0;
     const int tri = P.compute == DT_F32 && P.class_lower[c] ? (prm.adjoint ? 2 : 1) : 0;
-    if (!(tail && res_splits_rows(mp, P.compute)))
+    if (!(tail && splits))
       return launch_stage_chain(mp, P.compute, prm, un, P.chain_count[c][k], tail, tri, stream);
+    if (proj) {
+      hipError_t e = launch_stage_chain(mp, P.compute, lean, un, P.chain_count[c][k], false, tri, stream);
+      if (e != hipSuccess) return e;
+      return launch_output_proj(mp, prm, rg, P.class_range_active[c][k], stream);
+    }
   }
-  const bool final_here = (prm.flags & SF_EPILOGUE) &&
-                          (prm.adjoint ? k == 0 : (k < (int)P.class_final[c].size() &&
-                                                   P.class_final[c][k] > 0));
-  if (P.stage_kernel != SSM_STAGE_TILED && res_supported(mp, P.compute) &&
-      !(final_here && res_splits_rows(mp, P.compute))) {
-    const ResRange* rg = reinterpret_cast<const ResRange*>(P.ws + P.r_meta.off + P.m_ranges) +
-                         P.class_range_start[c];
-    return launch_stage_res(mp, P.compute, prm, rg, P.class_range_active[c][k], stream);
+  if (P.stage_kernel != SSM_STAGE_TILED && res_supported(mp, P.compute)) {
+    if (!(final_here && splits))
+      return launch_stage_res(mp, P.compute, prm, rg, P.class_range_active[c][k], stream);
+    if (proj) {
+      hipError_t e = launch_stage_res(mp, P.compute, lean, rg, P.class_range_active[c][k], stream);
+      if (e != hipSuccess) return e;
+      return launch_output_proj(mp, prm, rg, P.class_range_active[c][k], stream);
+    }
   }
   return launch_stage(mp, P.compute, P.class_bm[c], prm, stream);
 }

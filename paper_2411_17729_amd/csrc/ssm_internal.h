@@ -359,6 +359,14 @@ hipError_t launch_input_split(int mp, int ct, int p, int kdim, bool xb, const St
 bool chain_supported(int mp, int ct);
 // tail: some sequence of the launch has its last stage here (the forward
 // epilogue or the final-state copy may be due); false selects the lean variant.
+// The output y = C x + D u (adjoint: du = Bbar^T g + D^T dy) of the sequences
+// whose last stage of the direction is prm.k, from the state rows that stage
+// stored in prm.xout; for stage launches that ran without their epilogue
+// (FP32 at padded m 256, where a stage's rows are split between workgroups).
+// ew: outputs, er: inputs per row (both at most 16).
+bool output_proj_supported(int mp, int ct, int ew, int er);
+hipError_t launch_output_proj(int mp, const StageParams& prm, const ResRange* ranges, int n_ranges,
+                              hipStream_t s);
 // tri (FP32 operands; ignored for BF16): 1 when every operator of the launch
 // has lower-triangular powers, 2 for the adjoint of such a launch, 0 otherwise
 // (a launch with tri != 0 over a power that is not triangular is wrong).
