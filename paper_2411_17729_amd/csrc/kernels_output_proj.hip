@@ -35,6 +35,9 @@ __global__ __launch_bounds__(256) void k_output_proj(StageParams prm, const ResR
   const int64_t so = adj ? sq.y_off : sq.u_off, dof = adj ? sq.u_off : sq.y_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
+  __shared__ float ds[16 * 16];  // D (or D^T), ew x er
+  for (int e = threadIdx.x; e < ew * er; e += 256) ds[e] = dm[e];
+  __syncthreads();
 
   f32x4 ca[NV];  // row j of C (zero past ew), entries 16 a + 4 g ..
 #pragma unroll
@@ -56,19 +59,30 @@ __global__ __launch_bounds__(256) void k_output_proj(StageParams prm, const ResR
 #pragma unroll
     for (int a = 0; a < NV; ++a)
       xv[a] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rx, off + 64u * a, 0, 0));
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the row's inputs, loaded before the contraction so that they arrive
+    // during it
+    const bool live = l < L && l < rg.row0 + rg.nrows;
+    float uv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      uv[c] = live && c < er ? load_src<float>(prm.src, prm.src_dtype, so + (int64_t)l * er + c) : 0.f;
+    // four accumulator chains (steps t), added at the end
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int a = 0; a < NV; ++a)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[a][t], xv[a][t], acc, 0, 0, 0);
-    if (l < L && l < rg.row0 + rg.nrows) {
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[a][t], xv[a][t], acc[t], 0, 0, 0);
+    if (live) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int out = 4 * g + v;
         if (out < ew) {
-          float yv = acc[v];
-          for (int c = 0; c < er; ++c)
-            yv = fmaf(dm[out * er + c], load_src<float>(prm.src, prm.src_dtype, so + (int64_t)l * er + c), yv);
+          float yv = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
+#pragma unroll
+          for (int c = 0; c < 16; ++c)
+            if (c < er) yv = fmaf(ds[out * er + c], uv[c], yv);
           dst[dof + (int64_t)l * ew + out] = yv;
         }
       }
