@@ -602,9 +602,11 @@ def bench_ragged(args):
     tn = tune.best_tuning(wl, compute="bf16", allow_bf16_state=True)
     # the forward plan as tuned; the backward plan without the extra padding
     # (its passes keep FP32 state and run per stage, so the padded rows would
-    # only add work)
+    # only add work) and with the automatic chain segments (the forward's tuned
+    # length is for its few chain launches; short segments re-read a partner
+    # block each)
     plan = CC.plan_for_workload(wl, compute="bf16", **tn)
-    tb = dict(tn, min_padded_m=0)
+    tb = dict(tn, min_padded_m=0, chain_blocks=0)
     plan_b = CC.plan_for_workload(wl, compute="bf16", with_backward=True, ckpt_every=args.ckpt_every, **tb)
     info = plan.info()
     u = CC.pack_u(wl, dtype=torch.float32)
@@ -669,7 +671,7 @@ def bench_ragged(args):
                      "launches_timed": n_k, "apply_kernel_ms": round(t_k, 5),
                      "algorithmic_bytes_per_apply": round(info["stage_bytes"])},
         "backward": {"value": round(wl.total_steps / (ms_b * 1e-3), 1), "ms_per_step": round(ms_b, 4),
-                     "graph": True, "plan": "the forward's tuning with min_padded_m = 0",
+                     "graph": True, "plan": "the forward's tuning with min_padded_m = 0 and automatic chain segments",
                      "breakdown_ms": {"forward_stages": round(b_fwd[1], 3), "adjoint_stages": round(b_adj[1], 3),
                                       "reductions": round(b_red[1], 3),
                                       "launches": [b_fwd[0], b_adj[0], b_red[0]],
