@@ -171,13 +171,15 @@ static hipError_t launch_outer_t(const RedParams& prm, int tiles_y, hipStream_t 
 // one side of the outer product is at most 16 wide. Thread t takes column
 // t mod W' of the wide side (W' the power of two >= its width) and every
 // (256 / W')-th row of the chunk, so a row of the wide side is read with one
-// coalesced access per thread and the narrow row (the same for every thread
-// of a row) comes from the cache; each thread keeps 16 sums, added over the
-// row phases through LDS at the end.
+// coalesced access per thread. The narrow rows (the same for every thread of
+// a row) are staged in LDS 64 rows at a time, each element loaded once by
+// the workgroup, and read back as broadcasts. Each thread keeps 16 sums,
+// added over the row phases through LDS at the end.
 template <int MP, typename X>
 __global__ __launch_bounds__(256) void k_outer_thin(RedParams prm) {
-  constexpr int NN = 16;
+  constexpr int NN = 16, G = 64;
   __shared__ X red[NN][256];
+  __shared__ X nsm[G][NN];
   const RedChunk ch = prm.chunks[blockIdx.x];
   const SeqDev sq = prm.seqs[ch.seq];
   const bool first = prm.a_first && prm.k >= 0 && prm.k == sq.last;
@@ -194,19 +196,43 @@ __global__ __launch_bounds__(256) void k_outer_thin(RedParams prm) {
   X acc[NN];
 #pragma unroll
   for (int j = 0; j < NN; ++j) acc[j] = (X)0;
+  // (uniform over the workgroup: every thread meets the same barriers)
   const bool active = !(prm.check_last && prm.k > sq.last);
   const int64_t s = prm.k >= 0 ? ((int64_t)1 << prm.k) : 0;
   int64_t lo = ch.row0;
   if (lo < s) lo = s;
   const int64_t hi = (int64_t)ch.row0 + ch.nrows;
-  if (active && c < ww) {
+  if (active) {
     // B rows are shifted by s: the wide side's when A is narrow, else the narrow side's
     const int64_t sw = a_narrow ? s : 0, sn = a_narrow ? 0 : s;
-    for (int64_t l = lo + ph; l < hi; l += phases) {
-      const X wv = Ww.at(l - sw, c);
+    for (int64_t base = lo; base < hi; base += G) {
+      const int nr = (int)(hi - base < G ? hi - base : G);
+      for (int e = t; e < nr * nw; e += 256) {
+        const int r = e / nw, j = e - r * nw;
+        nsm[r][j] = Nw.at(base + r - sn, j);
+      }
+      __syncthreads();
+      if (c < ww) {
+        // eight rows of the thread in flight at a time
+        int r = ph;
+        for (; r + 7 * phases < nr; r += 8 * phases) {
+          X wv[8];
 #pragma unroll
-      for (int j = 0; j < NN; ++j)
-        if (j < nw) acc[j] += Nw.at(l - sn, j) * wv;
+          for (int i = 0; i < 8; ++i) wv[i] = Ww.at(base + r + i * phases - sw, c);
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < NN; ++j)
+              if (j < nw) acc[j] += nsm[r + i * phases][j] * wv[i];
+        }
+        for (; r < nr; r += phases) {
+          const X wv = Ww.at(base + r - sw, c);
+#pragma unroll
+          for (int j = 0; j < NN; ++j)
+            if (j < nw) acc[j] += nsm[r][j] * wv;
+        }
+      }
+      __syncthreads();
     }
   }
 #pragma unroll
