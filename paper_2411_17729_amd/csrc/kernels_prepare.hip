@@ -438,8 +438,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmJob* jobs) {
                                       : 0.0;
     }
   };
-  load(0);
-  for (int k0 = 0; k0 < jb.K; k0 += KT) {
+  // the K range where both operands of this output tile can be nonzero
+  int kb = 0, ke = jb.K;
+  if (jb.tri && *jb.tri) {
+    if (jb.tri_mode & 1) ke = min(ke, tm + 64);  // op(A)(i, k) = 0 for k > i
+    if (jb.tri_mode & 2) kb = max(kb, tm);       // op(A)(i, k) = 0 for k < i
+    if (jb.tri_mode & 4) kb = max(kb, tn);       // op(B)(k, j) = 0 for k < j
+    if (jb.tri_mode & 8) ke = min(ke, tn + 64);  // op(B)(k, j) = 0 for k > j
+    kb = kb / KT * KT;
+  }
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += KT) {
     __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
@@ -451,7 +460,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmJob* jobs) {
       Bs[j][kk] = rb[t];
     }
     __syncthreads();
-    if (k0 + KT < jb.K) load(k0 + KT);
+    if (k0 + KT < ke) load(k0 + KT);
 #pragma unroll
     for (int ks = 0; ks < KT; ks += 4) {
       const int kk = ks + (lane >> 4);

@@ -1424,20 +1424,27 @@ void plan_backward_jobs(ssm_plan_s& P) {
       P.bkind.push_back(kind);
     }
   };
-  // squaring adjoint: G_k += G_{k+1} P_k^T + P_k^T G_{k+1}, k = N-1..0
+  // squaring adjoint: G_k += G_{k+1} P_k^T + P_k^T G_{k+1}, k = N-1..0; where
+  // prepare marked the operator's powers lower triangular, P_k^T is upper
+  // triangular and the products skip its zero K ranges
+  const OpDev* ops_d = reinterpret_cast<const OpDev*>(P.ws + P.r_meta.off + P.m_ops);
   for (int k = P.max_N - 1; k >= 0; --k) {
     for (int half = 0; half < 2; ++half) {
       int start = (int)P.bjobs.size();
-      for (const OpDev& o : P.ops) {
+      for (size_t oi = 0; oi < P.ops.size(); ++oi) {
+        const OpDev& o = P.ops[oi];
         if (o.N <= k) continue;
         const int64_t mm = (int64_t)o.mp * o.mp;
         double* Gk = G + o.g_dp + k * mm;
         double* Gk1 = Gk + mm;
         double* Pk = pw + o.pw + k * mm;
+        const int32_t* low = &ops_d[oi].lower;
         if (half == 0)
-          P.bjobs.push_back(GemmJob{Gk1, Pk, Gk, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 1, 1.0, 1.0});
+          P.bjobs.push_back(
+              GemmJob{Gk1, Pk, Gk, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 1, 1.0, 1.0, nullptr, low, 8});
         else
-          P.bjobs.push_back(GemmJob{Pk, Gk1, Gk, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 1, 0, 1.0, 1.0});
+          P.bjobs.push_back(
+              GemmJob{Pk, Gk1, Gk, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 1, 0, 1.0, 1.0, nullptr, low, 2});
       }
       close_group(start, 0);
     }

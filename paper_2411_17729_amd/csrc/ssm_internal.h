@@ -262,6 +262,11 @@ struct GemmJob {
   int32_t transA, transB;
   double alpha, beta;
   const int32_t* gate;  // if set, the job runs only where *gate != 0
+  // if set and *tri != 0, op(A) and op(B) are triangular as tri_mode says
+  // (1: op(A) lower, 2: op(A) upper, 4: op(B) lower, 8: op(B) upper) and the
+  // contraction leaves out the K ranges where one of them is zero
+  const int32_t* tri;
+  int32_t tri_mode;
 };
 
 // Rows per workgroup tile of the stage kernel for a padded state size and
