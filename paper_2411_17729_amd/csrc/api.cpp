@@ -643,13 +643,18 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     P->job_dims.push_back({mx, mxn});
     P->job_kind.push_back(0);
   }
+  // the lower-triangular mark of operator i (set on the device before the
+  // squarings): where it is set, every power is lower triangular and the
+  // products with a power below leave out the zero K ranges
+  const OpDev* ops_dev = reinterpret_cast<const OpDev*>(P->ws + P->r_meta.off + P->m_ops);
+  auto low = [&](const OpDev& o) { return &ops_dev[&o - P->ops.data()].lower; };
   for (int kk = 0; kk < P->max_N; ++kk) {  // P_{k+1} = P_k P_k
     int start = (int)J.size(), mx = 0;
     for (const OpDev& o : P->ops) {
       if (o.N <= kk) continue;
       const int64_t mm = (int64_t)o.mp * o.mp;
       double* Pk = pw + o.pw + kk * mm;
-      J.push_back(GemmJob{Pk, Pk, Pk + mm, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 0, 1.0, 0.0});
+      J.push_back(GemmJob{Pk, Pk, Pk + mm, o.mp, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 0, 1.0, 0.0, nullptr, low(o), 1 | 4});
       mx = std::max(mx, o.mp);
     }
     P->job_groups.push_back({start, (int)J.size() - start});
@@ -678,7 +683,7 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
         const int64_t mm = (int64_t)o.mp * o.mp;
         const int w = o.p << i;
         J.push_back(GemmJob{pw + o.pw + i * mm, kw + o.kw, kw + o.kw + w, o.mp, w, o.mp, o.mp, o.kst,
-                            o.kst, 0, 0, 1.0, 0.0});
+                            o.kst, 0, 0, 1.0, 0.0, nullptr, low(o), 1});
         mx = std::max(mx, o.mp);
         mn = std::max(mn, w);
       }
@@ -701,7 +706,7 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
       if (o.cpl < 0) continue;
       const int64_t mm = (int64_t)o.mp * o.mp;
       J.push_back(GemmJob{P->src[i].C, pw + o.pw + o.cpl * mm, kw + o.cpw, o.q, o.mp, o.m, o.m, o.mp,
-                          o.mp, 0, 0, 1.0, 0.0});
+                          o.mp, 0, 0, 1.0, 0.0, nullptr, low(o), 4});
       mx = std::max(mx, o.q);
       mn = std::max(mn, o.mp);
     }
@@ -744,7 +749,7 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
         const int64_t mm = (int64_t)o.mp * o.mp;
         const int rows = 16 << t;
         J.push_back(GemmJob{kw + o.fold_gw, pw + o.pw + (o.fold_k0 + t) * mm, kw + o.fold_gw + (int64_t)rows * o.mp,
-                            rows, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 0, 1.0, 0.0});
+                            rows, o.mp, o.mp, o.mp, o.mp, o.mp, 0, 0, 1.0, 0.0, nullptr, low(o), 4});
         mx = std::max(mx, rows);
         mn = std::max(mn, o.mp);
       }
@@ -882,6 +887,9 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
     if (e != hipSuccess) return bail(hip_fail(e, "discretization GEMM launch"));
     ++g;
   }
+  // Abar (P_0) is complete: mark the operators whose Abar is lower triangular
+  e = launch_mark_lower(reinterpret_cast<OpDev*>(meta + P->m_ops), P->n_ops, pw, stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "triangular mark launch"));
   for (; g < P->job_groups.size(); ++g) {
     const auto& grp = P->job_groups[g];
     if (P->job_kind[g] == 1)
@@ -892,8 +900,6 @@ static ssm_status prepare_impl(const ssm_seq_desc* seqs, int32_t n_seq, const ss
                           P->job_dims[g].second, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "squaring GEMM launch"));
   }
-  e = launch_mark_lower(reinterpret_cast<OpDev*>(meta + P->m_ops), P->n_ops, pw, stream);
-  if (e != hipSuccess) return bail(hip_fail(e, "triangular mark launch"));
   if (P->max_kry > 0 || any_cp) {
     e = launch_pack_krylov(ops_d, P->n_ops, P->at<double>(P->r_kw), P->ws + P->r_pc.off, P->compute,
                            P->max_mp, stream);
