@@ -236,3 +236,27 @@ def test_fp32_split_halves(mix):
     for a, b in zip(CC.unpack_y(wl, y), _oracle(wl)):
         assert parity_err(a, b) <= 1e-5
     _compare(wl, "f32", launch="per_stage", stage_kernel="chain")
+
+
+@pytest.mark.parametrize("pq", [(16, 16), (3, 17)])
+def test_fp32_m256_output_widths(pq):
+    """FP32 at padded m 256: the last stage runs lean and a separate pass forms
+    y = C x + D u (du = Bbar^T g + D^T dy) while p and q are at most 16 (the
+    widest case here); with q = 17 the tiled stage kernel forms it instead.
+    Forward against the FP64 oracle, gradients against the oracle's."""
+    from paper_2411_17729_amd import cascade as CC
+    from tests.test_gpu_backward import _compare
+    p, q = pq
+    rng = np.random.default_rng(37)
+    sets, seqs = [], []
+    for i, (m, L, N) in enumerate([(256, 700, 9), (230, 333, 8)]):
+        A, _ = W.hippo_legs(m)
+        sets.append(W.ParamSet(A, rng.standard_normal((m, p)) / math.sqrt(m),
+                               rng.standard_normal((q, m)) / math.sqrt(m),
+                               rng.standard_normal((q, p)) / math.sqrt(m)))
+        seqs.append(W.Sequence(i, float(10 ** rng.uniform(-3, -1)), L, N, rng.standard_normal((L, p))))
+    wl = W.Workload("output_widths", sets, seqs)
+    y, info = _apply(wl, "f32")
+    for a, b in zip(CC.unpack_y(wl, y), _oracle(wl)):
+        assert parity_err(a, b) <= 1e-5
+    _compare(wl, "f32", launch="per_stage", stage_kernel="chain")
