@@ -32,22 +32,24 @@ namespace ssmc {
 // segments seg0 .. seg0 + 8 S - 1, wave w taking seg0 + w S .. seg0 + w S + S - 1.
 // When the power does not fit in LDS (FP32, m = 256) two workgroups share a
 // unit, each holding half of P_k's rows and producing half of every output
-// row: half h the 16-entry pieces 2 e + h, e < 8. Both load whole input rows,
-// which the next block needs as its shifted operand. The split form has no
-// output epilogue. To keep register indices static, a split workgroup holds
-// its own pieces first: register piece i is row piece 2 (i mod 8) + h for
-// i < 8 and 2 (i mod 8) + 1 - h after, and its LDS copy of P_k has the columns
-// permuted the same way, so MFMA step a still pairs register piece a with the
-// matching columns.
+// row: half h the 16-entry pieces 4 i + 2 h and 4 i + 2 h + 1, i < 4, so that
+// each stores whole 128-byte lines. Both load whole input rows, which the
+// next block needs as its shifted operand. The split form has no output
+// epilogue. To keep register indices static, a split workgroup holds its own
+// pieces first: register piece e < 8 is row piece 4 (e / 2) + 2 h + e mod 2,
+// and register piece 8 + e the other half's 4 (e / 2) + 2 (1 - h) + e mod 2;
+// its LDS copy of P_k has the columns permuted the same way, so MFMA step a
+// still pairs register piece a with the matching columns.
 //
 // TRI (FP32): 1 when every power of the launch is lower triangular (the
 // adjoint's P_k^T upper triangular: TRI 2), and the contraction leaves out the
 // 16 x 16 blocks that are zero; the host chooses it, so the unrolled loop has
 // no branches. Output piece o needs input pieces up to o (from o for the
-// adjoint); with the interleaved halves both halves take register pieces a
-// with a mod 8 <= e for their e-th own piece (>= e for the adjoint), which
-// includes one zero block per own piece for one of the halves but keeps a
-// single pattern for both, and splits the 136 nonzero blocks 72 / 72.
+// adjoint). For its e-th own piece a half takes its own register pieces
+// a <= e (>= e for the adjoint) and the other half's pieces 8 + a with
+// a / 2 <= e / 2 (>= for the adjoint): one pattern for both halves, which
+// includes a few zero blocks for one of them and gives each half 76 of its
+// 128 blocks (together the 136 nonzero ones and 16 zero ones).
 template <int MP, int CT, bool TAIL, int S = 1, int TRI = 0>
 __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUnit un,
                                            unsigned char* smem_chain, int split = 0) {
@@ -135,9 +137,9 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
                : 0x80000000u;
   };
   // stage input of this lane's row of a block, accumulator layout
-  // byte offset of register piece i within a row (interleaved for a split)
+  // byte offset of register piece i within a row (interleaved pairs for a split)
   auto piece = [&](int i) -> uint32_t {
-    return (uint32_t)(C::NS > 1 ? (((i & 7) << 1) | (half ^ (i >> 3))) : i) * 64u;
+    return (uint32_t)(C::NS > 1 ? 4 * ((i & 7) >> 1) + 2 * (half ^ (i >> 3)) + (i & 1) : i) * 64u;
   };
   auto load_block = [&](uint32_t off, f32x4(&v)[NV]) {
 #pragma unroll
@@ -239,8 +241,9 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
         // output piece ro (P_k^T of the adjoint none below); the test folds
         // to a constant once the loops are unrolled
         auto on = [&](int a, int nb) {
-          const int ai = C::NS > 1 ? (a & 7) : a;
-          return TRI == 0 || (TRI == 1 ? ai <= nb : ai >= nb);
+          const int ai = C::NS > 1 && a >= 8 ? ((a & 7) >> 1) : a;
+          const int bi = C::NS > 1 && a >= 8 ? (nb >> 1) : nb;
+          return TRI == 0 || (TRI == 1 ? ai <= bi : ai >= bi);
         };
         // power fragments of step a + 1 read while step a is contracted; the
         // scheduling fence keeps the reads from running further ahead
@@ -330,12 +333,13 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
     load_block(block_off(q, 0, f0[q], f1[q]), x[q]);
   }
   // this workgroup's rows of P_k (or P_k^T) into LDS (for a split, row
-  // piece e is P's piece 2 e + half), contraction columns permuted for BF16
-  // and for a split
+  // piece e is P's piece 4 (e / 2) + 2 half + e mod 2), contraction columns
+  // permuted for BF16 and for a split
   {
     const Op* P = reinterpret_cast<const Op*>(prm.P) + (adj ? o.pct : o.pc) + (int64_t)k * MP * MP;
     auto prow = [&](int r) -> int64_t {
-      return (int64_t)(C::NS > 1 ? 16 * (2 * (r >> 4) + half) + (r & 15) : r) * MP;
+      const int e = r >> 4;
+      return (int64_t)(C::NS > 1 ? 16 * (4 * (e >> 1) + 2 * half + (e & 1)) + (r & 15) : r) * MP;
     };
     if constexpr (CT == DT_BF16) {
       for (int e = threadIdx.x; e < NB * 16 * (MP / 8); e += 512) {
@@ -350,7 +354,8 @@ __device__ __forceinline__ void chain_unit(const StageParams& prm, const ChainUn
       for (int e = threadIdx.x; e < NB * 16 * (MP / 4); e += 512) {
         const int r = e / (MP / 4), n = (e % (MP / 4)) * 4;
         const int ri = n >> 4;  // register piece of input piece ri (see piece())
-        const int pos = C::NS > 1 ? 16 * ((ri >> 1) | (((ri & 1) ^ half) << 3)) + (n & 15) : n;
+        const int pos =
+            C::NS > 1 ? 16 * ((2 * (ri >> 2) + (ri & 1)) | ((((ri >> 1) & 1) ^ half) << 3)) + (n & 15) : n;
         *reinterpret_cast<uint4*>(Ps + r * SP + pos) =
             *reinterpret_cast<const uint4*>(P + prow(r) + n);
       }
