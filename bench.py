@@ -292,6 +292,12 @@ def main():
         n_launch, k_ms = kern
         avg_ms = k_ms / max(n_launch, 1)
         per_launch_bytes = nbytes / launches
+        dense_flops = flops / launches
+        # every power lower triangular (HiPPO): a stage product needs the
+        # m (m + 1) / 2 nonzero entries of P_k, not m^2, so that is the
+        # algorithmic count (the dense one stays beside it)
+        tri = info["n_ops"] > 0 and info["lower_ops"] == info["n_ops"]
+        flops = flops * ((ps.m + 1) / (2 * ps.m) if tri else 1.0)
         per_launch_flops = flops / launches
         gbps = per_launch_bytes / (avg_ms * 1e-3) / 1e9
         tflops = per_launch_flops / (avg_ms * 1e-3) / 1e12
@@ -311,13 +317,17 @@ def main():
                    "algorithmic_bytes_per_launch": round(per_launch_bytes),
                    "algorithmic_flops_per_launch": round(per_launch_flops),
                    "mfma_util": round(tflops / peak_tf, 4), "hbm_GBps": round(gbps, 1)})
-        if name == "k_stage_chain" and dtype == "f32" and info["lower_ops"] == info["n_ops"]:
+        if tri:
+            rf["dense_flops_per_launch"] = round(dense_flops)
+            rf["flops_note"] = "lower-triangular powers: m (m + 1) / 2 of the m^2 entries of P_k"
+        if name == "k_stage_chain" and dtype == "f32" and tri:
             # the FP32 chain kernel skips the zero 16 x 16 blocks of the lower-triangular
-            # powers: of (m/16)^2 blocks per product it runs (m/16)(m/16 + 1)/2
+            # powers: of (m/16)^2 blocks per product it runs (m/16)(m/16 + 1)/2, and at
+            # padded m 256 (two workgroups per unit, one skip pattern for both) 2 x 76 of 256
             nv = ps.m // 16
-            frac = nv * (nv + 1) / 2 / (nv * nv)
+            frac = 152 / 256 if ps.m > 128 else nv * (nv + 1) / 2 / (nv * nv)
             rf["mfma_blocks_executed_frac"] = round(frac, 4)
-            rf["mfma_util_executed"] = round(tflops * frac / peak_tf, 4)
+            rf["mfma_util_executed"] = round(dense_flops / (avg_ms * 1e-3) / 1e12 * frac / peak_tf, 4)
         return rf
 
     # ---------------- headline: the cascade in the chosen dtype ----------------
